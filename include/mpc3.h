@@ -1,0 +1,217 @@
+/*
+ * mpc3.h -- three-party secure linear-function evaluation over Z_{2^64}
+ * (Lu, Zhang, Li, Ren, arXiv 2411.09287) on one MI355X.
+ *
+ * All three parties P0, P1, P2 run in one process on one GPU.  A "sent" message
+ * is a device buffer; its size is counted per (phase, sender, receiver) and
+ * nothing is transmitted.  Ring arithmetic is uint64 with wrap-around.
+ *
+ * Shares (Preliminaries, "<.>-sharing"): a shared value v is held as three
+ * planes m, r1, r2 with m = v + r1 + r2.  P1 holds (m, r1), P2 holds (m, r2),
+ * P0 holds (r1, r2).  Verification runs in the Galois ring
+ * GR(2^64, d) = Z_{2^64}[x] / (x^64 + x^4 + x^3 + x + 1) (Sec. 3), whose
+ * elements are d = 64 uint64 coefficients, x^0 first.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named *_dev are device pointers (hipMalloc'd or torch tensors
+ *     used as raw 64-bit storage) owned by the caller.  The library never
+ *     frees caller memory.  Matrices are row-major and dense (rows x cols).
+ *   - Calls are asynchronous on the context's HIP stream unless stated.
+ *     mpc3_verify, mpc3_reconstruct and mpc3_comm_stats synchronise.
+ *   - Return value: MPC3_OK or a negative MPC3_E_* code.  After a failed
+ *     verification every call returns MPC3_E_ABORTED (security with abort,
+ *     Sec. 2 "Security Model").
+ *   - The context keeps pointers to the operands of every product until it
+ *     is verified: keep X, W, Z and truncation-pair planes alive and
+ *     unmodified until mpc3_verify has covered them.
+ */
+#ifndef MPC3_H
+#define MPC3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpc3_ctx mpc3_ctx;
+
+/* <v> as three device planes of rows*cols uint64 each (m, [r]_1, [r]_2). */
+typedef struct {
+    uint64_t *m, *r1, *r2;
+    int64_t rows, cols;
+} mpc3_share_t;
+
+/* Truncation pair of Pi_Trunc^t (Fig. "The maliciously secure truncation
+ * protocol"): <r_x> and <r_z> = <ash(r_x, t)> for n outputs.  The caller
+ * allocates the six planes (n words each); mpc3_trunc_pair fills them and id. */
+typedef struct {
+    mpc3_share_t rx, rz;
+    int32_t t;
+    int64_t n;
+    uint64_t id;
+} mpc3_trunc_pair_t;
+
+/* Bytes per [phase][sender][receiver] and communication rounds per phase. */
+typedef struct {
+    uint64_t bytes[4][3][3];
+    uint32_t rounds[4];
+} mpc3_comm;
+
+enum {
+    MPC3_OK = 0,
+    MPC3_E_ARG = -1,        /* null pointer or out-of-range parameter */
+    MPC3_E_SHAPE = -2,      /* operand shapes do not match */
+    MPC3_E_NOMEM = -3,      /* device allocation failed */
+    MPC3_E_ABORTED = -4,    /* a verification failed or Pi_Rec saw inconsistent shares */
+    MPC3_E_UNVERIFIED = -5, /* reconstruct requested while products await verification */
+    MPC3_E_HIP = -6,        /* a HIP runtime call failed */
+    MPC3_E_STATE = -7       /* call not valid in the current state */
+};
+
+enum { MPC3_VARIANT_U64 = 0, MPC3_VARIANT_LIMB_I8 = 1 };
+
+/* Phases of the communication counters. */
+enum { MPC3_PH_OFFLINE = 0, MPC3_PH_ONLINE = 1, MPC3_PH_VERIFY_OFFLINE = 2, MPC3_PH_VERIFY_ONLINE = 3 };
+
+/* Kinds of pending products, for mpc3_verify's selection mask. */
+enum { MPC3_VERIFY_INNER = 1, MPC3_VERIFY_TRUNC = 2, MPC3_VERIFY_MULT = 4, MPC3_VERIFY_ALL = 7 };
+
+/* Message sites for mpc3_inject (an additive error on one word of one message). */
+enum {
+    MPC3_SITE_INNER_GAMMA2 = 1,  /* P0 -> P2 [Gamma]_2 of Pi_Inner; index = output element */
+    MPC3_SITE_INNER_M1 = 2,      /* P1 -> P2 [m_Z]_1 of Pi_Inner; index = output element */
+    MPC3_SITE_TRUNC_GAMMA2 = 3,  /* P0 -> P2 [Gamma]_2 of the r_x product of Pi_Trunc; index = output */
+    MPC3_SITE_TRUNC_M1 = 4,      /* P1 -> P2 [m]_1 of the r_z product of Pi_Trunc; index = output */
+    MPC3_SITE_MULT_GAMMA2 = 5,   /* P0 -> P2 [Gamma]_2 of Pi_Mult; index = element */
+    MPC3_SITE_VER_H0_M1 = 6,     /* P1 -> P2 [m]_1 of h(0) in Pi_Reduce; index = inst<<16 | round<<8 | coeff */
+    MPC3_SITE_VER_H2_GAMMA2 = 7, /* P0 -> P2 [Gamma]_2 of h(x) in Pi_Reduce; same index layout */
+    MPC3_SITE_VER_DELTA_M1 = 8,  /* P1 -> P2 [m]_1 of Delta in Pi_InnerVerify; index = inst<<16 | coeff */
+    MPC3_SITE_REC_R1 = 9         /* P0 -> P2 [r]_1 in Pi_Rec of mpc3_reconstruct; index = element */
+};
+
+/* Messages of the most recent Pi_Inner / Pi_Mult, for mpc3_message. */
+enum { MPC3_MSG_GAMMA2 = 0, MPC3_MSG_M1 = 1, MPC3_MSG_M2 = 2 };
+
+/* Public transcript slots of one verification instance, for mpc3_verify_log.
+ * Each slot is d words.  Round-indexed slots take round = 0 .. R-1. */
+enum {
+    MPC3_LOG_R = 0,          /* revealed challenge r of Pi_Tran / Pi_BIVerify */
+    MPC3_LOG_Z = 1,          /* claimed <z> after the power-weighted sum, m plane */
+    MPC3_LOG_ZETA = 2,       /* revealed point of round k */
+    MPC3_LOG_H0_M1 = 3, MPC3_LOG_H0_M2 = 4, MPC3_LOG_H0_G2 = 5,
+    MPC3_LOG_H2_M1 = 6, MPC3_LOG_H2_M2 = 7, MPC3_LOG_H2_G2 = 8,
+    MPC3_LOG_DELTA = 9,      /* revealed Delta of Pi_InnerVerify */
+    MPC3_LOG_DELTA_M1 = 10, MPC3_LOG_DELTA_M2 = 11, MPC3_LOG_DELTA_G2 = 12
+};
+
+/* Context: seeds eta_01, eta_02, eta_12 (and an all-party seed for inputs
+ * owned by P1 or P2) are SHA-256(master_seed || "eta" || ids).  d must be 64.
+ * frac_bits is the fixed-point precision (13).  workspace_bytes sizes the
+ * initial device arena (0 = grow on demand).  hip_stream is a hipStream_t or
+ * NULL for the default stream.  Preliminaries, "Notation" and "Secret sharing". */
+int mpc3_ctx_create(const uint8_t master_seed[32], int d, int frac_bits, size_t workspace_bytes,
+                    void* hip_stream, mpc3_ctx** out);
+int mpc3_ctx_destroy(mpc3_ctx* ctx);
+
+/* Kernel family for every matrix product: MPC3_VARIANT_U64 (64-bit integer
+ * VALU) or MPC3_VARIANT_LIMB_I8 (8-bit limbs on int8 MFMA, recombined modulo
+ * 2^64).  Both give bit-identical results. */
+int mpc3_set_variant(mpc3_ctx* ctx, int variant);
+
+/* Truncations per Pi_BIVerify instance of the truncation gates (default 16384). */
+int mpc3_set_chunk(mpc3_ctx* ctx, int64_t truncations_per_instance);
+
+/* Keep the messages of each Pi_Inner / Pi_Mult for mpc3_message (default off). */
+int mpc3_keep_messages(mpc3_ctx* ctx, int on);
+
+/* Fixed-point encoding (Preliminaries, "Notation"): out = floor(x * 2^f) mod 2^64
+ * for n doubles.  x_dev and out_dev are device buffers of n elements. */
+int mpc3_encode(mpc3_ctx* ctx, const double* x_dev, int64_t n, uint64_t* out_dev);
+
+/* Decoding: out = (int64) v / 2^f as double. */
+int mpc3_decode(mpc3_ctx* ctx, const uint64_t* v_dev, int64_t n, double* out_dev);
+
+/* Pi_<.>^{l,k}(x) (Preliminaries, "Secret sharing"): owner k in {0,1,2}
+ * shares rows*cols words x_dev into the caller's planes out->m, r1, r2
+ * (out->rows, out->cols give the shape).  [r]_1 and [r]_2 come from the
+ * pairwise PRGs; the owner sends m = x + r1 + r2. */
+int mpc3_share(mpc3_ctx* ctx, int owner, const uint64_t* x_dev, mpc3_share_t* out);
+
+/* Preprocessing of Pi_Trunc^t for n outputs (Fig. "The maliciously secure
+ * truncation protocol", Sec. 4.2): draws the bit lists of P0+P1 and P0+P2, runs
+ * the two inner products (over all 64 bit positions) that give <r_x> and
+ * <r_z> = <ash(r_x, t)>, and registers both for verification.  1 <= t <= 62. */
+int mpc3_trunc_pair(mpc3_ctx* ctx, int64_t n, int t, mpc3_trunc_pair_t* out);
+
+/* Pi_Inner for every output of Z = X W (Fig. "The Inner Product Protocol";
+ * Sec. 4.1 treats a matrix product as M*N inner products).  X is M x K, W is
+ * K x N, Z (caller planes) is M x N.  out_mask != NULL makes the output mask
+ * the pair's r_x (the truncation pair is generated first, Sec. 4.2);
+ * NULL draws a fresh mask.  Registers the product for verification. */
+int mpc3_inner(mpc3_ctx* ctx, const mpc3_share_t* X, const mpc3_share_t* W,
+               const mpc3_trunc_pair_t* out_mask, mpc3_share_t* Z);
+
+/* Convolution lowering: cols (B*OH*OW rows, KH*KW*C cols) from an NHWC shared
+ * tensor x (B*H*W*C words per plane), zero padding pad, stride 1.  Each plane
+ * is rearranged alone (a local linear map); Sec. 4.1 evaluates a convolution
+ * as one inner product per output. */
+int mpc3_im2col(mpc3_ctx* ctx, const mpc3_share_t* x, int B, int H, int W, int C, int KH, int KW,
+                int pad, mpc3_share_t* cols);
+
+/* Pi_Mult elementwise on rows*cols values (Fig. "The Multiplication Protocol"). */
+int mpc3_mult(mpc3_ctx* ctx, const mpc3_share_t* a, const mpc3_share_t* b, mpc3_share_t* c);
+
+/* Online Pi_Trunc: out.m = ash(Z.m, t); the output mask is the pair's r_z.
+ * No communication (Sec. 4.2). */
+int mpc3_trunc(mpc3_ctx* ctx, const mpc3_trunc_pair_t* p, const mpc3_share_t* Z, mpc3_share_t* out);
+
+/* Post-processing verification (Sec. 3): for the pending products selected by
+ * kinds (MPC3_VERIFY_* mask), one Pi_BIVerify^R per Pi_Inner call (compressed
+ * with the separable challenge r^(mN+n) = (r^N)^m r^n), one per chunk of
+ * truncation gates, and one Pi_MultVerify^R per Pi_Mult call.  R < 0 picks
+ * max(0, ceil(log2 n) - 3).  *ok = 1 iff every Delta is 0; otherwise *ok = 0
+ * and the context is aborted.  Synchronises. */
+int mpc3_verify(mpc3_ctx* ctx, int R, int kinds, int* ok);
+
+/* Pi_Rec (Preliminaries, "Verifiability of share reconstruction"): open X
+ * into out_dev (rows*cols words) after cross-checking the copies each party
+ * received.  Requires every pending product to be verified (else
+ * MPC3_E_UNVERIFIED); an inconsistency aborts.  to_party < 0 opens to all.
+ * Synchronises. */
+int mpc3_reconstruct(mpc3_ctx* ctx, const mpc3_share_t* X, int to_party, uint64_t* out_dev);
+
+/* Counted communication so far (host struct).  Synchronises. */
+int mpc3_comm_stats(mpc3_ctx* ctx, mpc3_comm* out);
+
+/* Testing: add e (mod 2^64) to one word of the next message at site
+ * (MPC3_SITE_*).  The error models the additive attack of a malicious party. */
+int mpc3_inject(mpc3_ctx* ctx, int site, int64_t index, uint64_t e);
+
+/* Testing: copy n words of message `which` (MPC3_MSG_*) of the most recent
+ * Pi_Inner or Pi_Mult into out_dev.  Needs mpc3_keep_messages(ctx, 1). */
+int mpc3_message(mpc3_ctx* ctx, int kind /* 0 inner, 1 mult */, int which, uint64_t* out_dev, int64_t n);
+
+/* Testing: d words of one transcript slot (MPC3_LOG_*) of verification
+ * instance `instance` of the most recent mpc3_verify, into host memory.
+ * Also reports the instance's R and padded dimension when the pointers are
+ * not NULL. */
+int mpc3_verify_log(mpc3_ctx* ctx, int64_t instance, int slot, int round, uint64_t* out_host,
+                    int* R_out, int64_t* dim_out);
+
+/* Measurement: while on, every Pi_Inner matrix-product launch is bracketed by HIP
+ * events on the context's stream.  mpc3_profile_read synchronises and returns the
+ * summed event time (ms), the number of launches and their algorithmic work in ring
+ * multiply-accumulates (5 M K N per Pi_Inner: P0 1, P1 2, P2 2), then clears them. */
+int mpc3_profile(mpc3_ctx* ctx, int on);
+int mpc3_profile_read(mpc3_ctx* ctx, double* total_ms, int64_t* launches, double* ring_macs);
+
+/* Static description of a return code. */
+const char* mpc3_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPC3_H */

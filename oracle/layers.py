@@ -1,0 +1,27 @@
+"""Convolution lowering (oracle; test infrastructure only).
+
+Sec. 4.1 evaluates a convolution as one inner product per output.  A stride-1
+convolution of an NHWC tensor with KH x KW x C kernels and zero padding p is the
+matrix product of the rows (b, oh, ow) of the patch matrix, whose columns are
+(kh, kw, c), with the weights reshaped to (KH*KW*C) x Cout.  Each share plane is
+rearranged alone, which is local and linear.
+"""
+import numpy as np
+
+
+def im2col(x, kh, kw, pad):
+    """x: (B, H, W, C) uint64 plane -> (B*OH*OW, KH*KW*C)."""
+    B, H, W, C = x.shape
+    xp = np.zeros((B, H + 2 * pad, W + 2 * pad, C), dtype=np.uint64)
+    xp[:, pad:pad + H, pad:pad + W, :] = x
+    OH, OW = H + 2 * pad - kh + 1, W + 2 * pad - kw + 1
+    out = np.zeros((B, OH, OW, kh, kw, C), dtype=np.uint64)
+    for i in range(kh):
+        for j in range(kw):
+            out[:, :, :, i, j, :] = xp[:, i:i + OH, j:j + OW, :]
+    return out.reshape(B * OH * OW, kh * kw * C)
+
+
+def im2col_share(s, kh, kw, pad):
+    from .protocol import Share
+    return Share(*[im2col(p, kh, kw, pad) for p in s.comps()])

@@ -535,15 +535,20 @@ class Ctx:
         z = Share(*[gr.scale(v.reshape(-1), pw).sum(axis=0, dtype=U64) for v in c.comps()])
         return x, y, z
 
-    def verify(self, R=-1, literal=False):
+    KIND = {"inner": 1, "trunc": 2, "mult": 4}
+
+    def verify(self, R=-1, literal=False, kinds=7):
         """Post-processing: one Pi_BIVerify per Pi_Inner call, the truncation gates in
-        chunks, one Pi_MultVerify per Pi_Mult call; abort unless every Delta is 0."""
+        chunks, one Pi_MultVerify per Pi_Mult call; abort unless every Delta is 0.
+        `kinds` selects which pending products are verified now (1 inner, 2 trunc, 4 mult)."""
         self.check()
         op = self.next_op()
         ok = True
         s = 0
         self.vlog = []
-        for item in self.pending:
+        selected = [it for it in self.pending if self.KIND[it[0]] & kinds]
+        rest = [it for it in self.pending if not self.KIND[it[0]] & kinds]
+        for item in selected:
             if item[0] == "inner":
                 _, X, W, Z = item
                 log = {"kind": "inner", "s": s}
@@ -574,7 +579,7 @@ class Ctx:
                 ok &= self.fold_and_check(x, y, z, op, s, R, log)
                 self.vlog.append(log)
                 s += 1
-        self.pending = []
+        self.pending = rest
         if not ok:
             self.aborted = True
         return bool(ok)

@@ -1,0 +1,937 @@
+// Protocol engine: the parties' steps as launches on one HIP stream, the pending-product
+// registry, communication counters, message-error injection and the C ABI of mpc3.h.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <stdexcept>
+#include <vector>
+
+#include "../../include/mpc3.h"
+#include "gemm.h"
+#include "host_util.h"
+#include "kernels.h"
+
+using namespace mpc3;
+
+namespace {
+
+struct HipError : std::runtime_error {
+    HipError() : std::runtime_error("hip") {}
+};
+struct CodeError : std::runtime_error {
+    int code;
+    explicit CodeError(int c) : std::runtime_error("code"), code(c) {}
+};
+
+inline void ck(hipError_t e) {
+    if (e != hipSuccess) throw HipError();
+}
+
+// Bump allocator over cached device blocks; reset at the start of each call.  Reuse is safe
+// because every launch of the context is ordered on its one stream.
+struct Scratch {
+    struct Blk {
+        char* p;
+        size_t cap;
+    };
+    std::vector<Blk> blks;
+    size_t cur = 0, off = 0;
+    struct Mark {
+        size_t cur, off;
+    };
+    void reset() { cur = 0; off = 0; }
+    Mark mark() const { return Mark{cur, off}; }
+    void restore(Mark m) { cur = m.cur; off = m.off; }
+    void* alloc(size_t n) {
+        n = (n + 255) & ~(size_t)255;
+        if (n == 0) n = 256;
+        while (cur < blks.size()) {
+            if (off + n <= blks[cur].cap) {
+                void* p = blks[cur].p + off;
+                off += n;
+                return p;
+            }
+            ++cur;
+            off = 0;
+        }
+        const size_t cap = std::max(n, (size_t)256 << 20);
+        void* p = nullptr;
+        if (hipMalloc(&p, cap) != hipSuccess) throw CodeError(MPC3_E_NOMEM);
+        blks.push_back(Blk{(char*)p, cap});
+        cur = blks.size() - 1;
+        off = n;
+        return p;
+    }
+    u64* words(int64_t n) { return (u64*)alloc((size_t)std::max<int64_t>(n, 1) * 8); }
+    void release() {
+        for (auto& b : blks) (void)hipFree(b.p);
+        blks.clear();
+        reset();
+    }
+};
+
+struct InjSlot {
+    bool active = false;
+    int64_t index = 0;
+    uint64_t e = 0;
+};
+
+struct Pending {
+    int kind;          // MPC3_VERIFY_INNER / TRUNC / MULT
+    mpc3_share_t X, W, Z;
+    mpc3_trunc_pair_t pair;
+    uint32_t op;
+};
+
+constexpr int RMAX = 40;
+constexpr int NSLOT = 2 + 7 * RMAX + 4;
+
+struct InstanceInfo {
+    int R;
+    int64_t npad;
+};
+
+}  // namespace
+
+struct mpc3_ctx {
+    Keys keys;
+    hipStream_t stream = nullptr;
+    int variant = MPC3_VARIANT_U64;
+    int frac = 13;
+    int64_t chunk = 1 << 14;
+    bool keep_msgs = false;
+    bool aborted = false;
+    uint32_t op = 0;
+    uint64_t bytes[4][3][3] = {};
+    uint32_t rounds[4] = {};
+    std::vector<Pending> pending;
+    InjSlot inj[16];
+    Scratch scratch;
+    u64* inv_dev = nullptr;    // inv_x, inv_(1-x), inv_(x(x-1))
+    // messages of the last Pi_Inner / Pi_Mult
+    u64* msg[2][3] = {};
+    int64_t msg_cap[2] = {0, 0};
+    int64_t msg_n[2] = {0, 0};
+    // public transcript of the last verification
+    std::vector<uint64_t> vlog;
+    std::vector<InstanceInfo> vinfo;
+    // launch timing of the Pi_Inner products
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    double prof_macs = 0;
+};
+
+namespace {
+
+void send(mpc3_ctx* c, int ph, int s, int d, uint64_t n) { c->bytes[ph][s][d] += n; }
+
+// Pi_Rec of a d-word value: P0 sends [r]_1 to P2 and [r]_2 to P1, P1 sends m to P0, three hashes.
+void count_reveal(mpc3_ctx* c, int ph) {
+    send(c, ph, 0, 2, 8 * 64);
+    send(c, ph, 0, 1, 8 * 64);
+    send(c, ph, 1, 0, 8 * 64);
+    send(c, ph, 1, 2, 32);
+    send(c, ph, 2, 0, 32);
+    send(c, ph, 2, 1, 32);
+    c->rounds[ph] += 1;
+}
+
+Inj take(mpc3_ctx* c, int site, int64_t limit) {
+    InjSlot& s = c->inj[site];
+    if (!s.active || s.index < 0 || s.index >= limit) return Inj{-1, 0};
+    s.active = false;
+    return Inj{s.index, s.e};
+}
+
+// verification-phase sites: index = instance << 16 | round << 8 | coefficient
+Inj take_ver(mpc3_ctx* c, int site, int64_t inst, int round) {
+    InjSlot& s = c->inj[site];
+    if (!s.active) return Inj{-1, 0};
+    const int64_t ii = s.index >> 16;
+    const int rr = (int)((s.index >> 8) & 0xFF);
+    if (ii != inst || (round >= 0 && rr != round)) return Inj{-1, 0};
+    s.active = false;
+    return Inj{s.index & 0xFF, s.e};
+}
+
+View view(const u64* p, int64_t s0, int64_t s1, int64_t sb = 0) { return View{p, s0, s1, sb}; }
+OutView oview(u64* p, int64_t s0, int64_t s1, int64_t sb = 0) { return OutView{p, s0, s1, sb}; }
+
+void run_gemm(mpc3_ctx* c, const GemmArgs& g) { ck(gemm(g, c->variant, c->stream)); }
+
+GemmArgs plain(int64_t M, int64_t N, int64_t K, View A, View B, OutView C, bool acc, int batch = 1) {
+    GemmArgs g{};
+    g.M = M; g.N = N; g.K = K; g.batch = batch; g.party = false; g.accumulate = acc;
+    g.A[0] = A; g.B[0] = B; g.C[0] = C;
+    g.Dadd = View{nullptr, 0, 0, 0};
+    return g;
+}
+
+void zero(mpc3_ctx* c, void* p, size_t bytes) { ck(hipMemsetAsync(p, 0, bytes, c->stream)); }
+
+// table[i] = base^i for i < n (table: n x 64), doubling: table[len + i] = table[i] base^len.
+void power_table(mpc3_ctx* c, const u64* base, int64_t n, u64* table) {
+    hipStream_t s = c->stream;
+    launch_set_one(table, s);
+    if (n <= 1) return;
+    Scratch::Mark mk = c->scratch.mark();
+    u64* P = c->scratch.words(64);
+    u64* P2 = c->scratch.words(64);
+    u64* WP = c->scratch.words(4096);
+    ck(hipMemcpyAsync(P, base, 512, hipMemcpyDeviceToDevice, s));
+    for (int64_t len = 1; len < n; len *= 2) {
+        const int64_t cnt = std::min(len, n - len);
+        launch_mulmat(P, 64, 1, WP, s);
+        run_gemm(c, plain(cnt, 64, 64, view(table, 64, 1), view(WP, 64, 1), oview(table + len * 64, 64, 1), false));
+        if (2 * len < n) {
+            run_gemm(c, plain(1, 64, 64, view(P, 64, 1), view(WP, 64, 1), oview(P2, 64, 1), false));
+            std::swap(P, P2);
+        }
+    }
+    c->scratch.restore(mk);
+}
+
+int auto_rounds(int64_t n0, int R) {
+    int need = 0;
+    while (((int64_t)1 << need) < n0) ++need;
+    if (R < 0) R = std::max(0, need - 3);
+    return std::min(R, need);
+}
+
+int64_t padded(int64_t n0, int R) {
+    const int64_t b = (int64_t)1 << R;
+    return (n0 + b - 1) / b * b;
+}
+
+struct VerCtx {
+    uint32_t op;
+    int64_t inst;
+    u64* log;      // device transcript base for this instance (NSLOT x 64)
+    int* flag;     // device flag of this instance
+};
+
+u64* slot(const VerCtx& v, int s, int round = 0) {
+    switch (s) {
+        case MPC3_LOG_R: return v.log;
+        case MPC3_LOG_Z: return v.log + 64;
+        case MPC3_LOG_DELTA: return v.log + (2 + 7 * RMAX) * 64;
+        case MPC3_LOG_DELTA_M1: return v.log + (3 + 7 * RMAX) * 64;
+        case MPC3_LOG_DELTA_M2: return v.log + (4 + 7 * RMAX) * 64;
+        case MPC3_LOG_DELTA_G2: return v.log + (5 + 7 * RMAX) * 64;
+        default: return v.log + (2 + 7 * round + (s - MPC3_LOG_ZETA)) * 64;
+    }
+}
+
+// Party product of two strided element lists (P0, P1, P2 sums) into C0..C2 (3 x 64x64, zeroed).
+void gr_dot_party(mpc3_ctx* c, int64_t n, const u64* A[3], int64_t astride, const u64* B[3], int64_t bstride,
+                  u64* C) {
+    GemmArgs g{};
+    g.M = 64; g.N = 64; g.K = n; g.batch = 1; g.party = true; g.accumulate = true;
+    for (int p = 0; p < 3; ++p) {
+        g.A[p] = view(A[p], 1, astride);      // (coefficient j, element i)
+        g.B[p] = view(B[p], bstride, 1);      // (element i, coefficient l)
+        g.C[p] = oview(C + p * 4096, 64, 1);
+    }
+    zero(c, C, 3 * 4096 * 8);
+    run_gemm(c, g);
+}
+
+// Pi_PolyEvl over GR of pairs (a_i, b_i) given by plane pointers and row strides.
+void polyevl_run(mpc3_ctx* c, const VerCtx& v, int64_t n, const u64* A[3], int64_t astride, const u64* B[3],
+                 int64_t bstride, uint32_t pr, uint32_t pg, uint32_t sub, Inj im1, Inj ig2, u64* out, u64* lm1,
+                 u64* lm2, u64* lg2, u64* reveal, int* flag) {
+    u64* C = c->scratch.words(3 * 4096);
+    gr_dot_party(c, n, A, astride, B, bstride, C);
+    PolyEvlArgs a{};
+    a.C = C; a.k = c->keys; a.op = v.op; a.pr = pr; a.pg = pg; a.sub = sub;
+    a.inj_m1 = im1.index >= 0 ? (int)im1.index : -1; a.e_m1 = im1.e;
+    a.inj_g2 = ig2.index >= 0 ? (int)ig2.index : -1; a.e_g2 = ig2.e;
+    a.out = out; a.log_m1 = lm1; a.log_m2 = lm2; a.log_g2 = lg2; a.reveal = reveal; a.nonzero_flag = flag;
+    launch_polyevl_finish(a, c->stream);
+    // one Pi_PolyEvl: P0 -> P2 [Gamma]_2 (verification offline), P1 <-> P2 (verification online)
+    send(c, MPC3_PH_VERIFY_OFFLINE, 0, 2, 8 * 64);
+    send(c, MPC3_PH_VERIFY_ONLINE, 1, 2, 8 * 64);
+    send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8 * 64);
+}
+
+// R x Pi_Reduce, then Pi_InnerVerify.  XY: 6 planes (x: m, r1, r2; y: m, r1, r2) of n rows.
+void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, int R) {
+    hipStream_t s = c->stream;
+    for (int k = 0; k < R; ++k) {
+        const int64_t half = n / 2;
+        const uint32_t sub = ((uint32_t)v.inst << 8) | (uint32_t)k;
+        u64* h0 = c->scratch.words(3 * 64);
+        u64* h2 = c->scratch.words(3 * 64);
+        {   // h(0) = sum f_i(0) g_i(0): rows 2i of x and y
+            const u64* A[3] = {XY, XY + n * 64, XY + 2 * n * 64};
+            const u64* B[3] = {XY + 3 * n * 64, XY + 4 * n * 64, XY + 5 * n * 64};
+            polyevl_run(c, v, half, A, 128, B, 128, P_VER_H0_R, P_VER_H0_GAMMA, sub,
+                        take_ver(c, MPC3_SITE_VER_H0_M1, v.inst, k), Inj{-1, 0}, h0, slot(v, MPC3_LOG_H0_M1, k),
+                        slot(v, MPC3_LOG_H0_M2, k), slot(v, MPC3_LOG_H0_G2, k), nullptr, nullptr);
+        }
+        {   // h(x) = sum f_i(x) g_i(x), f_i(x) = f_i(0) + x (f_i(1) - f_i(0))
+            u64* F2 = c->scratch.words(6 * half * 64);
+            launch_at_x(XY, 6, n, F2, s);
+            const u64* A[3] = {F2, F2 + half * 64, F2 + 2 * half * 64};
+            const u64* B[3] = {F2 + 3 * half * 64, F2 + 4 * half * 64, F2 + 5 * half * 64};
+            polyevl_run(c, v, half, A, 64, B, 64, P_VER_H2_R, P_VER_H2_GAMMA, sub, Inj{-1, 0},
+                        take_ver(c, MPC3_SITE_VER_H2_GAMMA2, v.inst, k), h2, slot(v, MPC3_LOG_H2_M1, k),
+                        slot(v, MPC3_LOG_H2_M2, k), slot(v, MPC3_LOG_H2_G2, k), nullptr, nullptr);
+        }
+        c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
+        u64* zeta = c->scratch.words(64);
+        RoundArgs ra{};
+        ra.k = c->keys; ra.op = v.op; ra.sub = sub; ra.inv = c->inv_dev; ra.h0 = h0; ra.h2 = h2; ra.z = z;
+        ra.zeta_out = zeta; ra.log_zeta = slot(v, MPC3_LOG_ZETA, k);
+        launch_round_finish(ra, s);
+        count_reveal(c, MPC3_PH_VERIFY_ONLINE);
+        // fold: row i <- f_i(0) + zeta (f_i(1) - f_i(0)) for all six planes
+        u64* Wz = c->scratch.words(4096);
+        launch_mulmat(zeta, 64, 1, Wz, s);
+        u64* Dd = c->scratch.words(6 * half * 64);
+        launch_sub_pairs(XY, 6, n, Dd, s);
+        u64* XYn = c->scratch.words(6 * half * 64);
+        GemmArgs g = plain(half, 64, 64, view(Dd, 64, 1, half * 64), view(Wz, 64, 1, 0),
+                           oview(XYn, 64, 1, half * 64), false, 6);
+        g.Dadd = view(XY, 128, 1, n * 64);
+        run_gemm(c, g);
+        XY = XYn;
+        n = half;
+    }
+    // Pi_InnerVerify
+    u64* alpha = c->scratch.words(3 * 64);
+    launch_random_gr(c->keys, v.op, P_VER_ALPHA, (uint32_t)v.inst, alpha, nullptr, nullptr, s);
+    u64* Wa = c->scratch.words(3 * 4096);
+    launch_mulmat(alpha, 64, 3, Wa, s);
+    u64* C = c->scratch.words(3 * n * 64);
+    {
+        GemmArgs g{};
+        g.M = n; g.N = 64; g.K = 64; g.batch = 1; g.party = true; g.accumulate = false;
+        for (int p = 0; p < 3; ++p) {
+            g.A[p] = view(XY + p * n * 64, 64, 1);
+            g.B[p] = view(Wa + p * 4096, 64, 1);
+            g.C[p] = oview(C + p * n * 64, 64, 1);
+        }
+        run_gemm(c, g);
+    }
+    const int64_t n1 = n + 1;
+    u64* XP = c->scratch.words(3 * n1 * 64);
+    // x'_i = Pi_Mult(x_i, alpha): rows 0..n-1 of each plane; row n = -alpha
+    {
+        u64* tmp = c->scratch.words(3 * n * 64);
+        launch_xp_epilogue(n, c->keys, v.op, (uint32_t)v.inst, C, C + n * 64, C + 2 * n * 64, tmp, tmp + n * 64,
+                           tmp + 2 * n * 64, s);
+        for (int p = 0; p < 3; ++p)
+            ck(hipMemcpyAsync(XP + p * n1 * 64, tmp + p * n * 64, n * 512, hipMemcpyDeviceToDevice, s));
+        launch_neg_elem(alpha, 64, XP + n * 64, n1 * 64, s);
+    }
+    send(c, MPC3_PH_VERIFY_OFFLINE, 0, 2, 8 * 64 * n);
+    send(c, MPC3_PH_VERIFY_ONLINE, 1, 2, 8 * 64 * n);
+    send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8 * 64 * n);
+    c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
+    u64* YZ = c->scratch.words(3 * n1 * 64);
+    for (int p = 0; p < 3; ++p) {
+        ck(hipMemcpyAsync(YZ + p * n1 * 64, XY + (3 + p) * n * 64, n * 512, hipMemcpyDeviceToDevice, s));
+        ck(hipMemcpyAsync(YZ + p * n1 * 64 + n * 64, z + p * 64, 512, hipMemcpyDeviceToDevice, s));
+    }
+    u64* delta = c->scratch.words(3 * 64);
+    const u64* A[3] = {XP, XP + n1 * 64, XP + 2 * n1 * 64};
+    const u64* B[3] = {YZ, YZ + n1 * 64, YZ + 2 * n1 * 64};
+    polyevl_run(c, v, n1, A, 64, B, 64, P_VER_DELTA_R, P_VER_DELTA_GAMMA, (uint32_t)v.inst,
+                take_ver(c, MPC3_SITE_VER_DELTA_M1, v.inst, -1), Inj{-1, 0}, delta, slot(v, MPC3_LOG_DELTA_M1),
+                slot(v, MPC3_LOG_DELTA_M2), slot(v, MPC3_LOG_DELTA_G2), slot(v, MPC3_LOG_DELTA), v.flag);
+    c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
+    count_reveal(c, MPC3_PH_VERIFY_ONLINE);
+}
+
+u64* challenge(mpc3_ctx* c, const VerCtx& v) {
+    u64* r = c->scratch.words(64);
+    launch_random_gr(c->keys, v.op, P_VER_R, (uint32_t)v.inst, nullptr, r, slot(v, MPC3_LOG_R), c->stream);
+    count_reveal(c, MPC3_PH_VERIFY_ONLINE);
+    return r;
+}
+
+void verify_inner(mpc3_ctx* c, const VerCtx& v, const Pending& it, int Rarg) {
+    hipStream_t s = c->stream;
+    const int64_t M = it.X.rows, K = it.X.cols, N = it.W.cols;
+    u64* r = challenge(c, v);
+    u64* sigma = c->scratch.words(N * 64);
+    power_table(c, r, N, sigma);
+    u64* rN = c->scratch.words(64);
+    {
+        u64* Wr = c->scratch.words(4096);
+        launch_mulmat(r, 64, 1, Wr, s);
+        run_gemm(c, plain(1, 64, 64, view(sigma + (N - 1) * 64, 64, 1), view(Wr, 64, 1), oview(rN, 64, 1), false));
+    }
+    u64* rho = c->scratch.words(M * 64);
+    power_table(c, rN, M, rho);
+    const int R = auto_rounds(K, Rarg);
+    const int64_t np = padded(K, R);
+    u64* XY = c->scratch.words(6 * np * 64);
+    zero(c, XY, (size_t)6 * np * 64 * 8);
+    const u64* Xc[3] = {it.X.m, it.X.r1, it.X.r2};
+    const u64* Wc[3] = {it.W.m, it.W.r1, it.W.r2};
+    const u64* Zc[3] = {it.Z.m, it.Z.r1, it.Z.r2};
+    for (int p = 0; p < 3; ++p) {
+        // U_k = sum_m rho_m X[m, k]   (K x 64)
+        run_gemm(c, plain(K, 64, M, view(Xc[p], 1, K), view(rho, 64, 1), oview(XY + p * np * 64, 64, 1), true));
+        // V_k = sum_n sigma_n W[k, n] (K x 64)
+        run_gemm(c, plain(K, 64, N, view(Wc[p], N, 1), view(sigma, 64, 1), oview(XY + (3 + p) * np * 64, 64, 1),
+                          true));
+    }
+    u64* z = c->scratch.words(3 * 64);
+    {
+        u64* T = c->scratch.words(3 * N * 64);
+        zero(c, T, (size_t)3 * N * 64 * 8);
+        u64* Cz = c->scratch.words(3 * 4096);
+        zero(c, Cz, 3 * 4096 * 8);
+        for (int p = 0; p < 3; ++p) {
+            // T_n = sum_m rho_m Z[m, n]; z = sum_n sigma_n T_n (ring products, anti-diagonal fold)
+            run_gemm(c, plain(N, 64, M, view(Zc[p], 1, N), view(rho, 64, 1), oview(T + p * N * 64, 64, 1), true));
+            run_gemm(c, plain(64, 64, N, view(sigma, 1, 64), view(T + p * N * 64, 64, 1), oview(Cz + p * 4096, 64, 1),
+                              true));
+        }
+        launch_fold_plain(Cz, 3, z, s);
+    }
+    ck(hipMemcpyAsync(slot(v, MPC3_LOG_Z), z, 512, hipMemcpyDeviceToDevice, s));
+    c->vinfo.push_back(InstanceInfo{R, np});
+    fold_and_check(c, v, XY, np, z, R);
+}
+
+void verify_mult(mpc3_ctx* c, const VerCtx& v, const Pending& it, int Rarg) {
+    hipStream_t s = c->stream;
+    const int64_t n = it.X.rows * it.X.cols;
+    u64* r = challenge(c, v);
+    u64* pw = c->scratch.words(n * 64);
+    power_table(c, r, n, pw);
+    const int R = auto_rounds(n, Rarg);
+    const int64_t np = padded(n, R);
+    u64* XY = c->scratch.words(6 * np * 64);
+    zero(c, XY, (size_t)6 * np * 64 * 8);
+    launch_scale_rows(n, it.X.m, it.X.r1, it.X.r2, pw, XY, np * 64, s);      // x'_i = r^i a_i
+    launch_lift_rows(n, it.W.m, it.W.r1, it.W.r2, XY + 3 * np * 64, np * 64, s);
+    u64* z = c->scratch.words(3 * 64);
+    zero(c, z, 3 * 64 * 8);
+    const u64* Zc[3] = {it.Z.m, it.Z.r1, it.Z.r2};
+    for (int p = 0; p < 3; ++p)
+        run_gemm(c, plain(1, 64, n, view(Zc[p], 0, 1), view(pw, 64, 1), oview(z + p * 64, 64, 1), true));
+    ck(hipMemcpyAsync(slot(v, MPC3_LOG_Z), z, 512, hipMemcpyDeviceToDevice, s));
+    c->vinfo.push_back(InstanceInfo{R, np});
+    fold_and_check(c, v, XY, np, z, R);
+}
+
+void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t lo, int64_t T, int Rarg) {
+    hipStream_t s = c->stream;
+    const mpc3_trunc_pair_t& p = it.pair;
+    u64* r = challenge(c, v);
+    u64* pw = c->scratch.words(2 * T * 64);
+    power_table(c, r, 2 * T, pw);
+    const int64_t n0 = 128 * T;
+    const int R = auto_rounds(n0, Rarg);
+    const int64_t np = padded(n0, R);
+    u64* XY = c->scratch.words(6 * np * 64);
+    zero(c, XY, (size_t)6 * np * 64 * 8);
+    u64* B1 = c->scratch.words(T);
+    u64* B2 = c->scratch.words(T);
+    launch_fill_at(B1, T, lo, c->keys.k01, make_tag(it.op, P_TRUNC_B, 1, 0), s);
+    launch_fill_at(B2, T, lo, c->keys.k02, make_tag(it.op, P_TRUNC_B, 2, 0), s);
+    u64* w3 = c->scratch.words(6 * T);
+    launch_trunc_instance2(lo, T, p.t, B1, B2, pw, p.rx.m, p.rx.r1, p.rx.r2, p.rz.m, p.rz.r1, p.rz.r2,
+                           XY + 1 * np * 64, XY + 5 * np * 64, w3, s);
+    u64* z = c->scratch.words(3 * 64);
+    zero(c, z, 3 * 64 * 8);
+    for (int q = 0; q < 3; ++q)
+        run_gemm(c, plain(1, 64, 2 * T, view(w3 + q * 2 * T, 0, 1), view(pw, 64, 1), oview(z + q * 64, 64, 1), true));
+    ck(hipMemcpyAsync(slot(v, MPC3_LOG_Z), z, 512, hipMemcpyDeviceToDevice, s));
+    c->vinfo.push_back(InstanceInfo{R, np});
+    fold_and_check(c, v, XY, np, z, R);
+}
+
+int guard(mpc3_ctx* c) {
+    if (!c) return MPC3_E_ARG;
+    if (c->aborted) return MPC3_E_ABORTED;
+    return MPC3_OK;
+}
+
+template <class F>
+int wrap(F&& f) {
+    try {
+        return f();
+    } catch (const CodeError& e) {
+        return e.code;
+    } catch (const HipError&) {
+        return MPC3_E_HIP;
+    } catch (const std::bad_alloc&) {
+        return MPC3_E_NOMEM;
+    }
+}
+
+bool valid(const mpc3_share_t* s) { return s && s->m && s->r1 && s->r2 && s->rows >= 0 && s->cols >= 0; }
+
+void ensure_msgs(mpc3_ctx* c, int kind, int64_t n) {
+    if (c->msg_cap[kind] < n) {
+        for (int i = 0; i < 3; ++i) {
+            if (c->msg[kind][i]) (void)hipFree(c->msg[kind][i]);
+            void* p = nullptr;
+            if (hipMalloc(&p, (size_t)n * 8) != hipSuccess) throw CodeError(MPC3_E_NOMEM);
+            c->msg[kind][i] = (u64*)p;
+        }
+        c->msg_cap[kind] = n;
+    }
+    c->msg_n[kind] = n;
+}
+
+Key key_of(const uint8_t d[32]) {
+    Key k;
+    memcpy(k.w, d, 32);
+    return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpc3_ctx_create(const uint8_t master_seed[32], int d, int frac_bits, size_t workspace_bytes,
+                    void* hip_stream, mpc3_ctx** out) {
+    if (!master_seed || !out || d != 64 || frac_bits < 0 || frac_bits > 62) return MPC3_E_ARG;
+    return wrap([&] {
+        mpc3_ctx* c = new mpc3_ctx();
+        c->stream = (hipStream_t)hip_stream;
+        c->frac = frac_bits;
+        auto eta = [&](std::initializer_list<uint8_t> ids) {
+            host::Sha256 h;
+            h.update(master_seed, 32);
+            h.update("eta", 3);
+            for (uint8_t i : ids) h.update(&i, 1);
+            uint8_t dg[32];
+            h.final(dg);
+            return key_of(dg);
+        };
+        c->keys.k01 = eta({0, 1});
+        c->keys.k02 = eta({0, 2});
+        c->keys.k12 = eta({1, 2});
+        c->keys.kall = eta({0, 1, 2});
+        // 1/x, 1/(1-x), 1/(x(x-1)): Lagrange denominators over the nodes {0, 1, x}
+        host::Elem X(64, 0), one = host::gr_const(1);
+        X[1] = 1;
+        host::Elem omx(64), xm1(64);
+        for (int k = 0; k < 64; ++k) {
+            omx[k] = one[k] - X[k];
+            xm1[k] = X[k] - one[k];
+        }
+        host::Elem inv[3] = {host::gr_inv(X), host::gr_inv(omx), host::gr_inv(host::gr_mul(X, xm1))};
+        void* p = nullptr;
+        if (hipMalloc(&p, 3 * 512) != hipSuccess) {
+            delete c;
+            return (int)MPC3_E_NOMEM;
+        }
+        c->inv_dev = (u64*)p;
+        std::vector<uint64_t> hv(3 * 64);
+        for (int i = 0; i < 3; ++i) memcpy(hv.data() + 64 * i, inv[i].data(), 512);
+        if (hipMemcpy(c->inv_dev, hv.data(), 3 * 512, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(p);
+            delete c;
+            return (int)MPC3_E_HIP;
+        }
+        if (workspace_bytes) {
+            c->scratch.alloc(workspace_bytes);
+            c->scratch.reset();
+        }
+        *out = c;
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_ctx_destroy(mpc3_ctx* c) {
+    if (!c) return MPC3_E_ARG;
+    (void)hipStreamSynchronize(c->stream);
+    c->scratch.release();
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < 3; ++i)
+            if (c->msg[k][i]) (void)hipFree(c->msg[k][i]);
+    if (c->inv_dev) (void)hipFree(c->inv_dev);
+    delete c;
+    return MPC3_OK;
+}
+
+int mpc3_set_variant(mpc3_ctx* c, int variant) {
+    if (!c || (variant != MPC3_VARIANT_U64 && variant != MPC3_VARIANT_LIMB_I8)) return MPC3_E_ARG;
+    c->variant = variant;
+    return MPC3_OK;
+}
+
+int mpc3_set_chunk(mpc3_ctx* c, int64_t t) {
+    if (!c || t <= 0 || t > (1 << 20)) return MPC3_E_ARG;
+    c->chunk = t;
+    return MPC3_OK;
+}
+
+int mpc3_keep_messages(mpc3_ctx* c, int on) {
+    if (!c) return MPC3_E_ARG;
+    c->keep_msgs = on != 0;
+    return MPC3_OK;
+}
+
+int mpc3_encode(mpc3_ctx* c, const double* x, int64_t n, uint64_t* out) {
+    int g = guard(c);
+    if (g) return g;
+    if ((!x || !out) && n > 0) return MPC3_E_ARG;
+    return wrap([&] {
+        launch_encode(x, n, c->frac, out, c->stream);
+        ck(hipGetLastError());
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_decode(mpc3_ctx* c, const uint64_t* v, int64_t n, double* out) {
+    if (!c) return MPC3_E_ARG;
+    if ((!v || !out) && n > 0) return MPC3_E_ARG;
+    return wrap([&] {
+        launch_decode(v, n, c->frac, out, c->stream);
+        ck(hipGetLastError());
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_share(mpc3_ctx* c, int owner, const uint64_t* x, mpc3_share_t* out) {
+    int g = guard(c);
+    if (g) return g;
+    if (owner < 0 || owner > 2 || !valid(out) || (!x && out->rows * out->cols > 0)) return MPC3_E_ARG;
+    return wrap([&] {
+        const uint32_t op = c->op++;
+        const int64_t n = out->rows * out->cols;
+        const Key k1 = owner == 2 ? c->keys.kall : c->keys.k01;
+        const Key k2 = owner == 1 ? c->keys.kall : c->keys.k02;
+        launch_share(x, n, k1, make_tag(op, P_SHARE_R, 1, 0), k2, make_tag(op, P_SHARE_R, 2, 0), out->m, out->r1,
+                     out->r2, c->stream);
+        ck(hipGetLastError());
+        for (int dst = 1; dst <= 2; ++dst)
+            if (dst != owner) send(c, MPC3_PH_ONLINE, owner, dst, 8 * n);
+        c->rounds[MPC3_PH_ONLINE] += 1;
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_trunc_pair(mpc3_ctx* c, int64_t n, int t, mpc3_trunc_pair_t* out) {
+    int g = guard(c);
+    if (g) return g;
+    if (!out || n < 0 || t < 1 || t > 62 || !out->rx.m || !out->rx.r1 || !out->rx.r2 || !out->rz.m ||
+        !out->rz.r1 || !out->rz.r2)
+        return MPC3_E_ARG;
+    return wrap([&] {
+        const uint32_t op = c->op++;
+        out->t = t;
+        out->n = n;
+        out->id = op;
+        out->rx.rows = out->rz.rows = n;
+        out->rx.cols = out->rz.cols = 1;
+        launch_trunc_pair(n, t, c->keys, op, take(c, MPC3_SITE_TRUNC_GAMMA2, n), take(c, MPC3_SITE_TRUNC_M1, n),
+                          out->rx.m, out->rx.r1, out->rx.r2, out->rz.m, out->rz.r1, out->rz.r2, c->stream);
+        ck(hipGetLastError());
+        for (int q = 0; q < 2; ++q) {
+            send(c, MPC3_PH_OFFLINE, 0, 2, 8 * n);
+            send(c, MPC3_PH_OFFLINE, 1, 2, 8 * n);
+            send(c, MPC3_PH_OFFLINE, 2, 1, 8 * n);
+        }
+        c->rounds[MPC3_PH_OFFLINE] += 1;
+        Pending p{};
+        p.kind = MPC3_VERIFY_TRUNC;
+        p.pair = *out;
+        p.op = op;
+        c->pending.push_back(p);
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_inner(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W, const mpc3_trunc_pair_t* pair,
+               mpc3_share_t* Z) {
+    int g = guard(c);
+    if (g) return g;
+    if (!valid(X) || !valid(W) || !valid(Z)) return MPC3_E_ARG;
+    const int64_t M = X->rows, K = X->cols, N = W->cols;
+    if (W->rows != K || Z->rows != M || Z->cols != N) return MPC3_E_SHAPE;
+    if (pair && pair->n != M * N) return MPC3_E_SHAPE;
+    return wrap([&] {
+        const uint32_t op = c->op++;
+        const int64_t n = M * N;
+        hipStream_t s = c->stream;
+        c->scratch.reset();
+        u64* G1 = c->scratch.words(n);
+        u64* C = c->scratch.words(3 * n);
+        launch_inner_pre(n, c->keys, op, pair ? pair->rx.m : nullptr, pair ? pair->rx.r1 : nullptr,
+                         pair ? pair->rx.r2 : nullptr, Z->r1, Z->r2, G1, s);
+        GemmArgs ga{};
+        ga.M = M; ga.N = N; ga.K = K; ga.batch = 1; ga.party = true; ga.accumulate = false;
+        const u64* Xp[3] = {X->m, X->r1, X->r2};
+        const u64* Wp[3] = {W->m, W->r1, W->r2};
+        for (int p = 0; p < 3; ++p) {
+            ga.A[p] = view(Xp[p], K, 1);
+            ga.B[p] = view(Wp[p], N, 1);
+            ga.C[p] = oview(C + p * n, N, 1);
+        }
+        if (K == 0) {
+            zero(c, C, (size_t)3 * n * 8);
+        } else if (c->prof) {
+            hipEvent_t e0, e1;
+            ck(hipEventCreate(&e0));
+            ck(hipEventCreate(&e1));
+            ck(hipEventRecord(e0, s));
+            run_gemm(c, ga);
+            ck(hipEventRecord(e1, s));
+            c->ev.push_back({e0, e1});
+            c->prof_macs += 5.0 * (double)M * (double)K * (double)N;
+        } else {
+            run_gemm(c, ga);
+        }
+        u64 *mg2 = nullptr, *mm1 = nullptr, *mm2 = nullptr;
+        if (c->keep_msgs) {
+            ensure_msgs(c, 0, n);
+            mg2 = c->msg[0][0]; mm1 = c->msg[0][1]; mm2 = c->msg[0][2];
+        }
+        launch_inner_post(n, C, C + n, C + 2 * n, Z->r1, Z->r2, G1, take(c, MPC3_SITE_INNER_GAMMA2, n),
+                          take(c, MPC3_SITE_INNER_M1, n), Z->m, mg2, mm1, mm2, s);
+        ck(hipGetLastError());
+        send(c, MPC3_PH_OFFLINE, 0, 2, 8 * n);
+        c->rounds[MPC3_PH_OFFLINE] += 1;
+        send(c, MPC3_PH_ONLINE, 1, 2, 8 * n);
+        send(c, MPC3_PH_ONLINE, 2, 1, 8 * n);
+        c->rounds[MPC3_PH_ONLINE] += 1;
+        Pending p{};
+        p.kind = MPC3_VERIFY_INNER;
+        p.X = *X; p.W = *W; p.Z = *Z;
+        p.op = op;
+        c->pending.push_back(p);
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_im2col(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, int KH, int KW, int pad,
+                mpc3_share_t* cols) {
+    int g = guard(c);
+    if (g) return g;
+    if (!valid(x) || !valid(cols) || B < 0 || H <= 0 || W <= 0 || C <= 0 || KH <= 0 || KW <= 0 || pad < 0)
+        return MPC3_E_ARG;
+    const int OH = H + 2 * pad - KH + 1, OW = W + 2 * pad - KW + 1;
+    if (OH <= 0 || OW <= 0) return MPC3_E_SHAPE;
+    if (x->rows * x->cols != (int64_t)B * H * W * C) return MPC3_E_SHAPE;
+    if (cols->rows != (int64_t)B * OH * OW || cols->cols != (int64_t)KH * KW * C) return MPC3_E_SHAPE;
+    return wrap([&] {
+        launch_im2col(x->m, B, H, W, C, KH, KW, pad, cols->m, c->stream);
+        launch_im2col(x->r1, B, H, W, C, KH, KW, pad, cols->r1, c->stream);
+        launch_im2col(x->r2, B, H, W, C, KH, KW, pad, cols->r2, c->stream);
+        ck(hipGetLastError());
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_mult(mpc3_ctx* c, const mpc3_share_t* a, const mpc3_share_t* b, mpc3_share_t* o) {
+    int g = guard(c);
+    if (g) return g;
+    if (!valid(a) || !valid(b) || !valid(o)) return MPC3_E_ARG;
+    const int64_t n = a->rows * a->cols;
+    if (b->rows * b->cols != n || o->rows * o->cols != n) return MPC3_E_SHAPE;
+    return wrap([&] {
+        const uint32_t op = c->op++;
+        u64 *mg2 = nullptr, *mm1 = nullptr, *mm2 = nullptr;
+        if (c->keep_msgs) {
+            ensure_msgs(c, 1, n);
+            mg2 = c->msg[1][0]; mm1 = c->msg[1][1]; mm2 = c->msg[1][2];
+        }
+        launch_mult(n, c->keys, op, a->m, a->r1, a->r2, b->m, b->r1, b->r2, take(c, MPC3_SITE_MULT_GAMMA2, n), o->m,
+                    o->r1, o->r2, mg2, mm1, mm2, c->stream);
+        ck(hipGetLastError());
+        send(c, MPC3_PH_OFFLINE, 0, 2, 8 * n);
+        c->rounds[MPC3_PH_OFFLINE] += 1;
+        send(c, MPC3_PH_ONLINE, 1, 2, 8 * n);
+        send(c, MPC3_PH_ONLINE, 2, 1, 8 * n);
+        c->rounds[MPC3_PH_ONLINE] += 1;
+        Pending p{};
+        p.kind = MPC3_VERIFY_MULT;
+        p.X = *a; p.W = *b; p.Z = *o;
+        p.op = op;
+        c->pending.push_back(p);
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_trunc(mpc3_ctx* c, const mpc3_trunc_pair_t* p, const mpc3_share_t* Z, mpc3_share_t* out) {
+    int g = guard(c);
+    if (g) return g;
+    if (!p || !valid(Z) || !valid(out)) return MPC3_E_ARG;
+    const int64_t n = Z->rows * Z->cols;
+    if (p->n != n || out->rows * out->cols != n) return MPC3_E_SHAPE;
+    return wrap([&] {
+        launch_trunc_shift(n, p->t, Z->m, p->rz.m, p->rz.r1, p->rz.r2, out->m, out->r1, out->r2, c->stream);
+        ck(hipGetLastError());
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_verify(mpc3_ctx* c, int R, int kinds, int* ok) {
+    int g = guard(c);
+    if (g) return g;
+    if (!ok || R > RMAX || kinds <= 0 || kinds > MPC3_VERIFY_ALL) return MPC3_E_ARG;
+    return wrap([&] {
+        const uint32_t op = c->op++;
+        hipStream_t s = c->stream;
+        c->scratch.reset();
+        std::vector<Pending> sel, rest;
+        for (auto& p : c->pending) (p.kind & kinds ? sel : rest).push_back(p);
+        int64_t ninst = 0;
+        for (auto& p : sel)
+            ninst += p.kind == MPC3_VERIFY_TRUNC ? (p.pair.n + c->chunk - 1) / c->chunk : 1;
+        u64* logd = c->scratch.words(std::max<int64_t>(ninst, 1) * NSLOT * 64);
+        int* flags = (int*)c->scratch.alloc(std::max<int64_t>(ninst, 1) * sizeof(int));
+        zero(c, logd, (size_t)std::max<int64_t>(ninst, 1) * NSLOT * 64 * 8);
+        zero(c, flags, std::max<int64_t>(ninst, 1) * sizeof(int));
+        c->vinfo.clear();
+        int64_t inst = 0;
+        for (auto& p : sel) {
+            if (p.kind == MPC3_VERIFY_TRUNC) {
+                for (int64_t lo = 0; lo < p.pair.n; lo += c->chunk) {
+                    const int64_t T = std::min(c->chunk, p.pair.n - lo);
+                    Scratch::Mark mk = c->scratch.mark();
+                    VerCtx v{op, inst, logd + inst * NSLOT * 64, flags + inst};
+                    verify_trunc_chunk(c, v, p, lo, T, R);
+                    c->scratch.restore(mk);
+                    ++inst;
+                }
+            } else {
+                Scratch::Mark mk = c->scratch.mark();
+                VerCtx v{op, inst, logd + inst * NSLOT * 64, flags + inst};
+                if (p.kind == MPC3_VERIFY_INNER) verify_inner(c, v, p, R);
+                else verify_mult(c, v, p, R);
+                c->scratch.restore(mk);
+                ++inst;
+            }
+        }
+        std::vector<int> hflags(std::max<int64_t>(ninst, 1), 0);
+        c->vlog.assign((size_t)std::max<int64_t>(ninst, 1) * NSLOT * 64, 0);
+        ck(hipMemcpyAsync(hflags.data(), flags, hflags.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+        ck(hipMemcpyAsync(c->vlog.data(), logd, c->vlog.size() * 8, hipMemcpyDeviceToHost, s));
+        ck(hipStreamSynchronize(s));
+        c->pending = rest;
+        bool pass = true;
+        for (int64_t i = 0; i < ninst; ++i) pass = pass && hflags[i] == 0;
+        *ok = pass ? 1 : 0;
+        if (!pass) c->aborted = true;
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_reconstruct(mpc3_ctx* c, const mpc3_share_t* X, int to_party, uint64_t* out) {
+    int g = guard(c);
+    if (g) return g;
+    if (!valid(X) || !out || to_party > 2) return MPC3_E_ARG;
+    if (!c->pending.empty()) return MPC3_E_UNVERIFIED;
+    return wrap([&] {
+        const int64_t n = X->rows * X->cols;
+        c->scratch.reset();
+        int* flag = (int*)c->scratch.alloc(sizeof(int));
+        zero(c, flag, sizeof(int));
+        launch_reconstruct(n, X->m, X->r1, X->r2, take(c, MPC3_SITE_REC_R1, n), out, flag, c->stream);
+        ck(hipGetLastError());
+        int h = 0;
+        ck(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        ck(hipStreamSynchronize(c->stream));
+        send(c, MPC3_PH_ONLINE, 0, 2, 8 * n);
+        send(c, MPC3_PH_ONLINE, 0, 1, 8 * n);
+        send(c, MPC3_PH_ONLINE, 1, 0, 8 * n);
+        send(c, MPC3_PH_ONLINE, 1, 2, 32);
+        send(c, MPC3_PH_ONLINE, 2, 0, 32);
+        send(c, MPC3_PH_ONLINE, 2, 1, 32);
+        c->rounds[MPC3_PH_ONLINE] += 1;
+        if (h) {
+            c->aborted = true;
+            return (int)MPC3_E_ABORTED;
+        }
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_comm_stats(mpc3_ctx* c, mpc3_comm* out) {
+    if (!c || !out) return MPC3_E_ARG;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MPC3_E_HIP;
+    memcpy(out->bytes, c->bytes, sizeof c->bytes);
+    memcpy(out->rounds, c->rounds, sizeof c->rounds);
+    return MPC3_OK;
+}
+
+int mpc3_inject(mpc3_ctx* c, int site, int64_t index, uint64_t e) {
+    if (!c || site < 1 || site > 9 || index < 0) return MPC3_E_ARG;
+    c->inj[site] = InjSlot{true, index, e};
+    return MPC3_OK;
+}
+
+int mpc3_message(mpc3_ctx* c, int kind, int which, uint64_t* out, int64_t n) {
+    if (!c || kind < 0 || kind > 1 || which < 0 || which > 2 || !out) return MPC3_E_ARG;
+    if (!c->msg[kind][which] || n > c->msg_n[kind]) return MPC3_E_STATE;
+    if (hipMemcpyAsync(out, c->msg[kind][which], (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return MPC3_E_HIP;
+    return MPC3_OK;
+}
+
+int mpc3_verify_log(mpc3_ctx* c, int64_t instance, int sl, int round, uint64_t* out, int* R_out, int64_t* dim_out) {
+    if (!c || instance < 0 || instance >= (int64_t)c->vinfo.size() || round < 0 || round >= RMAX) return MPC3_E_ARG;
+    if (R_out) *R_out = c->vinfo[instance].R;
+    if (dim_out) *dim_out = c->vinfo[instance].npad;
+    if (!out) return MPC3_OK;
+    if (sl < 0 || sl > MPC3_LOG_DELTA_G2) return MPC3_E_ARG;
+    const int64_t base = instance * NSLOT * 64;
+    int64_t off;
+    switch (sl) {
+        case MPC3_LOG_R: off = 0; break;
+        case MPC3_LOG_Z: off = 64; break;
+        case MPC3_LOG_DELTA: off = (2 + 7 * RMAX) * 64; break;
+        case MPC3_LOG_DELTA_M1: off = (3 + 7 * RMAX) * 64; break;
+        case MPC3_LOG_DELTA_M2: off = (4 + 7 * RMAX) * 64; break;
+        case MPC3_LOG_DELTA_G2: off = (5 + 7 * RMAX) * 64; break;
+        default: off = (2 + 7 * round + (sl - MPC3_LOG_ZETA)) * 64;
+    }
+    memcpy(out, c->vlog.data() + base + off, 512);
+    return MPC3_OK;
+}
+
+int mpc3_profile(mpc3_ctx* c, int on) {
+    if (!c) return MPC3_E_ARG;
+    c->prof = on != 0;
+    return MPC3_OK;
+}
+
+int mpc3_profile_read(mpc3_ctx* c, double* total_ms, int64_t* launches, double* ring_macs) {
+    if (!c || !total_ms || !launches || !ring_macs) return MPC3_E_ARG;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MPC3_E_HIP;
+    double t = 0;
+    for (auto& p : c->ev) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, p.first, p.second) != hipSuccess) return MPC3_E_HIP;
+        t += ms;
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    *total_ms = t;
+    *launches = (int64_t)c->ev.size();
+    *ring_macs = c->prof_macs;
+    c->ev.clear();
+    c->prof_macs = 0;
+    return MPC3_OK;
+}
+
+const char* mpc3_strerror(int code) {
+    switch (code) {
+        case MPC3_OK: return "ok";
+        case MPC3_E_ARG: return "invalid argument";
+        case MPC3_E_SHAPE: return "shape mismatch";
+        case MPC3_E_NOMEM: return "device allocation failed";
+        case MPC3_E_ABORTED: return "aborted: verification failed or inconsistent shares";
+        case MPC3_E_UNVERIFIED: return "products await verification";
+        case MPC3_E_HIP: return "HIP runtime error";
+        case MPC3_E_STATE: return "invalid state";
+        default: return "unknown";
+    }
+}
+
+}  // extern "C"

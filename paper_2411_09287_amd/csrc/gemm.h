@@ -1,0 +1,36 @@
+// Matrix products over Z_{2^64}: the one contraction shape behind every heavy step.
+#pragma once
+#include "common.h"
+
+namespace mpc3 {
+
+// A strided view: element (i, j) of batch b is p[b*sb + i*s0 + j*s1].
+struct View {
+    const u64* p;
+    int64_t s0, s1, sb;
+};
+struct OutView {
+    u64* p;
+    int64_t s0, s1, sb;
+};
+
+// C = A B over Z_{2^64}.  A is M x K, B is K x N (per batch).
+//   plain:  C = A B (+ D when D.p != null and no split), or C += A B (atomic) when accumulate.
+//   party:  three accumulators from the share planes of A = (Am, A1, A2), B = (Bm, B1, B2):
+//           C0 = (A1 + A2)(B1 + B2)              (P0: r_x r_y)
+//           C1 = Am B1 + A1 Bm                   (P1: m_x [r_y]_1 + m_y [r_x]_1)
+//           C2 = Am (Bm - B2) - A2 Bm            (P2: m_x m_y - m_x [r_y]_2 - m_y [r_x]_2)
+struct GemmArgs {
+    int64_t M, N, K;
+    int batch;
+    bool party;
+    bool accumulate;          // atomic C += ...  (required when ksplit > 1; C must be initialised)
+    View A[3], B[3];          // plain uses index 0
+    OutView C[3];
+    View Dadd;                // plain, non-accumulating: C = AB + Dadd
+};
+
+// Launch on `stream` with the chosen backend (0 = u64 VALU, 1 = int8 limbs on MFMA).
+hipError_t gemm(const GemmArgs& g, int variant, hipStream_t stream);
+
+}  // namespace mpc3

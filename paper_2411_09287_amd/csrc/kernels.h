@@ -1,0 +1,97 @@
+// Launch wrappers for the elementwise, PRG and Galois-ring kernels.
+#pragma once
+#include "common.h"
+
+namespace mpc3 {
+
+// An additive error on one word of one message (index < 0: inactive).
+struct Inj {
+    int64_t index;
+    u64 e;
+};
+
+struct Keys {
+    Key k01, k02, k12, kall;
+};
+
+// --- Z_{2^64} elementwise steps -------------------------------------------
+void launch_fill(u64* out, int64_t n, Key k, Tag t, hipStream_t s);
+// out[i] = G(k, t, start + i) for i < n
+void launch_fill_at(u64* out, int64_t n, int64_t start, Key k, Tag t, hipStream_t s);
+void launch_encode(const double* x, int64_t n, int frac, u64* out, hipStream_t s);
+void launch_decode(const u64* v, int64_t n, int frac, double* out, hipStream_t s);
+void launch_share(const u64* x, int64_t n, Key k1, Tag t1, Key k2, Tag t2, u64* m, u64* r1, u64* r2,
+                  hipStream_t s);
+void launch_trunc_pair(int64_t n, int t, const Keys& k, u32 op, Inj g2x, Inj m1z, u64* rxm, u64* rx1,
+                       u64* rx2, u64* rzm, u64* rz1, u64* rz2, hipStream_t s);
+void launch_inner_pre(int64_t n, const Keys& k, u32 op, const u64* pm, const u64* p1, const u64* p2,
+                      u64* zr1, u64* zr2, u64* g1, hipStream_t s);
+void launch_inner_post(int64_t n, const u64* c0, const u64* c1, const u64* c2, const u64* zr1,
+                       const u64* zr2, const u64* g1, Inj g2inj, Inj m1inj, u64* zm, u64* msg_g2,
+                       u64* msg_m1, u64* msg_m2, hipStream_t s);
+void launch_trunc_shift(int64_t n, int t, const u64* zm, const u64* rzm, const u64* rz1, const u64* rz2,
+                        u64* om, u64* o1, u64* o2, hipStream_t s);
+void launch_mult(int64_t n, const Keys& k, u32 op, const u64* am, const u64* a1, const u64* a2,
+                 const u64* bm, const u64* b1, const u64* b2, Inj g2inj, u64* cm, u64* c1, u64* c2,
+                 u64* msg_g2, u64* msg_m1, u64* msg_m2, hipStream_t s);
+void launch_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int pad, u64* out,
+                   hipStream_t s);
+void launch_reconstruct(int64_t n, const u64* m, const u64* r1, const u64* r2, Inj r1inj, u64* out,
+                        int* flag, hipStream_t s);
+
+// --- Galois-ring steps (d = 64; an element is 64 consecutive words) ---------
+// v = m - r1 - r2 of a random <.>^{l[x]} drawn with (op, purpose, sub); also keeps the share.
+void launch_random_gr(const Keys& k, u32 op, u32 purpose, u32 sub, u64* share3 /* m,r1,r2: 3*64 */,
+                      u64* value /* nullable */, u64* log /* nullable */, hipStream_t s);
+// Multiplication matrices: W_b row j = v_b * x^j for nb elements v_b = src + b*stride.
+void launch_mulmat(const u64* src, int64_t stride, int nb, u64* W, hipStream_t s);
+// Anti-diagonal fold of 64x64 products and reduction modulo f, nb matrices (stride 4096).
+void launch_fold_plain(const u64* C, int nb, u64* out, hipStream_t s);
+// Pi_PolyEvl outputs from the three party products C0, C1, C2 (each 64x64).
+struct PolyEvlArgs {
+    const u64* C;          // 3 consecutive 64x64 matrices
+    Keys k;
+    u32 op, pr, pg, sub;
+    int inj_m1, inj_g2;    // coefficient index or -1
+    u64 e_m1, e_g2;
+    u64* out;              // share m, r1, r2 (3*64)
+    u64* log_m1; u64* log_m2; u64* log_g2;   // nullable
+    u64* reveal;           // nullable: writes the opened value
+    int* nonzero_flag;     // nullable: set if the opened value is not 0
+};
+void launch_polyevl_finish(const PolyEvlArgs& a, hipStream_t s);
+// f2 = f0 + x (f1 - f0) for nc planes of n rows (rows 2i, 2i+1 -> row i).
+void launch_at_x(const u64* XY, int nc, int64_t n, u64* out, hipStream_t s);
+// D = row(2i+1) - row(2i) for nc planes.
+void launch_sub_pairs(const u64* XY, int nc, int64_t n, u64* D, hipStream_t s);
+struct RoundArgs {
+    Keys k;
+    u32 op, sub;
+    const u64* inv;        // inv_x, inv_1mx, inv_xxm1 (3*64)
+    const u64* h0;         // share (3*64)
+    const u64* h2;         // share (3*64)
+    u64* z;                // share (3*64), updated in place
+    u64* zeta_out;         // 64
+    u64* log_zeta;         // nullable
+};
+void launch_round_finish(const RoundArgs& a, hipStream_t s);
+// x'_i = Pi_Mult over GR of x_i and alpha from the party products (n x 64 each), with fresh masks.
+void launch_xp_epilogue(int64_t n, const Keys& k, u32 op, u32 sub, const u64* C0, const u64* C1,
+                        const u64* C2, u64* XPm, u64* XP1, u64* XP2, hipStream_t s);
+// out[c] = -src[c] for the 3 planes of one element (64 words each, plane stride ps_in/ps_out).
+void launch_neg_elem(const u64* src, int64_t ps_in, u64* dst, int64_t ps_out, hipStream_t s);
+// Scaled lift: out[c][i] = a_c[i] * P[i] (P: n x 64 power table), 3 planes a_c (any may be null -> 0).
+void launch_scale_rows(int64_t n, const u64* a0, const u64* a1, const u64* a2, const u64* P, u64* out,
+                       int64_t plane_stride, hipStream_t s);
+// Constant-term lift: out[c][i] = (a_c[i], 0, ..., 0).
+void launch_lift_rows(int64_t n, const u64* a0, const u64* a1, const u64* a2, u64* out,
+                      int64_t plane_stride, hipStream_t s);
+// Truncation-gate instance of outputs [lo, lo + T) from their bit words B1, B2 (T each):
+// writes the x' r1-plane (scaled by r^g from P), the y r2-plane (lifted) and the gate
+// outputs w (3 planes of 2T words).
+void launch_trunc_instance2(int64_t lo, int64_t T, int t, const u64* B1, const u64* B2, const u64* P,
+                            const u64* rxm, const u64* rx1, const u64* rx2, const u64* rzm, const u64* rz1,
+                            const u64* rz2, u64* x1plane, u64* y2plane, u64* w3, hipStream_t s);
+void launch_set_one(u64* p, hipStream_t s);   // the ring element 1
+
+}  // namespace mpc3

@@ -1,0 +1,645 @@
+// Elementwise, PRG and Galois-ring kernels of the protocol (gfx950).
+#include "kernels.h"
+
+namespace mpc3 {
+
+namespace {
+
+constexpr int TPB = 256;
+
+__host__ inline unsigned nblocks(int64_t work, int per_block) {
+    return (unsigned)((work + per_block - 1) / per_block);
+}
+
+// ---------------------------------------------------------------------------
+// Z_{2^64} elementwise
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill(u64* out, int64_t n, int64_t start, Key k, Tag t) {
+    // thread = one keystream block = 8 words of G(k, t, .) starting at an 8-aligned index
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t first = (start >> 3) + b;
+    const int64_t w0 = first * 8;
+    if (w0 >= start + n) return;
+    u64 w[8];
+    prg_block8(k, t, (u64)first, w);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t i = w0 + q - start;
+        if (i >= 0 && i < n) out[i] = w[q];
+    }
+}
+
+__global__ void k_encode(const double* x, int64_t n, double scale, u64* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (u64)(int64_t)floor(x[i] * scale);
+}
+
+__global__ void k_decode(const u64* v, int64_t n, double scale, double* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (double)(int64_t)v[i] / scale;
+}
+
+__global__ void k_share(const u64* x, int64_t n, Key k1, Tag t1, Key k2, Tag t2, u64* m, u64* r1, u64* r2) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = b * 8;
+    if (i0 >= n) return;
+    u64 w1[8], w2[8];
+    prg_block8(k1, t1, (u64)b, w1);
+    prg_block8(k2, t2, (u64)b, w2);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t i = i0 + q;
+        if (i < n) {
+            r1[i] = w1[q];
+            r2[i] = w2[q];
+            m[i] = x[i] + w1[q] + w2[q];   // the owner's message m = x + [r]_1 + [r]_2
+        }
+    }
+}
+
+// Pi_Trunc preprocessing for outputs p: bit words B1 (P0,P1) and B2 (P0,P2); the two
+// inner products over the 64 bit positions collapse to word operations:
+//   sum_j 2^{j+1} b1_j * (-b2_j) = -2 (B1 & B2),   sum_j 2 c_j b1_j * (-b2_j) = -2 ash(B1 & B2, t).
+__global__ void k_trunc_pair(int64_t n, int t, Keys k, u32 op, Inj g2x, Inj m1z, u64* rxm, u64* rx1,
+                             u64* rx2, u64* rzm, u64* rz1, u64* rz2) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = b * 8;
+    if (i0 >= n) return;
+    u64 B1[8], B2[8], a1[8], a2[8], g1[8];
+    prg_block8(k.k01, make_tag(op, P_TRUNC_B, 1, 0), b, B1);
+    prg_block8(k.k02, make_tag(op, P_TRUNC_B, 2, 0), b, B2);
+    // r_x product: fresh output mask [r_w]_1, [r_w]_2 and P0's [Gamma]_1
+    prg_block8(k.k01, make_tag(op, P_TRUNC_WX_R, 1, 0), b, a1);
+    prg_block8(k.k02, make_tag(op, P_TRUNC_WX_R, 2, 0), b, a2);
+    prg_block8(k.k01, make_tag(op, P_TRUNC_WX_GAMMA, 1, 0), b, g1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t p = i0 + q;
+        if (p >= n) break;
+        const u64 gamma = (0 - 2 * (B1[q] & B2[q])) + a1[q] + a2[q];        // P0
+        u64 g2 = gamma - g1[q];                                              // P0 -> P2
+        if (p == g2x.index) g2 += g2x.e;
+        const u64 m = g1[q] + g2;                                            // P1 <-> P2 exchange
+        rxm[p] = m;
+        rx1[p] = a1[q] - B1[q];     // + sum 2^j <b1_j> = (0, -B1, 0)
+        rx2[p] = a2[q] - B2[q];     // + sum 2^j <b2_j> = (0, 0, -B2)
+    }
+    prg_block8(k.k01, make_tag(op, P_TRUNC_WZ_R, 1, 0), b, a1);
+    prg_block8(k.k02, make_tag(op, P_TRUNC_WZ_R, 2, 0), b, a2);
+    prg_block8(k.k01, make_tag(op, P_TRUNC_WZ_GAMMA, 1, 0), b, g1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t p = i0 + q;
+        if (p >= n) break;
+        const u64 gamma = (0 - 2 * ash(B1[q] & B2[q], t)) + a1[q] + a2[q];
+        const u64 g2 = gamma - g1[q];
+        u64 m1 = g1[q];
+        if (p == m1z.index) m1 += m1z.e;
+        rzm[p] = m1 + g2;
+        rz1[p] = a1[q] - ash(B1[q], t);
+        rz2[p] = a2[q] - ash(B2[q], t);
+    }
+}
+
+// Pi_Inner preprocessing: output-wire mask [r_Z] (fresh, or the truncation pair's r_x) and [Gamma]_1.
+__global__ void k_inner_pre(int64_t n, Keys k, u32 op, const u64* pm, const u64* p1, const u64* p2,
+                            u64* zr1, u64* zr2, u64* g1) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = b * 8;
+    if (i0 >= n) return;
+    u64 w[8];
+    prg_block8(k.k01, make_tag(op, P_INNER_GAMMA, 1, 0), b, w);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (i0 + q < n) g1[i0 + q] = w[q];
+    if (pm) {   // P1: [r_x]_1 = m_{r_x} - [r_{r_x}]_1 ; P2: [r_x]_2 = -[r_{r_x}]_2
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = i0 + q;
+            if (i < n) {
+                zr1[i] = pm[i] - p1[i];
+                zr2[i] = 0 - p2[i];
+            }
+        }
+    } else {
+        u64 v[8];
+        prg_block8(k.k01, make_tag(op, P_INNER_RZ, 1, 0), b, w);
+        prg_block8(k.k02, make_tag(op, P_INNER_RZ, 2, 0), b, v);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = i0 + q;
+            if (i < n) {
+                zr1[i] = w[q];
+                zr2[i] = v[q];
+            }
+        }
+    }
+}
+
+// Pi_Inner messages and output from the party accumulators.
+__global__ void k_inner_post(int64_t n, const u64* c0, const u64* c1, const u64* c2, const u64* zr1,
+                             const u64* zr2, const u64* g1, Inj g2inj, Inj m1inj, u64* zm, u64* mg2,
+                             u64* mm1, u64* mm2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const u64 gamma = c0[i] + zr1[i] + zr2[i];        // P0: R_X R_W + r_Z
+    u64 g2 = gamma - g1[i];                           // P0 -> P2
+    if (i == g2inj.index) g2 += g2inj.e;
+    u64 m1 = g1[i] - c1[i];                           // P1
+    if (i == m1inj.index) m1 += m1inj.e;
+    const u64 m2 = c2[i] + g2;                        // P2
+    zm[i] = m1 + m2;                                  // after the P1 <-> P2 exchange
+    if (mg2) {
+        mg2[i] = g2;
+        mm1[i] = m1;
+        mm2[i] = m2;
+    }
+}
+
+__global__ void k_trunc_shift(int64_t n, int t, const u64* zm, const u64* rzm, const u64* rz1,
+                              const u64* rz2, u64* om, u64* o1, u64* o2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    om[i] = ash(zm[i], t);
+    o1[i] = rzm[i] - rz1[i];
+    o2[i] = 0 - rz2[i];
+}
+
+__global__ void k_mult(int64_t n, Keys k, u32 op, const u64* am, const u64* a1, const u64* a2,
+                       const u64* bm, const u64* b1, const u64* b2, Inj g2inj, u64* cm, u64* c1, u64* c2,
+                       u64* mg2, u64* mm1, u64* mm2) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = b * 8;
+    if (i0 >= n) return;
+    u64 rz1[8], rz2[8], g1[8];
+    prg_block8(k.k01, make_tag(op, P_MULT_RZ, 1, 0), b, rz1);
+    prg_block8(k.k02, make_tag(op, P_MULT_RZ, 2, 0), b, rz2);
+    prg_block8(k.k01, make_tag(op, P_MULT_GAMMA, 1, 0), b, g1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t i = i0 + q;
+        if (i >= n) break;
+        const u64 gamma = (a1[i] + a2[i]) * (b1[i] + b2[i]) + rz1[q] + rz2[q];
+        u64 g2 = gamma - g1[q];
+        if (i == g2inj.index) g2 += g2inj.e;
+        const u64 m1 = g1[q] - am[i] * b1[i] - bm[i] * a1[i];
+        const u64 m2 = am[i] * bm[i] - am[i] * b2[i] - bm[i] * a2[i] + g2;
+        cm[i] = m1 + m2;
+        c1[i] = rz1[q];
+        c2[i] = rz2[q];
+        if (mg2) {
+            mg2[i] = g2;
+            mm1[i] = m1;
+            mm2[i] = m2;
+        }
+    }
+}
+
+// rows (b, oh, ow), columns (kh, kw, c) of a stride-1 convolution with zero padding
+__global__ void k_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int pad, int OH, int OW,
+                         u64* out) {
+    const int64_t K = (int64_t)KH * KW * C;
+    const int64_t total = (int64_t)B * OH * OW * K;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int64_t row = idx / K;
+    const int col = (int)(idx - row * K);
+    const int c = col % C;
+    const int kw = (col / C) % KW;
+    const int kh = col / (C * KW);
+    const int ow = (int)(row % OW);
+    const int oh = (int)((row / OW) % OH);
+    const int b = (int)(row / ((int64_t)OW * OH));
+    const int ih = oh + kh - pad, iw = ow + kw - pad;
+    u64 v = 0;
+    if (ih >= 0 && ih < H && iw >= 0 && iw < W) v = x[(((int64_t)b * H + ih) * W + iw) * C + c];
+    out[idx] = v;
+}
+
+__global__ void k_reconstruct(int64_t n, const u64* m, const u64* r1, const u64* r2, Inj inj, u64* out,
+                              int* flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const u64 mine = r1[i];                                      // P1's [r]_1 (hashed to P2)
+    const u64 sent = r1[i] + (i == inj.index ? inj.e : 0);       // P0's [r]_1 as P2 receives it
+    if (sent != mine) atomicOr(flag, 1);
+    out[i] = m[i] - r1[i] - r2[i];
+}
+
+// ---------------------------------------------------------------------------
+// Galois ring GR(2^64, 64): products and reduction inside one 64-lane group
+// ---------------------------------------------------------------------------
+
+// Reduce the product whose coefficient k is `lo` and coefficient 64 + k is `hi` (lane k).
+__device__ u64 reduce_lane(u64 lo, u64 hi, u64* sh, int k) {
+    sh[k] = hi;
+    __syncthreads();
+    u64 v = lo;
+#pragma unroll
+    for (int q = 0; q < NTAPS; ++q) {
+        const int j = k - tap(q);
+        if (j >= 0) v -= sh[j];
+    }
+    // positions 64 + p (p <= 2) reached by x^{64+j} x^{t} with j + t >= 64 are reduced again
+#pragma unroll
+    for (int q = 0; q < NTAPS; ++q) {
+        const int p = k - tap(q);
+        if (p >= 0 && p <= 2) {
+            u64 ov = 0;
+#pragma unroll
+            for (int r = 0; r < NTAPS; ++r) {
+                const int j = 64 + p - tap(r);
+                if (j >= 0 && j <= 62) ov -= sh[j];
+            }
+            v -= ov;
+        }
+    }
+    __syncthreads();
+    return v;
+}
+
+// Coefficient k of a * b with a, b visible to the 64-lane group.
+__device__ u64 gr_mul_lane(const u64* a, const u64* b, u64* sh, int k) {
+    u64 lo = 0, hi = 0;
+    for (int i = 0; i < 64; ++i) {
+        const u64 p = a[i] * b[(k - i) & 63];
+        if (i <= k) lo += p; else hi += p;
+    }
+    return reduce_lane(lo, hi, sh, k);
+}
+
+__global__ void k_random_gr(Keys k, u32 op, u32 purpose, u32 sub, u64* share3, u64* value, u64* log) {
+    const int c = threadIdx.x;
+    const u64 m = prg_word(k.k12, make_tag(op, purpose, 0, sub), c);
+    const u64 r1 = prg_word(k.k01, make_tag(op, purpose, 1, sub), c);
+    const u64 r2 = prg_word(k.k02, make_tag(op, purpose, 2, sub), c);
+    if (share3) {
+        share3[c] = m;
+        share3[64 + c] = r1;
+        share3[128 + c] = r2;
+    }
+    const u64 v = m - r1 - r2;
+    if (value) value[c] = v;
+    if (log) log[c] = v;
+}
+
+__global__ void k_mulmat(const u64* src, int64_t stride, u64* W) {
+    __shared__ u64 cur[64];
+    const int k = threadIdx.x;
+    const u64* v = src + blockIdx.x * stride;
+    u64* out = W + (int64_t)blockIdx.x * 4096;
+    u64 c = v[k];
+    for (int j = 0; j < 64; ++j) {
+        out[j * 64 + k] = c;          // row j = v * x^j
+        cur[k] = c;
+        __syncthreads();
+        const u64 top = cur[63];
+        u64 nc = k ? cur[k - 1] : 0;
+#pragma unroll
+        for (int q = 0; q < NTAPS; ++q)
+            if (k == tap(q)) nc -= top;
+        __syncthreads();
+        c = nc;
+    }
+}
+
+// Anti-diagonal sums of a 64x64 matrix (row j, column l -> coefficient j + l), reduced.
+__device__ u64 fold_lane(const u64* C, u64* sh, int k) {
+    u64 lo = 0, hi = 0;
+    for (int j = 0; j <= k; ++j) lo += C[j * 64 + (k - j)];
+    for (int j = k + 1; j < 64; ++j) hi += C[j * 64 + (k + 64 - j)];
+    return reduce_lane(lo, hi, sh, k);
+}
+
+__global__ void k_fold_plain(const u64* C, u64* out) {
+    __shared__ u64 sh[64];
+    const int k = threadIdx.x;
+    out[blockIdx.x * 64 + k] = fold_lane(C + (int64_t)blockIdx.x * 4096, sh, k);
+}
+
+__global__ void k_polyevl_finish(PolyEvlArgs a) {
+    __shared__ u64 sh[64];
+    __shared__ int nz;
+    const int k = threadIdx.x;
+    if (k == 0) nz = 0;
+    const u64 s0 = fold_lane(a.C, sh, k);            // sum R_a R_b            (P0)
+    const u64 s1 = fold_lane(a.C + 4096, sh, k);     // sum m_a r1_b + m_b r1_a (P1)
+    const u64 s2 = fold_lane(a.C + 8192, sh, k);     // sum m_a (m_b - r2_b) - r2_a m_b (P2)
+    const u64 rc1 = prg_word(a.k.k01, make_tag(a.op, a.pr, 1, a.sub), k);
+    const u64 rc2 = prg_word(a.k.k02, make_tag(a.op, a.pr, 2, a.sub), k);
+    const u64 g1 = prg_word(a.k.k01, make_tag(a.op, a.pg, 1, a.sub), k);
+    u64 g2 = s0 + rc1 + rc2 - g1;                     // P0 -> P2
+    if (k == a.inj_g2) g2 += a.e_g2;
+    u64 m1 = g1 - s1;                                 // P1 -> P2
+    if (k == a.inj_m1) m1 += a.e_m1;
+    const u64 m2 = s2 + g2;                           // P2 -> P1
+    const u64 m = m1 + m2;
+    a.out[k] = m;
+    a.out[64 + k] = rc1;
+    a.out[128 + k] = rc2;
+    if (a.log_m1) {
+        a.log_m1[k] = m1;
+        a.log_m2[k] = m2;
+        a.log_g2[k] = g2;
+    }
+    if (a.reveal) {
+        const u64 v = m - rc1 - rc2;
+        a.reveal[k] = v;
+        if (v) atomicOr(&nz, 1);
+        __syncthreads();
+        if (k == 0 && nz) atomicOr(a.nonzero_flag, 1);
+    }
+}
+
+// x * v for lane k: shift up by one coefficient and reduce x^64.
+__device__ __forceinline__ u64 xmul_coeff(const u64* v, int k) {
+    u64 r = k ? v[k - 1] : 0;
+#pragma unroll
+    for (int q = 0; q < NTAPS; ++q)
+        if (k == tap(q)) r -= v[63];
+    return r;
+}
+
+__global__ void k_at_x(const u64* XY, int64_t n, u64* out) {
+    // block: one (plane, pair i); 64 lanes = coefficients
+    const int k = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    const int c = blockIdx.y;
+    const u64* f0 = XY + ((int64_t)c * n + 2 * i) * 64;
+    const u64* f1 = f0 + 64;
+    __shared__ u64 dsh[64];
+    dsh[k] = f1[k] - f0[k];
+    __syncthreads();
+    out[((int64_t)c * (n / 2) + i) * 64 + k] = f0[k] + xmul_coeff(dsh, k);
+}
+
+__global__ void k_sub_pairs(const u64* XY, int64_t n, u64* D) {
+    const int64_t half = n / 2;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // over half*64 words
+    const int c = blockIdx.y;
+    if (idx >= half * 64) return;
+    const int64_t i = idx >> 6;
+    const int k = (int)(idx & 63);
+    const u64* base = XY + (int64_t)c * n * 64;
+    D[(int64_t)c * half * 64 + idx] = base[(2 * i + 1) * 64 + k] - base[(2 * i) * 64 + k];
+}
+
+__global__ void k_round_finish(RoundArgs a) {
+    __shared__ u64 sh[64];
+    __shared__ u64 zeta[64], zm1[64], zmx[64], t[64], L[3][64], hh[3][3][64];
+    const int k = threadIdx.x;
+    const u64 m = prg_word(a.k.k12, make_tag(a.op, P_VER_ZETA, 0, a.sub), k);
+    const u64 r1 = prg_word(a.k.k01, make_tag(a.op, P_VER_ZETA, 1, a.sub), k);
+    const u64 r2 = prg_word(a.k.k02, make_tag(a.op, P_VER_ZETA, 2, a.sub), k);
+    const u64 z = m - r1 - r2;                       // revealed point
+    zeta[k] = z;
+    zm1[k] = z - (k == 0 ? 1 : 0);                   // zeta - 1
+    zmx[k] = z - (k == 1 ? 1 : 0);                   // zeta - x
+    a.zeta_out[k] = z;
+    if (a.log_zeta) a.log_zeta[k] = z;
+    for (int c = 0; c < 3; ++c) {
+        hh[0][c][k] = a.h0[c * 64 + k];
+        hh[2][c][k] = a.h2[c * 64 + k];
+        hh[1][c][k] = a.z[c * 64 + k] - a.h0[c * 64 + k];    // h(1) = z - h(0)
+    }
+    __syncthreads();
+    // Lagrange weights over the nodes {0, 1, x}
+    t[k] = gr_mul_lane(zm1, zmx, sh, k);
+    __syncthreads();
+    L[0][k] = gr_mul_lane(t, a.inv, sh, k);              // (z-1)(z-x) / x
+    __syncthreads();
+    t[k] = gr_mul_lane(zeta, zmx, sh, k);
+    __syncthreads();
+    L[1][k] = gr_mul_lane(t, a.inv + 64, sh, k);         // z(z-x) / (1-x)
+    __syncthreads();
+    t[k] = gr_mul_lane(zeta, zm1, sh, k);
+    __syncthreads();
+    L[2][k] = gr_mul_lane(t, a.inv + 128, sh, k);        // z(z-1) / (x(x-1))
+    __syncthreads();
+    for (int c = 0; c < 3; ++c) {
+        u64 acc = 0;
+        for (int i = 0; i < 3; ++i) {
+            acc += gr_mul_lane(L[i], hh[i][c], sh, k);
+            __syncthreads();
+        }
+        a.z[c * 64 + k] = acc;
+    }
+}
+
+__global__ void k_xp_epilogue(int64_t n, Keys k, u32 op, u32 sub, const u64* C0, const u64* C1,
+                              const u64* C2, u64* XPm, u64* XP1, u64* XP2) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w0 = b * 8;
+    if (w0 >= n * 64) return;
+    u64 r1[8], r2[8], g1[8];
+    prg_block8(k.k01, make_tag(op, P_VER_XP_R, 1, sub), b, r1);
+    prg_block8(k.k02, make_tag(op, P_VER_XP_R, 2, sub), b, r2);
+    prg_block8(k.k01, make_tag(op, P_VER_XP_GAMMA, 1, sub), b, g1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t w = w0 + q;
+        const u64 g2 = C0[w] + r1[q] + r2[q] - g1[q];   // P0: R_x R_alpha + r; sends [Gamma]_2
+        const u64 m1 = g1[q] - C1[w];                    // P1
+        const u64 m2 = C2[w] + g2;                       // P2
+        XPm[w] = m1 + m2;
+        XP1[w] = r1[q];
+        XP2[w] = r2[q];
+    }
+}
+
+__global__ void k_neg_elem(const u64* src, int64_t psi, u64* dst, int64_t pso) {
+    const int k = threadIdx.x;
+    for (int c = 0; c < 3; ++c) dst[c * pso + k] = 0 - src[c * psi + k];
+}
+
+__global__ void k_scale_rows(int64_t n, const u64* a0, const u64* a1, const u64* a2, const u64* P, u64* out,
+                             int64_t ps) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * 64) return;
+    const int64_t i = idx >> 6;
+    const u64 p = P[idx];
+    out[idx] = a0 ? a0[i] * p : 0;
+    out[ps + idx] = a1 ? a1[i] * p : 0;
+    out[2 * ps + idx] = a2 ? a2[i] * p : 0;
+}
+
+__global__ void k_lift_rows(int64_t n, const u64* a0, const u64* a1, const u64* a2, u64* out, int64_t ps) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * 64) return;
+    const int64_t i = idx >> 6;
+    const bool c0 = (idx & 63) == 0;
+    out[idx] = (c0 && a0) ? a0[i] : 0;
+    out[ps + idx] = (c0 && a1) ? a1[i] : 0;
+    out[2 * ps + idx] = (c0 && a2) ? a2[i] : 0;
+}
+
+// element e = 128 q + 64 s + j of truncation lo + q (gate g = 2q + s):
+//   x'_e = r^g (0, w_s(j) b1_j, 0),  y_e = (0, 0, -b2_j) lifted
+__global__ void k_trunc_instance(int64_t T, int t, const u64* B1, const u64* B2, const u64* P, u64* x1,
+                                 u64* y2) {
+    const int k = threadIdx.x;
+    const int64_t e = blockIdx.x;
+    const int64_t q = e >> 7;
+    const int s = (int)((e >> 6) & 1);
+    const int j = (int)(e & 63);
+    const u64 b1 = (B1[q] >> j) & 1, b2 = (B2[q] >> j) & 1;
+    u64 w;
+    if (s == 0) {
+        w = j == 63 ? 0 : (u64)1 << (j + 1);            // 2^{j+1} (2^64 = 0)
+    } else {
+        u64 c = 0;
+        if (j >= t && j < 63) c = (u64)1 << (j - t);
+        if (j == 63) c = 0 - ((u64)1 << (63 - t));
+        w = 2 * c;
+    }
+    const int64_t g = 2 * q + s;
+    x1[e * 64 + k] = (w * b1) * P[g * 64 + k];
+    y2[e * 64 + k] = k == 0 ? 0 - b2 : 0;
+}
+
+__global__ void k_trunc_w(int64_t lo, int64_t T, int t, const u64* B1, const u64* B2, const u64* rxm,
+                          const u64* rx1, const u64* rx2, const u64* rzm, const u64* rz1, const u64* rz2,
+                          u64* w3) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= T) return;
+    const int64_t p = lo + q;
+    const u64 b1 = B1[q], b2 = B2[q];
+    // gate outputs <w> = <r> - (linear part): w_x = (m, r1 + B1, r2 + B2), w_z with ash(B, t)
+    w3[2 * q] = rxm[p];
+    w3[2 * T + 2 * q] = rx1[p] + b1;
+    w3[4 * T + 2 * q] = rx2[p] + b2;
+    w3[2 * q + 1] = rzm[p];
+    w3[2 * T + 2 * q + 1] = rz1[p] + ash(b1, t);
+    w3[4 * T + 2 * q + 1] = rz2[p] + ash(b2, t);
+}
+
+__global__ void k_set_one(u64* p) { p[threadIdx.x] = threadIdx.x == 0 ? 1 : 0; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+
+void launch_fill(u64* out, int64_t n, Key k, Tag t, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill, dim3(nblocks((n + 7) / 8 + 1, TPB)), dim3(TPB), 0, s, out, n, (int64_t)0, k, t);
+}
+void launch_fill_at(u64* out, int64_t n, int64_t start, Key k, Tag t, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill, dim3(nblocks((n + 7) / 8 + 2, TPB)), dim3(TPB), 0, s, out, n, start, k, t);
+}
+void launch_encode(const double* x, int64_t n, int frac, u64* out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_encode, dim3(nblocks(n, TPB)), dim3(TPB), 0, s, x, n, (double)((u64)1 << frac), out);
+}
+void launch_decode(const u64* v, int64_t n, int frac, double* out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_decode, dim3(nblocks(n, TPB)), dim3(TPB), 0, s, v, n, (double)((u64)1 << frac), out);
+}
+void launch_share(const u64* x, int64_t n, Key k1, Tag t1, Key k2, Tag t2, u64* m, u64* r1, u64* r2,
+                  hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_share, dim3(nblocks((n + 7) / 8, TPB)), dim3(TPB), 0, s, x, n, k1, t1, k2, t2, m, r1, r2);
+}
+void launch_trunc_pair(int64_t n, int t, const Keys& k, u32 op, Inj g2x, Inj m1z, u64* rxm, u64* rx1,
+                       u64* rx2, u64* rzm, u64* rz1, u64* rz2, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_trunc_pair, dim3(nblocks((n + 7) / 8, TPB)), dim3(TPB), 0, s, n, t, k, op, g2x, m1z,
+                       rxm, rx1, rx2, rzm, rz1, rz2);
+}
+void launch_inner_pre(int64_t n, const Keys& k, u32 op, const u64* pm, const u64* p1, const u64* p2,
+                      u64* zr1, u64* zr2, u64* g1, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_inner_pre, dim3(nblocks((n + 7) / 8, TPB)), dim3(TPB), 0, s, n, k, op, pm, p1, p2, zr1,
+                       zr2, g1);
+}
+void launch_inner_post(int64_t n, const u64* c0, const u64* c1, const u64* c2, const u64* zr1,
+                       const u64* zr2, const u64* g1, Inj g2inj, Inj m1inj, u64* zm, u64* msg_g2,
+                       u64* msg_m1, u64* msg_m2, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_inner_post, dim3(nblocks(n, TPB)), dim3(TPB), 0, s, n, c0, c1, c2, zr1, zr2, g1, g2inj,
+                       m1inj, zm, msg_g2, msg_m1, msg_m2);
+}
+void launch_trunc_shift(int64_t n, int t, const u64* zm, const u64* rzm, const u64* rz1, const u64* rz2,
+                        u64* om, u64* o1, u64* o2, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_trunc_shift, dim3(nblocks(n, TPB)), dim3(TPB), 0, s, n, t, zm, rzm, rz1, rz2, om, o1, o2);
+}
+void launch_mult(int64_t n, const Keys& k, u32 op, const u64* am, const u64* a1, const u64* a2,
+                 const u64* bm, const u64* b1, const u64* b2, Inj g2inj, u64* cm, u64* c1, u64* c2,
+                 u64* msg_g2, u64* msg_m1, u64* msg_m2, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_mult, dim3(nblocks((n + 7) / 8, TPB)), dim3(TPB), 0, s, n, k, op, am, a1, a2, bm, b1, b2,
+                       g2inj, cm, c1, c2, msg_g2, msg_m1, msg_m2);
+}
+void launch_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int pad, u64* out,
+                   hipStream_t s) {
+    const int OH = H + 2 * pad - KH + 1, OW = W + 2 * pad - KW + 1;
+    const int64_t total = (int64_t)B * OH * OW * KH * KW * C;
+    if (total <= 0) return;
+    hipLaunchKernelGGL(k_im2col, dim3(nblocks(total, TPB)), dim3(TPB), 0, s, x, B, H, W, C, KH, KW, pad, OH, OW,
+                       out);
+}
+void launch_reconstruct(int64_t n, const u64* m, const u64* r1, const u64* r2, Inj r1inj, u64* out,
+                        int* flag, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_reconstruct, dim3(nblocks(n, TPB)), dim3(TPB), 0, s, n, m, r1, r2, r1inj, out, flag);
+}
+void launch_random_gr(const Keys& k, u32 op, u32 purpose, u32 sub, u64* share3, u64* value, u64* log,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_random_gr, dim3(1), dim3(64), 0, s, k, op, purpose, sub, share3, value, log);
+}
+void launch_mulmat(const u64* src, int64_t stride, int nb, u64* W, hipStream_t s) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_mulmat, dim3(nb), dim3(64), 0, s, src, stride, W);
+}
+void launch_fold_plain(const u64* C, int nb, u64* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_fold_plain, dim3(nb), dim3(64), 0, s, C, out);
+}
+void launch_polyevl_finish(const PolyEvlArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_polyevl_finish, dim3(1), dim3(64), 0, s, a);
+}
+void launch_at_x(const u64* XY, int nc, int64_t n, u64* out, hipStream_t s) {
+    if (n < 2) return;
+    hipLaunchKernelGGL(k_at_x, dim3((unsigned)(n / 2), nc), dim3(64), 0, s, XY, n, out);
+}
+void launch_sub_pairs(const u64* XY, int nc, int64_t n, u64* D, hipStream_t s) {
+    if (n < 2) return;
+    hipLaunchKernelGGL(k_sub_pairs, dim3(nblocks(n / 2 * 64, TPB), nc), dim3(TPB), 0, s, XY, n, D);
+}
+void launch_round_finish(const RoundArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_round_finish, dim3(1), dim3(64), 0, s, a);
+}
+void launch_xp_epilogue(int64_t n, const Keys& k, u32 op, u32 sub, const u64* C0, const u64* C1,
+                        const u64* C2, u64* XPm, u64* XP1, u64* XP2, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_xp_epilogue, dim3(nblocks(n * 8, TPB)), dim3(TPB), 0, s, n, k, op, sub, C0, C1, C2, XPm,
+                       XP1, XP2);
+}
+void launch_neg_elem(const u64* src, int64_t ps_in, u64* dst, int64_t ps_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_neg_elem, dim3(1), dim3(64), 0, s, src, ps_in, dst, ps_out);
+}
+void launch_scale_rows(int64_t n, const u64* a0, const u64* a1, const u64* a2, const u64* P, u64* out,
+                       int64_t ps, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_scale_rows, dim3(nblocks(n * 64, TPB)), dim3(TPB), 0, s, n, a0, a1, a2, P, out, ps);
+}
+void launch_lift_rows(int64_t n, const u64* a0, const u64* a1, const u64* a2, u64* out, int64_t ps,
+                      hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_lift_rows, dim3(nblocks(n * 64, TPB)), dim3(TPB), 0, s, n, a0, a1, a2, out, ps);
+}
+void launch_trunc_instance2(int64_t lo, int64_t T, int t, const u64* B1, const u64* B2, const u64* P,
+                            const u64* rxm, const u64* rx1, const u64* rx2, const u64* rzm, const u64* rz1,
+                            const u64* rz2, u64* x1plane, u64* y2plane, u64* w3, hipStream_t s) {
+    if (T <= 0) return;
+    hipLaunchKernelGGL(k_trunc_instance, dim3((unsigned)(T * 128)), dim3(64), 0, s, T, t, B1, B2, P, x1plane,
+                       y2plane);
+    hipLaunchKernelGGL(k_trunc_w, dim3(nblocks(T, TPB)), dim3(TPB), 0, s, lo, T, t, B1, B2, rxm, rx1, rx2, rzm,
+                       rz1, rz2, w3);
+}
+void launch_set_one(u64* p, hipStream_t s) { hipLaunchKernelGGL(k_set_one, dim3(1), dim3(64), 0, s, p); }
+
+}  // namespace mpc3

@@ -1,0 +1,290 @@
+"""ctypes binding of libmpc3.so (include/mpc3.h): argument marshalling only.
+
+Every step of the protocol runs in the library's HIP kernels; torch provides device
+memory (int64 tensors used as raw 64-bit words) and the stream.  The library must be
+built (``python -m paper_2411_09287_amd.build``); loading fails loudly otherwise.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpc3.so")
+
+OK, E_ARG, E_SHAPE, E_NOMEM, E_ABORTED, E_UNVERIFIED, E_HIP, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
+VARIANT_U64, VARIANT_LIMB_I8 = 0, 1
+PH_OFFLINE, PH_ONLINE, PH_VERIFY_OFFLINE, PH_VERIFY_ONLINE = 0, 1, 2, 3
+VERIFY_INNER, VERIFY_TRUNC, VERIFY_MULT, VERIFY_ALL = 1, 2, 4, 7
+(SITE_INNER_GAMMA2, SITE_INNER_M1, SITE_TRUNC_GAMMA2, SITE_TRUNC_M1, SITE_MULT_GAMMA2, SITE_VER_H0_M1,
+ SITE_VER_H2_GAMMA2, SITE_VER_DELTA_M1, SITE_REC_R1) = range(1, 10)
+MSG_GAMMA2, MSG_M1, MSG_M2 = 0, 1, 2
+(LOG_R, LOG_Z, LOG_ZETA, LOG_H0_M1, LOG_H0_M2, LOG_H0_G2, LOG_H2_M1, LOG_H2_M2, LOG_H2_G2, LOG_DELTA,
+ LOG_DELTA_M1, LOG_DELTA_M2, LOG_DELTA_G2) = range(13)
+
+
+class Share(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_void_p), ("r1", ctypes.c_void_p), ("r2", ctypes.c_void_p),
+                ("rows", ctypes.c_int64), ("cols", ctypes.c_int64)]
+
+
+class TruncPair(ctypes.Structure):
+    _fields_ = [("rx", Share), ("rz", Share), ("t", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("id", ctypes.c_uint64)]
+
+
+class Comm(ctypes.Structure):
+    _fields_ = [("bytes", ctypes.c_uint64 * 36), ("rounds", ctypes.c_uint32 * 4)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_U64 = ctypes.c_uint64
+SIGNATURES = {
+    "mpc3_ctx_create": (_I, [_P, _I, _I, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "mpc3_ctx_destroy": (_I, [_P]),
+    "mpc3_set_variant": (_I, [_P, _I]),
+    "mpc3_set_chunk": (_I, [_P, _I64]),
+    "mpc3_keep_messages": (_I, [_P, _I]),
+    "mpc3_encode": (_I, [_P, _P, _I64, _P]),
+    "mpc3_decode": (_I, [_P, _P, _I64, _P]),
+    "mpc3_share": (_I, [_P, _I, _P, ctypes.POINTER(Share)]),
+    "mpc3_trunc_pair": (_I, [_P, _I64, _I, ctypes.POINTER(TruncPair)]),
+    "mpc3_inner": (_I, [_P, ctypes.POINTER(Share), ctypes.POINTER(Share), ctypes.POINTER(TruncPair),
+                        ctypes.POINTER(Share)]),
+    "mpc3_im2col": (_I, [_P, ctypes.POINTER(Share), _I, _I, _I, _I, _I, _I, _I, ctypes.POINTER(Share)]),
+    "mpc3_mult": (_I, [_P, ctypes.POINTER(Share), ctypes.POINTER(Share), ctypes.POINTER(Share)]),
+    "mpc3_trunc": (_I, [_P, ctypes.POINTER(TruncPair), ctypes.POINTER(Share), ctypes.POINTER(Share)]),
+    "mpc3_verify": (_I, [_P, _I, _I, ctypes.POINTER(_I)]),
+    "mpc3_reconstruct": (_I, [_P, ctypes.POINTER(Share), _I, _P]),
+    "mpc3_comm_stats": (_I, [_P, ctypes.POINTER(Comm)]),
+    "mpc3_inject": (_I, [_P, _I, _I64, _U64]),
+    "mpc3_message": (_I, [_P, _I, _I, _P, _I64]),
+    "mpc3_verify_log": (_I, [_P, _I64, _I, _I, _P, ctypes.POINTER(_I), ctypes.POINTER(_I64)]),
+    "mpc3_profile": (_I, [_P, _I]),
+    "mpc3_profile_read": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64),
+                                ctypes.POINTER(ctypes.c_double)]),
+    "mpc3_strerror": (ctypes.c_char_p, [_I]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmpc3.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2411_09287_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class Mpc3Error(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {lib().mpc3_strerror(code).decode()} ({code})")
+
+
+def _ck(code, where):
+    if code != OK:
+        raise Mpc3Error(code, where)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def to_words(a, device="cuda"):
+    """uint64 numpy array -> int64 tensor on the device (same 64-bit patterns)."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+    return torch.from_numpy(a.view(np.int64)).to(device)
+
+
+def from_words(t):
+    """int64 tensor -> uint64 numpy array."""
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+class DShare:
+    """<v> on the device: three int64 tensors of one shape (m, [r]_1, [r]_2)."""
+
+    def __init__(self, m, r1, r2):
+        self.m, self.r1, self.r2 = m, r1, r2
+
+    @classmethod
+    def empty(cls, rows, cols, device="cuda"):
+        return cls(*[torch.empty((rows, cols), dtype=torch.int64, device=device) for _ in range(3)])
+
+    @property
+    def rows(self):
+        return self.m.shape[0]
+
+    @property
+    def cols(self):
+        return self.m.shape[1] if self.m.dim() > 1 else 1
+
+    def c(self):
+        return Share(self.m.data_ptr(), self.r1.data_ptr(), self.r2.data_ptr(), self.rows, self.cols)
+
+    def numpy(self):
+        return tuple(from_words(t) for t in (self.m, self.r1, self.r2))
+
+
+class DPair:
+    """Truncation pair: planes of <r_x> and <r_z> (n words each) plus the C struct."""
+
+    def __init__(self, n, device="cuda"):
+        self.rx = DShare.empty(n, 1, device)
+        self.rz = DShare.empty(n, 1, device)
+        self.s = TruncPair(self.rx.c(), self.rz.c(), 0, n, 0)
+
+    @property
+    def n(self):
+        return self.s.n
+
+    @property
+    def t(self):
+        return self.s.t
+
+
+class Context:
+    """One three-party context on the current torch stream."""
+
+    def __init__(self, master_seed, d=64, frac_bits=13, workspace_bytes=0, device="cuda", stream=None):
+        self.device = device
+        self.frac_bits = frac_bits
+        seed = (ctypes.c_uint8 * 32).from_buffer_copy(bytes(master_seed))
+        st = stream if stream is not None else torch.cuda.current_stream(device)
+        self._stream = st
+        h = ctypes.c_void_p()
+        _ck(lib().mpc3_ctx_create(seed, d, frac_bits, workspace_bytes, ctypes.c_void_p(st.cuda_stream),
+                                  ctypes.byref(h)), "mpc3_ctx_create")
+        self.h = h
+        self._keep = []          # operands the context still points at
+
+    def close(self):
+        if self.h:
+            lib().mpc3_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- configuration -------------------------------------------------------
+    def set_variant(self, v):
+        _ck(lib().mpc3_set_variant(self.h, v), "mpc3_set_variant")
+
+    def set_chunk(self, t):
+        _ck(lib().mpc3_set_chunk(self.h, t), "mpc3_set_chunk")
+
+    def keep_messages(self, on=True):
+        _ck(lib().mpc3_keep_messages(self.h, int(on)), "mpc3_keep_messages")
+
+    # -- protocol --------------------------------------------------------------
+    def encode(self, x):
+        x = x.to(self.device, torch.float64).contiguous()
+        out = torch.empty(x.shape, dtype=torch.int64, device=self.device)
+        _ck(lib().mpc3_encode(self.h, _ptr(x), x.numel(), _ptr(out)), "mpc3_encode")
+        return out
+
+    def decode(self, v):
+        out = torch.empty(v.shape, dtype=torch.float64, device=self.device)
+        _ck(lib().mpc3_decode(self.h, _ptr(v), v.numel(), _ptr(out)), "mpc3_decode")
+        return out
+
+    def share(self, x, owner=0):
+        x = x.contiguous()
+        rows = x.shape[0] if x.dim() else 1
+        cols = x.numel() // rows if rows else 0
+        out = DShare.empty(rows, cols, self.device)
+        s = out.c()
+        _ck(lib().mpc3_share(self.h, owner, _ptr(x), ctypes.byref(s)), "mpc3_share")
+        return out
+
+    def trunc_pair(self, n, t):
+        p = DPair(n, self.device)
+        _ck(lib().mpc3_trunc_pair(self.h, n, t, ctypes.byref(p.s)), "mpc3_trunc_pair")
+        self._keep.append(p)
+        return p
+
+    def inner(self, X, W, pair=None, out=None):
+        Z = out if out is not None else DShare.empty(X.rows, W.cols, self.device)
+        xs, ws, zs = X.c(), W.c(), Z.c()
+        _ck(lib().mpc3_inner(self.h, ctypes.byref(xs), ctypes.byref(ws),
+                             ctypes.byref(pair.s) if pair is not None else None, ctypes.byref(zs)), "mpc3_inner")
+        self._keep.append((X, W, Z))
+        return Z
+
+    def im2col(self, x, B, H, W, C, KH, KW, pad):
+        OH, OW = H + 2 * pad - KH + 1, W + 2 * pad - KW + 1
+        cols = DShare.empty(B * OH * OW, KH * KW * C, self.device)
+        xs, cs = x.c(), cols.c()
+        _ck(lib().mpc3_im2col(self.h, ctypes.byref(xs), B, H, W, C, KH, KW, pad, ctypes.byref(cs)), "mpc3_im2col")
+        return cols
+
+    def mult(self, a, b):
+        c = DShare.empty(a.rows, a.cols, self.device)
+        sa, sb, sc = a.c(), b.c(), c.c()
+        _ck(lib().mpc3_mult(self.h, ctypes.byref(sa), ctypes.byref(sb), ctypes.byref(sc)), "mpc3_mult")
+        self._keep.append((a, b, c))
+        return c
+
+    def trunc(self, pair, Z):
+        out = DShare.empty(Z.rows, Z.cols, self.device)
+        zs, os_ = Z.c(), out.c()
+        _ck(lib().mpc3_trunc(self.h, ctypes.byref(pair.s), ctypes.byref(zs), ctypes.byref(os_)), "mpc3_trunc")
+        return out
+
+    def verify(self, R=-1, kinds=VERIFY_ALL):
+        ok = ctypes.c_int(0)
+        _ck(lib().mpc3_verify(self.h, R, kinds, ctypes.byref(ok)), "mpc3_verify")
+        if kinds == VERIFY_ALL:
+            self._keep = []
+        return bool(ok.value)
+
+    def reconstruct(self, X, to_party=-1):
+        out = torch.empty(X.m.shape, dtype=torch.int64, device=self.device)
+        xs = X.c()
+        _ck(lib().mpc3_reconstruct(self.h, ctypes.byref(xs), to_party, _ptr(out)), "mpc3_reconstruct")
+        return out
+
+    def comm_stats(self):
+        c = Comm()
+        _ck(lib().mpc3_comm_stats(self.h, ctypes.byref(c)), "mpc3_comm_stats")
+        b = np.array(list(c.bytes), dtype=np.uint64).reshape(4, 3, 3)
+        return b, list(c.rounds)
+
+    def inject(self, site, index, e):
+        _ck(lib().mpc3_inject(self.h, site, index, e & ((1 << 64) - 1)), "mpc3_inject")
+
+    def message(self, kind, which, n):
+        out = torch.empty(n, dtype=torch.int64, device=self.device)
+        _ck(lib().mpc3_message(self.h, kind, which, _ptr(out), n), "mpc3_message")
+        return out
+
+    def profile(self, on=True):
+        _ck(lib().mpc3_profile(self.h, int(on)), "mpc3_profile")
+
+    def profile_read(self):
+        t, n, w = ctypes.c_double(0), ctypes.c_int64(0), ctypes.c_double(0)
+        _ck(lib().mpc3_profile_read(self.h, ctypes.byref(t), ctypes.byref(n), ctypes.byref(w)), "mpc3_profile_read")
+        return t.value, n.value, w.value
+
+    def verify_log(self, instance, slot, rnd=0):
+        buf = (ctypes.c_uint64 * 64)()
+        R = ctypes.c_int(0)
+        dim = ctypes.c_int64(0)
+        _ck(lib().mpc3_verify_log(self.h, instance, slot, rnd, buf, ctypes.byref(R), ctypes.byref(dim)),
+            "mpc3_verify_log")
+        return np.array(list(buf), dtype=np.uint64), R.value, dim.value

@@ -1,0 +1,234 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, bit for bit, on the
+same seeds and the same call sequence; plus properties at full workload sizes."""
+import numpy as np
+import pytest
+
+from oracle import prg
+from oracle.layers import im2col_share
+from oracle.protocol import Ctx
+from oracle.ring import encode as o_encode
+from paper_2411_09287_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2411_09287_amd import mpc3  # noqa: E402
+
+SEED = bytes(range(1, 33))
+MASK = (1 << 64) - 1
+
+
+def u64(g, *shape):
+    return g.integers(0, 1 << 64, size=shape, dtype=np.uint64, endpoint=False)
+
+
+def pair_of(variant=0, chunk=8, keep=True):
+    o = Ctx(SEED, chunk=chunk)
+    c = mpc3.Context(SEED)
+    c.set_variant(variant)
+    c.set_chunk(chunk)
+    if keep:
+        c.keep_messages(True)
+    return o, c
+
+
+def same_share(gs, os_):
+    gm, g1, g2 = gs.numpy()
+    return (np.array_equal(gm.reshape(-1), os_.m.reshape(-1)) and np.array_equal(g1.reshape(-1), os_.r1.reshape(-1))
+            and np.array_equal(g2.reshape(-1), os_.r2.reshape(-1)))
+
+
+def test_encode_decode_parity():
+    g = np.random.default_rng(0)
+    x = np.concatenate([g.standard_normal(1000) * 50, [0.0, -0.0, 1.5, -1.5, 2.0 ** -13, -(2.0 ** -14)]])
+    c = mpc3.Context(SEED)
+    v = c.encode(torch.from_numpy(x))
+    assert np.array_equal(mpc3.from_words(v), o_encode(x, 13))
+    d = c.decode(v).cpu().numpy()
+    assert np.array_equal(d, o_encode(x, 13).view(np.int64).astype(np.float64) / 8192.0)
+
+
+@pytest.mark.parametrize("owner", [0, 1, 2])
+@pytest.mark.parametrize("n", [1, 7, 8, 9, 1000, 4099])
+def test_share_parity(owner, n):
+    g = np.random.default_rng(n)
+    x = u64(g, n)
+    o, c = pair_of()
+    so = o.share(x.reshape(n, 1), owner=owner)
+    sg = c.share(mpc3.to_words(x.reshape(n, 1)), owner=owner)
+    assert same_share(sg, so)
+
+
+SHAPES = [(1, 1, 1), (5, 7, 3), (64, 128, 64), (130, 77, 65), (33, 300, 17), (2, 1025, 3)]
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_inner_parity(variant, shape):
+    M, K, N = shape
+    g = np.random.default_rng(M * 7 + K * 3 + N)
+    X0, W0 = u64(g, M, K), u64(g, K, N)
+    o, c = pair_of(variant)
+    Xo, Wo = o.share(X0), o.share(W0)
+    Zo = o.inner(Xo, Wo)
+    Xg, Wg = c.share(mpc3.to_words(X0)), c.share(mpc3.to_words(W0))
+    Zg = c.inner(Xg, Wg)
+    assert same_share(Zg, Zo)
+    for which, key in [(mpc3.MSG_GAMMA2, "gamma2"), (mpc3.MSG_M1, "m1"), (mpc3.MSG_M2, "m2")]:
+        msg = mpc3.from_words(c.message(0, which, M * N))
+        assert np.array_equal(msg, o.msgs["inner"][key].reshape(-1)), key
+
+
+@pytest.mark.parametrize("n,t", [(1, 13), (37, 13), (64, 1), (100, 62), (4096, 13)])
+def test_trunc_pair_parity(n, t):
+    o, c = pair_of()
+    po = o.trunc_pair(n, t)
+    pg = c.trunc_pair(n, t)
+    assert same_share(pg.rx, po["rx"]) and same_share(pg.rz, po["rz"])
+
+
+def _pipeline(o, c, g, M, K, N, inj=None):
+    """share -> truncation pair -> Pi_Inner -> Pi_Trunc -> Pi_Mult on both sides."""
+    X0, W0 = u64(g, M, K), u64(g, K, N)
+    a0, b0 = u64(g, 5, 1), u64(g, 5, 1)
+    if inj:
+        o.inject(*inj)
+        c.inject(*inj)
+    Xo, Wo = o.share(X0), o.share(W0)
+    Xg, Wg = c.share(mpc3.to_words(X0)), c.share(mpc3.to_words(W0))
+    po, pg = o.trunc_pair(M * N, 13), c.trunc_pair(M * N, 13)
+    Zo, Zg = o.inner(Xo, Wo, po), c.inner(Xg, Wg, pg)
+    To, Tg = o.trunc(po, Zo), c.trunc(pg, Zg)
+    ao, bo = o.share(a0), o.share(b0)
+    ag, bg = c.share(mpc3.to_words(a0)), c.share(mpc3.to_words(b0))
+    co, cg = o.mult(ao, bo), c.mult(ag, bg)
+    assert same_share(Zg, Zo) and same_share(Tg, To) and same_share(cg, co)
+    return To, Tg
+
+
+def _compare_transcripts(o, c):
+    for s, log in enumerate(o.vlog):
+        r, R, dim = c.verify_log(s, mpc3.LOG_R)
+        assert np.array_equal(r, log["r"]), s
+        assert R == log["R"] and dim == log["npad"]
+        assert np.array_equal(c.verify_log(s, mpc3.LOG_Z)[0], log["z"].m)
+        for k, rl in enumerate(log["rounds"]):
+            assert np.array_equal(c.verify_log(s, mpc3.LOG_ZETA, k)[0], rl["zeta"]), (s, k)
+            for slot, key in [(mpc3.LOG_H0_M1, "m1"), (mpc3.LOG_H0_M2, "m2"), (mpc3.LOG_H0_G2, "gamma2")]:
+                assert np.array_equal(c.verify_log(s, slot, k)[0], rl["h0"][key]), (s, k, key)
+            for slot, key in [(mpc3.LOG_H2_M1, "m1"), (mpc3.LOG_H2_M2, "m2"), (mpc3.LOG_H2_G2, "gamma2")]:
+                assert np.array_equal(c.verify_log(s, slot, k)[0], rl["h2"][key]), (s, k, key)
+        assert np.array_equal(c.verify_log(s, mpc3.LOG_DELTA)[0], log["delta"])
+        for slot, key in [(mpc3.LOG_DELTA_M1, "m1"), (mpc3.LOG_DELTA_M2, "m2"), (mpc3.LOG_DELTA_G2, "gamma2")]:
+            assert np.array_equal(c.verify_log(s, slot)[0], log["delta_tr"][key]), (s, key)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("shape,R", [((3, 5, 4), -1), ((4, 27, 6), 2), ((6, 64, 5), 6), ((2, 3, 2), 0)])
+def test_verify_transcript_parity(variant, shape, R):
+    g = np.random.default_rng(sum(shape) + R)
+    o, c = pair_of(variant, chunk=4)
+    To, Tg = _pipeline(o, c, g, *shape)
+    ok_o = o.verify(R=R)
+    ok_g = c.verify(R=R)
+    assert ok_o and ok_g
+    _compare_transcripts(o, c)
+    out_g = mpc3.from_words(c.reconstruct(Tg)).reshape(-1)
+    assert np.array_equal(out_g, o.reconstruct(To).reshape(-1))
+    bg, rg = c.comm_stats()
+    assert np.array_equal(bg, np.array(o.comm, dtype=np.uint64)) and rg == o.rounds
+
+
+SITES = [mpc3.SITE_INNER_GAMMA2, mpc3.SITE_INNER_M1, mpc3.SITE_TRUNC_GAMMA2, mpc3.SITE_TRUNC_M1,
+         mpc3.SITE_MULT_GAMMA2, mpc3.SITE_VER_H0_M1, mpc3.SITE_VER_H2_GAMMA2, mpc3.SITE_VER_DELTA_M1]
+
+
+@pytest.mark.parametrize("site", SITES)
+@pytest.mark.parametrize("e", [1, 1 << 63])
+def test_injected_error_detected(site, e):
+    g = np.random.default_rng(site)
+    o, c = pair_of(0, chunk=4)
+    To, Tg = _pipeline(o, c, g, 2, 5, 3, inj=(site, 3, e))
+    assert not o.verify() and not c.verify()
+    _compare_transcripts(o, c)
+    with pytest.raises(mpc3.Mpc3Error) as ei:
+        c.reconstruct(Tg)
+    assert ei.value.code == mpc3.E_ABORTED
+
+
+def test_reconstruct_inconsistency_aborts():
+    c = mpc3.Context(SEED)
+    s = c.share(mpc3.to_words(np.arange(10, dtype=np.uint64).reshape(10, 1)))
+    assert np.array_equal(mpc3.from_words(c.reconstruct(s)).reshape(-1), np.arange(10))
+    c.inject(mpc3.SITE_REC_R1, 4, 77)
+    with pytest.raises(mpc3.Mpc3Error) as ei:
+        c.reconstruct(s)
+    assert ei.value.code == mpc3.E_ABORTED
+
+
+def test_reconstruct_requires_verification():
+    c = mpc3.Context(SEED)
+    g = np.random.default_rng(3)
+    Z = c.inner(c.share(mpc3.to_words(u64(g, 2, 2))), c.share(mpc3.to_words(u64(g, 2, 2))))
+    with pytest.raises(mpc3.Mpc3Error) as ei:
+        c.reconstruct(Z)
+    assert ei.value.code == mpc3.E_UNVERIFIED
+    assert c.verify()
+    c.reconstruct(Z)
+
+
+@pytest.mark.parametrize("B,H,W,C,KH,KW,pad", [(2, 6, 5, 3, 3, 3, 1), (1, 8, 8, 1, 5, 5, 0), (3, 4, 4, 2, 3, 3, 1)])
+def test_im2col_parity(B, H, W, C, KH, KW, pad):
+    g = np.random.default_rng(B * H)
+    x0 = u64(g, B, H, W, C)
+    o, c = pair_of()
+    xo = o.share(x0.reshape(B, -1))
+    xg = c.share(mpc3.to_words(x0.reshape(B, -1)))
+    co = im2col_share(xo.map(lambda a: a.reshape(B, H, W, C)), KH, KW, pad)
+    cg = c.im2col(xg, B, H, W, C, KH, KW, pad)
+    assert same_share(cg, co)
+
+
+def test_variants_bit_identical_on_ragged_shapes():
+    g = np.random.default_rng(11)
+    for M, K, N in [(67, 129, 33), (256, 512, 64), (1, 2048, 1)]:
+        X0, W0 = u64(g, M, K), u64(g, K, N)
+        outs = []
+        for v in (0, 1):
+            c = mpc3.Context(SEED)
+            c.set_variant(v)
+            outs.append(c.inner(c.share(mpc3.to_words(X0)), c.share(mpc3.to_words(W0))).numpy())
+        assert all(np.array_equal(a, b) for a, b in zip(*outs))
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_full_size_layer_sampled(variant):
+    """VGG conv2 shape (32768 x 576 x 64): sampled outputs against Python-integer dot
+    products, masks against the oracle PRG, and an honest verification that passes."""
+    M, K, N = workloads.model_shapes("vgg")[1]
+    g = np.random.default_rng(99)
+    X0, W0 = u64(g, M, K), u64(g, K, N)
+    c = mpc3.Context(SEED)
+    c.set_variant(variant)
+    Z = c.inner(c.share(mpc3.to_words(X0)), c.share(mpc3.to_words(W0)))
+    assert c.verify(kinds=mpc3.VERIFY_INNER)
+    val = mpc3.from_words(c.reconstruct(Z))
+    zr1 = mpc3.from_words(Z.r1)
+    op = 2     # two shares precede the product
+    for m, n in [(0, 0), (M - 1, N - 1), (12345, 17), (M // 2, 63)]:
+        want = sum(int(X0[m, k]) * int(W0[k, n]) for k in range(K)) & MASK
+        assert int(val[m, n]) == want
+        seeds = prg.pair_seeds(SEED)
+        assert zr1[m, n] == prg.words(seeds[(0, 1)], prg.tag(op, prg.INNER_RZ, 1), 1, m * N + n)[0]
+
+
+def test_full_size_layer_rejects_top_bit_error():
+    M, K, N = workloads.model_shapes("vgg")[1]
+    g = np.random.default_rng(5)
+    c = mpc3.Context(SEED)
+    c.inject(mpc3.SITE_INNER_M1, 123456, 1 << 63)
+    c.inner(c.share(mpc3.to_words(u64(g, M, K))), c.share(mpc3.to_words(u64(g, K, N))))
+    assert not c.verify()
