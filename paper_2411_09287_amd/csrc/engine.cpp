@@ -160,7 +160,14 @@ Inj take_ver(mpc3_ctx* c, int site, int64_t inst, int round) {
 View view(const u64* p, int64_t s0, int64_t s1, int64_t sb = 0) { return View{p, s0, s1, sb}; }
 OutView oview(u64* p, int64_t s0, int64_t s1, int64_t sb = 0) { return OutView{p, s0, s1, sb}; }
 
-void run_gemm(mpc3_ctx* c, const GemmArgs& g) { ck(gemm(g, c->variant, c->stream)); }
+void* scratch_alloc(void* self, size_t n) { return ((Scratch*)self)->alloc(n); }
+
+void run_gemm(mpc3_ctx* c, const GemmArgs& g) {
+    GemmArgs a = g;
+    a.ws_alloc = scratch_alloc;
+    a.ws_self = &c->scratch;
+    ck(gemm(a, c->variant, c->stream));
+}
 
 GemmArgs plain(int64_t M, int64_t N, int64_t K, View A, View B, OutView C, bool acc, int batch = 1) {
     GemmArgs g{};

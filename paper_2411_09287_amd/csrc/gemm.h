@@ -28,6 +28,9 @@ struct GemmArgs {
     View A[3], B[3];          // plain uses index 0
     OutView C[3];
     View Dadd;                // plain, non-accumulating: C = AB + Dadd
+    // device workspace for the limb backend (stream-ordered bump allocator of the caller)
+    void* (*ws_alloc)(void* self, size_t bytes);
+    void* ws_self;
 };
 
 // Launch on `stream` with the chosen backend (0 = u64 VALU, 1 = int8 limbs on MFMA).

@@ -62,7 +62,8 @@ def test_share_parity(owner, n):
     assert same_share(sg, so)
 
 
-SHAPES = [(1, 1, 1), (5, 7, 3), (64, 128, 64), (130, 77, 65), (33, 300, 17), (2, 1025, 3)]
+SHAPES = [(1, 1, 1), (5, 7, 3), (64, 128, 64), (130, 77, 65), (33, 300, 17), (2, 1025, 3),
+          (130, 300, 129), (257, 1030, 70)]
 
 
 @pytest.mark.parametrize("variant", [0, 1])
@@ -194,7 +195,8 @@ def test_im2col_parity(B, H, W, C, KH, KW, pad):
 
 def test_variants_bit_identical_on_ragged_shapes():
     g = np.random.default_rng(11)
-    for M, K, N in [(67, 129, 33), (256, 512, 64), (1, 2048, 1)]:
+    for M, K, N in [(67, 129, 33), (256, 512, 64), (1, 2048, 1), (1000, 33, 200), (64, 9000, 64),
+                    (4097, 27, 65)]:
         X0, W0 = u64(g, M, K), u64(g, K, N)
         outs = []
         for v in (0, 1):
@@ -232,3 +234,22 @@ def test_full_size_layer_rejects_top_bit_error():
     c.inject(mpc3.SITE_INNER_M1, 123456, 1 << 63)
     c.inner(c.share(mpc3.to_words(u64(g, M, K))), c.share(mpc3.to_words(u64(g, K, N))))
     assert not c.verify()
+
+
+def test_variant_transcripts_identical():
+    """The whole verification transcript is the same on both kernel families."""
+    g = np.random.default_rng(21)
+    X0, W0 = u64(g, 512, 300), u64(g, 300, 96)
+    logs = []
+    for v in (0, 1):
+        c = mpc3.Context(SEED)
+        c.set_variant(v)
+        Z = c.inner(c.share(mpc3.to_words(X0)), c.share(mpc3.to_words(W0)))
+        assert c.verify()
+        R = c.verify_log(0, mpc3.LOG_R)[1]
+        entries = [c.verify_log(0, s)[0] for s in (mpc3.LOG_R, mpc3.LOG_Z, mpc3.LOG_DELTA)]
+        entries += [c.verify_log(0, s, k)[0] for k in range(R) for s in (mpc3.LOG_ZETA, mpc3.LOG_H0_M1,
+                                                                          mpc3.LOG_H2_G2)]
+        logs.append((Z.numpy(), entries))
+    assert all(np.array_equal(a, b) for a, b in zip(logs[0][0], logs[1][0]))
+    assert all(np.array_equal(a, b) for a, b in zip(logs[0][1], logs[1][1]))
