@@ -118,6 +118,14 @@ struct mpc3_ctx {
     // public transcript of the last verification
     std::vector<uint64_t> vlog;
     std::vector<InstanceInfo> vinfo;
+    // verification instances run on NV worker streams, each with its own workspace;
+    // cs / sc are the stream and workspace the helpers below enqueue on
+    static constexpr int NV = 4;
+    hipStream_t vs[NV] = {};
+    Scratch vsc[NV];
+    hipEvent_t ev_fork = nullptr, ev_join[NV] = {};
+    hipStream_t cs = nullptr;
+    Scratch* sc = nullptr;
     // launch timing of the Pi_Inner products
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -165,8 +173,8 @@ void* scratch_alloc(void* self, size_t n) { return ((Scratch*)self)->alloc(n); }
 void run_gemm(mpc3_ctx* c, const GemmArgs& g) {
     GemmArgs a = g;
     a.ws_alloc = scratch_alloc;
-    a.ws_self = &c->scratch;
-    ck(gemm(a, c->variant, c->stream));
+    a.ws_self = c->sc;
+    ck(gemm(a, c->variant, c->cs));
 }
 
 GemmArgs plain(int64_t M, int64_t N, int64_t K, View A, View B, OutView C, bool acc, int batch = 1) {
@@ -177,17 +185,17 @@ GemmArgs plain(int64_t M, int64_t N, int64_t K, View A, View B, OutView C, bool 
     return g;
 }
 
-void zero(mpc3_ctx* c, void* p, size_t bytes) { ck(hipMemsetAsync(p, 0, bytes, c->stream)); }
+void zero(mpc3_ctx* c, void* p, size_t bytes) { ck(hipMemsetAsync(p, 0, bytes, c->cs)); }
 
 // table[i] = base^i for i < n (table: n x 64), doubling: table[len + i] = table[i] base^len.
 void power_table(mpc3_ctx* c, const u64* base, int64_t n, u64* table) {
-    hipStream_t s = c->stream;
+    hipStream_t s = c->cs;
     launch_set_one(table, s);
     if (n <= 1) return;
-    Scratch::Mark mk = c->scratch.mark();
-    u64* P = c->scratch.words(64);
-    u64* P2 = c->scratch.words(64);
-    u64* WP = c->scratch.words(4096);
+    Scratch::Mark mk = c->sc->mark();
+    u64* P = c->sc->words(64);
+    u64* P2 = c->sc->words(64);
+    u64* WP = c->sc->words(4096);
     ck(hipMemcpyAsync(P, base, 512, hipMemcpyDeviceToDevice, s));
     for (int64_t len = 1; len < n; len *= 2) {
         const int64_t cnt = std::min(len, n - len);
@@ -198,7 +206,7 @@ void power_table(mpc3_ctx* c, const u64* base, int64_t n, u64* table) {
             std::swap(P, P2);
         }
     }
-    c->scratch.restore(mk);
+    c->sc->restore(mk);
 }
 
 int auto_rounds(int64_t n0, int R) {
@@ -250,14 +258,14 @@ void gr_dot_party(mpc3_ctx* c, int64_t n, const u64* A[3], int64_t astride, cons
 void polyevl_run(mpc3_ctx* c, const VerCtx& v, int64_t n, const u64* A[3], int64_t astride, const u64* B[3],
                  int64_t bstride, uint32_t pr, uint32_t pg, uint32_t sub, Inj im1, Inj ig2, u64* out, u64* lm1,
                  u64* lm2, u64* lg2, u64* reveal, int* flag) {
-    u64* C = c->scratch.words(3 * 4096);
+    u64* C = c->sc->words(3 * 4096);
     gr_dot_party(c, n, A, astride, B, bstride, C);
     PolyEvlArgs a{};
     a.C = C; a.k = c->keys; a.op = v.op; a.pr = pr; a.pg = pg; a.sub = sub;
     a.inj_m1 = im1.index >= 0 ? (int)im1.index : -1; a.e_m1 = im1.e;
     a.inj_g2 = ig2.index >= 0 ? (int)ig2.index : -1; a.e_g2 = ig2.e;
     a.out = out; a.log_m1 = lm1; a.log_m2 = lm2; a.log_g2 = lg2; a.reveal = reveal; a.nonzero_flag = flag;
-    launch_polyevl_finish(a, c->stream);
+    launch_polyevl_finish(a, c->cs);
     // one Pi_PolyEvl: P0 -> P2 [Gamma]_2 (verification offline), P1 <-> P2 (verification online)
     send(c, MPC3_PH_VERIFY_OFFLINE, 0, 2, 8 * 64);
     send(c, MPC3_PH_VERIFY_ONLINE, 1, 2, 8 * 64);
@@ -266,12 +274,12 @@ void polyevl_run(mpc3_ctx* c, const VerCtx& v, int64_t n, const u64* A[3], int64
 
 // R x Pi_Reduce, then Pi_InnerVerify.  XY: 6 planes (x: m, r1, r2; y: m, r1, r2) of n rows.
 void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, int R) {
-    hipStream_t s = c->stream;
+    hipStream_t s = c->cs;
     for (int k = 0; k < R; ++k) {
         const int64_t half = n / 2;
         const uint32_t sub = ((uint32_t)v.inst << 8) | (uint32_t)k;
-        u64* h0 = c->scratch.words(3 * 64);
-        u64* h2 = c->scratch.words(3 * 64);
+        u64* h0 = c->sc->words(3 * 64);
+        u64* h2 = c->sc->words(3 * 64);
         {   // h(0) = sum f_i(0) g_i(0): rows 2i of x and y
             const u64* A[3] = {XY, XY + n * 64, XY + 2 * n * 64};
             const u64* B[3] = {XY + 3 * n * 64, XY + 4 * n * 64, XY + 5 * n * 64};
@@ -280,7 +288,7 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
                         slot(v, MPC3_LOG_H0_M2, k), slot(v, MPC3_LOG_H0_G2, k), nullptr, nullptr);
         }
         {   // h(x) = sum f_i(x) g_i(x), f_i(x) = f_i(0) + x (f_i(1) - f_i(0))
-            u64* F2 = c->scratch.words(6 * half * 64);
+            u64* F2 = c->sc->words(6 * half * 64);
             launch_at_x(XY, 6, n, F2, s);
             const u64* A[3] = {F2, F2 + half * 64, F2 + 2 * half * 64};
             const u64* B[3] = {F2 + 3 * half * 64, F2 + 4 * half * 64, F2 + 5 * half * 64};
@@ -289,18 +297,18 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
                         slot(v, MPC3_LOG_H2_M2, k), slot(v, MPC3_LOG_H2_G2, k), nullptr, nullptr);
         }
         c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
-        u64* zeta = c->scratch.words(64);
+        u64* zeta = c->sc->words(64);
         RoundArgs ra{};
         ra.k = c->keys; ra.op = v.op; ra.sub = sub; ra.inv = c->inv_dev; ra.h0 = h0; ra.h2 = h2; ra.z = z;
         ra.zeta_out = zeta; ra.log_zeta = slot(v, MPC3_LOG_ZETA, k);
         launch_round_finish(ra, s);
         count_reveal(c, MPC3_PH_VERIFY_ONLINE);
         // fold: row i <- f_i(0) + zeta (f_i(1) - f_i(0)) for all six planes
-        u64* Wz = c->scratch.words(4096);
+        u64* Wz = c->sc->words(4096);
         launch_mulmat(zeta, 64, 1, Wz, s);
-        u64* Dd = c->scratch.words(6 * half * 64);
+        u64* Dd = c->sc->words(6 * half * 64);
         launch_sub_pairs(XY, 6, n, Dd, s);
-        u64* XYn = c->scratch.words(6 * half * 64);
+        u64* XYn = c->sc->words(6 * half * 64);
         GemmArgs g = plain(half, 64, 64, view(Dd, 64, 1, half * 64), view(Wz, 64, 1, 0),
                            oview(XYn, 64, 1, half * 64), false, 6);
         g.Dadd = view(XY, 128, 1, n * 64);
@@ -309,11 +317,11 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
         n = half;
     }
     // Pi_InnerVerify
-    u64* alpha = c->scratch.words(3 * 64);
+    u64* alpha = c->sc->words(3 * 64);
     launch_random_gr(c->keys, v.op, P_VER_ALPHA, (uint32_t)v.inst, alpha, nullptr, nullptr, s);
-    u64* Wa = c->scratch.words(3 * 4096);
+    u64* Wa = c->sc->words(3 * 4096);
     launch_mulmat(alpha, 64, 3, Wa, s);
-    u64* C = c->scratch.words(3 * n * 64);
+    u64* C = c->sc->words(3 * n * 64);
     {
         GemmArgs g{};
         g.M = n; g.N = 64; g.K = 64; g.batch = 1; g.party = true; g.accumulate = false;
@@ -325,10 +333,10 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
         run_gemm(c, g);
     }
     const int64_t n1 = n + 1;
-    u64* XP = c->scratch.words(3 * n1 * 64);
+    u64* XP = c->sc->words(3 * n1 * 64);
     // x'_i = Pi_Mult(x_i, alpha): rows 0..n-1 of each plane; row n = -alpha
     {
-        u64* tmp = c->scratch.words(3 * n * 64);
+        u64* tmp = c->sc->words(3 * n * 64);
         launch_xp_epilogue(n, c->keys, v.op, (uint32_t)v.inst, C, C + n * 64, C + 2 * n * 64, tmp, tmp + n * 64,
                            tmp + 2 * n * 64, s);
         for (int p = 0; p < 3; ++p)
@@ -339,12 +347,12 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
     send(c, MPC3_PH_VERIFY_ONLINE, 1, 2, 8 * 64 * n);
     send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8 * 64 * n);
     c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
-    u64* YZ = c->scratch.words(3 * n1 * 64);
+    u64* YZ = c->sc->words(3 * n1 * 64);
     for (int p = 0; p < 3; ++p) {
         ck(hipMemcpyAsync(YZ + p * n1 * 64, XY + (3 + p) * n * 64, n * 512, hipMemcpyDeviceToDevice, s));
         ck(hipMemcpyAsync(YZ + p * n1 * 64 + n * 64, z + p * 64, 512, hipMemcpyDeviceToDevice, s));
     }
-    u64* delta = c->scratch.words(3 * 64);
+    u64* delta = c->sc->words(3 * 64);
     const u64* A[3] = {XP, XP + n1 * 64, XP + 2 * n1 * 64};
     const u64* B[3] = {YZ, YZ + n1 * 64, YZ + 2 * n1 * 64};
     polyevl_run(c, v, n1, A, 64, B, 64, P_VER_DELTA_R, P_VER_DELTA_GAMMA, (uint32_t)v.inst,
@@ -355,29 +363,29 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
 }
 
 u64* challenge(mpc3_ctx* c, const VerCtx& v) {
-    u64* r = c->scratch.words(64);
-    launch_random_gr(c->keys, v.op, P_VER_R, (uint32_t)v.inst, nullptr, r, slot(v, MPC3_LOG_R), c->stream);
+    u64* r = c->sc->words(64);
+    launch_random_gr(c->keys, v.op, P_VER_R, (uint32_t)v.inst, nullptr, r, slot(v, MPC3_LOG_R), c->cs);
     count_reveal(c, MPC3_PH_VERIFY_ONLINE);
     return r;
 }
 
 void verify_inner(mpc3_ctx* c, const VerCtx& v, const Pending& it, int Rarg) {
-    hipStream_t s = c->stream;
+    hipStream_t s = c->cs;
     const int64_t M = it.X.rows, K = it.X.cols, N = it.W.cols;
     u64* r = challenge(c, v);
-    u64* sigma = c->scratch.words(N * 64);
+    u64* sigma = c->sc->words(N * 64);
     power_table(c, r, N, sigma);
-    u64* rN = c->scratch.words(64);
+    u64* rN = c->sc->words(64);
     {
-        u64* Wr = c->scratch.words(4096);
+        u64* Wr = c->sc->words(4096);
         launch_mulmat(r, 64, 1, Wr, s);
         run_gemm(c, plain(1, 64, 64, view(sigma + (N - 1) * 64, 64, 1), view(Wr, 64, 1), oview(rN, 64, 1), false));
     }
-    u64* rho = c->scratch.words(M * 64);
+    u64* rho = c->sc->words(M * 64);
     power_table(c, rN, M, rho);
     const int R = auto_rounds(K, Rarg);
     const int64_t np = padded(K, R);
-    u64* XY = c->scratch.words(6 * np * 64);
+    u64* XY = c->sc->words(6 * np * 64);
     zero(c, XY, (size_t)6 * np * 64 * 8);
     const u64* Xc[3] = {it.X.m, it.X.r1, it.X.r2};
     const u64* Wc[3] = {it.W.m, it.W.r1, it.W.r2};
@@ -389,11 +397,11 @@ void verify_inner(mpc3_ctx* c, const VerCtx& v, const Pending& it, int Rarg) {
         run_gemm(c, plain(K, 64, N, view(Wc[p], N, 1), view(sigma, 64, 1), oview(XY + (3 + p) * np * 64, 64, 1),
                           true));
     }
-    u64* z = c->scratch.words(3 * 64);
+    u64* z = c->sc->words(3 * 64);
     {
-        u64* T = c->scratch.words(3 * N * 64);
+        u64* T = c->sc->words(3 * N * 64);
         zero(c, T, (size_t)3 * N * 64 * 8);
-        u64* Cz = c->scratch.words(3 * 4096);
+        u64* Cz = c->sc->words(3 * 4096);
         zero(c, Cz, 3 * 4096 * 8);
         for (int p = 0; p < 3; ++p) {
             // T_n = sum_m rho_m Z[m, n]; z = sum_n sigma_n T_n (ring products, anti-diagonal fold)
@@ -409,18 +417,18 @@ void verify_inner(mpc3_ctx* c, const VerCtx& v, const Pending& it, int Rarg) {
 }
 
 void verify_mult(mpc3_ctx* c, const VerCtx& v, const Pending& it, int Rarg) {
-    hipStream_t s = c->stream;
+    hipStream_t s = c->cs;
     const int64_t n = it.X.rows * it.X.cols;
     u64* r = challenge(c, v);
-    u64* pw = c->scratch.words(n * 64);
+    u64* pw = c->sc->words(n * 64);
     power_table(c, r, n, pw);
     const int R = auto_rounds(n, Rarg);
     const int64_t np = padded(n, R);
-    u64* XY = c->scratch.words(6 * np * 64);
+    u64* XY = c->sc->words(6 * np * 64);
     zero(c, XY, (size_t)6 * np * 64 * 8);
     launch_scale_rows(n, it.X.m, it.X.r1, it.X.r2, pw, XY, np * 64, s);      // x'_i = r^i a_i
     launch_lift_rows(n, it.W.m, it.W.r1, it.W.r2, XY + 3 * np * 64, np * 64, s);
-    u64* z = c->scratch.words(3 * 64);
+    u64* z = c->sc->words(3 * 64);
     zero(c, z, 3 * 64 * 8);
     const u64* Zc[3] = {it.Z.m, it.Z.r1, it.Z.r2};
     for (int p = 0; p < 3; ++p)
@@ -431,24 +439,24 @@ void verify_mult(mpc3_ctx* c, const VerCtx& v, const Pending& it, int Rarg) {
 }
 
 void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t lo, int64_t T, int Rarg) {
-    hipStream_t s = c->stream;
+    hipStream_t s = c->cs;
     const mpc3_trunc_pair_t& p = it.pair;
     u64* r = challenge(c, v);
-    u64* pw = c->scratch.words(2 * T * 64);
+    u64* pw = c->sc->words(2 * T * 64);
     power_table(c, r, 2 * T, pw);
     const int64_t n0 = 128 * T;
     const int R = auto_rounds(n0, Rarg);
     const int64_t np = padded(n0, R);
-    u64* XY = c->scratch.words(6 * np * 64);
+    u64* XY = c->sc->words(6 * np * 64);
     zero(c, XY, (size_t)6 * np * 64 * 8);
-    u64* B1 = c->scratch.words(T);
-    u64* B2 = c->scratch.words(T);
+    u64* B1 = c->sc->words(T);
+    u64* B2 = c->sc->words(T);
     launch_fill_at(B1, T, lo, c->keys.k01, make_tag(it.op, P_TRUNC_B, 1, 0), s);
     launch_fill_at(B2, T, lo, c->keys.k02, make_tag(it.op, P_TRUNC_B, 2, 0), s);
-    u64* w3 = c->scratch.words(6 * T);
+    u64* w3 = c->sc->words(6 * T);
     launch_trunc_instance2(lo, T, p.t, B1, B2, pw, p.rx.m, p.rx.r1, p.rx.r2, p.rz.m, p.rz.r1, p.rz.r2,
                            XY + 1 * np * 64, XY + 5 * np * 64, w3, s);
-    u64* z = c->scratch.words(3 * 64);
+    u64* z = c->sc->words(3 * 64);
     zero(c, z, 3 * 64 * 8);
     for (int q = 0; q < 3; ++q)
         run_gemm(c, plain(1, 64, 2 * T, view(w3 + q * 2 * T, 0, 1), view(pw, 64, 1), oview(z + q * 64, 64, 1), true));
@@ -507,6 +515,8 @@ int mpc3_ctx_create(const uint8_t master_seed[32], int d, int frac_bits, size_t 
     return wrap([&] {
         mpc3_ctx* c = new mpc3_ctx();
         c->stream = (hipStream_t)hip_stream;
+        c->cs = c->stream;
+        c->sc = &c->scratch;
         c->frac = frac_bits;
         auto eta = [&](std::initializer_list<uint8_t> ids) {
             host::Sha256 h;
@@ -556,6 +566,15 @@ int mpc3_ctx_destroy(mpc3_ctx* c) {
     if (!c) return MPC3_E_ARG;
     (void)hipStreamSynchronize(c->stream);
     c->scratch.release();
+    for (int i = 0; i < mpc3_ctx::NV; ++i) {
+        if (c->vs[i]) {
+            (void)hipStreamSynchronize(c->vs[i]);
+            (void)hipStreamDestroy(c->vs[i]);
+            (void)hipEventDestroy(c->ev_join[i]);
+        }
+        c->vsc[i].release();
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     for (int k = 0; k < 2; ++k)
         for (int i = 0; i < 3; ++i)
             if (c->msg[k][i]) (void)hipFree(c->msg[k][i]);
@@ -795,25 +814,52 @@ int mpc3_verify(mpc3_ctx* c, int R, int kinds, int* ok) {
         zero(c, logd, (size_t)std::max<int64_t>(ninst, 1) * NSLOT * 64 * 8);
         zero(c, flags, std::max<int64_t>(ninst, 1) * sizeof(int));
         c->vinfo.clear();
+        if (!c->ev_fork) {
+            ck(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+            for (int i = 0; i < mpc3_ctx::NV; ++i) {
+                ck(hipStreamCreateWithFlags(&c->vs[i], hipStreamNonBlocking));
+                ck(hipEventCreateWithFlags(&c->ev_join[i], hipEventDisableTiming));
+            }
+        }
+        ck(hipEventRecord(c->ev_fork, s));
+        for (int i = 0; i < mpc3_ctx::NV; ++i) {
+            ck(hipStreamWaitEvent(c->vs[i], c->ev_fork, 0));
+            c->vsc[i].reset();
+        }
+        // instances are independent: instance i runs on worker stream i mod NV
+        struct Restore {
+            mpc3_ctx* c;
+            ~Restore() { c->cs = c->stream; c->sc = &c->scratch; }
+        } restore{c};
         int64_t inst = 0;
+        auto lane = [&](int64_t i) {
+            c->cs = c->vs[i % mpc3_ctx::NV];
+            c->sc = &c->vsc[i % mpc3_ctx::NV];
+        };
         for (auto& p : sel) {
             if (p.kind == MPC3_VERIFY_TRUNC) {
                 for (int64_t lo = 0; lo < p.pair.n; lo += c->chunk) {
                     const int64_t T = std::min(c->chunk, p.pair.n - lo);
-                    Scratch::Mark mk = c->scratch.mark();
+                    lane(inst);
+                    Scratch::Mark mk = c->sc->mark();
                     VerCtx v{op, inst, logd + inst * NSLOT * 64, flags + inst};
                     verify_trunc_chunk(c, v, p, lo, T, R);
-                    c->scratch.restore(mk);
+                    c->sc->restore(mk);
                     ++inst;
                 }
             } else {
-                Scratch::Mark mk = c->scratch.mark();
+                lane(inst);
+                Scratch::Mark mk = c->sc->mark();
                 VerCtx v{op, inst, logd + inst * NSLOT * 64, flags + inst};
                 if (p.kind == MPC3_VERIFY_INNER) verify_inner(c, v, p, R);
                 else verify_mult(c, v, p, R);
-                c->scratch.restore(mk);
+                c->sc->restore(mk);
                 ++inst;
             }
+        }
+        for (int i = 0; i < mpc3_ctx::NV; ++i) {
+            ck(hipEventRecord(c->ev_join[i], c->vs[i]));
+            ck(hipStreamWaitEvent(s, c->ev_join[i], 0));
         }
         std::vector<int> hflags(std::max<int64_t>(ninst, 1), 0);
         c->vlog.assign((size_t)std::max<int64_t>(ninst, 1) * NSLOT * 64, 0);

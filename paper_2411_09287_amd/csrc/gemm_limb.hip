@@ -6,6 +6,11 @@
 // 36 int8 matrix products accumulated into 8 int32 planes.  |P_s| <= K 8 2^14, so the
 // int32 planes are folded into 64-bit partial sums every 8192 of K.  The result is
 // bit-identical to the 64-bit integer product.
+//
+// The balanced digits of a are the bytes of (a + 0x8080..80) xor 0x8080..80 read as
+// int8: the byte carries of that addition are exactly the carries of the balanced
+// representation.  Tiles are read as 64-bit words, converted in registers, transposed
+// to digit planes in LDS and fed to v_mfma_i32_32x32x32_i8; no digit planes touch HBM.
 #include "gemm.h"
 
 namespace mpc3 {
@@ -17,131 +22,197 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int TM = 64, TN = 64, KB = 32, KSEG = 8192;
+constexpr int TM = 64, TN = 64, KB = 32, KSEG = 8192, NT = 256;
+constexpr u64 OFF = 0x8080808080808080ull;
+constexpr int PLANE = 64 * KB;            // bytes of one digit plane of a 64 x 32 tile
 
-inline int64_t rup(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
-
-// Source of a digit conversion: v(r, k) = sum_i c_i P_i[r*s_r + k*s_k] (up to 3 planes).
-struct DigitSrc {
-    const u64* p[3];
-    int c[3];
+// One operand of a product segment: v(r, k) = sum_i c_i P_i[b + r*s_r + k*s_k].
+struct Opnd {
+    const u64* p[2];
+    int c[2];
     int64_t s_r, s_k;
+    int64_t rows;                         // valid rows (M for A, N for B)
 };
 
-// dst[d*plane + r*ld + koff + k]: balanced digit d of v(r, k); zero for r >= rows or k >= K.
-// One thread converts 16 consecutive k of one row.
-__global__ void k_digits(DigitSrc s, int64_t rows, int64_t K, int64_t Rp, int64_t nch, int8_t* dst,
-                         int64_t plane, int64_t ld, int64_t koff, int kfast) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= Rp * nch) return;
-    int64_t r, ch;
-    if (kfast) { r = idx / nch; ch = idx - r * nch; }
-    else { ch = idx / Rp; r = idx - ch * Rp; }
-    u32 out[8][4];
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        u32 pk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int64_t k = ch * 16 + w * 4 + b;
-            u64 v = 0;
-            if (r < rows && k < K) {
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-                    if (s.c[i]) {
-                        const u64 x = s.p[i][r * s.s_r + k * s.s_k];
-                        v += s.c[i] > 0 ? x : (0 - x);
-                    }
-            }
-            int carry = 0;
-#pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                int x = (int)((v >> (8 * d)) & 0xFF) + carry;
-                carry = x >= 128;
-                x -= carry << 8;
-                pk[d] |= ((u32)(x & 0xFF)) << (8 * b);
-            }
-        }
-#pragma unroll
-        for (int d = 0; d < 8; ++d) out[d][w] = pk[d];
-    }
-#pragma unroll
-    for (int d = 0; d < 8; ++d) {
-        v4i q;
-        q.x = (int)out[d][0]; q.y = (int)out[d][1]; q.z = (int)out[d][2]; q.w = (int)out[d][3];
-        *(v4i*)(dst + d * plane + r * ld + koff + ch * 16) = q;
-    }
-}
+// A product: up to two K segments (each padded to Kp), operands for each.
+struct Prod {
+    Opnd a[2], b[2];
+    int nseg;
+    OutView C;
+};
 
 struct LArgs {
-    const int8_t* A8;
-    int64_t a_plane, lda;
-    const int8_t* B8;
-    int64_t b_plane, ldb;
-    int64_t M, N, Kc;           // Kc: contraction length (multiple of 32)
-    int64_t kchunk;             // per split (multiple of 32)
-    OutView C;
-    View D;
+    Prod prod[3];
+    int64_t M, N, K, Kp;                  // Kp: K rounded up to KB
+    int64_t kchunk;                       // per split, multiple of KB
+    int splits;
     int atomic;
+    View D;
 };
 
-__device__ __forceinline__ void flush(u64 part[16], v16i acc[8]) {
+// 8 consecutive k of one row of an operand, loaded raw: w[i] = v(row, k0 + i).
+__device__ __forceinline__ void load8(const Opnd& o, int64_t row, int64_t k0, int64_t K, u64 w[8]) {
+    const bool inrow = row < o.rows;
+    const int64_t base = row * o.s_r + k0 * o.s_k;
+    if (inrow && o.s_k == 1 && k0 + 8 <= K && ((base | (int64_t)(uintptr_t)o.p[0]) & 1) == 0 &&
+        (!o.c[1] || ((int64_t)(uintptr_t)o.p[1] & 15) == 0)) {
+        // 16-byte vector loads of the 8 contiguous words
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        u64 t = 0;
+        for (int h = 0; h < 4; ++h) {
+            const ulonglong2 x = *(const ulonglong2*)(o.p[0] + base + 2 * h);
+            w[2 * h] = x.x;
+            w[2 * h + 1] = x.y;
+        }
+        if (o.c[0] < 0)
 #pragma unroll
-        for (int s = 0; s < 8; ++s) t += ((u64)(int64_t)acc[s][v]) << (8 * s);
-        part[v] += t;
+            for (int i = 0; i < 8; ++i) w[i] = 0 - w[i];
+        if (o.c[1]) {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const ulonglong2 x = *(const ulonglong2*)(o.p[1] + base + 2 * h);
+                w[2 * h] += o.c[1] > 0 ? x.x : (0 - x.x);
+                w[2 * h + 1] += o.c[1] > 0 ? x.y : (0 - x.y);
+            }
+        }
+        return;
     }
 #pragma unroll
-    for (int s = 0; s < 8; ++s) acc[s] = v16i{0};
+    for (int i = 0; i < 8; ++i) {
+        const int64_t k = k0 + i;
+        u64 v = 0;
+        if (inrow && k < K) {
+            const int64_t off = base + i * o.s_k;
+            v = o.p[0][off];
+            if (o.c[0] < 0) v = 0 - v;
+            if (o.c[1]) {
+                const u64 x = o.p[1][off];
+                v += o.c[1] > 0 ? x : (0 - x);
+            }
+        }
+        w[i] = v;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_lgemm(LArgs a) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t m0 = (int64_t)blockIdx.y * TM + (w >> 1) * 32;
-    const int64_t n0 = (int64_t)blockIdx.x * TN + (w & 1) * 32;
+// 4x4 byte transpose: out_j byte i = in_i byte j.
+__device__ __forceinline__ void bt4(u32 a, u32 b, u32 c, u32 d, u32& o0, u32& o1, u32& o2, u32& o3) {
+    const u32 ab_lo = (a & 0x00FF00FFu) | ((b & 0x00FF00FFu) << 8);     // a0 b0 a2 b2
+    const u32 ab_hi = ((a >> 8) & 0x00FF00FFu) | (b & 0xFF00FF00u);     // a1 b1 a3 b3
+    const u32 cd_lo = (c & 0x00FF00FFu) | ((d & 0x00FF00FFu) << 8);
+    const u32 cd_hi = ((c >> 8) & 0x00FF00FFu) | (d & 0xFF00FF00u);
+    o0 = (ab_lo & 0xFFFFu) | (cd_lo << 16);
+    o2 = (ab_lo >> 16) | (cd_lo & 0xFFFF0000u);
+    o1 = (ab_hi & 0xFFFFu) | (cd_hi << 16);
+    o3 = (ab_hi >> 16) | (cd_hi & 0xFFFF0000u);
+}
+
+// Balanced digits of 8 words: q[d] byte i = digit d of word i.
+__device__ __forceinline__ void to_digits(const u64 w[8], u64 q[8]) {
+    u32 lo[8], hi[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const u64 v = (w[i] + OFF) ^ OFF;
+        lo[i] = (u32)v;
+        hi[i] = (u32)(v >> 32);
+    }
+    u32 t0[4], t1[4], t2[4], t3[4];
+    bt4(lo[0], lo[1], lo[2], lo[3], t0[0], t0[1], t0[2], t0[3]);   // digits 0..3 of words 0..3
+    bt4(lo[4], lo[5], lo[6], lo[7], t1[0], t1[1], t1[2], t1[3]);   // digits 0..3 of words 4..7
+    bt4(hi[0], hi[1], hi[2], hi[3], t2[0], t2[1], t2[2], t2[3]);   // digits 4..7 of words 0..3
+    bt4(hi[4], hi[5], hi[6], hi[7], t3[0], t3[1], t3[2], t3[3]);   // digits 4..7 of words 4..7
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        q[d] = (u64)t0[d] | ((u64)t1[d] << 32);
+        q[4 + d] = (u64)t2[d] | ((u64)t3[d] << 32);
+    }
+}
+
+// Thread -> (row, k-octet) of a 64 x 32 tile.  When k is contiguous in memory, 4 threads
+// share a row and read 64 contiguous bytes each; otherwise 64 threads cover 64 rows of
+// one k-octet so a wave reads 64 consecutive words per k.
+__device__ __forceinline__ void tile_coord(const Opnd& o, int t, int& row, int& oct) {
+    if (o.s_k == 1) { row = t >> 2; oct = t & 3; }
+    else { row = t & 63; oct = t >> 6; }
+}
+
+__device__ __forceinline__ void fetch(const Prod& P, int64_t kglob, int64_t Kp, int64_t K, int64_t r0a,
+                                      int64_t r0b, int t, u64 wa[8], u64 wb[8], int& ra, int& oa, int& rb,
+                                      int& ob) {
+    const int seg = (int)(kglob / Kp);
+    const int64_t k0 = kglob - seg * Kp;
+    const Opnd& A = P.a[seg];
+    const Opnd& B = P.b[seg];
+    tile_coord(A, t, ra, oa);
+    tile_coord(B, t, rb, ob);
+    load8(A, r0a + ra, k0 + 8 * oa, K, wa);
+    load8(B, r0b + rb, k0 + 8 * ob, K, wb);
+}
+
+__device__ __forceinline__ void stash(int8_t* lds, int row, int oct, const u64 w[8]) {
+    u64 q[8];
+    to_digits(w, q);
+#pragma unroll
+    for (int d = 0; d < 8; ++d) *(u64*)(lds + d * PLANE + row * KB + oct * 8) = q[d];
+}
+
+__global__ __launch_bounds__(NT, 2) void k_lgemm(LArgs a) {
+    __shared__ __attribute__((aligned(16))) int8_t As[2][8 * PLANE];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[2][8 * PLANE];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int prod = blockIdx.z / a.splits, split = blockIdx.z % a.splits;
+    const Prod& P = a.prod[prod];
+    const int64_t Ktot = (int64_t)P.nseg * a.Kp;
+    const int64_t kbeg = (int64_t)split * a.kchunk;
+    const int64_t kend = min(Ktot, kbeg + a.kchunk);     // kchunk <= KSEG: no int32 overflow
+    const int64_t r0a = (int64_t)blockIdx.y * TM, r0b = (int64_t)blockIdx.x * TN;
+    const int wy = w >> 1, wx = w & 1;
     const int r = lane & 31, kh = (lane >> 5) * 16;
-    const int64_t kbeg = (int64_t)blockIdx.z * a.kchunk;
-    const int64_t kend = min(a.Kc, kbeg + a.kchunk);
-    const int8_t* ap = a.A8 + (m0 + r) * a.lda + kh;
-    const int8_t* bp = a.B8 + (n0 + r) * a.ldb + kh;
+    const int aoff = (wy * 32 + r) * KB + kh, boff = (wx * 32 + r) * KB + kh;
+
     v16i acc[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) acc[s] = v16i{0};
-    u64 part[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) part[v] = 0;
-    int64_t since = 0;
-    for (int64_t k0 = kbeg; k0 < kend; k0 += KB) {
-        v4i A[8], B[8];
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            A[d] = *(const v4i*)(ap + d * a.a_plane + k0);
-            B[d] = *(const v4i*)(bp + d * a.b_plane + k0);
-        }
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-#pragma unroll
-            for (int i = 0; i <= s; ++i)
-                acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i], B[s - i], acc[s], 0, 0, 0);
-        since += KB;
-        if (since == KSEG) {
-            flush(part, acc);
-            since = 0;
-        }
+
+    u64 wa[8], wb[8];
+    int ra, oa, rb, ob;
+    if (kbeg < kend) {
+        fetch(P, kbeg, a.Kp, a.K, r0a, r0b, t, wa, wb, ra, oa, rb, ob);
+        stash(As[0], ra, oa, wa);
+        stash(Bs[0], rb, ob, wb);
     }
-    flush(part, acc);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += KB) {
+        const bool more = k0 + KB < kend;
+        if (more) fetch(P, k0 + KB, a.Kp, a.K, r0a, r0b, t, wa, wb, ra, oa, rb, ob);
+        v4i B[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) B[d] = *(const v4i*)(Bs[buf] + d * PLANE + boff);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const v4i A = *(const v4i*)(As[buf] + i * PLANE + aoff);
+#pragma unroll
+            for (int s = i; s < 8; ++s)
+                acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[s - i], acc[s], 0, 0, 0);
+        }
+        if (more) {
+            stash(As[buf ^ 1], ra, oa, wa);
+            stash(Bs[buf ^ 1], rb, ob, wb);
+        }
+        __syncthreads();
+        buf ^= 1;
+    }
     // 32x32 accumulator layout: lane -> column (lane & 31); register v -> row
     // 8 (v >> 2) + 4 (lane >> 5) + (v & 3)
-    const int64_t n = n0 + (lane & 31);
+    const int64_t n = r0b + wx * 32 + (lane & 31);
     if (n >= a.N) return;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-        const int64_t m = m0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int64_t m = r0a + wy * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         if (m >= a.M) continue;
-        u64* p = a.C.p + m * a.C.s0 + n * a.C.s1;
-        u64 val = part[v];
+        u64 val = 0;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) val += ((u64)(int64_t)acc[s][v]) << (8 * s);
+        u64* p = P.C.p + m * P.C.s0 + n * P.C.s1;
         if (a.atomic) {
             atomicAdd((unsigned long long*)p, (unsigned long long)val);
         } else {
@@ -151,110 +222,116 @@ __global__ __launch_bounds__(256) void k_lgemm(LArgs a) {
     }
 }
 
-struct Planes {
-    int8_t* p;
-    int64_t plane, ld;
-};
+inline int64_t rup(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-// Convert rows x K (view with strides) into digit planes at k offset koff.
-void digits(const DigitSrc& s, int64_t rows, int64_t K, const Planes& P, int64_t Rp, int64_t Kp, int64_t koff,
-            hipStream_t st) {
-    const int64_t nch = Kp / 16;
-    const int64_t work = Rp * nch;
-    const int kfast = s.s_k == 1 ? 1 : 0;
-    hipLaunchKernelGGL(k_digits, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, st, s, rows, K, Rp, nch, P.p,
-                       P.plane, P.ld, koff, kfast);
+Opnd opnd(const View& v, int64_t b, bool transpose, int64_t rows, int c0 = 1) {
+    Opnd o{};
+    o.p[0] = v.p + b * v.sb;
+    o.c[0] = c0;
+    o.p[1] = nullptr;
+    o.c[1] = 0;
+    o.s_r = transpose ? v.s1 : v.s0;
+    o.s_k = transpose ? v.s0 : v.s1;
+    o.rows = rows;
+    return o;
 }
 
-DigitSrc src1(const View& v, int64_t b, bool transpose) {
-    DigitSrc s{};
-    s.p[0] = v.p + b * v.sb;
-    s.c[0] = 1;
-    s.s_r = transpose ? v.s1 : v.s0;
-    s.s_k = transpose ? v.s0 : v.s1;
-    return s;
-}
-
-DigitSrc combo(const View* v, int64_t b, bool transpose, int c0, int c1, int c2) {
-    DigitSrc s{};
-    const int cs[3] = {c0, c1, c2};
-    for (int i = 0; i < 3; ++i) {
-        s.p[i] = v[i].p ? v[i].p + b * v[i].sb : nullptr;
-        s.c[i] = v[i].p ? cs[i] : 0;
+// c0 * P[i0] + c1 * P[i1] over the three planes of a party operand
+Opnd combo(const View* v, int64_t b, bool transpose, int64_t rows, int i0, int c0, int i1, int c1) {
+    Opnd o = opnd(v[i0], b, transpose, rows, c0);
+    if (i1 >= 0) {
+        o.p[1] = v[i1].p + b * v[i1].sb;
+        o.c[1] = c1;
     }
-    s.s_r = transpose ? v[0].s1 : v[0].s0;
-    s.s_k = transpose ? v[0].s0 : v[0].s1;
-    return s;
-}
-
-hipError_t launch_lgemm(const Planes& A, const Planes& B, int64_t M, int64_t N, int64_t Kc, const OutView& C,
-                        const View& D, bool atomic, hipStream_t st) {
-    const int64_t tm = rup(M, TM) / TM, tn = rup(N, TN) / TN;
-    if (tm > 65535) return hipErrorInvalidValue;
-    int64_t splits = 1;
-    if (atomic) {
-        const int64_t tiles = tm * tn;
-        const int64_t want = (1024 + tiles - 1) / tiles;
-        splits = std::max<int64_t>(1, std::min<int64_t>(want, Kc / 256));
-    }
-    int64_t kchunk = rup((Kc + splits - 1) / splits, KB);
-    splits = (Kc + kchunk - 1) / kchunk;
-    if (splits < 1) splits = 1;
-    LArgs a{A.p, A.plane, A.ld, B.p, B.plane, B.ld, M, N, Kc, kchunk, C, D, atomic ? 1 : 0};
-    hipLaunchKernelGGL(k_lgemm, dim3((unsigned)tn, (unsigned)tm, (unsigned)splits), dim3(256), 0, st, a);
-    return hipGetLastError();
+    return o;
 }
 
 }  // namespace
 
 hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-    // Small products stay on the vector ALU: the digit conversions would dominate.
-    if ((double)g.M * (double)g.N * (double)g.K < (double)(1 << 22) || !g.ws_alloc) return gemm_u64(g, st);
-    if (g.K == 0) return gemm_u64(g, st);
-    const int64_t Mp = rup(g.M, TM), Np = rup(g.N, TN), Kp = rup(g.K, KB);
+    // Small products stay on the vector ALU, where the launch is cheaper.
+    if ((double)g.M * (double)g.N * (double)g.K < (double)(1 << 22) || g.K == 0) return gemm_u64(g, st);
+    const int64_t tm = rup(g.M, TM) / TM, tn = rup(g.N, TN) / TN;
+    if (tm > 65535) return hipErrorInvalidValue;
+    const int64_t Kp = rup(g.K, KB);
     for (int b = 0; b < g.batch; ++b) {
+        LArgs a{};
+        a.M = g.M; a.N = g.N; a.K = g.K; a.Kp = Kp;
+        a.atomic = g.accumulate ? 1 : 0;
+        a.D = g.Dadd;
+        if (a.D.p) a.D.p += b * a.D.sb;
+        int nprod;
+        int64_t maxseg;
         if (!g.party) {
-            Planes A{(int8_t*)g.ws_alloc(g.ws_self, (size_t)8 * Mp * Kp), Mp * Kp, Kp};
-            Planes B{(int8_t*)g.ws_alloc(g.ws_self, (size_t)8 * Np * Kp), Np * Kp, Kp};
-            digits(src1(g.A[0], b, false), g.M, g.K, A, Mp, Kp, 0, st);
-            digits(src1(g.B[0], b, true), g.N, g.K, B, Np, Kp, 0, st);
-            OutView C = g.C[0];
-            C.p += b * C.sb;
-            View D = g.Dadd;
-            if (D.p) D.p += b * D.sb;
-            hipError_t e = launch_lgemm(A, B, g.M, g.N, Kp, C, D, g.accumulate, st);
-            if (e != hipSuccess) return e;
+            nprod = 1;
+            maxseg = 1;
+            Prod& P = a.prod[0];
+            P.nseg = 1;
+            P.a[0] = opnd(g.A[0], b, false, g.M);
+            P.b[0] = opnd(g.B[0], b, true, g.N);
+            P.C = g.C[0];
+            P.C.p += b * P.C.sb;
         } else {
-            // A segments along k: [A1 | Am | -A2 | A1 + A2]
-            const int64_t lda = 4 * Kp;
-            Planes A{(int8_t*)g.ws_alloc(g.ws_self, (size_t)8 * Mp * lda), Mp * lda, lda};
-            const View* av = g.A;
-            digits(combo(av, b, false, 0, 1, 0), g.M, g.K, A, Mp, Kp, 0, st);
-            digits(combo(av, b, false, 1, 0, 0), g.M, g.K, A, Mp, Kp, Kp, st);
-            digits(combo(av, b, false, 0, 0, -1), g.M, g.K, A, Mp, Kp, 2 * Kp, st);
-            digits(combo(av, b, false, 0, 1, 1), g.M, g.K, A, Mp, Kp, 3 * Kp, st);
-            const View* bv = g.B;
-            // C1 = A1 Bm + Am B1 ; C2 = Am (Bm - B2) + (-A2) Bm ; C0 = (A1 + A2)(B1 + B2)
-            Planes B1{(int8_t*)g.ws_alloc(g.ws_self, (size_t)8 * Np * 2 * Kp), Np * 2 * Kp, 2 * Kp};
-            Planes B2{(int8_t*)g.ws_alloc(g.ws_self, (size_t)8 * Np * 2 * Kp), Np * 2 * Kp, 2 * Kp};
-            Planes B0{(int8_t*)g.ws_alloc(g.ws_self, (size_t)8 * Np * Kp), Np * Kp, Kp};
-            digits(combo(bv, b, true, 1, 0, 0), g.N, g.K, B1, Np, Kp, 0, st);
-            digits(combo(bv, b, true, 0, 1, 0), g.N, g.K, B1, Np, Kp, Kp, st);
-            digits(combo(bv, b, true, 1, 0, -1), g.N, g.K, B2, Np, Kp, 0, st);
-            digits(combo(bv, b, true, 1, 0, 0), g.N, g.K, B2, Np, Kp, Kp, st);
-            digits(combo(bv, b, true, 0, 1, 1), g.N, g.K, B0, Np, Kp, 0, st);
-            const View noD{nullptr, 0, 0, 0};
-            OutView C0 = g.C[0], C1 = g.C[1], C2 = g.C[2];
-            C0.p += b * C0.sb; C1.p += b * C1.sb; C2.p += b * C2.sb;
-            Planes A1m{A.p, A.plane, A.ld}, Amn{A.p + Kp, A.plane, A.ld}, As{A.p + 3 * Kp, A.plane, A.ld};
-            hipError_t e = launch_lgemm(A1m, B1, g.M, g.N, 2 * Kp, C1, noD, g.accumulate, st);
-            if (e == hipSuccess) e = launch_lgemm(Amn, B2, g.M, g.N, 2 * Kp, C2, noD, g.accumulate, st);
-            if (e == hipSuccess) e = launch_lgemm(As, B0, g.M, g.N, Kp, C0, noD, g.accumulate, st);
-            if (e != hipSuccess) return e;
+            // planes 0, 1, 2 = m, [r]_1, [r]_2
+            nprod = 3;
+            maxseg = 2;
+            const View* A = g.A;
+            const View* B = g.B;
+            // C0 = (A1 + A2)(B1 + B2)
+            Prod& P0 = a.prod[0];
+            P0.nseg = 1;
+            P0.a[0] = combo(A, b, false, g.M, 1, 1, 2, 1);
+            P0.b[0] = combo(B, b, true, g.N, 1, 1, 2, 1);
+            // C1 = A1 Bm + Am B1
+            Prod& P1 = a.prod[1];
+            P1.nseg = 2;
+            P1.a[0] = combo(A, b, false, g.M, 1, 1, -1, 0);
+            P1.b[0] = combo(B, b, true, g.N, 0, 1, -1, 0);
+            P1.a[1] = combo(A, b, false, g.M, 0, 1, -1, 0);
+            P1.b[1] = combo(B, b, true, g.N, 1, 1, -1, 0);
+            // C2 = Am (Bm - B2) + (-A2) Bm
+            Prod& P2 = a.prod[2];
+            P2.nseg = 2;
+            P2.a[0] = combo(A, b, false, g.M, 0, 1, -1, 0);
+            P2.b[0] = combo(B, b, true, g.N, 0, 1, 2, -1);
+            P2.a[1] = combo(A, b, false, g.M, 2, -1, -1, 0);
+            P2.b[1] = combo(B, b, true, g.N, 0, 1, -1, 0);
+            for (int p = 0; p < 3; ++p) {
+                a.prod[p].C = g.C[p];
+                a.prod[p].C.p += b * a.prod[p].C.sb;
+            }
         }
+        int64_t splits = 1;
+        bool dense = !a.D.p && !g.accumulate;
+        for (int p = 0; p < nprod; ++p)
+            dense = dense && a.prod[p].C.s1 == 1 && a.prod[p].C.s0 == g.N;
+        const bool too_long = maxseg * Kp > KSEG;
+        if (too_long && !g.accumulate && !dense) return gemm_u64(g, st);
+        if (dense && (too_long || (tm * tn * nprod < 256 && maxseg * Kp >= 2048))) {
+            for (int p = 0; p < nprod; ++p) {
+                hipError_t e = hipMemsetAsync(a.prod[p].C.p, 0, (size_t)g.M * g.N * 8, st);
+                if (e != hipSuccess) return e;
+            }
+            a.atomic = 1;
+        }
+        if (a.atomic) {
+            const int64_t tiles = tm * tn * nprod;
+            const int64_t want = (1024 + tiles - 1) / tiles;
+            splits = std::max<int64_t>(1, std::min<int64_t>(want, maxseg * Kp / 256));
+        }
+        splits = std::max<int64_t>(splits, (maxseg * Kp + KSEG - 1) / KSEG);
+        // K blocks never straddle a segment (Kp is a multiple of KB); chunks may
+        const int64_t kchunk = rup((maxseg * Kp + splits - 1) / splits, KB);
+        splits = (maxseg * Kp + kchunk - 1) / kchunk;
+        a.kchunk = kchunk;
+        a.splits = (int)splits;
+        if (nprod * splits > 65535) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_lgemm, dim3((unsigned)tn, (unsigned)tm, (unsigned)(nprod * splits)), dim3(NT), 0, st, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 }  // namespace mpc3

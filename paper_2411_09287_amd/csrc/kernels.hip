@@ -305,6 +305,57 @@ __global__ void k_mulmat(const u64* src, int64_t stride, u64* W) {
 }
 
 // Anti-diagonal sums of a 64x64 matrix (row j, column l -> coefficient j + l), reduced.
+// 256 threads: the matrix is staged in LDS with coalesced loads; thread (q, k) sums the
+// rows 16q .. 16q+15 of diagonal k and 64 + k; the four partial sums are then combined.
+__device__ u64 fold_block(const u64* C, u64* tile /* 4096 */, u64* part /* 2*256 */, u64* sh, int t) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) tile[i * 256 + t] = C[i * 256 + t];
+    __syncthreads();
+    const int k = t & 63, q = t >> 6;
+    u64 lo = 0, hi = 0;
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+        const int j = 16 * q + jj;
+        if (j <= k) lo += tile[j * 64 + (k - j)];
+        else hi += tile[j * 64 + (k + 64 - j)];
+    }
+    part[t] = lo;
+    part[256 + t] = hi;
+    __syncthreads();
+    u64 v = 0;
+    if (t < 64) {
+        lo = part[t] + part[64 + t] + part[128 + t] + part[192 + t];
+        hi = part[256 + t] + part[320 + t] + part[384 + t] + part[448 + t];
+    }
+    // reduce_lane synchronises the block; all threads take part
+    if (t < 64) sh[t] = hi;
+    __syncthreads();
+    if (t < 64) {
+        v = lo;
+#pragma unroll
+        for (int qq = 0; qq < NTAPS; ++qq) {
+            const int j = t - tap(qq);
+            if (j >= 0) v -= sh[j];
+        }
+#pragma unroll
+        for (int qq = 0; qq < NTAPS; ++qq) {
+            const int p = t - tap(qq);
+            if (p >= 0 && p <= 2) {
+                u64 ov = 0;
+#pragma unroll
+                for (int r = 0; r < NTAPS; ++r) {
+                    const int j = 64 + p - tap(r);
+                    if (j >= 0 && j <= 62) ov -= sh[j];
+                }
+                v -= ov;
+            }
+        }
+    }
+    __syncthreads();
+    return v;
+}
+
+// one-wave variant for the small ring products below
 __device__ u64 fold_lane(const u64* C, u64* sh, int k) {
     u64 lo = 0, hi = 0;
     for (int j = 0; j <= k; ++j) lo += C[j * 64 + (k - j)];
@@ -313,43 +364,51 @@ __device__ u64 fold_lane(const u64* C, u64* sh, int k) {
 }
 
 __global__ void k_fold_plain(const u64* C, u64* out) {
+    __shared__ u64 tile[4096];
+    __shared__ u64 part[512];
     __shared__ u64 sh[64];
-    const int k = threadIdx.x;
-    out[blockIdx.x * 64 + k] = fold_lane(C + (int64_t)blockIdx.x * 4096, sh, k);
+    const int t = threadIdx.x;
+    const u64 v = fold_block(C + (int64_t)blockIdx.x * 4096, tile, part, sh, t);
+    if (t < 64) out[blockIdx.x * 64 + t] = v;
 }
 
 __global__ void k_polyevl_finish(PolyEvlArgs a) {
+    __shared__ u64 tile[4096];
+    __shared__ u64 part[512];
     __shared__ u64 sh[64];
     __shared__ int nz;
-    const int k = threadIdx.x;
-    if (k == 0) nz = 0;
-    const u64 s0 = fold_lane(a.C, sh, k);            // sum R_a R_b            (P0)
-    const u64 s1 = fold_lane(a.C + 4096, sh, k);     // sum m_a r1_b + m_b r1_a (P1)
-    const u64 s2 = fold_lane(a.C + 8192, sh, k);     // sum m_a (m_b - r2_b) - r2_a m_b (P2)
-    const u64 rc1 = prg_word(a.k.k01, make_tag(a.op, a.pr, 1, a.sub), k);
-    const u64 rc2 = prg_word(a.k.k02, make_tag(a.op, a.pr, 2, a.sub), k);
-    const u64 g1 = prg_word(a.k.k01, make_tag(a.op, a.pg, 1, a.sub), k);
-    u64 g2 = s0 + rc1 + rc2 - g1;                     // P0 -> P2
-    if (k == a.inj_g2) g2 += a.e_g2;
-    u64 m1 = g1 - s1;                                 // P1 -> P2
-    if (k == a.inj_m1) m1 += a.e_m1;
-    const u64 m2 = s2 + g2;                           // P2 -> P1
-    const u64 m = m1 + m2;
-    a.out[k] = m;
-    a.out[64 + k] = rc1;
-    a.out[128 + k] = rc2;
-    if (a.log_m1) {
-        a.log_m1[k] = m1;
-        a.log_m2[k] = m2;
-        a.log_g2[k] = g2;
+    const int t = threadIdx.x;
+    if (t == 0) nz = 0;
+    const u64 s0 = fold_block(a.C, tile, part, sh, t);             // sum R_a R_b            (P0)
+    const u64 s1 = fold_block(a.C + 4096, tile, part, sh, t);      // sum m_a r1_b + m_b r1_a (P1)
+    const u64 s2 = fold_block(a.C + 8192, tile, part, sh, t);      // sum m_a (m_b - r2_b) - r2_a m_b (P2)
+    if (t < 64) {
+        const int k = t;
+        const u64 rc1 = prg_word(a.k.k01, make_tag(a.op, a.pr, 1, a.sub), k);
+        const u64 rc2 = prg_word(a.k.k02, make_tag(a.op, a.pr, 2, a.sub), k);
+        const u64 g1 = prg_word(a.k.k01, make_tag(a.op, a.pg, 1, a.sub), k);
+        u64 g2 = s0 + rc1 + rc2 - g1;                     // P0 -> P2
+        if (k == a.inj_g2) g2 += a.e_g2;
+        u64 m1 = g1 - s1;                                 // P1 -> P2
+        if (k == a.inj_m1) m1 += a.e_m1;
+        const u64 m2 = s2 + g2;                           // P2 -> P1
+        const u64 m = m1 + m2;
+        a.out[k] = m;
+        a.out[64 + k] = rc1;
+        a.out[128 + k] = rc2;
+        if (a.log_m1) {
+            a.log_m1[k] = m1;
+            a.log_m2[k] = m2;
+            a.log_g2[k] = g2;
+        }
+        if (a.reveal) {
+            const u64 v = m - rc1 - rc2;
+            a.reveal[k] = v;
+            if (v) atomicOr(&nz, 1);
+        }
     }
-    if (a.reveal) {
-        const u64 v = m - rc1 - rc2;
-        a.reveal[k] = v;
-        if (v) atomicOr(&nz, 1);
-        __syncthreads();
-        if (k == 0 && nz) atomicOr(a.nonzero_flag, 1);
-    }
+    __syncthreads();
+    if (t == 0 && a.reveal && nz) atomicOr(a.nonzero_flag, 1);
 }
 
 // x * v for lane k: shift up by one coefficient and reduce x^64.
@@ -385,46 +444,75 @@ __global__ void k_sub_pairs(const u64* XY, int64_t n, u64* D) {
     D[(int64_t)c * half * 64 + idx] = base[(2 * i + 1) * 64 + k] - base[(2 * i) * 64 + k];
 }
 
+// Ring product of per-wave operands: wave w multiplies a[w] by b[w] (64 lanes = coefficients).
+// Every thread of the block calls it (it synchronises the block).
+__device__ u64 gr_mul_waves(const u64* a, const u64* b, u64* sh, int k) {
+    u64 lo = 0, hi = 0;
+    for (int i = 0; i < 64; ++i) {
+        const u64 p = a[i] * b[(k - i) & 63];
+        if (i <= k) lo += p; else hi += p;
+    }
+    return reduce_lane(lo, hi, sh, k);
+}
+
 __global__ void k_round_finish(RoundArgs a) {
-    __shared__ u64 sh[64];
-    __shared__ u64 zeta[64], zm1[64], zmx[64], t[64], L[3][64], hh[3][3][64];
-    const int k = threadIdx.x;
-    const u64 m = prg_word(a.k.k12, make_tag(a.op, P_VER_ZETA, 0, a.sub), k);
-    const u64 r1 = prg_word(a.k.k01, make_tag(a.op, P_VER_ZETA, 1, a.sub), k);
-    const u64 r2 = prg_word(a.k.k02, make_tag(a.op, P_VER_ZETA, 2, a.sub), k);
-    const u64 z = m - r1 - r2;                       // revealed point
-    zeta[k] = z;
-    zm1[k] = z - (k == 0 ? 1 : 0);                   // zeta - 1
-    zmx[k] = z - (k == 1 ? 1 : 0);                   // zeta - x
-    a.zeta_out[k] = z;
-    if (a.log_zeta) a.log_zeta[k] = z;
-    for (int c = 0; c < 3; ++c) {
+    // 256 threads = 4 waves; wave w works on its own operands in LDS
+    __shared__ u64 sh[4][64];
+    __shared__ u64 opa[4][64], opb[4][64], res[4][64];
+    __shared__ u64 zeta[64], zm1[64], zmx[64], L[3][64], hh[3][3][64];
+    const int t = threadIdx.x, w = t >> 6, k = t & 63;
+    if (w == 0) {
+        const u64 m = prg_word(a.k.k12, make_tag(a.op, P_VER_ZETA, 0, a.sub), k);
+        const u64 r1 = prg_word(a.k.k01, make_tag(a.op, P_VER_ZETA, 1, a.sub), k);
+        const u64 r2 = prg_word(a.k.k02, make_tag(a.op, P_VER_ZETA, 2, a.sub), k);
+        const u64 z = m - r1 - r2;                   // revealed point
+        zeta[k] = z;
+        zm1[k] = z - (k == 0 ? 1 : 0);               // zeta - 1
+        zmx[k] = z - (k == 1 ? 1 : 0);               // zeta - x
+        a.zeta_out[k] = z;
+        if (a.log_zeta) a.log_zeta[k] = z;
+    } else {
+        const int c = w - 1;
         hh[0][c][k] = a.h0[c * 64 + k];
         hh[2][c][k] = a.h2[c * 64 + k];
         hh[1][c][k] = a.z[c * 64 + k] - a.h0[c * 64 + k];    // h(1) = z - h(0)
     }
     __syncthreads();
-    // Lagrange weights over the nodes {0, 1, x}
-    t[k] = gr_mul_lane(zm1, zmx, sh, k);
-    __syncthreads();
-    L[0][k] = gr_mul_lane(t, a.inv, sh, k);              // (z-1)(z-x) / x
-    __syncthreads();
-    t[k] = gr_mul_lane(zeta, zmx, sh, k);
-    __syncthreads();
-    L[1][k] = gr_mul_lane(t, a.inv + 64, sh, k);         // z(z-x) / (1-x)
-    __syncthreads();
-    t[k] = gr_mul_lane(zeta, zm1, sh, k);
-    __syncthreads();
-    L[2][k] = gr_mul_lane(t, a.inv + 128, sh, k);        // z(z-1) / (x(x-1))
-    __syncthreads();
-    for (int c = 0; c < 3; ++c) {
-        u64 acc = 0;
-        for (int i = 0; i < 3; ++i) {
-            acc += gr_mul_lane(L[i], hh[i][c], sh, k);
-            __syncthreads();
-        }
-        a.z[c * 64 + k] = acc;
+    // Lagrange weights over the nodes {0, 1, x}: L0 = (z-1)(z-x)/x, L1 = z(z-x)/(1-x),
+    // L2 = z(z-1)/(x(x-1)); waves 0..2 compute one each, wave 3 idles
+    if (w < 3) {
+        opa[w][k] = w == 0 ? zm1[k] : zeta[k];
+        opb[w][k] = w == 2 ? zm1[k] : zmx[k];
+    } else {
+        opa[w][k] = 0;
+        opb[w][k] = 0;
     }
+    __syncthreads();
+    u64 v = gr_mul_waves(opa[w], opb[w], sh[w], k);
+    res[w][k] = v;
+    __syncthreads();
+    opa[w][k] = res[w][k];
+    opb[w][k] = w < 3 ? a.inv[w * 64 + k] : 0;
+    __syncthreads();
+    v = gr_mul_waves(opa[w], opb[w], sh[w], k);
+    if (w < 3) L[w][k] = v;
+    __syncthreads();
+    // z'_c = sum_i L_i h_i,c : 9 products, waves take (i, c) pairs in three passes
+    u64 acc = 0;
+    for (int pass = 0; pass < 3; ++pass) {
+        const int c = pass;         // plane handled in this pass
+        if (w < 3) {
+            opa[w][k] = L[w][k];
+            opb[w][k] = hh[w][c][k];
+        }
+        __syncthreads();
+        v = gr_mul_waves(opa[w], opb[w], sh[w], k);
+        res[w][k] = w < 3 ? v : 0;
+        __syncthreads();
+        if (w == 0) a.z[c * 64 + k] = res[0][k] + res[1][k] + res[2][k];
+        __syncthreads();
+    }
+    (void)acc;
 }
 
 __global__ void k_xp_epilogue(int64_t n, Keys k, u32 op, u32 sub, const u64* C0, const u64* C1,
@@ -596,10 +684,10 @@ void launch_mulmat(const u64* src, int64_t stride, int nb, u64* W, hipStream_t s
     hipLaunchKernelGGL(k_mulmat, dim3(nb), dim3(64), 0, s, src, stride, W);
 }
 void launch_fold_plain(const u64* C, int nb, u64* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_fold_plain, dim3(nb), dim3(64), 0, s, C, out);
+    hipLaunchKernelGGL(k_fold_plain, dim3(nb), dim3(256), 0, s, C, out);
 }
 void launch_polyevl_finish(const PolyEvlArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_polyevl_finish, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_polyevl_finish, dim3(1), dim3(256), 0, s, a);
 }
 void launch_at_x(const u64* XY, int nc, int64_t n, u64* out, hipStream_t s) {
     if (n < 2) return;
@@ -610,7 +698,7 @@ void launch_sub_pairs(const u64* XY, int nc, int64_t n, u64* D, hipStream_t s) {
     hipLaunchKernelGGL(k_sub_pairs, dim3(nblocks(n / 2 * 64, TPB), nc), dim3(TPB), 0, s, XY, n, D);
 }
 void launch_round_finish(const RoundArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_round_finish, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_round_finish, dim3(1), dim3(256), 0, s, a);
 }
 void launch_xp_epilogue(int64_t n, const Keys& k, u32 op, u32 sub, const u64* C0, const u64* C1,
                         const u64* C2, u64* XPm, u64* XP1, u64* XP2, hipStream_t s) {
