@@ -70,7 +70,7 @@ enum {
     MPC3_E_STATE = -7       /* call not valid in the current state */
 };
 
-enum { MPC3_VARIANT_U64 = 0, MPC3_VARIANT_LIMB_I8 = 1 };
+enum { MPC3_VARIANT_U64 = 0, MPC3_VARIANT_LIMB_I8 = 1, MPC3_VARIANT_AUTO = 2 };
 
 /* Phases of the communication counters. */
 enum { MPC3_PH_OFFLINE = 0, MPC3_PH_ONLINE = 1, MPC3_PH_VERIFY_OFFLINE = 2, MPC3_PH_VERIFY_ONLINE = 3 };
@@ -120,6 +120,15 @@ int mpc3_ctx_destroy(mpc3_ctx* ctx);
  * 2^64).  Both give bit-identical results. */
 int mpc3_set_variant(mpc3_ctx* ctx, int variant);
 
+/* Autotuner: time both kernel families on the three-party product of an M x K by K x N
+ * layer (random operands in the context's workspace, `reps` timed runs each after one
+ * warm-up) and remember the faster one for that shape.  With MPC3_VARIANT_AUTO every
+ * Pi_Inner uses the remembered choice for its shape (the limb family when the shape was
+ * never tuned).  *choice receives the pick; ms_u64 / ms_limb (nullable) the median times.
+ * Synchronises.  Results are bit-identical either way; only speed differs. */
+int mpc3_autotune(mpc3_ctx* ctx, int64_t M, int64_t K, int64_t N, int reps, int* choice, double* ms_u64,
+                  double* ms_limb);
+
 /* Truncations per Pi_BIVerify instance of the truncation gates (default 16384). */
 int mpc3_set_chunk(mpc3_ctx* ctx, int64_t truncations_per_instance);
 
@@ -159,6 +168,11 @@ int mpc3_inner(mpc3_ctx* ctx, const mpc3_share_t* X, const mpc3_share_t* W,
  * as one inner product per output. */
 int mpc3_im2col(mpc3_ctx* ctx, const mpc3_share_t* x, int B, int H, int W, int C, int KH, int KW,
                 int pad, mpc3_share_t* cols);
+
+/* 2x2 sum pooling (stride 2) of an NHWC shared tensor x (B*H*W*C words per plane)
+ * into out (B*(H/2)*(W/2)*C): each plane is summed alone, a local linear map
+ * (Preliminaries, linear homomorphism of <.>-shares).  H and W must be even. */
+int mpc3_sumpool2(mpc3_ctx* ctx, const mpc3_share_t* x, int B, int H, int W, int C, mpc3_share_t* out);
 
 /* Pi_Mult elementwise on rows*cols values (Fig. "The Multiplication Protocol"). */
 int mpc3_mult(mpc3_ctx* ctx, const mpc3_share_t* a, const mpc3_share_t* b, mpc3_share_t* c);

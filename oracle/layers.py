@@ -25,3 +25,15 @@ def im2col(x, kh, kw, pad):
 def im2col_share(s, kh, kw, pad):
     from .protocol import Share
     return Share(*[im2col(p, kh, kw, pad) for p in s.comps()])
+
+
+def sumpool2(x):
+    """2x2 sum pooling with stride 2 of a (B, H, W, C) uint64 plane (wraps mod 2^64)."""
+    B, H, W, C = x.shape
+    v = x.reshape(B, H // 2, 2, W // 2, 2, C)
+    return v[:, :, 0, :, 0] + v[:, :, 0, :, 1] + v[:, :, 1, :, 0] + v[:, :, 1, :, 1]
+
+
+def sumpool2_share(s, B, H, W, C):
+    from .protocol import Share
+    return Share(*[sumpool2(p.reshape(B, H, W, C)).reshape(B, -1) for p in s.comps()])

@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <new>
 #include <stdexcept>
 #include <vector>
@@ -126,6 +128,8 @@ struct mpc3_ctx {
     hipEvent_t ev_fork = nullptr, ev_join[NV] = {};
     hipStream_t cs = nullptr;
     Scratch* sc = nullptr;
+    // autotuned kernel family per (M, K, N) of a three-party product
+    std::map<std::tuple<int64_t, int64_t, int64_t>, int> tuned;
     // launch timing of the Pi_Inner products
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -272,49 +276,96 @@ void polyevl_run(mpc3_ctx* c, const VerCtx& v, int64_t n, const u64* A[3], int64
     send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8 * 64);
 }
 
-// R x Pi_Reduce, then Pi_InnerVerify.  XY: 6 planes (x: m, r1, r2; y: m, r1, r2) of n rows.
-void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, int R) {
+// Pi_PolyEvl where the x vectors only have a [r]_1 plane and the y vectors only a [r]_2
+// plane (the truncation gates): P0's sum is x.r1 (x) y.r2, the P1 and P2 sums are 0.
+void polyevl_sparse(mpc3_ctx* c, const VerCtx& v, int64_t n, const u64* X1, int64_t astride, const u64* Y2,
+                    int64_t bstride, uint32_t pr, uint32_t pg, uint32_t sub, Inj im1, Inj ig2, u64* out, u64* lm1,
+                    u64* lm2, u64* lg2) {
+    u64* C = c->sc->words(3 * 4096);
+    zero(c, C, 3 * 4096 * 8);
+    run_gemm(c, plain(64, 64, n, view(X1, 1, astride), view(Y2, bstride, 1), oview(C, 64, 1), true));
+    PolyEvlArgs a{};
+    a.C = C; a.k = c->keys; a.op = v.op; a.pr = pr; a.pg = pg; a.sub = sub;
+    a.inj_m1 = im1.index >= 0 ? (int)im1.index : -1; a.e_m1 = im1.e;
+    a.inj_g2 = ig2.index >= 0 ? (int)ig2.index : -1; a.e_g2 = ig2.e;
+    a.out = out; a.log_m1 = lm1; a.log_m2 = lm2; a.log_g2 = lg2;
+    launch_polyevl_finish(a, c->cs);
+    send(c, MPC3_PH_VERIFY_OFFLINE, 0, 2, 8 * 64);
+    send(c, MPC3_PH_VERIFY_ONLINE, 1, 2, 8 * 64);
+    send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8 * 64);
+}
+
+// The Lagrange step of a round: reveal zeta, update z, return zeta.
+u64* round_finish(mpc3_ctx* c, const VerCtx& v, uint32_t sub, int k, const u64* h0, const u64* h2, u64* z) {
+    u64* zeta = c->sc->words(64);
+    RoundArgs ra{};
+    ra.k = c->keys; ra.op = v.op; ra.sub = sub; ra.inv = c->inv_dev; ra.h0 = h0; ra.h2 = h2; ra.z = z;
+    ra.zeta_out = zeta; ra.log_zeta = slot(v, MPC3_LOG_ZETA, k);
+    launch_round_finish(ra, c->cs);
+    count_reveal(c, MPC3_PH_VERIFY_ONLINE);
+    return zeta;
+}
+
+// R x Pi_Reduce (rounds k0 .. R-1), then Pi_InnerVerify.
+// Dense: XY holds 6 planes (x: m, r1, r2; y: m, r1, r2) of n rows.
+// Sparse: XY holds 2 planes (x.r1, y.r2) of n rows; every other plane is 0.
+void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, int R, int k0 = 0,
+                    bool sparse = false) {
     hipStream_t s = c->cs;
-    for (int k = 0; k < R; ++k) {
+    const int np = sparse ? 2 : 6;
+    for (int k = k0; k < R; ++k) {
         const int64_t half = n / 2;
         const uint32_t sub = ((uint32_t)v.inst << 8) | (uint32_t)k;
         u64* h0 = c->sc->words(3 * 64);
         u64* h2 = c->sc->words(3 * 64);
-        {   // h(0) = sum f_i(0) g_i(0): rows 2i of x and y
-            const u64* A[3] = {XY, XY + n * 64, XY + 2 * n * 64};
-            const u64* B[3] = {XY + 3 * n * 64, XY + 4 * n * 64, XY + 5 * n * 64};
-            polyevl_run(c, v, half, A, 128, B, 128, P_VER_H0_R, P_VER_H0_GAMMA, sub,
-                        take_ver(c, MPC3_SITE_VER_H0_M1, v.inst, k), Inj{-1, 0}, h0, slot(v, MPC3_LOG_H0_M1, k),
-                        slot(v, MPC3_LOG_H0_M2, k), slot(v, MPC3_LOG_H0_G2, k), nullptr, nullptr);
-        }
-        {   // h(x) = sum f_i(x) g_i(x), f_i(x) = f_i(0) + x (f_i(1) - f_i(0))
-            u64* F2 = c->sc->words(6 * half * 64);
-            launch_at_x(XY, 6, n, F2, s);
-            const u64* A[3] = {F2, F2 + half * 64, F2 + 2 * half * 64};
-            const u64* B[3] = {F2 + 3 * half * 64, F2 + 4 * half * 64, F2 + 5 * half * 64};
-            polyevl_run(c, v, half, A, 64, B, 64, P_VER_H2_R, P_VER_H2_GAMMA, sub, Inj{-1, 0},
-                        take_ver(c, MPC3_SITE_VER_H2_GAMMA2, v.inst, k), h2, slot(v, MPC3_LOG_H2_M1, k),
-                        slot(v, MPC3_LOG_H2_M2, k), slot(v, MPC3_LOG_H2_G2, k), nullptr, nullptr);
+        const Inj i_h0 = take_ver(c, MPC3_SITE_VER_H0_M1, v.inst, k);
+        const Inj i_h2 = take_ver(c, MPC3_SITE_VER_H2_GAMMA2, v.inst, k);
+        u64* F2 = c->sc->words(np * half * 64);
+        launch_at_x(XY, np, n, F2, s);         // f_i(x) = f_i(0) + x (f_i(1) - f_i(0))
+        if (sparse) {
+            polyevl_sparse(c, v, half, XY, 128, XY + n * 64, 128, P_VER_H0_R, P_VER_H0_GAMMA, sub, i_h0,
+                           Inj{-1, 0}, h0, slot(v, MPC3_LOG_H0_M1, k), slot(v, MPC3_LOG_H0_M2, k),
+                           slot(v, MPC3_LOG_H0_G2, k));
+            polyevl_sparse(c, v, half, F2, 64, F2 + half * 64, 64, P_VER_H2_R, P_VER_H2_GAMMA, sub, Inj{-1, 0},
+                           i_h2, h2, slot(v, MPC3_LOG_H2_M1, k), slot(v, MPC3_LOG_H2_M2, k),
+                           slot(v, MPC3_LOG_H2_G2, k));
+        } else {
+            {   // h(0) = sum f_i(0) g_i(0): rows 2i of x and y
+                const u64* A[3] = {XY, XY + n * 64, XY + 2 * n * 64};
+                const u64* B[3] = {XY + 3 * n * 64, XY + 4 * n * 64, XY + 5 * n * 64};
+                polyevl_run(c, v, half, A, 128, B, 128, P_VER_H0_R, P_VER_H0_GAMMA, sub, i_h0, Inj{-1, 0}, h0,
+                            slot(v, MPC3_LOG_H0_M1, k), slot(v, MPC3_LOG_H0_M2, k), slot(v, MPC3_LOG_H0_G2, k),
+                            nullptr, nullptr);
+            }
+            {   // h(x) = sum f_i(x) g_i(x)
+                const u64* A[3] = {F2, F2 + half * 64, F2 + 2 * half * 64};
+                const u64* B[3] = {F2 + 3 * half * 64, F2 + 4 * half * 64, F2 + 5 * half * 64};
+                polyevl_run(c, v, half, A, 64, B, 64, P_VER_H2_R, P_VER_H2_GAMMA, sub, Inj{-1, 0}, i_h2, h2,
+                            slot(v, MPC3_LOG_H2_M1, k), slot(v, MPC3_LOG_H2_M2, k), slot(v, MPC3_LOG_H2_G2, k),
+                            nullptr, nullptr);
+            }
         }
         c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
-        u64* zeta = c->sc->words(64);
-        RoundArgs ra{};
-        ra.k = c->keys; ra.op = v.op; ra.sub = sub; ra.inv = c->inv_dev; ra.h0 = h0; ra.h2 = h2; ra.z = z;
-        ra.zeta_out = zeta; ra.log_zeta = slot(v, MPC3_LOG_ZETA, k);
-        launch_round_finish(ra, s);
-        count_reveal(c, MPC3_PH_VERIFY_ONLINE);
-        // fold: row i <- f_i(0) + zeta (f_i(1) - f_i(0)) for all six planes
+        u64* zeta = round_finish(c, v, sub, k, h0, h2, z);
+        // fold: row i <- f_i(0) + zeta (f_i(1) - f_i(0)) on every stored plane
         u64* Wz = c->sc->words(4096);
         launch_mulmat(zeta, 64, 1, Wz, s);
-        u64* Dd = c->sc->words(6 * half * 64);
-        launch_sub_pairs(XY, 6, n, Dd, s);
-        u64* XYn = c->sc->words(6 * half * 64);
+        u64* Dd = c->sc->words(np * half * 64);
+        launch_sub_pairs(XY, np, n, Dd, s);
+        u64* XYn = c->sc->words(np * half * 64);
         GemmArgs g = plain(half, 64, 64, view(Dd, 64, 1, half * 64), view(Wz, 64, 1, 0),
-                           oview(XYn, 64, 1, half * 64), false, 6);
+                           oview(XYn, 64, 1, half * 64), false, np);
         g.Dadd = view(XY, 128, 1, n * 64);
         run_gemm(c, g);
         XY = XYn;
         n = half;
+    }
+    if (sparse) {   // back to six planes for the final check: x = (0, r1, 0), y = (0, 0, r2)
+        u64* D6 = c->sc->words(6 * n * 64);
+        zero(c, D6, (size_t)6 * n * 64 * 8);
+        ck(hipMemcpyAsync(D6 + 1 * n * 64, XY, n * 512, hipMemcpyDeviceToDevice, s));
+        ck(hipMemcpyAsync(D6 + 5 * n * 64, XY + n * 64, n * 512, hipMemcpyDeviceToDevice, s));
+        XY = D6;
     }
     // Pi_InnerVerify
     u64* alpha = c->sc->words(3 * 64);
@@ -443,26 +494,75 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
     const mpc3_trunc_pair_t& p = it.pair;
     u64* r = challenge(c, v);
     u64* pw = c->sc->words(2 * T * 64);
-    power_table(c, r, 2 * T, pw);
+    power_table(c, r, 2 * T, pw);                 // r^g for the 2T gates of the chunk
     const int64_t n0 = 128 * T;
     const int R = auto_rounds(n0, Rarg);
     const int64_t np = padded(n0, R);
-    u64* XY = c->sc->words(6 * np * 64);
-    zero(c, XY, (size_t)6 * np * 64 * 8);
     u64* B1 = c->sc->words(T);
     u64* B2 = c->sc->words(T);
     launch_fill_at(B1, T, lo, c->keys.k01, make_tag(it.op, P_TRUNC_B, 1, 0), s);
     launch_fill_at(B2, T, lo, c->keys.k02, make_tag(it.op, P_TRUNC_B, 2, 0), s);
+    // claimed z = sum_g r^g w_g for each plane
     u64* w3 = c->sc->words(6 * T);
-    launch_trunc_instance2(lo, T, p.t, B1, B2, pw, p.rx.m, p.rx.r1, p.rx.r2, p.rz.m, p.rz.r1, p.rz.r2,
-                           XY + 1 * np * 64, XY + 5 * np * 64, w3, s);
+    launch_trunc_w(lo, T, p.t, B1, B2, p.rx.m, p.rx.r1, p.rx.r2, p.rz.m, p.rz.r1, p.rz.r2, w3, s);
     u64* z = c->sc->words(3 * 64);
     zero(c, z, 3 * 64 * 8);
     for (int q = 0; q < 3; ++q)
         run_gemm(c, plain(1, 64, 2 * T, view(w3 + q * 2 * T, 0, 1), view(pw, 64, 1), oview(z + q * 64, 64, 1), true));
     ck(hipMemcpyAsync(slot(v, MPC3_LOG_Z), z, 512, hipMemcpyDeviceToDevice, s));
     c->vinfo.push_back(InstanceInfo{R, np});
-    fold_and_check(c, v, XY, np, z, R);
+    if (R == 0) {
+        // no reduction: lift the gates (x' = r^g a_e on the r1 plane, y = b_e on the r2 plane)
+        u64* XY = c->sc->words(6 * np * 64);
+        zero(c, XY, (size_t)6 * np * 64 * 8);
+        launch_trunc_instance2(lo, T, p.t, B1, B2, pw, p.rx.m, p.rx.r1, p.rx.r2, p.rz.m, p.rz.r1, p.rz.r2,
+                               XY + 1 * np * 64, XY + 5 * np * 64, w3, s);
+        fold_and_check(c, v, XY, np, z, 0);
+        return;
+    }
+    // Round 0 from the gate structure: x_e = r^g a_e, y_e = b_e (scalars), pairs within a gate.
+    const uint32_t sub = ((uint32_t)v.inst << 8);
+    u64* sums = c->sc->words(8 * T);
+    launch_trunc_round0_sums(T, p.t, B1, B2, sums, s);
+    u64* P = c->sc->words(4 * 64);
+    zero(c, P, 4 * 64 * 8);
+    run_gemm(c, plain(4, 64, 2 * T, view(sums, 2 * T, 1), view(pw, 64, 1), oview(P, 64, 1), true));
+    u64* S = c->sc->words(3 * 64);              // prefolded P0 / P1 / P2 sums of one Pi_PolyEvl
+    u64* h0 = c->sc->words(3 * 64);
+    u64* h2 = c->sc->words(3 * 64);
+    const Inj i_h0 = take_ver(c, MPC3_SITE_VER_H0_M1, v.inst, 0);
+    const Inj i_h2 = take_ver(c, MPC3_SITE_VER_H2_GAMMA2, v.inst, 0);
+    auto finish = [&](uint32_t pr, uint32_t pg, Inj im1, Inj ig2, u64* out, int l1, int l2, int lg) {
+        PolyEvlArgs a{};
+        a.C = S; a.prefolded = 1; a.k = c->keys; a.op = v.op; a.pr = pr; a.pg = pg; a.sub = sub;
+        a.inj_m1 = im1.index >= 0 ? (int)im1.index : -1; a.e_m1 = im1.e;
+        a.inj_g2 = ig2.index >= 0 ? (int)ig2.index : -1; a.e_g2 = ig2.e;
+        a.out = out; a.log_m1 = slot(v, l1, 0); a.log_m2 = slot(v, l2, 0); a.log_g2 = slot(v, lg, 0);
+        launch_polyevl_finish(a, s);
+        send(c, MPC3_PH_VERIFY_OFFLINE, 0, 2, 8 * 64);
+        send(c, MPC3_PH_VERIFY_ONLINE, 1, 2, 8 * 64);
+        send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8 * 64);
+    };
+    zero(c, S, 3 * 64 * 8);
+    ck(hipMemcpyAsync(S, P, 512, hipMemcpyDeviceToDevice, s));           // h(0) = sum_g s_g r^g
+    finish(P_VER_H0_R, P_VER_H0_GAMMA, i_h0, Inj{-1, 0}, h0, MPC3_LOG_H0_M1, MPC3_LOG_H0_M2, MPC3_LOG_H0_G2);
+    u64* S2 = c->sc->words(3 * 64);
+    zero(c, S2, 3 * 64 * 8);
+    launch_x_poly(P + 64, S2, s);                                        // h(x) = P0 + x P1 + x^2 P2
+    S = S2;
+    finish(P_VER_H2_R, P_VER_H2_GAMMA, Inj{-1, 0}, i_h2, h2, MPC3_LOG_H2_M1, MPC3_LOG_H2_M2, MPC3_LOG_H2_G2);
+    c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
+    u64* zeta = round_finish(c, v, sub, 0, h0, h2, z);
+    // folded vectors: x_i = a0 r^g + da (zeta r^g), y_i = b0 + db zeta
+    u64* Wz = c->sc->words(4096);
+    launch_mulmat(zeta, 64, 1, Wz, s);
+    u64* ZR = c->sc->words(2 * T * 64);
+    run_gemm(c, plain(2 * T, 64, 64, view(pw, 64, 1), view(Wz, 64, 1), oview(ZR, 64, 1), false));
+    const int64_t half = np / 2;
+    u64* XY = c->sc->words(2 * half * 64);
+    zero(c, XY, (size_t)2 * half * 64 * 8);
+    launch_trunc_fold0(T, p.t, B1, B2, pw, ZR, zeta, XY, XY + half * 64, s);
+    fold_and_check(c, v, XY, half, z, R, 1, true);
 }
 
 int guard(mpc3_ctx* c) {
@@ -584,9 +684,61 @@ int mpc3_ctx_destroy(mpc3_ctx* c) {
 }
 
 int mpc3_set_variant(mpc3_ctx* c, int variant) {
-    if (!c || (variant != MPC3_VARIANT_U64 && variant != MPC3_VARIANT_LIMB_I8)) return MPC3_E_ARG;
+    if (!c || variant < MPC3_VARIANT_U64 || variant > MPC3_VARIANT_AUTO) return MPC3_E_ARG;
     c->variant = variant;
     return MPC3_OK;
+}
+
+int mpc3_autotune(mpc3_ctx* c, int64_t M, int64_t K, int64_t N, int reps, int* choice, double* ms_u64,
+                  double* ms_limb) {
+    int g = guard(c);
+    if (g) return g;
+    if (M <= 0 || K <= 0 || N <= 0 || reps <= 0 || !choice) return MPC3_E_ARG;
+    return wrap([&] {
+        hipStream_t s = c->stream;
+        c->scratch.reset();
+        u64* X = c->scratch.words(3 * M * K);
+        u64* W = c->scratch.words(3 * K * N);
+        u64* C = c->scratch.words(3 * M * N);
+        // operand words from the PRG under a tag no protocol step uses (op = ~0)
+        launch_fill(X, 3 * M * K, c->keys.kall, make_tag(0xFFFFFFFFu, 0xFFFF, 1, 0), s);
+        launch_fill(W, 3 * K * N, c->keys.kall, make_tag(0xFFFFFFFFu, 0xFFFF, 2, 0), s);
+        GemmArgs ga{};
+        ga.M = M; ga.N = N; ga.K = K; ga.batch = 1; ga.party = true; ga.accumulate = false;
+        for (int p = 0; p < 3; ++p) {
+            ga.A[p] = view(X + p * M * K, K, 1);
+            ga.B[p] = view(W + p * K * N, N, 1);
+            ga.C[p] = oview(C + p * M * N, N, 1);
+        }
+        double med[2];
+        hipEvent_t e0, e1;
+        ck(hipEventCreate(&e0));
+        ck(hipEventCreate(&e1));
+        const int keep = c->variant;
+        for (int v = 0; v < 2; ++v) {
+            c->variant = v;
+            std::vector<float> t(reps);
+            run_gemm(c, ga);
+            for (int i = 0; i < reps; ++i) {
+                ck(hipEventRecord(e0, s));
+                run_gemm(c, ga);
+                ck(hipEventRecord(e1, s));
+                ck(hipEventSynchronize(e1));
+                ck(hipEventElapsedTime(&t[i], e0, e1));
+            }
+            std::sort(t.begin(), t.end());
+            med[v] = t[reps / 2];
+        }
+        c->variant = keep;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        const int pick = med[1] < med[0] ? MPC3_VARIANT_LIMB_I8 : MPC3_VARIANT_U64;
+        c->tuned[std::make_tuple(M, K, N)] = pick;
+        *choice = pick;
+        if (ms_u64) *ms_u64 = med[0];
+        if (ms_limb) *ms_limb = med[1];
+        return (int)MPC3_OK;
+    });
 }
 
 int mpc3_set_chunk(mpc3_ctx* c, int64_t t) {
@@ -698,6 +850,16 @@ int mpc3_inner(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W, const 
             ga.B[p] = view(Wp[p], N, 1);
             ga.C[p] = oview(C + p * n, N, 1);
         }
+        const int keep_variant = c->variant;
+        if (c->variant == MPC3_VARIANT_AUTO) {
+            auto it = c->tuned.find(std::make_tuple(M, K, N));
+            c->variant = it == c->tuned.end() ? MPC3_VARIANT_LIMB_I8 : it->second;
+        }
+        struct VariantRestore {
+            mpc3_ctx* c;
+            int v;
+            ~VariantRestore() { c->variant = v; }
+        } vr{c, keep_variant};
         if (K == 0) {
             zero(c, C, (size_t)3 * n * 8);
         } else if (c->prof) {
@@ -748,6 +910,21 @@ int mpc3_im2col(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, 
         launch_im2col(x->m, B, H, W, C, KH, KW, pad, cols->m, c->stream);
         launch_im2col(x->r1, B, H, W, C, KH, KW, pad, cols->r1, c->stream);
         launch_im2col(x->r2, B, H, W, C, KH, KW, pad, cols->r2, c->stream);
+        ck(hipGetLastError());
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_sumpool2(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, mpc3_share_t* out) {
+    int g = guard(c);
+    if (g) return g;
+    if (!valid(x) || !valid(out) || B < 0 || H <= 0 || W <= 0 || C <= 0 || (H & 1) || (W & 1)) return MPC3_E_ARG;
+    if (x->rows * x->cols != (int64_t)B * H * W * C || out->rows * out->cols != (int64_t)B * (H / 2) * (W / 2) * C)
+        return MPC3_E_SHAPE;
+    return wrap([&] {
+        launch_sumpool2(x->m, B, H, W, C, out->m, c->stream);
+        launch_sumpool2(x->r1, B, H, W, C, out->r1, c->stream);
+        launch_sumpool2(x->r2, B, H, W, C, out->r2, c->stream);
         ck(hipGetLastError());
         return (int)MPC3_OK;
     });

@@ -211,7 +211,7 @@ hipError_t gemm_u64(const GemmArgs& g, hipStream_t stream) {
 }
 
 hipError_t gemm(const GemmArgs& g, int variant, hipStream_t stream) {
-    if (variant == 1) return gemm_limb(g, stream);
+    if (variant != 0) return gemm_limb(g, stream);
     return gemm_u64(g, stream);
 }
 

@@ -36,6 +36,7 @@ void launch_mult(int64_t n, const Keys& k, u32 op, const u64* am, const u64* a1,
                  u64* msg_g2, u64* msg_m1, u64* msg_m2, hipStream_t s);
 void launch_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int pad, u64* out,
                    hipStream_t s);
+void launch_sumpool2(const u64* x, int B, int H, int W, int C, u64* out, hipStream_t s);
 void launch_reconstruct(int64_t n, const u64* m, const u64* r1, const u64* r2, Inj r1inj, u64* out,
                         int* flag, hipStream_t s);
 
@@ -58,6 +59,7 @@ struct PolyEvlArgs {
     u64* log_m1; u64* log_m2; u64* log_g2;   // nullable
     u64* reveal;           // nullable: writes the opened value
     int* nonzero_flag;     // nullable: set if the opened value is not 0
+    int prefolded;         // C holds the three reduced sums (3*64 words) instead of 64x64 products
 };
 void launch_polyevl_finish(const PolyEvlArgs& a, hipStream_t s);
 // f2 = f0 + x (f1 - f0) for nc planes of n rows (rows 2i, 2i+1 -> row i).
@@ -93,5 +95,19 @@ void launch_trunc_instance2(int64_t lo, int64_t T, int t, const u64* B1, const u
                             const u64* rxm, const u64* rx1, const u64* rx2, const u64* rzm, const u64* rz1,
                             const u64* rz2, u64* x1plane, u64* y2plane, u64* w3, hipStream_t s);
 void launch_set_one(u64* p, hipStream_t s);   // the ring element 1
+// Gate outputs <w> of truncations [lo, lo + T): w3 = 3 planes of 2T words (x-gate, z-gate).
+void launch_trunc_w(int64_t lo, int64_t T, int t, const u64* B1, const u64* B2, const u64* rxm, const u64* rx1,
+                    const u64* rx2, const u64* rzm, const u64* rz1, const u64* rz2, u64* w3, hipStream_t s);
+
+// First reduction round of a truncation-gate instance, per gate g < 2T: the scalar sums
+// s_h0 = sum_{even j} a_j b_j and, over the pairs (j, j+1), s0 = sum a0 b0,
+// s1 = sum (a0 db + da b0), s2 = sum da db (out: 4 rows of 2T words).
+void launch_trunc_round0_sums(int64_t T, int t, const u64* B1, const u64* B2, u64* out, hipStream_t s);
+// out = P0 + x P1 + x^2 P2 (three consecutive ring elements -> one).
+void launch_x_poly(const u64* P, u64* out, hipStream_t s);
+// Folded first-round vectors: x_i = a0 R[g] + da ZR[g], y_i = lift(b0) + db zeta, for the
+// 64 T pairs of the chunk (x plane and y plane, 64 words per element).
+void launch_trunc_fold0(int64_t T, int t, const u64* B1, const u64* B2, const u64* R, const u64* ZR,
+                        const u64* zeta, u64* xplane, u64* yplane, hipStream_t s);
 
 }  // namespace mpc3

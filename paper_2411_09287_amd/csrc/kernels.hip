@@ -217,6 +217,19 @@ __global__ void k_im2col(const u64* x, int B, int H, int W, int C, int KH, int K
     out[idx] = v;
 }
 
+__global__ void k_sumpool2(const u64* x, int B, int H, int W, int C, u64* out) {
+    const int OH = H / 2, OW = W / 2;
+    const int64_t total = (int64_t)B * OH * OW * C;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int c = (int)(idx % C);
+    const int ow = (int)((idx / C) % OW);
+    const int oh = (int)((idx / ((int64_t)C * OW)) % OH);
+    const int b = (int)(idx / ((int64_t)C * OW * OH));
+    const u64* p = x + (((int64_t)b * H + 2 * oh) * W + 2 * ow) * C + c;
+    out[idx] = p[0] + p[C] + p[(int64_t)W * C] + p[(int64_t)W * C + C];
+}
+
 __global__ void k_reconstruct(int64_t n, const u64* m, const u64* r1, const u64* r2, Inj inj, u64* out,
                               int* flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -379,9 +392,16 @@ __global__ void k_polyevl_finish(PolyEvlArgs a) {
     __shared__ int nz;
     const int t = threadIdx.x;
     if (t == 0) nz = 0;
-    const u64 s0 = fold_block(a.C, tile, part, sh, t);             // sum R_a R_b            (P0)
-    const u64 s1 = fold_block(a.C + 4096, tile, part, sh, t);      // sum m_a r1_b + m_b r1_a (P1)
-    const u64 s2 = fold_block(a.C + 8192, tile, part, sh, t);      // sum m_a (m_b - r2_b) - r2_a m_b (P2)
+    u64 s0, s1, s2;
+    if (a.prefolded) {
+        s0 = t < 64 ? a.C[t] : 0;
+        s1 = t < 64 ? a.C[64 + t] : 0;
+        s2 = t < 64 ? a.C[128 + t] : 0;
+    } else {
+        s0 = fold_block(a.C, tile, part, sh, t);             // sum R_a R_b            (P0)
+        s1 = fold_block(a.C + 4096, tile, part, sh, t);      // sum m_a r1_b + m_b r1_a (P1)
+        s2 = fold_block(a.C + 8192, tile, part, sh, t);      // sum m_a (m_b - r2_b) - r2_a m_b (P2)
+    }
     if (t < 64) {
         const int k = t;
         const u64 rc1 = prg_word(a.k.k01, make_tag(a.op, a.pr, 1, a.sub), k);
@@ -604,6 +624,70 @@ __global__ void k_trunc_w(int64_t lo, int64_t T, int t, const u64* B1, const u64
 
 __global__ void k_set_one(u64* p) { p[threadIdx.x] = threadIdx.x == 0 ? 1 : 0; }
 
+// weight of bit j in gate s of a truncation: 2^{j+1} (x-gate), 2 c_j (z-gate), with
+// c_j = 2^{j-t} for t <= j < 63, c_63 = -2^{63-t}, 0 below t
+__device__ __forceinline__ u64 gate_weight(int s, int j, int t) {
+    if (s == 0) return j == 63 ? 0 : (u64)1 << (j + 1);
+    u64 c = 0;
+    if (j >= t && j < 63) c = (u64)1 << (j - t);
+    if (j == 63) c = 0 - ((u64)1 << (63 - t));
+    return 2 * c;
+}
+
+__global__ void k_trunc_round0_sums(int64_t T, int t, const u64* B1, const u64* B2, u64* out) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= 2 * T) return;
+    const int64_t q = g >> 1;
+    const int s = (int)(g & 1);
+    const u64 x1 = B1[q], x2 = B2[q];
+    u64 h0 = 0, s0 = 0, s1 = 0, s2 = 0;
+    for (int j = 0; j < 64; j += 2) {
+        const u64 a0 = gate_weight(s, j, t) * ((x1 >> j) & 1);
+        const u64 a1 = gate_weight(s, j + 1, t) * ((x1 >> (j + 1)) & 1);
+        const u64 b0 = 0 - ((x2 >> j) & 1);
+        const u64 b1 = 0 - ((x2 >> (j + 1)) & 1);
+        const u64 da = a1 - a0, db = b1 - b0;
+        h0 += a0 * b0;
+        s0 += a0 * b0;
+        s1 += a0 * db + da * b0;
+        s2 += da * db;
+    }
+    out[g] = h0;
+    out[2 * T + g] = s0;
+    out[4 * T + g] = s1;
+    out[6 * T + g] = s2;
+}
+
+__global__ void k_x_poly(const u64* P, u64* out) {
+    __shared__ u64 v[64], w[64];
+    const int k = threadIdx.x;
+    v[k] = P[128 + k];
+    __syncthreads();
+    const u64 a = xmul_coeff(v, k) + P[64 + k];      // x P2 + P1
+    __syncthreads();
+    w[k] = a;
+    __syncthreads();
+    out[k] = xmul_coeff(w, k) + P[k];                // x (x P2 + P1) + P0
+}
+
+__global__ void k_trunc_fold0(int64_t T, int t, const u64* B1, const u64* B2, const u64* R, const u64* ZR,
+                              const u64* zeta, u64* xp, u64* yp) {
+    const int k = threadIdx.x;
+    const int64_t i = blockIdx.x;            // new element = pair (2i, 2i+1) of the chunk
+    const int64_t e0 = 2 * i;
+    const int64_t q = e0 >> 7;
+    const int s = (int)((e0 >> 6) & 1);
+    const int j = (int)(e0 & 63);
+    const int64_t g = 2 * q + s;
+    const u64 x1 = B1[q], x2 = B2[q];
+    const u64 a0 = gate_weight(s, j, t) * ((x1 >> j) & 1);
+    const u64 a1 = gate_weight(s, j + 1, t) * ((x1 >> (j + 1)) & 1);
+    const u64 b0 = 0 - ((x2 >> j) & 1);
+    const u64 b1 = 0 - ((x2 >> (j + 1)) & 1);
+    xp[i * 64 + k] = a0 * R[g * 64 + k] + (a1 - a0) * ZR[g * 64 + k];
+    yp[i * 64 + k] = (k == 0 ? b0 : 0) + (b1 - b0) * zeta[k];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -670,6 +754,11 @@ void launch_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int
     hipLaunchKernelGGL(k_im2col, dim3(nblocks(total, TPB)), dim3(TPB), 0, s, x, B, H, W, C, KH, KW, pad, OH, OW,
                        out);
 }
+void launch_sumpool2(const u64* x, int B, int H, int W, int C, u64* out, hipStream_t s) {
+    const int64_t total = (int64_t)B * (H / 2) * (W / 2) * C;
+    if (total <= 0) return;
+    hipLaunchKernelGGL(k_sumpool2, dim3(nblocks(total, TPB)), dim3(TPB), 0, s, x, B, H, W, C, out);
+}
 void launch_reconstruct(int64_t n, const u64* m, const u64* r1, const u64* r2, Inj r1inj, u64* out,
                         int* flag, hipStream_t s) {
     if (n <= 0) return;
@@ -729,5 +818,24 @@ void launch_trunc_instance2(int64_t lo, int64_t T, int t, const u64* B1, const u
                        rz1, rz2, w3);
 }
 void launch_set_one(u64* p, hipStream_t s) { hipLaunchKernelGGL(k_set_one, dim3(1), dim3(64), 0, s, p); }
+void launch_trunc_w(int64_t lo, int64_t T, int t, const u64* B1, const u64* B2, const u64* rxm, const u64* rx1,
+                    const u64* rx2, const u64* rzm, const u64* rz1, const u64* rz2, u64* w3, hipStream_t s) {
+    if (T <= 0) return;
+    hipLaunchKernelGGL(k_trunc_w, dim3(nblocks(T, TPB)), dim3(TPB), 0, s, lo, T, t, B1, B2, rxm, rx1, rx2, rzm, rz1,
+                       rz2, w3);
+}
+void launch_trunc_round0_sums(int64_t T, int t, const u64* B1, const u64* B2, u64* out, hipStream_t s) {
+    if (T <= 0) return;
+    hipLaunchKernelGGL(k_trunc_round0_sums, dim3(nblocks(2 * T, TPB)), dim3(TPB), 0, s, T, t, B1, B2, out);
+}
+void launch_x_poly(const u64* P, u64* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_x_poly, dim3(1), dim3(64), 0, s, P, out);
+}
+void launch_trunc_fold0(int64_t T, int t, const u64* B1, const u64* B2, const u64* R, const u64* ZR,
+                        const u64* zeta, u64* xplane, u64* yplane, hipStream_t s) {
+    if (T <= 0) return;
+    hipLaunchKernelGGL(k_trunc_fold0, dim3((unsigned)(64 * T)), dim3(64), 0, s, T, t, B1, B2, R, ZR, zeta, xplane,
+                       yplane);
+}
 
 }  // namespace mpc3

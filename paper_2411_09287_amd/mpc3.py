@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpc3.so")
 
 OK, E_ARG, E_SHAPE, E_NOMEM, E_ABORTED, E_UNVERIFIED, E_HIP, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
-VARIANT_U64, VARIANT_LIMB_I8 = 0, 1
+VARIANT_U64, VARIANT_LIMB_I8, VARIANT_AUTO = 0, 1, 2
 PH_OFFLINE, PH_ONLINE, PH_VERIFY_OFFLINE, PH_VERIFY_ONLINE = 0, 1, 2, 3
 VERIFY_INNER, VERIFY_TRUNC, VERIFY_MULT, VERIFY_ALL = 1, 2, 4, 7
 (SITE_INNER_GAMMA2, SITE_INNER_M1, SITE_TRUNC_GAMMA2, SITE_TRUNC_M1, SITE_MULT_GAMMA2, SITE_VER_H0_M1,
@@ -47,6 +47,8 @@ SIGNATURES = {
     "mpc3_ctx_destroy": (_I, [_P]),
     "mpc3_set_variant": (_I, [_P, _I]),
     "mpc3_set_chunk": (_I, [_P, _I64]),
+    "mpc3_autotune": (_I, [_P, _I64, _I64, _I64, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double)]),
     "mpc3_keep_messages": (_I, [_P, _I]),
     "mpc3_encode": (_I, [_P, _P, _I64, _P]),
     "mpc3_decode": (_I, [_P, _P, _I64, _P]),
@@ -55,6 +57,7 @@ SIGNATURES = {
     "mpc3_inner": (_I, [_P, ctypes.POINTER(Share), ctypes.POINTER(Share), ctypes.POINTER(TruncPair),
                         ctypes.POINTER(Share)]),
     "mpc3_im2col": (_I, [_P, ctypes.POINTER(Share), _I, _I, _I, _I, _I, _I, _I, ctypes.POINTER(Share)]),
+    "mpc3_sumpool2": (_I, [_P, ctypes.POINTER(Share), _I, _I, _I, _I, ctypes.POINTER(Share)]),
     "mpc3_mult": (_I, [_P, ctypes.POINTER(Share), ctypes.POINTER(Share), ctypes.POINTER(Share)]),
     "mpc3_trunc": (_I, [_P, ctypes.POINTER(TruncPair), ctypes.POINTER(Share), ctypes.POINTER(Share)]),
     "mpc3_verify": (_I, [_P, _I, _I, ctypes.POINTER(_I)]),
@@ -185,6 +188,12 @@ class Context:
     def set_variant(self, v):
         _ck(lib().mpc3_set_variant(self.h, v), "mpc3_set_variant")
 
+    def autotune(self, M, K, N, reps=3):
+        ch, a, b = ctypes.c_int(0), ctypes.c_double(0), ctypes.c_double(0)
+        _ck(lib().mpc3_autotune(self.h, M, K, N, reps, ctypes.byref(ch), ctypes.byref(a), ctypes.byref(b)),
+            "mpc3_autotune")
+        return ch.value, a.value, b.value
+
     def set_chunk(self, t):
         _ck(lib().mpc3_set_chunk(self.h, t), "mpc3_set_chunk")
 
@@ -232,6 +241,12 @@ class Context:
         xs, cs = x.c(), cols.c()
         _ck(lib().mpc3_im2col(self.h, ctypes.byref(xs), B, H, W, C, KH, KW, pad, ctypes.byref(cs)), "mpc3_im2col")
         return cols
+
+    def sumpool2(self, x, B, H, W, C):
+        out = DShare.empty(B, (H // 2) * (W // 2) * C, self.device)
+        xs, os_ = x.c(), out.c()
+        _ck(lib().mpc3_sumpool2(self.h, ctypes.byref(xs), B, H, W, C, ctypes.byref(os_)), "mpc3_sumpool2")
+        return out
 
     def mult(self, a, b):
         c = DShare.empty(a.rows, a.cols, self.device)

@@ -1,0 +1,93 @@
+"""Secure evaluation of a chained linear network through the C ABI.
+
+The linear layers of the MLP, LeNet-shaped and VGG-shaped networks are chained:
+convolution (im2col) or dense product with Pi_Inner, Pi_Trunc by the fixed-point
+precision, and 2x2 average pooling between stages.  Average pooling is a sum pool of the
+shares (a local linear map) with the factor 1/4 folded into the next layer's plaintext
+weights before encoding.  ReLU / max-pool are non-linear layers outside this path.
+
+Weights are encoded and shared once; every call of `forward` shares a new input batch,
+evaluates the layers and leaves the products pending for `verify`.
+"""
+import numpy as np
+import torch
+
+from . import mpc3, workloads
+
+
+def plan(name):
+    """Layers of a model with the pooling that links them: list of dicts."""
+    spec = workloads.MODELS[name]
+    layers = spec["layers"]
+    out = []
+    for i, layer in enumerate(layers):
+        d = {"layer": layer, "pool_after": False}
+        if layer[0] == "conv":
+            _, kh, kw, cin, cout, pad, (h, w) = layer
+            oh, ow = h + 2 * pad - kh + 1, w + 2 * pad - kw + 1
+            d["out_hw"] = (oh, ow)
+            if i + 1 < len(layers):
+                nxt = layers[i + 1]
+                if nxt[0] == "conv":
+                    d["pool_after"] = tuple(nxt[6]) == (oh // 2, ow // 2) and (oh, ow) != tuple(nxt[6])
+                else:
+                    d["pool_after"] = nxt[1] == (oh // 2) * (ow // 2) * cout
+        out.append(d)
+    return out
+
+
+def float_weights(name, seed=200):
+    """Plaintext weights (K x N), with 1/4 folded in after every average pool."""
+    ws = []
+    pooled = False
+    for i, d in enumerate(plan(name)):
+        layer = d["layer"]
+        M, K, N = workloads.layer_gemm_shape(layer, 1)
+        w = workloads.layer_weight(layer, seed + i).reshape(K, N)
+        if pooled:
+            w = w / 4.0
+        ws.append(w)
+        pooled = d["pool_after"]
+    return ws
+
+
+class Network:
+    """Shared weights of one model on one context."""
+
+    def __init__(self, ctx, name, seed=200):
+        self.ctx = ctx
+        self.name = name
+        self.plan = plan(name)
+        self.frac = ctx.frac_bits
+        self.w_float = float_weights(name, seed)
+        self.weights = [ctx.share(ctx.encode(torch.from_numpy(w).to(ctx.device))) for w in self.w_float]
+
+    def shapes(self, batch):
+        return [workloads.layer_gemm_shape(d["layer"], batch) for d in self.plan]
+
+    def forward(self, x, trunc=True):
+        """x: float64 tensor (batch, ...) of the model's input shape on the device.
+        Returns the shared logits (batch x classes); products stay pending."""
+        ctx = self.ctx
+        batch = x.shape[0]
+        h = ctx.share(ctx.encode(x).reshape(batch, -1))
+        for i, d in enumerate(self.plan):
+            layer = d["layer"]
+            if layer[0] == "conv":
+                _, kh, kw, cin, cout, pad, (hh, ww) = layer
+                X = ctx.im2col(h, batch, hh, ww, cin, kh, kw, pad)
+            else:
+                X = h if h.cols == layer[1] else mpc3.DShare(*[t.reshape(batch, -1) for t in (h.m, h.r1, h.r2)])
+            M, N = X.rows, self.weights[i].cols
+            if trunc:
+                pair = ctx.trunc_pair(M * N, self.frac)
+                Z = ctx.inner(X, self.weights[i], pair)
+                Y = ctx.trunc(pair, Z)
+            else:
+                Y = ctx.inner(X, self.weights[i])
+            if d["pool_after"]:
+                oh, ow = d["out_hw"]
+                Y = ctx.sumpool2(mpc3.DShare(*[t.reshape(batch, -1) for t in (Y.m, Y.r1, Y.r2)]),
+                                 batch, oh, ow, layer[4])
+            h = Y if layer[0] == "fc" else mpc3.DShare(*[t.reshape(batch, -1) for t in (Y.m, Y.r1, Y.r2)])
+        return h
