@@ -295,6 +295,20 @@ void polyevl_sparse(mpc3_ctx* c, const VerCtx& v, int64_t n, const u64* X1, int6
     send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8 * 64);
 }
 
+// Pi_PolyEvl outputs from a P0 product C (64x64, P1 and P2 sums zero: the truncation gates).
+void polyevl_from(mpc3_ctx* c, const VerCtx& v, const u64* C, uint32_t pr, uint32_t pg, uint32_t sub, Inj im1,
+                  Inj ig2, u64* out, u64* lm1, u64* lm2, u64* lg2) {
+    PolyEvlArgs a{};
+    a.C = C; a.k = c->keys; a.op = v.op; a.pr = pr; a.pg = pg; a.sub = sub;
+    a.inj_m1 = im1.index >= 0 ? (int)im1.index : -1; a.e_m1 = im1.e;
+    a.inj_g2 = ig2.index >= 0 ? (int)ig2.index : -1; a.e_g2 = ig2.e;
+    a.out = out; a.log_m1 = lm1; a.log_m2 = lm2; a.log_g2 = lg2;
+    launch_polyevl_finish(a, c->cs);
+    send(c, MPC3_PH_VERIFY_OFFLINE, 0, 2, 8 * 64);
+    send(c, MPC3_PH_VERIFY_ONLINE, 1, 2, 8 * 64);
+    send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8 * 64);
+}
+
 // The Lagrange step of a round: reveal zeta, update z, return zeta.
 u64* round_finish(mpc3_ctx* c, const VerCtx& v, uint32_t sub, int k, const u64* h0, const u64* h2, u64* z) {
     u64* zeta = c->sc->words(64);
@@ -520,49 +534,86 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
         fold_and_check(c, v, XY, np, z, 0);
         return;
     }
-    // Round 0 from the gate structure: x_e = r^g a_e, y_e = b_e (scalars), pairs within a gate.
-    const uint32_t sub = ((uint32_t)v.inst << 8);
-    u64* sums = c->sc->words(8 * T);
-    launch_trunc_round0_sums(T, p.t, B1, B2, sums, s);
-    u64* P = c->sc->words(4 * 64);
-    zero(c, P, 4 * 64 * 8);
-    run_gemm(c, plain(4, 64, 2 * T, view(sums, 2 * T, 1), view(pw, 64, 1), oview(P, 64, 1), true));
-    u64* S = c->sc->words(3 * 64);              // prefolded P0 / P1 / P2 sums of one Pi_PolyEvl
-    u64* h0 = c->sc->words(3 * 64);
-    u64* h2 = c->sc->words(3 * 64);
-    const Inj i_h0 = take_ver(c, MPC3_SITE_VER_H0_M1, v.inst, 0);
-    const Inj i_h2 = take_ver(c, MPC3_SITE_VER_H2_GAMMA2, v.inst, 0);
-    auto finish = [&](uint32_t pr, uint32_t pg, Inj im1, Inj ig2, u64* out, int l1, int l2, int lg) {
-        PolyEvlArgs a{};
-        a.C = S; a.prefolded = 1; a.k = c->keys; a.op = v.op; a.pr = pr; a.pg = pg; a.sub = sub;
-        a.inj_m1 = im1.index >= 0 ? (int)im1.index : -1; a.e_m1 = im1.e;
-        a.inj_g2 = ig2.index >= 0 ? (int)ig2.index : -1; a.e_g2 = ig2.e;
-        a.out = out; a.log_m1 = slot(v, l1, 0); a.log_m2 = slot(v, l2, 0); a.log_g2 = slot(v, lg, 0);
-        launch_polyevl_finish(a, s);
-        send(c, MPC3_PH_VERIFY_OFFLINE, 0, 2, 8 * 64);
-        send(c, MPC3_PH_VERIFY_ONLINE, 1, 2, 8 * 64);
-        send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8 * 64);
-    };
-    zero(c, S, 3 * 64 * 8);
-    ck(hipMemcpyAsync(S, P, 512, hipMemcpyDeviceToDevice, s));           // h(0) = sum_g s_g r^g
-    finish(P_VER_H0_R, P_VER_H0_GAMMA, i_h0, Inj{-1, 0}, h0, MPC3_LOG_H0_M1, MPC3_LOG_H0_M2, MPC3_LOG_H0_G2);
-    u64* S2 = c->sc->words(3 * 64);
-    zero(c, S2, 3 * 64 * 8);
-    launch_x_poly(P + 64, S2, s);                                        // h(x) = P0 + x P1 + x^2 P2
-    S = S2;
-    finish(P_VER_H2_R, P_VER_H2_GAMMA, Inj{-1, 0}, i_h2, h2, MPC3_LOG_H2_M1, MPC3_LOG_H2_M2, MPC3_LOG_H2_G2);
-    c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
-    u64* zeta = round_finish(c, v, sub, 0, h0, h2, z);
-    // folded vectors: x_i = a0 r^g + da (zeta r^g), y_i = b0 + db zeta
+    // Symbolic rounds: pairs stay inside a gate (64 elements) for six folds.  After j folds,
+    // element i of gate g is x = r^g sum_S alpha_S zeta^S, y = sum_S gamma_S zeta^S, so h(0) and
+    // h(x) are power-weighted sums over the gates of scalar coefficients per monomial.
+    const int KS = std::min(R, 5);
+    const int64_t G = 2 * T;
+    u64* al = c->sc->words(G * 64);
+    u64* ga = c->sc->words(G * 64);
+    u64* al2 = c->sc->words(G * 64);
+    u64* ga2 = c->sc->words(G * 64);
+    launch_sym_init(T, p.t, B1, B2, al, ga, s);
+    int maxnu = 1;
+    for (int j = 0; j < KS; ++j) maxnu *= 3;
+    u64* Z = c->sc->words(3 * maxnu * 64);          // zeta^u, u in {0,1,2}^j
+    u64* Zn = c->sc->words(3 * maxnu * 64);
+    u64* XZ = c->sc->words(3 * maxnu * 64);         // x^e zeta^u
+    u64* ML = c->sc->words(64 * 64);                // zeta^S, S a subset of the j points
+    u64* MLn = c->sc->words(64 * 64);
+    launch_set_one(Z, s);
+    launch_set_one(ML, s);
     u64* Wz = c->sc->words(4096);
-    launch_mulmat(zeta, 64, 1, Wz, s);
-    u64* ZR = c->sc->words(2 * T * 64);
-    run_gemm(c, plain(2 * T, 64, 64, view(pw, 64, 1), view(Wz, 64, 1), oview(ZR, 64, 1), false));
-    const int64_t half = np / 2;
+    int nu = 1;
+    for (int j = 0; j < KS; ++j) {
+        const uint32_t sub = ((uint32_t)v.inst << 8) | (uint32_t)j;
+        Scratch::Mark mk = c->sc->mark();
+        u64* c0 = c->sc->words((int64_t)nu * G);
+        u64* cx = c->sc->words((int64_t)3 * nu * G);
+        launch_sym_coeffs(j, G, al, ga, c0, cx, s);
+        u64* PS = c->sc->words(nu * 64);
+        u64* PSX = c->sc->words(3 * nu * 64);
+        zero(c, PS, (size_t)nu * 512);
+        zero(c, PSX, (size_t)3 * nu * 512);
+        run_gemm(c, plain(nu, 64, G, view(c0, G, 1), view(pw, 64, 1), oview(PS, 64, 1), true));
+        run_gemm(c, plain(3 * nu, 64, G, view(cx, G, 1), view(pw, 64, 1), oview(PSX, 64, 1), true));
+        ck(hipMemcpyAsync(XZ, Z, (size_t)nu * 512, hipMemcpyDeviceToDevice, s));
+        launch_xshift_rows(Z, nu, 1, XZ + nu * 64, s);
+        launch_xshift_rows(Z, nu, 2, XZ + 2 * nu * 64, s);
+        u64* h0 = c->sc->words(3 * 64);
+        u64* h2 = c->sc->words(3 * 64);
+        u64* C = c->sc->words(3 * 4096);
+        zero(c, C, 3 * 4096 * 8);
+        run_gemm(c, plain(64, 64, nu, view(Z, 1, 64), view(PS, 64, 1), oview(C, 64, 1), true));
+        polyevl_from(c, v, C, P_VER_H0_R, P_VER_H0_GAMMA, sub, take_ver(c, MPC3_SITE_VER_H0_M1, v.inst, j),
+                     Inj{-1, 0}, h0, slot(v, MPC3_LOG_H0_M1, j), slot(v, MPC3_LOG_H0_M2, j),
+                     slot(v, MPC3_LOG_H0_G2, j));
+        u64* C2 = c->sc->words(3 * 4096);
+        zero(c, C2, 3 * 4096 * 8);
+        run_gemm(c, plain(64, 64, 3 * nu, view(XZ, 1, 64), view(PSX, 64, 1), oview(C2, 64, 1), true));
+        polyevl_from(c, v, C2, P_VER_H2_R, P_VER_H2_GAMMA, sub, Inj{-1, 0},
+                     take_ver(c, MPC3_SITE_VER_H2_GAMMA2, v.inst, j), h2, slot(v, MPC3_LOG_H2_M1, j),
+                     slot(v, MPC3_LOG_H2_M2, j), slot(v, MPC3_LOG_H2_G2, j));
+        c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
+        u64* zeta = round_finish(c, v, sub, j, h0, h2, z);
+        launch_sym_fold(j, G, al, ga, al2, ga2, s);
+        std::swap(al, al2);
+        std::swap(ga, ga2);
+        // tables for j + 1 folds
+        launch_mulmat(zeta, 64, 1, Wz, s);
+        ck(hipMemcpyAsync(Zn, Z, (size_t)nu * 512, hipMemcpyDeviceToDevice, s));
+        run_gemm(c, plain(nu, 64, 64, view(Z, 64, 1), view(Wz, 64, 1), oview(Zn + nu * 64, 64, 1), false));
+        run_gemm(c, plain(nu, 64, 64, view(Zn + nu * 64, 64, 1), view(Wz, 64, 1), oview(Zn + 2 * nu * 64, 64, 1),
+                          false));
+        std::swap(Z, Zn);
+        const int L = 1 << j;
+        ck(hipMemcpyAsync(MLn, ML, (size_t)L * 512, hipMemcpyDeviceToDevice, s));
+        run_gemm(c, plain(L, 64, 64, view(ML, 64, 1), view(Wz, 64, 1), oview(MLn + L * 64, 64, 1), false));
+        std::swap(ML, MLn);
+        nu *= 3;
+        c->sc->restore(mk);
+    }
+    // materialise: per gate 64 / 2^KS elements of 2^KS coefficients each
+    const int L = 1 << KS;
+    const int64_t per = 64 / L, nel = G * per;
+    const int64_t half = np >> KS;
     u64* XY = c->sc->words(2 * half * 64);
     zero(c, XY, (size_t)2 * half * 64 * 8);
-    launch_trunc_fold0(T, p.t, B1, B2, pw, ZR, zeta, XY, XY + half * 64, s);
-    fold_and_check(c, v, XY, half, z, R, 1, true);
+    u64* Q = c->sc->words(nel * 64);
+    run_gemm(c, plain(nel, 64, L, view(al, L, 1), view(ML, 64, 1), oview(Q, 64, 1), false));
+    launch_gr_mul_rows(pw, Q, nel, per, XY, s);                                         // x = r^g Q
+    run_gemm(c, plain(nel, 64, L, view(ga, L, 1), view(ML, 64, 1), oview(XY + half * 64, 64, 1), false));
+    fold_and_check(c, v, XY, half, z, R, KS, true);
 }
 
 int guard(mpc3_ctx* c) {

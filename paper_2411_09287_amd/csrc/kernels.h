@@ -99,15 +99,22 @@ void launch_set_one(u64* p, hipStream_t s);   // the ring element 1
 void launch_trunc_w(int64_t lo, int64_t T, int t, const u64* B1, const u64* B2, const u64* rxm, const u64* rx1,
                     const u64* rx2, const u64* rzm, const u64* rz1, const u64* rz2, u64* w3, hipStream_t s);
 
-// First reduction round of a truncation-gate instance, per gate g < 2T: the scalar sums
-// s_h0 = sum_{even j} a_j b_j and, over the pairs (j, j+1), s0 = sum a0 b0,
-// s1 = sum (a0 db + da b0), s2 = sum da db (out: 4 rows of 2T words).
-void launch_trunc_round0_sums(int64_t T, int t, const u64* B1, const u64* B2, u64* out, hipStream_t s);
-// out = P0 + x P1 + x^2 P2 (three consecutive ring elements -> one).
-void launch_x_poly(const u64* P, u64* out, hipStream_t s);
-// Folded first-round vectors: x_i = a0 R[g] + da ZR[g], y_i = lift(b0) + db zeta, for the
-// 64 T pairs of the chunk (x plane and y plane, 64 words per element).
-void launch_trunc_fold0(int64_t T, int t, const u64* B1, const u64* B2, const u64* R, const u64* ZR,
-                        const u64* zeta, u64* xplane, u64* yplane, hipStream_t s);
+// Symbolic reduction rounds of truncation gates.  After j folds, element i of gate g is
+// x = r^g sum_S alpha[g][i][S] zeta^S and y = sum_S gamma[g][i][S] zeta^S (S a subset of
+// the j revealed points, bit b <-> point b+1); 64 coefficients per gate and side.
+// Initial coefficients (j = 0): alpha = gate weight * bit of B1, gamma = -bit of B2.
+void launch_sym_init(int64_t T, int t, const u64* B1, const u64* B2, u64* alpha, u64* gamma, hipStream_t s);
+// Coefficients of h(0) (3^j monomials zeta^u) and h(x) (3^(j+1) monomials x^e zeta^u,
+// index u + 3^j e) for every gate: c0 [3^j][G], cx [3^(j+1)][G].
+void launch_sym_coeffs(int j, int64_t G, const u64* alpha, const u64* gamma, u64* c0, u64* cx, hipStream_t s);
+// Fold at the next point: coefficients for j+1 folds.
+void launch_sym_fold(int j, int64_t G, const u64* alpha, const u64* gamma, u64* alpha_n, u64* gamma_n,
+                     hipStream_t s);
+// rows out[i] = x^e * in[i] for e = 1, 2 (n rows of 64 words).
+void launch_xshift_rows(const u64* in, int64_t n, int e, u64* out, hipStream_t s);
+// out[i] = P[i / per] * Q[i] (ring products, one 64-lane group per row).
+void launch_gr_mul_rows(const u64* P, const u64* Q, int64_t n, int64_t per, u64* out, hipStream_t s);
+
+
 
 }  // namespace mpc3

@@ -634,59 +634,117 @@ __device__ __forceinline__ u64 gate_weight(int s, int j, int t) {
     return 2 * c;
 }
 
-__global__ void k_trunc_round0_sums(int64_t T, int t, const u64* B1, const u64* B2, u64* out) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= 2 * T) return;
+__global__ void k_sym_init(int64_t T, int t, const u64* B1, const u64* B2, u64* alpha, u64* gamma) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;    // gate * 64 + bit
+    if (idx >= 2 * T * 64) return;
+    const int64_t g = idx >> 6;
+    const int j = (int)(idx & 63);
     const int64_t q = g >> 1;
     const int s = (int)(g & 1);
-    const u64 x1 = B1[q], x2 = B2[q];
-    u64 h0 = 0, s0 = 0, s1 = 0, s2 = 0;
-    for (int j = 0; j < 64; j += 2) {
-        const u64 a0 = gate_weight(s, j, t) * ((x1 >> j) & 1);
-        const u64 a1 = gate_weight(s, j + 1, t) * ((x1 >> (j + 1)) & 1);
-        const u64 b0 = 0 - ((x2 >> j) & 1);
-        const u64 b1 = 0 - ((x2 >> (j + 1)) & 1);
-        const u64 da = a1 - a0, db = b1 - b0;
-        h0 += a0 * b0;
-        s0 += a0 * b0;
-        s1 += a0 * db + da * b0;
-        s2 += da * db;
+    alpha[idx] = gate_weight(s, j, t) * ((B1[q] >> j) & 1);
+    gamma[idx] = 0 - ((B2[q] >> j) & 1);
+}
+
+__device__ __forceinline__ int pow3(int j) {
+    int r = 1;
+    for (int i = 0; i < j; ++i) r *= 3;
+    return r;
+}
+
+// One thread per gate.  For monomial u (base-3 digits u_b in {0,1,2}), the pairs (S, T) with
+// S_b + T_b = u_b: digit 0 -> (0,0), 2 -> (1,1), 1 -> (0,1) or (1,0).
+__global__ void k_sym_coeffs(int j, int64_t G, const u64* alpha, const u64* gamma, u64* c0, u64* cx) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    const int L = 1 << j;                  // coefficients per element
+    const int npairs = 32 >> j;            // pairs per gate
+    const int nu = pow3(j);
+    const u64* A = alpha + g * 64;
+    const u64* C = gamma + g * 64;
+    for (int u = 0; u < nu; ++u) {
+        // digits of u, positions of the 1-digits
+        int base = 0, ones[8], nones = 0;
+        int uu = u;
+        for (int b = 0; b < j; ++b) {
+            const int d = uu % 3;
+            uu /= 3;
+            if (d == 2) base |= 1 << b;
+            if (d == 1) ones[nones++] = b;
+        }
+        u64 h0 = 0, e0 = 0, e1 = 0, e2 = 0;
+        for (int m = 0; m < (1 << nones); ++m) {
+            int S = base, T = base;
+            for (int q = 0; q < nones; ++q) {
+                if ((m >> q) & 1) S |= 1 << ones[q];
+                else T |= 1 << ones[q];
+            }
+            for (int i = 0; i < npairs; ++i) {
+                const u64 a0 = A[(2 * i) * L + S], a1 = A[(2 * i + 1) * L + S];
+                const u64 b0 = C[(2 * i) * L + T], b1 = C[(2 * i + 1) * L + T];
+                const u64 da = a1 - a0, db = b1 - b0;
+                h0 += a0 * b0;                 // f(0) g(0)
+                e0 += a0 * b0;                 // f(x) g(x) = (a0 + x da)(b0 + x db)
+                e1 += a0 * db + da * b0;
+                e2 += da * db;
+            }
+        }
+        c0[(int64_t)u * G + g] = h0;
+        cx[(int64_t)u * G + g] = e0;
+        cx[(int64_t)(u + nu) * G + g] = e1;
+        cx[(int64_t)(u + 2 * nu) * G + g] = e2;
     }
-    out[g] = h0;
-    out[2 * T + g] = s0;
-    out[4 * T + g] = s1;
-    out[6 * T + g] = s2;
 }
 
-__global__ void k_x_poly(const u64* P, u64* out) {
-    __shared__ u64 v[64], w[64];
-    const int k = threadIdx.x;
-    v[k] = P[128 + k];
-    __syncthreads();
-    const u64 a = xmul_coeff(v, k) + P[64 + k];      // x P2 + P1
-    __syncthreads();
-    w[k] = a;
-    __syncthreads();
-    out[k] = xmul_coeff(w, k) + P[k];                // x (x P2 + P1) + P0
+// thread per (gate, new element i, new subset S)
+__global__ void k_sym_fold(int j, int64_t G, const u64* alpha, const u64* gamma, u64* an, u64* gn) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= G * 64) return;
+    const int64_t g = idx >> 6;
+    const int r = (int)(idx & 63);
+    const int L = 1 << j, L2 = 2 * L;
+    const int i = r / L2, S = r % L2;
+    const u64* A = alpha + g * 64;
+    const u64* C = gamma + g * 64;
+    u64 va, vc;
+    if (S < L) {              // the point's bit clear: coefficient of f_i(0)
+        va = A[(2 * i) * L + S];
+        vc = C[(2 * i) * L + S];
+    } else {                  // bit set: f_i(1) - f_i(0)
+        const int S0 = S - L;
+        va = A[(2 * i + 1) * L + S0] - A[(2 * i) * L + S0];
+        vc = C[(2 * i + 1) * L + S0] - C[(2 * i) * L + S0];
+    }
+    an[idx] = va;
+    gn[idx] = vc;
 }
 
-__global__ void k_trunc_fold0(int64_t T, int t, const u64* B1, const u64* B2, const u64* R, const u64* ZR,
-                              const u64* zeta, u64* xp, u64* yp) {
+__global__ void k_xshift_rows(const u64* in, int64_t n, int e, u64* out) {
+    __shared__ u64 v[64];
     const int k = threadIdx.x;
-    const int64_t i = blockIdx.x;            // new element = pair (2i, 2i+1) of the chunk
-    const int64_t e0 = 2 * i;
-    const int64_t q = e0 >> 7;
-    const int s = (int)((e0 >> 6) & 1);
-    const int j = (int)(e0 & 63);
-    const int64_t g = 2 * q + s;
-    const u64 x1 = B1[q], x2 = B2[q];
-    const u64 a0 = gate_weight(s, j, t) * ((x1 >> j) & 1);
-    const u64 a1 = gate_weight(s, j + 1, t) * ((x1 >> (j + 1)) & 1);
-    const u64 b0 = 0 - ((x2 >> j) & 1);
-    const u64 b1 = 0 - ((x2 >> (j + 1)) & 1);
-    xp[i * 64 + k] = a0 * R[g * 64 + k] + (a1 - a0) * ZR[g * 64 + k];
-    yp[i * 64 + k] = (k == 0 ? b0 : 0) + (b1 - b0) * zeta[k];
+    const int64_t i = blockIdx.x;
+    v[k] = in[i * 64 + k];
+    __syncthreads();
+    u64 a = xmul_coeff(v, k);
+    if (e == 2) {
+        __syncthreads();
+        v[k] = a;
+        __syncthreads();
+        a = xmul_coeff(v, k);
+    }
+    out[i * 64 + k] = a;
 }
+
+__global__ void k_gr_mul_rows(const u64* P, const u64* Q, int64_t per, u64* out) {
+    __shared__ u64 a[64], b[64], sh[64];
+    const int k = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    a[k] = P[(i / per) * 64 + k];
+    b[k] = Q[i * 64 + k];
+    __syncthreads();
+    out[i * 64 + k] = gr_mul_lane(a, b, sh, k);
+}
+
+
 
 }  // namespace
 
@@ -824,18 +882,26 @@ void launch_trunc_w(int64_t lo, int64_t T, int t, const u64* B1, const u64* B2, 
     hipLaunchKernelGGL(k_trunc_w, dim3(nblocks(T, TPB)), dim3(TPB), 0, s, lo, T, t, B1, B2, rxm, rx1, rx2, rzm, rz1,
                        rz2, w3);
 }
-void launch_trunc_round0_sums(int64_t T, int t, const u64* B1, const u64* B2, u64* out, hipStream_t s) {
+void launch_sym_init(int64_t T, int t, const u64* B1, const u64* B2, u64* alpha, u64* gamma, hipStream_t s) {
     if (T <= 0) return;
-    hipLaunchKernelGGL(k_trunc_round0_sums, dim3(nblocks(2 * T, TPB)), dim3(TPB), 0, s, T, t, B1, B2, out);
+    hipLaunchKernelGGL(k_sym_init, dim3(nblocks(2 * T * 64, TPB)), dim3(TPB), 0, s, T, t, B1, B2, alpha, gamma);
 }
-void launch_x_poly(const u64* P, u64* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_x_poly, dim3(1), dim3(64), 0, s, P, out);
+void launch_sym_coeffs(int j, int64_t G, const u64* alpha, const u64* gamma, u64* c0, u64* cx, hipStream_t s) {
+    if (G <= 0) return;
+    hipLaunchKernelGGL(k_sym_coeffs, dim3(nblocks(G, 64)), dim3(64), 0, s, j, G, alpha, gamma, c0, cx);
 }
-void launch_trunc_fold0(int64_t T, int t, const u64* B1, const u64* B2, const u64* R, const u64* ZR,
-                        const u64* zeta, u64* xplane, u64* yplane, hipStream_t s) {
-    if (T <= 0) return;
-    hipLaunchKernelGGL(k_trunc_fold0, dim3((unsigned)(64 * T)), dim3(64), 0, s, T, t, B1, B2, R, ZR, zeta, xplane,
-                       yplane);
+void launch_sym_fold(int j, int64_t G, const u64* alpha, const u64* gamma, u64* an, u64* gn, hipStream_t s) {
+    if (G <= 0) return;
+    hipLaunchKernelGGL(k_sym_fold, dim3(nblocks(G * 64, TPB)), dim3(TPB), 0, s, j, G, alpha, gamma, an, gn);
 }
+void launch_xshift_rows(const u64* in, int64_t n, int e, u64* out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_xshift_rows, dim3((unsigned)n), dim3(64), 0, s, in, n, e, out);
+}
+void launch_gr_mul_rows(const u64* P, const u64* Q, int64_t n, int64_t per, u64* out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gr_mul_rows, dim3((unsigned)n), dim3(64), 0, s, P, Q, per, out);
+}
+
 
 }  // namespace mpc3
