@@ -147,13 +147,36 @@ __device__ __forceinline__ void fetch(const Prod& P, int64_t kglob, int64_t Kp, 
     load8(B, r0b + rb, k0 + 8 * ob, K, wb);
 }
 
+// LDS layouts of a 64 x 32 digit tile (PLANE bytes per digit):
+//   KC (operand read with k contiguous): [row][32 k]      - 16-byte fragment reads
+//   otherwise:                           [octet][row][8 k] - conflict-free 8-byte stores
+template <bool KC>
 __device__ __forceinline__ void stash(int8_t* lds, int row, int oct, const u64 w[8]) {
     u64 q[8];
     to_digits(w, q);
 #pragma unroll
-    for (int d = 0; d < 8; ++d) *(u64*)(lds + d * PLANE + row * KB + oct * 8) = q[d];
+    for (int d = 0; d < 8; ++d) {
+        if constexpr (KC) *(u64*)(lds + d * PLANE + row * KB + oct * 8) = q[d];
+        else *(u64*)(lds + d * PLANE + oct * 512 + row * 8) = q[d];
+    }
 }
 
+// 16 consecutive k (kh .. kh+15) of one tile row for digit plane `plane`
+template <bool KC>
+__device__ __forceinline__ v4i frag(const int8_t* plane, int row, int kh) {
+    if constexpr (KC) {
+        return *(const v4i*)(plane + row * KB + kh);
+    } else {
+        const int o = kh >> 3;
+        const u64 lo = *(const u64*)(plane + o * 512 + row * 8);
+        const u64 hi = *(const u64*)(plane + (o + 1) * 512 + row * 8);
+        v4i r;
+        r.x = (int)(u32)lo; r.y = (int)(u32)(lo >> 32); r.z = (int)(u32)hi; r.w = (int)(u32)(hi >> 32);
+        return r;
+    }
+}
+
+template <bool AK, bool BK>
 __global__ __launch_bounds__(NT, 2) void k_lgemm(LArgs a) {
     __shared__ __attribute__((aligned(16))) int8_t As[2][8 * PLANE];
     __shared__ __attribute__((aligned(16))) int8_t Bs[2][8 * PLANE];
@@ -166,7 +189,7 @@ __global__ __launch_bounds__(NT, 2) void k_lgemm(LArgs a) {
     const int64_t r0a = (int64_t)blockIdx.y * TM, r0b = (int64_t)blockIdx.x * TN;
     const int wy = w >> 1, wx = w & 1;
     const int r = lane & 31, kh = (lane >> 5) * 16;
-    const int aoff = (wy * 32 + r) * KB + kh, boff = (wx * 32 + r) * KB + kh;
+    const int arow = wy * 32 + r, brow = wx * 32 + r;
 
     v16i acc[8];
 #pragma unroll
@@ -176,8 +199,8 @@ __global__ __launch_bounds__(NT, 2) void k_lgemm(LArgs a) {
     int ra, oa, rb, ob;
     if (kbeg < kend) {
         fetch(P, kbeg, a.Kp, a.K, r0a, r0b, t, wa, wb, ra, oa, rb, ob);
-        stash(As[0], ra, oa, wa);
-        stash(Bs[0], rb, ob, wb);
+        stash<AK>(As[0], ra, oa, wa);
+        stash<BK>(Bs[0], rb, ob, wb);
     }
     __syncthreads();
     int buf = 0;
@@ -186,17 +209,17 @@ __global__ __launch_bounds__(NT, 2) void k_lgemm(LArgs a) {
         if (more) fetch(P, k0 + KB, a.Kp, a.K, r0a, r0b, t, wa, wb, ra, oa, rb, ob);
         v4i B[8];
 #pragma unroll
-        for (int d = 0; d < 8; ++d) B[d] = *(const v4i*)(Bs[buf] + d * PLANE + boff);
+        for (int d = 0; d < 8; ++d) B[d] = frag<BK>(Bs[buf] + d * PLANE, brow, kh);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const v4i A = *(const v4i*)(As[buf] + i * PLANE + aoff);
+            const v4i A = frag<AK>(As[buf] + i * PLANE, arow, kh);
 #pragma unroll
             for (int s = i; s < 8; ++s)
                 acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[s - i], acc[s], 0, 0, 0);
         }
         if (more) {
-            stash(As[buf ^ 1], ra, oa, wa);
-            stash(Bs[buf ^ 1], rb, ob, wb);
+            stash<AK>(As[buf ^ 1], ra, oa, wa);
+            stash<BK>(Bs[buf ^ 1], rb, ob, wb);
         }
         __syncthreads();
         buf ^= 1;
@@ -327,7 +350,12 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         a.kchunk = kchunk;
         a.splits = (int)splits;
         if (nprod * splits > 65535) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_lgemm, dim3((unsigned)tn, (unsigned)tm, (unsigned)(nprod * splits)), dim3(NT), 0, st, a);
+        const dim3 grid((unsigned)tn, (unsigned)tm, (unsigned)(nprod * splits));
+        const bool ak = a.prod[0].a[0].s_k == 1, bk = a.prod[0].b[0].s_k == 1;
+        if (ak && bk) hipLaunchKernelGGL((k_lgemm<true, true>), grid, dim3(NT), 0, st, a);
+        else if (ak) hipLaunchKernelGGL((k_lgemm<true, false>), grid, dim3(NT), 0, st, a);
+        else if (bk) hipLaunchKernelGGL((k_lgemm<false, true>), grid, dim3(NT), 0, st, a);
+        else hipLaunchKernelGGL((k_lgemm<false, false>), grid, dim3(NT), 0, st, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
