@@ -132,9 +132,9 @@ def run_mix(args):
         ctx.set_variant(variant)
         srv = serve.Server(ctx)
         if variant == mpc3.VARIANT_AUTO:
-            n = srv.tune(reqs)
+            n = srv.tune(reqs, log=lambda m: log(f"[mix] {m}"))
             log(f"[mix] tuned {n} layer shapes")
-        res = srv.run(reqs, pack=pack)
+        res = srv.run(reqs, pack=pack, log=lambda m: log(f"[mix] {label} {m}"))
         out[label] = serve.summary(res)
         log(f"[mix] {label}: {json.dumps(out[label])}")
     return reqs, out

@@ -122,14 +122,16 @@ int mpc3_set_variant(mpc3_ctx* ctx, int variant);
 
 /* Autotuner: time both kernel families on the three-party product of an M x K by K x N
  * layer (random operands in the context's workspace, `reps` timed runs each after one
- * warm-up) and remember the faster one for that shape.  With MPC3_VARIANT_AUTO every
- * Pi_Inner uses the remembered choice for its shape (the limb family when the shape was
- * never tuned).  *choice receives the pick; ms_u64 / ms_limb (nullable) the median times.
+ * warm-up) and remember the faster one for that shape.  The choice is kept per
+ * (M rounded up to a power of two, K, N), so one call covers every M in (2^(k-1), 2^k].
+ * With MPC3_VARIANT_AUTO every Pi_Inner uses the remembered choice for its shape (the
+ * limb family when the shape was never tuned).  *choice receives the pick; ms_u64 / ms_limb (nullable) the median times.
  * Synchronises.  Results are bit-identical either way; only speed differs. */
 int mpc3_autotune(mpc3_ctx* ctx, int64_t M, int64_t K, int64_t N, int reps, int* choice, double* ms_u64,
                   double* ms_limb);
 
-/* Truncations per Pi_BIVerify instance of the truncation gates (default 16384). */
+/* Truncations per Pi_BIVerify instance of the truncation gates (default 262144, at most
+ * 2^20; a chunk of T truncations holds about 20 KiB x T of workspace while verified). */
 int mpc3_set_chunk(mpc3_ctx* ctx, int64_t truncations_per_instance);
 
 /* Keep the messages of each Pi_Inner / Pi_Mult for mpc3_message (default off). */

@@ -103,7 +103,7 @@ struct mpc3_ctx {
     hipStream_t stream = nullptr;
     int variant = MPC3_VARIANT_U64;
     int frac = 13;
-    int64_t chunk = 1 << 14;
+    int64_t chunk = 1 << 18;
     bool keep_msgs = false;
     bool aborted = false;
     uint32_t op = 0;
@@ -211,6 +211,13 @@ void power_table(mpc3_ctx* c, const u64* base, int64_t n, u64* table) {
         }
     }
     c->sc->restore(mk);
+}
+
+// Autotuner key: rows rounded up to a power of two (2^(k-1) < M <= 2^k share a choice).
+int64_t m_bucket(int64_t M) {
+    int64_t b = 1;
+    while (b < M) b *= 2;
+    return b;
 }
 
 int auto_rounds(int64_t n0, int R) {
@@ -558,15 +565,13 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
     for (int j = 0; j < KS; ++j) {
         const uint32_t sub = ((uint32_t)v.inst << 8) | (uint32_t)j;
         Scratch::Mark mk = c->sc->mark();
-        u64* c0 = c->sc->words((int64_t)nu * G);
+        // h(0) is the x^0 part of h(x): rows 0 .. nu-1 of the power-weighted coefficient sums
         u64* cx = c->sc->words((int64_t)3 * nu * G);
-        launch_sym_coeffs(j, G, al, ga, c0, cx, s);
-        u64* PS = c->sc->words(nu * 64);
+        launch_sym_coeffs(j, G, al, ga, cx, s);
         u64* PSX = c->sc->words(3 * nu * 64);
-        zero(c, PS, (size_t)nu * 512);
         zero(c, PSX, (size_t)3 * nu * 512);
-        run_gemm(c, plain(nu, 64, G, view(c0, G, 1), view(pw, 64, 1), oview(PS, 64, 1), true));
         run_gemm(c, plain(3 * nu, 64, G, view(cx, G, 1), view(pw, 64, 1), oview(PSX, 64, 1), true));
+        const u64* PS = PSX;
         ck(hipMemcpyAsync(XZ, Z, (size_t)nu * 512, hipMemcpyDeviceToDevice, s));
         launch_xshift_rows(Z, nu, 1, XZ + nu * 64, s);
         launch_xshift_rows(Z, nu, 2, XZ + 2 * nu * 64, s);
@@ -784,7 +789,7 @@ int mpc3_autotune(mpc3_ctx* c, int64_t M, int64_t K, int64_t N, int reps, int* c
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         const int pick = med[1] < med[0] ? MPC3_VARIANT_LIMB_I8 : MPC3_VARIANT_U64;
-        c->tuned[std::make_tuple(M, K, N)] = pick;
+        c->tuned[std::make_tuple(m_bucket(M), K, N)] = pick;
         *choice = pick;
         if (ms_u64) *ms_u64 = med[0];
         if (ms_limb) *ms_limb = med[1];
@@ -903,7 +908,7 @@ int mpc3_inner(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W, const 
         }
         const int keep_variant = c->variant;
         if (c->variant == MPC3_VARIANT_AUTO) {
-            auto it = c->tuned.find(std::make_tuple(M, K, N));
+            auto it = c->tuned.find(std::make_tuple(m_bucket(M), K, N));
             c->variant = it == c->tuned.end() ? MPC3_VARIANT_LIMB_I8 : it->second;
         }
         struct VariantRestore {

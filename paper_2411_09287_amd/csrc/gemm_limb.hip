@@ -245,6 +245,202 @@ __global__ __launch_bounds__(NT, 2) void k_lgemm(LArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Second form: B pre-converted to digit tiles.
+//
+// When B is re-read by many row tiles (a layer's weights, K x N against M >> 64 rows) its
+// balanced digits are written once to a tile buffer and the product kernel copies them to
+// LDS unchanged; only A is converted in the kernel.  A tile is k-block kb (32 deep) of 64
+// consecutive B columns: 8 digit planes x 64 rows x 32 bytes (16 KiB), stored exactly as
+// it sits in LDS.  Within a row the two 16-byte halves are swapped when swz(row) = 1, so
+// the 16-byte fragment reads of 16 consecutive rows fall on distinct banks.
+constexpr int TILE_BYTES = 8 * PLANE;
+
+__device__ __forceinline__ int swz(int row) { return ((row >> 2) ^ (row >> 3)) & 1; }
+
+// byte offset of digit plane d, tile row r, k-octet o (8 bytes) within a tile
+__device__ __forceinline__ int toff(int d, int r, int o) {
+    return d * PLANE + r * KB + (((o >> 1) ^ swz(r)) << 4) + ((o & 1) << 3);
+}
+
+// Digit tiles of an operand (rows x K, any strides, optional two-plane combination):
+// tile (t, kb) at byte (t * nkb + kb) * TILE_BYTES; rows >= o.rows and k >= K are zero.
+__global__ void k_to_tiles(Opnd o, int64_t K, int64_t nkb, int64_t rows_pad, int8_t* out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows_pad * nkb * 4) return;
+    int64_t r, o8;
+    if (o.s_k == 1) { o8 = idx % (nkb * 4); r = idx / (nkb * 4); }
+    else { r = idx % rows_pad; o8 = idx / rows_pad; }
+    u64 w[8], q[8];
+    load8(o, r, o8 * 8, K, w);
+    to_digits(w, q);
+    int8_t* base = out + ((r >> 6) * nkb + (o8 >> 2)) * TILE_BYTES;
+    const int rr = (int)(r & 63), oc = (int)(o8 & 3);
+#pragma unroll
+    for (int d = 0; d < 8; ++d) *(u64*)(base + toff(d, rr, oc)) = q[d];
+}
+
+// A segment of a product: a = c0 P0 + c1 P1 (k contiguous, row stride lda), B digit tiles.
+struct Seg2 {
+    const u64* p0;
+    const u64* p1;
+    int c0, c1;
+    const int8_t* bt;
+};
+struct Prod2 {
+    Seg2 seg[2];
+    int nseg;
+    OutView C;
+};
+struct L2Args {
+    Prod2 prod[3];
+    int64_t M, N, K, lda;
+    int64_t nkb;                 // k-blocks per segment
+    int64_t kcb;                 // k-blocks per split (segments concatenated)
+    int nprod, splits, tn;
+    int atomic;
+    View D;
+};
+
+// 8 raw words of one A row starting at rp (k0 .. k0+7 of the row; 0 beyond K).
+// FAST: every row is 16-byte aligned and K is a multiple of the k-block.
+template <bool FAST>
+__device__ __forceinline__ void raw8(const u64* rp, int64_t k0, int64_t K, u64 x[8]) {
+    if (FAST) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const ulonglong2 v = *(const ulonglong2*)(rp + 2 * h);
+            x[2 * h] = v.x;
+            x[2 * h + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = k0 + i < K ? rp[i] : 0;
+    }
+}
+
+template <bool TWO, bool FAST>
+__global__ __launch_bounds__(NT, 2) void k_lgemm2(L2Args a) {
+    __shared__ __attribute__((aligned(16))) int8_t As[2][TILE_BYTES];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[2][TILE_BYTES];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    // Workgroup ids are dealt round-robin to the 8 XCDs; renumber so that every XCD works
+    // through a contiguous run of tiles (the column tiles and products of one row tile
+    // share their A rows in that XCD's L2).
+    const int nwg = gridDim.x, L = blockIdx.x, q8 = nwg / 8;
+    const int T = L < 8 * q8 ? (L % 8) * q8 + L / 8 : L;
+    const int tni = T % a.tn;
+    int rest = T / a.tn;
+    const int prod = rest % a.nprod;
+    rest /= a.nprod;
+    const int split = rest % a.splits;
+    const int tmi = rest / a.splits;
+    const Prod2& P = a.prod[prod];
+    const int nkb = (int)a.nkb;
+    const int gbeg = split * (int)a.kcb;
+    const int gend = min(P.nseg * nkb, gbeg + (int)a.kcb);
+    const int64_t r0a = (int64_t)tmi * TM, r0b = (int64_t)tni * TN;
+    const int ra = t >> 2, oa = t & 3;
+    // rows past M load row M-1: they only feed accumulator rows that are never stored
+    const int64_t aoff = min(r0a + ra, a.M - 1) * a.lda + 8 * oa;
+    // per-segment pointers, held in registers for the whole loop
+    const u64* pa0[2];
+    const u64* pa1[2];
+    const int8_t* pb[2];
+    int c0[2], c1[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const Seg2& S = P.seg[s < P.nseg ? s : 0];
+        pa0[s] = S.p0 + aoff;
+        pa1[s] = S.c1 ? S.p1 + aoff : S.p0 + aoff;
+        c0[s] = S.c0;
+        c1[s] = S.c1;
+        pb[s] = S.bt + (int64_t)tni * nkb * TILE_BYTES + t * 16;
+    }
+    const int wy = w >> 1, wx = w & 1, r = lane & 31, hf = lane >> 5;
+    const int arow = wy * 32 + r, brow = wx * 32 + r;
+    const int aread = arow * KB + ((hf ^ swz(arow)) << 4), bread = brow * KB + ((hf ^ swz(brow)) << 4);
+    const int astore = ra * KB + ((((oa >> 1) ^ swz(ra))) << 4) + ((oa & 1) << 3);
+
+    v16i acc[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) acc[s] = v16i{0};
+
+    u64 x0[8], x1[8];
+    v4i bx[4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x1[i] = 0;
+    // global loads of k-block g into registers (no arithmetic, so nothing waits on them)
+    auto issue = [&](int g) {
+        const int s = g >= nkb ? 1 : 0;
+        const int kb = g - s * nkb;
+        const int64_t k0 = (int64_t)kb * KB;
+        raw8<FAST>((s ? pa0[1] : pa0[0]) + k0, k0 + 8 * oa, a.K, x0);
+        if (TWO && (s ? c1[1] : c1[0])) raw8<FAST>((s ? pa1[1] : pa1[0]) + k0, k0 + 8 * oa, a.K, x1);
+        const int8_t* bp = (s ? pb[1] : pb[0]) + (int64_t)kb * TILE_BYTES;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) bx[h] = *(const v4i*)(bp + h * 4096);
+    };
+    // combine, convert and store k-block g into LDS buffer `buf`
+    auto commit = [&](int g, int buf) {
+        const int s = g >= nkb ? 1 : 0;
+        const int cc0 = s ? c0[1] : c0[0], cc1 = s ? c1[1] : c1[0];
+        u64 wv[8], q[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            u64 v = cc0 < 0 ? 0 - x0[i] : x0[i];
+            if (TWO && cc1) v += cc1 > 0 ? x1[i] : 0 - x1[i];
+            wv[i] = v;
+        }
+        to_digits(wv, q);
+#pragma unroll
+        for (int d = 0; d < 8; ++d) *(u64*)(As[buf] + d * PLANE + astore) = q[d];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) *(v4i*)(Bs[buf] + t * 16 + h * 4096) = bx[h];
+    };
+
+    if (gbeg < gend) {
+        issue(gbeg);
+        commit(gbeg, 0);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int g = gbeg; g < gend; ++g) {
+        const bool more = g + 1 < gend;
+        issue(more ? g + 1 : g);          // the last prefetch re-reads a valid block
+        v4i B[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) B[d] = *(const v4i*)(Bs[buf] + d * PLANE + bread);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const v4i A = *(const v4i*)(As[buf] + i * PLANE + aread);
+#pragma unroll
+            for (int s = i; s < 8; ++s)
+                acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[s - i], acc[s], 0, 0, 0);
+        }
+        if (more) commit(g + 1, buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    const int64_t n = r0b + wx * 32 + (lane & 31);
+    if (n >= a.N) return;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int64_t m = r0a + wy * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (m >= a.M) continue;
+        u64 val = 0;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) val += ((u64)(int64_t)acc[s][v]) << (8 * s);
+        u64* p = P.C.p + m * P.C.s0 + n * P.C.s1;
+        if (a.atomic) {
+            atomicAdd((unsigned long long*)p, (unsigned long long)val);
+        } else {
+            if (a.D.p) val += a.D.p[m * a.D.s0 + n * a.D.s1];
+            *p = val;
+        }
+    }
+}
+
 inline int64_t rup(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 Opnd opnd(const View& v, int64_t b, bool transpose, int64_t rows, int c0 = 1) {
@@ -350,6 +546,70 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         a.kchunk = kchunk;
         a.splits = (int)splits;
         if (nprod * splits > 65535) return hipErrorInvalidValue;
+        // B pre-converted to digit tiles when every A segment is k-contiguous with one row
+        // stride and B is re-read by at least two row tiles
+        bool two = tm >= 2 && g.ws_alloc;
+        for (int p = 0; p < nprod && two; ++p)
+            for (int sg = 0; sg < a.prod[p].nseg; ++sg)
+                two = two && a.prod[p].a[sg].s_k == 1 && a.prod[p].a[sg].s_r == a.prod[0].a[0].s_r;
+        if (two) {
+            const int64_t nkb = Kp / KB, rows_pad = tn * TN;
+            const size_t tbytes = (size_t)tn * nkb * TILE_BYTES;
+            L2Args l{};
+            l.M = g.M; l.N = g.N; l.K = g.K; l.lda = a.prod[0].a[0].s_r;
+            l.nkb = nkb; l.kcb = kchunk / KB; l.nprod = nprod; l.splits = (int)splits; l.tn = (int)tn;
+            l.atomic = a.atomic; l.D = a.D;
+            // distinct B operands (the party form uses four: B1+B2, Bm, B1, Bm-B2)
+            Opnd done[6];
+            const int8_t* buf[6];
+            int ndone = 0;
+            bool combo_a = false;
+            for (int p = 0; p < nprod; ++p) {
+                const Prod& P = a.prod[p];
+                Prod2& Q = l.prod[p];
+                Q.nseg = P.nseg;
+                Q.C = P.C;
+                for (int sg = 0; sg < P.nseg; ++sg) {
+                    const Opnd& ao = P.a[sg];
+                    const Opnd& bo = P.b[sg];
+                    Q.seg[sg] = Seg2{ao.p[0], ao.p[1], ao.c[0], ao.c[1], nullptr};
+                    combo_a = combo_a || ao.c[1] != 0;
+                    int hit = -1;
+                    for (int i = 0; i < ndone; ++i)
+                        if (done[i].p[0] == bo.p[0] && done[i].c[0] == bo.c[0] && done[i].p[1] == bo.p[1] &&
+                            done[i].c[1] == bo.c[1] && done[i].s_r == bo.s_r && done[i].s_k == bo.s_k)
+                            hit = i;
+                    if (hit < 0) {
+                        int8_t* tb = (int8_t*)g.ws_alloc(g.ws_self, tbytes);
+                        if (!tb) return hipErrorOutOfMemory;
+                        const int64_t threads = rows_pad * nkb * 4;
+                        hipLaunchKernelGGL(k_to_tiles, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, bo,
+                                           g.K, nkb, rows_pad, tb);
+                        done[ndone] = bo;
+                        buf[ndone] = tb;
+                        hit = ndone++;
+                    }
+                    Q.seg[sg].bt = buf[hit];
+                }
+            }
+            const int64_t nwg = tn * tm * nprod * splits;
+            if (nwg > 0x7FFFFFFF || nkb * 2 > 0x7FFFFFFF) return hipErrorInvalidValue;
+            // fast loads: K a multiple of the k-block and every A row 16-byte aligned
+            bool fast = g.K % KB == 0 && l.lda % 2 == 0;
+            for (int p = 0; p < nprod; ++p)
+                for (int sg = 0; sg < l.prod[p].nseg; ++sg) {
+                    const Seg2& S = l.prod[p].seg[sg];
+                    fast = fast && ((uintptr_t)S.p0 & 15) == 0 && (!S.c1 || ((uintptr_t)S.p1 & 15) == 0);
+                }
+            const dim3 gr((unsigned)nwg), bl(NT);
+            if (combo_a && fast) hipLaunchKernelGGL((k_lgemm2<true, true>), gr, bl, 0, st, l);
+            else if (combo_a) hipLaunchKernelGGL((k_lgemm2<true, false>), gr, bl, 0, st, l);
+            else if (fast) hipLaunchKernelGGL((k_lgemm2<false, true>), gr, bl, 0, st, l);
+            else hipLaunchKernelGGL((k_lgemm2<false, false>), gr, bl, 0, st, l);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            continue;
+        }
         const dim3 grid((unsigned)tn, (unsigned)tm, (unsigned)(nprod * splits));
         const bool ak = a.prod[0].a[0].s_k == 1, bk = a.prod[0].b[0].s_k == 1;
         if (ak && bk) hipLaunchKernelGGL((k_lgemm<true, true>), grid, dim3(NT), 0, st, a);

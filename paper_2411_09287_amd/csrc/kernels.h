@@ -106,7 +106,7 @@ void launch_trunc_w(int64_t lo, int64_t T, int t, const u64* B1, const u64* B2, 
 void launch_sym_init(int64_t T, int t, const u64* B1, const u64* B2, u64* alpha, u64* gamma, hipStream_t s);
 // Coefficients of h(0) (3^j monomials zeta^u) and h(x) (3^(j+1) monomials x^e zeta^u,
 // index u + 3^j e) for every gate: c0 [3^j][G], cx [3^(j+1)][G].
-void launch_sym_coeffs(int j, int64_t G, const u64* alpha, const u64* gamma, u64* c0, u64* cx, hipStream_t s);
+void launch_sym_coeffs(int j, int64_t G, const u64* alpha, const u64* gamma, u64* cx, hipStream_t s);
 // Fold at the next point: coefficients for j+1 folds.
 void launch_sym_fold(int j, int64_t G, const u64* alpha, const u64* gamma, u64* alpha_n, u64* gamma_n,
                      hipStream_t s);

@@ -651,18 +651,32 @@ __device__ __forceinline__ int pow3(int j) {
     return r;
 }
 
-// One thread per gate.  For monomial u (base-3 digits u_b in {0,1,2}), the pairs (S, T) with
-// S_b + T_b = u_b: digit 0 -> (0,0), 2 -> (1,1), 1 -> (0,1) or (1,0).
-__global__ void k_sym_coeffs(int j, int64_t G, const u64* alpha, const u64* gamma, u64* c0, u64* cx) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= G) return;
+// Coefficients of x^e zeta^u (e in 0..2, u < 3^j) of sum_i f_i(x) g_i(x) for every gate.
+// For monomial u (base-3 digits u_b in {0,1,2}) the subset pairs (S, T) with S_b + T_b = u_b
+// are: digit 0 -> (0,0), 2 -> (1,1), 1 -> (0,1) or (1,0).  A block stages SYM_GB gates in LDS
+// (rows padded to 129 words so that lanes on different gates use different banks) and one
+// thread handles one (gate, u); with f = a0 + x (a1 - a0), g = b0 + x (b1 - b0) the three
+// coefficients are a0 b0, a1 b1 - a0 b0 - da db and da db.
+constexpr int SYM_GB = 16, SYM_ROW = 129;
+__global__ __launch_bounds__(256) void k_sym_coeffs(int j, int64_t G, const u64* alpha, const u64* gamma,
+                                                     u64* cx) {
+    __shared__ u64 sa[SYM_GB * SYM_ROW], sg[SYM_GB * SYM_ROW];
+    const int64_t g0 = (int64_t)blockIdx.x * SYM_GB;
+    const int ng = (int)min((int64_t)SYM_GB, G - g0);
+    for (int t = threadIdx.x; t < ng * 64; t += blockDim.x) {
+        const int gg = t >> 6, k = t & 63;
+        sa[gg * SYM_ROW + k] = alpha[(g0 + gg) * 64 + k];
+        sg[gg * SYM_ROW + k] = gamma[(g0 + gg) * 64 + k];
+    }
+    __syncthreads();
     const int L = 1 << j;                  // coefficients per element
     const int npairs = 32 >> j;            // pairs per gate
     const int nu = pow3(j);
-    const u64* A = alpha + g * 64;
-    const u64* C = gamma + g * 64;
-    for (int u = 0; u < nu; ++u) {
-        // digits of u, positions of the 1-digits
+    for (int item = threadIdx.x; item < SYM_GB * nu; item += blockDim.x) {
+        const int gg = item % SYM_GB, u = item / SYM_GB;
+        if (gg >= ng) continue;
+        const u64* A = sa + gg * SYM_ROW;
+        const u64* C = sg + gg * SYM_ROW;
         int base = 0, ones[8], nones = 0;
         int uu = u;
         for (int b = 0; b < j; ++b) {
@@ -671,7 +685,7 @@ __global__ void k_sym_coeffs(int j, int64_t G, const u64* alpha, const u64* gamm
             if (d == 2) base |= 1 << b;
             if (d == 1) ones[nones++] = b;
         }
-        u64 h0 = 0, e0 = 0, e1 = 0, e2 = 0;
+        u64 e0 = 0, e2 = 0, s1 = 0;
         for (int m = 0; m < (1 << nones); ++m) {
             int S = base, T = base;
             for (int q = 0; q < nones; ++q) {
@@ -681,16 +695,14 @@ __global__ void k_sym_coeffs(int j, int64_t G, const u64* alpha, const u64* gamm
             for (int i = 0; i < npairs; ++i) {
                 const u64 a0 = A[(2 * i) * L + S], a1 = A[(2 * i + 1) * L + S];
                 const u64 b0 = C[(2 * i) * L + T], b1 = C[(2 * i + 1) * L + T];
-                const u64 da = a1 - a0, db = b1 - b0;
-                h0 += a0 * b0;                 // f(0) g(0)
-                e0 += a0 * b0;                 // f(x) g(x) = (a0 + x da)(b0 + x db)
-                e1 += a0 * db + da * b0;
-                e2 += da * db;
+                e0 += a0 * b0;
+                s1 += a1 * b1;
+                e2 += (a1 - a0) * (b1 - b0);
             }
         }
-        c0[(int64_t)u * G + g] = h0;
+        const int64_t g = g0 + gg;
         cx[(int64_t)u * G + g] = e0;
-        cx[(int64_t)(u + nu) * G + g] = e1;
+        cx[(int64_t)(u + nu) * G + g] = s1 - e0 - e2;
         cx[(int64_t)(u + 2 * nu) * G + g] = e2;
     }
 }
@@ -886,9 +898,9 @@ void launch_sym_init(int64_t T, int t, const u64* B1, const u64* B2, u64* alpha,
     if (T <= 0) return;
     hipLaunchKernelGGL(k_sym_init, dim3(nblocks(2 * T * 64, TPB)), dim3(TPB), 0, s, T, t, B1, B2, alpha, gamma);
 }
-void launch_sym_coeffs(int j, int64_t G, const u64* alpha, const u64* gamma, u64* c0, u64* cx, hipStream_t s) {
+void launch_sym_coeffs(int j, int64_t G, const u64* alpha, const u64* gamma, u64* cx, hipStream_t s) {
     if (G <= 0) return;
-    hipLaunchKernelGGL(k_sym_coeffs, dim3(nblocks(G, 64)), dim3(64), 0, s, j, G, alpha, gamma, c0, cx);
+    hipLaunchKernelGGL(k_sym_coeffs, dim3(nblocks(G, SYM_GB)), dim3(256), 0, s, j, G, alpha, gamma, cx);
 }
 void launch_sym_fold(int j, int64_t G, const u64* alpha, const u64* gamma, u64* an, u64* gn, hipStream_t s) {
     if (G <= 0) return;

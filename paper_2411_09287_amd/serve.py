@@ -20,6 +20,14 @@ from . import mpc3, workloads
 from .network import Network
 
 MODEL_NAMES = ("mlp", "lenet", "vgg")
+
+
+def m_bucket(M):
+    """Rows rounded up to a power of two: the autotuner keeps one choice per bucket."""
+    b = 1
+    while b < M:
+        b *= 2
+    return b
 DEFAULT_CAP = {"mlp": 512, "lenet": 256, "vgg": 64}
 
 
@@ -62,17 +70,21 @@ class Server:
         self.nets = {m: Network(ctx, m) for m in models}
         self.cap = dict(DEFAULT_CAP if cap is None else cap)
 
-    def tune(self, reqs, reps=3):
-        """Autotune the kernel family for every layer shape the packs will produce."""
+    def tune(self, reqs, reps=3, log=None):
+        """Autotune the kernel family for every layer shape the packs will produce.  The
+        library keeps one choice per (M rounded up to a power of two, K, N), so each such
+        bucket is timed once, at its largest M."""
         shapes = set()
         for p in packs_of(reqs, self.cap):
             b = sum(r[2] for r in p)
-            shapes.update(self.nets[p[0][1]].shapes(b))
-        for M, K, N in sorted(shapes):
+            shapes.update((m_bucket(M), K, N) for M, K, N in self.nets[p[0][1]].shapes(b))
+        for i, (M, K, N) in enumerate(sorted(shapes)):
             self.ctx.autotune(M, K, N, reps)
+            if log and (i + 1) % 16 == 0:
+                log(f"tuned {i + 1}/{len(shapes)} shapes")
         return len(shapes)
 
-    def run(self, reqs, pack=True):
+    def run(self, reqs, pack=True, log=None):
         """Serve all requests; returns per-request latency (s), makespan (s) and images."""
         ctx = self.ctx
         inputs = {r[0]: request_input(r[1], r[2], r[0], ctx.device) for r in reqs}
@@ -80,7 +92,10 @@ class Server:
         t0 = time.perf_counter()
         lat = {}
         ok_all = True
-        for p in packs_of(reqs, self.cap, pack):
+        packs = packs_of(reqs, self.cap, pack)
+        for n_done, p in enumerate(packs):
+            if log and n_done % 64 == 0:
+                log(f"pack {n_done}/{len(packs)}")
             net = self.nets[p[0][1]]
             x = torch.cat([inputs[r[0]] for r in p]) if len(p) > 1 else inputs[p[0][0]]
             out = net.forward(x)
@@ -95,7 +110,7 @@ class Server:
         makespan = time.perf_counter() - t0
         images = sum(r[2] for r in reqs)
         return {"ok": ok_all, "latency": lat, "makespan": makespan, "images": images,
-                "packs": len(packs_of(reqs, self.cap, pack))}
+                "packs": len(packs)}
 
 
 def summary(res):
