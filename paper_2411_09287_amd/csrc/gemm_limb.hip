@@ -280,11 +280,11 @@ __global__ void k_to_tiles(Opnd o, int64_t K, int64_t nkb, int64_t rows_pad, int
     for (int d = 0; d < 8; ++d) *(u64*)(base + toff(d, rr, oc)) = q[d];
 }
 
-// A segment of a product: a = c0 P0 + c1 P1 (k contiguous, row stride lda), B digit tiles.
+// A segment of a product: one A plane (k contiguous, row stride lda) and the digit tiles of
+// its B operand.  Every sign and sum of the party form sits on the B side, so A is read
+// as stored.
 struct Seg2 {
-    const u64* p0;
-    const u64* p1;
-    int c0, c1;
+    const u64* p;
     const int8_t* bt;
 };
 struct Prod2 {
@@ -295,15 +295,17 @@ struct Prod2 {
 struct L2Args {
     Prod2 prod[3];
     int64_t M, N, K, lda;
-    int64_t nkb;                 // k-blocks per segment
-    int64_t kcb;                 // k-blocks per split (segments concatenated)
+    int nkb;                     // k-blocks per segment
+    int kcb;                     // k-blocks per split (segments concatenated)
     int nprod, splits, tn;
     int atomic;
     View D;
 };
 
-// 8 raw words of one A row starting at rp (k0 .. k0+7 of the row; 0 beyond K).
-// FAST: every row is 16-byte aligned and K is a multiple of the k-block.
+// 8 raw words of one A row: rp points at k = k0 (the thread's octet); words at k >= K read
+// as 0.  FAST: every row is 16-byte aligned and K is a multiple of the k-block, so the
+// octet is four 16-byte loads.  Otherwise eight 8-byte loads of clamped (valid)
+// addresses, masked afterwards, with no branches.
 template <bool FAST>
 __device__ __forceinline__ void raw8(const u64* rp, int64_t k0, int64_t K, u64 x[8]) {
     if (FAST) {
@@ -314,12 +316,28 @@ __device__ __forceinline__ void raw8(const u64* rp, int64_t k0, int64_t K, u64 x
             x[2 * h + 1] = v.y;
         }
     } else {
+        const int64_t last = K - 1 - k0;      // index of the row's last word relative to rp
 #pragma unroll
-        for (int i = 0; i < 8; ++i) x[i] = k0 + i < K ? rp[i] : 0;
+        for (int i = 0; i < 8; ++i) {
+            const u64 v = rp[min((int64_t)i, last)];
+            x[i] = i <= last ? v : 0;
+        }
     }
 }
 
-template <bool TWO, bool FAST>
+// s_waitcnt with only the vector-memory counter constrained (vmcnt <= n)
+template <int n>
+__device__ __forceinline__ void wait_vm() {
+    __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// Per k-block g:
+//   - the B digit tile of block g+1 is copied from global memory straight into the other
+//     LDS buffer (global_load_lds, 16 bytes a lane, no registers);
+//   - the A words of block g+2 are loaded into registers;
+//   - the A words of block g+1 (loaded one block earlier) are converted to digits while
+//     the 36 MFMAs of block g run, and stored to the other LDS buffer after them.
+template <bool FAST>
 __global__ __launch_bounds__(NT, 2) void k_lgemm2(L2Args a) {
     __shared__ __attribute__((aligned(16))) int8_t As[2][TILE_BYTES];
     __shared__ __attribute__((aligned(16))) int8_t Bs[2][TILE_BYTES];
@@ -336,92 +354,166 @@ __global__ __launch_bounds__(NT, 2) void k_lgemm2(L2Args a) {
     const int split = rest % a.splits;
     const int tmi = rest / a.splits;
     const Prod2& P = a.prod[prod];
-    const int nkb = (int)a.nkb;
-    const int gbeg = split * (int)a.kcb;
-    const int gend = min(P.nseg * nkb, gbeg + (int)a.kcb);
+    const int nkb = a.nkb;
+    const int gbeg = split * a.kcb;
+    const int gend = min(P.nseg * nkb, gbeg + a.kcb);
     const int64_t r0a = (int64_t)tmi * TM, r0b = (int64_t)tni * TN;
     const int ra = t >> 2, oa = t & 3;
     // rows past M load row M-1: they only feed accumulator rows that are never stored
     const int64_t aoff = min(r0a + ra, a.M - 1) * a.lda + 8 * oa;
-    // per-segment pointers, held in registers for the whole loop
-    const u64* pa0[2];
-    const u64* pa1[2];
+    const u64* pa[2];
     const int8_t* pb[2];
-    int c0[2], c1[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const Seg2& S = P.seg[s < P.nseg ? s : 0];
-        pa0[s] = S.p0 + aoff;
-        pa1[s] = S.c1 ? S.p1 + aoff : S.p0 + aoff;
-        c0[s] = S.c0;
-        c1[s] = S.c1;
+        pa[s] = S.p + aoff;
         pb[s] = S.bt + (int64_t)tni * nkb * TILE_BYTES + t * 16;
     }
     const int wy = w >> 1, wx = w & 1, r = lane & 31, hf = lane >> 5;
     const int arow = wy * 32 + r, brow = wx * 32 + r;
     const int aread = arow * KB + ((hf ^ swz(arow)) << 4), bread = brow * KB + ((hf ^ swz(brow)) << 4);
-    const int astore = ra * KB + ((((oa >> 1) ^ swz(ra))) << 4) + ((oa & 1) << 3);
+    const int astore = ra * KB + (((oa >> 1) ^ swz(ra)) << 4) + ((oa & 1) << 3);
 
     v16i acc[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) acc[s] = v16i{0};
 
-    u64 x0[8], x1[8];
-    v4i bx[4];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) x1[i] = 0;
-    // global loads of k-block g into registers (no arithmetic, so nothing waits on them)
-    auto issue = [&](int g) {
+    auto loadA = [&](int g, u64 x[8]) {
         const int s = g >= nkb ? 1 : 0;
-        const int kb = g - s * nkb;
-        const int64_t k0 = (int64_t)kb * KB;
-        raw8<FAST>((s ? pa0[1] : pa0[0]) + k0, k0 + 8 * oa, a.K, x0);
-        if (TWO && (s ? c1[1] : c1[0])) raw8<FAST>((s ? pa1[1] : pa1[0]) + k0, k0 + 8 * oa, a.K, x1);
-        const int8_t* bp = (s ? pb[1] : pb[0]) + (int64_t)kb * TILE_BYTES;
+        const int64_t k0 = (int64_t)(g - s * nkb) * KB;
+        raw8<FAST>((s ? pa[1] : pa[0]) + k0, k0 + 8 * oa, a.K, x);
+    };
+    auto dmaB = [&](int g, int buf) {
+        const int s = g >= nkb ? 1 : 0;
+        const int8_t* bp = (s ? pb[1] : pb[0]) + (int64_t)(g - s * nkb) * TILE_BYTES;
+        int8_t* bl = Bs[buf] + w * 1024;
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+            __builtin_amdgcn_global_load_lds((const void*)(bp + h * 4096), (void*)(bl + h * 4096), 16, 0, 0);
+    };
+    auto storeA = [&](const u64 q[8], int buf) {
+#pragma unroll
+        for (int d = 0; d < 8; ++d) *(u64*)(As[buf] + d * PLANE + astore) = q[d];
+    };
+
+    u64 xa[8], xb[8];
+    v4i bx[4];
+    auto loadB = [&](int g) {
+        const int s = g >= nkb ? 1 : 0;
+        const int8_t* bp = (s ? pb[1] : pb[0]) + (int64_t)(g - s * nkb) * TILE_BYTES;
 #pragma unroll
         for (int h = 0; h < 4; ++h) bx[h] = *(const v4i*)(bp + h * 4096);
     };
-    // combine, convert and store k-block g into LDS buffer `buf`
-    auto commit = [&](int g, int buf) {
-        const int s = g >= nkb ? 1 : 0;
-        const int cc0 = s ? c0[1] : c0[0], cc1 = s ? c1[1] : c1[0];
-        u64 wv[8], q[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            u64 v = cc0 < 0 ? 0 - x0[i] : x0[i];
-            if (TWO && cc1) v += cc1 > 0 ? x1[i] : 0 - x1[i];
-            wv[i] = v;
-        }
-        to_digits(wv, q);
-#pragma unroll
-        for (int d = 0; d < 8; ++d) *(u64*)(As[buf] + d * PLANE + astore) = q[d];
+    auto storeB = [&](int buf) {
 #pragma unroll
         for (int h = 0; h < 4; ++h) *(v4i*)(Bs[buf] + t * 16 + h * 4096) = bx[h];
     };
-
-    if (gbeg < gend) {
-        issue(gbeg);
-        commit(gbeg, 0);
-    }
-    __syncthreads();
     int buf = 0;
-    for (int g = gbeg; g < gend; ++g) {
-        const bool more = g + 1 < gend;
-        issue(more ? g + 1 : g);          // the last prefetch re-reads a valid block
-        v4i B[8];
-#pragma unroll
-        for (int d = 0; d < 8; ++d) B[d] = *(const v4i*)(Bs[buf] + d * PLANE + bread);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const v4i A = *(const v4i*)(As[buf] + i * PLANE + aread);
-#pragma unroll
-            for (int s = i; s < 8; ++s)
-                acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[s - i], acc[s], 0, 0, 0);
+    if (!FAST) {
+        // ragged K or unaligned rows: B copied straight into LDS, A converted after the MFMAs
+        if (gbeg < gend) {
+            dmaB(gbeg, 0);
+            loadA(gbeg, xa);
+            u64 q[8];
+            to_digits(xa, q);
+            storeA(q, 0);
         }
-        if (more) commit(g + 1, buf ^ 1);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        buf ^= 1;
+        for (int g = gbeg; g < gend; ++g) {
+            v4i B[8], A[8];
+#pragma unroll
+            for (int d = 0; d < 8; ++d) B[d] = *(const v4i*)(Bs[buf] + d * PLANE + bread);
+#pragma unroll
+            for (int d = 0; d < 8; ++d) A[d] = *(const v4i*)(As[buf] + d * PLANE + aread);
+            const int g1 = min(g + 1, gend - 1);      // past the end: re-reads a valid block
+            dmaB(g1, buf ^ 1);
+            loadA(g1, xa);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+#pragma unroll
+                for (int s = i; s < 8; ++s)
+                    acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i], B[s - i], acc[s], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            u64 q[8];
+            to_digits(xa, q);
+            storeA(q, buf ^ 1);
+            wait_vm<0>();
+            __syncthreads();
+            buf ^= 1;
+        }
+    } else {
+        // Block g+1's B tile goes through registers, block g+2's A words are loaded, and
+        // block g+1's A words (loaded one block earlier) are converted in pieces placed
+        // between the MFMA rows of block g, so the vector ALU works while the matrix
+        // cores do.  Only plain loads are in flight, so every wait is exact.
+        if (gbeg < gend) {
+            loadB(gbeg);
+            loadA(gbeg, xb);
+            u64 q[8];
+            to_digits(xb, q);
+            storeA(q, 0);
+            storeB(0);
+            loadA(min(gbeg + 1, gend - 1), xa);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        auto body = [&](int g, const u64 xc[8], u64 xn[8]) {
+            loadB(min(g + 1, gend - 1));              // past the end: re-reads valid blocks
+            loadA(min(g + 2, gend - 1), xn);
+            __builtin_amdgcn_sched_barrier(0);
+            v4i B[8];
+#pragma unroll
+            for (int d = 0; d < 8; ++d) B[d] = *(const v4i*)(Bs[buf] + d * PLANE + bread);
+            u32 lo[8], hi[8], tq[4][4];
+            v4i A = *(const v4i*)(As[buf] + aread);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                // next row's A fragment is read while this row's MFMAs run
+                const v4i An = i < 7 ? *(const v4i*)(As[buf] + (i + 1) * PLANE + aread) : A;
+#pragma unroll
+                for (int s = i; s < 8; ++s)
+                    acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[s - i], acc[s], 0, 0, 0);
+                A = An;
+                // (the empty asm pins each piece here: without it the compiler sinks the
+                // arithmetic to its use after the last MFMA)
+                if (i == 0) {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const u64 v = (xc[j] + OFF) ^ OFF;
+                        lo[j] = (u32)v;
+                        hi[j] = (u32)(v >> 32);
+                        asm volatile("" : "+v"(lo[j]), "+v"(hi[j]));
+                    }
+                } else if (i <= 4) {
+                    const int b = i - 1;          // 0: lo 0-3, 1: lo 4-7, 2: hi 0-3, 3: hi 4-7
+                    const u32* src = (b < 2 ? lo : hi) + 4 * (b & 1);
+                    bt4(src[0], src[1], src[2], src[3], tq[b][0], tq[b][1], tq[b][2], tq[b][3]);
+                    asm volatile("" : "+v"(tq[b][0]), "+v"(tq[b][1]), "+v"(tq[b][2]), "+v"(tq[b][3]));
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            u64 q[8];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                q[d] = (u64)tq[0][d] | ((u64)tq[1][d] << 32);
+                q[4 + d] = (u64)tq[2][d] | ((u64)tq[3][d] << 32);
+            }
+            storeA(q, buf ^ 1);
+            storeB(buf ^ 1);
+            wait_vm<4>();           // B of block g+1 is stored; A of block g+2 may fly on
+            __syncthreads();
+            buf ^= 1;
+        };
+        int g = gbeg;
+        for (; g + 1 < gend; g += 2) {
+            body(g, xa, xb);
+            body(g + 1, xb, xa);
+        }
+        if (g < gend) body(g, xa, xb);
     }
+
     const int64_t n = r0b + wx * 32 + (lane & 31);
     if (n >= a.N) return;
 #pragma unroll
@@ -546,66 +638,62 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         a.kchunk = kchunk;
         a.splits = (int)splits;
         if (nprod * splits > 65535) return hipErrorInvalidValue;
-        // B pre-converted to digit tiles when every A segment is k-contiguous with one row
+        // B pre-converted to digit tiles when every A plane is k-contiguous with one row
         // stride and B is re-read by at least two row tiles
+        const int na = g.party ? 3 : 1;
         bool two = tm >= 2 && g.ws_alloc;
-        for (int p = 0; p < nprod && two; ++p)
-            for (int sg = 0; sg < a.prod[p].nseg; ++sg)
-                two = two && a.prod[p].a[sg].s_k == 1 && a.prod[p].a[sg].s_r == a.prod[0].a[0].s_r;
+        for (int p = 0; p < na && two; ++p) two = g.A[p].s1 == 1 && g.A[p].s0 == g.A[0].s0;
         if (two) {
             const int64_t nkb = Kp / KB, rows_pad = tn * TN;
+            if (nkb * 2 > 0x7FFFFFFF || tn * tm * nprod * splits > 0x7FFFFFFF) return hipErrorInvalidValue;
             const size_t tbytes = (size_t)tn * nkb * TILE_BYTES;
+            auto tiles = [&](const Opnd& bo) -> const int8_t* {
+                int8_t* tb = (int8_t*)g.ws_alloc(g.ws_self, tbytes);
+                if (!tb) return nullptr;
+                const int64_t threads = rows_pad * nkb * 4;
+                hipLaunchKernelGGL(k_to_tiles, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, bo, g.K,
+                                   nkb, rows_pad, tb);
+                return tb;
+            };
             L2Args l{};
-            l.M = g.M; l.N = g.N; l.K = g.K; l.lda = a.prod[0].a[0].s_r;
-            l.nkb = nkb; l.kcb = kchunk / KB; l.nprod = nprod; l.splits = (int)splits; l.tn = (int)tn;
+            l.M = g.M; l.N = g.N; l.K = g.K; l.lda = g.A[0].s0;
+            l.nkb = (int)nkb; l.kcb = (int)(kchunk / KB); l.nprod = nprod; l.splits = (int)splits; l.tn = (int)tn;
             l.atomic = a.atomic; l.D = a.D;
-            // distinct B operands (the party form uses four: B1+B2, Bm, B1, Bm-B2)
-            Opnd done[6];
-            const int8_t* buf[6];
-            int ndone = 0;
-            bool combo_a = false;
-            for (int p = 0; p < nprod; ++p) {
-                const Prod& P = a.prod[p];
-                Prod2& Q = l.prod[p];
-                Q.nseg = P.nseg;
-                Q.C = P.C;
-                for (int sg = 0; sg < P.nseg; ++sg) {
-                    const Opnd& ao = P.a[sg];
-                    const Opnd& bo = P.b[sg];
-                    Q.seg[sg] = Seg2{ao.p[0], ao.p[1], ao.c[0], ao.c[1], nullptr};
-                    combo_a = combo_a || ao.c[1] != 0;
-                    int hit = -1;
-                    for (int i = 0; i < ndone; ++i)
-                        if (done[i].p[0] == bo.p[0] && done[i].c[0] == bo.c[0] && done[i].p[1] == bo.p[1] &&
-                            done[i].c[1] == bo.c[1] && done[i].s_r == bo.s_r && done[i].s_k == bo.s_k)
-                            hit = i;
-                    if (hit < 0) {
-                        int8_t* tb = (int8_t*)g.ws_alloc(g.ws_self, tbytes);
-                        if (!tb) return hipErrorOutOfMemory;
-                        const int64_t threads = rows_pad * nkb * 4;
-                        hipLaunchKernelGGL(k_to_tiles, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, bo,
-                                           g.K, nkb, rows_pad, tb);
-                        done[ndone] = bo;
-                        buf[ndone] = tb;
-                        hit = ndone++;
-                    }
-                    Q.seg[sg].bt = buf[hit];
+            const u64* Ap[3];
+            for (int p = 0; p < na; ++p) Ap[p] = g.A[p].p + b * g.A[p].sb;
+            if (!g.party) {
+                const int8_t* t0 = tiles(opnd(g.B[0], b, true, g.N));
+                if (!t0) return hipErrorOutOfMemory;
+                l.prod[0].nseg = 1;
+                l.prod[0].seg[0] = Seg2{Ap[0], t0};
+                l.prod[0].C = a.prod[0].C;
+            } else {
+                // planes 0, 1, 2 = m, [r]_1, [r]_2; signs and sums on the B side:
+                //   C0 = A1 (B1 + B2) + A2 (B1 + B2)
+                //   C1 = A1 Bm + Am B1
+                //   C2 = Am (Bm - B2) + A2 (-Bm)
+                const View* B = g.B;
+                const int8_t* s12 = tiles(combo(B, b, true, g.N, 1, 1, 2, 1));
+                const int8_t* bm = tiles(combo(B, b, true, g.N, 0, 1, -1, 0));
+                const int8_t* b1 = tiles(combo(B, b, true, g.N, 1, 1, -1, 0));
+                const int8_t* bm2 = tiles(combo(B, b, true, g.N, 0, 1, 2, -1));
+                const int8_t* nbm = tiles(combo(B, b, true, g.N, 0, -1, -1, 0));
+                if (!s12 || !bm || !b1 || !bm2 || !nbm) return hipErrorOutOfMemory;
+                const Seg2 segs[3][2] = {{{Ap[1], s12}, {Ap[2], s12}},
+                                         {{Ap[1], bm}, {Ap[0], b1}},
+                                         {{Ap[0], bm2}, {Ap[2], nbm}}};
+                for (int p = 0; p < 3; ++p) {
+                    l.prod[p].nseg = 2;
+                    l.prod[p].seg[0] = segs[p][0];
+                    l.prod[p].seg[1] = segs[p][1];
+                    l.prod[p].C = a.prod[p].C;
                 }
             }
-            const int64_t nwg = tn * tm * nprod * splits;
-            if (nwg > 0x7FFFFFFF || nkb * 2 > 0x7FFFFFFF) return hipErrorInvalidValue;
-            // fast loads: K a multiple of the k-block and every A row 16-byte aligned
             bool fast = g.K % KB == 0 && l.lda % 2 == 0;
-            for (int p = 0; p < nprod; ++p)
-                for (int sg = 0; sg < l.prod[p].nseg; ++sg) {
-                    const Seg2& S = l.prod[p].seg[sg];
-                    fast = fast && ((uintptr_t)S.p0 & 15) == 0 && (!S.c1 || ((uintptr_t)S.p1 & 15) == 0);
-                }
-            const dim3 gr((unsigned)nwg), bl(NT);
-            if (combo_a && fast) hipLaunchKernelGGL((k_lgemm2<true, true>), gr, bl, 0, st, l);
-            else if (combo_a) hipLaunchKernelGGL((k_lgemm2<true, false>), gr, bl, 0, st, l);
-            else if (fast) hipLaunchKernelGGL((k_lgemm2<false, true>), gr, bl, 0, st, l);
-            else hipLaunchKernelGGL((k_lgemm2<false, false>), gr, bl, 0, st, l);
+            for (int p = 0; p < na; ++p) fast = fast && ((uintptr_t)Ap[p] & 15) == 0;
+            const dim3 gr((unsigned)(tn * tm * nprod * splits)), bl(NT);
+            if (fast) hipLaunchKernelGGL(k_lgemm2<true>, gr, bl, 0, st, l);
+            else hipLaunchKernelGGL(k_lgemm2<false>, gr, bl, 0, st, l);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             continue;
