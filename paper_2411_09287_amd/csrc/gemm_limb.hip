@@ -297,7 +297,9 @@ struct L2Args {
     int64_t M, N, K, lda;
     int nkb;                     // k-blocks per segment
     int kcb;                     // k-blocks per split (segments concatenated)
-    int nprod, splits, tn;
+    int nprod, splits;
+    int tn;                      // column groups of the grid (NS tiles of 64 each)
+    int tn64;                    // 64-column tiles of B
     int atomic;
     View D;
 };
@@ -325,23 +327,35 @@ __device__ __forceinline__ void raw8(const u64* rp, int64_t k0, int64_t K, u64 x
     }
 }
 
+// the 8 digit bytes of an octet of k (q[d]: digit d) at byte offset off of each plane
+__device__ __forceinline__ void storeA8(int8_t* tile, int off, const u64 q[8]) {
+#pragma unroll
+    for (int d = 0; d < 8; ++d) *(u64*)(tile + d * PLANE + off) = q[d];
+}
+
 // s_waitcnt with only the vector-memory counter constrained (vmcnt <= n)
 template <int n>
 __device__ __forceinline__ void wait_vm() {
     __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 }
 
-// Per k-block g:
-//   - the B digit tile of block g+1 is copied from global memory straight into the other
-//     LDS buffer (global_load_lds, 16 bytes a lane, no registers);
-//   - the A words of block g+2 are loaded into registers;
-//   - the A words of block g+1 (loaded one block earlier) are converted to digits while
-//     the 36 MFMAs of block g run, and stored to the other LDS buffer after them.
-template <bool FAST>
-__global__ __launch_bounds__(NT, 2) void k_lgemm2(L2Args a) {
+// One workgroup computes a 64 x (64 NS) tile of one product with 4 NS waves (32 x 32 each).
+// Per k-block g (FAST: K a multiple of 32, aligned rows):
+//   - the B digit tiles of block g+1 are loaded into registers and the A words of block
+//     g+2 are loaded, all before the MFMAs of block g;
+//   - block g+1's A words (loaded one block earlier) are converted to digits in pieces
+//     placed between the MFMA rows of block g, so the vector ALU works while the matrix
+//     cores do, and stored to the other LDS buffer afterwards.  Only plain loads are in
+//     flight, so every wait the compiler places is exact.
+// Otherwise (NS = 1): B tiles are copied straight into LDS (global_load_lds) and A words are
+// converted after the MFMAs.
+template <bool FAST, int NS>
+__global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
+    constexpr int WPT = 8 / NS;                  // A words converted per thread and k-block
     __shared__ __attribute__((aligned(16))) int8_t As[2][TILE_BYTES];
-    __shared__ __attribute__((aligned(16))) int8_t Bs[2][TILE_BYTES];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[2][NS * TILE_BYTES];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int sub = w >> 2, wl = w & 3;
     // Workgroup ids are dealt round-robin to the 8 XCDs; renumber so that every XCD works
     // through a contiguous run of tiles (the column tiles and products of one row tile
     // share their A rows in that XCD's L2).
@@ -357,66 +371,121 @@ __global__ __launch_bounds__(NT, 2) void k_lgemm2(L2Args a) {
     const int nkb = a.nkb;
     const int gbeg = split * a.kcb;
     const int gend = min(P.nseg * nkb, gbeg + a.kcb);
-    const int64_t r0a = (int64_t)tmi * TM, r0b = (int64_t)tni * TN;
-    const int ra = t >> 2, oa = t & 3;
+    const int tcol = tni * NS + sub;             // this wave group's 64-column tile
+    const int64_t r0a = (int64_t)tmi * TM, r0b = (int64_t)tcol * TN;
+    // A loader: row ra, WPT consecutive words at k = part * WPT
+    const int ra = NS == 1 ? t >> 2 : t >> 3, part = NS == 1 ? t & 3 : t & 7;
     // rows past M load row M-1: they only feed accumulator rows that are never stored
-    const int64_t aoff = min(r0a + ra, a.M - 1) * a.lda + 8 * oa;
+    const int64_t aoff = min(r0a + ra, a.M - 1) * a.lda + part * WPT;
+    const int tt = t & (NT - 1);
+    // column tiles past the last one read the last one: their outputs are never stored
+    const int64_t boff = (int64_t)min(tcol, a.tn64 - 1) * nkb * TILE_BYTES + tt * 16;
     const u64* pa[2];
     const int8_t* pb[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const Seg2& S = P.seg[s < P.nseg ? s : 0];
         pa[s] = S.p + aoff;
-        pb[s] = S.bt + (int64_t)tni * nkb * TILE_BYTES + t * 16;
+        pb[s] = S.bt + boff;
     }
-    const int wy = w >> 1, wx = w & 1, r = lane & 31, hf = lane >> 5;
+    const int wy = wl >> 1, wx = wl & 1, r = lane & 31, hf = lane >> 5;
     const int arow = wy * 32 + r, brow = wx * 32 + r;
-    const int aread = arow * KB + ((hf ^ swz(arow)) << 4), bread = brow * KB + ((hf ^ swz(brow)) << 4);
-    const int astore = ra * KB + (((oa >> 1) ^ swz(ra)) << 4) + ((oa & 1) << 3);
+    const int aread = arow * KB + ((hf ^ swz(arow)) << 4);
+    const int bread = sub * TILE_BYTES + brow * KB + ((hf ^ swz(brow)) << 4);
+    // A digits of this thread's words: NS = 1 an 8-byte octet, NS = 2 a 4-byte quad
+    const int astore = NS == 1 ? ra * KB + (((part >> 1) ^ swz(ra)) << 4) + ((part & 1) << 3)
+                               : ra * KB + (((part >> 2) ^ swz(ra)) << 4) + ((part & 3) << 2);
 
     v16i acc[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) acc[s] = v16i{0};
 
-    auto loadA = [&](int g, u64 x[8]) {
+    auto seg_of = [&](int g, int& kb) {
         const int s = g >= nkb ? 1 : 0;
-        const int64_t k0 = (int64_t)(g - s * nkb) * KB;
-        raw8<FAST>((s ? pa[1] : pa[0]) + k0, k0 + 8 * oa, a.K, x);
+        kb = g - s * nkb;
+        return s;
+    };
+    auto loadA = [&](int g, u64 x[WPT]) {
+        int kb;
+        const int s = seg_of(g, kb);
+        const int64_t k0 = (int64_t)kb * KB;
+        const u64* rp = (s ? pa[1] : pa[0]) + k0;
+        if (FAST) {
+#pragma unroll
+            for (int h = 0; h < WPT / 2; ++h) {
+                const ulonglong2 v = *(const ulonglong2*)(rp + 2 * h);
+                x[2 * h] = v.x;
+                x[2 * h + 1] = v.y;
+            }
+        } else {
+            raw8<false>(rp, k0 + part * WPT, a.K, x);
+        }
     };
     auto dmaB = [&](int g, int buf) {
-        const int s = g >= nkb ? 1 : 0;
-        const int8_t* bp = (s ? pb[1] : pb[0]) + (int64_t)(g - s * nkb) * TILE_BYTES;
+        int kb;
+        const int s = seg_of(g, kb);
+        const int8_t* bp = (s ? pb[1] : pb[0]) + (int64_t)kb * TILE_BYTES;
         int8_t* bl = Bs[buf] + w * 1024;
 #pragma unroll
         for (int h = 0; h < 4; ++h)
             __builtin_amdgcn_global_load_lds((const void*)(bp + h * 4096), (void*)(bl + h * 4096), 16, 0, 0);
     };
-    auto storeA = [&](const u64 q[8], int buf) {
-#pragma unroll
-        for (int d = 0; d < 8; ++d) *(u64*)(As[buf] + d * PLANE + astore) = q[d];
-    };
-
-    u64 xa[8], xb[8];
     v4i bx[4];
     auto loadB = [&](int g) {
-        const int s = g >= nkb ? 1 : 0;
-        const int8_t* bp = (s ? pb[1] : pb[0]) + (int64_t)(g - s * nkb) * TILE_BYTES;
+        int kb;
+        const int s = seg_of(g, kb);
+        const int8_t* bp = (s ? pb[1] : pb[0]) + (int64_t)kb * TILE_BYTES;
 #pragma unroll
         for (int h = 0; h < 4; ++h) bx[h] = *(const v4i*)(bp + h * 4096);
     };
     auto storeB = [&](int buf) {
 #pragma unroll
-        for (int h = 0; h < 4; ++h) *(v4i*)(Bs[buf] + t * 16 + h * 4096) = bx[h];
+        for (int h = 0; h < 4; ++h) *(v4i*)(Bs[buf] + sub * TILE_BYTES + tt * 16 + h * 4096) = bx[h];
     };
+    // digits of WPT words as 4 x (WPT/2) transposed dwords tq[b]: b = 0, 1 the low words'
+    // digits 0..3 (WPT = 8: words 0..3, 4..7), then the high digits 4..7
+    auto store_digits = [&](const u32 tq[4][4], int buf) {
+        if (WPT == 8) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                *(u64*)(As[buf] + d * PLANE + astore) = (u64)tq[0][d] | ((u64)tq[1][d] << 32);
+                *(u64*)(As[buf] + (4 + d) * PLANE + astore) = (u64)tq[2][d] | ((u64)tq[3][d] << 32);
+            }
+        } else {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                *(u32*)(As[buf] + d * PLANE + astore) = tq[0][d];
+                *(u32*)(As[buf] + (4 + d) * PLANE + astore) = tq[1][d];
+            }
+        }
+    };
+    // conversion piece c of WPT words (c = 0: balanced bytes; c >= 1: one 4x4 transpose)
+    auto piece = [&](int c, const u64 xc[WPT], u32 lo[WPT], u32 hi[WPT], u32 tq[4][4]) {
+        if (c == 0) {
+#pragma unroll
+            for (int j = 0; j < WPT; ++j) {
+                const u64 v = (xc[j] + OFF) ^ OFF;
+                lo[j] = (u32)v;
+                hi[j] = (u32)(v >> 32);
+                asm volatile("" : "+v"(lo[j]), "+v"(hi[j]));
+            }
+        } else if (c <= WPT / 2) {
+            const int b = c - 1;
+            const u32* src = WPT == 8 ? (b < 2 ? lo : hi) + 4 * (b & 1) : (b == 0 ? lo : hi);
+            bt4(src[0], src[1], src[2], src[3], tq[b][0], tq[b][1], tq[b][2], tq[b][3]);
+            asm volatile("" : "+v"(tq[b][0]), "+v"(tq[b][1]), "+v"(tq[b][2]), "+v"(tq[b][3]));
+        }
+    };
+
+    u64 xa[WPT], xb[WPT];
     int buf = 0;
-    if (!FAST) {
-        // ragged K or unaligned rows: B copied straight into LDS, A converted after the MFMAs
+    if constexpr (!FAST) {
         if (gbeg < gend) {
             dmaB(gbeg, 0);
             loadA(gbeg, xa);
             u64 q[8];
             to_digits(xa, q);
-            storeA(q, 0);
+            storeA8(As[0], astore, q);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
@@ -438,71 +507,49 @@ __global__ __launch_bounds__(NT, 2) void k_lgemm2(L2Args a) {
             __builtin_amdgcn_sched_barrier(0);
             u64 q[8];
             to_digits(xa, q);
-            storeA(q, buf ^ 1);
+            storeA8(As[buf ^ 1], astore, q);
             wait_vm<0>();
             __syncthreads();
             buf ^= 1;
         }
     } else {
-        // Block g+1's B tile goes through registers, block g+2's A words are loaded, and
-        // block g+1's A words (loaded one block earlier) are converted in pieces placed
-        // between the MFMA rows of block g, so the vector ALU works while the matrix
-        // cores do.  Only plain loads are in flight, so every wait is exact.
         if (gbeg < gend) {
             loadB(gbeg);
             loadA(gbeg, xb);
-            u64 q[8];
-            to_digits(xb, q);
-            storeA(q, 0);
+            u32 lo[WPT], hi[WPT], tq[4][4];
+#pragma unroll
+            for (int c = 0; c <= WPT / 2; ++c) piece(c, xb, lo, hi, tq);
+            store_digits(tq, 0);
             storeB(0);
             loadA(min(gbeg + 1, gend - 1), xa);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        auto body = [&](int g, const u64 xc[8], u64 xn[8]) {
+        auto body = [&](int g, const u64 xc[WPT], u64 xn[WPT]) {
             loadB(min(g + 1, gend - 1));              // past the end: re-reads valid blocks
             loadA(min(g + 2, gend - 1), xn);
             __builtin_amdgcn_sched_barrier(0);
             v4i B[8];
 #pragma unroll
             for (int d = 0; d < 8; ++d) B[d] = *(const v4i*)(Bs[buf] + d * PLANE + bread);
-            u32 lo[8], hi[8], tq[4][4];
+            u32 lo[WPT], hi[WPT], tq[4][4];
             v4i A = *(const v4i*)(As[buf] + aread);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                // next row's A fragment is read while this row's MFMAs run
+                // the next row's A fragment is read while this row's MFMAs run
                 const v4i An = i < 7 ? *(const v4i*)(As[buf] + (i + 1) * PLANE + aread) : A;
 #pragma unroll
                 for (int s = i; s < 8; ++s)
                     acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[s - i], acc[s], 0, 0, 0);
                 A = An;
-                // (the empty asm pins each piece here: without it the compiler sinks the
-                // arithmetic to its use after the last MFMA)
-                if (i == 0) {
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const u64 v = (xc[j] + OFF) ^ OFF;
-                        lo[j] = (u32)v;
-                        hi[j] = (u32)(v >> 32);
-                        asm volatile("" : "+v"(lo[j]), "+v"(hi[j]));
-                    }
-                } else if (i <= 4) {
-                    const int b = i - 1;          // 0: lo 0-3, 1: lo 4-7, 2: hi 0-3, 3: hi 4-7
-                    const u32* src = (b < 2 ? lo : hi) + 4 * (b & 1);
-                    bt4(src[0], src[1], src[2], src[3], tq[b][0], tq[b][1], tq[b][2], tq[b][3]);
-                    asm volatile("" : "+v"(tq[b][0]), "+v"(tq[b][1]), "+v"(tq[b][2]), "+v"(tq[b][3]));
-                }
+                // (the empty asm in piece() pins each part here: without it the compiler
+                // sinks the arithmetic to its use after the last MFMA)
+                piece(i, xc, lo, hi, tq);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            u64 q[8];
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                q[d] = (u64)tq[0][d] | ((u64)tq[1][d] << 32);
-                q[4 + d] = (u64)tq[2][d] | ((u64)tq[3][d] << 32);
-            }
-            storeA(q, buf ^ 1);
+            store_digits(tq, buf ^ 1);
             storeB(buf ^ 1);
-            wait_vm<4>();           // B of block g+1 is stored; A of block g+2 may fly on
+            wait_vm<WPT / 2>();     // B of block g+1 is stored; A of block g+2 may fly on
             __syncthreads();
             buf ^= 1;
         };
@@ -657,7 +704,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             };
             L2Args l{};
             l.M = g.M; l.N = g.N; l.K = g.K; l.lda = g.A[0].s0;
-            l.nkb = (int)nkb; l.kcb = (int)(kchunk / KB); l.nprod = nprod; l.splits = (int)splits; l.tn = (int)tn;
+            l.nkb = (int)nkb; l.kcb = (int)(kchunk / KB); l.nprod = nprod; l.splits = (int)splits;
             l.atomic = a.atomic; l.D = a.D;
             const u64* Ap[3];
             for (int p = 0; p < na; ++p) Ap[p] = g.A[p].p + b * g.A[p].sb;
@@ -691,9 +738,15 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             }
             bool fast = g.K % KB == 0 && l.lda % 2 == 0;
             for (int p = 0; p < na; ++p) fast = fast && ((uintptr_t)Ap[p] & 15) == 0;
-            const dim3 gr((unsigned)(tn * tm * nprod * splits)), bl(NT);
-            if (fast) hipLaunchKernelGGL(k_lgemm2<true>, gr, bl, 0, st, l);
-            else hipLaunchKernelGGL(k_lgemm2<false>, gr, bl, 0, st, l);
+            // two 64-column tiles per workgroup (eight waves sharing one converted A tile)
+            // when the aligned path applies and N spans more than one tile
+            const int ns = fast && tn >= 2 ? 2 : 1;
+            l.tn64 = (int)tn;
+            l.tn = (int)((tn + ns - 1) / ns);
+            const dim3 gr((unsigned)(l.tn * tm * nprod * splits));
+            if (ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2>), gr, dim3(2 * NT), 0, st, l);
+            else if (fast) hipLaunchKernelGGL((k_lgemm2<true, 1>), gr, dim3(NT), 0, st, l);
+            else hipLaunchKernelGGL((k_lgemm2<false, 1>), gr, dim3(NT), 0, st, l);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             continue;
