@@ -130,7 +130,7 @@ int mpc3_set_variant(mpc3_ctx* ctx, int variant);
 int mpc3_autotune(mpc3_ctx* ctx, int64_t M, int64_t K, int64_t N, int reps, int* choice, double* ms_u64,
                   double* ms_limb);
 
-/* Truncations per Pi_BIVerify instance of the truncation gates (default 262144, at most
+/* Truncations per Pi_BIVerify instance of the truncation gates (default 524288, at most
  * 2^20; a chunk of T truncations holds about 20 KiB x T of workspace while verified). */
 int mpc3_set_chunk(mpc3_ctx* ctx, int64_t truncations_per_instance);
 

@@ -52,7 +52,7 @@ SITE_VER_H2_GAMMA2 = 7
 SITE_VER_DELTA_M1 = 8
 SITE_REC_R1 = 9
 
-DEFAULT_CHUNK = 1 << 18     # truncations per Pi_BIVerify instance of the truncation gates
+DEFAULT_CHUNK = 1 << 19     # truncations per Pi_BIVerify instance of the truncation gates
 
 
 class Aborted(Exception):

@@ -103,7 +103,7 @@ struct mpc3_ctx {
     hipStream_t stream = nullptr;
     int variant = MPC3_VARIANT_U64;
     int frac = 13;
-    int64_t chunk = 1 << 18;
+    int64_t chunk = 1 << 19;
     bool keep_msgs = false;
     bool aborted = false;
     uint32_t op = 0;
@@ -342,7 +342,8 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
         const Inj i_h0 = take_ver(c, MPC3_SITE_VER_H0_M1, v.inst, k);
         const Inj i_h2 = take_ver(c, MPC3_SITE_VER_H2_GAMMA2, v.inst, k);
         u64* F2 = c->sc->words(np * half * 64);
-        launch_at_x(XY, np, n, F2, s);         // f_i(x) = f_i(0) + x (f_i(1) - f_i(0))
+        u64* Dd = c->sc->words(np * half * 64);
+        launch_at_x_diff(XY, np, n, F2, Dd, s);   // D_i = f_i(1) - f_i(0), f_i(x) = f_i(0) + x D_i
         if (sparse) {
             polyevl_sparse(c, v, half, XY, 128, XY + n * 64, 128, P_VER_H0_R, P_VER_H0_GAMMA, sub, i_h0,
                            Inj{-1, 0}, h0, slot(v, MPC3_LOG_H0_M1, k), slot(v, MPC3_LOG_H0_M2, k),
@@ -371,8 +372,6 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
         // fold: row i <- f_i(0) + zeta (f_i(1) - f_i(0)) on every stored plane
         u64* Wz = c->sc->words(4096);
         launch_mulmat(zeta, 64, 1, Wz, s);
-        u64* Dd = c->sc->words(np * half * 64);
-        launch_sub_pairs(XY, np, n, Dd, s);
         u64* XYn = c->sc->words(np * half * 64);
         GemmArgs g = plain(half, 64, 64, view(Dd, 64, 1, half * 64), view(Wz, 64, 1, 0),
                            oview(XYn, 64, 1, half * 64), false, np);
@@ -514,8 +513,12 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
     hipStream_t s = c->cs;
     const mpc3_trunc_pair_t& p = it.pair;
     u64* r = challenge(c, v);
-    u64* pw = c->sc->words(2 * T * 64);
-    power_table(c, r, 2 * T, pw);                 // r^g for the 2T gates of the chunk
+    // Symbolic rounds sum over blocks of BK gates (half the largest power of two <= 2T, from
+    // 16 to 4096; any BK gives the same sums): the power table covers at least one block.
+    int64_t BK = 16;
+    while (BK * 4 <= 2 * T && BK < 4096) BK *= 2;
+    u64* pw = c->sc->words(std::max(2 * T, BK) * 64);
+    power_table(c, r, std::max(2 * T, BK), pw);   // r^g for the 2T gates of the chunk (and up to BK)
     const int64_t n0 = 128 * T;
     const int R = auto_rounds(n0, Rarg);
     const int64_t np = padded(n0, R);
@@ -542,15 +545,17 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
         return;
     }
     // Symbolic rounds: pairs stay inside a gate (64 elements) for six folds.  After j folds,
-    // element i of gate g is x = r^g sum_S alpha_S zeta^S, y = sum_S gamma_S zeta^S, so h(0) and
-    // h(x) are power-weighted sums over the gates of scalar coefficients per monomial.
+    // element i of gate g is x = r^g sum_S alpha_S zeta^S, y = sum_S gamma_S zeta^S, so h(0)
+    // and h(x) are power-weighted sums over the gates of scalar coefficients per monomial.
+    // The weighted sum over the G gates runs blocked: for blocks of BK gates,
+    //   sum_g c_g r^g = sum_b r^{b BK} (sum_{g' < BK} c_{b BK + g'} r^{g'}),
+    // an inner product with the first BK powers (3^(j+1) G / BK rows) and an outer one with
+    // the multiplication matrices of r^{b BK}.
     const int KS = std::min(R, 5);
     const int64_t G = 2 * T;
-    u64* al = c->sc->words(G * 64);
-    u64* ga = c->sc->words(G * 64);
-    u64* al2 = c->sc->words(G * 64);
-    u64* ga2 = c->sc->words(G * 64);
-    launch_sym_init(T, p.t, B1, B2, al, ga, s);
+    const int64_t nb = (G + BK - 1) / BK, ld = nb * BK;
+    u64* Tb = c->sc->words(nb * 4096);
+    launch_mulmat(pw, BK * 64, (int)nb, Tb, s);     // rows of r^{b BK}
     int maxnu = 1;
     for (int j = 0; j < KS; ++j) maxnu *= 3;
     u64* Z = c->sc->words(3 * maxnu * 64);          // zeta^u, u in {0,1,2}^j
@@ -566,11 +571,12 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
         const uint32_t sub = ((uint32_t)v.inst << 8) | (uint32_t)j;
         Scratch::Mark mk = c->sc->mark();
         // h(0) is the x^0 part of h(x): rows 0 .. nu-1 of the power-weighted coefficient sums
-        u64* cx = c->sc->words((int64_t)3 * nu * G);
-        launch_sym_coeffs(j, G, al, ga, cx, s);
+        u64* cx = c->sc->words((int64_t)3 * nu * ld);
+        launch_sym_coeffs(j, G, ld, p.t, B1, B2, cx, s);
+        u64* Cp = c->sc->words((int64_t)3 * nu * nb * 64);
+        run_gemm(c, plain(3 * nu * nb, 64, BK, view(cx, BK, 1), view(pw, 64, 1), oview(Cp, 64, 1), false));
         u64* PSX = c->sc->words(3 * nu * 64);
-        zero(c, PSX, (size_t)3 * nu * 512);
-        run_gemm(c, plain(3 * nu, 64, G, view(cx, G, 1), view(pw, 64, 1), oview(PSX, 64, 1), true));
+        run_gemm(c, plain(3 * nu, 64, nb * 64, view(Cp, nb * 64, 1), view(Tb, 64, 1), oview(PSX, 64, 1), false));
         const u64* PS = PSX;
         ck(hipMemcpyAsync(XZ, Z, (size_t)nu * 512, hipMemcpyDeviceToDevice, s));
         launch_xshift_rows(Z, nu, 1, XZ + nu * 64, s);
@@ -591,9 +597,6 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
                      slot(v, MPC3_LOG_H2_M2, j), slot(v, MPC3_LOG_H2_G2, j));
         c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
         u64* zeta = round_finish(c, v, sub, j, h0, h2, z);
-        launch_sym_fold(j, G, al, ga, al2, ga2, s);
-        std::swap(al, al2);
-        std::swap(ga, ga2);
         // tables for j + 1 folds
         launch_mulmat(zeta, 64, 1, Wz, s);
         ck(hipMemcpyAsync(Zn, Z, (size_t)nu * 512, hipMemcpyDeviceToDevice, s));
@@ -612,6 +615,9 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
     const int L = 1 << KS;
     const int64_t per = 64 / L, nel = G * per;
     const int64_t half = np >> KS;
+    u64* al = c->sc->words(G * 64);
+    u64* ga = c->sc->words(G * 64);
+    launch_sym_level(KS, G, p.t, B1, B2, al, ga, s);
     u64* XY = c->sc->words(2 * half * 64);
     zero(c, XY, (size_t)2 * half * 64 * 8);
     u64* Q = c->sc->words(nel * 64);

@@ -611,7 +611,6 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
     // Small products stay on the vector ALU, where the launch is cheaper.
     if ((double)g.M * (double)g.N * (double)g.K < (double)(1 << 22) || g.K == 0) return gemm_u64(g, st);
     const int64_t tm = rup(g.M, TM) / TM, tn = rup(g.N, TN) / TN;
-    if (tm > 65535) return hipErrorInvalidValue;
     const int64_t Kp = rup(g.K, KB);
     for (int b = 0; b < g.batch; ++b) {
         LArgs a{};
@@ -751,6 +750,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             if (e != hipSuccess) return e;
             continue;
         }
+        if (tm > 65535) return hipErrorInvalidValue;
         const dim3 grid((unsigned)tn, (unsigned)tm, (unsigned)(nprod * splits));
         const bool ak = a.prod[0].a[0].s_k == 1, bk = a.prod[0].b[0].s_k == 1;
         if (ak && bk) hipLaunchKernelGGL((k_lgemm<true, true>), grid, dim3(NT), 0, st, a);

@@ -3,6 +3,8 @@
 // Each product a*b mod 2^64 is split as a_lo*b_lo (a 64-bit multiply-add,
 // v_mad_u64_u32) plus 2^32 (a_lo*b_hi + a_hi*b_lo), whose low 32 bits are
 // accumulated separately and folded in once at the end.
+#include <algorithm>
+
 #include "gemm.h"
 
 namespace mpc3 {
@@ -211,8 +213,23 @@ hipError_t gemm_u64(const GemmArgs& g, hipStream_t stream) {
 }
 
 hipError_t gemm(const GemmArgs& g, int variant, hipStream_t stream) {
-    if (variant != 0) return gemm_limb(g, stream);
-    return gemm_u64(g, stream);
+    // the row tiles of both backends' two-dimensional grids stay below 65535: taller
+    // products run as row slices (A, C and the added D advance by whole rows)
+    const int64_t maxm = (int64_t)65535 * 64;
+    for (int64_t r0 = 0; r0 < g.M || r0 == 0; r0 += maxm) {
+        GemmArgs s = g;
+        s.M = std::min(maxm, g.M - r0);
+        if (r0) {
+            for (int p = 0; p < (g.party ? 3 : 1); ++p) {
+                s.A[p].p += r0 * g.A[p].s0;
+                s.C[p].p += r0 * g.C[p].s0;
+            }
+            if (s.Dadd.p) s.Dadd.p += r0 * g.Dadd.s0;
+        }
+        hipError_t e = variant != 0 ? gemm_limb(s, stream) : gemm_u64(s, stream);
+        if (e != hipSuccess || g.M <= 0) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace mpc3

@@ -62,10 +62,8 @@ struct PolyEvlArgs {
     int prefolded;         // C holds the three reduced sums (3*64 words) instead of 64x64 products
 };
 void launch_polyevl_finish(const PolyEvlArgs& a, hipStream_t s);
-// f2 = f0 + x (f1 - f0) for nc planes of n rows (rows 2i, 2i+1 -> row i).
-void launch_at_x(const u64* XY, int nc, int64_t n, u64* out, hipStream_t s);
-// D = row(2i+1) - row(2i) for nc planes.
-void launch_sub_pairs(const u64* XY, int nc, int64_t n, u64* D, hipStream_t s);
+// For nc planes of n rows (rows 2i, 2i+1 -> row i): D = f1 - f0 and F = f0 + x D.
+void launch_at_x_diff(const u64* XY, int nc, int64_t n, u64* F, u64* D, hipStream_t s);
 struct RoundArgs {
     Keys k;
     u32 op, sub;
@@ -102,14 +100,14 @@ void launch_trunc_w(int64_t lo, int64_t T, int t, const u64* B1, const u64* B2, 
 // Symbolic reduction rounds of truncation gates.  After j folds, element i of gate g is
 // x = r^g sum_S alpha[g][i][S] zeta^S and y = sum_S gamma[g][i][S] zeta^S (S a subset of
 // the j revealed points, bit b <-> point b+1); 64 coefficients per gate and side.
-// Initial coefficients (j = 0): alpha = gate weight * bit of B1, gamma = -bit of B2.
-void launch_sym_init(int64_t T, int t, const u64* B1, const u64* B2, u64* alpha, u64* gamma, hipStream_t s);
-// Coefficients of h(0) (3^j monomials zeta^u) and h(x) (3^(j+1) monomials x^e zeta^u,
-// index u + 3^j e) for every gate: c0 [3^j][G], cx [3^(j+1)][G].
-void launch_sym_coeffs(int j, int64_t G, const u64* alpha, const u64* gamma, u64* cx, hipStream_t s);
-// Fold at the next point: coefficients for j+1 folds.
-void launch_sym_fold(int j, int64_t G, const u64* alpha, const u64* gamma, u64* alpha_n, u64* gamma_n,
-                     hipStream_t s);
+// Initial coefficients (j = 0): alpha = gate weight * bit of B1, gamma = -bit of B2; level j
+// is computed from them directly (B1, B2: the chunk's T words each, G = 2T gates).
+// sym_coeffs: the 3 * 3^j power-weight rows of round j (cx row stride ld >= G, zero-padded).
+// sym_level: the level-j alpha and gamma (G x 64 words each).
+void launch_sym_coeffs(int j, int64_t G, int64_t ld, int t, const u64* B1, const u64* B2, u64* cx,
+                       hipStream_t s);
+void launch_sym_level(int j, int64_t G, int t, const u64* B1, const u64* B2, u64* alpha, u64* gamma,
+                      hipStream_t s);
 // rows out[i] = x^e * in[i] for e = 1, 2 (n rows of 64 words).
 void launch_xshift_rows(const u64* in, int64_t n, int e, u64* out, hipStream_t s);
 // out[i] = P[i / per] * Q[i] (ring products, one 64-lane group per row).

@@ -440,28 +440,22 @@ __device__ __forceinline__ u64 xmul_coeff(const u64* v, int k) {
     return r;
 }
 
-__global__ void k_at_x(const u64* XY, int64_t n, u64* out) {
-    // block: one (plane, pair i); 64 lanes = coefficients
+// One pass over the pairs of every plane c: D = f(1) - f(0) and F = f(0) + x D, the line
+// through (0, f(0)) and (1, f(1)) at the node x (block: one (plane, pair); lanes =
+// coefficients).
+__global__ void k_at_x_diff(const u64* XY, int64_t n, u64* F, u64* D) {
     const int k = threadIdx.x;
     const int64_t i = blockIdx.x;
     const int c = blockIdx.y;
     const u64* f0 = XY + ((int64_t)c * n + 2 * i) * 64;
     const u64* f1 = f0 + 64;
     __shared__ u64 dsh[64];
-    dsh[k] = f1[k] - f0[k];
+    const u64 a = f0[k], d = f1[k] - a;
+    dsh[k] = d;
     __syncthreads();
-    out[((int64_t)c * (n / 2) + i) * 64 + k] = f0[k] + xmul_coeff(dsh, k);
-}
-
-__global__ void k_sub_pairs(const u64* XY, int64_t n, u64* D) {
-    const int64_t half = n / 2;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // over half*64 words
-    const int c = blockIdx.y;
-    if (idx >= half * 64) return;
-    const int64_t i = idx >> 6;
-    const int k = (int)(idx & 63);
-    const u64* base = XY + (int64_t)c * n * 64;
-    D[(int64_t)c * half * 64 + idx] = base[(2 * i + 1) * 64 + k] - base[(2 * i) * 64 + k];
+    const int64_t o = ((int64_t)c * (n / 2) + i) * 64 + k;
+    D[o] = d;
+    F[o] = a + xmul_coeff(dsh, k);
 }
 
 // Ring product of per-wave operands: wave w multiplies a[w] by b[w] (64 lanes = coefficients).
@@ -634,15 +628,35 @@ __device__ __forceinline__ u64 gate_weight(int s, int j, int t) {
     return 2 * c;
 }
 
-__global__ void k_sym_init(int64_t T, int t, const u64* B1, const u64* B2, u64* alpha, u64* gamma) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;    // gate * 64 + bit
-    if (idx >= 2 * T * 64) return;
-    const int64_t g = idx >> 6;
-    const int j = (int)(idx & 63);
-    const int64_t q = g >> 1;
-    const int s = (int)(g & 1);
-    alpha[idx] = gate_weight(s, j, t) * ((B1[q] >> j) & 1);
-    gamma[idx] = 0 - ((B2[q] >> j) & 1);
+// The gates of the truncation chunk, written out per gate g = 2q + s (q the truncation in the
+// chunk, s = 0 the x-gate, 1 the z-gate): 64 x values alpha_k = w_s(k) bit_k(B1_q) and 64 y
+// values gamma_k = -bit_k(B2_q).  After j symbolic folds, element i of a gate is
+// sum_S alpha_{i,S} zeta^S over the subsets S of the j folded points, with
+//     alpha_{i,S} = sum_{m subset of S} (-1)^{|S \ m|} alpha_{i 2^j + m}
+// (each fold keeps f(0) as the coefficient of a new point's absence and f(1) - f(0) as that
+// of its presence; zeta itself does not enter).  sym_stage writes these level-j values for
+// `ng` gates into LDS rows of SYM_ROW words: the gate values, then j in-place
+// difference passes over the low j bits of the element index.
+constexpr int SYM_GB = 16, SYM_ROW = 129;
+__device__ void sym_stage(int j, int64_t g0, int ng, int t, const u64* B1, const u64* B2, u64* sa, u64* sg) {
+    for (int e = threadIdx.x; e < ng * 64; e += blockDim.x) {
+        const int gg = e >> 6, k = e & 63;
+        const int64_t g = g0 + gg;
+        const int64_t q = g >> 1;
+        sa[gg * SYM_ROW + k] = gate_weight((int)(g & 1), k, t) * ((B1[q] >> k) & 1);
+        sg[gg * SYM_ROW + k] = 0 - ((B2[q] >> k) & 1);
+    }
+    for (int b = 0; b < j; ++b) {
+        __syncthreads();
+        // every word whose index has bit b set subtracts its partner without it
+        for (int e = threadIdx.x; e < ng * 32; e += blockDim.x) {
+            const int gg = e >> 5, h = e & 31;
+            const int k = ((h >> b) << (b + 1)) | (1 << b) | (h & ((1 << b) - 1));
+            sa[gg * SYM_ROW + k] -= sa[gg * SYM_ROW + (k ^ (1 << b))];
+            sg[gg * SYM_ROW + k] -= sg[gg * SYM_ROW + (k ^ (1 << b))];
+        }
+    }
+    __syncthreads();
 }
 
 __device__ __forceinline__ int pow3(int j) {
@@ -651,30 +665,31 @@ __device__ __forceinline__ int pow3(int j) {
     return r;
 }
 
-// Coefficients of x^e zeta^u (e in 0..2, u < 3^j) of sum_i f_i(x) g_i(x) for every gate.
+// Coefficients of x^e zeta^u (e in 0..2, u < 3^j) of sum_i f_i(x) g_i(x) for every gate,
+// row (u + 3^j e) of cx with row stride ld (columns G .. ld-1 are written as 0).
 // For monomial u (base-3 digits u_b in {0,1,2}) the subset pairs (S, T) with S_b + T_b = u_b
-// are: digit 0 -> (0,0), 2 -> (1,1), 1 -> (0,1) or (1,0).  A block stages SYM_GB gates in LDS
-// (rows padded to 129 words so that lanes on different gates use different banks) and one
-// thread handles one (gate, u); with f = a0 + x (a1 - a0), g = b0 + x (b1 - b0) the three
-// coefficients are a0 b0, a1 b1 - a0 b0 - da db and da db.
-constexpr int SYM_GB = 16, SYM_ROW = 129;
-__global__ __launch_bounds__(256) void k_sym_coeffs(int j, int64_t G, const u64* alpha, const u64* gamma,
-                                                     u64* cx) {
+// are: digit 0 -> (0,0), 2 -> (1,1), 1 -> (0,1) or (1,0).  One thread handles one
+// (gate, u); with f = a0 + x (a1 - a0), g = b0 + x (b1 - b0) the three coefficients are
+// a0 b0, a1 b1 - a0 b0 - da db and da db.
+__global__ __launch_bounds__(256) void k_sym_coeffs(int j, int64_t G, int64_t ld, int t, const u64* B1,
+                                                     const u64* B2, u64* cx) {
     __shared__ u64 sa[SYM_GB * SYM_ROW], sg[SYM_GB * SYM_ROW];
     const int64_t g0 = (int64_t)blockIdx.x * SYM_GB;
-    const int ng = (int)min((int64_t)SYM_GB, G - g0);
-    for (int t = threadIdx.x; t < ng * 64; t += blockDim.x) {
-        const int gg = t >> 6, k = t & 63;
-        sa[gg * SYM_ROW + k] = alpha[(g0 + gg) * 64 + k];
-        sg[gg * SYM_ROW + k] = gamma[(g0 + gg) * 64 + k];
-    }
-    __syncthreads();
+    const int ng = (int)max((int64_t)0, min((int64_t)SYM_GB, G - g0));
+    sym_stage(j, g0, ng, t, B1, B2, sa, sg);
     const int L = 1 << j;                  // coefficients per element
     const int npairs = 32 >> j;            // pairs per gate
     const int nu = pow3(j);
     for (int item = threadIdx.x; item < SYM_GB * nu; item += blockDim.x) {
         const int gg = item % SYM_GB, u = item / SYM_GB;
-        if (gg >= ng) continue;
+        const int64_t g = g0 + gg;
+        if (g >= ld) continue;
+        if (gg >= ng) {                    // padding columns
+            cx[(int64_t)u * ld + g] = 0;
+            cx[(int64_t)(u + nu) * ld + g] = 0;
+            cx[(int64_t)(u + 2 * nu) * ld + g] = 0;
+            continue;
+        }
         const u64* A = sa + gg * SYM_ROW;
         const u64* C = sg + gg * SYM_ROW;
         int base = 0, ones[8], nones = 0;
@@ -700,34 +715,24 @@ __global__ __launch_bounds__(256) void k_sym_coeffs(int j, int64_t G, const u64*
                 e2 += (a1 - a0) * (b1 - b0);
             }
         }
-        const int64_t g = g0 + gg;
-        cx[(int64_t)u * G + g] = e0;
-        cx[(int64_t)(u + nu) * G + g] = s1 - e0 - e2;
-        cx[(int64_t)(u + 2 * nu) * G + g] = e2;
+        cx[(int64_t)u * ld + g] = e0;
+        cx[(int64_t)(u + nu) * ld + g] = s1 - e0 - e2;
+        cx[(int64_t)(u + 2 * nu) * ld + g] = e2;
     }
 }
 
-// thread per (gate, new element i, new subset S)
-__global__ void k_sym_fold(int j, int64_t G, const u64* alpha, const u64* gamma, u64* an, u64* gn) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= G * 64) return;
-    const int64_t g = idx >> 6;
-    const int r = (int)(idx & 63);
-    const int L = 1 << j, L2 = 2 * L;
-    const int i = r / L2, S = r % L2;
-    const u64* A = alpha + g * 64;
-    const u64* C = gamma + g * 64;
-    u64 va, vc;
-    if (S < L) {              // the point's bit clear: coefficient of f_i(0)
-        va = A[(2 * i) * L + S];
-        vc = C[(2 * i) * L + S];
-    } else {                  // bit set: f_i(1) - f_i(0)
-        const int S0 = S - L;
-        va = A[(2 * i + 1) * L + S0] - A[(2 * i) * L + S0];
-        vc = C[(2 * i + 1) * L + S0] - C[(2 * i) * L + S0];
+// The level-j values themselves (G x 64 words each, element-major as in LDS).
+__global__ __launch_bounds__(256) void k_sym_level(int j, int64_t G, int t, const u64* B1, const u64* B2,
+                                                    u64* alpha, u64* gamma) {
+    __shared__ u64 sa[SYM_GB * SYM_ROW], sg[SYM_GB * SYM_ROW];
+    const int64_t g0 = (int64_t)blockIdx.x * SYM_GB;
+    const int ng = (int)min((int64_t)SYM_GB, G - g0);
+    sym_stage(j, g0, ng, t, B1, B2, sa, sg);
+    for (int e = threadIdx.x; e < ng * 64; e += blockDim.x) {
+        const int gg = e >> 6, k = e & 63;
+        alpha[(g0 + gg) * 64 + k] = sa[gg * SYM_ROW + k];
+        gamma[(g0 + gg) * 64 + k] = sg[gg * SYM_ROW + k];
     }
-    an[idx] = va;
-    gn[idx] = vc;
 }
 
 __global__ void k_xshift_rows(const u64* in, int64_t n, int e, u64* out) {
@@ -848,13 +853,9 @@ void launch_fold_plain(const u64* C, int nb, u64* out, hipStream_t s) {
 void launch_polyevl_finish(const PolyEvlArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_polyevl_finish, dim3(1), dim3(256), 0, s, a);
 }
-void launch_at_x(const u64* XY, int nc, int64_t n, u64* out, hipStream_t s) {
+void launch_at_x_diff(const u64* XY, int nc, int64_t n, u64* F, u64* D, hipStream_t s) {
     if (n < 2) return;
-    hipLaunchKernelGGL(k_at_x, dim3((unsigned)(n / 2), nc), dim3(64), 0, s, XY, n, out);
-}
-void launch_sub_pairs(const u64* XY, int nc, int64_t n, u64* D, hipStream_t s) {
-    if (n < 2) return;
-    hipLaunchKernelGGL(k_sub_pairs, dim3(nblocks(n / 2 * 64, TPB), nc), dim3(TPB), 0, s, XY, n, D);
+    hipLaunchKernelGGL(k_at_x_diff, dim3((unsigned)(n / 2), nc), dim3(64), 0, s, XY, n, F, D);
 }
 void launch_round_finish(const RoundArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_round_finish, dim3(1), dim3(256), 0, s, a);
@@ -894,17 +895,15 @@ void launch_trunc_w(int64_t lo, int64_t T, int t, const u64* B1, const u64* B2, 
     hipLaunchKernelGGL(k_trunc_w, dim3(nblocks(T, TPB)), dim3(TPB), 0, s, lo, T, t, B1, B2, rxm, rx1, rx2, rzm, rz1,
                        rz2, w3);
 }
-void launch_sym_init(int64_t T, int t, const u64* B1, const u64* B2, u64* alpha, u64* gamma, hipStream_t s) {
-    if (T <= 0) return;
-    hipLaunchKernelGGL(k_sym_init, dim3(nblocks(2 * T * 64, TPB)), dim3(TPB), 0, s, T, t, B1, B2, alpha, gamma);
+void launch_sym_coeffs(int j, int64_t G, int64_t ld, int t, const u64* B1, const u64* B2, u64* cx,
+                       hipStream_t s) {
+    if (ld <= 0) return;
+    hipLaunchKernelGGL(k_sym_coeffs, dim3(nblocks(ld, SYM_GB)), dim3(256), 0, s, j, G, ld, t, B1, B2, cx);
 }
-void launch_sym_coeffs(int j, int64_t G, const u64* alpha, const u64* gamma, u64* cx, hipStream_t s) {
+void launch_sym_level(int j, int64_t G, int t, const u64* B1, const u64* B2, u64* alpha, u64* gamma,
+                      hipStream_t s) {
     if (G <= 0) return;
-    hipLaunchKernelGGL(k_sym_coeffs, dim3(nblocks(G, SYM_GB)), dim3(256), 0, s, j, G, alpha, gamma, cx);
-}
-void launch_sym_fold(int j, int64_t G, const u64* alpha, const u64* gamma, u64* an, u64* gn, hipStream_t s) {
-    if (G <= 0) return;
-    hipLaunchKernelGGL(k_sym_fold, dim3(nblocks(G * 64, TPB)), dim3(TPB), 0, s, j, G, alpha, gamma, an, gn);
+    hipLaunchKernelGGL(k_sym_level, dim3(nblocks(G, SYM_GB)), dim3(256), 0, s, j, G, t, B1, B2, alpha, gamma);
 }
 void launch_xshift_rows(const u64* in, int64_t n, int e, u64* out, hipStream_t s) {
     if (n <= 0) return;

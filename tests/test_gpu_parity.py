@@ -143,6 +143,19 @@ def test_verify_transcript_parity(variant, shape, R):
     assert np.array_equal(bg, np.array(o.comm, dtype=np.uint64)) and rg == o.rounds
 
 
+@pytest.mark.parametrize("variant", [0, 1])
+def test_truncation_gate_rounds_blocked_parity(variant):
+    """Chunks of 12 and 6 truncations (24 and 12 gates): the symbolic rounds' power-weighted
+    sums run in blocks of 16 gates (two blocks, then one zero-padded block), all five
+    symbolic rounds and the materialised rounds after them."""
+    g = np.random.default_rng(77)
+    o, c = pair_of(variant, chunk=12)
+    To, Tg = _pipeline(o, c, g, 5, 7, 6)
+    assert o.verify() and c.verify()
+    _compare_transcripts(o, c)
+    assert np.array_equal(mpc3.from_words(c.reconstruct(Tg)).reshape(-1), o.reconstruct(To).reshape(-1))
+
+
 SITES = [mpc3.SITE_INNER_GAMMA2, mpc3.SITE_INNER_M1, mpc3.SITE_TRUNC_GAMMA2, mpc3.SITE_TRUNC_M1,
          mpc3.SITE_MULT_GAMMA2, mpc3.SITE_VER_H0_M1, mpc3.SITE_VER_H2_GAMMA2, mpc3.SITE_VER_DELTA_M1]
 
