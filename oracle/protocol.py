@@ -468,40 +468,63 @@ class Ctx:
         return r
 
     # -- building the Galois-ring instance for each kind of pending triple ----
-    def instance_inner_compressed(self, X, W, Z, r):
-        """Pi_BIVerify of M*N inner products, compressed with the separable challenge."""
-        gr = self.gr
-        M, K = X.m.shape
-        N = W.m.shape[1]
-        sigma = gr.powers(r, N)                    # r^n
-        rho = gr.powers(gr.pow(r, N), M)           # (r^N)^m, so r^{mN+n} = rho_m sigma_n
-        U = Share(*[Xc.T @ rho for Xc in X.comps()])          # U_k = sum_m rho_m X[m,k]
-        V = Share(*[Wc @ sigma for Wc in W.comps()])          # V_k = sum_n sigma_n W[k,n]
-        z = Share(*[gr.dot(sigma, Zc.T @ rho) for Zc in Z.comps()])   # sum rho_m sigma_n Z[m,n]
-        return U, V, z
+    @staticmethod
+    def _inner_offsets(items):
+        """Gate offsets o_l of a batch of Pi_Inner products: gate (m, n) of product l is
+        i = o_l + n M_l + m (column-major inside a product, products in call order)."""
+        offs, o = [], 0
+        for X, W, Z in items:
+            offs.append(o)
+            o += X.m.shape[0] * W.m.shape[1]
+        return offs
 
-    def instance_inner_literal(self, X, W, Z, r):
-        """Pi_BIVerify as printed: lift, weight gate g = m*N + n by r^g, consolidate to M*N*K."""
+    def instance_inner_compressed(self, items, r):
+        """One Pi_BIVerify instance for a batch of Pi_Inner products, gate i weighted by r^i
+        on the x side.  With i = o_l + n M_l + m the weight factors as
+        r^{o_l} * r^m * (r^{M_l})^n, so product l contributes the K_l pairs
+            x_k = r^{o_l} sum_m r^m X[m,k],   y_k = sum_n (r^{M_l})^n W[k,n]
+        and z = sum_l r^{o_l} sum_{m,n} r^m (r^{M_l})^n Z[m,n]."""
         gr = self.gr
-        M, K = X.m.shape
-        N = W.m.shape[1]
-        pw = gr.powers(r, M * N)
-        xs, ys = [], []
-        for c in range(3):
-            Xc, Wc = X.comps()[c], W.comps()[c]
-            xe = np.zeros((M * N * K, self.d), dtype=U64)
-            ye = np.zeros((M * N * K, self.d), dtype=U64)
-            for m in range(M):
+        offs = self._inner_offsets(items)
+        xs, ys = [[], [], []], [[], [], []]
+        zs = [np.zeros(self.d, dtype=U64) for _ in range(3)]
+        for (X, W, Z), o in zip(items, offs):
+            M, K = X.m.shape
+            N = W.m.shape[1]
+            rho = gr.powers(r, M)                       # r^m
+            sigma = gr.powers(gr.pow(r, M), N)          # (r^M)^n
+            c = gr.pow(r, o)                            # r^{o_l}
+            for q, (Xc, Wc, Zc) in enumerate(zip(X.comps(), W.comps(), Z.comps())):
+                xs[q].append(gr.mul(c[None, :], Xc.T @ rho))
+                ys[q].append(Wc @ sigma)
+                zs[q] = zs[q] + gr.mul(c, gr.dot(sigma, Zc.T @ rho))
+        return (Share(*[np.concatenate(v) for v in xs]), Share(*[np.concatenate(v) for v in ys]), Share(*zs))
+
+    def instance_inner_literal(self, items, r):
+        """The same batch as printed: every gate i = o_l + n M_l + m lifted and weighted by
+        r^i, consolidated to M_l N_l K_l pairs per product."""
+        gr = self.gr
+        offs = self._inner_offsets(items)
+        total = offs[-1] + items[-1][0].m.shape[0] * items[-1][1].m.shape[1]
+        pw = gr.powers(r, total)
+        xs, ys, zs = [[], [], []], [[], [], []], [np.zeros(self.d, dtype=U64) for _ in range(3)]
+        for (X, W, Z), o in zip(items, offs):
+            M, K = X.m.shape
+            N = W.m.shape[1]
+            for c in range(3):
+                Xc, Wc, Zc = X.comps()[c], W.comps()[c], Z.comps()[c]
+                xe = np.zeros((M * N * K, self.d), dtype=U64)
+                ye = np.zeros((M * N * K, self.d), dtype=U64)
                 for n in range(N):
-                    g = m * N + n
-                    for k in range(K):
-                        xe[g * K + k] = gr.scale(Xc[m, k], pw[g])
-                        ye[g * K + k] = gr.const(Wc[k, n])
-            xs.append(xe)
-            ys.append(ye)
-        z = Share(*[sum((gr.scale(Zc[g // N, g % N], pw[g]) for g in range(M * N)),
-                        np.zeros(self.d, dtype=U64)) for Zc in Z.comps()])
-        return Share(*xs), Share(*ys), z
+                    for m in range(M):
+                        i = o + n * M + m
+                        for k in range(K):
+                            xe[((n * M) + m) * K + k] = gr.scale(Xc[m, k], pw[i])
+                            ye[((n * M) + m) * K + k] = gr.const(Wc[k, n])
+                        zs[c] = zs[c] + gr.scale(Zc[m, n], pw[i])
+                xs[c].append(xe)
+                ys[c].append(ye)
+        return (Share(*[np.concatenate(v) for v in xs]), Share(*[np.concatenate(v) for v in ys]), Share(*zs))
 
     def instance_trunc(self, pair, lo, hi, r):
         """Pi_BIVerify of the truncation gates of outputs [lo, hi): 128 elements per output."""
@@ -538,9 +561,10 @@ class Ctx:
     KIND = {"inner": 1, "trunc": 2, "mult": 4}
 
     def verify(self, R=-1, literal=False, kinds=7):
-        """Post-processing: one Pi_BIVerify per Pi_Inner call, the truncation gates in
-        chunks, one Pi_MultVerify per Pi_Mult call; abort unless every Delta is 0.
-        `kinds` selects which pending products are verified now (1 inner, 2 trunc, 4 mult)."""
+        """Post-processing: one Pi_BIVerify for all pending Pi_Inner products (first), the
+        truncation gates in chunks, one Pi_MultVerify per Pi_Mult call; abort unless every
+        Delta is 0.  `kinds` selects which pending products are verified now (1 inner,
+        2 trunc, 4 mult)."""
         self.check()
         op = self.next_op()
         ok = True
@@ -548,18 +572,20 @@ class Ctx:
         self.vlog = []
         selected = [it for it in self.pending if self.KIND[it[0]] & kinds]
         rest = [it for it in self.pending if not self.KIND[it[0]] & kinds]
+        inner = [it[1:] for it in selected if it[0] == "inner"]
+        if inner:
+            log = {"kind": "inner", "s": s}
+            r = self.challenge(op, s, log)
+            inst = self.instance_inner_literal if literal else self.instance_inner_compressed
+            x, y, z = inst(inner, r)
+            log["z"] = z
+            ok &= self.fold_and_check(x, y, z, op, s, R, log)
+            self.vlog.append(log)
+            s += 1
         for item in selected:
             if item[0] == "inner":
-                _, X, W, Z = item
-                log = {"kind": "inner", "s": s}
-                r = self.challenge(op, s, log)
-                inst = self.instance_inner_literal if literal else self.instance_inner_compressed
-                x, y, z = inst(X, W, Z, r)
-                log["z"] = z
-                ok &= self.fold_and_check(x, y, z, op, s, R, log)
-                self.vlog.append(log)
-                s += 1
-            elif item[0] == "trunc":
+                continue
+            if item[0] == "trunc":
                 pair = item[1]
                 for lo in range(0, pair["n"], self.chunk):
                     hi = min(pair["n"], lo + self.chunk)

@@ -165,7 +165,10 @@ SITES = [mpc3.SITE_INNER_GAMMA2, mpc3.SITE_INNER_M1, mpc3.SITE_TRUNC_GAMMA2, mpc
 def test_injected_error_detected(site, e):
     g = np.random.default_rng(site)
     o, c = pair_of(0, chunk=4)
-    To, Tg = _pipeline(o, c, g, 2, 5, 3, inj=(site, 3, e))
+    # verification sites index (instance << 16 | round << 8 | coefficient): instance 1 is
+    # the first truncation chunk (the batched Pi_Inner instance, 0, has no rounds here)
+    idx = (1 << 16) | 3 if site in (mpc3.SITE_VER_H0_M1, mpc3.SITE_VER_H2_GAMMA2, mpc3.SITE_VER_DELTA_M1) else 3
+    To, Tg = _pipeline(o, c, g, 2, 5, 3, inj=(site, idx, e))
     assert not o.verify() and not c.verify()
     _compare_transcripts(o, c)
     with pytest.raises(mpc3.Mpc3Error) as ei:

@@ -154,7 +154,7 @@ def test_verify_honest_all_kinds():
     ctx.inner(ctx.share(_u64(g, 3, 2)), ctx.share(_u64(g, 2, 4)))
     assert ctx.verify()
     kinds = [l["kind"] for l in ctx.vlog]
-    assert kinds == ["trunc", "trunc", "trunc", "inner", "mult", "inner"]   # registry order
+    assert kinds == ["inner", "trunc", "trunc", "trunc", "mult"]   # all Pi_Inner products in one
     assert all(not np.any(l["delta"]) for l in ctx.vlog)
 
 
@@ -170,7 +170,9 @@ VERIFY_SITES = {SITE_VER_H0_M1, SITE_VER_H2_GAMMA2, SITE_VER_DELTA_M1}
 def test_verify_detects_injected_error(site, e):
     g = np.random.default_rng(8)
     ctx = Ctx(SEED, chunk=4)
-    ctx.inject(site, 3, e)
+    # verification sites index (instance << 16 | round << 8 | coefficient): instance 1 is
+    # the first truncation chunk (the batched Pi_Inner instance, 0, has no rounds here)
+    ctx.inject(site, (1 << 16) | 3 if site in VERIFY_SITES else 3, e)
     X, W = ctx.share(_u64(g, 2, 5)), ctx.share(_u64(g, 5, 3))
     pair = ctx.trunc_pair(6, 13)
     Z = ctx.inner(X, W, pair)
@@ -203,22 +205,35 @@ def test_reconstruct_detects_inconsistent_share():
 
 
 def test_compressed_claim_equals_literal_claim():
-    """The separable challenge: sum_k U_k V_k and z equal the literal consolidated
-    sum over all M*N*K elements (brute force on a tiny shape)."""
+    """One instance for a batch of products: sum_k x_k y_k and z of the compressed form
+    equal the literal consolidated sum over all gates i = o_l + n M_l + m, each weighted
+    by r^i (brute force on two tiny products of different shapes)."""
     g = np.random.default_rng(11)
     ctx = Ctx(SEED)
     gr = ctx.gr
-    M, K, N = 3, 4, 2
-    X, W = ctx.share(_u64(g, M, K)), ctx.share(_u64(g, K, N))
-    Z = ctx.inner(X, W)
+    items = []
+    for M, K, N in [(3, 4, 2), (2, 3, 3)]:
+        X, W = ctx.share(_u64(g, M, K)), ctx.share(_u64(g, K, N))
+        items.append((X, W, ctx.inner(X, W)))
     r = g.integers(0, 1 << 64, size=64, dtype=np.uint64, endpoint=False)
-    U, V, zc = ctx.instance_inner_compressed(X, W, Z, r)
-    x, y, zl = ctx.instance_inner_literal(X, W, Z, r)
+    U, V, zc = ctx.instance_inner_compressed(items, r)
+    x, y, zl = ctx.instance_inner_literal(items, r)
+    assert U.m.shape == (4 + 3, 64)
     for c in range(3):
         assert np.array_equal(zc.comps()[c], zl.comps()[c])
     for c1, c2 in itertools.product(range(3), repeat=2):
         assert np.array_equal(gr.dot(U.comps()[c1], V.comps()[c2]), gr.dot(x.comps()[c1], y.comps()[c2]))
     assert np.array_equal(gr.dot(U.value(), V.value()), zc.value())
+    # z is the weighted sum of the products' gates, written out with Python integers
+    want = np.zeros(64, dtype=np.uint64)
+    i = 0
+    for X, W, Z in items:
+        Zv = Z.value()
+        for n in range(Zv.shape[1]):
+            for m in range(Zv.shape[0]):
+                want = want + gr.scale(Zv[m, n], gr.pow(r, i))
+                i += 1
+    assert np.array_equal(zc.value(), want)
     ctx.pending = []
 
 
