@@ -4,8 +4,7 @@ Default workload: the VGG-shaped network (batch 32, 32x32x3, 3x3 "same" convolut
 64-64-128-128-256-256 with 2x2 average pooling, FC 4096-256-10), chained as a linear
 network (ReLU / max-pool are outside this path).  One timed step evaluates one batch of
 synthetic input: encode and share the batch, and for every layer im2col, the truncation
-pair, Pi_Inner, truncation and pooling; then the compressed Pi_BIVerify of every layer's
-product.  Right after each step (outside the timed window, timed on its own) the
+pair, Pi_Inner, truncation and pooling; then one batched Pi_BIVerify of all layer products.  Right after each step (outside the timed window, timed on its own) the
 truncation gates are verified and the logits opened with Pi_Rec.
 
 Printed metric: verified secure-matmul GOPS = sum over layers of 2 M K N / step time,
@@ -193,7 +192,7 @@ def main():
         "config": {"workload": f"{args.workload} linear network, batch {r['batch']}", "variant": args.variant,
                    "layers": [list(s) for s in r["shapes"]],
                    "window": "encode+share, im2col, truncation pairs, Pi_Inner, truncation, pooling, "
-                             "per-layer compressed verification",
+                             "one batched Pi_BIVerify of every layer product",
                    "linear_images_per_s": r["batch"] / t,
                    "truncation_gate_verify_ms": vt * 1e3,
                    "truncations_per_s": r["ntrunc"] / vt,

@@ -181,6 +181,18 @@ void run_gemm(mpc3_ctx* c, const GemmArgs& g) {
     ck(gemm(a, c->variant, c->cs));
 }
 
+// Few rows and columns against a long K: the 64-bit kernel, K split over workgroups that
+// add into the (zeroed) output.
+void run_gemm_skinny(mpc3_ctx* c, const GemmArgs& g) {
+    GemmArgs a = g;
+    a.accumulate = true;
+    for (int p = 0; p < (a.party ? 3 : 1); ++p) {
+        if (a.C[p].s1 != 1 || a.C[p].s0 != a.N || a.batch != 1) throw CodeError(MPC3_E_ARG);  // dense output
+        ck(hipMemsetAsync(a.C[p].p, 0, (size_t)a.M * a.N * 8, c->cs));
+    }
+    ck(gemm(a, 0, c->cs));
+}
+
 GemmArgs plain(int64_t M, int64_t N, int64_t K, View A, View B, OutView C, bool acc, int batch = 1) {
     GemmArgs g{};
     g.M = M; g.N = N; g.K = K; g.batch = batch; g.party = false; g.accumulate = acc;
@@ -440,48 +452,65 @@ u64* challenge(mpc3_ctx* c, const VerCtx& v) {
     return r;
 }
 
-void verify_inner(mpc3_ctx* c, const VerCtx& v, const Pending& it, int Rarg) {
+// One Pi_BIVerify instance for all pending Pi_Inner products.  Gate (m, n) of product l
+// is i = o_l + n M_l + m and carries r^i on the x side, so product l contributes K_l pairs
+//     x_k = r^{o_l} sum_m r^m X[m,k],   y_k = sum_n r^{M_l n} W[k,n],
+// and z = sum_l sum_n r^{o_l + M_l n} (sum_m r^m Z[m,n]).  Every power comes from two
+// tables, r^i for i < L and r^{L q}.
+void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pending*>& items, int Rarg) {
     hipStream_t s = c->cs;
-    const int64_t M = it.X.rows, K = it.X.cols, N = it.W.cols;
     u64* r = challenge(c, v);
-    u64* sigma = c->sc->words(N * 64);
-    power_table(c, r, N, sigma);
-    u64* rN = c->sc->words(64);
-    {
-        u64* Wr = c->sc->words(4096);
-        launch_mulmat(r, 64, 1, Wr, s);
-        run_gemm(c, plain(1, 64, 64, view(sigma + (N - 1) * 64, 64, 1), view(Wr, 64, 1), oview(rN, 64, 1), false));
+    int64_t Mmax = 1, total = 0, Ksum = 0;
+    for (const Pending* it : items) {
+        Mmax = std::max(Mmax, it->X.rows);
+        total += it->X.rows * it->W.cols;
+        Ksum += it->X.cols;
     }
-    u64* rho = c->sc->words(M * 64);
-    power_table(c, rN, M, rho);
-    const int R = auto_rounds(K, Rarg);
-    const int64_t np = padded(K, R);
+    int64_t L = 64;
+    while (L < Mmax) L *= 2;
+    const int64_t nhi = (total - 1) / L + 1;
+    u64* lo = c->sc->words(L * 64);
+    power_table(c, r, L, lo);                       // r^i, i < L
+    u64* rL = c->sc->words(64);
+    launch_gr_mul_rows(lo + (L - 1) * 64, r, 1, 1, rL, s);   // r^L
+    u64* hi = c->sc->words(nhi * 64);
+    power_table(c, rL, nhi, hi);                    // r^{L q}
+    const int R = auto_rounds(Ksum, Rarg);
+    const int64_t np = padded(Ksum, R);
     u64* XY = c->sc->words(6 * np * 64);
     zero(c, XY, (size_t)6 * np * 64 * 8);
-    const u64* Xc[3] = {it.X.m, it.X.r1, it.X.r2};
-    const u64* Wc[3] = {it.W.m, it.W.r1, it.W.r2};
-    const u64* Zc[3] = {it.Z.m, it.Z.r1, it.Z.r2};
-    for (int p = 0; p < 3; ++p) {
-        // U_k = sum_m rho_m X[m, k]   (K x 64)
-        run_gemm(c, plain(K, 64, M, view(Xc[p], 1, K), view(rho, 64, 1), oview(XY + p * np * 64, 64, 1), true));
-        // V_k = sum_n sigma_n W[k, n] (K x 64)
-        run_gemm(c, plain(K, 64, N, view(Wc[p], N, 1), view(sigma, 64, 1), oview(XY + (3 + p) * np * 64, 64, 1),
-                          true));
+    u64* Cz = c->sc->words(3 * 4096);
+    zero(c, Cz, 3 * 4096 * 8);
+    int64_t row = 0, off = 0;
+    for (const Pending* it : items) {
+        const int64_t M = it->X.rows, K = it->X.cols, N = it->W.cols;
+        Scratch::Mark mk = c->sc->mark();
+        u64* sig = c->sc->words(N * 64);             // r^{M n}
+        u64* sigo = c->sc->words(N * 64);            // r^{o_l + M n} (row 0: r^{o_l})
+        launch_pow_ap(lo, hi, L, 0, M, N, sig, s);
+        launch_pow_ap(lo, hi, L, off, M, N, sigo, s);
+        const u64* Xc[3] = {it->X.m, it->X.r1, it->X.r2};
+        const u64* Wc[3] = {it->W.m, it->W.r1, it->W.r2};
+        const u64* Zc[3] = {it->Z.m, it->Z.r1, it->Z.r2};
+        u64* T = c->sc->words(N * 64);
+        for (int p = 0; p < 3; ++p) {
+            u64* U = XY + p * np * 64 + row * 64;
+            // x_k = r^{o_l} sum_m r^m X[m, k]
+            run_gemm(c, plain(K, 64, M, view(Xc[p], 1, K), view(lo, 64, 1), oview(U, 64, 1), false));
+            launch_gr_mul_rows(sigo, U, K, K, U, s);
+            // y_k = sum_n r^{M n} W[k, n]
+            run_gemm(c, plain(K, 64, N, view(Wc[p], N, 1), view(sig, 64, 1), oview(XY + (3 + p) * np * 64 + row * 64, 64, 1),
+                              false));
+            // T_n = sum_m r^m Z[m, n]; z += sum_n r^{o_l + M n} T_n (ring products, folded below)
+            run_gemm(c, plain(N, 64, M, view(Zc[p], 1, N), view(lo, 64, 1), oview(T, 64, 1), false));
+            run_gemm(c, plain(64, 64, N, view(sigo, 1, 64), view(T, 64, 1), oview(Cz + p * 4096, 64, 1), true));
+        }
+        c->sc->restore(mk);
+        row += K;
+        off += M * N;
     }
     u64* z = c->sc->words(3 * 64);
-    {
-        u64* T = c->sc->words(3 * N * 64);
-        zero(c, T, (size_t)3 * N * 64 * 8);
-        u64* Cz = c->sc->words(3 * 4096);
-        zero(c, Cz, 3 * 4096 * 8);
-        for (int p = 0; p < 3; ++p) {
-            // T_n = sum_m rho_m Z[m, n]; z = sum_n sigma_n T_n (ring products, anti-diagonal fold)
-            run_gemm(c, plain(N, 64, M, view(Zc[p], 1, N), view(rho, 64, 1), oview(T + p * N * 64, 64, 1), true));
-            run_gemm(c, plain(64, 64, N, view(sigma, 1, 64), view(T + p * N * 64, 64, 1), oview(Cz + p * 4096, 64, 1),
-                              true));
-        }
-        launch_fold_plain(Cz, 3, z, s);
-    }
+    launch_fold_plain(Cz, 3, z, s);
     ck(hipMemcpyAsync(slot(v, MPC3_LOG_Z), z, 512, hipMemcpyDeviceToDevice, s));
     c->vinfo.push_back(InstanceInfo{R, np});
     fold_and_check(c, v, XY, np, z, R);
@@ -576,7 +605,8 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
         u64* Cp = c->sc->words((int64_t)3 * nu * nb * 64);
         run_gemm(c, plain(3 * nu * nb, 64, BK, view(cx, BK, 1), view(pw, 64, 1), oview(Cp, 64, 1), false));
         u64* PSX = c->sc->words(3 * nu * 64);
-        run_gemm(c, plain(3 * nu, 64, nb * 64, view(Cp, nb * 64, 1), view(Tb, 64, 1), oview(PSX, 64, 1), false));
+        run_gemm_skinny(c, plain(3 * nu, 64, nb * 64, view(Cp, nb * 64, 1), view(Tb, 64, 1), oview(PSX, 64, 1),
+                                 false));
         const u64* PS = PSX;
         ck(hipMemcpyAsync(XZ, Z, (size_t)nu * 512, hipMemcpyDeviceToDevice, s));
         launch_xshift_rows(Z, nu, 1, XZ + nu * 64, s);
@@ -1045,9 +1075,13 @@ int mpc3_verify(mpc3_ctx* c, int R, int kinds, int* ok) {
         c->scratch.reset();
         std::vector<Pending> sel, rest;
         for (auto& p : c->pending) (p.kind & kinds ? sel : rest).push_back(p);
-        int64_t ninst = 0;
+        // all Pi_Inner products form instance 0; then the truncation chunks and each Pi_Mult
+        std::vector<const Pending*> inner;
         for (auto& p : sel)
-            ninst += p.kind == MPC3_VERIFY_TRUNC ? (p.pair.n + c->chunk - 1) / c->chunk : 1;
+            if (p.kind == MPC3_VERIFY_INNER) inner.push_back(&p);
+        int64_t ninst = inner.empty() ? 0 : 1;
+        for (auto& p : sel)
+            if (p.kind != MPC3_VERIFY_INNER) ninst += p.kind == MPC3_VERIFY_TRUNC ? (p.pair.n + c->chunk - 1) / c->chunk : 1;
         u64* logd = c->scratch.words(std::max<int64_t>(ninst, 1) * NSLOT * 64);
         int* flags = (int*)c->scratch.alloc(std::max<int64_t>(ninst, 1) * sizeof(int));
         zero(c, logd, (size_t)std::max<int64_t>(ninst, 1) * NSLOT * 64 * 8);
@@ -1075,7 +1109,16 @@ int mpc3_verify(mpc3_ctx* c, int R, int kinds, int* ok) {
             c->cs = c->vs[i % mpc3_ctx::NV];
             c->sc = &c->vsc[i % mpc3_ctx::NV];
         };
+        if (!inner.empty()) {
+            lane(inst);
+            Scratch::Mark mk = c->sc->mark();
+            VerCtx v{op, inst, logd + inst * NSLOT * 64, flags + inst};
+            verify_inner_batch(c, v, inner, R);
+            c->sc->restore(mk);
+            ++inst;
+        }
         for (auto& p : sel) {
+            if (p.kind == MPC3_VERIFY_INNER) continue;
             if (p.kind == MPC3_VERIFY_TRUNC) {
                 for (int64_t lo = 0; lo < p.pair.n; lo += c->chunk) {
                     const int64_t T = std::min(c->chunk, p.pair.n - lo);
@@ -1090,8 +1133,7 @@ int mpc3_verify(mpc3_ctx* c, int R, int kinds, int* ok) {
                 lane(inst);
                 Scratch::Mark mk = c->sc->mark();
                 VerCtx v{op, inst, logd + inst * NSLOT * 64, flags + inst};
-                if (p.kind == MPC3_VERIFY_INNER) verify_inner(c, v, p, R);
-                else verify_mult(c, v, p, R);
+                verify_mult(c, v, p, R);
                 c->sc->restore(mk);
                 ++inst;
             }

@@ -763,6 +763,17 @@ __global__ void k_gr_mul_rows(const u64* P, const u64* Q, int64_t per, u64* out)
 
 
 
+// out[j] = r^{e0 + j step} from two power tables: lo[i] = r^i (i < L), hi[q] = r^{L q}.
+__global__ void k_pow_ap(const u64* lo, const u64* hi, int64_t L, int64_t e0, int64_t step, u64* out) {
+    __shared__ u64 a[64], b[64], sh[64];
+    const int k = threadIdx.x;
+    const int64_t e = e0 + (int64_t)blockIdx.x * step;
+    a[k] = hi[(e / L) * 64 + k];
+    b[k] = lo[(e % L) * 64 + k];
+    __syncthreads();
+    out[(int64_t)blockIdx.x * 64 + k] = gr_mul_lane(a, b, sh, k);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -908,6 +919,11 @@ void launch_sym_level(int j, int64_t G, int t, const u64* B1, const u64* B2, u64
 void launch_xshift_rows(const u64* in, int64_t n, int e, u64* out, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_xshift_rows, dim3((unsigned)n), dim3(64), 0, s, in, n, e, out);
+}
+void launch_pow_ap(const u64* lo, const u64* hi, int64_t L, int64_t e0, int64_t step, int64_t n, u64* out,
+                   hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_pow_ap, dim3((unsigned)n), dim3(64), 0, s, lo, hi, L, e0, step, out);
 }
 void launch_gr_mul_rows(const u64* P, const u64* Q, int64_t n, int64_t per, u64* out, hipStream_t s) {
     if (n <= 0) return;
