@@ -4,7 +4,8 @@ Default workload: the VGG-shaped network (batch 32, 32x32x3, 3x3 "same" convolut
 64-64-128-128-256-256 with 2x2 average pooling, FC 4096-256-10), chained as a linear
 network (ReLU / max-pool are outside this path).  One timed step evaluates one batch of
 synthetic input: encode and share the batch, and for every layer im2col, the truncation
-pair, Pi_Inner, truncation and pooling; then one batched Pi_BIVerify of all layer products.  Right after each step (outside the timed window, timed on its own) the
+pair, Pi_Inner, truncation and pooling; then one batched Pi_BIVerify of all layer
+products.  Right after each step (outside the timed window, timed on its own) the
 truncation gates are verified and the logits opened with Pi_Rec.
 
 Printed metric: verified secure-matmul GOPS = sum over layers of 2 M K N / step time,
@@ -27,6 +28,8 @@ import numpy as np  # noqa: E402
 from paper_2411_09287_amd import workloads  # noqa: E402
 
 INT8_PEAK_TOPS = 5000.0       # MI355X dense int8 MFMA
+ENVELOPE = (32768, 2304, 256)  # largest VGG-style conv product (batch 32, 3x3x256 -> 256)
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "pi_inner_vgg_hbm_traffic.txt")
 # 64-bit integer multiply-accumulate on the vector ALU: 256 CUs x 64 lanes x 2.4 GHz of
 # 32-bit multiplies at quarter rate, three multiplies per u64 MAC.
 U64_ALU_PEAK_TMACS = 256 * 64 * 2.4e9 / 4 / 3 / 1e12
@@ -88,8 +91,36 @@ def run_gpu(args):
             raise SystemExit("verification failed in an honest run")
         log(f"[bench] step {i + 1}/{args.steps} {times[-1] * 1e3:.2f} ms (truncation gates {vt * 1e3:.1f} ms)")
     ktime, launches, macs = ctx.profile_read()
+    env = None if args.no_envelope else envelope(ctx)
     return {"batch": batch, "shapes": shapes, "ops": ops, "ntrunc": ntrunc, "times": times, "vtimes": vtimes,
-            "ktime": ktime, "launches": launches, "macs": macs}
+            "ktime": ktime, "launches": launches, "macs": macs, "envelope": env}
+
+
+def measured_traffic(variant):
+    """HBM bytes per Pi_Inner product call measured with rocprofv3 counters (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy), valid only while the product kernel's source is
+    the one they were taken on; None otherwise."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    kv = dict(ln.split(":", 1) for ln in lines if ln.startswith(("source_sha256:", "bytes_per_call_")))
+    src = os.path.join(ROOT, "paper_2411_09287_amd", "csrc", "gemm_limb.hip" if variant != "u64" else "gemm_u64.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("source_sha256", "").strip() != digest:
+        return None
+    v = kv.get(f"bytes_per_call_{variant}")
+    return float(v) if v else None
+
+
+def envelope(ctx, reps=5):
+    """Both kernel families on the envelope product (three-party form)."""
+    M, K, N = ENVELOPE
+    _, ms_u64, ms_limb = ctx.autotune(M, K, N, reps)
+    ops = 72.0 * 5 * M * K * N
+    return {"shape": list(ENVELOPE), "u64_ms": ms_u64, "limb_ms": ms_limb, "limb_over_u64": ms_u64 / ms_limb,
+            "limb_int8_tops": ops / (ms_limb * 1e-3) / 1e12, "limb_int8_frac": ops / (ms_limb * 1e-3) / 1e12 / INT8_PEAK_TOPS}
 
 
 def cpu_baseline(args, shapes):
@@ -139,6 +170,25 @@ def run_mix(args):
     return reqs, out
 
 
+def hbm_copy(gib):
+    """A plain device-to-device copy of `gib` GiB: its time gives the achievable HBM rate and,
+    under rocprofv3 --pmc, the counter reading of a known byte count."""
+    import torch
+    torch.cuda.set_device(0)
+    n = int(gib * (1 << 30)) // 8
+    a = torch.empty(n, dtype=torch.int64, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    print(json.dumps({"copy_bytes": 8 * n, "ms": ms, "read_plus_write_GBps": 2 * 8 * n / (ms * 1e-3) / 1e9}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,7 +200,12 @@ def main():
     ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-envelope", action="store_true")
+    ap.add_argument("--hbm-copy", type=float, default=0.0, help="only time a device copy of this many GiB")
     args = ap.parse_args()
+    if args.hbm_copy > 0:
+        hbm_copy(args.hbm_copy)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
         raise SystemExit(2)
@@ -180,7 +235,9 @@ def main():
         achieved = macs_per_launch * 72 / (avg_launch_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOPS",
                 "frac": achieved / INT8_PEAK_TOPS, "traffic": None}
-    roof["kernel"] = "Pi_Inner three-party product, all layers of the step"
+    traffic = measured_traffic(args.variant)
+    roof["traffic"] = traffic
+    roof["kernel"] = "Pi_Inner three-party product (one call: B-digit conversion + product), all layers"
     roof["avg_launch_ms"] = avg_launch_ms
     roof["launches"] = r["launches"]
     cpu = None if args.no_cpu else cpu_baseline(args, r["shapes"])
@@ -196,7 +253,8 @@ def main():
                    "linear_images_per_s": r["batch"] / t,
                    "truncation_gate_verify_ms": vt * 1e3,
                    "truncations_per_s": r["ntrunc"] / vt,
-                   "images_per_s_incl_truncation_gates": r["batch"] / (t + vt)},
+                   "images_per_s_incl_truncation_gates": r["batch"] / (t + vt),
+                   "envelope_product": r["envelope"]},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

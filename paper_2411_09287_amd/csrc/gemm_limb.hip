@@ -659,13 +659,26 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
                 a.prod[p].C.p += b * a.prod[p].C.sb;
             }
         }
+        // B pre-converted to digit tiles when every A plane is k-contiguous with one row
+        // stride and B is re-read by at least two row tiles; two 64-column tiles per
+        // workgroup (one workgroup per CU) when rows are aligned, K is whole k-blocks and
+        // N spans more than one tile
+        const int na = g.party ? 3 : 1;
+        bool two = tm >= 2 && g.ws_alloc;
+        for (int p = 0; p < na && two; ++p) two = g.A[p].s1 == 1 && g.A[p].s0 == g.A[0].s0;
+        bool fast = two && g.K % KB == 0 && g.A[0].s0 % 2 == 0;
+        for (int p = 0; p < na && fast; ++p) fast = ((uintptr_t)(g.A[p].p + b * g.A[p].sb) & 15) == 0;
+        const int ns = fast && tn >= 2 ? 2 : 1;
+        // K is split (atomic adds into a zeroed output) only when the 64 x 64 tiles number
+        // fewer than the CUs: measured, a split costs more than a half-filled second wave
+        const int64_t groups = tm * tn * nprod, fill = 256;
         int64_t splits = 1;
         bool dense = !a.D.p && !g.accumulate;
         for (int p = 0; p < nprod; ++p)
             dense = dense && a.prod[p].C.s1 == 1 && a.prod[p].C.s0 == g.N;
         const bool too_long = maxseg * Kp > KSEG;
         if (too_long && !g.accumulate && !dense) return gemm_u64(g, st);
-        if (dense && (too_long || (tm * tn * nprod < 256 && maxseg * Kp >= 2048))) {
+        if (dense && (too_long || (groups < fill && maxseg * Kp >= 2048))) {
             for (int p = 0; p < nprod; ++p) {
                 hipError_t e = hipMemsetAsync(a.prod[p].C.p, 0, (size_t)g.M * g.N * 8, st);
                 if (e != hipSuccess) return e;
@@ -673,8 +686,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             a.atomic = 1;
         }
         if (a.atomic) {
-            const int64_t tiles = tm * tn * nprod;
-            const int64_t want = (1024 + tiles - 1) / tiles;
+            const int64_t want = (4 * fill + groups - 1) / groups;
             splits = std::max<int64_t>(1, std::min<int64_t>(want, maxseg * Kp / 256));
         }
         splits = std::max<int64_t>(splits, (maxseg * Kp + KSEG - 1) / KSEG);
@@ -684,11 +696,6 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         a.kchunk = kchunk;
         a.splits = (int)splits;
         if (nprod * splits > 65535) return hipErrorInvalidValue;
-        // B pre-converted to digit tiles when every A plane is k-contiguous with one row
-        // stride and B is re-read by at least two row tiles
-        const int na = g.party ? 3 : 1;
-        bool two = tm >= 2 && g.ws_alloc;
-        for (int p = 0; p < na && two; ++p) two = g.A[p].s1 == 1 && g.A[p].s0 == g.A[0].s0;
         if (two) {
             const int64_t nkb = Kp / KB, rows_pad = tn * TN;
             if (nkb * 2 > 0x7FFFFFFF || tn * tm * nprod * splits > 0x7FFFFFFF) return hipErrorInvalidValue;
@@ -735,11 +742,6 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
                     l.prod[p].C = a.prod[p].C;
                 }
             }
-            bool fast = g.K % KB == 0 && l.lda % 2 == 0;
-            for (int p = 0; p < na; ++p) fast = fast && ((uintptr_t)Ap[p] & 15) == 0;
-            // two 64-column tiles per workgroup (eight waves sharing one converted A tile)
-            // when the aligned path applies and N spans more than one tile
-            const int ns = fast && tn >= 2 ? 2 : 1;
             l.tn64 = (int)tn;
             l.tn = (int)((tn + ns - 1) / ns);
             const dim3 gr((unsigned)(l.tn * tm * nprod * splits));
