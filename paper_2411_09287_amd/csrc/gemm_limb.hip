@@ -294,7 +294,7 @@ struct Prod2 {
 };
 struct L2Args {
     Prod2 prod[3];
-    int64_t M, N, K, lda;
+    int64_t M, N, K, lda, ldk;   // A element (row, k) at row * lda + k * ldk
     int nkb;                     // k-blocks per segment
     int kcb;                     // k-blocks per split (segments concatenated)
     int nprod, splits;
@@ -349,7 +349,7 @@ __device__ __forceinline__ void wait_vm() {
 //     flight, so every wait the compiler places is exact.
 // Otherwise (NS = 1): B tiles are copied straight into LDS (global_load_lds) and A words are
 // converted after the MFMAs.
-template <bool FAST, int NS>
+template <bool FAST, int NS, bool TA = false>
 __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
     constexpr int WPT = 8 / NS;                  // A words converted per thread and k-block
     __shared__ __attribute__((aligned(16))) int8_t As[2][TILE_BYTES];
@@ -374,9 +374,13 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
     const int tcol = tni * NS + sub;             // this wave group's 64-column tile
     const int64_t r0a = (int64_t)tmi * TM, r0b = (int64_t)tcol * TN;
     // A loader: row ra, WPT consecutive words at k = part * WPT
-    const int ra = NS == 1 ? t >> 2 : t >> 3, part = NS == 1 ? t & 3 : t & 7;
+    // A loader: row ra, WPT consecutive k at k = part * WPT.  With k contiguous (TA false)
+    // 32 / WPT threads share a row; with rows contiguous (TA, a transposed view) 64
+    // consecutive threads take 64 consecutive rows, so each of their loads is coalesced.
+    const int ra = TA ? t & 63 : (NS == 1 ? t >> 2 : t >> 3);
+    const int part = TA ? t >> 6 : (NS == 1 ? t & 3 : t & 7);
     // rows past M load row M-1: they only feed accumulator rows that are never stored
-    const int64_t aoff = min(r0a + ra, a.M - 1) * a.lda + part * WPT;
+    const int64_t aoff = min(r0a + ra, a.M - 1) * a.lda + part * WPT * a.ldk;
     const int tt = t & (NT - 1);
     // column tiles past the last one read the last one: their outputs are never stored
     const int64_t boff = (int64_t)min(tcol, a.tn64 - 1) * nkb * TILE_BYTES + tt * 16;
@@ -409,8 +413,11 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
         int kb;
         const int s = seg_of(g, kb);
         const int64_t k0 = (int64_t)kb * KB;
-        const u64* rp = (s ? pa[1] : pa[0]) + k0;
-        if (FAST) {
+        const u64* rp = (s ? pa[1] : pa[0]) + k0 * a.ldk;
+        if (TA) {
+#pragma unroll
+            for (int i = 0; i < WPT; ++i) x[i] = rp[i * a.ldk];
+        } else if (FAST) {
 #pragma unroll
             for (int h = 0; h < WPT / 2; ++h) {
                 const ulonglong2 v = *(const ulonglong2*)(rp + 2 * h);
@@ -664,10 +671,14 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         // workgroup (one workgroup per CU) when rows are aligned, K is whole k-blocks and
         // N spans more than one tile
         const int na = g.party ? 3 : 1;
-        bool two = tm >= 2 && g.ws_alloc;
-        for (int p = 0; p < na && two; ++p) two = g.A[p].s1 == 1 && g.A[p].s0 == g.A[0].s0;
-        bool fast = two && g.K % KB == 0 && g.A[0].s0 % 2 == 0;
-        for (int p = 0; p < na && fast; ++p) fast = ((uintptr_t)(g.A[p].p + b * g.A[p].sb) & 15) == 0;
+        bool kc = tm >= 2 && g.ws_alloc, ta = kc && g.K % KB == 0;
+        for (int p = 0; p < na; ++p) {
+            kc = kc && g.A[p].s1 == 1 && g.A[p].s0 == g.A[0].s0;
+            ta = ta && g.A[p].s0 == 1 && g.A[p].s1 == g.A[0].s1;   // transposed view, rows contiguous
+        }
+        const bool two = kc || ta;
+        bool fast = ta || (kc && g.K % KB == 0 && g.A[0].s0 % 2 == 0);
+        for (int p = 0; p < na && fast && !ta; ++p) fast = ((uintptr_t)(g.A[p].p + b * g.A[p].sb) & 15) == 0;
         const int ns = fast && tn >= 2 ? 2 : 1;
         // K is split (atomic adds into a zeroed output) only when the 64 x 64 tiles number
         // fewer than the CUs: measured, a split costs more than a half-filled second wave
@@ -709,7 +720,9 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
                 return tb;
             };
             L2Args l{};
-            l.M = g.M; l.N = g.N; l.K = g.K; l.lda = g.A[0].s0;
+            l.M = g.M; l.N = g.N; l.K = g.K;
+            l.lda = ta ? 1 : g.A[0].s0;
+            l.ldk = ta ? g.A[0].s1 : 1;
             l.nkb = (int)nkb; l.kcb = (int)(kchunk / KB); l.nprod = nprod; l.splits = (int)splits;
             l.atomic = a.atomic; l.D = a.D;
             const u64* Ap[3];
@@ -745,7 +758,9 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             l.tn64 = (int)tn;
             l.tn = (int)((tn + ns - 1) / ns);
             const dim3 gr((unsigned)(l.tn * tm * nprod * splits));
-            if (ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2>), gr, dim3(2 * NT), 0, st, l);
+            if (ta && ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2, true>), gr, dim3(2 * NT), 0, st, l);
+            else if (ta) hipLaunchKernelGGL((k_lgemm2<true, 1, true>), gr, dim3(NT), 0, st, l);
+            else if (ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2>), gr, dim3(2 * NT), 0, st, l);
             else if (fast) hipLaunchKernelGGL((k_lgemm2<true, 1>), gr, dim3(NT), 0, st, l);
             else hipLaunchKernelGGL((k_lgemm2<false, 1>), gr, dim3(NT), 0, st, l);
             hipError_t e = hipGetLastError();

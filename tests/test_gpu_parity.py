@@ -128,7 +128,8 @@ def _compare_transcripts(o, c):
 
 
 @pytest.mark.parametrize("variant", [0, 1])
-@pytest.mark.parametrize("shape,R", [((3, 5, 4), -1), ((4, 27, 6), 2), ((6, 64, 5), 6), ((2, 3, 2), 0)])
+@pytest.mark.parametrize("shape,R", [((3, 5, 4), -1), ((4, 27, 6), 2), ((6, 64, 5), 6), ((2, 3, 2), 0),
+                                     ((64, 160, 4), -1)])
 def test_verify_transcript_parity(variant, shape, R):
     g = np.random.default_rng(sum(shape) + R)
     o, c = pair_of(variant, chunk=4)
