@@ -203,12 +203,49 @@ GemmArgs plain(int64_t M, int64_t N, int64_t K, View A, View B, OutView C, bool 
 
 void zero(mpc3_ctx* c, void* p, size_t bytes) { ck(hipMemsetAsync(p, 0, bytes, c->cs)); }
 
-// table[i] = base^i for i < n (table: n x 64), doubling: table[len + i] = table[i] base^len.
-void power_table(mpc3_ctx* c, const u64* base, int64_t n, u64* table) {
+// table[i] = base^i for i < n (table: n x 64).
+//   n <= 256: doubling, one launch per level (table[len + i] = table[i] base^len, with the
+//             next square in the same launch);
+//   n <= 65536: two such tables, base^j (j < 128) and base^(128 q), and one launch of
+//             their products base^i = base^(128 (i >> 7)) base^(i & 127);
+//   larger: doubling whose levels are products with the multiplication matrix of base^len
+//           (matrix cores for the wide levels).
+void power_levels(mpc3_ctx* c, const u64* base, int64_t n, u64* table) {
     hipStream_t s = c->cs;
     launch_set_one(table, s);
     if (n <= 1) return;
     Scratch::Mark mk = c->sc->mark();
+    u64* P = c->sc->words(64);
+    u64* P2 = c->sc->words(64);
+    ck(hipMemcpyAsync(P, base, 512, hipMemcpyDeviceToDevice, s));
+    for (int64_t len = 1; len < n; len *= 2) {
+        const int64_t cnt = std::min(len, n - len);
+        launch_pow_level(table, len, cnt, P, 2 * len < n ? P2 : nullptr, s);
+        std::swap(P, P2);
+    }
+    c->sc->restore(mk);
+}
+
+void power_table(mpc3_ctx* c, const u64* base, int64_t n, u64* table) {
+    hipStream_t s = c->cs;
+    if (n <= 256) {
+        power_levels(c, base, n, table);
+        return;
+    }
+    Scratch::Mark mk = c->sc->mark();
+    if (n <= 65536) {
+        const int64_t B = 128, nq = (n - 1) / B + 1;
+        u64* lo = c->sc->words(B * 64);
+        power_levels(c, base, B, lo);
+        u64* bB = c->sc->words(64);
+        launch_gr_mul_rows(lo + (B - 1) * 64, base, 1, 1, bB, s);     // base^128
+        u64* hi = c->sc->words(nq * 64);
+        power_levels(c, bB, nq, hi);
+        launch_pow_ap(lo, hi, B, 0, 1, n, table, s);
+        c->sc->restore(mk);
+        return;
+    }
+    launch_set_one(table, s);
     u64* P = c->sc->words(64);
     u64* P2 = c->sc->words(64);
     u64* WP = c->sc->words(4096);
@@ -385,9 +422,10 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
         u64* Wz = c->sc->words(4096);
         launch_mulmat(zeta, 64, 1, Wz, s);
         u64* XYn = c->sc->words(np * half * 64);
-        GemmArgs g = plain(half, 64, 64, view(Dd, 64, 1, half * 64), view(Wz, 64, 1, 0),
-                           oview(XYn, 64, 1, half * 64), false, np);
-        g.Dadd = view(XY, 128, 1, n * 64);
+        // the planes are stacked, so the np planes run as one product of np * half rows:
+        // row c * half + i of D and of the output, row 2 (c * half + i) of XY (n = 2 half)
+        GemmArgs g = plain(np * half, 64, 64, view(Dd, 64, 1), view(Wz, 64, 1), oview(XYn, 64, 1), false);
+        g.Dadd = view(XY, 128, 1);
         run_gemm(c, g);
         XY = XYn;
         n = half;

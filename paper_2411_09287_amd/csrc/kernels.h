@@ -112,6 +112,9 @@ void launch_sym_level(int j, int64_t G, int t, const u64* B1, const u64* B2, u64
 void launch_xshift_rows(const u64* in, int64_t n, int e, u64* out, hipStream_t s);
 // out[i] = P[i / per] * Q[i] (ring products, one 64-lane group per row).
 void launch_gr_mul_rows(const u64* P, const u64* Q, int64_t n, int64_t per, u64* out, hipStream_t s);
+// One doubling level of a power table: out[len + i] = out[i] * P for i < cnt; Pn = P^2
+// when Pn is not null.
+void launch_pow_level(u64* out, int64_t len, int64_t cnt, const u64* P, u64* Pn, hipStream_t s);
 // out[j] = r^(e0 + j step) for j < n, from lo[i] = r^i (i < L) and hi[q] = r^(L q)
 // (every exponent below L times the rows of hi).
 void launch_pow_ap(const u64* lo, const u64* hi, int64_t L, int64_t e0, int64_t step, int64_t n, u64* out,

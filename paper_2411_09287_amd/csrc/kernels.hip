@@ -763,6 +763,20 @@ __global__ void k_gr_mul_rows(const u64* P, const u64* Q, int64_t per, u64* out)
 
 
 
+// One doubling level of a power table: out[len + i] = out[i] * P for i < cnt (blocks
+// 0 .. cnt-1) and, when Pn is given, Pn = P * P (block cnt).
+__global__ void k_pow_level(u64* out, int64_t len, int64_t cnt, const u64* P, u64* Pn) {
+    __shared__ u64 a[64], b[64], sh[64];
+    const int k = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    a[k] = P[k];
+    b[k] = i < cnt ? out[i * 64 + k] : P[k];
+    __syncthreads();
+    const u64 v = gr_mul_lane(a, b, sh, k);
+    if (i < cnt) out[(len + i) * 64 + k] = v;
+    else Pn[k] = v;
+}
+
 // out[j] = r^{e0 + j step} from two power tables: lo[i] = r^i (i < L), hi[q] = r^{L q}.
 __global__ void k_pow_ap(const u64* lo, const u64* hi, int64_t L, int64_t e0, int64_t step, u64* out) {
     __shared__ u64 a[64], b[64], sh[64];
@@ -919,6 +933,9 @@ void launch_sym_level(int j, int64_t G, int t, const u64* B1, const u64* B2, u64
 void launch_xshift_rows(const u64* in, int64_t n, int e, u64* out, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_xshift_rows, dim3((unsigned)n), dim3(64), 0, s, in, n, e, out);
+}
+void launch_pow_level(u64* out, int64_t len, int64_t cnt, const u64* P, u64* Pn, hipStream_t s) {
+    hipLaunchKernelGGL(k_pow_level, dim3((unsigned)(cnt + (Pn ? 1 : 0))), dim3(64), 0, s, out, len, cnt, P, Pn);
 }
 void launch_pow_ap(const u64* lo, const u64* hi, int64_t L, int64_t e0, int64_t step, int64_t n, u64* out,
                    hipStream_t s) {
