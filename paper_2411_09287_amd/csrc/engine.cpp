@@ -126,6 +126,9 @@ struct mpc3_ctx {
     hipStream_t vs[NV] = {};
     Scratch vsc[NV];
     hipEvent_t ev_fork = nullptr, ev_join[NV] = {};
+    // a batched instance spreads its per-product work over the worker streams with these
+    Scratch vsc2[NV];
+    hipEvent_t ev_fork2 = nullptr, ev_join2[NV] = {};
     hipStream_t cs = nullptr;
     Scratch* sc = nullptr;
     // autotuned kernel family per (M, K, N) of a three-party product
@@ -519,9 +522,19 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
     zero(c, XY, (size_t)6 * np * 64 * 8);
     u64* Cz = c->sc->words(3 * 4096);
     zero(c, Cz, 3 * 4096 * 8);
-    int64_t row = 0, off = 0;
+    // the products' compressions are independent: they run on the worker streams (each with
+    // its own workspace) and add their claims into Cz atomically, then join this stream
+    hipStream_t home = c->cs;
+    Scratch* home_sc = c->sc;
+    ck(hipEventRecord(c->ev_fork2, home));
+    for (int i = 0; i < mpc3_ctx::NV; ++i) ck(hipStreamWaitEvent(c->vs[i], c->ev_fork2, 0));
+    int64_t row = 0, off = 0, li = 0;
     for (const Pending* it : items) {
         const int64_t M = it->X.rows, K = it->X.cols, N = it->W.cols;
+        const int w = (int)(li++ % mpc3_ctx::NV);
+        c->cs = c->vs[w];
+        c->sc = &c->vsc2[w];
+        s = c->cs;
         Scratch::Mark mk = c->sc->mark();
         u64* sig = c->sc->words(N * 64);             // r^{M n}
         u64* sigo = c->sc->words(N * 64);            // r^{o_l + M n} (row 0: r^{o_l})
@@ -546,6 +559,12 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
         c->sc->restore(mk);
         row += K;
         off += M * N;
+    }
+    c->cs = s = home;
+    c->sc = home_sc;
+    for (int i = 0; i < mpc3_ctx::NV; ++i) {
+        ck(hipEventRecord(c->ev_join2[i], c->vs[i]));
+        ck(hipStreamWaitEvent(home, c->ev_join2[i], 0));
     }
     u64* z = c->sc->words(3 * 64);
     launch_fold_plain(Cz, 3, z, s);
@@ -801,10 +820,13 @@ int mpc3_ctx_destroy(mpc3_ctx* c) {
             (void)hipStreamSynchronize(c->vs[i]);
             (void)hipStreamDestroy(c->vs[i]);
             (void)hipEventDestroy(c->ev_join[i]);
+            (void)hipEventDestroy(c->ev_join2[i]);
         }
         c->vsc[i].release();
+        c->vsc2[i].release();
     }
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_fork2) (void)hipEventDestroy(c->ev_fork2);
     for (int k = 0; k < 2; ++k)
         for (int i = 0; i < 3; ++i)
             if (c->msg[k][i]) (void)hipFree(c->msg[k][i]);
@@ -1127,15 +1149,18 @@ int mpc3_verify(mpc3_ctx* c, int R, int kinds, int* ok) {
         c->vinfo.clear();
         if (!c->ev_fork) {
             ck(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+            ck(hipEventCreateWithFlags(&c->ev_fork2, hipEventDisableTiming));
             for (int i = 0; i < mpc3_ctx::NV; ++i) {
                 ck(hipStreamCreateWithFlags(&c->vs[i], hipStreamNonBlocking));
                 ck(hipEventCreateWithFlags(&c->ev_join[i], hipEventDisableTiming));
+                ck(hipEventCreateWithFlags(&c->ev_join2[i], hipEventDisableTiming));
             }
         }
         ck(hipEventRecord(c->ev_fork, s));
         for (int i = 0; i < mpc3_ctx::NV; ++i) {
             ck(hipStreamWaitEvent(c->vs[i], c->ev_fork, 0));
             c->vsc[i].reset();
+            c->vsc2[i].reset();
         }
         // instances are independent: instance i runs on worker stream i mod NV
         struct Restore {

@@ -193,10 +193,10 @@ hipError_t gemm_u64(const GemmArgs& g, hipStream_t stream) {
     const int64_t tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
     if (tm > 65535) return hipErrorInvalidValue;
     int ksplit = 1;
-    if (g.accumulate && g.K > 64) {
+    if (g.accumulate && g.K > BK) {
         const int64_t tiles = tm * tn * g.batch;
         const int64_t want = (1024 + tiles - 1) / tiles;          // aim for ~1k workgroups
-        const int64_t maxs = (g.K + 63) / 64;                      // at least 64 of K per split
+        const int64_t maxs = (g.K + BK - 1) / BK;                  // at least one K step per split
         ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({want, maxs, 4096}));
     }
     int64_t kchunk = (g.K + ksplit - 1) / ksplit;
