@@ -202,9 +202,16 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-envelope", action="store_true")
     ap.add_argument("--hbm-copy", type=float, default=0.0, help="only time a device copy of this many GiB")
+    ap.add_argument("--envelope-only", action="store_true", help="only time the envelope product")
     args = ap.parse_args()
     if args.hbm_copy > 0:
         hbm_copy(args.hbm_copy)
+        return
+    if args.envelope_only:
+        import torch
+        from paper_2411_09287_amd import mpc3
+        torch.cuda.set_device(0)
+        print(json.dumps(envelope(mpc3.Context(workloads.master_seed(4)))))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
