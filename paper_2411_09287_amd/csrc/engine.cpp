@@ -184,15 +184,12 @@ void run_gemm(mpc3_ctx* c, const GemmArgs& g) {
     ck(gemm(a, c->variant, c->cs));
 }
 
-// Few rows and columns against a long K: the 64-bit kernel, K split over workgroups that
-// add into the (zeroed) output.
+// Few rows and columns against a long K: the 64-bit kernel (it splits K over workgroups,
+// partial sums in the workspace).
 void run_gemm_skinny(mpc3_ctx* c, const GemmArgs& g) {
     GemmArgs a = g;
-    a.accumulate = true;
-    for (int p = 0; p < (a.party ? 3 : 1); ++p) {
-        if (a.C[p].s1 != 1 || a.C[p].s0 != a.N || a.batch != 1) throw CodeError(MPC3_E_ARG);  // dense output
-        ck(hipMemsetAsync(a.C[p].p, 0, (size_t)a.M * a.N * 8, c->cs));
-    }
+    a.ws_alloc = scratch_alloc;
+    a.ws_self = c->sc;
     ck(gemm(a, 0, c->cs));
 }
 
@@ -303,17 +300,16 @@ u64* slot(const VerCtx& v, int s, int round = 0) {
     }
 }
 
-// Party product of two strided element lists (P0, P1, P2 sums) into C0..C2 (3 x 64x64, zeroed).
+// Party product of two strided element lists (P0, P1, P2 sums) into C0..C2 (3 x 64x64).
 void gr_dot_party(mpc3_ctx* c, int64_t n, const u64* A[3], int64_t astride, const u64* B[3], int64_t bstride,
                   u64* C) {
     GemmArgs g{};
-    g.M = 64; g.N = 64; g.K = n; g.batch = 1; g.party = true; g.accumulate = true;
+    g.M = 64; g.N = 64; g.K = n; g.batch = 1; g.party = true; g.accumulate = false;
     for (int p = 0; p < 3; ++p) {
         g.A[p] = view(A[p], 1, astride);      // (coefficient j, element i)
         g.B[p] = view(B[p], bstride, 1);      // (element i, coefficient l)
         g.C[p] = oview(C + p * 4096, 64, 1);
     }
-    zero(c, C, 3 * 4096 * 8);
     run_gemm(c, g);
 }
 
@@ -341,8 +337,8 @@ void polyevl_sparse(mpc3_ctx* c, const VerCtx& v, int64_t n, const u64* X1, int6
                     int64_t bstride, uint32_t pr, uint32_t pg, uint32_t sub, Inj im1, Inj ig2, u64* out, u64* lm1,
                     u64* lm2, u64* lg2) {
     u64* C = c->sc->words(3 * 4096);
-    zero(c, C, 3 * 4096 * 8);
-    run_gemm(c, plain(64, 64, n, view(X1, 1, astride), view(Y2, bstride, 1), oview(C, 64, 1), true));
+    zero(c, C + 4096, 2 * 4096 * 8);
+    run_gemm(c, plain(64, 64, n, view(X1, 1, astride), view(Y2, bstride, 1), oview(C, 64, 1), false));
     PolyEvlArgs a{};
     a.C = C; a.k = c->keys; a.op = v.op; a.pr = pr; a.pg = pg; a.sub = sub;
     a.inj_m1 = im1.index >= 0 ? (int)im1.index : -1; a.e_m1 = im1.e;
@@ -586,10 +582,9 @@ void verify_mult(mpc3_ctx* c, const VerCtx& v, const Pending& it, int Rarg) {
     launch_scale_rows(n, it.X.m, it.X.r1, it.X.r2, pw, XY, np * 64, s);      // x'_i = r^i a_i
     launch_lift_rows(n, it.W.m, it.W.r1, it.W.r2, XY + 3 * np * 64, np * 64, s);
     u64* z = c->sc->words(3 * 64);
-    zero(c, z, 3 * 64 * 8);
     const u64* Zc[3] = {it.Z.m, it.Z.r1, it.Z.r2};
     for (int p = 0; p < 3; ++p)
-        run_gemm(c, plain(1, 64, n, view(Zc[p], 0, 1), view(pw, 64, 1), oview(z + p * 64, 64, 1), true));
+        run_gemm(c, plain(1, 64, n, view(Zc[p], 0, 1), view(pw, 64, 1), oview(z + p * 64, 64, 1), false));
     ck(hipMemcpyAsync(slot(v, MPC3_LOG_Z), z, 512, hipMemcpyDeviceToDevice, s));
     c->vinfo.push_back(InstanceInfo{R, np});
     fold_and_check(c, v, XY, np, z, R);
@@ -616,9 +611,8 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
     u64* w3 = c->sc->words(6 * T);
     launch_trunc_w(lo, T, p.t, B1, B2, p.rx.m, p.rx.r1, p.rx.r2, p.rz.m, p.rz.r1, p.rz.r2, w3, s);
     u64* z = c->sc->words(3 * 64);
-    zero(c, z, 3 * 64 * 8);
     for (int q = 0; q < 3; ++q)
-        run_gemm(c, plain(1, 64, 2 * T, view(w3 + q * 2 * T, 0, 1), view(pw, 64, 1), oview(z + q * 64, 64, 1), true));
+        run_gemm(c, plain(1, 64, 2 * T, view(w3 + q * 2 * T, 0, 1), view(pw, 64, 1), oview(z + q * 64, 64, 1), false));
     ck(hipMemcpyAsync(slot(v, MPC3_LOG_Z), z, 512, hipMemcpyDeviceToDevice, s));
     c->vinfo.push_back(InstanceInfo{R, np});
     if (R == 0) {
@@ -671,14 +665,14 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
         u64* h0 = c->sc->words(3 * 64);
         u64* h2 = c->sc->words(3 * 64);
         u64* C = c->sc->words(3 * 4096);
-        zero(c, C, 3 * 4096 * 8);
-        run_gemm(c, plain(64, 64, nu, view(Z, 1, 64), view(PS, 64, 1), oview(C, 64, 1), true));
+        zero(c, C + 4096, 2 * 4096 * 8);
+        run_gemm(c, plain(64, 64, nu, view(Z, 1, 64), view(PS, 64, 1), oview(C, 64, 1), false));
         polyevl_from(c, v, C, P_VER_H0_R, P_VER_H0_GAMMA, sub, take_ver(c, MPC3_SITE_VER_H0_M1, v.inst, j),
                      Inj{-1, 0}, h0, slot(v, MPC3_LOG_H0_M1, j), slot(v, MPC3_LOG_H0_M2, j),
                      slot(v, MPC3_LOG_H0_G2, j));
         u64* C2 = c->sc->words(3 * 4096);
-        zero(c, C2, 3 * 4096 * 8);
-        run_gemm(c, plain(64, 64, 3 * nu, view(XZ, 1, 64), view(PSX, 64, 1), oview(C2, 64, 1), true));
+        zero(c, C2 + 4096, 2 * 4096 * 8);
+        run_gemm(c, plain(64, 64, 3 * nu, view(XZ, 1, 64), view(PSX, 64, 1), oview(C2, 64, 1), false));
         polyevl_from(c, v, C2, P_VER_H2_R, P_VER_H2_GAMMA, sub, Inj{-1, 0},
                      take_ver(c, MPC3_SITE_VER_H2_GAMMA2, v.inst, j), h2, slot(v, MPC3_LOG_H2_M1, j),
                      slot(v, MPC3_LOG_H2_M2, j), slot(v, MPC3_LOG_H2_G2, j));

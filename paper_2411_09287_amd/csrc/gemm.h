@@ -15,7 +15,7 @@ struct OutView {
 };
 
 // C = A B over Z_{2^64}.  A is M x K, B is K x N (per batch).
-//   plain:  C = A B (+ D when D.p != null and no split), or C += A B (atomic) when accumulate.
+//   plain:  C = A B (+ D when D.p != null), or C += A B (atomic) when accumulate.
 //   party:  three accumulators from the share planes of A = (Am, A1, A2), B = (Bm, B1, B2):
 //           C0 = (A1 + A2)(B1 + B2)              (P0: r_x r_y)
 //           C1 = Am B1 + A1 Bm                   (P1: m_x [r_y]_1 + m_y [r_x]_1)
@@ -24,16 +24,27 @@ struct GemmArgs {
     int64_t M, N, K;
     int batch;
     bool party;
-    bool accumulate;          // atomic C += ...  (required when ksplit > 1; C must be initialised)
+    bool accumulate;          // C += A B with 64-bit atomic adds (C initialised by the caller)
     View A[3], B[3];          // plain uses index 0
     OutView C[3];
     View Dadd;                // plain, non-accumulating: C = AB + Dadd
-    // device workspace for the limb backend (stream-ordered bump allocator of the caller)
+    // device workspace (stream-ordered bump allocator of the caller): digit tiles of the limb
+    // backend, split-K partial sums of both backends; without it K is split only with
+    // atomic adds into an accumulating (or zeroed) output
     void* (*ws_alloc)(void* self, size_t bytes);
     void* ws_self;
 };
 
 // Launch on `stream` with the chosen backend (0 = u64 VALU, 1 = int8 limbs on MFMA).
 hipError_t gemm(const GemmArgs& g, int variant, hipStream_t stream);
+
+// Split-K partial sums: part holds batch x splits x nprod planes of M x N words (n fastest).
+// C[p] = sum over splits (+ D when D.p is set, nprod == 1), or C[p] += sum (64-bit atomic
+// add) when atomic.
+hipError_t split_reduce(const u64* part, int64_t M, int64_t N, int nprod, int splits, int batch,
+                        const OutView* C, const View& D, bool atomic, hipStream_t stream);
+
+// Bytes of partial sums one product may use before the split count is cut back.
+constexpr size_t PART_MAX = (size_t)1 << 30;
 
 }  // namespace mpc3

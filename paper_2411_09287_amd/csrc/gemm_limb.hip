@@ -11,6 +11,8 @@
 // int8: the byte carries of that addition are exactly the carries of the balanced
 // representation.  Tiles are read as 64-bit words, converted in registers, transposed
 // to digit planes in LDS and fed to v_mfma_i32_32x32x32_i8; no digit planes touch HBM.
+#include <type_traits>
+
 #include "gemm.h"
 
 namespace mpc3 {
@@ -48,6 +50,7 @@ struct LArgs {
     int splits;
     int atomic;
     View D;
+    u64* part;                            // split-K partial sums: plane (split, product) of M x N
 };
 
 // 8 consecutive k of one row of an operand, loaded raw: w[i] = v(row, k0 + i).
@@ -235,6 +238,10 @@ __global__ __launch_bounds__(NT, 2) void k_lgemm(LArgs a) {
         u64 val = 0;
 #pragma unroll
         for (int s = 0; s < 8; ++s) val += ((u64)(int64_t)acc[s][v]) << (8 * s);
+        if (a.part) {
+            a.part[((int64_t)split * (gridDim.z / a.splits) + prod) * a.M * a.N + m * a.N + n] = val;
+            continue;
+        }
         u64* p = P.C.p + m * P.C.s0 + n * P.C.s1;
         if (a.atomic) {
             atomicAdd((unsigned long long*)p, (unsigned long long)val);
@@ -280,11 +287,12 @@ __global__ void k_to_tiles(Opnd o, int64_t K, int64_t nkb, int64_t rows_pad, int
     for (int d = 0; d < 8; ++d) *(u64*)(base + toff(d, rr, oc)) = q[d];
 }
 
-// A segment of a product: one A plane (k contiguous, row stride lda) and the digit tiles of
-// its B operand.  Every sign and sum of the party form sits on the B side, so A is read
-// as stored.
+// A segment of a product: one A plane (k contiguous, row stride lda), or the sum of two
+// planes when p2 is set, and the digit tiles of its B operand.  Every sign of the party
+// form sits on the B side.
 struct Seg2 {
     const u64* p;
+    const u64* p2;
     const int8_t* bt;
 };
 struct Prod2 {
@@ -300,8 +308,11 @@ struct L2Args {
     int nprod, splits;
     int tn;                      // column groups of the grid (NS tiles of 64 each)
     int tn64;                    // 64-column tiles of B
+    int tm;                      // 64-row tiles
+    int rb;                      // row tiles per group of the launch order
     int atomic;
     View D;
+    u64* part;                   // split-K partial sums: plane (split, product) of M x N
 };
 
 // 8 raw words of one A row: rp points at k = k0 (the thread's octet); words at k >= K read
@@ -357,16 +368,22 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int sub = w >> 2, wl = w & 3;
     // Workgroup ids are dealt round-robin to the 8 XCDs; renumber so that every XCD works
-    // through a contiguous run of tiles (the column tiles and products of one row tile
-    // share their A rows in that XCD's L2).
+    // through a contiguous run of T.  In T order, groups of rb row tiles take every column
+    // group of one (product, split) before the next: the workgroups an XCD runs at once
+    // walk K together over the same B tiles, and the column groups of a row tile share
+    // its A rows, in that XCD's L2.
     const int nwg = gridDim.x, L = blockIdx.x, q8 = nwg / 8;
     const int T = L < 8 * q8 ? (L % 8) * q8 + L / 8 : L;
-    const int tni = T % a.tn;
-    int rest = T / a.tn;
+    const int per = a.tn * a.nprod * a.splits;   // workgroups per row tile
+    const int grp = T / (a.rb * per);
+    const int first = grp * a.rb, rows = min(a.tm - first, a.rb);
+    const int within = T - grp * a.rb * per;
+    const int tmi = first + within % rows;
+    int rest = within / rows;
+    const int tni = rest % a.tn;
+    rest /= a.tn;
     const int prod = rest % a.nprod;
-    rest /= a.nprod;
-    const int split = rest % a.splits;
-    const int tmi = rest / a.splits;
+    const int split = rest / a.nprod;
     const Prod2& P = a.prod[prod];
     const int nkb = a.nkb;
     const int gbeg = split * a.kcb;
@@ -392,6 +409,8 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
         pa[s] = S.p + aoff;
         pb[s] = S.bt + boff;
     }
+    // a summed segment (only ever the first): its second plane
+    const u64* pa2 = P.seg[0].p2 ? P.seg[0].p2 + aoff : nullptr;
     const int wy = wl >> 1, wx = wl & 1, r = lane & 31, hf = lane >> 5;
     const int arow = wy * 32 + r, brow = wx * 32 + r;
     const int aread = arow * KB + ((hf ^ swz(arow)) << 4);
@@ -409,23 +428,29 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
         kb = g - s * nkb;
         return s;
     };
-    auto loadA = [&](int g, u64 x[WPT]) {
+    // the WPT words of block g at x[0, WPT); with SUM the second plane's at x[WPT, 2 WPT)
+    auto loadA = [&](int g, u64* x, auto sum_c) {
+        constexpr bool SUM = decltype(sum_c)::value;
         int kb;
         const int s = seg_of(g, kb);
         const int64_t k0 = (int64_t)kb * KB;
-        const u64* rp = (s ? pa[1] : pa[0]) + k0 * a.ldk;
-        if (TA) {
 #pragma unroll
-            for (int i = 0; i < WPT; ++i) x[i] = rp[i * a.ldk];
-        } else if (FAST) {
+        for (int h = 0; h < (SUM ? 2 : 1); ++h) {
+            const u64* rp = (h ? pa2 : s ? pa[1] : pa[0]) + k0 * a.ldk;
+            u64* xh = x + h * WPT;
+            if (TA) {
 #pragma unroll
-            for (int h = 0; h < WPT / 2; ++h) {
-                const ulonglong2 v = *(const ulonglong2*)(rp + 2 * h);
-                x[2 * h] = v.x;
-                x[2 * h + 1] = v.y;
+                for (int i = 0; i < WPT; ++i) xh[i] = rp[i * a.ldk];
+            } else if (FAST) {
+#pragma unroll
+                for (int q = 0; q < WPT / 2; ++q) {
+                    const ulonglong2 v = *(const ulonglong2*)(rp + 2 * q);
+                    xh[2 * q] = v.x;
+                    xh[2 * q + 1] = v.y;
+                }
+            } else {
+                raw8<false>(rp, k0 + part * WPT, a.K, xh);
             }
-        } else {
-            raw8<false>(rp, k0 + part * WPT, a.K, x);
         }
     };
     auto dmaB = [&](int g, int buf) {
@@ -467,11 +492,12 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
         }
     };
     // conversion piece c of WPT words (c = 0: balanced bytes; c >= 1: one 4x4 transpose)
-    auto piece = [&](int c, const u64 xc[WPT], u32 lo[WPT], u32 hi[WPT], u32 tq[4][4]) {
+    auto piece = [&](int c, const u64* xc, u32 lo[WPT], u32 hi[WPT], u32 tq[4][4], auto sum_c) {
+        constexpr bool SUM = decltype(sum_c)::value;
         if (c == 0) {
 #pragma unroll
             for (int j = 0; j < WPT; ++j) {
-                const u64 v = (xc[j] + OFF) ^ OFF;
+                const u64 v = ((SUM ? xc[j] + xc[WPT + j] : xc[j]) + OFF) ^ OFF;
                 lo[j] = (u32)v;
                 hi[j] = (u32)(v >> 32);
                 asm volatile("" : "+v"(lo[j]), "+v"(hi[j]));
@@ -484,88 +510,105 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
         }
     };
 
-    u64 xa[WPT], xb[WPT];
     int buf = 0;
-    if constexpr (!FAST) {
-        if (gbeg < gend) {
-            dmaB(gbeg, 0);
-            loadA(gbeg, xa);
-            u64 q[8];
-            to_digits(xa, q);
-            storeA8(As[0], astore, q);
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        for (int g = gbeg; g < gend; ++g) {
-            v4i B[8], A[8];
+    // SUM: the product's only segment is over the sum of two A planes
+    auto mainloop = [&](auto sum_c) {
+        constexpr bool SUM = decltype(sum_c)::value;
+        constexpr int XW = SUM ? 2 * WPT : WPT;
+        u64 xa[XW], xb[XW];
+        if constexpr (!FAST) {
+            auto convert = [&](int to) {
+                if (SUM)
 #pragma unroll
-            for (int d = 0; d < 8; ++d) B[d] = *(const v4i*)(Bs[buf] + d * PLANE + bread);
-#pragma unroll
-            for (int d = 0; d < 8; ++d) A[d] = *(const v4i*)(As[buf] + d * PLANE + aread);
-            const int g1 = min(g + 1, gend - 1);      // past the end: re-reads a valid block
-            dmaB(g1, buf ^ 1);
-            loadA(g1, xa);
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-#pragma unroll
-                for (int s = i; s < 8; ++s)
-                    acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i], B[s - i], acc[s], 0, 0, 0);
-            __builtin_amdgcn_sched_barrier(0);
-            u64 q[8];
-            to_digits(xa, q);
-            storeA8(As[buf ^ 1], astore, q);
-            wait_vm<0>();
-            __syncthreads();
-            buf ^= 1;
-        }
-    } else {
-        if (gbeg < gend) {
-            loadB(gbeg);
-            loadA(gbeg, xb);
-            u32 lo[WPT], hi[WPT], tq[4][4];
-#pragma unroll
-            for (int c = 0; c <= WPT / 2; ++c) piece(c, xb, lo, hi, tq);
-            store_digits(tq, 0);
-            storeB(0);
-            loadA(min(gbeg + 1, gend - 1), xa);
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        auto body = [&](int g, const u64 xc[WPT], u64 xn[WPT]) {
-            loadB(min(g + 1, gend - 1));              // past the end: re-reads valid blocks
-            loadA(min(g + 2, gend - 1), xn);
-            __builtin_amdgcn_sched_barrier(0);
-            v4i B[8];
-#pragma unroll
-            for (int d = 0; d < 8; ++d) B[d] = *(const v4i*)(Bs[buf] + d * PLANE + bread);
-            u32 lo[WPT], hi[WPT], tq[4][4];
-            v4i A = *(const v4i*)(As[buf] + aread);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                // the next row's A fragment is read while this row's MFMAs run
-                const v4i An = i < 7 ? *(const v4i*)(As[buf] + (i + 1) * PLANE + aread) : A;
-#pragma unroll
-                for (int s = i; s < 8; ++s)
-                    acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[s - i], acc[s], 0, 0, 0);
-                A = An;
-                // (the empty asm in piece() pins each part here: without it the compiler
-                // sinks the arithmetic to its use after the last MFMA)
-                piece(i, xc, lo, hi, tq);
-                __builtin_amdgcn_sched_barrier(0);
+                    for (int i = 0; i < WPT; ++i) xa[i] += xa[WPT + i];
+                u64 q[8];
+                to_digits(xa, q);
+                storeA8(As[to], astore, q);
+            };
+            if (gbeg < gend) {
+                dmaB(gbeg, 0);
+                loadA(gbeg, xa, sum_c);
+                convert(0);
             }
-            store_digits(tq, buf ^ 1);
-            storeB(buf ^ 1);
-            wait_vm<WPT / 2>();     // B of block g+1 is stored; A of block g+2 may fly on
+            __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
-            buf ^= 1;
-        };
-        int g = gbeg;
-        for (; g + 1 < gend; g += 2) {
-            body(g, xa, xb);
-            body(g + 1, xb, xa);
+            for (int g = gbeg; g < gend; ++g) {
+                v4i B[8], A[8];
+#pragma unroll
+                for (int d = 0; d < 8; ++d) B[d] = *(const v4i*)(Bs[buf] + d * PLANE + bread);
+#pragma unroll
+                for (int d = 0; d < 8; ++d) A[d] = *(const v4i*)(As[buf] + d * PLANE + aread);
+                const int g1 = min(g + 1, gend - 1);      // past the end: re-reads a valid block
+                dmaB(g1, buf ^ 1);
+                loadA(g1, xa, sum_c);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int s = i; s < 8; ++s)
+                        acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i], B[s - i], acc[s], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                convert(buf ^ 1);
+                wait_vm<0>();
+                __syncthreads();
+                buf ^= 1;
+            }
+        } else {
+            if (gbeg < gend) {
+                loadB(gbeg);
+                loadA(gbeg, xb, sum_c);
+                u32 lo[WPT], hi[WPT], tq[4][4];
+#pragma unroll
+                for (int c = 0; c <= WPT / 2; ++c) piece(c, xb, lo, hi, tq, sum_c);
+                store_digits(tq, 0);
+                storeB(0);
+                loadA(min(gbeg + 1, gend - 1), xa, sum_c);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            auto body = [&](int g, const u64* xc, u64* xn) {
+                loadB(min(g + 1, gend - 1));              // past the end: re-reads valid blocks
+                loadA(min(g + 2, gend - 1), xn, sum_c);
+                __builtin_amdgcn_sched_barrier(0);
+                v4i B[8];
+#pragma unroll
+                for (int d = 0; d < 8; ++d) B[d] = *(const v4i*)(Bs[buf] + d * PLANE + bread);
+                u32 lo[WPT], hi[WPT], tq[4][4];
+                v4i A = *(const v4i*)(As[buf] + aread);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    // the next row's A fragment is read while this row's MFMAs run
+                    const v4i An = i < 7 ? *(const v4i*)(As[buf] + (i + 1) * PLANE + aread) : A;
+#pragma unroll
+                    for (int s = i; s < 8; ++s)
+                        acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[s - i], acc[s], 0, 0, 0);
+                    A = An;
+                    // (the empty asm in piece() pins each part here: without it the compiler
+                    // sinks the arithmetic to its use after the last MFMA)
+                    piece(i, xc, lo, hi, tq, sum_c);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                store_digits(tq, buf ^ 1);
+                storeB(buf ^ 1);
+                // B of block g+1 is stored; the A words of block g+2 may still be in flight
+                wait_vm<(SUM ? 2 : 1) * (TA ? WPT : WPT / 2)>();
+                __syncthreads();
+                buf ^= 1;
+            };
+            int g = gbeg;
+            for (; g + 1 < gend; g += 2) {
+                body(g, xa, xb);
+                body(g + 1, xb, xa);
+            }
+            if (g < gend) body(g, xa, xb);
         }
-        if (g < gend) body(g, xa, xb);
+    };
+    // (one-tile FAST kernels convert 8 words per thread: a second plane would spill)
+    if constexpr (NS == 2 || !FAST) {
+        if (pa2) mainloop(std::true_type{});
+        else mainloop(std::false_type{});
+    } else {
+        mainloop(std::false_type{});
     }
 
     const int64_t n = r0b + wx * 32 + (lane & 31);
@@ -577,6 +620,10 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
         u64 val = 0;
 #pragma unroll
         for (int s = 0; s < 8; ++s) val += ((u64)(int64_t)acc[s][v]) << (8 * s);
+        if (a.part) {
+            a.part[((int64_t)split * a.nprod + prod) * a.M * a.N + m * a.N + n] = val;
+            continue;
+        }
         u64* p = P.C.p + m * P.C.s0 + n * P.C.s1;
         if (a.atomic) {
             atomicAdd((unsigned long long*)p, (unsigned long long)val);
@@ -680,33 +727,52 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         bool fast = ta || (kc && g.K % KB == 0 && g.A[0].s0 % 2 == 0);
         for (int p = 0; p < na && fast && !ta; ++p) fast = ((uintptr_t)(g.A[p].p + b * g.A[p].sb) & 15) == 0;
         const int ns = fast && tn >= 2 ? 2 : 1;
-        // K is split (atomic adds into a zeroed output) only when the 64 x 64 tiles number
-        // fewer than the CUs: measured, a split costs more than a half-filled second wave
+        // K is split when the 64 x 64 tiles number fewer than the CUs (measured: a split costs
+        // more than a half-filled second wave) and when it exceeds what the 32-bit digit sums
+        // hold.  The splits write partial sums to the workspace and one pass adds them up
+        // (atomic adds into the output only for accumulating callers without a workspace).
         const int64_t groups = tm * tn * nprod, fill = 256;
-        int64_t splits = 1;
-        bool dense = !a.D.p && !g.accumulate;
-        for (int p = 0; p < nprod; ++p)
-            dense = dense && a.prod[p].C.s1 == 1 && a.prod[p].C.s0 == g.N;
-        const bool too_long = maxseg * Kp > KSEG;
-        if (too_long && !g.accumulate && !dense) return gemm_u64(g, st);
-        if (dense && (too_long || (groups < fill && maxseg * Kp >= 2048))) {
-            for (int p = 0; p < nprod; ++p) {
+        const int64_t need = (maxseg * Kp + KSEG - 1) / KSEG;
+        int64_t splits = need;
+        if (groups < fill && maxseg * Kp >= 2048) {
+            const int64_t want = (4 * fill + groups - 1) / groups;
+            splits = std::max<int64_t>(splits, std::min<int64_t>(want, maxseg * Kp / 64));
+        }
+        const size_t plane = (size_t)nprod * g.M * g.N * 8;
+        const bool part_ok = g.ws_alloc != nullptr && plane * need <= PART_MAX;
+        if (part_ok) splits = std::min<int64_t>(splits, std::max<int64_t>(need, (int64_t)(PART_MAX / plane)));
+        else splits = need;
+        if (splits > 1 && !part_ok) {
+            // without room for partials: atomic adds, into a zeroed output when the caller
+            // does not accumulate (a dense output with nothing added)
+            bool dense = !g.accumulate && !a.D.p;
+            for (int p = 0; p < nprod; ++p) dense = dense && a.prod[p].C.s1 == 1 && a.prod[p].C.s0 == g.N;
+            if (!g.accumulate && !dense) return gemm_u64(g, st);
+            for (int p = 0; p < nprod && !g.accumulate; ++p) {
                 hipError_t e = hipMemsetAsync(a.prod[p].C.p, 0, (size_t)g.M * g.N * 8, st);
                 if (e != hipSuccess) return e;
             }
             a.atomic = 1;
         }
-        if (a.atomic) {
-            const int64_t want = (4 * fill + groups - 1) / groups;
-            splits = std::max<int64_t>(1, std::min<int64_t>(want, maxseg * Kp / 256));
-        }
-        splits = std::max<int64_t>(splits, (maxseg * Kp + KSEG - 1) / KSEG);
         // K blocks never straddle a segment (Kp is a multiple of KB); chunks may
         const int64_t kchunk = rup((maxseg * Kp + splits - 1) / splits, KB);
         splits = (maxseg * Kp + kchunk - 1) / kchunk;
         a.kchunk = kchunk;
         a.splits = (int)splits;
         if (nprod * splits > 65535) return hipErrorInvalidValue;
+        a.part = nullptr;
+        if (splits > 1 && part_ok) {
+            a.part = (u64*)g.ws_alloc(g.ws_self, plane * splits);
+            if (!a.part) return hipErrorOutOfMemory;
+            a.atomic = 0;
+        }
+        OutView outs[3];
+        for (int p = 0; p < nprod; ++p) outs[p] = a.prod[p].C;
+        auto finish = [&]() -> hipError_t {
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess || !a.part) return e;
+            return split_reduce(a.part, g.M, g.N, nprod, (int)splits, 1, outs, a.D, g.accumulate, st);
+        };
         if (two) {
             const int64_t nkb = Kp / KB, rows_pad = tn * TN;
             if (nkb * 2 > 0x7FFFFFFF || tn * tm * nprod * splits > 0x7FFFFFFF) return hipErrorInvalidValue;
@@ -724,18 +790,18 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             l.lda = ta ? 1 : g.A[0].s0;
             l.ldk = ta ? g.A[0].s1 : 1;
             l.nkb = (int)nkb; l.kcb = (int)(kchunk / KB); l.nprod = nprod; l.splits = (int)splits;
-            l.atomic = a.atomic; l.D = a.D;
+            l.atomic = a.atomic; l.D = a.D; l.part = a.part;
             const u64* Ap[3];
             for (int p = 0; p < na; ++p) Ap[p] = g.A[p].p + b * g.A[p].sb;
             if (!g.party) {
                 const int8_t* t0 = tiles(opnd(g.B[0], b, true, g.N));
                 if (!t0) return hipErrorOutOfMemory;
                 l.prod[0].nseg = 1;
-                l.prod[0].seg[0] = Seg2{Ap[0], t0};
+                l.prod[0].seg[0] = Seg2{Ap[0], nullptr, t0};
                 l.prod[0].C = a.prod[0].C;
             } else {
-                // planes 0, 1, 2 = m, [r]_1, [r]_2; signs and sums on the B side:
-                //   C0 = A1 (B1 + B2) + A2 (B1 + B2)
+                // planes 0, 1, 2 = m, [r]_1, [r]_2; signs and the B sum on the B side:
+                //   C0 = (A1 + A2)(B1 + B2)       (one segment over two A planes)
                 //   C1 = A1 Bm + Am B1
                 //   C2 = Am (Bm - B2) + A2 (-Bm)
                 const View* B = g.B;
@@ -745,11 +811,13 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
                 const int8_t* bm2 = tiles(combo(B, b, true, g.N, 0, 1, 2, -1));
                 const int8_t* nbm = tiles(combo(B, b, true, g.N, 0, -1, -1, 0));
                 if (!s12 || !bm || !b1 || !bm2 || !nbm) return hipErrorOutOfMemory;
-                const Seg2 segs[3][2] = {{{Ap[1], s12}, {Ap[2], s12}},
-                                         {{Ap[1], bm}, {Ap[0], b1}},
-                                         {{Ap[0], bm2}, {Ap[2], nbm}}};
+                // (kernels that convert 8 A words per thread take C0 as two segments)
+                const bool sum = ns == 2 || !fast;
+                const Seg2 segs[3][2] = {{{Ap[1], sum ? Ap[2] : nullptr, s12}, {Ap[2], nullptr, s12}},
+                                         {{Ap[1], nullptr, bm}, {Ap[0], nullptr, b1}},
+                                         {{Ap[0], nullptr, bm2}, {Ap[2], nullptr, nbm}}};
                 for (int p = 0; p < 3; ++p) {
-                    l.prod[p].nseg = 2;
+                    l.prod[p].nseg = p == 0 && sum ? 1 : 2;
                     l.prod[p].seg[0] = segs[p][0];
                     l.prod[p].seg[1] = segs[p][1];
                     l.prod[p].C = a.prod[p].C;
@@ -757,13 +825,16 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             }
             l.tn64 = (int)tn;
             l.tn = (int)((tn + ns - 1) / ns);
+            l.tm = (int)tm;
+            // about as many workgroups per group as one XCD holds at once (32 CUs)
+            l.rb = (int)std::max<int64_t>(1, std::min<int64_t>(tm, (ns == 2 ? 32 : 64) / l.tn));
             const dim3 gr((unsigned)(l.tn * tm * nprod * splits));
             if (ta && ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2, true>), gr, dim3(2 * NT), 0, st, l);
             else if (ta) hipLaunchKernelGGL((k_lgemm2<true, 1, true>), gr, dim3(NT), 0, st, l);
             else if (ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2>), gr, dim3(2 * NT), 0, st, l);
             else if (fast) hipLaunchKernelGGL((k_lgemm2<true, 1>), gr, dim3(NT), 0, st, l);
             else hipLaunchKernelGGL((k_lgemm2<false, 1>), gr, dim3(NT), 0, st, l);
-            hipError_t e = hipGetLastError();
+            hipError_t e = finish();
             if (e != hipSuccess) return e;
             continue;
         }
@@ -774,7 +845,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         else if (ak) hipLaunchKernelGGL((k_lgemm<true, false>), grid, dim3(NT), 0, st, a);
         else if (bk) hipLaunchKernelGGL((k_lgemm<false, true>), grid, dim3(NT), 0, st, a);
         else hipLaunchKernelGGL((k_lgemm<false, false>), grid, dim3(NT), 0, st, a);
-        hipError_t e = hipGetLastError();
+        hipError_t e = finish();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

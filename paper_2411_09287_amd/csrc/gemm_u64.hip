@@ -99,7 +99,7 @@ __device__ __forceinline__ void store(const OutView& o, int b, int64_t m, int64_
 }
 
 template <bool PARTY>
-__global__ __launch_bounds__(NT) void k_gemm_u64(GemmArgs g, int ksplit, int64_t kchunk) {
+__global__ __launch_bounds__(NT) void k_gemm_u64(GemmArgs g, int ksplit, int64_t kchunk, u64* part) {
     constexpr int NP = PARTY ? 3 : 1;
     constexpr int NA = PARTY ? 3 : 1;
     __shared__ u64 As[NP][BK][BM];
@@ -167,6 +167,7 @@ __global__ __launch_bounds__(NT) void k_gemm_u64(GemmArgs g, int ksplit, int64_t
         __syncthreads();
     }
 
+    // partial sums (split-K through part): plane (b, split, p) of M x N words
     const bool atomic = g.accumulate;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -179,10 +180,57 @@ __global__ __launch_bounds__(NT) void k_gemm_u64(GemmArgs g, int ksplit, int64_t
 #pragma unroll
             for (int p = 0; p < NA; ++p) {
                 u64 v = val(acc[p][i][j]);
+                if (part) {
+                    part[(((int64_t)b * ksplit + split) * NA + p) * g.M * g.N + m * g.N + n] = v;
+                    continue;
+                }
                 if (!PARTY && !atomic && g.Dadd.p) v += g.Dadd.p[b * g.Dadd.sb + m * g.Dadd.s0 + n * g.Dadd.s1];
                 store(g.C[p], b, m, n, v, atomic);
             }
         }
+    }
+}
+
+struct RedArgs {
+    const u64* part;
+    int64_t M, N;
+    int nprod, splits, batch, atomic;
+    OutView C[3];
+    View D;
+};
+
+// Block = 64 consecutive output words x W waves: wave w adds the partials of splits w,
+// w + W, ... for its 64 words (coalesced 512-byte reads), then the W sums are added in LDS.
+__global__ __launch_bounds__(1024) void k_split_reduce(RedArgs r) {
+    __shared__ u64 acc[16][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, W = blockDim.x >> 6;
+    const int64_t mn = r.M * r.N;
+    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = idx < (int64_t)r.batch * r.nprod * mn;
+    const int64_t e = idx % mn, bp = idx / mn;
+    const int p = (int)(bp % r.nprod);
+    const int64_t b = bp / r.nprod;
+    u64 v = 0;
+    if (live) {
+        const u64* q = r.part + (b * r.splits * r.nprod + p) * mn + e;
+        const int64_t step = (int64_t)r.nprod * mn;
+        int s = w;
+        for (; s + 3 * W < r.splits; s += 4 * W)
+            v += q[s * step] + q[(s + W) * step] + q[(s + 2 * W) * step] + q[(s + 3 * W) * step];
+        for (; s < r.splits; s += W) v += q[s * step];
+    }
+    acc[w][lane] = v;
+    __syncthreads();
+    if (w != 0 || !live) return;
+    for (int i = 1; i < W; ++i) v += acc[i][lane];
+    const int64_t m = e / r.N, n = e % r.N;
+    const OutView& o = r.C[p];
+    u64* dst = o.p + b * o.sb + m * o.s0 + n * o.s1;
+    if (r.atomic) {
+        atomicAdd((unsigned long long*)dst, (unsigned long long)v);
+    } else {
+        if (r.D.p) v += r.D.p[b * r.D.sb + m * r.D.s0 + n * r.D.s1];
+        *dst = v;
     }
 }
 
@@ -192,23 +240,52 @@ hipError_t gemm_u64(const GemmArgs& g, hipStream_t stream) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     const int64_t tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
     if (tm > 65535) return hipErrorInvalidValue;
+    // K is split when the output tiles number fewer than the CUs (or the caller accumulates):
+    // partial sums to the workspace and one reduction pass, else atomic adds (accumulating
+    // callers without a workspace)
+    const int nprod = g.party ? 3 : 1;
+    const int64_t tiles = tm * tn * g.batch;
     int ksplit = 1;
-    if (g.accumulate && g.K > BK) {
-        const int64_t tiles = tm * tn * g.batch;
+    const bool part_ok = g.ws_alloc != nullptr;
+    if (g.K > BK && (part_ok || g.accumulate) && (g.accumulate || tiles < 256)) {
         const int64_t want = (1024 + tiles - 1) / tiles;          // aim for ~1k workgroups
         const int64_t maxs = (g.K + BK - 1) / BK;                  // at least one K step per split
-        ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({want, maxs, 4096}));
+        int64_t cap = 4096;
+        if (part_ok) cap = std::min<int64_t>(cap, (int64_t)(PART_MAX / ((size_t)nprod * g.M * g.N * 8 * g.batch)));
+        ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({want, maxs, cap}));
     }
     int64_t kchunk = (g.K + ksplit - 1) / ksplit;
     kchunk = ((kchunk + BK - 1) / BK) * BK;
     ksplit = (int)((g.K + kchunk - 1) / kchunk);
     if (ksplit < 1) ksplit = 1;
     if ((int64_t)g.batch * ksplit > 65535) return hipErrorInvalidValue;
+    u64* part = nullptr;
+    if (ksplit > 1 && part_ok) {
+        part = (u64*)g.ws_alloc(g.ws_self, (size_t)g.batch * ksplit * nprod * g.M * g.N * 8);
+        if (!part) return hipErrorOutOfMemory;
+    }
     dim3 grid((unsigned)tn, (unsigned)tm, (unsigned)(g.batch * ksplit));
     if (g.party)
-        hipLaunchKernelGGL(k_gemm_u64<true>, grid, dim3(NT), 0, stream, g, ksplit, kchunk);
+        hipLaunchKernelGGL(k_gemm_u64<true>, grid, dim3(NT), 0, stream, g, ksplit, kchunk, part);
     else
-        hipLaunchKernelGGL(k_gemm_u64<false>, grid, dim3(NT), 0, stream, g, ksplit, kchunk);
+        hipLaunchKernelGGL(k_gemm_u64<false>, grid, dim3(NT), 0, stream, g, ksplit, kchunk, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !part) return e;
+    return split_reduce(part, g.M, g.N, nprod, ksplit, g.batch, g.C, g.Dadd, g.accumulate, stream);
+}
+
+hipError_t split_reduce(const u64* part, int64_t M, int64_t N, int nprod, int splits, int batch,
+                        const OutView* C, const View& D, bool atomic, hipStream_t stream) {
+    RedArgs r{};
+    r.part = part;
+    r.M = M; r.N = N; r.nprod = nprod; r.splits = splits; r.batch = batch; r.atomic = atomic ? 1 : 0;
+    for (int p = 0; p < nprod; ++p) r.C[p] = C[p];
+    r.D = nprod == 1 ? D : View{nullptr, 0, 0, 0};
+    const int64_t n = (int64_t)batch * nprod * M * N;
+    if (n == 0) return hipSuccess;
+    if ((n + 63) / 64 > 0x7FFFFFFF) return hipErrorInvalidValue;
+    const int W = std::min(splits, 16);
+    hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((n + 63) / 64)), dim3(64 * W), 0, stream, r);
     return hipGetLastError();
 }
 

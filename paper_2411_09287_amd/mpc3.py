@@ -171,7 +171,8 @@ class Context:
         _ck(lib().mpc3_ctx_create(seed, d, frac_bits, workspace_bytes, ctypes.c_void_p(st.cuda_stream),
                                   ctypes.byref(h)), "mpc3_ctx_create")
         self.h = h
-        self._keep = []          # operands the context still points at
+        # operands the context still points at, per kind of pending product
+        self._keep = {VERIFY_INNER: [], VERIFY_TRUNC: [], VERIFY_MULT: []}
 
     def close(self):
         if self.h:
@@ -224,7 +225,7 @@ class Context:
     def trunc_pair(self, n, t):
         p = DPair(n, self.device)
         _ck(lib().mpc3_trunc_pair(self.h, n, t, ctypes.byref(p.s)), "mpc3_trunc_pair")
-        self._keep.append(p)
+        self._keep[VERIFY_TRUNC].append(p)
         return p
 
     def inner(self, X, W, pair=None, out=None):
@@ -232,7 +233,7 @@ class Context:
         xs, ws, zs = X.c(), W.c(), Z.c()
         _ck(lib().mpc3_inner(self.h, ctypes.byref(xs), ctypes.byref(ws),
                              ctypes.byref(pair.s) if pair is not None else None, ctypes.byref(zs)), "mpc3_inner")
-        self._keep.append((X, W, Z))
+        self._keep[VERIFY_INNER].append((X, W, Z))
         return Z
 
     def im2col(self, x, B, H, W, C, KH, KW, pad):
@@ -252,7 +253,7 @@ class Context:
         c = DShare.empty(a.rows, a.cols, self.device)
         sa, sb, sc = a.c(), b.c(), c.c()
         _ck(lib().mpc3_mult(self.h, ctypes.byref(sa), ctypes.byref(sb), ctypes.byref(sc)), "mpc3_mult")
-        self._keep.append((a, b, c))
+        self._keep[VERIFY_MULT].append((a, b, c))
         return c
 
     def trunc(self, pair, Z):
@@ -264,8 +265,9 @@ class Context:
     def verify(self, R=-1, kinds=VERIFY_ALL):
         ok = ctypes.c_int(0)
         _ck(lib().mpc3_verify(self.h, R, kinds, ctypes.byref(ok)), "mpc3_verify")
-        if kinds == VERIFY_ALL:
-            self._keep = []
+        for k in self._keep:
+            if kinds & k:
+                self._keep[k] = []
         return bool(ok.value)
 
     def reconstruct(self, X, to_party=-1):
