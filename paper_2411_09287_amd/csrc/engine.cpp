@@ -539,19 +539,31 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
         const u64* Xc[3] = {it->X.m, it->X.r1, it->X.r2};
         const u64* Wc[3] = {it->W.m, it->W.r1, it->W.r2};
         const u64* Zc[3] = {it->Z.m, it->Z.r1, it->Z.r2};
-        u64* T = c->sc->words(N * 64);
-        for (int p = 0; p < 3; ++p) {
-            u64* U = XY + p * np * 64 + row * 64;
-            // x_k = r^{o_l} sum_m r^m X[m, k]
-            run_gemm(c, plain(K, 64, M, view(Xc[p], 1, K), view(lo, 64, 1), oview(U, 64, 1), false));
-            launch_gr_mul_rows(sigo, U, K, K, U, s);
-            // y_k = sum_n r^{M n} W[k, n]
-            run_gemm(c, plain(K, 64, N, view(Wc[p], N, 1), view(sig, 64, 1), oview(XY + (3 + p) * np * 64 + row * 64, 64, 1),
-                              false));
-            // T_n = sum_m r^m Z[m, n]; z += sum_n r^{o_l + M n} T_n (ring products, folded below)
-            run_gemm(c, plain(N, 64, M, view(Zc[p], 1, N), view(lo, 64, 1), oview(T, 64, 1), false));
-            run_gemm(c, plain(64, 64, N, view(sigo, 1, 64), view(T, 64, 1), oview(Cz + p * 4096, 64, 1), true));
-        }
+        u64* T = c->sc->words(3 * N * 64);
+        // one product per step for the three share planes (shared right operand)
+        auto three = [&](GemmArgs g, const u64* const* Ap, int64_t as0, int64_t as1, auto out) {
+            g.shared = 3;
+            for (int p = 0; p < 3; ++p) {
+                g.A[p] = view(Ap[p], as0, as1);
+                g.C[p] = out(p);
+            }
+            run_gemm(c, g);
+        };
+        u64* U = XY + row * 64;
+        // x_k = r^{o_l} sum_m r^m X[m, k]
+        three(plain(K, 64, M, View{}, view(lo, 64, 1), OutView{}, false), Xc, 1, K,
+              [&](int p) { return oview(U + p * np * 64, 64, 1); });
+        launch_gr_mul_rows(sigo, U, K, K, U, s, 3, np * 64);
+        // y_k = sum_n r^{M n} W[k, n]
+        three(plain(K, 64, N, View{}, view(sig, 64, 1), OutView{}, false), Wc, N, 1,
+              [&](int p) { return oview(XY + (3 + p) * np * 64 + row * 64, 64, 1); });
+        // T_n = sum_m r^m Z[m, n]; z += sum_n r^{o_l + M n} T_n (ring products, folded below;
+        // as the transposed product T^T r^{o_l + M n} into a transposed view of Cz)
+        three(plain(N, 64, M, View{}, view(lo, 64, 1), OutView{}, false), Zc, 1, N,
+              [&](int p) { return oview(T + p * N * 64, 64, 1); });
+        const u64* Tp[3] = {T, T + N * 64, T + 2 * N * 64};
+        three(plain(64, 64, N, View{}, view(sigo, 64, 1), OutView{}, true), Tp, 1, 64,
+              [&](int p) { return oview(Cz + p * 4096, 1, 64); });
         c->sc->restore(mk);
         row += K;
         off += M * N;

@@ -24,6 +24,7 @@ struct GemmArgs {
     int64_t M, N, K;
     int batch;
     bool party;
+    int shared;               // plain, 2 or 3: C[p] = A[p] B[0] for p < shared in one launch
     bool accumulate;          // C += A B with 64-bit atomic adds (C initialised by the caller)
     View A[3], B[3];          // plain uses index 0
     OutView C[3];

@@ -663,7 +663,7 @@ Opnd combo(const View* v, int64_t b, bool transpose, int64_t rows, int i0, int c
 hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     // Small products stay on the vector ALU, where the launch is cheaper.
-    if ((double)g.M * (double)g.N * (double)g.K < (double)(1 << 22) || g.K == 0) return gemm_u64(g, st);
+    if ((double)g.M * (double)g.N * (double)g.K < (double)(1 << 22) || g.K == 0) return gemm(g, 0, st);
     const int64_t tm = rup(g.M, TM) / TM, tn = rup(g.N, TN) / TN;
     const int64_t Kp = rup(g.K, KB);
     for (int b = 0; b < g.batch; ++b) {
@@ -675,14 +675,17 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         int nprod;
         int64_t maxseg;
         if (!g.party) {
-            nprod = 1;
+            // one product, or up to three A operands against one B (g.shared)
+            nprod = g.shared > 1 ? g.shared : 1;
             maxseg = 1;
-            Prod& P = a.prod[0];
-            P.nseg = 1;
-            P.a[0] = opnd(g.A[0], b, false, g.M);
-            P.b[0] = opnd(g.B[0], b, true, g.N);
-            P.C = g.C[0];
-            P.C.p += b * P.C.sb;
+            for (int p = 0; p < nprod; ++p) {
+                Prod& P = a.prod[p];
+                P.nseg = 1;
+                P.a[0] = opnd(g.A[p], b, false, g.M);
+                P.b[0] = opnd(g.B[0], b, true, g.N);
+                P.C = g.C[p];
+                P.C.p += b * P.C.sb;
+            }
         } else {
             // planes 0, 1, 2 = m, [r]_1, [r]_2
             nprod = 3;
@@ -717,7 +720,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         // stride and B is re-read by at least two row tiles; two 64-column tiles per
         // workgroup (one workgroup per CU) when rows are aligned, K is whole k-blocks and
         // N spans more than one tile
-        const int na = g.party ? 3 : 1;
+        const int na = g.party ? 3 : nprod;
         bool kc = tm >= 2 && g.ws_alloc, ta = kc && g.K % KB == 0;
         for (int p = 0; p < na; ++p) {
             kc = kc && g.A[p].s1 == 1 && g.A[p].s0 == g.A[0].s0;
@@ -747,7 +750,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             // does not accumulate (a dense output with nothing added)
             bool dense = !g.accumulate && !a.D.p;
             for (int p = 0; p < nprod; ++p) dense = dense && a.prod[p].C.s1 == 1 && a.prod[p].C.s0 == g.N;
-            if (!g.accumulate && !dense) return gemm_u64(g, st);
+            if (!g.accumulate && !dense) return gemm(g, 0, st);
             for (int p = 0; p < nprod && !g.accumulate; ++p) {
                 hipError_t e = hipMemsetAsync(a.prod[p].C.p, 0, (size_t)g.M * g.N * 8, st);
                 if (e != hipSuccess) return e;
@@ -796,9 +799,11 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             if (!g.party) {
                 const int8_t* t0 = tiles(opnd(g.B[0], b, true, g.N));
                 if (!t0) return hipErrorOutOfMemory;
-                l.prod[0].nseg = 1;
-                l.prod[0].seg[0] = Seg2{Ap[0], nullptr, t0};
-                l.prod[0].C = a.prod[0].C;
+                for (int p = 0; p < nprod; ++p) {
+                    l.prod[p].nseg = 1;
+                    l.prod[p].seg[0] = Seg2{Ap[p], nullptr, t0};
+                    l.prod[p].C = a.prod[p].C;
+                }
             } else {
                 // planes 0, 1, 2 = m, [r]_1, [r]_2; signs and the B sum on the B side:
                 //   C0 = (A1 + A2)(B1 + B2)       (one segment over two A planes)

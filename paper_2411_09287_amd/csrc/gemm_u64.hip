@@ -290,6 +290,19 @@ hipError_t split_reduce(const u64* part, int64_t M, int64_t N, int nprod, int sp
 }
 
 hipError_t gemm(const GemmArgs& g, int variant, hipStream_t stream) {
+    if (g.shared > 1 && (g.party || g.shared > 3 || g.Dadd.p)) return hipErrorInvalidValue;
+    if (variant == 0 && g.shared > 1) {
+        // the vector-ALU kernel takes the shared-B products one at a time
+        for (int p = 0; p < g.shared; ++p) {
+            GemmArgs s = g;
+            s.shared = 0;
+            s.A[0] = g.A[p];
+            s.C[0] = g.C[p];
+            hipError_t e = gemm(s, 0, stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     // the row tiles of both backends' two-dimensional grids stay below 65535: taller
     // products run as row slices (A, C and the added D advance by whole rows)
     const int64_t maxm = (int64_t)65535 * 64;
@@ -297,7 +310,7 @@ hipError_t gemm(const GemmArgs& g, int variant, hipStream_t stream) {
         GemmArgs s = g;
         s.M = std::min(maxm, g.M - r0);
         if (r0) {
-            for (int p = 0; p < (g.party ? 3 : 1); ++p) {
+            for (int p = 0; p < (g.party ? 3 : std::max(1, g.shared)); ++p) {
                 s.A[p].p += r0 * g.A[p].s0;
                 s.C[p].p += r0 * g.C[p].s0;
             }

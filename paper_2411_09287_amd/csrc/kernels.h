@@ -110,8 +110,10 @@ void launch_sym_level(int j, int64_t G, int t, const u64* B1, const u64* B2, u64
                       hipStream_t s);
 // rows out[i] = x^e * in[i] for e = 1, 2 (n rows of 64 words).
 void launch_xshift_rows(const u64* in, int64_t n, int e, u64* out, hipStream_t s);
-// out[i] = P[i / per] * Q[i] (ring products, one 64-lane group per row).
-void launch_gr_mul_rows(const u64* P, const u64* Q, int64_t n, int64_t per, u64* out, hipStream_t s);
+// out[i] = P[i / per] * Q[i] (ring products, one 64-lane group per row), for each of
+// `planes` planes of Q and out pstride words apart.
+void launch_gr_mul_rows(const u64* P, const u64* Q, int64_t n, int64_t per, u64* out, hipStream_t s, int planes = 1,
+                        int64_t pstride = 0);
 // One doubling level of a power table: out[len + i] = out[i] * P for i < cnt; Pn = P^2
 // when Pn is not null.
 void launch_pow_level(u64* out, int64_t len, int64_t cnt, const u64* P, u64* Pn, hipStream_t s);

@@ -751,14 +751,15 @@ __global__ void k_xshift_rows(const u64* in, int64_t n, int e, u64* out) {
     out[i * 64 + k] = a;
 }
 
-__global__ void k_gr_mul_rows(const u64* P, const u64* Q, int64_t per, u64* out) {
+__global__ void k_gr_mul_rows(const u64* P, const u64* Q, int64_t per, u64* out, int64_t pstride) {
     __shared__ u64 a[64], b[64], sh[64];
     const int k = threadIdx.x;
     const int64_t i = blockIdx.x;
+    const int64_t o = (int64_t)blockIdx.y * pstride + i * 64;    // plane blockIdx.y
     a[k] = P[(i / per) * 64 + k];
-    b[k] = Q[i * 64 + k];
+    b[k] = Q[o + k];
     __syncthreads();
-    out[i * 64 + k] = gr_mul_lane(a, b, sh, k);
+    out[o + k] = gr_mul_lane(a, b, sh, k);
 }
 
 
@@ -942,9 +943,10 @@ void launch_pow_ap(const u64* lo, const u64* hi, int64_t L, int64_t e0, int64_t 
     if (n <= 0) return;
     hipLaunchKernelGGL(k_pow_ap, dim3((unsigned)n), dim3(64), 0, s, lo, hi, L, e0, step, out);
 }
-void launch_gr_mul_rows(const u64* P, const u64* Q, int64_t n, int64_t per, u64* out, hipStream_t s) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_gr_mul_rows, dim3((unsigned)n), dim3(64), 0, s, P, Q, per, out);
+void launch_gr_mul_rows(const u64* P, const u64* Q, int64_t n, int64_t per, u64* out, hipStream_t s, int planes,
+                        int64_t pstride) {
+    if (n <= 0 || planes <= 0) return;
+    hipLaunchKernelGGL(k_gr_mul_rows, dim3((unsigned)n, (unsigned)planes), dim3(64), 0, s, P, Q, per, out, pstride);
 }
 
 
