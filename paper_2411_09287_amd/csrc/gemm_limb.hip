@@ -270,9 +270,16 @@ __device__ __forceinline__ int toff(int d, int r, int o) {
     return d * PLANE + r * KB + (((o >> 1) ^ swz(r)) << 4) + ((o & 1) << 3);
 }
 
-// Digit tiles of an operand (rows x K, any strides, optional two-plane combination):
-// tile (t, kb) at byte (t * nkb + kb) * TILE_BYTES; rows >= o.rows and k >= K are zero.
-__global__ void k_to_tiles(Opnd o, int64_t K, int64_t nkb, int64_t rows_pad, int8_t* out) {
+// Digit tiles of up to five operands (rows x K, any strides, optional two-plane
+// combination), operand blockIdx.y: tile (t, kb) at byte (t * nkb + kb) * TILE_BYTES;
+// rows >= o.rows and k >= K are zero.
+struct TileJob {
+    Opnd o[5];
+    int8_t* out[5];
+};
+__global__ void k_to_tiles(TileJob job, int64_t K, int64_t nkb, int64_t rows_pad) {
+    const Opnd& o = job.o[blockIdx.y];
+    int8_t* out = job.out[blockIdx.y];
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= rows_pad * nkb * 4) return;
     int64_t r, o8;
@@ -780,13 +787,19 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             const int64_t nkb = Kp / KB, rows_pad = tn * TN;
             if (nkb * 2 > 0x7FFFFFFF || tn * tm * nprod * splits > 0x7FFFFFFF) return hipErrorInvalidValue;
             const size_t tbytes = (size_t)tn * nkb * TILE_BYTES;
-            auto tiles = [&](const Opnd& bo) -> const int8_t* {
-                int8_t* tb = (int8_t*)g.ws_alloc(g.ws_self, tbytes);
-                if (!tb) return nullptr;
+            // the digit tiles of n B operands in one launch
+            auto tiles = [&](const Opnd* bo, int n, const int8_t** tb) -> bool {
+                TileJob job{};
+                for (int i = 0; i < n; ++i) {
+                    job.o[i] = bo[i];
+                    job.out[i] = (int8_t*)g.ws_alloc(g.ws_self, tbytes);
+                    if (!job.out[i]) return false;
+                    tb[i] = job.out[i];
+                }
                 const int64_t threads = rows_pad * nkb * 4;
-                hipLaunchKernelGGL(k_to_tiles, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, bo, g.K,
-                                   nkb, rows_pad, tb);
-                return tb;
+                hipLaunchKernelGGL(k_to_tiles, dim3((unsigned)((threads + 255) / 256), (unsigned)n), dim3(256), 0, st,
+                                   job, g.K, nkb, rows_pad);
+                return true;
             };
             L2Args l{};
             l.M = g.M; l.N = g.N; l.K = g.K;
@@ -797,8 +810,9 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             const u64* Ap[3];
             for (int p = 0; p < na; ++p) Ap[p] = g.A[p].p + b * g.A[p].sb;
             if (!g.party) {
-                const int8_t* t0 = tiles(opnd(g.B[0], b, true, g.N));
-                if (!t0) return hipErrorOutOfMemory;
+                const Opnd bo = opnd(g.B[0], b, true, g.N);
+                const int8_t* t0 = nullptr;
+                if (!tiles(&bo, 1, &t0)) return hipErrorOutOfMemory;
                 for (int p = 0; p < nprod; ++p) {
                     l.prod[p].nseg = 1;
                     l.prod[p].seg[0] = Seg2{Ap[p], nullptr, t0};
@@ -810,12 +824,12 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
                 //   C1 = A1 Bm + Am B1
                 //   C2 = Am (Bm - B2) + A2 (-Bm)
                 const View* B = g.B;
-                const int8_t* s12 = tiles(combo(B, b, true, g.N, 1, 1, 2, 1));
-                const int8_t* bm = tiles(combo(B, b, true, g.N, 0, 1, -1, 0));
-                const int8_t* b1 = tiles(combo(B, b, true, g.N, 1, 1, -1, 0));
-                const int8_t* bm2 = tiles(combo(B, b, true, g.N, 0, 1, 2, -1));
-                const int8_t* nbm = tiles(combo(B, b, true, g.N, 0, -1, -1, 0));
-                if (!s12 || !bm || !b1 || !bm2 || !nbm) return hipErrorOutOfMemory;
+                const Opnd bos[5] = {combo(B, b, true, g.N, 1, 1, 2, 1), combo(B, b, true, g.N, 0, 1, -1, 0),
+                                     combo(B, b, true, g.N, 1, 1, -1, 0), combo(B, b, true, g.N, 0, 1, 2, -1),
+                                     combo(B, b, true, g.N, 0, -1, -1, 0)};
+                const int8_t* tb[5];
+                if (!tiles(bos, 5, tb)) return hipErrorOutOfMemory;
+                const int8_t *s12 = tb[0], *bm = tb[1], *b1 = tb[2], *bm2 = tb[3], *nbm = tb[4];
                 // (kernels that convert 8 A words per thread take C0 as two segments)
                 const bool sum = ns == 2 || !fast;
                 const Seg2 segs[3][2] = {{{Ap[1], sum ? Ap[2] : nullptr, s12}, {Ap[2], nullptr, s12}},

@@ -102,33 +102,49 @@ __global__ void k_trunc_pair(int64_t n, int t, Keys k, u32 op, Inj g2x, Inj m1z,
     }
 }
 
-// Pi_Inner preprocessing: output-wire mask [r_Z] (fresh, or the truncation pair's r_x) and [Gamma]_1.
+// The words 8 blk0 .. 8 blk0 + 511 of G(key, tag, .) for one wave: each lane computes
+// block blk0 + lane, and the 64 x 8 words are exchanged through lds (64 x 9 words) so that
+// out[q] is word 8 blk0 + 64 q + lane (consecutive lanes, consecutive words).
+__device__ __forceinline__ void prg_wave512(const Key& k, const Tag& t, u64 blk0, u64* lds, u64 out[8]) {
+    const int lane = threadIdx.x & 63;
+    u64 w[8];
+    prg_block8(k, t, blk0 + lane, w);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) lds[lane * 9 + q] = w[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) out[q] = lds[(q * 8 + (lane >> 3)) * 9 + (lane & 7)];
+    __syncthreads();
+}
+
+// Pi_Inner preprocessing: output-wire mask [r_Z] (fresh, or the truncation pair's r_x) and
+// [Gamma]_1.  A wave covers 512 consecutive words; its lanes take consecutive words.
 __global__ void k_inner_pre(int64_t n, Keys k, u32 op, const u64* pm, const u64* p1, const u64* p2,
                             u64* zr1, u64* zr2, u64* g1) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t i0 = b * 8;
-    if (i0 >= n) return;
-    u64 w[8];
-    prg_block8(k.k01, make_tag(op, P_INNER_GAMMA, 1, 0), b, w);
+    __shared__ u64 lds[4][64 * 9];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t blk0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;   // the wave's first block
+    const int64_t base = blk0 * 8 + lane;
+    u64 w[8], v[8];
+    prg_wave512(k.k01, make_tag(op, P_INNER_GAMMA, 1, 0), blk0, lds[wv], w);
 #pragma unroll
     for (int q = 0; q < 8; ++q)
-        if (i0 + q < n) g1[i0 + q] = w[q];
+        if (base + 64 * q < n) g1[base + 64 * q] = w[q];
     if (pm) {   // P1: [r_x]_1 = m_{r_x} - [r_{r_x}]_1 ; P2: [r_x]_2 = -[r_{r_x}]_2
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int64_t i = i0 + q;
+            const int64_t i = base + 64 * q;
             if (i < n) {
                 zr1[i] = pm[i] - p1[i];
                 zr2[i] = 0 - p2[i];
             }
         }
     } else {
-        u64 v[8];
-        prg_block8(k.k01, make_tag(op, P_INNER_RZ, 1, 0), b, w);
-        prg_block8(k.k02, make_tag(op, P_INNER_RZ, 2, 0), b, v);
+        prg_wave512(k.k01, make_tag(op, P_INNER_RZ, 1, 0), blk0, lds[wv], w);
+        prg_wave512(k.k02, make_tag(op, P_INNER_RZ, 2, 0), blk0, lds[wv], v);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int64_t i = i0 + q;
+            const int64_t i = base + 64 * q;
             if (i < n) {
                 zr1[i] = w[q];
                 zr2[i] = v[q];
@@ -215,6 +231,59 @@ __global__ void k_im2col(const u64* x, int B, int H, int W, int C, int KH, int K
     u64 v = 0;
     if (ih >= 0 && ih < H && iw >= 0 && iw < W) v = x[(((int64_t)b * H + ih) * W + iw) * C + c];
     out[idx] = v;
+}
+
+// floor(n / d) for n < 2^31 by one multiply and shift: with s = ceil(log2 d) and
+// M = ceil(2^(32+s) / d), M d = 2^(32+s) + e (0 <= e < d) and n e < 2^(32+s), so the error
+// term stays below 1/d and the quotient is exact.
+struct FastDiv {
+    u64 M;
+    u32 d;
+    int sh;
+};
+__host__ inline FastDiv make_fastdiv(u32 d) {
+    FastDiv f{};
+    f.d = d;
+    f.sh = 0;
+    while ((1ull << f.sh) < d) ++f.sh;
+    const u64 p = 1ull << (32 + f.sh);
+    f.M = p / d + (p % d ? 1 : 0);
+    return f;
+}
+__device__ __forceinline__ u32 fdiv(u32 n, const FastDiv& f) { return (u32)(((u64)n * f.M) >> (32 + f.sh)); }
+
+struct Im2colArgs {
+    const u64* x[3];
+    u64* out[3];
+    int H, W, C, KW, OH, OW, pad;
+    u32 K, total;          // words per output row; V-word groups in a plane
+    FastDiv fK, fC, fKW, fOW, fOH;
+};
+
+// V consecutive output words per thread (V = 2: 16-byte loads and stores, C and K even),
+// 32-bit index arithmetic; blockIdx.y is the share plane.
+template <int V>
+__global__ void k_im2col3(Im2colArgs a) {
+    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.total) return;
+    const u64* x = a.x[blockIdx.y];
+    u64* out = a.out[blockIdx.y];
+    const u32 w = i * V;                          // word index within the plane
+    const u32 row = fdiv(w, a.fK), col = w - row * a.K;
+    const u32 seg = fdiv(col, a.fC), c = col - seg * a.C;
+    const u32 kh = fdiv(seg, a.fKW), kw = seg - kh * a.KW;
+    const u32 t = fdiv(row, a.fOW), ow = row - t * a.OW;
+    const u32 b = fdiv(t, a.fOH), oh = t - b * a.OH;
+    const int ih = (int)oh + (int)kh - a.pad, iw = (int)ow + (int)kw - a.pad;
+    const bool in = ih >= 0 && ih < a.H && iw >= 0 && iw < a.W;
+    const int64_t src = (((int64_t)b * a.H + ih) * a.W + iw) * a.C + c;
+    if (V == 2) {
+        ulonglong2 v = {0, 0};
+        if (in) v = *(const ulonglong2*)(x + src);
+        *(ulonglong2*)(out + w) = v;
+    } else {
+        out[w] = in ? x[src] : 0;
+    }
 }
 
 __global__ void k_sumpool2(const u64* x, int B, int H, int W, int C, u64* out) {
@@ -825,6 +894,7 @@ void launch_trunc_pair(int64_t n, int t, const Keys& k, u32 op, Inj g2x, Inj m1z
 void launch_inner_pre(int64_t n, const Keys& k, u32 op, const u64* pm, const u64* p1, const u64* p2,
                       u64* zr1, u64* zr2, u64* g1, hipStream_t s) {
     if (n <= 0) return;
+    static_assert(TPB == 256, "k_inner_pre holds four waves' exchange buffers");
     hipLaunchKernelGGL(k_inner_pre, dim3(nblocks((n + 7) / 8, TPB)), dim3(TPB), 0, s, n, k, op, pm, p1, p2, zr1,
                        zr2, g1);
 }
@@ -854,6 +924,36 @@ void launch_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int
     if (total <= 0) return;
     hipLaunchKernelGGL(k_im2col, dim3(nblocks(total, TPB)), dim3(TPB), 0, s, x, B, H, W, C, KH, KW, pad, OH, OW,
                        out);
+}
+
+void launch_im2col3(const u64* const x[3], int B, int H, int W, int C, int KH, int KW, int pad, u64* const out[3],
+                    hipStream_t s) {
+    const int OH = H + 2 * pad - KH + 1, OW = W + 2 * pad - KW + 1;
+    const int64_t K = (int64_t)KH * KW * C;
+    const int64_t total = (int64_t)B * OH * OW * K;
+    if (total <= 0) return;
+    bool aligned = true;
+    for (int p = 0; p < 3; ++p) aligned = aligned && (((uintptr_t)x[p] | (uintptr_t)out[p]) & 15) == 0;
+    if (total >= ((int64_t)1 << 31)) {       // beyond 32-bit word indices: one word per thread
+        for (int p = 0; p < 3; ++p) launch_im2col(x[p], B, H, W, C, KH, KW, pad, out[p], s);
+        return;
+    }
+    Im2colArgs a{};
+    for (int p = 0; p < 3; ++p) {
+        a.x[p] = x[p];
+        a.out[p] = out[p];
+    }
+    a.H = H; a.W = W; a.C = C; a.KW = KW; a.OH = OH; a.OW = OW; a.pad = pad;
+    a.K = (u32)K;
+    a.fK = make_fastdiv((u32)K); a.fC = make_fastdiv((u32)C); a.fKW = make_fastdiv((u32)KW);
+    a.fOW = make_fastdiv((u32)OW); a.fOH = make_fastdiv((u32)OH);
+    if (aligned && C % 2 == 0) {
+        a.total = (u32)(total / 2);
+        hipLaunchKernelGGL(k_im2col3<2>, dim3(nblocks(a.total, TPB), 3), dim3(TPB), 0, s, a);
+    } else {
+        a.total = (u32)total;
+        hipLaunchKernelGGL(k_im2col3<1>, dim3(nblocks(a.total, TPB), 3), dim3(TPB), 0, s, a);
+    }
 }
 void launch_sumpool2(const u64* x, int B, int H, int W, int C, u64* out, hipStream_t s) {
     const int64_t total = (int64_t)B * (H / 2) * (W / 2) * C;

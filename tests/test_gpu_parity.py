@@ -198,7 +198,8 @@ def test_reconstruct_requires_verification():
     c.reconstruct(Z)
 
 
-@pytest.mark.parametrize("B,H,W,C,KH,KW,pad", [(2, 6, 5, 3, 3, 3, 1), (1, 8, 8, 1, 5, 5, 0), (3, 4, 4, 2, 3, 3, 1)])
+@pytest.mark.parametrize("B,H,W,C,KH,KW,pad", [(2, 6, 5, 3, 3, 3, 1), (1, 8, 8, 1, 5, 5, 0), (3, 4, 4, 2, 3, 3, 1),
+                                                (2, 9, 7, 16, 3, 3, 1), (1, 5, 6, 64, 2, 3, 0)])
 def test_im2col_parity(B, H, W, C, KH, KW, pad):
     g = np.random.default_rng(B * H)
     x0 = u64(g, B, H, W, C)
