@@ -400,6 +400,22 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
                            i_h2, h2, slot(v, MPC3_LOG_H2_M1, k), slot(v, MPC3_LOG_H2_M2, k),
                            slot(v, MPC3_LOG_H2_G2, k));
         } else {
+            // h(0) and h(x) are independent: h(x) runs on a side stream (its workspace comes
+            // from the same bump allocator, so nothing is shared) and joins before round_finish
+            int lane_i = 0;
+            while (lane_i < mpc3_ctx::NV && c->vs[lane_i] != s) ++lane_i;
+            hipStream_t side = c->vs[(lane_i + 1) % mpc3_ctx::NV];
+            ck(hipEventRecord(c->ev_fork2, s));
+            ck(hipStreamWaitEvent(side, c->ev_fork2, 0));
+            {   // h(x) = sum f_i(x) g_i(x)
+                c->cs = side;
+                const u64* A[3] = {F2, F2 + half * 64, F2 + 2 * half * 64};
+                const u64* B[3] = {F2 + 3 * half * 64, F2 + 4 * half * 64, F2 + 5 * half * 64};
+                polyevl_run(c, v, half, A, 64, B, 64, P_VER_H2_R, P_VER_H2_GAMMA, sub, Inj{-1, 0}, i_h2, h2,
+                            slot(v, MPC3_LOG_H2_M1, k), slot(v, MPC3_LOG_H2_M2, k), slot(v, MPC3_LOG_H2_G2, k),
+                            nullptr, nullptr);
+                c->cs = s;
+            }
             {   // h(0) = sum f_i(0) g_i(0): rows 2i of x and y
                 const u64* A[3] = {XY, XY + n * 64, XY + 2 * n * 64};
                 const u64* B[3] = {XY + 3 * n * 64, XY + 4 * n * 64, XY + 5 * n * 64};
@@ -407,13 +423,8 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
                             slot(v, MPC3_LOG_H0_M1, k), slot(v, MPC3_LOG_H0_M2, k), slot(v, MPC3_LOG_H0_G2, k),
                             nullptr, nullptr);
             }
-            {   // h(x) = sum f_i(x) g_i(x)
-                const u64* A[3] = {F2, F2 + half * 64, F2 + 2 * half * 64};
-                const u64* B[3] = {F2 + 3 * half * 64, F2 + 4 * half * 64, F2 + 5 * half * 64};
-                polyevl_run(c, v, half, A, 64, B, 64, P_VER_H2_R, P_VER_H2_GAMMA, sub, Inj{-1, 0}, i_h2, h2,
-                            slot(v, MPC3_LOG_H2_M1, k), slot(v, MPC3_LOG_H2_M2, k), slot(v, MPC3_LOG_H2_G2, k),
-                            nullptr, nullptr);
-            }
+            ck(hipEventRecord(c->ev_join2[0], side));
+            ck(hipStreamWaitEvent(s, c->ev_join2[0], 0));
         }
         c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
         u64* zeta = round_finish(c, v, sub, k, h0, h2, z);

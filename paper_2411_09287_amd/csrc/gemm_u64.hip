@@ -98,12 +98,16 @@ __device__ __forceinline__ void store(const OutView& o, int b, int64_t m, int64_
         *p = v;
 }
 
-template <bool PARTY>
+// MODE 0: plain; 1: party (three sums from the share planes); 2: three A planes against
+// one B (shared right operand), three outputs.
+template <int MODE>
 __global__ __launch_bounds__(NT) void k_gemm_u64(GemmArgs g, int ksplit, int64_t kchunk, u64* part) {
-    constexpr int NP = PARTY ? 3 : 1;
-    constexpr int NA = PARTY ? 3 : 1;
+    constexpr bool PARTY = MODE == 1;
+    constexpr int NP = MODE != 0 ? 3 : 1;      // A planes
+    constexpr int NB = PARTY ? 3 : 1;          // B planes
+    constexpr int NA = MODE != 0 ? 3 : 1;      // accumulators
     __shared__ u64 As[NP][BK][BM];
-    __shared__ u64 Bs[NP][BK][BN];
+    __shared__ u64 Bs[NB][BK][BN];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     const int b = blockIdx.z / ksplit, split = blockIdx.z % ksplit;
     const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
@@ -120,20 +124,24 @@ __global__ __launch_bounds__(NT) void k_gemm_u64(GemmArgs g, int ksplit, int64_t
 
     for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
         load_a<NP>(As, g, b, m0, k0, kend, tid);
-        load_b<NP>(Bs, g, b, n0, k0, kend, tid);
+        load_b<NB>(Bs, g, b, n0, k0, kend, tid);
         __syncthreads();
 #pragma unroll 4
         for (int kk = 0; kk < BK; ++kk) {
             if constexpr (!PARTY) {
-                u64 a[4], bb[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) a[i] = As[0][kk][ty * 4 + i];
+                u64 bb[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) bb[j] = Bs[0][kk][tx * 4 + j];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int p = 0; p < NA; ++p) {
+                    u64 a[4];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) mac(acc[0][i][j], a[i], bb[j]);
+                    for (int i = 0; i < 4; ++i) a[i] = As[p][kk][ty * 4 + i];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) mac(acc[p][i][j], a[i], bb[j]);
+                }
             } else {
                 u64 am[4], a1[4], ra[4], na2[4], bm[4], b1[4], rb[4], bd[4];
 #pragma unroll
@@ -243,7 +251,7 @@ hipError_t gemm_u64(const GemmArgs& g, hipStream_t stream) {
     // K is split when the output tiles number fewer than the CUs (or the caller accumulates):
     // partial sums to the workspace and one reduction pass, else atomic adds (accumulating
     // callers without a workspace)
-    const int nprod = g.party ? 3 : 1;
+    const int nprod = g.party || g.shared == 3 ? 3 : 1;
     const int64_t tiles = tm * tn * g.batch;
     int ksplit = 1;
     const bool part_ok = g.ws_alloc != nullptr;
@@ -266,9 +274,11 @@ hipError_t gemm_u64(const GemmArgs& g, hipStream_t stream) {
     }
     dim3 grid((unsigned)tn, (unsigned)tm, (unsigned)(g.batch * ksplit));
     if (g.party)
-        hipLaunchKernelGGL(k_gemm_u64<true>, grid, dim3(NT), 0, stream, g, ksplit, kchunk, part);
+        hipLaunchKernelGGL(k_gemm_u64<1>, grid, dim3(NT), 0, stream, g, ksplit, kchunk, part);
+    else if (g.shared == 3)
+        hipLaunchKernelGGL(k_gemm_u64<2>, grid, dim3(NT), 0, stream, g, ksplit, kchunk, part);
     else
-        hipLaunchKernelGGL(k_gemm_u64<false>, grid, dim3(NT), 0, stream, g, ksplit, kchunk, part);
+        hipLaunchKernelGGL(k_gemm_u64<0>, grid, dim3(NT), 0, stream, g, ksplit, kchunk, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !part) return e;
     return split_reduce(part, g.M, g.N, nprod, ksplit, g.batch, g.C, g.Dadd, g.accumulate, stream);
@@ -291,7 +301,7 @@ hipError_t split_reduce(const u64* part, int64_t M, int64_t N, int nprod, int sp
 
 hipError_t gemm(const GemmArgs& g, int variant, hipStream_t stream) {
     if (g.shared > 1 && (g.party || g.shared > 3 || g.Dadd.p)) return hipErrorInvalidValue;
-    if (variant == 0 && g.shared > 1) {
+    if (variant == 0 && g.shared == 2) {
         // the vector-ALU kernel takes the shared-B products one at a time
         for (int p = 0; p < g.shared; ++p) {
             GemmArgs s = g;

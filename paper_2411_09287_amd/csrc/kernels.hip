@@ -351,11 +351,28 @@ __device__ u64 gr_mul_lane(const u64* a, const u64* b, u64* sh, int k) {
     return reduce_lane(lo, hi, sh, k);
 }
 
+// Words 0..63 of G(key_j, tag_j) for three streams j into out[j][.]: thread t < 24 computes
+// block t % 8 of stream t / 8 (one ChaCha block per eight words).  Every thread of the
+// block calls it (it synchronises the block; blockDim.x >= 24).
+__device__ void prg_rows3(const Key& k0, const Tag& t0, const Key& k1, const Tag& t1, const Key& k2,
+                          const Tag& t2, u64 (*out)[64]) {
+    const int t = threadIdx.x;
+    if (t < 24) {
+        const int j = t >> 3, b = t & 7;
+        u64 w[8];
+        prg_block8(j == 0 ? k0 : j == 1 ? k1 : k2, j == 0 ? t0 : j == 1 ? t1 : t2, (u64)b, w);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) out[j][8 * b + q] = w[q];
+    }
+    __syncthreads();
+}
+
 __global__ void k_random_gr(Keys k, u32 op, u32 purpose, u32 sub, u64* share3, u64* value, u64* log) {
+    __shared__ u64 rows[3][64];
     const int c = threadIdx.x;
-    const u64 m = prg_word(k.k12, make_tag(op, purpose, 0, sub), c);
-    const u64 r1 = prg_word(k.k01, make_tag(op, purpose, 1, sub), c);
-    const u64 r2 = prg_word(k.k02, make_tag(op, purpose, 2, sub), c);
+    prg_rows3(k.k12, make_tag(op, purpose, 0, sub), k.k01, make_tag(op, purpose, 1, sub), k.k02,
+              make_tag(op, purpose, 2, sub), rows);
+    const u64 m = rows[0][c], r1 = rows[1][c], r2 = rows[2][c];
     if (share3) {
         share3[c] = m;
         share3[64 + c] = r1;
@@ -471,11 +488,13 @@ __global__ void k_polyevl_finish(PolyEvlArgs a) {
         s1 = fold_block(a.C + 4096, tile, part, sh, t);      // sum m_a r1_b + m_b r1_a (P1)
         s2 = fold_block(a.C + 8192, tile, part, sh, t);      // sum m_a (m_b - r2_b) - r2_a m_b (P2)
     }
+    u64 (*rows)[64] = (u64(*)[64])part;                       // part is free again here
+    __syncthreads();
+    prg_rows3(a.k.k01, make_tag(a.op, a.pr, 1, a.sub), a.k.k02, make_tag(a.op, a.pr, 2, a.sub), a.k.k01,
+              make_tag(a.op, a.pg, 1, a.sub), rows);
     if (t < 64) {
         const int k = t;
-        const u64 rc1 = prg_word(a.k.k01, make_tag(a.op, a.pr, 1, a.sub), k);
-        const u64 rc2 = prg_word(a.k.k02, make_tag(a.op, a.pr, 2, a.sub), k);
-        const u64 g1 = prg_word(a.k.k01, make_tag(a.op, a.pg, 1, a.sub), k);
+        const u64 rc1 = rows[0][k], rc2 = rows[1][k], g1 = rows[2][k];
         u64 g2 = s0 + rc1 + rc2 - g1;                     // P0 -> P2
         if (k == a.inj_g2) g2 += a.e_g2;
         u64 m1 = g1 - s1;                                 // P1 -> P2
@@ -544,10 +563,10 @@ __global__ void k_round_finish(RoundArgs a) {
     __shared__ u64 opa[4][64], opb[4][64], res[4][64];
     __shared__ u64 zeta[64], zm1[64], zmx[64], L[3][64], hh[3][3][64];
     const int t = threadIdx.x, w = t >> 6, k = t & 63;
+    prg_rows3(a.k.k12, make_tag(a.op, P_VER_ZETA, 0, a.sub), a.k.k01, make_tag(a.op, P_VER_ZETA, 1, a.sub), a.k.k02,
+              make_tag(a.op, P_VER_ZETA, 2, a.sub), res);
     if (w == 0) {
-        const u64 m = prg_word(a.k.k12, make_tag(a.op, P_VER_ZETA, 0, a.sub), k);
-        const u64 r1 = prg_word(a.k.k01, make_tag(a.op, P_VER_ZETA, 1, a.sub), k);
-        const u64 r2 = prg_word(a.k.k02, make_tag(a.op, P_VER_ZETA, 2, a.sub), k);
+        const u64 m = res[0][k], r1 = res[1][k], r2 = res[2][k];
         const u64 z = m - r1 - r2;                   // revealed point
         zeta[k] = z;
         zm1[k] = z - (k == 0 ? 1 : 0);               // zeta - 1
