@@ -199,6 +199,84 @@ __global__ __launch_bounds__(NT) void k_gemm_u64(GemmArgs g, int ksplit, int64_t
     }
 }
 
+// Small outputs (M, N <= 64): a workgroup per 4 x 4 output block, its 256 threads splitting K
+// (thread t takes k = t, t + 256, ...) and adding their sums in a wave reduction and LDS.
+// MODE as for k_gemm_u64.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm_kpar(GemmArgs g) {
+    constexpr bool PARTY = MODE == 1;
+    constexpr int NP = MODE != 0 ? 3 : 1;
+    constexpr int NB = PARTY ? 3 : 1;
+    constexpr int NA = MODE != 0 ? 3 : 1;
+    constexpr int NV = NA * 16;
+    __shared__ u64 red[4][NV];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int b = blockIdx.z;
+    const int64_t m0 = (int64_t)blockIdx.y * 4, n0 = (int64_t)blockIdx.x * 4;
+    u64 acc[NA][4][4];
+#pragma unroll
+    for (int p = 0; p < NA; ++p)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[p][i][j] = 0;
+    for (int64_t k = t; k < g.K; k += 256) {
+        u64 a[NP][4], bb[NB][4];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const View& v = g.A[p];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                a[p][i] = m0 + i < g.M ? v.p[b * v.sb + (m0 + i) * v.s0 + k * v.s1] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const View& v = g.B[q];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bb[q][j] = n0 + j < g.N ? v.p[b * v.sb + k * v.s0 + (n0 + j) * v.s1] : 0;
+        }
+        if constexpr (PARTY) {
+            // planes 0, 1, 2 = m, [r]_1, [r]_2 (sums as in k_gemm_u64)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[0][i][j] += (a[1][i] + a[2][i]) * (bb[1][j] + bb[2][j]);
+                    acc[1][i][j] += a[0][i] * bb[1][j] + a[1][i] * bb[0][j];
+                    acc[2][i][j] += a[0][i] * (bb[0][j] - bb[2][j]) - a[2][i] * bb[0][j];
+                }
+        } else {
+#pragma unroll
+            for (int p = 0; p < NA; ++p)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[p][i][j] += a[p][i] * bb[0][j];
+        }
+    }
+    // wave sums, then the four waves through LDS
+#pragma unroll
+    for (int p = 0; p < NA; ++p)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                u64 v = acc[p][i][j];
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+                if (lane == 0) red[w][(p * 4 + i) * 4 + j] = v;
+            }
+    __syncthreads();
+    if (t >= NV) return;
+    const int p = t >> 4, i = (t >> 2) & 3, j = t & 3;
+    const int64_t m = m0 + i, n = n0 + j;
+    if (m >= g.M || n >= g.N) return;
+    u64 v = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+    if (MODE == 0 && !g.accumulate && g.Dadd.p) v += g.Dadd.p[b * g.Dadd.sb + m * g.Dadd.s0 + n * g.Dadd.s1];
+    store(g.C[p], b, m, n, v, g.accumulate);
+}
+
 struct RedArgs {
     const u64* part;
     int64_t M, N;
@@ -246,6 +324,14 @@ __global__ __launch_bounds__(1024) void k_split_reduce(RedArgs r) {
 
 hipError_t gemm_u64(const GemmArgs& g, hipStream_t stream) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    if (g.M <= 64 && g.N <= 64 && g.K <= 1024 && g.batch <= 65535) {
+        // one output tile: K across the threads of 4 x 4 output blocks
+        const dim3 grid((unsigned)((g.N + 3) / 4), (unsigned)((g.M + 3) / 4), (unsigned)g.batch);
+        if (g.party) hipLaunchKernelGGL(k_gemm_kpar<1>, grid, dim3(256), 0, stream, g);
+        else if (g.shared == 3) hipLaunchKernelGGL(k_gemm_kpar<2>, grid, dim3(256), 0, stream, g);
+        else hipLaunchKernelGGL(k_gemm_kpar<0>, grid, dim3(256), 0, stream, g);
+        return hipGetLastError();
+    }
     const int64_t tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
     if (tm > 65535) return hipErrorInvalidValue;
     // K is split when the output tiles number fewer than the CUs (or the caller accumulates):
@@ -301,6 +387,9 @@ hipError_t split_reduce(const u64* part, int64_t M, int64_t N, int nprod, int sp
 
 hipError_t gemm(const GemmArgs& g, int variant, hipStream_t stream) {
     if (g.shared > 1 && (g.party || g.shared > 3 || g.Dadd.p)) return hipErrorInvalidValue;
+    // one small output tile: the K-parallel kernel, whichever backend was asked for (both
+    // give the exact result)
+    if (g.M <= 64 && g.N <= 64 && g.K <= 1024 && g.shared != 2) return gemm_u64(g, stream);
     if (variant == 0 && g.shared == 2) {
         // the vector-ALU kernel takes the shared-B products one at a time
         for (int p = 0; p < g.shared; ++p) {
