@@ -365,11 +365,13 @@ void polyevl_from(mpc3_ctx* c, const VerCtx& v, const u64* C, uint32_t pr, uint3
 }
 
 // The Lagrange step of a round: reveal zeta, update z, return zeta.
-u64* round_finish(mpc3_ctx* c, const VerCtx& v, uint32_t sub, int k, const u64* h0, const u64* h2, u64* z) {
+// (Wz: the multiplication matrix of the revealed point, written by the same launch)
+u64* round_finish(mpc3_ctx* c, const VerCtx& v, uint32_t sub, int k, const u64* h0, const u64* h2, u64* z,
+                  u64* Wz) {
     u64* zeta = c->sc->words(64);
     RoundArgs ra{};
     ra.k = c->keys; ra.op = v.op; ra.sub = sub; ra.inv = c->inv_dev; ra.h0 = h0; ra.h2 = h2; ra.z = z;
-    ra.zeta_out = zeta; ra.log_zeta = slot(v, MPC3_LOG_ZETA, k);
+    ra.zeta_out = zeta; ra.log_zeta = slot(v, MPC3_LOG_ZETA, k); ra.mat_out = Wz;
     launch_round_finish(ra, c->cs);
     count_reveal(c, MPC3_PH_VERIFY_ONLINE);
     return zeta;
@@ -427,10 +429,9 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
             ck(hipStreamWaitEvent(s, c->ev_join2[0], 0));
         }
         c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
-        u64* zeta = round_finish(c, v, sub, k, h0, h2, z);
         // fold: row i <- f_i(0) + zeta (f_i(1) - f_i(0)) on every stored plane
         u64* Wz = c->sc->words(4096);
-        launch_mulmat(zeta, 64, 1, Wz, s);
+        round_finish(c, v, sub, k, h0, h2, z, Wz);
         u64* XYn = c->sc->words(np * half * 64);
         // the planes are stacked, so the np planes run as one product of np * half rows:
         // row c * half + i of D and of the output, row 2 (c * half + i) of XY (n = 2 half)
@@ -700,9 +701,8 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
                      take_ver(c, MPC3_SITE_VER_H2_GAMMA2, v.inst, j), h2, slot(v, MPC3_LOG_H2_M1, j),
                      slot(v, MPC3_LOG_H2_M2, j), slot(v, MPC3_LOG_H2_G2, j));
         c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
-        u64* zeta = round_finish(c, v, sub, j, h0, h2, z);
         // tables for j + 1 folds
-        launch_mulmat(zeta, 64, 1, Wz, s);
+        round_finish(c, v, sub, j, h0, h2, z, Wz);
         ck(hipMemcpyAsync(Zn, Z, (size_t)nu * 512, hipMemcpyDeviceToDevice, s));
         run_gemm(c, plain(nu, 64, 64, view(Z, 64, 1), view(Wz, 64, 1), oview(Zn + nu * 64, 64, 1), false));
         run_gemm(c, plain(nu, 64, 64, view(Zn + nu * 64, 64, 1), view(Wz, 64, 1), oview(Zn + 2 * nu * 64, 64, 1),

@@ -76,6 +76,7 @@ struct RoundArgs {
     u64* z;                // share (3*64), updated in place
     u64* zeta_out;         // 64
     u64* log_zeta;         // nullable
+    u64* mat_out;          // nullable: multiplication matrix of zeta (64 x 64, row j = zeta x^j)
 };
 void launch_round_finish(const RoundArgs& a, hipStream_t s);
 // x'_i = Pi_Mult over GR of x_i and alpha from the party products (n x 64 each), with fresh masks.

@@ -615,6 +615,20 @@ __global__ void k_round_finish(RoundArgs a) {
         __syncthreads();
     }
     (void)acc;
+    if (a.mat_out && w == 0) {
+        // row j + 1 = x * row j: shift the coefficients up by one and reduce x^64
+        u64 c = zeta[k];
+        for (int j = 0; j < 64; ++j) {
+            a.mat_out[j * 64 + k] = c;
+            const u64 top = __shfl(c, 63, 64);
+            u64 nc = __shfl_up(c, 1, 64);
+            if (k == 0) nc = 0;
+#pragma unroll
+            for (int q = 0; q < NTAPS; ++q)
+                if (k == tap(q)) nc -= top;
+            c = nc;
+        }
+    }
 }
 
 __global__ void k_xp_epilogue(int64_t n, Keys k, u32 op, u32 sub, const u64* C0, const u64* C1,
