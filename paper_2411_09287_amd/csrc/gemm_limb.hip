@@ -725,12 +725,12 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         }
         // B pre-converted to digit tiles when every A plane is k-contiguous with one row
         // stride (or a transposed view with contiguous rows) and B is re-read by at least two
-        // row tiles, or K is long (the conversion pass costs one more read and write of B,
-        // converting in the kernel a load latency per k-block); two 64-column tiles per
-        // workgroup (one workgroup per CU) when rows are aligned, K is whole k-blocks and
-        // N spans more than one tile
+        // row tiles, or K is long and B one column tile (the conversion pass costs one more
+        // read and write of B, converting in the kernel a load latency per k-block); two
+        // 64-column tiles per workgroup (one workgroup per CU) when rows are aligned, K is
+        // whole k-blocks and N spans more than one tile
         const int na = g.party ? 3 : nprod;
-        bool kc = (tm >= 2 || Kp >= 4096) && g.ws_alloc, ta = kc && g.K % KB == 0;
+        bool kc = (tm >= 2 || (Kp >= 4096 && tn == 1)) && g.ws_alloc, ta = kc && g.K % KB == 0;
         for (int p = 0; p < na; ++p) {
             kc = kc && g.A[p].s1 == 1 && g.A[p].s0 == g.A[0].s0;
             ta = ta && g.A[p].s0 == 1 && g.A[p].s1 == g.A[0].s1;   // transposed view, rows contiguous
@@ -743,6 +743,8 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         // more than a half-filled second wave) and when it exceeds what the 32-bit digit sums
         // hold.  The splits write partial sums to the workspace and one pass adds them up
         // (atomic adds into the output only for accumulating callers without a workspace).
+        // (measured: splitting to fill the last round of 64 x 128 workgroups costs more in
+        // partial sums than the idle CUs)
         const int64_t groups = tm * tn * nprod, fill = 256;
         const int64_t need = (maxseg * Kp + KSEG - 1) / KSEG;
         int64_t splits = need;
@@ -847,8 +849,13 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             l.tn64 = (int)tn;
             l.tn = (int)((tn + ns - 1) / ns);
             l.tm = (int)tm;
-            // about as many workgroups per group as one XCD holds at once (32 CUs)
-            l.rb = (int)std::max<int64_t>(1, std::min<int64_t>(tm, (ns == 2 ? 32 : 64) / l.tn));
+            // B tiles that fit an XCD's L2 with room to spare: the products and column groups
+            // of one row tile run together and share its A rows (rb = 1); larger B: about as
+            // many workgroups per group as one XCD holds at once (32 CUs), sharing B tiles
+            const size_t bbytes = (size_t)(g.party ? 5 : 1) * tn * nkb * TILE_BYTES;
+            l.rb = bbytes <= ((size_t)2 << 20)
+                       ? 1
+                       : (int)std::max<int64_t>(1, std::min<int64_t>(tm, (ns == 2 ? 32 : 64) / l.tn));
             const dim3 gr((unsigned)(l.tn * tm * nprod * splits));
             if (ta && ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2, true>), gr, dim3(2 * NT), 0, st, l);
             else if (ta) hipLaunchKernelGGL((k_lgemm2<true, 1, true>), gr, dim3(NT), 0, st, l);
