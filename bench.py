@@ -30,9 +30,11 @@ from paper_2411_09287_amd import workloads  # noqa: E402
 INT8_PEAK_TOPS = 5000.0       # MI355X dense int8 MFMA
 ENVELOPE = (32768, 2304, 256)  # largest VGG-style conv product (batch 32, 3x3x256 -> 256)
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "pi_inner_vgg_hbm_traffic.txt")
-# 64-bit integer multiply-accumulate on the vector ALU: 256 CUs x 64 lanes x 2.4 GHz of
-# 32-bit multiplies at quarter rate, three multiplies per u64 MAC.
-U64_ALU_PEAK_TMACS = 256 * 64 * 2.4e9 / 4 / 3 / 1e12
+# 64-bit integer multiply-accumulate on the vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# of single-issue vector instructions (39.3 T lane-instructions/s), four per u64 MAC in the
+# product kernel (one 32x32->64 multiply-add, two 32-bit low multiplies, one three-way add),
+# every one counted at the full issue rate: a ceiling, not a sustained rate.
+U64_ALU_PEAK_TMACS = 256 * 4 * 16 * 2.4e9 / 4 / 1e12
 
 
 def log(msg):
