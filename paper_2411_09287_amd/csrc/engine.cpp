@@ -520,6 +520,13 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
     const int64_t nhi = (total - 1) / L + 1;
     u64* lo = c->sc->words(L * 64);
     power_table(c, r, L, lo);                       // r^i, i < L
+    // the x and z compressions of every product multiply by leading rows of lo: the limb
+    // kernels take its digit tiles, converted once here
+    int8_t* lo_tiles = nullptr;
+    if (c->variant != MPC3_VARIANT_U64) {
+        lo_tiles = (int8_t*)c->sc->alloc(limb_btiles_bytes(L, 64));
+        ck(limb_btiles(view(lo, 64, 1), L, 64, lo_tiles, s));
+    }
     u64* rL = c->sc->words(64);
     launch_gr_mul_rows(lo + (L - 1) * 64, r, 1, 1, rL, s);   // r^L
     u64* hi = c->sc->words(nhi * 64);
@@ -563,7 +570,12 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
         };
         u64* U = XY + row * 64;
         // x_k = r^{o_l} sum_m r^m X[m, k]
-        three(plain(K, 64, M, View{}, view(lo, 64, 1), OutView{}, false), Xc, 1, K,
+        auto lo_b = [&](GemmArgs g) {
+            g.btiles = lo_tiles;
+            g.btiles_nkb = L / 32;
+            return g;
+        };
+        three(lo_b(plain(K, 64, M, View{}, view(lo, 64, 1), OutView{}, false)), Xc, 1, K,
               [&](int p) { return oview(U + p * np * 64, 64, 1); });
         launch_gr_mul_rows(sigo, U, K, K, U, s, 3, np * 64);
         // y_k = sum_n r^{M n} W[k, n]
@@ -571,7 +583,7 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
               [&](int p) { return oview(XY + (3 + p) * np * 64 + row * 64, 64, 1); });
         // T_n = sum_m r^m Z[m, n]; z += sum_n r^{o_l + M n} T_n (ring products, folded below;
         // as the transposed product T^T r^{o_l + M n} into a transposed view of Cz)
-        three(plain(N, 64, M, View{}, view(lo, 64, 1), OutView{}, false), Zc, 1, N,
+        three(lo_b(plain(N, 64, M, View{}, view(lo, 64, 1), OutView{}, false)), Zc, 1, N,
               [&](int p) { return oview(T + p * N * 64, 64, 1); });
         const u64* Tp[3] = {T, T + N * 64, T + 2 * N * 64};
         three(plain(64, 64, N, View{}, view(sigo, 64, 1), OutView{}, true), Tp, 1, 64,

@@ -34,6 +34,11 @@ struct GemmArgs {
     // atomic adds into an accumulating (or zeroed) output
     void* (*ws_alloc)(void* self, size_t bytes);
     void* ws_self;
+    // optional, plain form: B[0] already in the limb kernel's digit-tile form (limb_btiles),
+    // 64-column tiles of btiles_nkb 32-deep k-blocks each, of which the first K rows are
+    // used; read only by the limb kernel that takes converted B (B[0] must still be valid)
+    const int8_t* btiles;
+    int64_t btiles_nkb;
 };
 
 // Launch on `stream` with the chosen backend (0 = u64 VALU, 1 = int8 limbs on MFMA).
@@ -44,6 +49,11 @@ hipError_t gemm(const GemmArgs& g, int variant, hipStream_t stream);
 // add) when atomic.
 hipError_t split_reduce(const u64* part, int64_t M, int64_t N, int nprod, int splits, int batch,
                         const OutView* C, const View& D, bool atomic, hipStream_t stream);
+
+// Digit tiles of a K x N operand (any strides) for GemmArgs::btiles: limb_btiles_bytes(K, N)
+// bytes at out, k-blocks per column tile = (K + 31) / 32.
+size_t limb_btiles_bytes(int64_t K, int64_t N);
+hipError_t limb_btiles(const View& B, int64_t K, int64_t N, int8_t* out, hipStream_t stream);
 
 // Bytes of partial sums one product may use before the split count is cut back.
 constexpr size_t PART_MAX = (size_t)1 << 30;

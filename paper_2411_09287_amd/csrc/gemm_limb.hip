@@ -311,6 +311,7 @@ struct L2Args {
     Prod2 prod[3];
     int64_t M, N, K, lda, ldk;   // A element (row, k) at row * lda + k * ldk
     int nkb;                     // k-blocks per segment
+    int bnkb;                    // k-blocks per column tile in the B tile buffers
     int kcb;                     // k-blocks per split (segments concatenated)
     int nprod, splits;
     int tn;                      // column groups of the grid (NS tiles of 64 each)
@@ -407,7 +408,7 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
     const int64_t aoff = min(r0a + ra, a.M - 1) * a.lda + part * WPT * a.ldk;
     const int tt = t & (NT - 1);
     // column tiles past the last one read the last one: their outputs are never stored
-    const int64_t boff = (int64_t)min(tcol, a.tn64 - 1) * nkb * TILE_BYTES + tt * 16;
+    const int64_t boff = (int64_t)min(tcol, a.tn64 - 1) * a.bnkb * TILE_BYTES + tt * 16;
     const u64* pa[2];
     const int8_t* pb[2];
 #pragma unroll
@@ -667,6 +668,21 @@ Opnd combo(const View* v, int64_t b, bool transpose, int64_t rows, int i0, int c
 
 }  // namespace
 
+size_t limb_btiles_bytes(int64_t K, int64_t N) {
+    return (size_t)(rup(N, TN) / TN) * (size_t)(rup(K, KB) / KB) * TILE_BYTES;
+}
+
+hipError_t limb_btiles(const View& B, int64_t K, int64_t N, int8_t* out, hipStream_t st) {
+    const int64_t nkb = rup(K, KB) / KB, rows_pad = rup(N, TN);
+    if (K <= 0 || N <= 0) return hipSuccess;
+    TileJob job{};
+    job.o[0] = opnd(B, 0, true, N);
+    job.out[0] = out;
+    const int64_t threads = rows_pad * nkb * 4;
+    hipLaunchKernelGGL(k_to_tiles, dim3((unsigned)((threads + 255) / 256), 1), dim3(256), 0, st, job, K, nkb, rows_pad);
+    return hipGetLastError();
+}
+
 hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     // Small products stay on the vector ALU, where the launch is cheaper.
@@ -809,14 +825,19 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             l.M = g.M; l.N = g.N; l.K = g.K;
             l.lda = ta ? 1 : g.A[0].s0;
             l.ldk = ta ? g.A[0].s1 : 1;
-            l.nkb = (int)nkb; l.kcb = (int)(kchunk / KB); l.nprod = nprod; l.splits = (int)splits;
+            l.nkb = (int)nkb; l.bnkb = (int)nkb; l.kcb = (int)(kchunk / KB); l.nprod = nprod; l.splits = (int)splits;
             l.atomic = a.atomic; l.D = a.D; l.part = a.part;
             const u64* Ap[3];
             for (int p = 0; p < na; ++p) Ap[p] = g.A[p].p + b * g.A[p].sb;
             if (!g.party) {
                 const Opnd bo = opnd(g.B[0], b, true, g.N);
                 const int8_t* t0 = nullptr;
-                if (!tiles(&bo, 1, &t0)) return hipErrorOutOfMemory;
+                if (g.btiles && g.batch == 1 && g.btiles_nkb >= nkb) {
+                    t0 = g.btiles;             // converted by the caller
+                    l.bnkb = (int)g.btiles_nkb;
+                } else if (!tiles(&bo, 1, &t0)) {
+                    return hipErrorOutOfMemory;
+                }
                 for (int p = 0; p < nprod; ++p) {
                     l.prod[p].nseg = 1;
                     l.prod[p].seg[0] = Seg2{Ap[p], nullptr, t0};
