@@ -61,47 +61,6 @@ __global__ void k_share(const u64* x, int64_t n, Key k1, Tag t1, Key k2, Tag t2,
 // Pi_Trunc preprocessing for outputs p: bit words B1 (P0,P1) and B2 (P0,P2); the two
 // inner products over the 64 bit positions collapse to word operations:
 //   sum_j 2^{j+1} b1_j * (-b2_j) = -2 (B1 & B2),   sum_j 2 c_j b1_j * (-b2_j) = -2 ash(B1 & B2, t).
-__global__ void k_trunc_pair(int64_t n, int t, Keys k, u32 op, Inj g2x, Inj m1z, u64* rxm, u64* rx1,
-                             u64* rx2, u64* rzm, u64* rz1, u64* rz2) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t i0 = b * 8;
-    if (i0 >= n) return;
-    u64 B1[8], B2[8], a1[8], a2[8], g1[8];
-    prg_block8(k.k01, make_tag(op, P_TRUNC_B, 1, 0), b, B1);
-    prg_block8(k.k02, make_tag(op, P_TRUNC_B, 2, 0), b, B2);
-    // r_x product: fresh output mask [r_w]_1, [r_w]_2 and P0's [Gamma]_1
-    prg_block8(k.k01, make_tag(op, P_TRUNC_WX_R, 1, 0), b, a1);
-    prg_block8(k.k02, make_tag(op, P_TRUNC_WX_R, 2, 0), b, a2);
-    prg_block8(k.k01, make_tag(op, P_TRUNC_WX_GAMMA, 1, 0), b, g1);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int64_t p = i0 + q;
-        if (p >= n) break;
-        const u64 gamma = (0 - 2 * (B1[q] & B2[q])) + a1[q] + a2[q];        // P0
-        u64 g2 = gamma - g1[q];                                              // P0 -> P2
-        if (p == g2x.index) g2 += g2x.e;
-        const u64 m = g1[q] + g2;                                            // P1 <-> P2 exchange
-        rxm[p] = m;
-        rx1[p] = a1[q] - B1[q];     // + sum 2^j <b1_j> = (0, -B1, 0)
-        rx2[p] = a2[q] - B2[q];     // + sum 2^j <b2_j> = (0, 0, -B2)
-    }
-    prg_block8(k.k01, make_tag(op, P_TRUNC_WZ_R, 1, 0), b, a1);
-    prg_block8(k.k02, make_tag(op, P_TRUNC_WZ_R, 2, 0), b, a2);
-    prg_block8(k.k01, make_tag(op, P_TRUNC_WZ_GAMMA, 1, 0), b, g1);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int64_t p = i0 + q;
-        if (p >= n) break;
-        const u64 gamma = (0 - 2 * ash(B1[q] & B2[q], t)) + a1[q] + a2[q];
-        const u64 g2 = gamma - g1[q];
-        u64 m1 = g1[q];
-        if (p == m1z.index) m1 += m1z.e;
-        rzm[p] = m1 + g2;
-        rz1[p] = a1[q] - ash(B1[q], t);
-        rz2[p] = a2[q] - ash(B2[q], t);
-    }
-}
-
 // The words 8 blk0 .. 8 blk0 + 511 of G(key, tag, .) for one wave: each lane computes
 // block blk0 + lane, and the 64 x 8 words are exchanged through lds (64 x 9 words) so that
 // out[q] is word 8 blk0 + 64 q + lane (consecutive lanes, consecutive words).
@@ -115,6 +74,66 @@ __device__ __forceinline__ void prg_wave512(const Key& k, const Tag& t, u64 blk0
 #pragma unroll
     for (int q = 0; q < 8; ++q) out[q] = lds[(q * 8 + (lane >> 3)) * 9 + (lane & 7)];
     __syncthreads();
+}
+
+// A wave covers 512 consecutive elements and its lanes take consecutive ones (the keystream
+// words come through prg_wave512); the eight streams are drawn one after another.
+__global__ void k_trunc_pair(int64_t n, int t, Keys k, u32 op, Inj g2x, Inj m1z, u64* rxm, u64* rx1,
+                             u64* rx2, u64* rzm, u64* rz1, u64* rz2) {
+    __shared__ u64 lds[4][64 * 9];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t blk0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;
+    const int64_t base = blk0 * 8 + lane;
+    u64 B1[8], B2[8], acc[8], w[8];
+    prg_wave512(k.k01, make_tag(op, P_TRUNC_B, 1, 0), blk0, lds[wv], B1);
+    prg_wave512(k.k02, make_tag(op, P_TRUNC_B, 2, 0), blk0, lds[wv], B2);
+    // r_x product: fresh output mask [r_w]_1, [r_w]_2 and P0's [Gamma]_1
+    prg_wave512(k.k01, make_tag(op, P_TRUNC_WX_R, 1, 0), blk0, lds[wv], w);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t p = base + 64 * q;
+        acc[q] = (0 - 2 * (B1[q] & B2[q])) + w[q];                            // P0's gamma, part
+        if (p < n) rx1[p] = w[q] - B1[q];       // + sum 2^j <b1_j> = (0, -B1, 0)
+    }
+    prg_wave512(k.k02, make_tag(op, P_TRUNC_WX_R, 2, 0), blk0, lds[wv], w);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t p = base + 64 * q;
+        acc[q] += w[q];
+        if (p < n) rx2[p] = w[q] - B2[q];       // + sum 2^j <b2_j> = (0, 0, -B2)
+    }
+    prg_wave512(k.k01, make_tag(op, P_TRUNC_WX_GAMMA, 1, 0), blk0, lds[wv], w);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t p = base + 64 * q;
+        u64 g2 = acc[q] - w[q];                                                // P0 -> P2
+        if (p == g2x.index) g2 += g2x.e;
+        if (p < n) rxm[p] = w[q] + g2;                                         // P1 <-> P2 exchange
+    }
+    // r_z product
+    prg_wave512(k.k01, make_tag(op, P_TRUNC_WZ_R, 1, 0), blk0, lds[wv], w);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t p = base + 64 * q;
+        acc[q] = (0 - 2 * ash(B1[q] & B2[q], t)) + w[q];
+        if (p < n) rz1[p] = w[q] - ash(B1[q], t);
+    }
+    prg_wave512(k.k02, make_tag(op, P_TRUNC_WZ_R, 2, 0), blk0, lds[wv], w);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t p = base + 64 * q;
+        acc[q] += w[q];
+        if (p < n) rz2[p] = w[q] - ash(B2[q], t);
+    }
+    prg_wave512(k.k01, make_tag(op, P_TRUNC_WZ_GAMMA, 1, 0), blk0, lds[wv], w);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t p = base + 64 * q;
+        const u64 g2 = acc[q] - w[q];
+        u64 m1 = w[q];
+        if (p == m1z.index) m1 += m1z.e;
+        if (p < n) rzm[p] = m1 + g2;
+    }
 }
 
 // Pi_Inner preprocessing: output-wire mask [r_Z] (fresh, or the truncation pair's r_x) and
