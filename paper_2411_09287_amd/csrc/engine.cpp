@@ -619,8 +619,15 @@ void verify_mult(mpc3_ctx* c, const VerCtx& v, const Pending& it, int Rarg) {
     launch_lift_rows(n, it.W.m, it.W.r1, it.W.r2, XY + 3 * np * 64, np * 64, s);
     u64* z = c->sc->words(3 * 64);
     const u64* Zc[3] = {it.Z.m, it.Z.r1, it.Z.r2};
-    for (int p = 0; p < 3; ++p)
-        run_gemm(c, plain(1, 64, n, view(Zc[p], 0, 1), view(pw, 64, 1), oview(z + p * 64, 64, 1), false));
+    {   // the three planes' claims in one product with the power table as shared operand
+        GemmArgs g = plain(1, 64, n, View{}, view(pw, 64, 1), OutView{}, false);
+        g.shared = 3;
+        for (int p = 0; p < 3; ++p) {
+            g.A[p] = view(Zc[p], 0, 1);
+            g.C[p] = oview(z + p * 64, 64, 1);
+        }
+        run_gemm(c, g);
+    }
     ck(hipMemcpyAsync(slot(v, MPC3_LOG_Z), z, 512, hipMemcpyDeviceToDevice, s));
     c->vinfo.push_back(InstanceInfo{R, np});
     fold_and_check(c, v, XY, np, z, R);
@@ -647,8 +654,7 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
     u64* w3 = c->sc->words(6 * T);
     launch_trunc_w(lo, T, p.t, B1, B2, p.rx.m, p.rx.r1, p.rx.r2, p.rz.m, p.rz.r1, p.rz.r2, w3, s);
     u64* z = c->sc->words(3 * 64);
-    for (int q = 0; q < 3; ++q)
-        run_gemm(c, plain(1, 64, 2 * T, view(w3 + q * 2 * T, 0, 1), view(pw, 64, 1), oview(z + q * 64, 64, 1), false));
+    run_gemm(c, plain(3, 64, 2 * T, view(w3, 2 * T, 1), view(pw, 64, 1), oview(z, 64, 1), false));
     ck(hipMemcpyAsync(slot(v, MPC3_LOG_Z), z, 512, hipMemcpyDeviceToDevice, s));
     c->vinfo.push_back(InstanceInfo{R, np});
     if (R == 0) {

@@ -741,12 +741,14 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         }
         // B pre-converted to digit tiles when every A plane is k-contiguous with one row
         // stride (or a transposed view with contiguous rows) and B is re-read by at least two
-        // row tiles, or K is long and B one column tile (the conversion pass costs one more
-        // read and write of B, converting in the kernel a load latency per k-block); two
-        // 64-column tiles per workgroup (one workgroup per CU) when rows are aligned, K is
-        // whole k-blocks and N spans more than one tile
+        // row tiles, or the caller has converted B already, or one row tile of at least 32
+        // rows against one column tile and a long K (the conversion pass costs one more read
+        // and write of B, converting in the kernel a load latency per k-block; with fewer A
+        // rows B dominates the traffic); two 64-column tiles per workgroup (one workgroup per
+        // CU) when rows are aligned, K is whole k-blocks and N spans more than one tile
         const int na = g.party ? 3 : nprod;
-        bool kc = (tm >= 2 || (Kp >= 4096 && tn == 1)) && g.ws_alloc, ta = kc && g.K % KB == 0;
+        bool kc = (tm >= 2 || (g.btiles && !g.party) || (Kp >= 4096 && tn == 1 && g.M >= 32)) && g.ws_alloc;
+        bool ta = kc && g.K % KB == 0;
         for (int p = 0; p < na; ++p) {
             kc = kc && g.A[p].s1 == 1 && g.A[p].s0 == g.A[0].s0;
             ta = ta && g.A[p].s0 == 1 && g.A[p].s1 == g.A[0].s1;   // transposed view, rows contiguous
