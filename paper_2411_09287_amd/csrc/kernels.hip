@@ -786,6 +786,13 @@ __device__ __forceinline__ int pow3(int j) {
     return r;
 }
 
+// Monomial order for the threads of k_sym_coeffs: u < 3^j by the number of its base-3
+// digits equal to 1 (the work per (gate, u) is 2 to that power), so the lanes of a wave
+// take monomials of equal cost.
+struct SymOrder {
+    unsigned short u[243];
+};
+
 // Coefficients of x^e zeta^u (e in 0..2, u < 3^j) of sum_i f_i(x) g_i(x) for every gate,
 // row (u + 3^j e) of cx with row stride ld (columns G .. ld-1 are written as 0).
 // For monomial u (base-3 digits u_b in {0,1,2}) the subset pairs (S, T) with S_b + T_b = u_b
@@ -793,7 +800,7 @@ __device__ __forceinline__ int pow3(int j) {
 // (gate, u); with f = a0 + x (a1 - a0), g = b0 + x (b1 - b0) the three coefficients are
 // a0 b0, a1 b1 - a0 b0 - da db and da db.
 __global__ __launch_bounds__(256) void k_sym_coeffs(int j, int64_t G, int64_t ld, int t, const u64* B1,
-                                                     const u64* B2, u64* cx) {
+                                                     const u64* B2, u64* cx, SymOrder ord) {
     __shared__ u64 sa[SYM_GB * SYM_ROW], sg[SYM_GB * SYM_ROW];
     const int64_t g0 = (int64_t)blockIdx.x * SYM_GB;
     const int ng = (int)max((int64_t)0, min((int64_t)SYM_GB, G - g0));
@@ -802,7 +809,7 @@ __global__ __launch_bounds__(256) void k_sym_coeffs(int j, int64_t G, int64_t ld
     const int npairs = 32 >> j;            // pairs per gate
     const int nu = pow3(j);
     for (int item = threadIdx.x; item < SYM_GB * nu; item += blockDim.x) {
-        const int gg = item % SYM_GB, u = item / SYM_GB;
+        const int gg = item % SYM_GB, u = ord.u[item / SYM_GB];
         const int64_t g = g0 + gg;
         if (g >= ld) continue;
         if (gg >= ng) {                    // padding columns
@@ -1076,7 +1083,17 @@ void launch_trunc_w(int64_t lo, int64_t T, int t, const u64* B1, const u64* B2, 
 void launch_sym_coeffs(int j, int64_t G, int64_t ld, int t, const u64* B1, const u64* B2, u64* cx,
                        hipStream_t s) {
     if (ld <= 0) return;
-    hipLaunchKernelGGL(k_sym_coeffs, dim3(nblocks(ld, SYM_GB)), dim3(256), 0, s, j, G, ld, t, B1, B2, cx);
+    SymOrder ord{};
+    int nu = 1;
+    for (int i = 0; i < j; ++i) nu *= 3;
+    int r = 0;
+    for (int ones = 0; ones <= j; ++ones)
+        for (int u = 0; u < nu; ++u) {
+            int c = 0;
+            for (int v = u; v; v /= 3) c += v % 3 == 1;
+            if (c == ones) ord.u[r++] = (unsigned short)u;
+        }
+    hipLaunchKernelGGL(k_sym_coeffs, dim3(nblocks(ld, SYM_GB)), dim3(256), 0, s, j, G, ld, t, B1, B2, cx, ord);
 }
 void launch_sym_level(int j, int64_t G, int t, const u64* B1, const u64* B2, u64* alpha, u64* gamma,
                       hipStream_t s) {
