@@ -879,15 +879,43 @@ __global__ void k_xshift_rows(const u64* in, int64_t n, int e, u64* out) {
     out[i * 64 + k] = a;
 }
 
-__global__ void k_gr_mul_rows(const u64* P, const u64* Q, int64_t per, u64* out, int64_t pstride) {
-    __shared__ u64 a[64], b[64], sh[64];
+// One workgroup (one wave) per rpb consecutive rows (even), taken two at a time: rows 2j and
+// 2j + 1 with the same multiplier share its loads in one pass over the coefficients.
+__global__ void k_gr_mul_rows(const u64* P, const u64* Q, int64_t n, int64_t per, u64* out, int64_t pstride,
+                              int rpb) {
+    __shared__ u64 a[64], b0[64], b1[64], sh[64];
     const int k = threadIdx.x;
-    const int64_t i = blockIdx.x;
-    const int64_t o = (int64_t)blockIdx.y * pstride + i * 64;    // plane blockIdx.y
-    a[k] = P[(i / per) * 64 + k];
-    b[k] = Q[o + k];
-    __syncthreads();
-    out[o + k] = gr_mul_lane(a, b, sh, k);
+    const int64_t pl = (int64_t)blockIdx.y * pstride;              // plane blockIdx.y
+    const int64_t r0 = (int64_t)blockIdx.x * rpb;
+    for (int64_t i = r0; i < min(r0 + rpb, n); i += 2) {
+        const bool two = i + 1 < n && (i + 1) / per == i / per;
+        a[k] = P[(i / per) * 64 + k];
+        b0[k] = Q[pl + i * 64 + k];
+        if (two) b1[k] = Q[pl + (i + 1) * 64 + k];
+        __syncthreads();
+        if (two) {
+            u64 lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
+            for (int j = 0; j < 64; ++j) {
+                const u64 x = a[j];
+                const int c = (k - j) & 63;
+                const u64 p0 = x * b0[c], p1 = x * b1[c];
+                if (j <= k) { lo0 += p0; lo1 += p1; } else { hi0 += p0; hi1 += p1; }
+            }
+            const u64 v0 = reduce_lane(lo0, hi0, sh, k);
+            const u64 v1 = reduce_lane(lo1, hi1, sh, k);
+            out[pl + i * 64 + k] = v0;
+            out[pl + (i + 1) * 64 + k] = v1;
+        } else {
+            out[pl + i * 64 + k] = gr_mul_lane(a, b0, sh, k);
+            if (i + 1 < n) {                                       // row i + 1 alone
+                a[k] = P[((i + 1) / per) * 64 + k];
+                b0[k] = Q[pl + (i + 1) * 64 + k];
+                __syncthreads();
+                out[pl + (i + 1) * 64 + k] = gr_mul_lane(a, b0, sh, k);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 
@@ -1115,7 +1143,10 @@ void launch_pow_ap(const u64* lo, const u64* hi, int64_t L, int64_t e0, int64_t 
 void launch_gr_mul_rows(const u64* P, const u64* Q, int64_t n, int64_t per, u64* out, hipStream_t s, int planes,
                         int64_t pstride) {
     if (n <= 0 || planes <= 0) return;
-    hipLaunchKernelGGL(k_gr_mul_rows, dim3((unsigned)n, (unsigned)planes), dim3(64), 0, s, P, Q, per, out, pstride);
+    // many rows: 16 per workgroup (fewer, longer workgroups); few: 2, so they still spread
+    const int rpb = n >= 65536 ? 16 : 2;
+    hipLaunchKernelGGL(k_gr_mul_rows, dim3((unsigned)((n + rpb - 1) / rpb), (unsigned)planes), dim3(64), 0, s, P, Q, n,
+                       per, out, pstride, rpb);
 }
 
 
