@@ -174,6 +174,50 @@ def run_mix(args):
     return reqs, out
 
 
+def run_rtrade(args):
+    """Verification time against the repetition parameter R: Pi_MultVerify of n Pi_Mult
+    triples (n = 2^18, 2^20) for R = 0..10, GPU time measured, network time of the counted
+    verification messages from the LAN/MAN/WAN model; the R that minimises the sum."""
+    import torch
+    from paper_2411_09287_amd import mpc3, netmodel
+
+    torch.cuda.set_device(0)
+    ctx = mpc3.Context(workloads.master_seed(6))
+    ctx.set_variant(mpc3.VARIANT_LIMB_I8)
+    g = workloads.rng(6)
+    out = {}
+    for logn in (18, 20):
+        n = 1 << logn
+        a = ctx.share(mpc3.to_words(g.integers(0, 1 << 63, n, dtype=np.uint64)))
+        b = ctx.share(mpc3.to_words(g.integers(0, 1 << 63, n, dtype=np.uint64)))
+        table = {}
+        for R in range(0, 11):
+            best = None
+            for rep in range(3):
+                ctx.mult(a, b)
+                torch.cuda.synchronize()
+                c0 = ctx.comm_stats()
+                t0 = time.perf_counter()
+                ok = ctx.verify(R, mpc3.VERIFY_MULT)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if not ok:
+                    raise SystemExit("verification failed in an honest run")
+                cb, cr = netmodel.diff(ctx.comm_stats(), c0)
+                if best is None or dt < best[0]:
+                    best = (dt, cb, cr)
+            table[R] = best
+            log(f"[rtrade] |G|=2^{logn} R={R} gpu {best[0] * 1e3:.2f} ms")
+        out[f"2^{logn}"] = {
+            "gpu_ms": {R: v[0] * 1e3 for R, v in table.items()},
+            "verify_rounds": {R: v[2][2] + v[2][3] for R, v in table.items()},
+            "verify_bytes": {R: int(v[1][2].sum() + v[1][3].sum()) for R, v in table.items()},
+            "best": {net: {"R": R, "ms": tot * 1e3} for net in netmodel.NETWORKS
+                     for R, tot in [netmodel.best_r(table, net)]},
+        }
+    return out
+
+
 def hbm_copy(gib):
     """A plain device-to-device copy of `gib` GiB: its time gives the achievable HBM rate and,
     under rocprofv3 --pmc, the counter reading of a known byte count."""
@@ -199,7 +243,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--variant", choices=["u64", "limb", "auto"], default="limb")
-    ap.add_argument("--workload", default="vgg", choices=["vgg", "lenet", "mlp", "mix"])
+    ap.add_argument("--workload", default="vgg", choices=["vgg", "lenet", "mlp", "mix", "rtrade"])
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16)
@@ -220,6 +264,17 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
         raise SystemExit(2)
+
+    if args.workload == "rtrade":
+        res = run_rtrade(args)
+        best = res["2^20"]["best"]["MAN"]
+        line = {"metric": "verification time at the best R (Pi_MultVerify, 2^20 triples, MAN model)",
+                "value": best["ms"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 0,
+                "ms_per_step": best["ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+                "dtype": "int8-limb", "data": "synthetic",
+                "config": {"workload": "Pi_MultVerify of 2^18 and 2^20 triples, R = 0..10", **res}}
+        print(json.dumps(line))
+        return
 
     if args.workload == "mix":
         reqs, res = run_mix(args)
