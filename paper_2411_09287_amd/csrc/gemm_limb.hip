@@ -273,13 +273,17 @@ __device__ __forceinline__ int toff(int d, int r, int o) {
 // Digit tiles of up to five operands (rows x K, any strides, optional two-plane
 // combination), operand blockIdx.y: tile (t, kb) at byte (t * nkb + kb) * TILE_BYTES;
 // rows >= o.rows and k >= K are zero.
+// blockIdx.z is a batch: operand planes advance by ob words, tiles by tb bytes.
 struct TileJob {
     Opnd o[5];
     int8_t* out[5];
+    int64_t ob, tb;
 };
 __global__ void k_to_tiles(TileJob job, int64_t K, int64_t nkb, int64_t rows_pad) {
-    const Opnd& o = job.o[blockIdx.y];
-    int8_t* out = job.out[blockIdx.y];
+    Opnd o = job.o[blockIdx.y];
+    o.p[0] += blockIdx.z * job.ob;
+    if (o.p[1]) o.p[1] += blockIdx.z * job.ob;
+    int8_t* out = job.out[blockIdx.y] + blockIdx.z * job.tb;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= rows_pad * nkb * 4) return;
     int64_t r, o8;
@@ -320,7 +324,8 @@ struct L2Args {
     int rb;                      // row tiles per group of the launch order
     int atomic;
     View D;
-    u64* part;                   // split-K partial sums: plane (split, product) of M x N
+    u64* part;                   // split-K partial sums: plane (batch, split, product) of M x N
+    int64_t sbA, sbC, sbT;       // per batch: A planes and C (words), B tiles (bytes)
 };
 
 // 8 raw words of one A row: rp points at k = k0 (the thread's octet); words at k >= K read
@@ -381,8 +386,10 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
     // walk K together over the same B tiles, and the column groups of a row tile share
     // its A rows, in that XCD's L2.
     const int nwg = gridDim.x, L = blockIdx.x, q8 = nwg / 8;
-    const int T = L < 8 * q8 ? (L % 8) * q8 + L / 8 : L;
+    const int T0 = L < 8 * q8 ? (L % 8) * q8 + L / 8 : L;
     const int per = a.tn * a.nprod * a.splits;   // workgroups per row tile
+    const int bI = T0 / (per * a.tm);            // batch (consecutive runs of T)
+    const int T = T0 - bI * per * a.tm;
     const int grp = T / (a.rb * per);
     const int first = grp * a.rb, rows = min(a.tm - first, a.rb);
     const int within = T - grp * a.rb * per;
@@ -414,11 +421,11 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const Seg2& S = P.seg[s < P.nseg ? s : 0];
-        pa[s] = S.p + aoff;
-        pb[s] = S.bt + boff;
+        pa[s] = S.p + aoff + bI * a.sbA;
+        pb[s] = S.bt + boff + bI * a.sbT;
     }
     // a summed segment (only ever the first): its second plane
-    const u64* pa2 = P.seg[0].p2 ? P.seg[0].p2 + aoff : nullptr;
+    const u64* pa2 = P.seg[0].p2 ? P.seg[0].p2 + aoff + bI * a.sbA : nullptr;
     const int wy = wl >> 1, wx = wl & 1, r = lane & 31, hf = lane >> 5;
     const int arow = wy * 32 + r, brow = wx * 32 + r;
     const int aread = arow * KB + ((hf ^ swz(arow)) << 4);
@@ -629,14 +636,14 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
 #pragma unroll
         for (int s = 0; s < 8; ++s) val += ((u64)(int64_t)acc[s][v]) << (8 * s);
         if (a.part) {
-            a.part[((int64_t)split * a.nprod + prod) * a.M * a.N + m * a.N + n] = val;
+            a.part[(((int64_t)bI * a.splits + split) * a.nprod + prod) * a.M * a.N + m * a.N + n] = val;
             continue;
         }
-        u64* p = P.C.p + m * P.C.s0 + n * P.C.s1;
+        u64* p = P.C.p + bI * a.sbC + m * P.C.s0 + n * P.C.s1;
         if (a.atomic) {
             atomicAdd((unsigned long long*)p, (unsigned long long)val);
         } else {
-            if (a.D.p) val += a.D.p[m * a.D.s0 + n * a.D.s1];
+            if (a.D.p) val += a.D.p[bI * a.D.sb + m * a.D.s0 + n * a.D.s1];
             *p = val;
         }
     }
@@ -763,6 +770,17 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         // (atomic adds into the output only for accumulating callers without a workspace).
         // (measured: splitting to fill the last round of 64 x 128 workgroups costs more in
         // partial sums than the idle CUs)
+        // Batches with uniform strides (every A plane, every B plane and every output) run
+        // in one launch of the converted-B kernel: nbl batches from b = 0.
+        int64_t nbl = 1;
+        if (two && b == 0 && g.batch > 1) {
+            bool uni = true;
+            for (int p = 0; p < na; ++p) uni = uni && g.A[p].sb == g.A[0].sb;
+            for (int p = 0; p < (g.party ? 3 : 1); ++p) uni = uni && g.B[p].sb == g.B[0].sb;
+            for (int p = 0; p < nprod; ++p) uni = uni && g.C[p].sb == g.C[0].sb;
+            if (fast && !ta) uni = uni && g.A[0].sb % 2 == 0;    // every batch's rows 16-byte aligned
+            if (uni) nbl = g.batch;
+        }
         const int64_t groups = tm * tn * nprod, fill = 256;
         const int64_t need = (maxseg * Kp + KSEG - 1) / KSEG;
         int64_t splits = need;
@@ -770,7 +788,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             const int64_t want = (4 * fill + groups - 1) / groups;
             splits = std::max<int64_t>(splits, std::min<int64_t>(want, maxseg * Kp / 64));
         }
-        const size_t plane = (size_t)nprod * g.M * g.N * 8;
+        const size_t plane = (size_t)nprod * g.M * g.N * 8 * nbl;
         const bool part_ok = g.ws_alloc != nullptr && plane * need <= PART_MAX;
         if (part_ok) splits = std::min<int64_t>(splits, std::max<int64_t>(need, (int64_t)(PART_MAX / plane)));
         else splits = need;
@@ -803,24 +821,27 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         auto finish = [&]() -> hipError_t {
             hipError_t e = hipGetLastError();
             if (e != hipSuccess || !a.part) return e;
-            return split_reduce(a.part, g.M, g.N, nprod, (int)splits, 1, outs, a.D, g.accumulate, st);
+            return split_reduce(a.part, g.M, g.N, nprod, (int)splits, (int)nbl, outs, a.D, g.accumulate, st);
         };
         if (two) {
             const int64_t nkb = Kp / KB, rows_pad = tn * TN;
-            if (nkb * 2 > 0x7FFFFFFF || tn * tm * nprod * splits > 0x7FFFFFFF) return hipErrorInvalidValue;
+            if (nkb * 2 > 0x7FFFFFFF || tn * tm * nprod * splits * nbl > 0x7FFFFFFF || nbl > 65535)
+                return hipErrorInvalidValue;
             const size_t tbytes = (size_t)tn * nkb * TILE_BYTES;
-            // the digit tiles of n B operands in one launch
+            // the digit tiles of n B operands (of every batch of the launch) in one launch
             auto tiles = [&](const Opnd* bo, int n, const int8_t** tb) -> bool {
                 TileJob job{};
+                job.ob = g.B[0].sb;
+                job.tb = (int64_t)tbytes;
                 for (int i = 0; i < n; ++i) {
                     job.o[i] = bo[i];
-                    job.out[i] = (int8_t*)g.ws_alloc(g.ws_self, tbytes);
+                    job.out[i] = (int8_t*)g.ws_alloc(g.ws_self, tbytes * nbl);
                     if (!job.out[i]) return false;
                     tb[i] = job.out[i];
                 }
                 const int64_t threads = rows_pad * nkb * 4;
-                hipLaunchKernelGGL(k_to_tiles, dim3((unsigned)((threads + 255) / 256), (unsigned)n), dim3(256), 0, st,
-                                   job, g.K, nkb, rows_pad);
+                hipLaunchKernelGGL(k_to_tiles, dim3((unsigned)((threads + 255) / 256), (unsigned)n, (unsigned)nbl),
+                                   dim3(256), 0, st, job, g.K, nkb, rows_pad);
                 return true;
             };
             L2Args l{};
@@ -829,6 +850,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             l.ldk = ta ? g.A[0].s1 : 1;
             l.nkb = (int)nkb; l.bnkb = (int)nkb; l.kcb = (int)(kchunk / KB); l.nprod = nprod; l.splits = (int)splits;
             l.atomic = a.atomic; l.D = a.D; l.part = a.part;
+            l.sbA = g.A[0].sb; l.sbC = g.C[0].sb; l.sbT = (int64_t)tbytes;
             const u64* Ap[3];
             for (int p = 0; p < na; ++p) Ap[p] = g.A[p].p + b * g.A[p].sb;
             if (!g.party) {
@@ -879,7 +901,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             l.rb = bbytes <= ((size_t)2 << 20)
                        ? 1
                        : (int)std::max<int64_t>(1, std::min<int64_t>(tm, (ns == 2 ? 32 : 64) / l.tn));
-            const dim3 gr((unsigned)(l.tn * tm * nprod * splits));
+            const dim3 gr((unsigned)(l.tn * tm * nprod * splits * nbl));
             if (ta && ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2, true>), gr, dim3(2 * NT), 0, st, l);
             else if (ta) hipLaunchKernelGGL((k_lgemm2<true, 1, true>), gr, dim3(NT), 0, st, l);
             else if (ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2>), gr, dim3(2 * NT), 0, st, l);
@@ -887,6 +909,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             else hipLaunchKernelGGL((k_lgemm2<false, 1>), gr, dim3(NT), 0, st, l);
             hipError_t e = finish();
             if (e != hipSuccess) return e;
+            if (nbl > 1) return hipSuccess;     // every batch done
             continue;
         }
         if (tm > 65535) return hipErrorInvalidValue;

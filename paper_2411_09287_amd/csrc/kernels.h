@@ -49,6 +49,8 @@ void launch_random_gr(const Keys& k, u32 op, u32 purpose, u32 sub, u64* share3 /
                       u64* value /* nullable */, u64* log /* nullable */, hipStream_t s);
 // Multiplication matrices: W_b row j = v_b * x^j for nb elements v_b = src + b*stride.
 void launch_mulmat(const u64* src, int64_t stride, int nb, u64* W, hipStream_t s);
+// out[i * nq + j] = P[i] * Q[j] for i < np, j < nq (GR products).
+void launch_gr_outer(const u64* P, int64_t np, const u64* Q, int64_t nq, u64* out, hipStream_t s);
 // Anti-diagonal fold of 64x64 products and reduction modulo f, nb matrices (stride 4096).
 void launch_fold_plain(const u64* C, int nb, u64* out, hipStream_t s);
 // Pi_PolyEvl outputs from the three party products C0, C1, C2 (each 64x64).

@@ -920,6 +920,17 @@ __global__ void k_gr_mul_rows(const u64* P, const u64* Q, int64_t n, int64_t per
 
 
 
+// out[i * nq + j] = P[i] * Q[j] (one 64-lane group per product).
+__global__ void k_gr_outer(const u64* P, const u64* Q, int64_t nq, u64* out) {
+    __shared__ u64 a[64], b[64], sh[64];
+    const int k = threadIdx.x;
+    const int64_t i = blockIdx.x / nq, j = blockIdx.x % nq;
+    a[k] = P[i * 64 + k];
+    b[k] = Q[j * 64 + k];
+    __syncthreads();
+    out[(int64_t)blockIdx.x * 64 + k] = gr_mul_lane(a, b, sh, k);
+}
+
 // One doubling level of a power table: out[len + i] = out[i] * P for i < cnt (blocks
 // 0 .. cnt-1) and, when Pn is given, Pn = P * P (block cnt).
 __global__ void k_pow_level(u64* out, int64_t len, int64_t cnt, const u64* P, u64* Pn) {
@@ -1055,6 +1066,10 @@ void launch_reconstruct(int64_t n, const u64* m, const u64* r1, const u64* r2, I
 void launch_random_gr(const Keys& k, u32 op, u32 purpose, u32 sub, u64* share3, u64* value, u64* log,
                       hipStream_t s) {
     hipLaunchKernelGGL(k_random_gr, dim3(1), dim3(64), 0, s, k, op, purpose, sub, share3, value, log);
+}
+void launch_gr_outer(const u64* P, int64_t np, const u64* Q, int64_t nq, u64* out, hipStream_t s) {
+    if (np <= 0 || nq <= 0) return;
+    hipLaunchKernelGGL(k_gr_outer, dim3((unsigned)(np * nq)), dim3(64), 0, s, P, Q, nq, out);
 }
 void launch_mulmat(const u64* src, int64_t stride, int nb, u64* W, hipStream_t s) {
     if (nb <= 0) return;

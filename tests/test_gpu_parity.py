@@ -157,6 +157,20 @@ def test_truncation_gate_rounds_blocked_parity(variant):
     assert np.array_equal(mpc3.from_words(c.reconstruct(Tg)).reshape(-1), o.reconstruct(To).reshape(-1))
 
 
+@pytest.mark.parametrize("variant", [0, 1])
+def test_truncation_gate_materialisation_parity(variant):
+    """Chunks of 64 truncations (128 gates, a multiple of 64): on the limb variant the
+    materialised elements after the symbolic rounds come from the two batched matrix-core
+    products (64 tables r^l ML, then one product per 64 gates with the multiplication matrix
+    of r^(64 h)); the u64 variant keeps the row-wise ring products."""
+    g = np.random.default_rng(78)
+    o, c = pair_of(variant, chunk=64)
+    To, Tg = _pipeline(o, c, g, 8, 5, 16)
+    assert o.verify() and c.verify()
+    _compare_transcripts(o, c)
+    assert np.array_equal(mpc3.from_words(c.reconstruct(Tg)).reshape(-1), o.reconstruct(To).reshape(-1))
+
+
 SITES = [mpc3.SITE_INNER_GAMMA2, mpc3.SITE_INNER_M1, mpc3.SITE_TRUNC_GAMMA2, mpc3.SITE_TRUNC_M1,
          mpc3.SITE_MULT_GAMMA2, mpc3.SITE_VER_H0_M1, mpc3.SITE_VER_H2_GAMMA2, mpc3.SITE_VER_DELTA_M1]
 
