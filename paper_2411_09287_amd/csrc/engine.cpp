@@ -741,28 +741,32 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
     u64* ga = c->sc->words(G * 64);
     launch_sym_level(KS, G, p.t, B1, B2, al, ga, s);
     u64* XY = c->sc->words(2 * half * 64);
-    zero(c, XY, (size_t)2 * half * 64 * 8);
+    if (half > nel)    // the padding rows of both planes; rows below nel are written here
+        for (int e = 0; e < 2; ++e) zero(c, XY + (e * half + nel) * 64, (size_t)(half - nel) * 64 * 8);
     u64* Q = c->sc->words(nel * 64);
     if (c->variant != MPC3_VARIANT_U64 && G % 64 == 0 && per == 2) {
-        // x = r^g Q on the matrix cores, with r^g = r^(64 h) r^l (g = 64 h + l):
+        // x = r^g Q on the matrix cores, with r^g = r^(Bk h) r^l for g = Bk h + l (Bk a power
+        // of two near sqrt(G), from 64 to 1024, dividing G):
         // (1) r^l enters the monomial table: Q'[g, e] = sum_S alpha[g][e L + S] (r^l ML[S]),
-        //     one product per l (64 of them, rows h) and element e (two sharing the table);
-        // (2) x[g, e] = r^(64 h) Q'[g, e]: one product per h over its 128 rows with the
-        //     multiplication matrix of r^(64 h)
-        const int64_t nh = G / 64;
-        u64* MLr = c->sc->words((int64_t)64 * L * 64);
-        launch_gr_outer(pw, 64, ML, L, MLr, s);                                          // r^l ML[S]
-        GemmArgs g1 = plain(nh, 64, L, View{}, View{MLr, 64, 1, (int64_t)L * 64}, OutView{}, false, 64);
+        //     one product per l (Bk of them, rows h) and element e (two sharing the table);
+        // (2) x[g, e] = r^(Bk h) Q'[g, e]: one product per h over its 2 Bk rows with the
+        //     multiplication matrix of r^(Bk h)
+        int64_t Bk = 64;
+        while (Bk < 1024 && G % (2 * Bk) == 0 && 4 * Bk * Bk <= G) Bk *= 2;
+        const int64_t nh = G / Bk;
+        u64* MLr = c->sc->words(Bk * L * 64);
+        launch_gr_outer(pw, Bk, ML, L, MLr, s);                                          // r^l ML[S]
+        GemmArgs g1 = plain(nh, 64, L, View{}, View{MLr, 64, 1, (int64_t)L * 64}, OutView{}, false, (int)Bk);
         g1.shared = 2;
         for (int e = 0; e < 2; ++e) {
-            g1.A[e] = View{al + e * L, 64 * 64, 1, 64};
-            g1.C[e] = OutView{Q + e * 64, 2 * 64 * 64, 1, 2 * 64};
+            g1.A[e] = View{al + e * L, Bk * 2 * L, 1, 2 * L};
+            g1.C[e] = OutView{Q + e * 64, Bk * 2 * 64, 1, 2 * 64};
         }
         run_gemm(c, g1);
         u64* Mats = c->sc->words(nh * 4096);
-        launch_mulmat(pw, 64 * 64, (int)nh, Mats, s);                                    // Mat(r^(64 h))
-        run_gemm(c, plain(128, 64, 64, View{Q, 64, 1, 128 * 64}, View{Mats, 64, 1, 4096},
-                          OutView{XY, 64, 1, 128 * 64}, false, (int)nh));
+        launch_mulmat(pw, Bk * 64, (int)nh, Mats, s);                                    // Mat(r^(Bk h))
+        run_gemm(c, plain(2 * Bk, 64, 64, View{Q, 64, 1, 2 * Bk * 64}, View{Mats, 64, 1, 4096},
+                          OutView{XY, 64, 1, 2 * Bk * 64}, false, (int)nh));
     } else {
         run_gemm(c, plain(nel, 64, L, view(al, L, 1), view(ML, 64, 1), oview(Q, 64, 1), false));
         launch_gr_mul_rows(pw, Q, nel, per, XY, s);                                     // x = r^g Q

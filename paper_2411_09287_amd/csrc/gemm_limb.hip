@@ -692,21 +692,43 @@ hipError_t limb_btiles(const View& B, int64_t K, int64_t N, int8_t* out, hipStre
 
 hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-    // Small products stay on the vector ALU, where the launch is cheaper.
-    if ((double)g.M * (double)g.N * (double)g.K < (double)(1 << 22) || g.K == 0) return gemm(g, 0, st);
     const int64_t tm = rup(g.M, TM) / TM, tn = rup(g.N, TN) / TN;
     const int64_t Kp = rup(g.K, KB);
+    // B pre-converted to digit tiles when every A plane is k-contiguous with one row
+    // stride (or a transposed view with contiguous rows) and B is re-read by at least two
+    // row tiles, or the caller has converted B already, or one row tile of at least 32
+    // rows against one column tile and a long K (the conversion pass costs one more read
+    // and write of B, converting in the kernel a load latency per k-block; with fewer A
+    // rows B dominates the traffic); two 64-column tiles per workgroup (one workgroup per
+    // CU) when rows are aligned, K is whole k-blocks and N spans more than one tile
+    const int nprod = g.party ? 3 : (g.shared > 1 ? g.shared : 1);
+    const int na = g.party ? 3 : nprod;
+    bool kc = (tm >= 2 || (g.btiles && !g.party) || (Kp >= 4096 && tn == 1 && g.M >= 32)) && g.ws_alloc;
+    bool ta = kc && g.K % KB == 0;
+    for (int p = 0; p < na; ++p) {
+        kc = kc && g.A[p].s1 == 1 && g.A[p].s0 == g.A[0].s0;
+        ta = ta && g.A[p].s0 == 1 && g.A[p].s1 == g.A[0].s1;   // transposed view, rows contiguous
+    }
+    const bool two = kc || ta;
+    // Batches with uniform strides (every A plane, every B plane and every output) run in
+    // one launch of the converted-B kernel
+    bool uni = two && g.batch > 1 && g.batch <= 65535;
+    for (int p = 0; p < na; ++p) uni = uni && g.A[p].sb == g.A[0].sb;
+    for (int p = 0; p < (g.party ? 3 : 1); ++p) uni = uni && g.B[p].sb == g.B[0].sb;
+    for (int p = 0; p < nprod; ++p) uni = uni && g.C[p].sb == g.C[0].sb;
+    // Small products stay on the vector ALU, where the launch is cheaper (a uniform batch
+    // counts as one launch).
+    const double work = (double)g.M * (double)g.N * (double)g.K * (uni ? (double)g.batch : 1.0);
+    if (work < (double)(1 << 22) || g.K == 0) return gemm(g, 0, st);
     for (int b = 0; b < g.batch; ++b) {
         LArgs a{};
         a.M = g.M; a.N = g.N; a.K = g.K; a.Kp = Kp;
         a.atomic = g.accumulate ? 1 : 0;
         a.D = g.Dadd;
         if (a.D.p) a.D.p += b * a.D.sb;
-        int nprod;
         int64_t maxseg;
         if (!g.party) {
             // one product, or up to three A operands against one B (g.shared)
-            nprod = g.shared > 1 ? g.shared : 1;
             maxseg = 1;
             for (int p = 0; p < nprod; ++p) {
                 Prod& P = a.prod[p];
@@ -718,7 +740,6 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             }
         } else {
             // planes 0, 1, 2 = m, [r]_1, [r]_2
-            nprod = 3;
             maxseg = 2;
             const View* A = g.A;
             const View* B = g.B;
@@ -746,21 +767,6 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
                 a.prod[p].C.p += b * a.prod[p].C.sb;
             }
         }
-        // B pre-converted to digit tiles when every A plane is k-contiguous with one row
-        // stride (or a transposed view with contiguous rows) and B is re-read by at least two
-        // row tiles, or the caller has converted B already, or one row tile of at least 32
-        // rows against one column tile and a long K (the conversion pass costs one more read
-        // and write of B, converting in the kernel a load latency per k-block; with fewer A
-        // rows B dominates the traffic); two 64-column tiles per workgroup (one workgroup per
-        // CU) when rows are aligned, K is whole k-blocks and N spans more than one tile
-        const int na = g.party ? 3 : nprod;
-        bool kc = (tm >= 2 || (g.btiles && !g.party) || (Kp >= 4096 && tn == 1 && g.M >= 32)) && g.ws_alloc;
-        bool ta = kc && g.K % KB == 0;
-        for (int p = 0; p < na; ++p) {
-            kc = kc && g.A[p].s1 == 1 && g.A[p].s0 == g.A[0].s0;
-            ta = ta && g.A[p].s0 == 1 && g.A[p].s1 == g.A[0].s1;   // transposed view, rows contiguous
-        }
-        const bool two = kc || ta;
         bool fast = ta || (kc && g.K % KB == 0 && g.A[0].s0 % 2 == 0);
         for (int p = 0; p < na && fast && !ta; ++p) fast = ((uintptr_t)(g.A[p].p + b * g.A[p].sb) & 15) == 0;
         const int ns = fast && tn >= 2 ? 2 : 1;
@@ -770,17 +776,9 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         // (atomic adds into the output only for accumulating callers without a workspace).
         // (measured: splitting to fill the last round of 64 x 128 workgroups costs more in
         // partial sums than the idle CUs)
-        // Batches with uniform strides (every A plane, every B plane and every output) run
-        // in one launch of the converted-B kernel: nbl batches from b = 0.
-        int64_t nbl = 1;
-        if (two && b == 0 && g.batch > 1) {
-            bool uni = true;
-            for (int p = 0; p < na; ++p) uni = uni && g.A[p].sb == g.A[0].sb;
-            for (int p = 0; p < (g.party ? 3 : 1); ++p) uni = uni && g.B[p].sb == g.B[0].sb;
-            for (int p = 0; p < nprod; ++p) uni = uni && g.C[p].sb == g.C[0].sb;
-            if (fast && !ta) uni = uni && g.A[0].sb % 2 == 0;    // every batch's rows 16-byte aligned
-            if (uni) nbl = g.batch;
-        }
+        // a uniform batch: nbl batches from b = 0 in one launch (with 16-byte aligned rows in
+        // every batch for the kernels that load A in 16-byte pieces)
+        const int64_t nbl = uni && b == 0 && (!fast || ta || g.A[0].sb % 2 == 0) ? g.batch : 1;
         const int64_t groups = tm * tn * nprod, fill = 256;
         const int64_t need = (maxseg * Kp + KSEG - 1) / KSEG;
         int64_t splits = need;
@@ -794,7 +792,9 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         else splits = need;
         if (splits > 1 && !part_ok) {
             // without room for partials: atomic adds, into a zeroed output when the caller
-            // does not accumulate (a dense output with nothing added)
+            // does not accumulate (a dense output with nothing added); a batched launch
+            // takes the vector-ALU path instead
+            if (nbl > 1) return gemm(g, 0, st);
             bool dense = !g.accumulate && !a.D.p;
             for (int p = 0; p < nprod; ++p) dense = dense && a.prod[p].C.s1 == 1 && a.prod[p].C.s0 == g.N;
             if (!g.accumulate && !dense) return gemm(g, 0, st);

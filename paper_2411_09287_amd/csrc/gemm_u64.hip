@@ -320,6 +320,58 @@ __global__ __launch_bounds__(1024) void k_split_reduce(RedArgs r) {
     }
 }
 
+// A few rows against a tall operand (up to RD_M rows of A, N <= 64, long K): a workgroup
+// per range of kc rows of B, lane n for column n, wave w for rows k0 + w, k0 + w + 4, ...;
+// each B row is one 512-byte read and the A words are the same for every lane of a wave.
+// Partial sums of the range at part[(split * M + m) * N + n].
+constexpr int RD_M = 8;
+struct RowsArgs {
+    const u64* a[RD_M];          // row m of A: a[m][k * as1]
+    int64_t as1;
+    View B;
+    int M, N;
+    int64_t K, kc;
+    u64* part;
+};
+__global__ __launch_bounds__(256) void k_rows_dot(RowsArgs r) {
+    __shared__ u64 red[4][RD_M][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t k0 = (int64_t)blockIdx.x * r.kc, k1 = min(r.K, k0 + r.kc);
+    const bool col = lane < r.N;
+    const u64* bp = r.B.p + lane * r.B.s1;
+    const int64_t bs = r.B.s0, as = r.as1;
+    u64 acc[RD_M];
+#pragma unroll
+    for (int m = 0; m < RD_M; ++m) acc[m] = 0;
+    int64_t k = k0 + w;
+    for (; k + 12 < k1; k += 16) {
+        u64 b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) b[u] = col ? bp[(k + 4 * u) * bs] : 0;
+#pragma unroll
+        for (int m = 0; m < RD_M; ++m) {
+            if (m >= r.M) break;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[m] += r.a[m][(k + 4 * u) * as] * b[u];
+        }
+    }
+    for (; k < k1; k += 4) {
+        const u64 b = col ? bp[k * bs] : 0;
+#pragma unroll
+        for (int m = 0; m < RD_M; ++m) {
+            if (m >= r.M) break;
+            acc[m] += r.a[m][k * as] * b;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < RD_M; ++m) red[w][m][lane] = acc[m];
+    __syncthreads();
+    if (w != 0 || !col) return;
+    for (int m = 0; m < r.M; ++m)
+        r.part[((int64_t)blockIdx.x * r.M + m) * r.N + lane] =
+            red[0][m][lane] + red[1][m][lane] + red[2][m][lane] + red[3][m][lane];
+}
+
 }  // namespace
 
 hipError_t gemm_u64(const GemmArgs& g, hipStream_t stream) {
@@ -385,8 +437,53 @@ hipError_t split_reduce(const u64* part, int64_t M, int64_t N, int nprod, int sp
     return hipGetLastError();
 }
 
+// Plain or shared products with at most RD_M rows of A in all, N <= 64 and a long K
+// (A planes with one k stride): k_rows_dot over about 1024 ranges of K, then the split
+// reduction (which adds D, or adds into C with atomics when accumulating).
+static bool rows_fit(const GemmArgs& g) {
+    const int na = std::max(1, g.shared);
+    if (g.party || g.M <= 0 || g.M * na > RD_M || g.N <= 0 || g.N > 64 || g.K <= 1024 || !g.ws_alloc) return false;
+    for (int p = 1; p < na; ++p)
+        if (g.A[p].s1 != g.A[0].s1) return false;
+    return true;
+}
+static hipError_t gemm_rows(const GemmArgs& g, hipStream_t stream) {
+    const int na = std::max(1, g.shared);
+    const int64_t kc = std::max<int64_t>(256, (g.K + 1023) / 1024);
+    const int64_t splits = (g.K + kc - 1) / kc;
+    if (splits > 0x7FFFFFFF) return hipErrorInvalidValue;
+    for (int b = 0; b < g.batch; ++b) {
+        RowsArgs r{};
+        r.M = (int)(g.M * na);
+        r.N = (int)g.N;
+        r.K = g.K;
+        r.kc = kc;
+        r.as1 = g.A[0].s1;
+        for (int p = 0; p < na; ++p)
+            for (int64_t m = 0; m < g.M; ++m) r.a[p * g.M + m] = g.A[p].p + b * g.A[p].sb + m * g.A[p].s0;
+        r.B = g.B[0];
+        r.B.p += b * r.B.sb;
+        r.part = (u64*)g.ws_alloc(g.ws_self, (size_t)splits * r.M * g.N * 8);
+        if (!r.part) return hipErrorOutOfMemory;
+        View D = g.Dadd;
+        if (D.p) D.p += b * D.sb;
+        OutView C[3];
+        for (int p = 0; p < na; ++p) {
+            C[p] = g.C[p];
+            C[p].p += b * C[p].sb;
+        }
+        hipLaunchKernelGGL(k_rows_dot, dim3((unsigned)splits), dim3(256), 0, stream, r);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = split_reduce(r.part, g.M, g.N, na, (int)splits, 1, C, D, g.accumulate, stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t gemm(const GemmArgs& g, int variant, hipStream_t stream) {
     if (g.shared > 1 && (g.party || g.shared > 3 || g.Dadd.p)) return hipErrorInvalidValue;
+    // a few rows against a long K: one pass over B at full bandwidth, whichever backend
+    if (rows_fit(g)) return gemm_rows(g, stream);
     // one small output tile: the K-parallel kernel, whichever backend was asked for (both
     // give the exact result)
     if (g.M <= 64 && g.N <= 64 && g.K <= 1024 && g.shared != 2) return gemm_u64(g, stream);
