@@ -54,7 +54,7 @@ def run_gpu(args):
     net = network.Network(ctx, name)
     shapes = net.shapes(batch)
     if args.variant == "auto":
-        for M, K, N in shapes:
+        for M, K, N in net.exec_shapes(batch):
             ctx.autotune(M, K, N, 3)
     x = torch.from_numpy(workloads.rng(4).random((batch,) + tuple(workloads.MODELS[name]["input"]))).cuda()
     ops = sum(2.0 * M * K * N for M, K, N in shapes)

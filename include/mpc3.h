@@ -167,7 +167,11 @@ int mpc3_inner(mpc3_ctx* ctx, const mpc3_share_t* X, const mpc3_share_t* W,
 /* Convolution lowering: cols (B*OH*OW rows, KH*KW*C cols) from an NHWC shared
  * tensor x (B*H*W*C words per plane), zero padding pad, stride 1.  Each plane
  * is rearranged alone (a local linear map); Sec. 4.1 evaluates a convolution
- * as one inner product per output. */
+ * as one inner product per output.  cols may be wider than KH*KW*C: the extra
+ * columns are written as 0 in every plane (a share of 0), so a product with
+ * matching zero-padded weights is unchanged while its contraction width becomes
+ * a multiple of the matrix-core k-block.  MPC3_E_SHAPE if cols has another row
+ * count or fewer columns. */
 int mpc3_im2col(mpc3_ctx* ctx, const mpc3_share_t* x, int B, int H, int W, int C, int KH, int KW,
                 int pad, mpc3_share_t* cols);
 

@@ -1118,11 +1118,11 @@ int mpc3_im2col(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, 
     const int OH = H + 2 * pad - KH + 1, OW = W + 2 * pad - KW + 1;
     if (OH <= 0 || OW <= 0) return MPC3_E_SHAPE;
     if (x->rows * x->cols != (int64_t)B * H * W * C) return MPC3_E_SHAPE;
-    if (cols->rows != (int64_t)B * OH * OW || cols->cols != (int64_t)KH * KW * C) return MPC3_E_SHAPE;
+    if (cols->rows != (int64_t)B * OH * OW || cols->cols < (int64_t)KH * KW * C) return MPC3_E_SHAPE;
     return wrap([&] {
         const u64* const xs[3] = {x->m, x->r1, x->r2};
         u64* const os[3] = {cols->m, cols->r1, cols->r2};
-        launch_im2col3(xs, B, H, W, C, KH, KW, pad, os, c->stream);
+        launch_im2col3(xs, B, H, W, C, KH, KW, pad, cols->cols, os, c->stream);
         ck(hipGetLastError());
         return (int)MPC3_OK;
     });

@@ -34,11 +34,12 @@ void launch_trunc_shift(int64_t n, int t, const u64* zm, const u64* rzm, const u
 void launch_mult(int64_t n, const Keys& k, u32 op, const u64* am, const u64* a1, const u64* a2,
                  const u64* bm, const u64* b1, const u64* b2, Inj g2inj, u64* cm, u64* c1, u64* c2,
                  u64* msg_g2, u64* msg_m1, u64* msg_m2, hipStream_t s);
-void launch_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int pad, u64* out,
+// Output rows of ld >= KH KW C words: columns KH KW C .. ld-1 are written as 0.
+void launch_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int pad, int64_t ld, u64* out,
                    hipStream_t s);
 // The same for the three share planes in one launch.
-void launch_im2col3(const u64* const x[3], int B, int H, int W, int C, int KH, int KW, int pad, u64* const out[3],
-                    hipStream_t s);
+void launch_im2col3(const u64* const x[3], int B, int H, int W, int C, int KH, int KW, int pad, int64_t ld,
+                    u64* const out[3], hipStream_t s);
 void launch_sumpool2(const u64* x, int B, int H, int W, int C, u64* out, hipStream_t s);
 void launch_reconstruct(int64_t n, const u64* m, const u64* r1, const u64* r2, Inj r1inj, u64* out,
                         int* flag, hipStream_t s);

@@ -233,13 +233,17 @@ __global__ void k_mult(int64_t n, Keys k, u32 op, const u64* am, const u64* a1, 
 
 // rows (b, oh, ow), columns (kh, kw, c) of a stride-1 convolution with zero padding
 __global__ void k_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int pad, int OH, int OW,
-                         u64* out) {
+                         int64_t ld, u64* out) {
     const int64_t K = (int64_t)KH * KW * C;
-    const int64_t total = (int64_t)B * OH * OW * K;
+    const int64_t total = (int64_t)B * OH * OW * ld;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    const int64_t row = idx / K;
-    const int col = (int)(idx - row * K);
+    const int64_t row = idx / ld;
+    const int col = (int)(idx - row * ld);
+    if (col >= K) {                      // zero columns of a padded contraction width
+        out[idx] = 0;
+        return;
+    }
     const int c = col % C;
     const int kw = (col / C) % KW;
     const int kh = col / (C * KW);
@@ -275,8 +279,9 @@ struct Im2colArgs {
     const u64* x[3];
     u64* out[3];
     int H, W, C, KW, OH, OW, pad;
-    u32 K, total;          // words per output row; V-word groups in a plane
-    FastDiv fK, fC, fKW, fOW, fOH;
+    u32 K, ld, total;      // words per output row (KH KW C) and the row stride ld >= K
+                           // (columns K .. ld-1 are zero); V-word groups in a plane
+    FastDiv fLD, fC, fKW, fOW, fOH;
 };
 
 // V consecutive output words per thread (V = 2: 16-byte loads and stores, C and K even),
@@ -288,7 +293,12 @@ __global__ void k_im2col3(Im2colArgs a) {
     const u64* x = a.x[blockIdx.y];
     u64* out = a.out[blockIdx.y];
     const u32 w = i * V;                          // word index within the plane
-    const u32 row = fdiv(w, a.fK), col = w - row * a.K;
+    const u32 row = fdiv(w, a.fLD), col = w - row * a.ld;
+    if (col >= a.K) {                             // zero columns (K and ld even when V = 2)
+        if (V == 2) *(ulonglong2*)(out + w) = ulonglong2{0, 0};
+        else out[w] = 0;
+        return;
+    }
     const u32 seg = fdiv(col, a.fC), c = col - seg * a.C;
     const u32 kh = fdiv(seg, a.fKW), kw = seg - kh * a.KW;
     const u32 t = fdiv(row, a.fOW), ow = row - t * a.OW;
@@ -1015,25 +1025,25 @@ void launch_mult(int64_t n, const Keys& k, u32 op, const u64* am, const u64* a1,
     hipLaunchKernelGGL(k_mult, dim3(nblocks((n + 7) / 8, TPB)), dim3(TPB), 0, s, n, k, op, am, a1, a2, bm, b1, b2,
                        g2inj, cm, c1, c2, msg_g2, msg_m1, msg_m2);
 }
-void launch_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int pad, u64* out,
+void launch_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int pad, int64_t ld, u64* out,
                    hipStream_t s) {
     const int OH = H + 2 * pad - KH + 1, OW = W + 2 * pad - KW + 1;
-    const int64_t total = (int64_t)B * OH * OW * KH * KW * C;
+    const int64_t total = (int64_t)B * OH * OW * ld;
     if (total <= 0) return;
     hipLaunchKernelGGL(k_im2col, dim3(nblocks(total, TPB)), dim3(TPB), 0, s, x, B, H, W, C, KH, KW, pad, OH, OW,
-                       out);
+                       ld, out);
 }
 
-void launch_im2col3(const u64* const x[3], int B, int H, int W, int C, int KH, int KW, int pad, u64* const out[3],
-                    hipStream_t s) {
+void launch_im2col3(const u64* const x[3], int B, int H, int W, int C, int KH, int KW, int pad, int64_t ld,
+                    u64* const out[3], hipStream_t s) {
     const int OH = H + 2 * pad - KH + 1, OW = W + 2 * pad - KW + 1;
     const int64_t K = (int64_t)KH * KW * C;
-    const int64_t total = (int64_t)B * OH * OW * K;
-    if (total <= 0) return;
+    const int64_t total = (int64_t)B * OH * OW * ld;
+    if (total <= 0 || ld < K) return;
     bool aligned = true;
     for (int p = 0; p < 3; ++p) aligned = aligned && (((uintptr_t)x[p] | (uintptr_t)out[p]) & 15) == 0;
     if (total >= ((int64_t)1 << 31)) {       // beyond 32-bit word indices: one word per thread
-        for (int p = 0; p < 3; ++p) launch_im2col(x[p], B, H, W, C, KH, KW, pad, out[p], s);
+        for (int p = 0; p < 3; ++p) launch_im2col(x[p], B, H, W, C, KH, KW, pad, ld, out[p], s);
         return;
     }
     Im2colArgs a{};
@@ -1043,9 +1053,10 @@ void launch_im2col3(const u64* const x[3], int B, int H, int W, int C, int KH, i
     }
     a.H = H; a.W = W; a.C = C; a.KW = KW; a.OH = OH; a.OW = OW; a.pad = pad;
     a.K = (u32)K;
-    a.fK = make_fastdiv((u32)K); a.fC = make_fastdiv((u32)C); a.fKW = make_fastdiv((u32)KW);
+    a.ld = (u32)ld;
+    a.fLD = make_fastdiv((u32)ld); a.fC = make_fastdiv((u32)C); a.fKW = make_fastdiv((u32)KW);
     a.fOW = make_fastdiv((u32)OW); a.fOH = make_fastdiv((u32)OH);
-    if (aligned && C % 2 == 0) {
+    if (aligned && C % 2 == 0 && ld % 2 == 0) {
         a.total = (u32)(total / 2);
         hipLaunchKernelGGL(k_im2col3<2>, dim3(nblocks(a.total, TPB), 3), dim3(TPB), 0, s, a);
     } else {

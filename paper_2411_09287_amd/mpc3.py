@@ -236,9 +236,10 @@ class Context:
         self._keep[VERIFY_INNER].append((X, W, Z))
         return Z
 
-    def im2col(self, x, B, H, W, C, KH, KW, pad):
+    def im2col(self, x, B, H, W, C, KH, KW, pad, ld=None):
+        """ld (>= KH KW C): row width of the result, the extra columns zero."""
         OH, OW = H + 2 * pad - KH + 1, W + 2 * pad - KW + 1
-        cols = DShare.empty(B * OH * OW, KH * KW * C, self.device)
+        cols = DShare.empty(B * OH * OW, ld or KH * KW * C, self.device)
         xs, cs = x.c(), cols.c()
         _ck(lib().mpc3_im2col(self.h, ctypes.byref(xs), B, H, W, C, KH, KW, pad, ctypes.byref(cs)), "mpc3_im2col")
         return cols

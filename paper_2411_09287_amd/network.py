@@ -26,6 +26,10 @@ def plan(name):
             _, kh, kw, cin, cout, pad, (h, w) = layer
             oh, ow = h + 2 * pad - kh + 1, w + 2 * pad - kw + 1
             d["out_hw"] = (oh, ow)
+            # contraction width of the product: kh kw cin zero-padded to whole 32-deep
+            # k-blocks of the matrix-core kernel (zero columns of the lowered input against
+            # zero rows of the weights leave every output unchanged)
+            d["kpad"] = -(-kh * kw * cin // 32) * 32
             if i + 1 < len(layers):
                 nxt = layers[i + 1]
                 if nxt[0] == "conv":
@@ -60,10 +64,19 @@ class Network:
         self.plan = plan(name)
         self.frac = ctx.frac_bits
         self.w_float = float_weights(name, seed)
-        self.weights = [ctx.share(ctx.encode(torch.from_numpy(w).to(ctx.device))) for w in self.w_float]
+        self.weights = []
+        for d, w in zip(self.plan, self.w_float):
+            if d.get("kpad", w.shape[0]) > w.shape[0]:
+                w = np.concatenate([w, np.zeros((d["kpad"] - w.shape[0], w.shape[1]))])
+            self.weights.append(ctx.share(ctx.encode(torch.from_numpy(w).to(ctx.device))))
 
     def shapes(self, batch):
+        """The layers' products M x K x N as the model defines them."""
         return [workloads.layer_gemm_shape(d["layer"], batch) for d in self.plan]
+
+    def exec_shapes(self, batch):
+        """The products as evaluated (convolutions with the padded contraction width)."""
+        return [(M, self.plan[i].get("kpad", K), N) for i, (M, K, N) in enumerate(self.shapes(batch))]
 
     def forward(self, x, trunc=True):
         """x: float64 tensor (batch, ...) of the model's input shape on the device.
@@ -75,7 +88,7 @@ class Network:
             layer = d["layer"]
             if layer[0] == "conv":
                 _, kh, kw, cin, cout, pad, (hh, ww) = layer
-                X = ctx.im2col(h, batch, hh, ww, cin, kh, kw, pad)
+                X = ctx.im2col(h, batch, hh, ww, cin, kh, kw, pad, d["kpad"])
             else:
                 X = h if h.cols == layer[1] else mpc3.DShare(*[t.reshape(batch, -1) for t in (h.m, h.r1, h.r2)])
             M, N = X.rows, self.weights[i].cols

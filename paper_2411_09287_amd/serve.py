@@ -77,7 +77,7 @@ class Server:
         shapes = set()
         for p in packs_of(reqs, self.cap):
             b = sum(r[2] for r in p)
-            shapes.update((m_bucket(M), K, N) for M, K, N in self.nets[p[0][1]].shapes(b))
+            shapes.update((m_bucket(M), K, N) for M, K, N in self.nets[p[0][1]].exec_shapes(b))
         for i, (M, K, N) in enumerate(sorted(shapes)):
             self.ctx.autotune(M, K, N, reps)
             if log and (i + 1) % 16 == 0:

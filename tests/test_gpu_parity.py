@@ -266,6 +266,26 @@ def test_im2col_parity(B, H, W, C, KH, KW, pad):
     assert same_share(cg, co)
 
 
+@pytest.mark.parametrize("C,ld", [(3, 32), (3, 40), (2, 32)])
+def test_im2col_padded_width(C, ld):
+    """A result wider than KH KW C: the oracle's columns, then zero columns in every plane
+    (C = 2 takes the two-word path, C = 3 the one-word path)."""
+    B, H, W, KH, KW, pad = 2, 6, 5, 3, 3, 1
+    K = KH * KW * C
+    g = np.random.default_rng(C * ld)
+    x0 = u64(g, B, H, W, C)
+    o, c = pair_of()
+    xo = o.share(x0.reshape(B, -1))
+    xg = c.share(mpc3.to_words(x0.reshape(B, -1)))
+    co = im2col_share(xo.map(lambda a: a.reshape(B, H, W, C)), KH, KW, pad)
+    cg = c.im2col(xg, B, H, W, C, KH, KW, pad, ld)
+    assert (cg.rows, cg.cols) == (co.m.shape[0], ld)
+    for gp, op in zip(cg.numpy(), (co.m, co.r1, co.r2)):
+        gp = gp.reshape(-1, ld)
+        assert np.array_equal(gp[:, :K], op.reshape(-1, K))
+        assert not gp[:, K:].any()
+
+
 def test_variants_bit_identical_on_ragged_shapes():
     g = np.random.default_rng(11)
     for M, K, N in [(67, 129, 33), (256, 512, 64), (1, 2048, 1), (1000, 33, 200), (64, 9000, 64),
