@@ -809,14 +809,17 @@ struct SymOrder {
 // are: digit 0 -> (0,0), 2 -> (1,1), 1 -> (0,1) or (1,0).  One thread handles one
 // (gate, u); with f = a0 + x (a1 - a0), g = b0 + x (b1 - b0) the three coefficients are
 // a0 b0, a1 b1 - a0 b0 - da db and da db.
-__global__ __launch_bounds__(256) void k_sym_coeffs(int j, int64_t G, int64_t ld, int t, const u64* B1,
-                                                     const u64* B2, u64* cx, SymOrder ord) {
+// (the round j is a template parameter: the pair loop and the LDS strides are constants)
+template <int J>
+__global__ __launch_bounds__(256) void k_sym_coeffs(int64_t G, int64_t ld, int t, const u64* B1, const u64* B2,
+                                                     u64* cx, SymOrder ord) {
+    constexpr int j = J;
     __shared__ u64 sa[SYM_GB * SYM_ROW], sg[SYM_GB * SYM_ROW];
     const int64_t g0 = (int64_t)blockIdx.x * SYM_GB;
     const int ng = (int)max((int64_t)0, min((int64_t)SYM_GB, G - g0));
     sym_stage(j, g0, ng, t, B1, B2, sa, sg);
-    const int L = 1 << j;                  // coefficients per element
-    const int npairs = 32 >> j;            // pairs per gate
+    constexpr int L = 1 << j;              // coefficients per element
+    constexpr int npairs = 32 >> j;        // pairs per gate
     const int nu = pow3(j);
     for (int item = threadIdx.x; item < SYM_GB * nu; item += blockDim.x) {
         const int gg = item % SYM_GB, u = ord.u[item / SYM_GB];
@@ -1147,7 +1150,15 @@ void launch_sym_coeffs(int j, int64_t G, int64_t ld, int t, const u64* B1, const
             for (int v = u; v; v /= 3) c += v % 3 == 1;
             if (c == ones) ord.u[r++] = (unsigned short)u;
         }
-    hipLaunchKernelGGL(k_sym_coeffs, dim3(nblocks(ld, SYM_GB)), dim3(256), 0, s, j, G, ld, t, B1, B2, cx, ord);
+    const dim3 gr(nblocks(ld, SYM_GB)), bl(256);
+    switch (j) {
+        case 0: hipLaunchKernelGGL(k_sym_coeffs<0>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
+        case 1: hipLaunchKernelGGL(k_sym_coeffs<1>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
+        case 2: hipLaunchKernelGGL(k_sym_coeffs<2>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
+        case 3: hipLaunchKernelGGL(k_sym_coeffs<3>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
+        case 4: hipLaunchKernelGGL(k_sym_coeffs<4>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
+        default: break;     // j < 5: at most five symbolic rounds
+    }
 }
 void launch_sym_level(int j, int64_t G, int t, const u64* B1, const u64* B2, u64* alpha, u64* gamma,
                       hipStream_t s) {
