@@ -700,6 +700,7 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
         u64* PSX = c->sc->words(3 * nu * 64);
         run_gemm_skinny(c, plain(3 * nu, 64, nb * 64, view(Cp, nb * 64, 1), view(Tb, 64, 1), oview(PSX, 64, 1),
                                  false));
+        if (j >= sym_points_from()) launch_interp3(PSX, j + 1, s);   // point values -> coefficients
         const u64* PS = PSX;
         ck(hipMemcpyAsync(XZ, Z, (size_t)nu * 512, hipMemcpyDeviceToDevice, s));
         launch_xshift_rows(Z, nu, 1, XZ + nu * 64, s);

@@ -109,12 +109,17 @@ void launch_trunc_w(int64_t lo, int64_t T, int t, const u64* B1, const u64* B2, 
 // the j revealed points, bit b <-> point b+1); 64 coefficients per gate and side.
 // Initial coefficients (j = 0): alpha = gate weight * bit of B1, gamma = -bit of B2; level j
 // is computed from them directly (B1, B2: the chunk's T words each, G = 2T gates).
-// sym_coeffs: the 3 * 3^j power-weight rows of round j (cx row stride ld >= G, zero-padded).
+// sym_coeffs: the 3 * 3^j power-weight rows of round j (cx row stride ld >= G, zero-padded):
+// coefficients of x^e zeta^u for j < sym_points_from(), else values at the points
+// {0, 1, inf}^(1 + j) of (x, zeta); interp3 takes rows of such values (here after the
+// weighted sums over the gates) to the coefficients.
 // sym_level: the level-j alpha and gamma (G x 64 words each).
 void launch_sym_coeffs(int j, int64_t G, int64_t ld, int t, const u64* B1, const u64* B2, u64* cx,
                        hipStream_t s);
 void launch_sym_level(int j, int64_t G, int t, const u64* B1, const u64* B2, u64* alpha, u64* gamma,
                       hipStream_t s);
+void launch_interp3(u64* P, int nvar, hipStream_t s);
+int sym_points_from();
 // rows out[i] = x^e * in[i] for e = 1, 2 (n rows of 64 words).
 void launch_xshift_rows(const u64* in, int64_t n, int e, u64* out, hipStream_t s);
 // out[i] = P[i / per] * Q[i] (ring products, one 64-lane group per row), for each of

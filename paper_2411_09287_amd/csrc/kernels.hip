@@ -769,6 +769,9 @@ __device__ __forceinline__ u64 gate_weight(int s, int j, int t) {
 // `ng` gates into LDS rows of SYM_ROW words: the gate values, then j in-place
 // difference passes over the low j bits of the element index.
 constexpr int SYM_GB = 16, SYM_ROW = 129;
+// first round whose power-weight rows are point values (measured: fewer products pay off
+// from four pairs per gate down; below, the direct coefficients are faster)
+constexpr int SYM_POINTS = 3;
 __device__ void sym_stage(int j, int64_t g0, int ng, int t, const u64* B1, const u64* B2, u64* sa, u64* sg) {
     for (int e = threadIdx.x; e < ng * 64; e += blockDim.x) {
         const int gg = e >> 6, k = e & 63;
@@ -803,13 +806,21 @@ struct SymOrder {
     unsigned short u[243];
 };
 
-// Coefficients of x^e zeta^u (e in 0..2, u < 3^j) of sum_i f_i(x) g_i(x) for every gate,
-// row (u + 3^j e) of cx with row stride ld (columns G .. ld-1 are written as 0).
-// For monomial u (base-3 digits u_b in {0,1,2}) the subset pairs (S, T) with S_b + T_b = u_b
-// are: digit 0 -> (0,0), 2 -> (1,1), 1 -> (0,1) or (1,0).  One thread handles one
-// (gate, u); with f = a0 + x (a1 - a0), g = b0 + x (b1 - b0) the three coefficients are
-// a0 b0, a1 b1 - a0 b0 - da db and da db.
-// (the round j is a template parameter: the pair loop and the LDS strides are constants)
+// Power-weight rows of round j: for every gate, sum_i f_i(x) g_i(x) over its pairs i, as a
+// polynomial of degree <= 2 in x and in each of the j revealed points zeta_b; row
+// (u + 3^j e) of cx with row stride ld (columns G .. ld-1 are written as 0), u = sum_b u_b 3^b.
+// One thread handles one (gate, u), with f = a0 + x (a1 - a0) and g = b0 + x (b1 - b0):
+//  * rounds j < SYM_POINTS: the coefficients of x^e zeta^u.  The subset pairs (S, T) with
+//    S_b + T_b = u_b are: digit 0 -> (0,0), 2 -> (1,1), 1 -> (0,1) or (1,0); the three
+//    x-coefficients are a0 b0, a1 b1 - a0 b0 - da db and da db.
+//  * rounds j >= SYM_POINTS: the values at the point (x, zeta) in {0, 1, inf}^(1 + j) given
+//    by the digits (0 -> 0, 1 -> 1, 2 -> inf, the leading coefficient in that variable).  A
+//    multilinear factor evaluates there as the sum of its coefficients over the subsets S
+//    with S_b = 0 for digit 0, S_b = 1 for digit 2 and either for digit 1, and the x-points
+//    take a0 b0, a1 b1 and (a1 - a0)(b1 - b0): three products per pair instead of three per
+//    pair and subset split (k_interp3 turns the power-weighted sums of the values back into
+//    coefficients).
+// The round j is a template parameter (pair count and LDS strides constant).
 template <int J>
 __global__ __launch_bounds__(256) void k_sym_coeffs(int64_t G, int64_t ld, int t, const u64* B1, const u64* B2,
                                                      u64* cx, SymOrder ord) {
@@ -819,7 +830,7 @@ __global__ __launch_bounds__(256) void k_sym_coeffs(int64_t G, int64_t ld, int t
     const int ng = (int)max((int64_t)0, min((int64_t)SYM_GB, G - g0));
     sym_stage(j, g0, ng, t, B1, B2, sa, sg);
     constexpr int L = 1 << j;              // coefficients per element
-    constexpr int npairs = 32 >> j;        // pairs per gate
+    constexpr int NP = 32 >> j;            // pairs per gate
     const int nu = pow3(j);
     for (int item = threadIdx.x; item < SYM_GB * nu; item += blockDim.x) {
         const int gg = item % SYM_GB, u = ord.u[item / SYM_GB];
@@ -835,31 +846,84 @@ __global__ __launch_bounds__(256) void k_sym_coeffs(int64_t G, int64_t ld, int t
         const u64* C = sg + gg * SYM_ROW;
         int base = 0, ones[8], nones = 0;
         int uu = u;
+#pragma unroll
         for (int b = 0; b < j; ++b) {
             const int d = uu % 3;
             uu /= 3;
             if (d == 2) base |= 1 << b;
             if (d == 1) ones[nones++] = b;
         }
-        u64 e0 = 0, e2 = 0, s1 = 0;
-        for (int m = 0; m < (1 << nones); ++m) {
-            int S = base, T = base;
-            for (int q = 0; q < nones; ++q) {
-                if ((m >> q) & 1) S |= 1 << ones[q];
-                else T |= 1 << ones[q];
+        u64 v0 = 0, v1 = 0, v2 = 0;
+        if constexpr (j < SYM_POINTS) {
+            u64 e0 = 0, e2 = 0, s1 = 0;
+            for (int m = 0; m < (1 << nones); ++m) {
+                int S = base, T = base;
+                for (int q = 0; q < nones; ++q) {
+                    if ((m >> q) & 1) S |= 1 << ones[q];
+                    else T |= 1 << ones[q];
+                }
+                for (int i = 0; i < NP; ++i) {
+                    const u64 a0 = A[(2 * i) * L + S], a1 = A[(2 * i + 1) * L + S];
+                    const u64 b0 = C[(2 * i) * L + T], b1 = C[(2 * i + 1) * L + T];
+                    e0 += a0 * b0;
+                    s1 += a1 * b1;
+                    e2 += (a1 - a0) * (b1 - b0);
+                }
             }
-            for (int i = 0; i < npairs; ++i) {
-                const u64 a0 = A[(2 * i) * L + S], a1 = A[(2 * i + 1) * L + S];
-                const u64 b0 = C[(2 * i) * L + T], b1 = C[(2 * i + 1) * L + T];
-                e0 += a0 * b0;
-                s1 += a1 * b1;
-                e2 += (a1 - a0) * (b1 - b0);
+            v0 = e0;
+            v1 = s1 - e0 - e2;
+            v2 = e2;
+        } else {
+            // every pair's four sums advance together per subset (4 NP independent LDS
+            // reads in flight), then three products per pair
+            u64 a0[NP], a1[NP], b0[NP], b1[NP];
+#pragma unroll
+            for (int i = 0; i < NP; ++i) a0[i] = a1[i] = b0[i] = b1[i] = 0;
+            for (int m = 0; m < (1 << nones); ++m) {
+                int S = base;
+                for (int q = 0; q < nones; ++q)
+                    if ((m >> q) & 1) S |= 1 << ones[q];
+#pragma unroll
+                for (int i = 0; i < NP; ++i) {
+                    a0[i] += A[(2 * i) * L + S];
+                    a1[i] += A[(2 * i + 1) * L + S];
+                    b0[i] += C[(2 * i) * L + S];
+                    b1[i] += C[(2 * i + 1) * L + S];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                v0 += a0[i] * b0[i];
+                v1 += a1[i] * b1[i];
+                v2 += (a1[i] - a0[i]) * (b1[i] - b0[i]);
             }
         }
-        cx[(int64_t)u * ld + g] = e0;
-        cx[(int64_t)(u + nu) * ld + g] = s1 - e0 - e2;
-        cx[(int64_t)(u + 2 * nu) * ld + g] = e2;
+        cx[(int64_t)u * ld + g] = v0;
+        cx[(int64_t)(u + nu) * ld + g] = v1;
+        cx[(int64_t)(u + 2 * nu) * ld + g] = v2;
     }
+}
+
+// Values at {0, 1, inf}^nvar -> coefficients of degree <= 2 per variable, in place: rows
+// r = sum_b d_b 3^b (3^nvar <= 243 rows of 64 words); along each variable the triple
+// (h(0), h(1), h(inf)) becomes (c0, c1, c2) = (h(0), h(1) - h(0) - h(inf), h(inf)).
+__global__ __launch_bounds__(256) void k_interp3(u64* P, int nvar) {
+    __shared__ u64 T[243 * 64];
+    const int t = threadIdx.x, col = t & 63, grp = t >> 6;
+    int nr = 1;
+    for (int b = 0; b < nvar; ++b) nr *= 3;
+    for (int i = t; i < nr * 64; i += 256) T[i] = P[i];
+    __syncthreads();
+    for (int b = 0, st = 1; b < nvar; ++b, st *= 3) {
+        // triples: rows with digit b = 0, r = lo + 3 st hi (lo < st)
+        for (int q = grp; q < nr / 3; q += 4) {
+            const int r = q % st + 3 * st * (q / st);
+            const u64 h0 = T[r * 64 + col], h1 = T[(r + st) * 64 + col], hi = T[(r + 2 * st) * 64 + col];
+            T[(r + st) * 64 + col] = h1 - h0 - hi;
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < nr * 64; i += 256) P[i] = T[i];
 }
 
 // The level-j values themselves (G x 64 words each, element-major as in LDS).
@@ -1159,6 +1223,11 @@ void launch_sym_coeffs(int j, int64_t G, int64_t ld, int t, const u64* B1, const
         case 4: hipLaunchKernelGGL(k_sym_coeffs<4>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
         default: break;     // j < 5: at most five symbolic rounds
     }
+}
+int sym_points_from() { return SYM_POINTS; }
+void launch_interp3(u64* P, int nvar, hipStream_t s) {
+    if (nvar < 1 || nvar > 5) return;
+    hipLaunchKernelGGL(k_interp3, dim3(1), dim3(256), 0, s, P, nvar);
 }
 void launch_sym_level(int j, int64_t G, int t, const u64* B1, const u64* B2, u64* alpha, u64* gamma,
                       hipStream_t s) {
