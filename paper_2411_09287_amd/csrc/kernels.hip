@@ -904,6 +904,33 @@ __global__ __launch_bounds__(256) void k_sym_coeffs(int64_t G, int64_t ld, int t
     }
 }
 
+// Round 0 of the power-weight rows, one thread per gate straight from the bit words: with
+// alpha_k = w_s(k) bit_k(B1_q) and gamma_k = -bit_k(B2_q) (gate g = 2q + s), the x^0, x^1,
+// x^2 coefficients of sum_i f_i(x) g_i(x) over the 32 pairs (2i, 2i + 1) are a0 b0,
+// a1 b1 - a0 b0 - da db and da db summed (rows 0, 1, 2 of cx, row stride ld; columns
+// G .. ld-1 written as 0).
+__global__ void k_sym_round0(int64_t G, int64_t ld, int t, const u64* B1, const u64* B2, u64* cx) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ld) return;
+    u64 e0 = 0, s1 = 0, e2 = 0;
+    if (g < G) {
+        const int s = (int)(g & 1);
+        const u64 x = B1[g >> 1], y = B2[g >> 1];
+#pragma unroll 8
+        for (int i = 0; i < 32; ++i) {
+            const int k = 2 * i;
+            const u64 a0 = gate_weight(s, k, t) * ((x >> k) & 1), a1 = gate_weight(s, k + 1, t) * ((x >> (k + 1)) & 1);
+            const u64 b0 = 0 - ((y >> k) & 1), b1 = 0 - ((y >> (k + 1)) & 1);
+            e0 += a0 * b0;
+            s1 += a1 * b1;
+            e2 += (a1 - a0) * (b1 - b0);
+        }
+    }
+    cx[g] = e0;
+    cx[ld + g] = s1 - e0 - e2;
+    cx[2 * ld + g] = e2;
+}
+
 // Values at {0, 1, inf}^nvar -> coefficients of degree <= 2 per variable, in place: rows
 // r = sum_b d_b 3^b (3^nvar <= 243 rows of 64 words); along each variable the triple
 // (h(0), h(1), h(inf)) becomes (c0, c1, c2) = (h(0), h(1) - h(0) - h(inf), h(inf)).
@@ -1216,7 +1243,7 @@ void launch_sym_coeffs(int j, int64_t G, int64_t ld, int t, const u64* B1, const
         }
     const dim3 gr(nblocks(ld, SYM_GB)), bl(256);
     switch (j) {
-        case 0: hipLaunchKernelGGL(k_sym_coeffs<0>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
+        case 0: hipLaunchKernelGGL(k_sym_round0, dim3(nblocks(ld, TPB)), dim3(TPB), 0, s, G, ld, t, B1, B2, cx); break;
         case 1: hipLaunchKernelGGL(k_sym_coeffs<1>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
         case 2: hipLaunchKernelGGL(k_sym_coeffs<2>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
         case 3: hipLaunchKernelGGL(k_sym_coeffs<3>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
