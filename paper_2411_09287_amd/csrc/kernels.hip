@@ -931,6 +931,43 @@ __global__ void k_sym_round0(int64_t G, int64_t ld, int t, const u64* B1, const 
     cx[2 * ld + g] = e2;
 }
 
+// Round 1 likewise: level-1 element i of a gate has coefficients (v_2i, v_2i+1 - v_2i) in
+// zeta_0 (v = alpha or gamma), its pairs are the elements (2p, 2p + 1), and monomial u of
+// zeta_0 takes the subset splits (S, T) = (0, 0) for u = 0, (1, 1) for u = 2, (0, 1) and
+// (1, 0) for u = 1.  Rows u + 3 e of cx.
+__global__ void k_sym_round1(int64_t G, int64_t ld, int t, const u64* B1, const u64* B2, u64* cx) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ld) return;
+    u64 e0[3] = {0, 0, 0}, s1[3] = {0, 0, 0}, e2[3] = {0, 0, 0};
+    if (g < G) {
+        const int s = (int)(g & 1);
+        const u64 x = B1[g >> 1], y = B2[g >> 1];
+        auto al = [&](int k) { return gate_weight(s, k, t) * ((x >> k) & 1); };
+        auto ga = [&](int k) { return 0 - ((y >> k) & 1); };
+#pragma unroll 4
+        for (int p = 0; p < 16; ++p) {
+            const int k = 4 * p;
+            const u64 a0[2] = {al(k), al(k + 1) - al(k)}, a1[2] = {al(k + 2), al(k + 3) - al(k + 2)};
+            const u64 b0[2] = {ga(k), ga(k + 1) - ga(k)}, b1[2] = {ga(k + 2), ga(k + 3) - ga(k + 2)};
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp) {
+                // splits: (0,0) -> u 0, (1,1) -> u 2, (0,1) and (1,0) -> u 1
+                const int S = sp == 1 || sp == 3 ? 1 : 0, T = sp == 1 || sp == 2 ? 1 : 0;
+                const int u = sp == 0 ? 0 : sp == 1 ? 2 : 1;
+                e0[u] += a0[S] * b0[T];
+                s1[u] += a1[S] * b1[T];
+                e2[u] += (a1[S] - a0[S]) * (b1[T] - b0[T]);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        cx[u * ld + g] = e0[u];
+        cx[(u + 3) * ld + g] = s1[u] - e0[u] - e2[u];
+        cx[(u + 6) * ld + g] = e2[u];
+    }
+}
+
 // Values at {0, 1, inf}^nvar -> coefficients of degree <= 2 per variable, in place: rows
 // r = sum_b d_b 3^b (3^nvar <= 243 rows of 64 words); along each variable the triple
 // (h(0), h(1), h(inf)) becomes (c0, c1, c2) = (h(0), h(1) - h(0) - h(inf), h(inf)).
@@ -1244,7 +1281,7 @@ void launch_sym_coeffs(int j, int64_t G, int64_t ld, int t, const u64* B1, const
     const dim3 gr(nblocks(ld, SYM_GB)), bl(256);
     switch (j) {
         case 0: hipLaunchKernelGGL(k_sym_round0, dim3(nblocks(ld, TPB)), dim3(TPB), 0, s, G, ld, t, B1, B2, cx); break;
-        case 1: hipLaunchKernelGGL(k_sym_coeffs<1>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
+        case 1: hipLaunchKernelGGL(k_sym_round1, dim3(nblocks(ld, TPB)), dim3(TPB), 0, s, G, ld, t, B1, B2, cx); break;
         case 2: hipLaunchKernelGGL(k_sym_coeffs<2>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
         case 3: hipLaunchKernelGGL(k_sym_coeffs<3>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
         case 4: hipLaunchKernelGGL(k_sym_coeffs<4>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
