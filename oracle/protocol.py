@@ -6,7 +6,7 @@ m = v + [r]_1 + [r]_2; P1 holds (m, [r]_1), P2 holds (m, [r]_2), P0 holds
 written as the computation of the party that performs it, and every "sent"
 message is counted in bytes per (phase, sender, receiver).
 
-Readings of the paper taken here (each listed in the design doc):
+Readings of the paper taken here:
   * m = v + r (the Notation section), not the m = v - r of the introduction.
   * Gamma = sum r_x r_y + r_z, shared by P0 with Pi_[.](Gamma): [Gamma]_1 from eta_01,
     [Gamma]_2 = Gamma - [Gamma]_1 sent to P2.
