@@ -262,7 +262,7 @@ def main():
         print(json.dumps(envelope(mpc3.Context(workloads.master_seed(4)))))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        print(json.dumps({"error": "single-GPU benchmark: --gpus above 1 is not supported (the multi-GPU layout is a design note only)"}))
         raise SystemExit(2)
 
     if args.workload == "rtrade":

@@ -931,7 +931,7 @@ __global__ void k_sym_round0(int64_t G, int64_t ld, int t, const u64* B1, const 
     cx[2 * ld + g] = e2;
 }
 
-// Round 1 likewise: level-1 element i of a gate has coefficients (v_2i, v_2i+1 - v_2i) in
+// Symbolic round 1 likewise: level-1 element i of a gate has coefficients (v_2i, v_2i+1 - v_2i) in
 // zeta_0 (v = alpha or gamma), its pairs are the elements (2p, 2p + 1), and monomial u of
 // zeta_0 takes the subset splits (S, T) = (0, 0) for u = 0, (1, 1) for u = 2, (0, 1) and
 // (1, 0) for u = 1.  Rows u + 3 e of cx.
