@@ -772,13 +772,16 @@ constexpr int SYM_GB = 16, SYM_ROW = 129;
 // first round whose power-weight rows are point values (measured: fewer products pay off
 // from four pairs per gate down; below, the direct coefficients are faster)
 constexpr int SYM_POINTS = 3;
-__device__ void sym_stage(int j, int64_t g0, int ng, int t, const u64* B1, const u64* B2, u64* sa, u64* sg) {
+// y-side coefficients are differences of 0 / -1 values over at most j <= 5 bits
+// (|value| <= 2^(j-1)), held as 16-bit integers; a read converts them to Z_{2^64} by sign
+// extension.
+__device__ void sym_stage(int j, int64_t g0, int ng, int t, const u64* B1, const u64* B2, u64* sa, short* sg) {
     for (int e = threadIdx.x; e < ng * 64; e += blockDim.x) {
         const int gg = e >> 6, k = e & 63;
         const int64_t g = g0 + gg;
         const int64_t q = g >> 1;
         sa[gg * SYM_ROW + k] = gate_weight((int)(g & 1), k, t) * ((B1[q] >> k) & 1);
-        sg[gg * SYM_ROW + k] = 0 - ((B2[q] >> k) & 1);
+        sg[gg * SYM_ROW + k] = (short)-(int)((B2[q] >> k) & 1);
     }
     for (int b = 0; b < j; ++b) {
         __syncthreads();
@@ -787,7 +790,7 @@ __device__ void sym_stage(int j, int64_t g0, int ng, int t, const u64* B1, const
             const int gg = e >> 5, h = e & 31;
             const int k = ((h >> b) << (b + 1)) | (1 << b) | (h & ((1 << b) - 1));
             sa[gg * SYM_ROW + k] -= sa[gg * SYM_ROW + (k ^ (1 << b))];
-            sg[gg * SYM_ROW + k] -= sg[gg * SYM_ROW + (k ^ (1 << b))];
+            sg[gg * SYM_ROW + k] = (short)(sg[gg * SYM_ROW + k] - sg[gg * SYM_ROW + (k ^ (1 << b))]);
         }
     }
     __syncthreads();
@@ -825,7 +828,8 @@ template <int J>
 __global__ __launch_bounds__(256) void k_sym_coeffs(int64_t G, int64_t ld, int t, const u64* B1, const u64* B2,
                                                      u64* cx, SymOrder ord) {
     constexpr int j = J;
-    __shared__ u64 sa[SYM_GB * SYM_ROW], sg[SYM_GB * SYM_ROW];
+    __shared__ u64 sa[SYM_GB * SYM_ROW];
+    __shared__ short sg[SYM_GB * SYM_ROW];
     const int64_t g0 = (int64_t)blockIdx.x * SYM_GB;
     const int ng = (int)max((int64_t)0, min((int64_t)SYM_GB, G - g0));
     sym_stage(j, g0, ng, t, B1, B2, sa, sg);
@@ -843,7 +847,7 @@ __global__ __launch_bounds__(256) void k_sym_coeffs(int64_t G, int64_t ld, int t
             continue;
         }
         const u64* A = sa + gg * SYM_ROW;
-        const u64* C = sg + gg * SYM_ROW;
+        const short* C = sg + gg * SYM_ROW;
         int base = 0, ones[8], nones = 0;
         int uu = u;
 #pragma unroll
@@ -864,7 +868,7 @@ __global__ __launch_bounds__(256) void k_sym_coeffs(int64_t G, int64_t ld, int t
                 }
                 for (int i = 0; i < NP; ++i) {
                     const u64 a0 = A[(2 * i) * L + S], a1 = A[(2 * i + 1) * L + S];
-                    const u64 b0 = C[(2 * i) * L + T], b1 = C[(2 * i + 1) * L + T];
+                    const u64 b0 = (u64)(int64_t)C[(2 * i) * L + T], b1 = (u64)(int64_t)C[(2 * i + 1) * L + T];
                     e0 += a0 * b0;
                     s1 += a1 * b1;
                     e2 += (a1 - a0) * (b1 - b0);
@@ -887,8 +891,8 @@ __global__ __launch_bounds__(256) void k_sym_coeffs(int64_t G, int64_t ld, int t
                 for (int i = 0; i < NP; ++i) {
                     a0[i] += A[(2 * i) * L + S];
                     a1[i] += A[(2 * i + 1) * L + S];
-                    b0[i] += C[(2 * i) * L + S];
-                    b1[i] += C[(2 * i + 1) * L + S];
+                    b0[i] += (u64)(int64_t)C[(2 * i) * L + S];
+                    b1[i] += (u64)(int64_t)C[(2 * i + 1) * L + S];
                 }
             }
 #pragma unroll
@@ -993,14 +997,15 @@ __global__ __launch_bounds__(256) void k_interp3(u64* P, int nvar) {
 // The level-j values themselves (G x 64 words each, element-major as in LDS).
 __global__ __launch_bounds__(256) void k_sym_level(int j, int64_t G, int t, const u64* B1, const u64* B2,
                                                     u64* alpha, u64* gamma) {
-    __shared__ u64 sa[SYM_GB * SYM_ROW], sg[SYM_GB * SYM_ROW];
+    __shared__ u64 sa[SYM_GB * SYM_ROW];
+    __shared__ short sg[SYM_GB * SYM_ROW];
     const int64_t g0 = (int64_t)blockIdx.x * SYM_GB;
     const int ng = (int)min((int64_t)SYM_GB, G - g0);
     sym_stage(j, g0, ng, t, B1, B2, sa, sg);
     for (int e = threadIdx.x; e < ng * 64; e += blockDim.x) {
         const int gg = e >> 6, k = e & 63;
         alpha[(g0 + gg) * 64 + k] = sa[gg * SYM_ROW + k];
-        gamma[(g0 + gg) * 64 + k] = sg[gg * SYM_ROW + k];
+        gamma[(g0 + gg) * 64 + k] = (u64)(int64_t)sg[gg * SYM_ROW + k];
     }
 }
 
