@@ -972,6 +972,61 @@ __global__ void k_sym_round1(int64_t G, int64_t ld, int t, const u64* B1, const 
     }
 }
 
+// Symbolic round 2 likewise: level-2 element i covers the values v_4i .. v_4i+3 and has the
+// coefficients (v0, v1 - v0, v2 - v0, v3 - v2 - v1 + v0) in (zeta_0, zeta_1) (bit b of S for
+// zeta_b); its pairs are the elements (2p, 2p + 1), and monomial u = d0 + 3 d1 takes, per
+// digit, the splits (0, 0) for 0, (1, 1) for 2, (0, 1) and (1, 0) for 1.  Rows u + 9 e of cx.
+__global__ __launch_bounds__(256) void k_sym_round2(int64_t G, int64_t ld, int t, const u64* B1, const u64* B2,
+                                                     u64* cx) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ld) return;
+    u64 e0[9], s1[9], e2[9];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) e0[u] = s1[u] = e2[u] = 0;
+    if (g < G) {
+        const int s = (int)(g & 1);
+        const u64 x = B1[g >> 1], y = B2[g >> 1];
+        auto al = [&](int k) { return gate_weight(s, k, t) * ((x >> k) & 1); };
+        auto ga = [&](int k) { return 0 - ((y >> k) & 1); };
+        auto mob = [](u64 v0, u64 v1, u64 v2, u64 v3, u64* c) {
+            c[0] = v0;
+            c[1] = v1 - v0;
+            c[2] = v2 - v0;
+            c[3] = v3 - v2 - v1 + v0;
+        };
+        for (int p = 0; p < 8; ++p) {
+            const int k = 8 * p;
+            u64 a0[4], a1[4], b0[4], b1[4];
+            mob(al(k), al(k + 1), al(k + 2), al(k + 3), a0);
+            mob(al(k + 4), al(k + 5), al(k + 6), al(k + 7), a1);
+            mob(ga(k), ga(k + 1), ga(k + 2), ga(k + 3), b0);
+            mob(ga(k + 4), ga(k + 5), ga(k + 6), ga(k + 7), b1);
+#pragma unroll
+            for (int u = 0; u < 9; ++u) {
+                const int d0 = u % 3, d1 = u / 3;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    if ((d0 != 1 && (m & 1)) || (d1 != 1 && (m & 2))) continue;
+                    const int S0 = d0 == 2 ? 1 : d0 == 1 ? (m & 1) : 0;
+                    const int T0 = d0 == 2 ? 1 : d0 == 1 ? 1 - (m & 1) : 0;
+                    const int S1 = d1 == 2 ? 1 : d1 == 1 ? (m >> 1) & 1 : 0;
+                    const int T1 = d1 == 2 ? 1 : d1 == 1 ? 1 - ((m >> 1) & 1) : 0;
+                    const int S = S0 | S1 << 1, T = T0 | T1 << 1;
+                    e0[u] += a0[S] * b0[T];
+                    s1[u] += a1[S] * b1[T];
+                    e2[u] += (a1[S] - a0[S]) * (b1[T] - b0[T]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 9; ++u) {
+        cx[u * ld + g] = e0[u];
+        cx[(u + 9) * ld + g] = s1[u] - e0[u] - e2[u];
+        cx[(u + 18) * ld + g] = e2[u];
+    }
+}
+
 // Values at {0, 1, inf}^nvar -> coefficients of degree <= 2 per variable, in place: rows
 // r = sum_b d_b 3^b (3^nvar <= 243 rows of 64 words); along each variable the triple
 // (h(0), h(1), h(inf)) becomes (c0, c1, c2) = (h(0), h(1) - h(0) - h(inf), h(inf)).
@@ -1287,7 +1342,7 @@ void launch_sym_coeffs(int j, int64_t G, int64_t ld, int t, const u64* B1, const
     switch (j) {
         case 0: hipLaunchKernelGGL(k_sym_round0, dim3(nblocks(ld, TPB)), dim3(TPB), 0, s, G, ld, t, B1, B2, cx); break;
         case 1: hipLaunchKernelGGL(k_sym_round1, dim3(nblocks(ld, TPB)), dim3(TPB), 0, s, G, ld, t, B1, B2, cx); break;
-        case 2: hipLaunchKernelGGL(k_sym_coeffs<2>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
+        case 2: hipLaunchKernelGGL(k_sym_round2, dim3(nblocks(ld, TPB)), dim3(TPB), 0, s, G, ld, t, B1, B2, cx); break;
         case 3: hipLaunchKernelGGL(k_sym_coeffs<3>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
         case 4: hipLaunchKernelGGL(k_sym_coeffs<4>, gr, bl, 0, s, G, ld, t, B1, B2, cx, ord); break;
         default: break;     // j < 5: at most five symbolic rounds
