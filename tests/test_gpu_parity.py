@@ -188,17 +188,19 @@ def test_mult_claims_long_parity(variant):
 
 @pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("inj", [None, (mpc3.SITE_TRUNC_M1, 700, 1 << 40)])
-def test_long_truncation_chunk_verifies(variant, inj):
-    """One chunk of 1024 truncations (2048 gates: claims over 2048 powers, 32 blocks of 64
-    gates in the materialisation).  The oracle's verification at this size is too slow for a
-    test, so the forward values are compared with the oracle and the verification is checked
-    by its outcome: it passes on honest messages and fails on one added error."""
-    g = np.random.default_rng(81)
-    o = Ctx(SEED, chunk=1024)
+@pytest.mark.parametrize("M,N", [(32, 32), (64, 128)])
+def test_long_truncation_chunk_verifies(variant, inj, M, N):
+    """One chunk of M N truncations: 1024 (2048 gates: claims over 2048 powers, 32 blocks of
+    64 gates in the materialisation) and 8192 (16384 gates: blocks of 128 gates).  The
+    oracle's verification at these sizes is too slow for a test, so the forward values are
+    compared with the oracle and the verification is checked by its outcome: it passes on
+    honest messages and fails on one added error."""
+    g = np.random.default_rng(81 + N)
+    o = Ctx(SEED, chunk=M * N)
     c = mpc3.Context(SEED)
     c.set_variant(variant)
-    c.set_chunk(1024)
-    M, K, N = 32, 3, 32
+    c.set_chunk(M * N)
+    K = 3
     X0, W0 = u64(g, M, K), u64(g, K, N)
     if inj:
         o.inject(*inj)
