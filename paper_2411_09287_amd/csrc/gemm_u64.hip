@@ -321,9 +321,8 @@ __global__ __launch_bounds__(1024) void k_split_reduce(RedArgs r) {
 }
 
 // A few rows against a tall operand (up to RD_M rows of A, N <= 64, long K): a workgroup
-// per range of kc rows of B, lane n for column n, wave w for rows k0 + w, k0 + w + 4, ...;
-// each B row is one 512-byte read and the A words are the same for every lane of a wave.
-// Partial sums of the range at part[(split * M + m) * N + n].
+// per range of kc rows of B (a multiple of 64), lane n for column n; each B row is one
+// 512-byte read.  Partial sums of the range at part[(split * M + m) * N + n].
 constexpr int RD_M = 8;
 struct RowsArgs {
     const u64* a[RD_M];          // row m of A: a[m][k * as1]
@@ -333,6 +332,15 @@ struct RowsArgs {
     int64_t K, kc;
     u64* part;
 };
+__device__ __forceinline__ u64 lane_word(u64 v, int i) {       // v of lane i (i wave-uniform)
+    const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)v, i);
+    const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)(v >> 32), i);
+    return (u64)hi << 32 | lo;
+}
+
+// Wave w takes the 64-row pieces kb = k0 + 64 w, k0 + 64 (w + 4), ... of the range: its
+// lanes load the piece's A words (one vector load per row of A), then for each of the 64
+// rows every lane reads its column of B and takes the A words from the loading lane.
 __global__ __launch_bounds__(256) void k_rows_dot(RowsArgs r) {
     __shared__ u64 red[4][RD_M][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -343,24 +351,30 @@ __global__ __launch_bounds__(256) void k_rows_dot(RowsArgs r) {
     u64 acc[RD_M];
 #pragma unroll
     for (int m = 0; m < RD_M; ++m) acc[m] = 0;
-    int64_t k = k0 + w;
-    for (; k + 12 < k1; k += 16) {
-        u64 b[4];
+    for (int64_t kb = k0 + 64 * w; kb < k1; kb += 256) {
+        const int n = (int)min((int64_t)64, k1 - kb);
+        u64 av[RD_M];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) b[u] = col ? bp[(k + 4 * u) * bs] : 0;
+        for (int m = 0; m < RD_M; ++m) av[m] = m < r.M && lane < n ? r.a[m][(kb + lane) * as] : 0;
+        int i = 0;
+        for (; i + 4 <= n; i += 4) {
+            u64 b[4];
 #pragma unroll
-        for (int m = 0; m < RD_M; ++m) {
-            if (m >= r.M) break;
+            for (int u = 0; u < 4; ++u) b[u] = col ? bp[(kb + i + u) * bs] : 0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[m] += r.a[m][(k + 4 * u) * as] * b[u];
+            for (int m = 0; m < RD_M; ++m) {
+                if (m >= r.M) break;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[m] += lane_word(av[m], i + u) * b[u];
+            }
         }
-    }
-    for (; k < k1; k += 4) {
-        const u64 b = col ? bp[k * bs] : 0;
+        for (; i < n; ++i) {
+            const u64 b = col ? bp[(kb + i) * bs] : 0;
 #pragma unroll
-        for (int m = 0; m < RD_M; ++m) {
-            if (m >= r.M) break;
-            acc[m] += r.a[m][k * as] * b;
+            for (int m = 0; m < RD_M; ++m) {
+                if (m >= r.M) break;
+                acc[m] += lane_word(av[m], i) * b;
+            }
         }
     }
 #pragma unroll
@@ -449,7 +463,7 @@ static bool rows_fit(const GemmArgs& g) {
 }
 static hipError_t gemm_rows(const GemmArgs& g, hipStream_t stream) {
     const int na = std::max(1, g.shared);
-    const int64_t kc = std::max<int64_t>(256, (g.K + 1023) / 1024);
+    const int64_t kc = std::max<int64_t>(256, ((g.K + 1023) / 1024 + 63) / 64 * 64);
     const int64_t splits = (g.K + kc - 1) / kc;
     if (splits > 0x7FFFFFFF) return hipErrorInvalidValue;
     for (int b = 0; b < g.batch; ++b) {
