@@ -212,16 +212,20 @@ void zero(mpc3_ctx* c, void* p, size_t bytes) { ck(hipMemsetAsync(p, 0, bytes, c
 //           (matrix cores for the wide levels).
 void power_levels(mpc3_ctx* c, const u64* base, int64_t n, u64* table) {
     hipStream_t s = c->cs;
-    launch_set_one(table, s);
-    if (n <= 1) return;
+    if (n <= 1) {
+        launch_set_one(table, s);
+        return;
+    }
     Scratch::Mark mk = c->sc->mark();
-    u64* P = c->sc->words(64);
-    u64* P2 = c->sc->words(64);
-    ck(hipMemcpyAsync(P, base, 512, hipMemcpyDeviceToDevice, s));
-    for (int64_t len = 1; len < n; len *= 2) {
+    u64* buf[2] = {c->sc->words(64), c->sc->words(64)};
+    const u64* P = base;            // base^len: read from the caller's buffer at the first level
+    int nb = 0;
+    for (int64_t len = 1; len < n; len *= 2) {   // the first level also writes table[0] = 1
         const int64_t cnt = std::min(len, n - len);
-        launch_pow_level(table, len, cnt, P, 2 * len < n ? P2 : nullptr, s);
-        std::swap(P, P2);
+        u64* Pn = 2 * len < n ? buf[nb] : nullptr;
+        launch_pow_level(table, len, cnt, P, Pn, s);
+        P = Pn;
+        nb ^= 1;
     }
     c->sc->restore(mk);
 }

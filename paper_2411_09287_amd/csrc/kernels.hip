@@ -1134,12 +1134,15 @@ __global__ void k_gr_outer(const u64* P, const u64* Q, int64_t nq, u64* out) {
 
 // One doubling level of a power table: out[len + i] = out[i] * P for i < cnt (blocks
 // 0 .. cnt-1) and, when Pn is given, Pn = P * P (block cnt).
+// (the first level, len = 1, also writes out[0] = 1 and takes it as 1 without reading it)
 __global__ void k_pow_level(u64* out, int64_t len, int64_t cnt, const u64* P, u64* Pn) {
     __shared__ u64 a[64], b[64], sh[64];
     const int k = threadIdx.x;
     const int64_t i = blockIdx.x;
+    const bool first = len == 1;
     a[k] = P[k];
-    b[k] = i < cnt ? out[i * 64 + k] : P[k];
+    b[k] = i < cnt ? (first ? (u64)(k == 0) : out[i * 64 + k]) : P[k];
+    if (first && i == 0) out[k] = (u64)(k == 0);
     __syncthreads();
     const u64 v = gr_mul_lane(a, b, sh, k);
     if (i < cnt) out[(len + i) * 64 + k] = v;
