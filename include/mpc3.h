@@ -130,8 +130,9 @@ int mpc3_set_variant(mpc3_ctx* ctx, int variant);
 int mpc3_autotune(mpc3_ctx* ctx, int64_t M, int64_t K, int64_t N, int reps, int* choice, double* ms_u64,
                   double* ms_limb);
 
-/* Truncations per Pi_BIVerify instance of the truncation gates (default 524288, at most
- * 2^20; a chunk of T truncations holds about 20 KiB x T of workspace while verified). */
+/* Truncations per Pi_BIVerify instance of the truncation gates (default and maximum
+ * 524288 = 2^19; a chunk of T truncations holds about 20 KiB x T of workspace while
+ * verified).  MPC3_E_ARG outside 1 .. 2^19. */
 int mpc3_set_chunk(mpc3_ctx* ctx, int64_t truncations_per_instance);
 
 /* Keep the messages of each Pi_Inner / Pi_Mult for mpc3_message (default off). */
@@ -187,19 +188,27 @@ int mpc3_mult(mpc3_ctx* ctx, const mpc3_share_t* a, const mpc3_share_t* b, mpc3_
  * No communication (Sec. 4.2). */
 int mpc3_trunc(mpc3_ctx* ctx, const mpc3_trunc_pair_t* p, const mpc3_share_t* Z, mpc3_share_t* out);
 
-/* Post-processing verification (Sec. 3): for the pending products selected by
- * kinds (MPC3_VERIFY_* mask), one Pi_BIVerify^R per Pi_Inner call (compressed
- * with the separable challenge r^(mN+n) = (r^N)^m r^n), one per chunk of
- * truncation gates, and one Pi_MultVerify^R per Pi_Mult call.  R < 0 picks
- * max(0, ceil(log2 n) - 3).  *ok = 1 iff every Delta is 0; otherwise *ok = 0
- * and the context is aborted.  Synchronises. */
+/* Post-processing verification (Sec. 3) of the pending products selected by kinds
+ * (MPC3_VERIFY_* mask).  Instance 0 is one Pi_BIVerify^R over every pending Pi_Inner
+ * product together: the batch verification gives gate (m, n) of product l, in call
+ * order, the index i = o_l + M_l n + m (o_l = the number of gates of the products
+ * before it) and the weight r^i on its x side.  Because r^i = r^(o_l) r^m (r^(M_l))^n
+ * factorises, each product's M_l N_l K_l consolidated pairs compress exactly into K_l
+ * pairs (x_k = r^(o_l) sum_m r^m X[m,k], y_k = sum_n r^(M_l n) W[k,n]) with an
+ * unchanged claimed z.  Then one instance per chunk of truncation gates, and one
+ * Pi_MultVerify^R per Pi_Mult call.  R < 0 picks max(0, ceil(log2 n) - 3) for an
+ * instance of n pairs.  *ok = 1 iff every Delta is 0; otherwise *ok = 0 and the
+ * context is aborted.  Synchronises. */
 int mpc3_verify(mpc3_ctx* ctx, int R, int kinds, int* ok);
 
-/* Pi_Rec (Preliminaries, "Verifiability of share reconstruction"): open X
- * into out_dev (rows*cols words) after cross-checking the copies each party
- * received.  Requires every pending product to be verified (else
- * MPC3_E_UNVERIFIED); an inconsistency aborts.  to_party < 0 opens to all.
- * Synchronises. */
+/* Pi_Rec (Preliminaries, "Verifiability of share reconstruction"): open X into
+ * out_dev (rows*cols words) after cross-checking the copies the receivers got.
+ * to_party < 0 opens to all three parties (Pi_Rec^l); to_party = k opens to P_k
+ * alone (Pi_Rec^{l,k}): only P_k's missing plane (P0: m from P1, P1: [r]_2 from P0,
+ * P2: [r]_1 from P0) and the hash that checks it are sent and counted, and out_dev
+ * is P_k's output.  Requires every pending product to be verified (else
+ * MPC3_E_UNVERIFIED).  An inconsistency aborts the context and returns
+ * MPC3_E_ABORTED with out_dev left unwritten.  Synchronises. */
 int mpc3_reconstruct(mpc3_ctx* ctx, const mpc3_share_t* X, int to_party, uint64_t* out_dev);
 
 /* Counted communication so far (host struct).  Synchronises. */
@@ -226,6 +235,12 @@ int mpc3_verify_log(mpc3_ctx* ctx, int64_t instance, int slot, int round, uint64
  * multiply-accumulates (5 M K N per Pi_Inner: P0 1, P1 2, P2 2), then clears them. */
 int mpc3_profile(mpc3_ctx* ctx, int on);
 int mpc3_profile_read(mpc3_ctx* ctx, double* total_ms, int64_t* launches, double* ring_macs);
+
+/* The last failure of an entry point on this context: returns its MPC3_E_* code (0 if
+ * none; a failed verification is not recorded here), *hip_error the hipError_t of a
+ * failed HIP call (0 otherwise), and `where` (nullable, where_len bytes including the
+ * terminating 0) the entry point's name followed by the failing HIP call as written. */
+int mpc3_last_error(const mpc3_ctx* ctx, int* hip_error, char* where, size_t where_len);
 
 /* Static description of a return code. */
 const char* mpc3_strerror(int code);

@@ -613,27 +613,36 @@ class Ctx:
     # ======================================================================
     # Pi_Rec (Preliminaries, "Verifiability of share reconstruction")
     # ======================================================================
-    def reconstruct(self, X):
+    def reconstruct(self, X, to_party=-1):
+        """Pi_Rec^{l} to every party (to_party < 0) or Pi_Rec^{l,k} to party k alone.
+        Each party lacks one plane: P0 gets m from P1 (P2 sends H(m)), P1 gets [r]_2 from
+        P0 (P2 sends H([r]_2)), P2 gets [r]_1 from P0 (P1 sends H([r]_1)); a receiver
+        whose copy disagrees with the hash aborts before anything is opened."""
         self.check()
         if self.pending:
             raise Unverified()
         n = X.m.size
-        to_p2 = self._apply(SITE_REC_R1, X.r1.copy())   # P0 -> P2: [r]_1
-        to_p1 = X.r2.copy()                              # P0 -> P1: [r]_2
-        to_p0 = X.m.copy()                               # P1 -> P0: m
+        receivers = (0, 1, 2) if to_party < 0 else (to_party,)
 
         def H(a):
             return hashlib.sha256(np.ascontiguousarray(a, dtype="<u8").tobytes()).digest()
 
-        ok = (H(to_p2) == H(X.r1)        # P2: P0's [r]_1 against P1's hash of it
-              and H(to_p1) == H(X.r2)    # P1: P0's [r]_2 against P2's hash of it
-              and H(to_p0) == H(X.m))    # P0: P1's m against P2's hash of it
-        self.send(ONLINE, 0, 2, 8 * n)
-        self.send(ONLINE, 0, 1, 8 * n)
-        self.send(ONLINE, 1, 0, 8 * n)
-        self.send(ONLINE, 1, 2, 32)
-        self.send(ONLINE, 2, 0, 32)
-        self.send(ONLINE, 2, 1, 32)
+        ok = True
+        if 2 in receivers:
+            to_p2 = self._apply(SITE_REC_R1, X.r1.copy())        # P0 -> P2: [r]_1
+            ok &= H(to_p2) == H(X.r1)                            # against P1's hash of it
+            self.send(ONLINE, 0, 2, 8 * n)
+            self.send(ONLINE, 1, 2, 32)
+        if 1 in receivers:
+            to_p1 = X.r2.copy()                                  # P0 -> P1: [r]_2
+            ok &= H(to_p1) == H(X.r2)                            # against P2's hash of it
+            self.send(ONLINE, 0, 1, 8 * n)
+            self.send(ONLINE, 2, 1, 32)
+        if 0 in receivers:
+            to_p0 = X.m.copy()                                   # P1 -> P0: m
+            ok &= H(to_p0) == H(X.m)                             # against P2's hash of it
+            self.send(ONLINE, 1, 0, 8 * n)
+            self.send(ONLINE, 2, 0, 32)
         self.rounds[ONLINE] += 1
         if not ok:
             self.aborted = True

@@ -9,6 +9,7 @@
 #include <tuple>
 #include <new>
 #include <stdexcept>
+#include <string>
 #include <vector>
 
 #include "../../include/mpc3.h"
@@ -20,17 +21,22 @@ using namespace mpc3;
 
 namespace {
 
+// A failed HIP call: its error code and the call as written at the failing site.
 struct HipError : std::runtime_error {
-    HipError() : std::runtime_error("hip") {}
+    hipError_t err;
+    const char* call;
+    int line;
+    HipError(hipError_t e, const char* c, int l) : std::runtime_error("hip"), err(e), call(c), line(l) {}
 };
 struct CodeError : std::runtime_error {
     int code;
     explicit CodeError(int c) : std::runtime_error("code"), code(c) {}
 };
 
-inline void ck(hipError_t e) {
-    if (e != hipSuccess) throw HipError();
+inline void ck_at(hipError_t e, const char* call, int line) {
+    if (e != hipSuccess) throw HipError(e, call, line);
 }
+#define ck(e) ck_at((e), #e, __LINE__)
 
 // Bump allocator over cached device blocks; reset at the start of each call.  Reuse is safe
 // because every launch of the context is ordered on its one stream.
@@ -61,7 +67,10 @@ struct Scratch {
         }
         const size_t cap = std::max(n, (size_t)256 << 20);
         void* p = nullptr;
-        if (hipMalloc(&p, cap) != hipSuccess) throw CodeError(MPC3_E_NOMEM);
+        if (hipMalloc(&p, cap) != hipSuccess) {
+            (void)hipGetLastError();   // clear it, so that no later launch check reports it
+            throw CodeError(MPC3_E_NOMEM);
+        }
         blks.push_back(Blk{(char*)p, cap});
         cur = blks.size() - 1;
         off = n;
@@ -89,6 +98,9 @@ struct Pending {
 };
 
 constexpr int RMAX = 40;
+// Largest truncation chunk: the size whose instance has run at production scale (2^19
+// truncations, 2^20 gates, about 10 GiB of workspace).
+constexpr int64_t MAX_CHUNK = (int64_t)1 << 19;
 constexpr int NSLOT = 2 + 7 * RMAX + 4;
 
 struct InstanceInfo {
@@ -133,6 +145,11 @@ struct mpc3_ctx {
     Scratch* sc = nullptr;
     // autotuned kernel family per (M, K, N) of a three-party product
     std::map<std::tuple<int64_t, int64_t, int64_t>, int> tuned;
+    // the last failure of an entry point: its return code, the entry point, and for a
+    // failed HIP call the hipError_t and the call at the failing site
+    int err_code = 0, err_hip = 0, err_line = 0;
+    const char* err_fn = "";
+    std::string err_call;
     // launch timing of the Pi_Inner products
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -786,17 +803,36 @@ int guard(mpc3_ctx* c) {
     return MPC3_OK;
 }
 
+// Runs an entry point's body; a failure becomes its return code and is recorded in the
+// context (when there is one) for mpc3_last_error.
 template <class F>
-int wrap(F&& f) {
+int wrap(mpc3_ctx* c, const char* fn, F&& f) {
+    int code = MPC3_OK, hip = 0, line = 0;
+    const char* call = "";
+    // a failed call elsewhere in the process (another library's, or an earlier failed
+    // allocation) can leave HIP's last-error state set: the launch checks below should
+    // report only this entry point's own launches
+    (void)hipGetLastError();
     try {
-        return f();
+        code = f();
     } catch (const CodeError& e) {
-        return e.code;
-    } catch (const HipError&) {
-        return MPC3_E_HIP;
+        code = e.code;
+    } catch (const HipError& e) {
+        code = MPC3_E_HIP;
+        hip = (int)e.err;
+        call = e.call;
+        line = e.line;
     } catch (const std::bad_alloc&) {
-        return MPC3_E_NOMEM;
+        code = MPC3_E_NOMEM;
     }
+    if (c && code != MPC3_OK && code != MPC3_E_ABORTED) {
+        c->err_code = code;
+        c->err_hip = hip;
+        c->err_line = line;
+        c->err_fn = fn;
+        c->err_call = call;
+    }
+    return code;
 }
 
 bool valid(const mpc3_share_t* s) { return s && s->m && s->r1 && s->r2 && s->rows >= 0 && s->cols >= 0; }
@@ -806,7 +842,12 @@ void ensure_msgs(mpc3_ctx* c, int kind, int64_t n) {
         for (int i = 0; i < 3; ++i) {
             if (c->msg[kind][i]) (void)hipFree(c->msg[kind][i]);
             void* p = nullptr;
-            if (hipMalloc(&p, (size_t)n * 8) != hipSuccess) throw CodeError(MPC3_E_NOMEM);
+            if (hipMalloc(&p, (size_t)n * 8) != hipSuccess) {
+                (void)hipGetLastError();
+                c->msg[kind][i] = nullptr;
+                c->msg_cap[kind] = 0;
+                throw CodeError(MPC3_E_NOMEM);
+            }
             c->msg[kind][i] = (u64*)p;
         }
         c->msg_cap[kind] = n;
@@ -827,7 +868,7 @@ extern "C" {
 int mpc3_ctx_create(const uint8_t master_seed[32], int d, int frac_bits, size_t workspace_bytes,
                     void* hip_stream, mpc3_ctx** out) {
     if (!master_seed || !out || d != 64 || frac_bits < 0 || frac_bits > 62) return MPC3_E_ARG;
-    return wrap([&] {
+    return wrap(nullptr, __func__, [&] {
         mpc3_ctx* c = new mpc3_ctx();
         c->stream = (hipStream_t)hip_stream;
         c->cs = c->stream;
@@ -912,7 +953,7 @@ int mpc3_autotune(mpc3_ctx* c, int64_t M, int64_t K, int64_t N, int reps, int* c
     int g = guard(c);
     if (g) return g;
     if (M <= 0 || K <= 0 || N <= 0 || reps <= 0 || !choice) return MPC3_E_ARG;
-    return wrap([&] {
+    return wrap(c, __func__, [&] {
         hipStream_t s = c->stream;
         c->scratch.reset();
         u64* X = c->scratch.words(3 * M * K);
@@ -960,7 +1001,7 @@ int mpc3_autotune(mpc3_ctx* c, int64_t M, int64_t K, int64_t N, int reps, int* c
 }
 
 int mpc3_set_chunk(mpc3_ctx* c, int64_t t) {
-    if (!c || t <= 0 || t > (1 << 20)) return MPC3_E_ARG;
+    if (!c || t <= 0 || t > MAX_CHUNK) return MPC3_E_ARG;
     c->chunk = t;
     return MPC3_OK;
 }
@@ -975,7 +1016,7 @@ int mpc3_encode(mpc3_ctx* c, const double* x, int64_t n, uint64_t* out) {
     int g = guard(c);
     if (g) return g;
     if ((!x || !out) && n > 0) return MPC3_E_ARG;
-    return wrap([&] {
+    return wrap(c, __func__, [&] {
         launch_encode(x, n, c->frac, out, c->stream);
         ck(hipGetLastError());
         return (int)MPC3_OK;
@@ -985,7 +1026,7 @@ int mpc3_encode(mpc3_ctx* c, const double* x, int64_t n, uint64_t* out) {
 int mpc3_decode(mpc3_ctx* c, const uint64_t* v, int64_t n, double* out) {
     if (!c) return MPC3_E_ARG;
     if ((!v || !out) && n > 0) return MPC3_E_ARG;
-    return wrap([&] {
+    return wrap(c, __func__, [&] {
         launch_decode(v, n, c->frac, out, c->stream);
         ck(hipGetLastError());
         return (int)MPC3_OK;
@@ -996,7 +1037,7 @@ int mpc3_share(mpc3_ctx* c, int owner, const uint64_t* x, mpc3_share_t* out) {
     int g = guard(c);
     if (g) return g;
     if (owner < 0 || owner > 2 || !valid(out) || (!x && out->rows * out->cols > 0)) return MPC3_E_ARG;
-    return wrap([&] {
+    return wrap(c, __func__, [&] {
         const uint32_t op = c->op++;
         const int64_t n = out->rows * out->cols;
         const Key k1 = owner == 2 ? c->keys.kall : c->keys.k01;
@@ -1017,7 +1058,7 @@ int mpc3_trunc_pair(mpc3_ctx* c, int64_t n, int t, mpc3_trunc_pair_t* out) {
     if (!out || n < 0 || t < 1 || t > 62 || !out->rx.m || !out->rx.r1 || !out->rx.r2 || !out->rz.m ||
         !out->rz.r1 || !out->rz.r2)
         return MPC3_E_ARG;
-    return wrap([&] {
+    return wrap(c, __func__, [&] {
         const uint32_t op = c->op++;
         out->t = t;
         out->n = n;
@@ -1050,7 +1091,7 @@ int mpc3_inner(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W, const 
     const int64_t M = X->rows, K = X->cols, N = W->cols;
     if (W->rows != K || Z->rows != M || Z->cols != N) return MPC3_E_SHAPE;
     if (pair && pair->n != M * N) return MPC3_E_SHAPE;
-    return wrap([&] {
+    return wrap(c, __func__, [&] {
         const uint32_t op = c->op++;
         const int64_t n = M * N;
         hipStream_t s = c->stream;
@@ -1124,7 +1165,7 @@ int mpc3_im2col(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, 
     if (OH <= 0 || OW <= 0) return MPC3_E_SHAPE;
     if (x->rows * x->cols != (int64_t)B * H * W * C) return MPC3_E_SHAPE;
     if (cols->rows != (int64_t)B * OH * OW || cols->cols < (int64_t)KH * KW * C) return MPC3_E_SHAPE;
-    return wrap([&] {
+    return wrap(c, __func__, [&] {
         const u64* const xs[3] = {x->m, x->r1, x->r2};
         u64* const os[3] = {cols->m, cols->r1, cols->r2};
         launch_im2col3(xs, B, H, W, C, KH, KW, pad, cols->cols, os, c->stream);
@@ -1139,7 +1180,7 @@ int mpc3_sumpool2(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C
     if (!valid(x) || !valid(out) || B < 0 || H <= 0 || W <= 0 || C <= 0 || (H & 1) || (W & 1)) return MPC3_E_ARG;
     if (x->rows * x->cols != (int64_t)B * H * W * C || out->rows * out->cols != (int64_t)B * (H / 2) * (W / 2) * C)
         return MPC3_E_SHAPE;
-    return wrap([&] {
+    return wrap(c, __func__, [&] {
         launch_sumpool2(x->m, B, H, W, C, out->m, c->stream);
         launch_sumpool2(x->r1, B, H, W, C, out->r1, c->stream);
         launch_sumpool2(x->r2, B, H, W, C, out->r2, c->stream);
@@ -1154,7 +1195,7 @@ int mpc3_mult(mpc3_ctx* c, const mpc3_share_t* a, const mpc3_share_t* b, mpc3_sh
     if (!valid(a) || !valid(b) || !valid(o)) return MPC3_E_ARG;
     const int64_t n = a->rows * a->cols;
     if (b->rows * b->cols != n || o->rows * o->cols != n) return MPC3_E_SHAPE;
-    return wrap([&] {
+    return wrap(c, __func__, [&] {
         const uint32_t op = c->op++;
         u64 *mg2 = nullptr, *mm1 = nullptr, *mm2 = nullptr;
         if (c->keep_msgs) {
@@ -1184,7 +1225,7 @@ int mpc3_trunc(mpc3_ctx* c, const mpc3_trunc_pair_t* p, const mpc3_share_t* Z, m
     if (!p || !valid(Z) || !valid(out)) return MPC3_E_ARG;
     const int64_t n = Z->rows * Z->cols;
     if (p->n != n || out->rows * out->cols != n) return MPC3_E_SHAPE;
-    return wrap([&] {
+    return wrap(c, __func__, [&] {
         launch_trunc_shift(n, p->t, Z->m, p->rz.m, p->rz.r1, p->rz.r2, out->m, out->r1, out->r2, c->stream);
         ck(hipGetLastError());
         return (int)MPC3_OK;
@@ -1195,7 +1236,7 @@ int mpc3_verify(mpc3_ctx* c, int R, int kinds, int* ok) {
     int g = guard(c);
     if (g) return g;
     if (!ok || R > RMAX || kinds <= 0 || kinds > MPC3_VERIFY_ALL) return MPC3_E_ARG;
-    return wrap([&] {
+    return wrap(c, __func__, [&] {
         const uint32_t op = c->op++;
         hipStream_t s = c->stream;
         c->scratch.reset();
@@ -1290,22 +1331,27 @@ int mpc3_reconstruct(mpc3_ctx* c, const mpc3_share_t* X, int to_party, uint64_t*
     if (g) return g;
     if (!valid(X) || !out || to_party > 2) return MPC3_E_ARG;
     if (!c->pending.empty()) return MPC3_E_UNVERIFIED;
-    return wrap([&] {
+    return wrap(c, __func__, [&] {
         const int64_t n = X->rows * X->cols;
+        const bool all = to_party < 0;
+        const bool to0 = all || to_party == 0, to1 = all || to_party == 1, to2 = all || to_party == 2;
         c->scratch.reset();
         int* flag = (int*)c->scratch.alloc(sizeof(int));
         zero(c, flag, sizeof(int));
-        launch_reconstruct(n, X->m, X->r1, X->r2, take(c, MPC3_SITE_REC_R1, n), out, flag, c->stream);
+        // the receivers compare their copies with the hashes first; the values are written
+        // only when every comparison held, so an aborted opening leaves out_dev untouched
+        const Inj inj = take(c, MPC3_SITE_REC_R1, to2 ? n : 0);
+        if (to2) launch_rec_check(n, X->r1, inj, flag, c->stream);
+        launch_rec_open(n, X->m, X->r1, X->r2, flag, out, c->stream);
         ck(hipGetLastError());
         int h = 0;
         ck(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         ck(hipStreamSynchronize(c->stream));
-        send(c, MPC3_PH_ONLINE, 0, 2, 8 * n);
-        send(c, MPC3_PH_ONLINE, 0, 1, 8 * n);
-        send(c, MPC3_PH_ONLINE, 1, 0, 8 * n);
-        send(c, MPC3_PH_ONLINE, 1, 2, 32);
-        send(c, MPC3_PH_ONLINE, 2, 0, 32);
-        send(c, MPC3_PH_ONLINE, 2, 1, 32);
+        // P0 gets m from P1 and H(m) from P2; P1 gets [r]_2 from P0 and H([r]_2) from P2;
+        // P2 gets [r]_1 from P0 and H([r]_1) from P1
+        if (to0) { send(c, MPC3_PH_ONLINE, 1, 0, 8 * n); send(c, MPC3_PH_ONLINE, 2, 0, 32); }
+        if (to1) { send(c, MPC3_PH_ONLINE, 0, 1, 8 * n); send(c, MPC3_PH_ONLINE, 2, 1, 32); }
+        if (to2) { send(c, MPC3_PH_ONLINE, 0, 2, 8 * n); send(c, MPC3_PH_ONLINE, 1, 2, 32); }
         c->rounds[MPC3_PH_ONLINE] += 1;
         if (h) {
             c->aborted = true;
@@ -1381,6 +1427,19 @@ int mpc3_profile_read(mpc3_ctx* c, double* total_ms, int64_t* launches, double* 
     c->ev.clear();
     c->prof_macs = 0;
     return MPC3_OK;
+}
+
+int mpc3_last_error(const mpc3_ctx* c, int* hip_error, char* where, size_t where_len) {
+    if (!c) return MPC3_E_ARG;
+    if (hip_error) *hip_error = c->err_hip;
+    if (where && where_len) {
+        std::string w = c->err_code ? std::string(c->err_fn) : std::string();
+        if (!c->err_call.empty()) w += ": " + c->err_call + " (engine.cpp line " + std::to_string(c->err_line) + ")";
+        const size_t k = std::min(w.size(), where_len - 1);
+        memcpy(where, w.data(), k);
+        where[k] = 0;
+    }
+    return c->err_code;
 }
 
 const char* mpc3_strerror(int code) {

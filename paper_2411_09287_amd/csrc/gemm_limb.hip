@@ -57,7 +57,7 @@ struct LArgs {
 __device__ __forceinline__ void load8(const Opnd& o, int64_t row, int64_t k0, int64_t K, u64 w[8]) {
     const bool inrow = row < o.rows;
     const int64_t base = row * o.s_r + k0 * o.s_k;
-    if (inrow && o.s_k == 1 && k0 + 8 <= K && ((base | (int64_t)(uintptr_t)o.p[0]) & 1) == 0 &&
+    if (inrow && o.s_k == 1 && k0 + 8 <= K && (base & 1) == 0 && ((uintptr_t)o.p[0] & 15) == 0 &&
         (!o.c[1] || ((int64_t)(uintptr_t)o.p[1] & 15) == 0)) {
         // 16-byte vector loads of the 8 contiguous words
 #pragma unroll

@@ -41,8 +41,9 @@ void launch_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int
 void launch_im2col3(const u64* const x[3], int B, int H, int W, int C, int KH, int KW, int pad, int64_t ld,
                     u64* const out[3], hipStream_t s);
 void launch_sumpool2(const u64* x, int B, int H, int W, int C, u64* out, hipStream_t s);
-void launch_reconstruct(int64_t n, const u64* m, const u64* r1, const u64* r2, Inj r1inj, u64* out,
-                        int* flag, hipStream_t s);
+void launch_rec_check(int64_t n, const u64* r1, Inj r1inj, int* flag, hipStream_t s);
+void launch_rec_open(int64_t n, const u64* m, const u64* r1, const u64* r2, const int* flag, u64* out,
+                     hipStream_t s);
 
 // --- Galois-ring steps (d = 64; an element is 64 consecutive words) ---------
 // v = m - r1 - r2 of a random <.>^{l[x]} drawn with (op, purpose, sub); also keeps the share.

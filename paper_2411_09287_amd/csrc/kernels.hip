@@ -328,13 +328,20 @@ __global__ void k_sumpool2(const u64* x, int B, int H, int W, int C, u64* out) {
     out[idx] = p[0] + p[C] + p[(int64_t)W * C] + p[(int64_t)W * C + C];
 }
 
-__global__ void k_reconstruct(int64_t n, const u64* m, const u64* r1, const u64* r2, Inj inj, u64* out,
-                              int* flag) {
+// Pi_Rec: P2 compares the [r]_1 that P0 sent (with an injected error, if any) with P1's
+// hash of its own copy (equal hashes <=> equal words); any difference sets the flag.
+__global__ void k_rec_check(int64_t n, const u64* r1, Inj inj, int* flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const u64 mine = r1[i];                                      // P1's [r]_1 (hashed to P2)
-    const u64 sent = r1[i] + (i == inj.index ? inj.e : 0);       // P0's [r]_1 as P2 receives it
+    const u64 mine = r1[i];
+    const u64 sent = r1[i] + (i == inj.index ? inj.e : 0);
     if (sent != mine) atomicOr(flag, 1);
+}
+
+// The opened values, written only if no receiver saw an inconsistency.
+__global__ void k_rec_open(int64_t n, const u64* m, const u64* r1, const u64* r2, const int* flag, u64* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || *flag) return;
     out[i] = m[i] - r1[i] - r2[i];
 }
 
@@ -1263,10 +1270,14 @@ void launch_sumpool2(const u64* x, int B, int H, int W, int C, u64* out, hipStre
     if (total <= 0) return;
     hipLaunchKernelGGL(k_sumpool2, dim3(nblocks(total, TPB)), dim3(TPB), 0, s, x, B, H, W, C, out);
 }
-void launch_reconstruct(int64_t n, const u64* m, const u64* r1, const u64* r2, Inj r1inj, u64* out,
-                        int* flag, hipStream_t s) {
+void launch_rec_check(int64_t n, const u64* r1, Inj r1inj, int* flag, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_reconstruct, dim3(nblocks(n, TPB)), dim3(TPB), 0, s, n, m, r1, r2, r1inj, out, flag);
+    hipLaunchKernelGGL(k_rec_check, dim3(nblocks(n, TPB)), dim3(TPB), 0, s, n, r1, r1inj, flag);
+}
+void launch_rec_open(int64_t n, const u64* m, const u64* r1, const u64* r2, const int* flag, u64* out,
+                     hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_rec_open, dim3(nblocks(n, TPB)), dim3(TPB), 0, s, n, m, r1, r2, flag, out);
 }
 void launch_random_gr(const Keys& k, u32 op, u32 purpose, u32 sub, u64* share3, u64* value, u64* log,
                       hipStream_t s) {

@@ -69,6 +69,7 @@ SIGNATURES = {
     "mpc3_profile": (_I, [_P, _I]),
     "mpc3_profile_read": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64),
                                 ctypes.POINTER(ctypes.c_double)]),
+    "mpc3_last_error": (_I, [_P, ctypes.POINTER(_I), ctypes.c_char_p, ctypes.c_size_t]),
     "mpc3_strerror": (ctypes.c_char_p, [_I]),
 }
 
@@ -91,14 +92,20 @@ def lib():
 
 
 class Mpc3Error(RuntimeError):
-    def __init__(self, code, where):
+    def __init__(self, code, where, detail=""):
         self.code = code
-        super().__init__(f"{where}: {lib().mpc3_strerror(code).decode()} ({code})")
+        super().__init__(f"{where}: {lib().mpc3_strerror(code).decode()} ({code}){detail}")
 
 
-def _ck(code, where):
+def _ck(code, where, ctx=None):
     if code != OK:
-        raise Mpc3Error(code, where)
+        detail = ""
+        if ctx is not None and code == E_HIP:
+            hip = ctypes.c_int(0)
+            buf = ctypes.create_string_buffer(512)
+            lib().mpc3_last_error(ctx, ctypes.byref(hip), buf, 512)
+            detail = f" [hipError {hip.value} at {buf.value.decode()}]"
+        raise Mpc3Error(code, where, detail)
 
 
 def _ptr(t):
@@ -187,30 +194,30 @@ class Context:
 
     # -- configuration -------------------------------------------------------
     def set_variant(self, v):
-        _ck(lib().mpc3_set_variant(self.h, v), "mpc3_set_variant")
+        _ck(lib().mpc3_set_variant(self.h, v), "mpc3_set_variant", self.h)
 
     def autotune(self, M, K, N, reps=3):
         ch, a, b = ctypes.c_int(0), ctypes.c_double(0), ctypes.c_double(0)
         _ck(lib().mpc3_autotune(self.h, M, K, N, reps, ctypes.byref(ch), ctypes.byref(a), ctypes.byref(b)),
-            "mpc3_autotune")
+            "mpc3_autotune", self.h)
         return ch.value, a.value, b.value
 
     def set_chunk(self, t):
-        _ck(lib().mpc3_set_chunk(self.h, t), "mpc3_set_chunk")
+        _ck(lib().mpc3_set_chunk(self.h, t), "mpc3_set_chunk", self.h)
 
     def keep_messages(self, on=True):
-        _ck(lib().mpc3_keep_messages(self.h, int(on)), "mpc3_keep_messages")
+        _ck(lib().mpc3_keep_messages(self.h, int(on)), "mpc3_keep_messages", self.h)
 
     # -- protocol --------------------------------------------------------------
     def encode(self, x):
         x = x.to(self.device, torch.float64).contiguous()
         out = torch.empty(x.shape, dtype=torch.int64, device=self.device)
-        _ck(lib().mpc3_encode(self.h, _ptr(x), x.numel(), _ptr(out)), "mpc3_encode")
+        _ck(lib().mpc3_encode(self.h, _ptr(x), x.numel(), _ptr(out)), "mpc3_encode", self.h)
         return out
 
     def decode(self, v):
         out = torch.empty(v.shape, dtype=torch.float64, device=self.device)
-        _ck(lib().mpc3_decode(self.h, _ptr(v), v.numel(), _ptr(out)), "mpc3_decode")
+        _ck(lib().mpc3_decode(self.h, _ptr(v), v.numel(), _ptr(out)), "mpc3_decode", self.h)
         return out
 
     def share(self, x, owner=0):
@@ -219,12 +226,12 @@ class Context:
         cols = x.numel() // rows if rows else 0
         out = DShare.empty(rows, cols, self.device)
         s = out.c()
-        _ck(lib().mpc3_share(self.h, owner, _ptr(x), ctypes.byref(s)), "mpc3_share")
+        _ck(lib().mpc3_share(self.h, owner, _ptr(x), ctypes.byref(s)), "mpc3_share", self.h)
         return out
 
     def trunc_pair(self, n, t):
         p = DPair(n, self.device)
-        _ck(lib().mpc3_trunc_pair(self.h, n, t, ctypes.byref(p.s)), "mpc3_trunc_pair")
+        _ck(lib().mpc3_trunc_pair(self.h, n, t, ctypes.byref(p.s)), "mpc3_trunc_pair", self.h)
         self._keep[VERIFY_TRUNC].append(p)
         return p
 
@@ -232,7 +239,7 @@ class Context:
         Z = out if out is not None else DShare.empty(X.rows, W.cols, self.device)
         xs, ws, zs = X.c(), W.c(), Z.c()
         _ck(lib().mpc3_inner(self.h, ctypes.byref(xs), ctypes.byref(ws),
-                             ctypes.byref(pair.s) if pair is not None else None, ctypes.byref(zs)), "mpc3_inner")
+                             ctypes.byref(pair.s) if pair is not None else None, ctypes.byref(zs)), "mpc3_inner", self.h)
         self._keep[VERIFY_INNER].append((X, W, Z))
         return Z
 
@@ -241,62 +248,70 @@ class Context:
         OH, OW = H + 2 * pad - KH + 1, W + 2 * pad - KW + 1
         cols = DShare.empty(B * OH * OW, ld or KH * KW * C, self.device)
         xs, cs = x.c(), cols.c()
-        _ck(lib().mpc3_im2col(self.h, ctypes.byref(xs), B, H, W, C, KH, KW, pad, ctypes.byref(cs)), "mpc3_im2col")
+        _ck(lib().mpc3_im2col(self.h, ctypes.byref(xs), B, H, W, C, KH, KW, pad, ctypes.byref(cs)), "mpc3_im2col", self.h)
         return cols
 
     def sumpool2(self, x, B, H, W, C):
         out = DShare.empty(B, (H // 2) * (W // 2) * C, self.device)
         xs, os_ = x.c(), out.c()
-        _ck(lib().mpc3_sumpool2(self.h, ctypes.byref(xs), B, H, W, C, ctypes.byref(os_)), "mpc3_sumpool2")
+        _ck(lib().mpc3_sumpool2(self.h, ctypes.byref(xs), B, H, W, C, ctypes.byref(os_)), "mpc3_sumpool2", self.h)
         return out
 
     def mult(self, a, b):
         c = DShare.empty(a.rows, a.cols, self.device)
         sa, sb, sc = a.c(), b.c(), c.c()
-        _ck(lib().mpc3_mult(self.h, ctypes.byref(sa), ctypes.byref(sb), ctypes.byref(sc)), "mpc3_mult")
+        _ck(lib().mpc3_mult(self.h, ctypes.byref(sa), ctypes.byref(sb), ctypes.byref(sc)), "mpc3_mult", self.h)
         self._keep[VERIFY_MULT].append((a, b, c))
         return c
 
     def trunc(self, pair, Z):
         out = DShare.empty(Z.rows, Z.cols, self.device)
         zs, os_ = Z.c(), out.c()
-        _ck(lib().mpc3_trunc(self.h, ctypes.byref(pair.s), ctypes.byref(zs), ctypes.byref(os_)), "mpc3_trunc")
+        _ck(lib().mpc3_trunc(self.h, ctypes.byref(pair.s), ctypes.byref(zs), ctypes.byref(os_)), "mpc3_trunc", self.h)
         return out
 
     def verify(self, R=-1, kinds=VERIFY_ALL):
         ok = ctypes.c_int(0)
-        _ck(lib().mpc3_verify(self.h, R, kinds, ctypes.byref(ok)), "mpc3_verify")
+        _ck(lib().mpc3_verify(self.h, R, kinds, ctypes.byref(ok)), "mpc3_verify", self.h)
         for k in self._keep:
             if kinds & k:
                 self._keep[k] = []
         return bool(ok.value)
 
-    def reconstruct(self, X, to_party=-1):
-        out = torch.empty(X.m.shape, dtype=torch.int64, device=self.device)
+    def reconstruct(self, X, to_party=-1, out=None):
+        if out is None:
+            out = torch.empty(X.m.shape, dtype=torch.int64, device=self.device)
         xs = X.c()
-        _ck(lib().mpc3_reconstruct(self.h, ctypes.byref(xs), to_party, _ptr(out)), "mpc3_reconstruct")
+        _ck(lib().mpc3_reconstruct(self.h, ctypes.byref(xs), to_party, _ptr(out)), "mpc3_reconstruct", self.h)
         return out
+
+    def last_error(self):
+        """(code, hipError_t, where) of the last failed call on this context."""
+        hip = ctypes.c_int(0)
+        buf = ctypes.create_string_buffer(512)
+        code = lib().mpc3_last_error(self.h, ctypes.byref(hip), buf, 512)
+        return code, hip.value, buf.value.decode()
 
     def comm_stats(self):
         c = Comm()
-        _ck(lib().mpc3_comm_stats(self.h, ctypes.byref(c)), "mpc3_comm_stats")
+        _ck(lib().mpc3_comm_stats(self.h, ctypes.byref(c)), "mpc3_comm_stats", self.h)
         b = np.array(list(c.bytes), dtype=np.uint64).reshape(4, 3, 3)
         return b, list(c.rounds)
 
     def inject(self, site, index, e):
-        _ck(lib().mpc3_inject(self.h, site, index, e & ((1 << 64) - 1)), "mpc3_inject")
+        _ck(lib().mpc3_inject(self.h, site, index, e & ((1 << 64) - 1)), "mpc3_inject", self.h)
 
     def message(self, kind, which, n):
         out = torch.empty(n, dtype=torch.int64, device=self.device)
-        _ck(lib().mpc3_message(self.h, kind, which, _ptr(out), n), "mpc3_message")
+        _ck(lib().mpc3_message(self.h, kind, which, _ptr(out), n), "mpc3_message", self.h)
         return out
 
     def profile(self, on=True):
-        _ck(lib().mpc3_profile(self.h, int(on)), "mpc3_profile")
+        _ck(lib().mpc3_profile(self.h, int(on)), "mpc3_profile", self.h)
 
     def profile_read(self):
         t, n, w = ctypes.c_double(0), ctypes.c_int64(0), ctypes.c_double(0)
-        _ck(lib().mpc3_profile_read(self.h, ctypes.byref(t), ctypes.byref(n), ctypes.byref(w)), "mpc3_profile_read")
+        _ck(lib().mpc3_profile_read(self.h, ctypes.byref(t), ctypes.byref(n), ctypes.byref(w)), "mpc3_profile_read", self.h)
         return t.value, n.value, w.value
 
     def verify_log(self, instance, slot, rnd=0):
@@ -304,5 +319,5 @@ class Context:
         R = ctypes.c_int(0)
         dim = ctypes.c_int64(0)
         _ck(lib().mpc3_verify_log(self.h, instance, slot, rnd, buf, ctypes.byref(R), ctypes.byref(dim)),
-            "mpc3_verify_log")
+            "mpc3_verify_log", self.h)
         return np.array(list(buf), dtype=np.uint64), R.value, dim.value

@@ -108,3 +108,81 @@ def test_server_packs_and_verifies_small_mix():
     assert res["ok"] and set(res["latency"]) == {0, 1, 2, 3, 4}
     s = serve.summary(res)
     assert s["images"] == 12 and s["p50_ms"] <= s["p99_ms"]
+
+
+def oracle_forward(o, name, x, batch):
+    """The oracle through the call sequence of network.Network (weights shared first with
+    the convolutions' zero-padded rows, then per layer: im2col with zero columns up to the
+    padded width, truncation pair, Pi_Inner, truncation, sum pooling)."""
+    from oracle.layers import im2col_share
+    from oracle.protocol import Share
+
+    frac = workloads.FRAC_BITS
+    plan = network.plan(name)
+    weights = []
+    for d, w in zip(plan, network.float_weights(name)):
+        if d.get("kpad", w.shape[0]) > w.shape[0]:
+            w = np.concatenate([w, np.zeros((d["kpad"] - w.shape[0], w.shape[1]))])
+        weights.append(o.share(o_encode(w, frac)))
+    h = o.share(o_encode(x, frac).reshape(batch, -1))
+    for d, W in zip(plan, weights):
+        layer = d["layer"]
+        if layer[0] == "conv":
+            _, kh, kw, cin, cout, pad, (hh, ww) = layer
+            X = im2col_share(h.map(lambda a: a.reshape(batch, hh, ww, cin)), kh, kw, pad)
+            extra = d["kpad"] - X.m.shape[1]
+            if extra:
+                X = X.map(lambda a: np.concatenate([a, np.zeros((a.shape[0], extra), dtype=np.uint64)], axis=1))
+        else:
+            X = h.map(lambda a: a.reshape(batch, -1))
+        M, N = X.m.shape[0], W.m.shape[1]
+        pair = o.trunc_pair(M * N, frac)
+        Y = o.trunc(pair, o.inner(X, W, pair))
+        if d["pool_after"]:
+            oh, ow = d["out_hw"]
+            Y = sumpool2_share(Y.map(lambda a: a.reshape(batch, -1)), batch, oh, ow, layer[4])
+        h = Share(*[a.reshape(batch, -1) for a in Y.comps()])
+    return h
+
+
+_ORACLE_NET = {}
+
+
+@pytest.mark.parametrize("name,batch", [("lenet", 4), ("vgg", 2)])
+@pytest.mark.parametrize("variant", [mpc3.VARIANT_U64, mpc3.VARIANT_LIMB_I8])
+def test_network_chain_matches_oracle(name, batch, variant):
+    """The chained network against the oracle running the same calls on the same seeds:
+    every layer's shares, the whole transcript of the batched verification of all the
+    layer products (r, z, every zeta, the h(0) / h(x) messages, Delta and its messages),
+    and the opened logits, bit for bit; the truncation gates then verify on the GPU."""
+    seed = workloads.master_seed(4)
+    x = workloads.rng(32).random((batch,) + tuple(workloads.MODELS[name]["input"]))
+    if (name, batch) not in _ORACLE_NET:      # the oracle's side is the same for both variants
+        o = Ctx(seed)
+        ho = oracle_forward(o, name, x, batch)
+        assert o.verify(kinds=1)
+        _ORACLE_NET[(name, batch)] = (ho, o.vlog[0])
+    ho, log = _ORACLE_NET[(name, batch)]
+    c = mpc3.Context(seed)
+    c.set_variant(variant)
+    net = network.Network(c, name)
+    hg = net.forward(torch.from_numpy(x).cuda())
+    for a, b in zip(hg.numpy(), ho.comps()):
+        assert np.array_equal(a.reshape(-1), b.reshape(-1))
+    assert c.verify(kinds=mpc3.VERIFY_INNER)
+    r, R, dim = c.verify_log(0, mpc3.LOG_R)
+    assert np.array_equal(r, log["r"]) and R == log["R"] and dim == log["npad"]
+    assert R >= 7
+    assert np.array_equal(c.verify_log(0, mpc3.LOG_Z)[0], log["z"].m)
+    for k, rl in enumerate(log["rounds"]):
+        assert np.array_equal(c.verify_log(0, mpc3.LOG_ZETA, k)[0], rl["zeta"]), k
+        for slot, key in [(mpc3.LOG_H0_M1, "m1"), (mpc3.LOG_H0_M2, "m2"), (mpc3.LOG_H0_G2, "gamma2")]:
+            assert np.array_equal(c.verify_log(0, slot, k)[0], rl["h0"][key]), (k, key)
+        for slot, key in [(mpc3.LOG_H2_M1, "m1"), (mpc3.LOG_H2_M2, "m2"), (mpc3.LOG_H2_G2, "gamma2")]:
+            assert np.array_equal(c.verify_log(0, slot, k)[0], rl["h2"][key]), (k, key)
+    assert np.array_equal(c.verify_log(0, mpc3.LOG_DELTA)[0], log["delta"])
+    for slot, key in [(mpc3.LOG_DELTA_M1, "m1"), (mpc3.LOG_DELTA_M2, "m2"), (mpc3.LOG_DELTA_G2, "gamma2")]:
+        assert np.array_equal(c.verify_log(0, slot)[0], log["delta_tr"][key]), key
+    assert c.verify(kinds=mpc3.VERIFY_TRUNC)
+    logits = mpc3.from_words(c.reconstruct(hg)).reshape(-1)
+    assert np.array_equal(logits, ho.value().reshape(-1))

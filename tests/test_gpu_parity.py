@@ -63,24 +63,45 @@ def test_share_parity(owner, n):
 
 
 SHAPES = [(1, 1, 1), (5, 7, 3), (64, 128, 64), (130, 77, 65), (33, 300, 17), (2, 1025, 3),
-          (130, 300, 129), (257, 1030, 70)]
+          (130, 300, 129), (257, 1030, 70),
+          # the matrix-core kernels the VGG-style network runs, at sizes the oracle finishes:
+          (512, 576, 128),     # 64 x 128 tiles, B digit tiles converted once, P0's A planes summed
+          (2048, 1152, 256),   # the same with B tiles beyond one XCD's L2 (row-tile groups)
+          (32, 4096, 256),     # one row tile, both operands converted in the kernel (the FC layer)
+          (36864, 32, 20),     # one 32-deep k-block, 20 columns (LeNet's first convolution)
+          (8192, 32, 64)]      # the first VGG convolution's padded width at a quarter of its rows
+
+
+_ORACLE_INNER = {}
+
+
+def _oracle_inner(M, K, N):
+    """The oracle's shares and messages of one Pi_Inner on seeded operands (computed once
+    per shape; the result does not depend on the kernel family compared with it)."""
+    if (M, K, N) not in _ORACLE_INNER:
+        g = np.random.default_rng(M * 7 + K * 3 + N)
+        X0, W0 = u64(g, M, K), u64(g, K, N)
+        o = Ctx(SEED, chunk=8)
+        Zo = o.inner(o.share(X0), o.share(W0))
+        _ORACLE_INNER[(M, K, N)] = (X0, W0, Zo, o.msgs["inner"])
+    return _ORACLE_INNER[(M, K, N)]
 
 
 @pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_inner_parity(variant, shape):
     M, K, N = shape
-    g = np.random.default_rng(M * 7 + K * 3 + N)
-    X0, W0 = u64(g, M, K), u64(g, K, N)
-    o, c = pair_of(variant)
-    Xo, Wo = o.share(X0), o.share(W0)
-    Zo = o.inner(Xo, Wo)
+    X0, W0, Zo, msgs = _oracle_inner(M, K, N)
+    c = mpc3.Context(SEED)
+    c.set_variant(variant)
+    c.set_chunk(8)
+    c.keep_messages(True)
     Xg, Wg = c.share(mpc3.to_words(X0)), c.share(mpc3.to_words(W0))
     Zg = c.inner(Xg, Wg)
     assert same_share(Zg, Zo)
     for which, key in [(mpc3.MSG_GAMMA2, "gamma2"), (mpc3.MSG_M1, "m1"), (mpc3.MSG_M2, "m2")]:
         msg = mpc3.from_words(c.message(0, which, M * N))
-        assert np.array_equal(msg, o.msgs["inner"][key].reshape(-1)), key
+        assert np.array_equal(msg, msgs[key].reshape(-1)), key
 
 
 @pytest.mark.parametrize("n,t", [(1, 13), (37, 13), (64, 1), (100, 62), (4096, 13)])
@@ -218,11 +239,12 @@ SITES = [mpc3.SITE_INNER_GAMMA2, mpc3.SITE_INNER_M1, mpc3.SITE_TRUNC_GAMMA2, mpc
          mpc3.SITE_MULT_GAMMA2, mpc3.SITE_VER_H0_M1, mpc3.SITE_VER_H2_GAMMA2, mpc3.SITE_VER_DELTA_M1]
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("site", SITES)
 @pytest.mark.parametrize("e", [1, 1 << 63])
-def test_injected_error_detected(site, e):
+def test_injected_error_detected(site, e, variant):
     g = np.random.default_rng(site)
-    o, c = pair_of(0, chunk=4)
+    o, c = pair_of(variant, chunk=4)
     # verification sites index (instance << 16 | round << 8 | coefficient): instance 1 is
     # the first truncation chunk (the batched Pi_Inner instance, 0, has no rounds here)
     idx = (1 << 16) | 3 if site in (mpc3.SITE_VER_H0_M1, mpc3.SITE_VER_H2_GAMMA2, mpc3.SITE_VER_DELTA_M1) else 3
@@ -239,9 +261,58 @@ def test_reconstruct_inconsistency_aborts():
     s = c.share(mpc3.to_words(np.arange(10, dtype=np.uint64).reshape(10, 1)))
     assert np.array_equal(mpc3.from_words(c.reconstruct(s)).reshape(-1), np.arange(10))
     c.inject(mpc3.SITE_REC_R1, 4, 77)
+    sentinel = torch.full((10, 1), -12345, dtype=torch.int64, device="cuda")
+    with pytest.raises(mpc3.Mpc3Error) as ei:
+        c.reconstruct(s, out=sentinel)
+    assert ei.value.code == mpc3.E_ABORTED
+    # nothing is opened when a receiver saw an inconsistency
+    assert bool((sentinel == -12345).all())
     with pytest.raises(mpc3.Mpc3Error) as ei:
         c.reconstruct(s)
     assert ei.value.code == mpc3.E_ABORTED
+
+
+@pytest.mark.parametrize("to_party", [-1, 0, 1, 2])
+def test_reconstruct_to_one_party_parity(to_party):
+    """Pi_Rec^{l,k}: the value and the counted messages match the oracle's opening to P_k;
+    an error on P0 -> P2's [r]_1 aborts only an opening that P2 receives."""
+    x = np.arange(1, 34, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+    o, c = pair_of(0)
+    so, sg = o.share(x.reshape(-1, 1)), c.share(mpc3.to_words(x.reshape(-1, 1)))
+    want = o.reconstruct(so, to_party)
+    got = mpc3.from_words(c.reconstruct(sg, to_party)).reshape(-1)
+    assert np.array_equal(got, want.reshape(-1))
+    bg, rg = c.comm_stats()
+    assert np.array_equal(bg, np.array(o.comm, dtype=np.uint64)) and rg == o.rounds
+    c.inject(mpc3.SITE_REC_R1, 3, 1)
+    if to_party in (-1, 2):
+        with pytest.raises(mpc3.Mpc3Error) as ei:
+            c.reconstruct(sg, to_party)
+        assert ei.value.code == mpc3.E_ABORTED
+    else:
+        assert np.array_equal(mpc3.from_words(c.reconstruct(sg, to_party)).reshape(-1), want.reshape(-1))
+
+
+def test_chunk_limit_and_error_record():
+    c = mpc3.Context(SEED)
+    c.set_chunk(1 << 19)
+    for bad in (0, (1 << 19) + 1, 1 << 20):
+        with pytest.raises(mpc3.Mpc3Error) as ei:
+            c.set_chunk(bad)
+        assert ei.value.code == mpc3.E_ARG
+    assert c.last_error()[0] == 0
+    # a workspace request far beyond the device fails cleanly, is recorded with its entry
+    # point, and leaves the context usable
+    with pytest.raises(mpc3.Mpc3Error) as ei:
+        c.autotune(1 << 40, 1, 1, reps=1)
+    assert ei.value.code == mpc3.E_NOMEM
+    code, hip, where = c.last_error()
+    assert code == mpc3.E_NOMEM and where.startswith("mpc3_autotune")
+    g = np.random.default_rng(2)
+    X0, W0 = u64(g, 3, 4), u64(g, 4, 2)
+    Z = c.inner(c.share(mpc3.to_words(X0)), c.share(mpc3.to_words(W0)))
+    assert c.verify()
+    assert np.array_equal(mpc3.from_words(c.reconstruct(Z)), X0 @ W0)
 
 
 def test_reconstruct_requires_verification():
@@ -291,7 +362,12 @@ def test_im2col_padded_width(C, ld):
 def test_variants_bit_identical_on_ragged_shapes():
     g = np.random.default_rng(11)
     for M, K, N in [(67, 129, 33), (256, 512, 64), (1, 2048, 1), (1000, 33, 200), (64, 9000, 64),
-                    (4097, 27, 65)]:
+                    (4097, 27, 65),
+                    # every product of the VGG-style network at batch 32 (padded first width)
+                    (32768, 32, 64), (32768, 576, 64), (8192, 576, 128), (8192, 1152, 128),
+                    (2048, 1152, 256), (2048, 2304, 256), (32, 4096, 256), (32, 256, 10),
+                    # LeNet at batch 64 (padded widths) and the synthetic 25600 x 500 x 50
+                    (36864, 32, 20), (4096, 512, 50), (64, 800, 500), (64, 500, 10), (25600, 500, 50)]:
         X0, W0 = u64(g, M, K), u64(g, K, N)
         outs = []
         for v in (0, 1):
@@ -348,3 +424,22 @@ def test_variant_transcripts_identical():
         logs.append((Z.numpy(), entries))
     assert all(np.array_equal(a, b) for a, b in zip(logs[0][0], logs[1][0]))
     assert all(np.array_equal(a, b) for a, b in zip(logs[0][1], logs[1][1]))
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("inj", [None, (mpc3.SITE_TRUNC_M1, 300001, 1 << 40)])
+def test_production_truncation_chunk_verifies(variant, inj):
+    """One chunk of the default size, 524288 truncations (2^20 gates: claims over 2^20
+    powers, symbolic blocks of 4096 gates, materialisation blocks of 1024 gates), as the
+    network benchmark verifies them: an honest run passes and one added error fails."""
+    M, N, K = 8192, 64, 3
+    g = np.random.default_rng(90 + variant)
+    c = mpc3.Context(SEED)
+    c.set_variant(variant)
+    assert M * N == 1 << 19
+    if inj:
+        c.inject(*inj)
+    Xg, Wg = c.share(mpc3.to_words(u64(g, M, K))), c.share(mpc3.to_words(u64(g, K, N)))
+    pg = c.trunc_pair(M * N, 13)
+    c.trunc(pg, c.inner(Xg, Wg, pg))
+    assert c.verify() == (inj is None)
