@@ -67,7 +67,8 @@ enum {
     MPC3_E_ABORTED = -4,    /* a verification failed or Pi_Rec saw inconsistent shares */
     MPC3_E_UNVERIFIED = -5, /* reconstruct requested while products await verification */
     MPC3_E_HIP = -6,        /* a HIP runtime call failed */
-    MPC3_E_STATE = -7       /* call not valid in the current state */
+    MPC3_E_STATE = -7,      /* call not valid in the current state */
+    MPC3_E_LIMIT = -8       /* operands exceed the fixed workspace of mpc3_inner_static */
 };
 
 enum { MPC3_VARIANT_U64 = 0, MPC3_VARIANT_LIMB_I8 = 1, MPC3_VARIANT_AUTO = 2 };
@@ -164,6 +165,23 @@ int mpc3_trunc_pair(mpc3_ctx* ctx, int64_t n, int t, mpc3_trunc_pair_t* out);
  * NULL draws a fresh mask.  Registers the product for verification. */
 int mpc3_inner(mpc3_ctx* ctx, const mpc3_share_t* X, const mpc3_share_t* W,
                const mpc3_trunc_pair_t* out_mask, mpc3_share_t* Z);
+
+/* mpc3_inner for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * results, registration and counters as mpc3_inner, bit for bit, but the call's
+ * device workspace (the three party sums, P0's [Gamma]_1 and the matrix-core digit
+ * tiles of W) is one fixed array of 128 MiB per GPU, held from the library's load to
+ * the end of the process, so the call makes no hipMalloc, hipFree or other device
+ * allocation (the host-side list of pending products grows as for mpc3_inner).  The
+ * product keeps no split-K partial sums there (K is split only where the 32-bit digit
+ * sums require it).  MPC3_E_LIMIT, before any launch, when the operands need more
+ * than the array: about 32 bytes per output plus 40 bytes per element of W (VGG-style
+ * layers of a batch of 32 fit).  MPC3_E_STATE with mpc3_keep_messages on (message
+ * copies would need device memory); profiling (mpc3_profile) does not time it.  Every
+ * call on one GPU uses the same array: calls ordered on one stream are safe, calls
+ * of different contexts or streams that overlap in time on one GPU race. */
+int mpc3_inner_static(mpc3_ctx* ctx, const mpc3_share_t* X, const mpc3_share_t* W,
+                      const mpc3_trunc_pair_t* out_mask, mpc3_share_t* Z);
 
 /* Convolution lowering: cols (B*OH*OW rows, KH*KW*C cols) from an NHWC shared
  * tensor x (B*H*W*C words per plane), zero padding pad, stride 1.  Each plane

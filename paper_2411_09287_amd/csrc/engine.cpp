@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <new>
 #include <stdexcept>
@@ -18,6 +19,13 @@
 #include "kernels.h"
 
 using namespace mpc3;
+
+// Workspace of mpc3_inner_static, for callers that cannot allocate device memory: the three
+// party sums, P0's [Gamma]_1 and the matrix-core digit tiles of one product.  Each GPU holds
+// its own copy from the library's load to the end of the process.  Host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device (mpc3_ctx_create).
+constexpr size_t STATIC_WS_BYTES = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
 
 namespace {
 
@@ -150,6 +158,8 @@ struct mpc3_ctx {
     int err_code = 0, err_hip = 0, err_line = 0;
     const char* err_fn = "";
     std::string err_call;
+    // this device's copy of the static workspace (mpc3_inner_static)
+    void* static_ws = nullptr;
     // launch timing of the Pi_Inner products
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -194,6 +204,34 @@ OutView oview(u64* p, int64_t s0, int64_t s1, int64_t sb = 0) { return OutView{p
 
 void* scratch_alloc(void* self, size_t n) { return ((Scratch*)self)->alloc(n); }
 
+// Bump allocation over the static workspace; nullptr when it is full.
+struct StaticArena {
+    char* base;
+    size_t cap, off;
+};
+void* static_alloc(void* self, size_t n) {
+    StaticArena* a = (StaticArena*)self;
+    n = (n + 255) & ~(size_t)255;
+    if (n == 0) n = 256;
+    if (n > a->cap - a->off) return nullptr;
+    void* p = a->base + a->off;
+    a->off += n;
+    return p;
+}
+
+// Bytes of static workspace one M x K by K x N Pi_Inner takes at most: [Gamma]_1 and the
+// three party sums (4 M N words), and the matrix-core kernel's digit tiles of its five B
+// operands (8 bytes per element of the K x N operand padded to 32-deep k-blocks and
+// 64-column tiles), converted once per slice of at most 65535 * 64 rows.
+size_t static_ws_need(int64_t M, int64_t K, int64_t N) {
+    auto al = [](double b) { return std::ceil(b / 256.0) * 256.0; };
+    const double n = (double)M * (double)N;
+    const double slices = (double)std::max<int64_t>(1, (M + 65535 * 64 - 1) / (65535 * 64));
+    const double tiles = 5.0 * al(8.0 * (double)((K + 31) / 32 * 32) * (double)((N + 63) / 64 * 64));
+    const double need = al(8.0 * std::max(n, 1.0)) + al(24.0 * std::max(n, 1.0)) + slices * tiles;
+    return need > 1e18 ? (size_t)-1 : (size_t)need;
+}
+
 void run_gemm(mpc3_ctx* c, const GemmArgs& g) {
     GemmArgs a = g;
     a.ws_alloc = scratch_alloc;
@@ -218,7 +256,9 @@ GemmArgs plain(int64_t M, int64_t N, int64_t K, View A, View B, OutView C, bool 
     return g;
 }
 
-void zero(mpc3_ctx* c, void* p, size_t bytes) { ck(hipMemsetAsync(p, 0, bytes, c->cs)); }
+// Zero fill by a kernel rather than hipMemsetAsync, so that the same calls can be captured in
+// a graph (every size here is a multiple of 4 bytes).
+void zero(mpc3_ctx* c, void* p, size_t bytes) { ck(zero_words32(p, (int64_t)(bytes / 4), c->cs)); }
 
 // table[i] = base^i for i < n (table: n x 64).
 //   n <= 256: doubling, one launch per level (table[len + i] = table[i] base^len, with the
@@ -861,6 +901,75 @@ Key key_of(const uint8_t d[32]) {
     return k;
 }
 
+// Pi_Inner of every output of Z = X W: P0's offline Gamma (its [Gamma]_1 from the PRG), the
+// three parties' local sums as one three-party product, then the exchange (Fig. "The Inner
+// Product Protocol").  The workspace (the party sums, [Gamma]_1 and the product's own) comes
+// from `wsa`; with static_ws it is the fixed device array, no message copies are kept, no
+// launch is timed and the product keeps no split-K partial sums.
+void inner_body(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W, const mpc3_trunc_pair_t* pair,
+                mpc3_share_t* Z, void* (*wsa)(void*, size_t), void* wss, bool static_ws) {
+    const int64_t M = X->rows, K = X->cols, N = W->cols;
+    const uint32_t op = c->op++;
+    const int64_t n = M * N;
+    hipStream_t s = c->stream;
+    u64* G1 = (u64*)wsa(wss, (size_t)std::max<int64_t>(n, 1) * 8);
+    u64* C = (u64*)wsa(wss, (size_t)std::max<int64_t>(3 * n, 1) * 8);
+    if (!G1 || !C) throw CodeError(MPC3_E_NOMEM);
+    launch_inner_pre(n, c->keys, op, pair ? pair->rx.m : nullptr, pair ? pair->rx.r1 : nullptr,
+                     pair ? pair->rx.r2 : nullptr, Z->r1, Z->r2, G1, s);
+    GemmArgs ga{};
+    ga.M = M; ga.N = N; ga.K = K; ga.batch = 1; ga.party = true; ga.accumulate = false;
+    ga.ws_alloc = wsa;
+    ga.ws_self = wss;
+    ga.no_part = static_ws;
+    const u64* Xp[3] = {X->m, X->r1, X->r2};
+    const u64* Wp[3] = {W->m, W->r1, W->r2};
+    for (int p = 0; p < 3; ++p) {
+        ga.A[p] = view(Xp[p], K, 1);
+        ga.B[p] = view(Wp[p], N, 1);
+        ga.C[p] = oview(C + p * n, N, 1);
+    }
+    int variant = c->variant;
+    if (variant == MPC3_VARIANT_AUTO) {
+        auto it = c->tuned.find(std::make_tuple(m_bucket(M), K, N));
+        variant = it == c->tuned.end() ? MPC3_VARIANT_LIMB_I8 : it->second;
+    }
+    if (K == 0) {
+        zero(c, C, (size_t)3 * n * 8);
+    } else if (c->prof && !static_ws) {
+        hipEvent_t e0, e1;
+        ck(hipEventCreate(&e0));
+        ck(hipEventCreate(&e1));
+        ck(hipEventRecord(e0, s));
+        ck(gemm(ga, variant, s));
+        ck(hipEventRecord(e1, s));
+        c->ev.push_back({e0, e1});
+        c->prof_macs += 5.0 * (double)M * (double)K * (double)N;
+    } else {
+        const hipError_t e = gemm(ga, variant, s);
+        if (e == hipErrorOutOfMemory) throw CodeError(MPC3_E_NOMEM);
+        ck(e);
+    }
+    u64 *mg2 = nullptr, *mm1 = nullptr, *mm2 = nullptr;
+    if (c->keep_msgs && !static_ws) {
+        ensure_msgs(c, 0, n);
+        mg2 = c->msg[0][0]; mm1 = c->msg[0][1]; mm2 = c->msg[0][2];
+    }
+    launch_inner_post(n, C, C + n, C + 2 * n, Z->r1, Z->r2, G1, take(c, MPC3_SITE_INNER_GAMMA2, n),
+                      take(c, MPC3_SITE_INNER_M1, n), Z->m, mg2, mm1, mm2, s);
+    ck(hipGetLastError());
+    send(c, MPC3_PH_OFFLINE, 0, 2, 8 * n);
+    c->rounds[MPC3_PH_OFFLINE] += 1;
+    send(c, MPC3_PH_ONLINE, 1, 2, 8 * n);
+    send(c, MPC3_PH_ONLINE, 2, 1, 8 * n);
+    c->rounds[MPC3_PH_ONLINE] += 1;
+    Pending p{};
+    p.kind = MPC3_VERIFY_INNER;
+    p.X = *X; p.W = *W; p.Z = *Z;
+    p.op = op;
+    c->pending.push_back(p);
+}
+
 }  // namespace
 
 extern "C" {
@@ -908,6 +1017,30 @@ int mpc3_ctx_create(const uint8_t master_seed[32], int d, int frac_bits, size_t 
             (void)hipFree(p);
             delete c;
             return (int)MPC3_E_HIP;
+        }
+        // the static workspace's address on the current device, looked up once per device
+        {
+            static std::mutex mu;
+            static void* per_dev[256] = {};
+            int dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 256) {
+                (void)hipGetLastError();
+                (void)hipFree(p);
+                delete c;
+                return (int)MPC3_E_HIP;
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            if (!per_dev[dev]) {
+                void* ptr = nullptr;
+                if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+                    (void)hipGetLastError();
+                    (void)hipFree(p);
+                    delete c;
+                    return (int)MPC3_E_HIP;
+                }
+                per_dev[dev] = ptr;
+            }
+            c->static_ws = per_dev[dev];
         }
         if (workspace_bytes) {
             c->scratch.alloc(workspace_bytes);
@@ -1088,69 +1221,28 @@ int mpc3_inner(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W, const 
     int g = guard(c);
     if (g) return g;
     if (!valid(X) || !valid(W) || !valid(Z)) return MPC3_E_ARG;
-    const int64_t M = X->rows, K = X->cols, N = W->cols;
-    if (W->rows != K || Z->rows != M || Z->cols != N) return MPC3_E_SHAPE;
-    if (pair && pair->n != M * N) return MPC3_E_SHAPE;
+    if (W->rows != X->cols || Z->rows != X->rows || Z->cols != W->cols) return MPC3_E_SHAPE;
+    if (pair && pair->n != X->rows * W->cols) return MPC3_E_SHAPE;
     return wrap(c, __func__, [&] {
-        const uint32_t op = c->op++;
-        const int64_t n = M * N;
-        hipStream_t s = c->stream;
         c->scratch.reset();
-        u64* G1 = c->scratch.words(n);
-        u64* C = c->scratch.words(3 * n);
-        launch_inner_pre(n, c->keys, op, pair ? pair->rx.m : nullptr, pair ? pair->rx.r1 : nullptr,
-                         pair ? pair->rx.r2 : nullptr, Z->r1, Z->r2, G1, s);
-        GemmArgs ga{};
-        ga.M = M; ga.N = N; ga.K = K; ga.batch = 1; ga.party = true; ga.accumulate = false;
-        const u64* Xp[3] = {X->m, X->r1, X->r2};
-        const u64* Wp[3] = {W->m, W->r1, W->r2};
-        for (int p = 0; p < 3; ++p) {
-            ga.A[p] = view(Xp[p], K, 1);
-            ga.B[p] = view(Wp[p], N, 1);
-            ga.C[p] = oview(C + p * n, N, 1);
-        }
-        const int keep_variant = c->variant;
-        if (c->variant == MPC3_VARIANT_AUTO) {
-            auto it = c->tuned.find(std::make_tuple(m_bucket(M), K, N));
-            c->variant = it == c->tuned.end() ? MPC3_VARIANT_LIMB_I8 : it->second;
-        }
-        struct VariantRestore {
-            mpc3_ctx* c;
-            int v;
-            ~VariantRestore() { c->variant = v; }
-        } vr{c, keep_variant};
-        if (K == 0) {
-            zero(c, C, (size_t)3 * n * 8);
-        } else if (c->prof) {
-            hipEvent_t e0, e1;
-            ck(hipEventCreate(&e0));
-            ck(hipEventCreate(&e1));
-            ck(hipEventRecord(e0, s));
-            run_gemm(c, ga);
-            ck(hipEventRecord(e1, s));
-            c->ev.push_back({e0, e1});
-            c->prof_macs += 5.0 * (double)M * (double)K * (double)N;
-        } else {
-            run_gemm(c, ga);
-        }
-        u64 *mg2 = nullptr, *mm1 = nullptr, *mm2 = nullptr;
-        if (c->keep_msgs) {
-            ensure_msgs(c, 0, n);
-            mg2 = c->msg[0][0]; mm1 = c->msg[0][1]; mm2 = c->msg[0][2];
-        }
-        launch_inner_post(n, C, C + n, C + 2 * n, Z->r1, Z->r2, G1, take(c, MPC3_SITE_INNER_GAMMA2, n),
-                          take(c, MPC3_SITE_INNER_M1, n), Z->m, mg2, mm1, mm2, s);
-        ck(hipGetLastError());
-        send(c, MPC3_PH_OFFLINE, 0, 2, 8 * n);
-        c->rounds[MPC3_PH_OFFLINE] += 1;
-        send(c, MPC3_PH_ONLINE, 1, 2, 8 * n);
-        send(c, MPC3_PH_ONLINE, 2, 1, 8 * n);
-        c->rounds[MPC3_PH_ONLINE] += 1;
-        Pending p{};
-        p.kind = MPC3_VERIFY_INNER;
-        p.X = *X; p.W = *W; p.Z = *Z;
-        p.op = op;
-        c->pending.push_back(p);
+        inner_body(c, X, W, pair, Z, scratch_alloc, &c->scratch, false);
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_inner_static(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W, const mpc3_trunc_pair_t* pair,
+                      mpc3_share_t* Z) {
+    int g = guard(c);
+    if (g) return g;
+    if (!valid(X) || !valid(W) || !valid(Z)) return MPC3_E_ARG;
+    if (W->rows != X->cols || Z->rows != X->rows || Z->cols != W->cols) return MPC3_E_SHAPE;
+    if (pair && pair->n != X->rows * W->cols) return MPC3_E_SHAPE;
+    if (c->keep_msgs) return MPC3_E_STATE;      // message copies would need device memory
+    if (static_ws_need(X->rows, X->cols, W->cols) > STATIC_WS_BYTES) return MPC3_E_LIMIT;
+    return wrap(c, __func__, [&] {
+        if (!c->static_ws) throw CodeError(MPC3_E_STATE);
+        StaticArena arena{(char*)c->static_ws, STATIC_WS_BYTES, 0};
+        inner_body(c, X, W, pair, Z, static_alloc, &arena, true);
         return (int)MPC3_OK;
     });
 }
@@ -1452,6 +1544,7 @@ const char* mpc3_strerror(int code) {
         case MPC3_E_UNVERIFIED: return "products await verification";
         case MPC3_E_HIP: return "HIP runtime error";
         case MPC3_E_STATE: return "invalid state";
+        case MPC3_E_LIMIT: return "operands exceed the static workspace of the allocation-free entry point";
         default: return "unknown";
     }
 }

@@ -39,6 +39,9 @@ struct GemmArgs {
     // used; read only by the limb kernel that takes converted B (B[0] must still be valid)
     const int8_t* btiles;
     int64_t btiles_nkb;
+    // the workspace takes digit tiles only: K is split only where the 32-bit digit sums
+    // require it, with atomic adds into the (zero-filled) output
+    bool no_part;
 };
 
 // Launch on `stream` with the chosen backend (0 = u64 VALU, 1 = int8 limbs on MFMA).
@@ -54,6 +57,9 @@ hipError_t split_reduce(const u64* part, int64_t M, int64_t N, int nprod, int sp
 // bytes at out, k-blocks per column tile = (K + 31) / 32.
 size_t limb_btiles_bytes(int64_t K, int64_t N);
 hipError_t limb_btiles(const View& B, int64_t K, int64_t N, int8_t* out, hipStream_t stream);
+
+// Fills n 32-bit words with 0 (a kernel, so that it can also be captured in a graph).
+hipError_t zero_words32(void* p, int64_t n, hipStream_t stream);
 
 // Bytes of partial sums one product may use before the split count is cut back.
 constexpr size_t PART_MAX = (size_t)1 << 30;

@@ -787,7 +787,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             splits = std::max<int64_t>(splits, std::min<int64_t>(want, maxseg * Kp / 64));
         }
         const size_t plane = (size_t)nprod * g.M * g.N * 8 * nbl;
-        const bool part_ok = g.ws_alloc != nullptr && plane * need <= PART_MAX;
+        const bool part_ok = g.ws_alloc != nullptr && !g.no_part && plane * need <= PART_MAX;
         if (part_ok) splits = std::min<int64_t>(splits, std::max<int64_t>(need, (int64_t)(PART_MAX / plane)));
         else splits = need;
         if (splits > 1 && !part_ok) {
@@ -799,7 +799,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             for (int p = 0; p < nprod; ++p) dense = dense && a.prod[p].C.s1 == 1 && a.prod[p].C.s0 == g.N;
             if (!g.accumulate && !dense) return gemm(g, 0, st);
             for (int p = 0; p < nprod && !g.accumulate; ++p) {
-                hipError_t e = hipMemsetAsync(a.prod[p].C.p, 0, (size_t)g.M * g.N * 8, st);
+                hipError_t e = zero_words32(a.prod[p].C.p, 2 * g.M * g.N, st);
                 if (e != hipSuccess) return e;
             }
             a.atomic = 1;

@@ -406,7 +406,7 @@ hipError_t gemm_u64(const GemmArgs& g, hipStream_t stream) {
     const int nprod = g.party || g.shared == 3 ? 3 : 1;
     const int64_t tiles = tm * tn * g.batch;
     int ksplit = 1;
-    const bool part_ok = g.ws_alloc != nullptr;
+    const bool part_ok = g.ws_alloc != nullptr && !g.no_part;
     if (g.K > BK && (part_ok || g.accumulate) && (g.accumulate || tiles < 256)) {
         const int64_t want = (1024 + tiles - 1) / tiles;          // aim for ~1k workgroups
         const int64_t maxs = (g.K + BK - 1) / BK;                  // at least one K step per split
@@ -436,6 +436,31 @@ hipError_t gemm_u64(const GemmArgs& g, hipStream_t stream) {
     return split_reduce(part, g.M, g.N, nprod, ksplit, g.batch, g.C, g.Dadd, g.accumulate, stream);
 }
 
+__global__ __launch_bounds__(256) void k_zero32(uint32_t* p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+__global__ __launch_bounds__(256) void k_zero128(uint4* p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+hipError_t zero_words32(void* p, int64_t n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    uint32_t* w = (uint32_t*)p;
+    // 32-bit words up to a 16-byte boundary, 16-byte stores for the body, 32-bit words for the tail
+    int64_t head = (int64_t)(((16 - ((uintptr_t)w & 15)) & 15) / 4);
+    if (head > n) head = n;
+    const int64_t body = (n - head) / 4, tail = n - head - 4 * body;
+    if (head) hipLaunchKernelGGL(k_zero32, dim3(1), dim3(256), 0, stream, w, head);
+    if (body) {
+        const int64_t blocks = std::min<int64_t>((body + 255) / 256, 16384);
+        hipLaunchKernelGGL(k_zero128, dim3((unsigned)blocks), dim3(256), 0, stream, (uint4*)(w + head), body);
+    }
+    if (tail) hipLaunchKernelGGL(k_zero32, dim3(1), dim3(256), 0, stream, w + head + 4 * body, tail);
+    return hipGetLastError();
+}
+
 hipError_t split_reduce(const u64* part, int64_t M, int64_t N, int nprod, int splits, int batch,
                         const OutView* C, const View& D, bool atomic, hipStream_t stream) {
     RedArgs r{};
@@ -456,7 +481,8 @@ hipError_t split_reduce(const u64* part, int64_t M, int64_t N, int nprod, int sp
 // reduction (which adds D, or adds into C with atomics when accumulating).
 static bool rows_fit(const GemmArgs& g) {
     const int na = std::max(1, g.shared);
-    if (g.party || g.M <= 0 || g.M * na > RD_M || g.N <= 0 || g.N > 64 || g.K <= 1024 || !g.ws_alloc) return false;
+    if (g.party || g.M <= 0 || g.M * na > RD_M || g.N <= 0 || g.N > 64 || g.K <= 1024 || !g.ws_alloc || g.no_part)
+        return false;
     for (int p = 1; p < na; ++p)
         if (g.A[p].s1 != g.A[0].s1) return false;
     return true;

@@ -13,7 +13,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpc3.so")
 
-OK, E_ARG, E_SHAPE, E_NOMEM, E_ABORTED, E_UNVERIFIED, E_HIP, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
+OK, E_ARG, E_SHAPE, E_NOMEM, E_ABORTED, E_UNVERIFIED, E_HIP, E_STATE, E_LIMIT = 0, -1, -2, -3, -4, -5, -6, -7, -8
 VARIANT_U64, VARIANT_LIMB_I8, VARIANT_AUTO = 0, 1, 2
 PH_OFFLINE, PH_ONLINE, PH_VERIFY_OFFLINE, PH_VERIFY_ONLINE = 0, 1, 2, 3
 VERIFY_INNER, VERIFY_TRUNC, VERIFY_MULT, VERIFY_ALL = 1, 2, 4, 7
@@ -56,6 +56,8 @@ SIGNATURES = {
     "mpc3_trunc_pair": (_I, [_P, _I64, _I, ctypes.POINTER(TruncPair)]),
     "mpc3_inner": (_I, [_P, ctypes.POINTER(Share), ctypes.POINTER(Share), ctypes.POINTER(TruncPair),
                         ctypes.POINTER(Share)]),
+    "mpc3_inner_static": (_I, [_P, ctypes.POINTER(Share), ctypes.POINTER(Share), ctypes.POINTER(TruncPair),
+                               ctypes.POINTER(Share)]),
     "mpc3_im2col": (_I, [_P, ctypes.POINTER(Share), _I, _I, _I, _I, _I, _I, _I, ctypes.POINTER(Share)]),
     "mpc3_sumpool2": (_I, [_P, ctypes.POINTER(Share), _I, _I, _I, _I, ctypes.POINTER(Share)]),
     "mpc3_mult": (_I, [_P, ctypes.POINTER(Share), ctypes.POINTER(Share), ctypes.POINTER(Share)]),
@@ -240,6 +242,17 @@ class Context:
         xs, ws, zs = X.c(), W.c(), Z.c()
         _ck(lib().mpc3_inner(self.h, ctypes.byref(xs), ctypes.byref(ws),
                              ctypes.byref(pair.s) if pair is not None else None, ctypes.byref(zs)), "mpc3_inner", self.h)
+        self._keep[VERIFY_INNER].append((X, W, Z))
+        return Z
+
+    def inner_static(self, X, W, pair=None, out=None):
+        """mpc3_inner_static: Pi_Inner with the library's fixed device workspace (no allocation
+        inside the call; Z must be given or is allocated here, before the call)."""
+        Z = out if out is not None else DShare.empty(X.rows, W.cols, self.device)
+        xs, ws, zs = X.c(), W.c(), Z.c()
+        _ck(lib().mpc3_inner_static(self.h, ctypes.byref(xs), ctypes.byref(ws),
+                                    ctypes.byref(pair.s) if pair is not None else None, ctypes.byref(zs)),
+            "mpc3_inner_static", self.h)
         self._keep[VERIFY_INNER].append((X, W, Z))
         return Z
 
