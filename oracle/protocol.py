@@ -34,6 +34,7 @@ import numpy as np
 
 from . import prg
 from .gr import GR
+from .nonlinear import NonlinearMixin
 from .ring import ash
 
 U64 = np.uint64
@@ -53,6 +54,7 @@ SITE_VER_DELTA_M1 = 8
 SITE_REC_R1 = 9
 
 DEFAULT_CHUNK = 1 << 19     # truncations per Pi_BIVerify instance of the truncation gates
+DEFAULT_CHUNK_ROWS = 1 << 14  # edaBit inner products (64-element gates) per Pi_BIVerify instance
 
 
 class Aborted(Exception):
@@ -102,8 +104,8 @@ def _wt(v):
     return U64(v & MASK64)
 
 
-class Ctx:
-    def __init__(self, master_seed, d=64, frac_bits=13, chunk=DEFAULT_CHUNK):
+class Ctx(NonlinearMixin):
+    def __init__(self, master_seed, d=64, frac_bits=13, chunk=DEFAULT_CHUNK, chunk_rows=DEFAULT_CHUNK_ROWS):
         self.seeds = prg.pair_seeds(master_seed)
         if d < 2:
             raise ValueError("the verification needs d >= 2 (three interpolation nodes)")
@@ -115,6 +117,7 @@ class Ctx:
         self.inv_xxm1 = self.gr.inv(self.gr.mul(X, self.gr.sub(X, self.gr.const(1))))
         self.frac_bits = frac_bits
         self.chunk = chunk
+        self.chunk_rows = chunk_rows
         self.op = 0
         self.comm = [[[0] * 3 for _ in range(3)] for _ in range(4)]
         self.rounds = [0, 0, 0, 0]
@@ -239,8 +242,9 @@ class Ctx:
         self.pending.append(("inner", X, W, Z))
         return Z
 
-    def mult(self, a, b):
-        """Pi_Mult on equal-shaped arrays of shares (elementwise)."""
+    def mult(self, a, b, phase_on=ONLINE):
+        """Pi_Mult on equal-shaped arrays of shares (elementwise).  phase_on: the counter
+        phase of the P1 <-> P2 exchange (OFFLINE for input-independent preprocessing)."""
         self.check()
         op = self.next_op()
         n = a.m.size
@@ -254,9 +258,9 @@ class Ctx:
         self.rounds[OFFLINE] += 1
         m1 = neg(a.m * b.r1) - b.m * a.r1 + g1                      # P1
         m2 = a.m * b.m - a.m * b.r2 - b.m * a.r2 + g2               # P2
-        self.send(ONLINE, 1, 2, 8 * n)
-        self.send(ONLINE, 2, 1, 8 * n)
-        self.rounds[ONLINE] += 1
+        self.send(phase_on, 1, 2, 8 * n)
+        self.send(phase_on, 2, 1, 8 * n)
+        self.rounds[phase_on] += 1
         c = Share(m1 + m2, rz1, rz2)
         self.msgs["mult"] = {"gamma2": g2, "m1": m1, "m2": m2}
         self.pending.append(("mult", a, b, c))
@@ -558,13 +562,15 @@ class Ctx:
         z = Share(*[gr.scale(v.reshape(-1), pw).sum(axis=0, dtype=U64) for v in c.comps()])
         return x, y, z
 
-    KIND = {"inner": 1, "trunc": 2, "mult": 4}
+    KIND = {"inner": 1, "trunc": 2, "mult": 4, "rows": 8, "and": 8}
 
-    def verify(self, R=-1, literal=False, kinds=7):
-        """Post-processing: one Pi_BIVerify for all pending Pi_Inner products (first), the
-        truncation gates in chunks, one Pi_MultVerify per Pi_Mult call; abort unless every
-        Delta is 0.  `kinds` selects which pending products are verified now (1 inner,
-        2 trunc, 4 mult)."""
+    def verify(self, R=-1, literal=False, kinds=15):
+        """Post-processing: one Pi_BIVerify for all pending Pi_Inner products (first), then
+        in call order the truncation gates in chunks, one Pi_MultVerify per Pi_Mult call,
+        the edaBit inner products in chunks, and one Pi_MultVerify over GF(2^d) per layer
+        call's Boolean triples; abort unless every Delta is 0.  `kinds` selects which
+        pending products are verified now (1 inner, 2 trunc, 4 mult, 8 the non-linear
+        layers' edaBit inner products and Boolean triples)."""
         self.check()
         op = self.next_op()
         ok = True
@@ -596,6 +602,22 @@ class Ctx:
                     ok &= self.fold_and_check(x, y, z, op, s, R, log)
                     self.vlog.append(log)
                     s += 1
+            elif item[0] == "rows":
+                _, xs, ys, zs = item
+                for lo in range(0, xs.m.shape[0], self.chunk_rows):
+                    hi = min(xs.m.shape[0], lo + self.chunk_rows)
+                    log = {"kind": "rows", "s": s, "lo": lo, "hi": hi}
+                    r = self.challenge(op, s, log)
+                    x, y, z = self.instance_rows(xs, ys, zs, lo, hi, r)
+                    log["z"] = z
+                    ok &= self.fold_and_check(x, y, z, op, s, R, log)
+                    self.vlog.append(log)
+                    s += 1
+            elif item[0] == "and":
+                log = {"kind": "and", "s": s}
+                ok &= self.verify_and_item(item[1], op, s, R, log)
+                self.vlog.append(log)
+                s += 1
             else:
                 _, a, b, c = item
                 log = {"kind": "mult", "s": s}
