@@ -125,20 +125,17 @@ def envelope(ctx, reps=5):
             "limb_int8_tops": ops / (ms_limb * 1e-3) / 1e12, "limb_int8_frac": ops / (ms_limb * 1e-3) / 1e12 / INT8_PEAK_TOPS}
 
 
-def cpu_baseline(args, shapes):
-    """The oracle on a row sample of every layer of the step: share, truncation pair,
-    Pi_Inner and truncation per layer, then one batched verification of the sampled
-    products (no truncation gates), as in the timed GPU step."""
+def _oracle_rows(job):
+    """One worker of the CPU baseline: the oracle on `rows_of(M)` rows of every layer."""
     from oracle.protocol import Ctx
     from oracle.ring import encode
 
-    frac = args.cpu_sample
+    shapes, frac, part, parts = job
     o = Ctx(workloads.master_seed(4))
-    g = workloads.rng(9)
+    g = workloads.rng(9 + part)
     ops = 0.0
-    t0 = time.perf_counter()
     for M, K, N in shapes:
-        rows = max(1, M // frac)
+        rows = max(1, M // frac // parts)
         X = o.share(encode(g.random((rows, K)), 13))
         W = o.share(encode(g.standard_normal((K, N)) * 0.05, 13))
         pair = o.trunc_pair(rows * N, 13)
@@ -146,10 +143,224 @@ def cpu_baseline(args, shapes):
         ops += 2.0 * rows * K * N
     if not o.verify(kinds=1):
         raise SystemExit("oracle verification failed in an honest run")
+    return ops
+
+
+def cpu_baseline(args, shapes):
+    """The oracle on a row sample of every layer of the step: share, truncation pair,
+    Pi_Inner and truncation per layer, then one batched verification of the sampled
+    products (no truncation gates), as in the timed GPU step.  Once on one core (1/frac of
+    the rows) and once on `cores` worker processes, each taking 1/cores of a 4x larger
+    sample (its own context and verification: the same work split by row blocks)."""
+    import multiprocessing
+
+    frac = args.cpu_sample
+    t0 = time.perf_counter()
+    ops1 = _oracle_rows((shapes, frac, 0, 1))
+    dt1 = time.perf_counter() - t0
+    cores = args.cpu_cores
+    out = {"value": ops1 / dt1 / 1e9, "unit": "GOPS", "cores": 1, "kind": "oracle",
+           "sample": f"1/{frac} of the rows of every layer product (same K, N): share, truncation pair, "
+                     f"Pi_Inner, truncation per layer, one batched verification; {dt1:.1f} s on one core"}
+    if cores > 1:
+        frac_m = max(1, frac // 4)
+        t0 = time.perf_counter()
+        with multiprocessing.get_context("fork").Pool(cores) as pool:
+            opsm = sum(pool.map(_oracle_rows, [(shapes, frac_m, i, cores) for i in range(cores)]))
+        dtm = time.perf_counter() - t0
+        out["multi_core"] = {"value": opsm / dtm / 1e9, "unit": "GOPS", "cores": cores,
+                             "sample": f"1/{frac_m} of the rows in {cores} row blocks, one process each; "
+                                       f"{dtm:.1f} s wall"}
+    return out
+
+
+def comparisons(name, batch):
+    """Comparisons (ReLU evaluations) of one batch: every output of every layer but the last,
+    and for each 2x2 max pool of N outputs 2 N / 4 + N / 4 more."""
+    from paper_2411_09287_amd import network
+    plan = network.plan(name)
+    n = 0
+    for i, d in enumerate(plan):
+        M, K, N = workloads.layer_gemm_shape(d["layer"], batch)
+        if i + 1 < len(plan):
+            n += M * N
+            if d["pool_after"]:
+                n += M * N // 4 * 3
+    return n
+
+
+def _oracle_network(job):
+    """The oracle through network.Network's call sequence with ReLU and max pooling on
+    `batch` images, every product verified; returns the images done."""
+    from oracle.layers import im2col_share
+    from oracle.protocol import Share, Ctx
+    from oracle.ring import encode
+    from paper_2411_09287_amd import network
+
+    name, batch, seed = job
+    o = Ctx(workloads.master_seed(2))
+    plan = network.plan(name)
+    weights = []
+    for d, w in zip(plan, network.float_weights(name, nonlinear=True)):
+        if d.get("kpad", w.shape[0]) > w.shape[0]:
+            w = np.concatenate([w, np.zeros((d["kpad"] - w.shape[0], w.shape[1]))])
+        weights.append(o.share(encode(w, 13)))
+    x = workloads.rng(seed).random((batch,) + tuple(workloads.MODELS[name]["input"]))
+    h = o.share(encode(x, 13).reshape(batch, -1))
+    for i, (d, W) in enumerate(zip(plan, weights)):
+        layer = d["layer"]
+        if layer[0] == "conv":
+            _, kh, kw, cin, cout, pad, (hh, ww) = layer[:7]
+            X = im2col_share(h.map(lambda a: a.reshape(batch, hh, ww, cin)), kh, kw, pad, workloads.conv_stride(layer))
+            extra = d["kpad"] - X.m.shape[1]
+            if extra:
+                X = X.map(lambda a: np.concatenate([a, np.zeros((a.shape[0], extra), dtype=np.uint64)], axis=1))
+        else:
+            X = h.map(lambda a: a.reshape(batch, -1))
+        pair = o.trunc_pair(X.m.shape[0] * W.m.shape[1], 13)
+        Y = o.trunc(pair, o.inner(X, W, pair))
+        if i + 1 < len(plan):
+            Y = o.relu(Y)
+        if d["pool_after"]:
+            oh, ow = d["out_hw"]
+            Y = o.maxpool2(Y.map(lambda a: a.reshape(batch, -1)), batch, oh, ow, layer[4])
+        h = Share(*[a.reshape(batch, -1) for a in Y.comps()])
+    if not o.verify():
+        raise SystemExit("oracle verification failed in an honest run")
+    o.reconstruct(h)
+    return batch
+
+
+def cpu_baseline_nonlinear(args, comparisons_per_image):
+    """The oracle's secure inference with ReLU and max pooling, every product verified, on
+    one core, in images/s: the whole network on one image for the MLP; for the larger
+    networks (one image takes the oracle hours) the ReLU of 64 values with its verification
+    (the comparisons dominate the oracle's time), scaled by the comparisons of one image."""
+    from oracle.protocol import Ctx
+    from oracle.ring import encode
+
+    t0 = time.perf_counter()
+    if args.workload == "mlp":
+        n = _oracle_network((args.workload, 1, 3))
+        dt = time.perf_counter() - t0
+        return {"value": n / dt, "unit": "inferences/s", "cores": 1, "kind": "oracle",
+                "sample": f"one image of the mlp network with ReLU, every product verified; {dt:.1f} s on one core"}
+    o = Ctx(workloads.master_seed(2))
+    o.relu(o.share(encode(workloads.rng(3).standard_normal(64), 13)))
+    if not o.verify():
+        raise SystemExit("oracle verification failed in an honest run")
     dt = time.perf_counter() - t0
-    return {"value": ops / dt / 1e9, "unit": "GOPS", "cores": 1, "kind": "oracle",
-            "sample": f"1/{frac} of the rows of every layer product (same K, N): share, truncation pair, "
-                      f"Pi_Inner, truncation per layer, one batched verification; {dt:.1f} s on one core"}
+    return {"value": 64.0 / dt / comparisons_per_image, "unit": "inferences/s", "cores": 1, "kind": "oracle",
+            "sample": f"ReLU of 64 values with every product verified, {dt:.1f} s on one core, scaled to the "
+                      f"{comparisons_per_image} comparisons of one image (linear layers not counted)"}
+
+
+def run_nonlinear(args, cpu):
+    """Secure inference with ReLU and max pooling: one step evaluates a batch and verifies
+    every product it made (the layer products, the truncation gates, the Pi_Mult triples
+    and the Boolean triples of the non-linear layers), then opens the logits."""
+    import torch
+    from paper_2411_09287_amd import mpc3, network
+
+    torch.cuda.set_device(0)
+    name = args.workload
+    batch = workloads.MODELS[name]["batch"]
+    variant = {"limb": mpc3.VARIANT_LIMB_I8, "u64": mpc3.VARIANT_U64, "auto": mpc3.VARIANT_LIMB_I8}[args.variant]
+    ctx = mpc3.Context(workloads.master_seed(2))
+    ctx.set_variant(variant)
+    net = network.Network(ctx, name, nonlinear=True)
+    x = torch.from_numpy(workloads.rng(2).random((batch,) + tuple(workloads.MODELS[name]["input"]))).cuda()
+    phases = {}
+
+    def step():
+        out = net.forward(x)
+        ok = True
+        for label, kind in (("inner", mpc3.VERIFY_INNER), ("mult", mpc3.VERIFY_MULT),
+                            ("nonlinear", mpc3.VERIFY_NONLINEAR), ("trunc", mpc3.VERIFY_TRUNC)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ok = ctx.verify(-1, kind) and ok
+            phases.setdefault(label, []).append(time.perf_counter() - t0)
+        ctx.reconstruct(out)
+        return ok
+
+    for i in range(args.warmup):
+        if not step():
+            raise SystemExit("verification failed in an honest run")
+        log(f"[bench] warmup {i + 1}/{args.warmup}")
+    phases.clear()
+    times = []
+    c0 = ctx.comm_stats()
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if not step():
+            raise SystemExit("verification failed in an honest run")
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log(f"[bench] step {i + 1}/{args.steps} {times[-1] * 1e3:.1f} ms")
+    cb, cr = ctx.comm_stats()
+    t = float(np.median(times))
+    nrelu = comparisons(name, batch)
+    return {"metric": "verified secure inferences/s", "value": batch / t, "unit": "inferences/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": {"u64": "u64"}.get(args.variant, "int8-limb"),
+            "data": "synthetic",
+            "config": {"workload": f"{name} with ReLU and 2x2 max pooling, batch {batch}",
+                       "comparisons_per_batch": nrelu,
+                       "verify_ms": {k: float(np.median(v)) * 1e3 for k, v in phases.items()},
+                       "comm_bytes_per_batch": int((np.asarray(cb, dtype=np.int64) - np.asarray(c0[0], dtype=np.int64)).sum()) // max(args.steps, 1),
+                       "comm_rounds_per_batch": [(a - b) // max(args.steps, 1) for a, b in zip(cr, c0[1])]},
+            "roofline": None, "cpu_baseline": cpu}
+
+
+def run_depth(args):
+    """Multiplication circuits of depth 32 and 128 (Sec. 5.1, Fig. "dep"): a batch of
+    `width` values multiplied layer by layer, x_(k+1) = Pi_Mult(x_k, y_k), then one
+    verification of every layer's triples (R chosen by the cost model on the MAN setting).
+    Reports the GPU time of the evaluation and of the verification, the counted
+    communication and rounds, and the modelled MAN time of the whole run."""
+    import torch
+    from paper_2411_09287_amd import mpc3, netmodel
+
+    torch.cuda.set_device(0)
+    width = args.depth_width
+    g = workloads.rng(7)
+    out = {}
+    for depth in (32, 128):
+        ctx = mpc3.Context(workloads.master_seed(7))
+        ctx.set_variant(mpc3.VARIANT_LIMB_I8)
+        rtt, bw = netmodel.NETWORKS["MAN"]
+        ctx.set_network(rtt * 1e3, bw / 1e6, 0.1)
+        x0 = g.integers(0, 1 << 64, (width, 1), dtype=np.uint64, endpoint=False)
+        ys = [g.integers(0, 1 << 64, (width, 1), dtype=np.uint64, endpoint=False) for _ in range(depth)]
+        X = ctx.share(mpc3.to_words(x0))
+        Ys = [ctx.share(mpc3.to_words(y)) for y in ys]
+        torch.cuda.synchronize()
+        c0 = ctx.comm_stats()
+        t0 = time.perf_counter()
+        for k in range(depth):
+            X = ctx.mult(X, Ys[k])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ok = ctx.verify(mpc3.R_NETWORK, mpc3.VERIFY_MULT)
+        t2 = time.perf_counter()
+        if not ok:
+            raise SystemExit("verification failed in an honest run")
+        cb, cr = netmodel.diff(ctx.comm_stats(), c0)
+        got = mpc3.from_words(ctx.reconstruct(X)).reshape(-1)
+        want = x0.reshape(-1).copy()
+        for y in ys:
+            want = want * y.reshape(-1)
+        if not np.array_equal(got, want):
+            raise SystemExit("opened product differs from the plaintext product")
+        phases = (netmodel.OFFLINE, netmodel.ONLINE, netmodel.VERIFY_OFFLINE, netmodel.VERIFY_ONLINE)
+        man = netmodel.seconds(cb, cr, phases, "MAN")
+        out[f"depth_{depth}"] = {"eval_gpu_ms": (t1 - t0) * 1e3, "verify_gpu_ms": (t2 - t1) * 1e3,
+                                 "comm_bytes": int(np.asarray(cb).sum()), "rounds": cr,
+                                 "man_model_s": man, "mults_per_s_gpu": width * depth / (t2 - t0)}
+        log(f"[depth] {depth}: {json.dumps(out[f'depth_{depth}'])}")
+    return out
 
 
 def run_mix(args):
@@ -243,11 +454,16 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--variant", choices=["u64", "limb", "auto"], default="limb")
-    ap.add_argument("--workload", default="vgg", choices=["vgg", "lenet", "mlp", "mix", "rtrade"])
+    ap.add_argument("--workload", default="vgg", choices=["vgg", "lenet", "mlp", "matmul", "snn", "lenet5", "vgg16",
+                                                          "depth", "mix", "rtrade"])
     ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--depth-width", type=int, default=1 << 16, help="values per layer of the depth workload")
     ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-cores", type=int, default=8, help="worker processes of the multi-core CPU baseline")
+    ap.add_argument("--nonlinear", action="store_true",
+                    help="networks with ReLU and max pooling (edaBits); the step verifies every product")
     ap.add_argument("--no-envelope", action="store_true")
     ap.add_argument("--hbm-copy", type=float, default=0.0, help="only time a device copy of this many GiB")
     ap.add_argument("--envelope-only", action="store_true", help="only time the envelope product")
@@ -276,6 +492,18 @@ def main():
         print(json.dumps(line))
         return
 
+    if args.workload == "depth":
+        res = run_depth(args)
+        d = res["depth_128"]
+        line = {"metric": "verified secure multiplications/s (depth-128 circuit, GPU time)",
+                "value": d["mults_per_s_gpu"], "unit": "mults/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+                "ms_per_step": d["eval_gpu_ms"] + d["verify_gpu_ms"], "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "int8-limb", "data": "synthetic",
+                "config": {"workload": f"multiplication circuits of depth 32 and 128, width {args.depth_width}",
+                           **res}}
+        print(json.dumps(line))
+        return
+
     if args.workload == "mix":
         reqs, res = run_mix(args)
         main_res = res["limb_packed"]
@@ -288,6 +516,13 @@ def main():
         print(json.dumps(line))
         return
 
+    # the CPU baseline runs first, before this process initialises the GPU (its worker
+    # processes are forked)
+    if args.nonlinear:
+        cpu = None if args.no_cpu else cpu_baseline_nonlinear(args, comparisons(args.workload, 1))
+        print(json.dumps(run_nonlinear(args, cpu)))
+        return
+    cpu = None if args.no_cpu else cpu_baseline(args, workloads.model_shapes(args.workload))
     r = run_gpu(args)
     t = float(np.median(r["times"]))
     vt = float(np.median(r["vtimes"]))
@@ -306,7 +541,6 @@ def main():
     roof["kernel"] = "Pi_Inner three-party product (one call: B-digit conversion + product), all layers"
     roof["avg_launch_ms"] = avg_launch_ms
     roof["launches"] = r["launches"]
-    cpu = None if args.no_cpu else cpu_baseline(args, r["shapes"])
     line = {
         "metric": "verified Z_2^64 secure-matmul GOPS",
         "value": r["ops"] / t / 1e9, "unit": "GOPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -76,8 +76,11 @@ enum { MPC3_VARIANT_U64 = 0, MPC3_VARIANT_LIMB_I8 = 1, MPC3_VARIANT_AUTO = 2 };
 /* Phases of the communication counters. */
 enum { MPC3_PH_OFFLINE = 0, MPC3_PH_ONLINE = 1, MPC3_PH_VERIFY_OFFLINE = 2, MPC3_PH_VERIFY_ONLINE = 3 };
 
-/* Kinds of pending products, for mpc3_verify's selection mask. */
-enum { MPC3_VERIFY_INNER = 1, MPC3_VERIFY_TRUNC = 2, MPC3_VERIFY_MULT = 4, MPC3_VERIFY_ALL = 7 };
+/* Kinds of pending products, for mpc3_verify's selection mask.  NONLINEAR: the edaBit
+ * inner products and the Boolean triples of mpc3_edabits / mpc3_relu / mpc3_maxpool2 (their
+ * Pi_Mult triples over Z_{2^64} are of kind MULT). */
+enum { MPC3_VERIFY_INNER = 1, MPC3_VERIFY_TRUNC = 2, MPC3_VERIFY_MULT = 4, MPC3_VERIFY_NONLINEAR = 8,
+       MPC3_VERIFY_ALL = 15 };
 
 /* Message sites for mpc3_inject (an additive error on one word of one message). */
 enum {
@@ -89,7 +92,9 @@ enum {
     MPC3_SITE_VER_H0_M1 = 6,     /* P1 -> P2 [m]_1 of h(0) in Pi_Reduce; index = inst<<16 | round<<8 | coeff */
     MPC3_SITE_VER_H2_GAMMA2 = 7, /* P0 -> P2 [Gamma]_2 of h(x) in Pi_Reduce; same index layout */
     MPC3_SITE_VER_DELTA_M1 = 8,  /* P1 -> P2 [m]_1 of Delta in Pi_InnerVerify; index = inst<<16 | coeff */
-    MPC3_SITE_REC_R1 = 9         /* P0 -> P2 [r]_1 in Pi_Rec of mpc3_reconstruct; index = element */
+    MPC3_SITE_REC_R1 = 9,        /* P0 -> P2 [r]_1 in Pi_Rec of mpc3_reconstruct; index = element */
+    MPC3_SITE_AND_GAMMA2 = 10,   /* P0 -> P2 [Gamma]_2 of a Boolean Pi_Mult; index = word, e XORed */
+    MPC3_SITE_EDA_W_M1 = 11      /* P1 -> P2 [m]_1 of an edaBit inner product; index = edaBit */
 };
 
 /* Messages of the most recent Pi_Inner / Pi_Mult, for mpc3_message. */
@@ -135,6 +140,27 @@ int mpc3_autotune(mpc3_ctx* ctx, int64_t M, int64_t K, int64_t N, int reps, int*
  * 524288 = 2^19; a chunk of T truncations holds about 20 KiB x T of workspace while
  * verified).  MPC3_E_ARG outside 1 .. 2^19. */
 int mpc3_set_chunk(mpc3_ctx* ctx, int64_t truncations_per_instance);
+
+/* Instance sizes of the other verifications: Pi_Mult triples per Pi_MultVerify instance
+ * (default 2^20, at most 2^24; about 3.5 KiB of workspace per triple while verified) and
+ * edaBit inner products per Pi_BIVerify instance (default 2^14, at most 2^18; about
+ * 200 KiB each).  0 keeps a value.  MPC3_E_ARG outside the ranges. */
+int mpc3_set_verify_chunks(mpc3_ctx* ctx, int64_t mult_triples, int64_t edabit_rows);
+
+/* R argument of mpc3_verify: per instance, the number of Pi_Reduce rounds of least
+ * modelled time on the network set by mpc3_set_network. */
+enum { MPC3_R_NETWORK = -2 };
+
+/* Network cost model for the choice of R (Sec. 5.1, the trade-off of R between the
+ * rounds of more reductions and the size of the final check, on the LAN / MAN / WAN
+ * settings of the experiments).  An instance of n pairs (ring elements of w bytes: 512
+ * in GR(2^64, 64), 8 in GF(2^64)) with R reductions and n_R = n / 2^R final pairs
+ * sends w (2R + n_R + 1) bytes P0 -> P2 offline and has 2R + 4 online rounds whose
+ * busiest link carries w (2R + n_R + 1) + 32 (R + 2) bytes (the counters of
+ * mpc3_comm_stats); each phase costs rounds x rtt plus bytes over the bandwidth, plus
+ * gpu_round_ms of GPU latency per reduction round.  mpc3_verify(R = MPC3_R_NETWORK)
+ * takes the R in 0 .. ceil(log2 n) of least total (MPC3_E_STATE before this call). */
+int mpc3_set_network(mpc3_ctx* ctx, double rtt_ms, double mbit_per_s, double gpu_round_ms);
 
 /* Keep the messages of each Pi_Inner / Pi_Mult for mpc3_message (default off). */
 int mpc3_keep_messages(mpc3_ctx* ctx, int on);
@@ -194,6 +220,12 @@ int mpc3_inner_static(mpc3_ctx* ctx, const mpc3_share_t* X, const mpc3_share_t* 
 int mpc3_im2col(mpc3_ctx* ctx, const mpc3_share_t* x, int B, int H, int W, int C, int KH, int KW,
                 int pad, mpc3_share_t* cols);
 
+/* The same lowering with stride s: output (oh, ow) reads input (s oh + kh - pad,
+ * s ow + kw - pad); OH = (H + 2 pad - KH) / s + 1 (the S-NN layer of Sec. 5.2 has
+ * stride 2). */
+int mpc3_im2col_strided(mpc3_ctx* ctx, const mpc3_share_t* x, int B, int H, int W, int C, int KH, int KW,
+                        int pad, int stride, mpc3_share_t* cols);
+
 /* 2x2 sum pooling (stride 2) of an NHWC shared tensor x (B*H*W*C words per plane)
  * into out (B*(H/2)*(W/2)*C): each plane is summed alone, a local linear map
  * (Preliminaries, linear homomorphism of <.>-shares).  H and W must be even. */
@@ -202,20 +234,53 @@ int mpc3_sumpool2(mpc3_ctx* ctx, const mpc3_share_t* x, int B, int H, int W, int
 /* Pi_Mult elementwise on rows*cols values (Fig. "The Multiplication Protocol"). */
 int mpc3_mult(mpc3_ctx* ctx, const mpc3_share_t* a, const mpc3_share_t* b, mpc3_share_t* c);
 
+/* --- Non-linear layers (Sec. 4.3 "Secure Non-linear Function Evaluation") ---------
+ * Boolean shares <v>^1 = (m, [r]_1, [r]_2) with m = v XOR r1 XOR r2 are bit-sliced: one
+ * uint64 word per plane, for a 64-bit value its bit i in bit i.  The Boolean products
+ * (Pi_Mult with AND and XOR) are verified by Pi_MultVerify over GF(2^64) = GR(2, 64)
+ * (kind MPC3_VERIFY_NONLINEAR), the products over Z_{2^64} by Pi_MultVerify as for
+ * mpc3_mult.  Intermediate buffers are the context's and are freed once verified. */
+
+/* n edaBits (Fig. "The maliciously edaBits generation"): arith (n words per plane) receives
+ * <r>^l and bits (n words per plane) <r[0..63]>^1 of the same random r.  The bit products
+ * are one Pi_Mult of 64 n elements; the second multiplication is one 64-element inner
+ * product per edaBit: r = sum_i 2^i (m_i + r'_i) - sum_i 2^(i+1) m_i r'_i.  The paper's
+ * arithmetic bit shares (0, b, 0) and (0, 0, b) are taken as (0, -b, 0) and (0, 0, -b)
+ * so that they open to +b under m = v + r. */
+int mpc3_edabits(mpc3_ctx* ctx, int64_t n, mpc3_share_t* arith, mpc3_share_t* bits);
+
+/* n daBits: a random bit s per word in both sharings (arith <s>^l, bits <s>^1 in bit 0),
+ * from two Pi_Mult rounds: r' = b_1 XOR b_2, s = m XOR r'. */
+int mpc3_dabits(mpc3_ctx* ctx, int64_t n, mpc3_share_t* arith, mpc3_share_t* bits);
+
+/* ReLU of every value of x (rows*cols words per plane) into out: x * (1 - msb(x)).  Per
+ * value one edaBit and one daBit; Delta = x - r is opened (Pi_Rec), the carry into bit 63
+ * of Delta + r comes from a parallel-prefix adder (six Boolean Pi_Mult rounds on whole
+ * words); e = (1 - msb) XOR s is opened and <1 - msb>^l = e + (1 - 2e) <s>^l (B2A) is
+ * multiplied with x by Pi_Mult.  x and out must stay alive until verified. */
+int mpc3_relu(mpc3_ctx* ctx, const mpc3_share_t* x, mpc3_share_t* out);
+
+/* 2x2 max pooling (stride 2) of an NHWC tensor x (B*H*W*C words per plane, H and W even)
+ * into out (B*(H/2)*(W/2)*C): max(p, q) = q + ReLU(p - q) over the two pairs of a window,
+ * then over the two results.  x and out must stay alive until verified. */
+int mpc3_maxpool2(mpc3_ctx* ctx, const mpc3_share_t* x, int B, int H, int W, int C, mpc3_share_t* out);
+
 /* Online Pi_Trunc: out.m = ash(Z.m, t); the output mask is the pair's r_z.
  * No communication (Sec. 4.2). */
 int mpc3_trunc(mpc3_ctx* ctx, const mpc3_trunc_pair_t* p, const mpc3_share_t* Z, mpc3_share_t* out);
 
 /* Post-processing verification (Sec. 3) of the pending products selected by kinds
- * (MPC3_VERIFY_* mask).  Instance 0 is one Pi_BIVerify^R over every pending Pi_Inner
+ * (MPC3_VERIFY_* mask).  The non-linear layers' edaBit inner products run as
+ * Pi_BIVerify instances of 64-element gates (16384 per instance), their Boolean
+ * triples as one Pi_MultVerify over GF(2^64) per layer call.  Instance 0 is one Pi_BIVerify^R over every pending Pi_Inner
  * product together: the batch verification gives gate (m, n) of product l, in call
  * order, the index i = o_l + M_l n + m (o_l = the number of gates of the products
  * before it) and the weight r^i on its x side.  Because r^i = r^(o_l) r^m (r^(M_l))^n
  * factorises, each product's M_l N_l K_l consolidated pairs compress exactly into K_l
  * pairs (x_k = r^(o_l) sum_m r^m X[m,k], y_k = sum_n r^(M_l n) W[k,n]) with an
  * unchanged claimed z.  Then one instance per chunk of truncation gates, and one
- * Pi_MultVerify^R per Pi_Mult call.  R < 0 picks max(0, ceil(log2 n) - 3) for an
- * instance of n pairs.  *ok = 1 iff every Delta is 0; otherwise *ok = 0 and the
+ * Pi_MultVerify^R per chunk of each Pi_Mult call's triples.  R = -1 picks max(0, ceil(log2 n) - 3) for an
+ * instance of n pairs, MPC3_R_NETWORK the least modelled time (mpc3_set_network).  *ok = 1 iff every Delta is 0; otherwise *ok = 0 and the
  * context is aborted.  Synchronises. */
 int mpc3_verify(mpc3_ctx* ctx, int R, int kinds, int* ok);
 

@@ -55,6 +55,7 @@ SITE_REC_R1 = 9
 
 DEFAULT_CHUNK = 1 << 19     # truncations per Pi_BIVerify instance of the truncation gates
 DEFAULT_CHUNK_ROWS = 1 << 14  # edaBit inner products (64-element gates) per Pi_BIVerify instance
+DEFAULT_CHUNK_MULT = 1 << 20  # Pi_Mult triples per Pi_MultVerify instance
 
 
 class Aborted(Exception):
@@ -105,7 +106,8 @@ def _wt(v):
 
 
 class Ctx(NonlinearMixin):
-    def __init__(self, master_seed, d=64, frac_bits=13, chunk=DEFAULT_CHUNK, chunk_rows=DEFAULT_CHUNK_ROWS):
+    def __init__(self, master_seed, d=64, frac_bits=13, chunk=DEFAULT_CHUNK, chunk_rows=DEFAULT_CHUNK_ROWS,
+                 chunk_mult=DEFAULT_CHUNK_MULT):
         self.seeds = prg.pair_seeds(master_seed)
         if d < 2:
             raise ValueError("the verification needs d >= 2 (three interpolation nodes)")
@@ -118,6 +120,7 @@ class Ctx(NonlinearMixin):
         self.frac_bits = frac_bits
         self.chunk = chunk
         self.chunk_rows = chunk_rows
+        self.chunk_mult = chunk_mult
         self.op = 0
         self.comm = [[[0] * 3 for _ in range(3)] for _ in range(4)]
         self.rounds = [0, 0, 0, 0]
@@ -552,14 +555,14 @@ class Ctx(NonlinearMixin):
             zs.append(ze)
         return Share(*xs), Share(*ys), Share(*zs)
 
-    def instance_mult(self, a, b, c, r):
-        """Pi_Tran (Fig. "Compression of Multiplication Triples")."""
+    def instance_mult(self, a, b, c, r, lo=0, hi=None):
+        """Pi_Tran (Fig. "Compression of Multiplication Triples") of triples [lo, hi)."""
         gr = self.gr
-        n = a.m.size
-        pw = gr.powers(r, n)
-        x = Share(*[gr.scale(v.reshape(-1), pw) for v in a.comps()])
-        y = Share(*[gr.const(v.reshape(-1)) for v in b.comps()])
-        z = Share(*[gr.scale(v.reshape(-1), pw).sum(axis=0, dtype=U64) for v in c.comps()])
+        hi = a.m.size if hi is None else hi
+        pw = gr.powers(r, hi - lo)
+        x = Share(*[gr.scale(v.reshape(-1)[lo:hi], pw) for v in a.comps()])
+        y = Share(*[gr.const(v.reshape(-1)[lo:hi]) for v in b.comps()])
+        z = Share(*[gr.scale(v.reshape(-1)[lo:hi], pw).sum(axis=0, dtype=U64) for v in c.comps()])
         return x, y, z
 
     KIND = {"inner": 1, "trunc": 2, "mult": 4, "rows": 8, "and": 8}
@@ -567,7 +570,7 @@ class Ctx(NonlinearMixin):
     def verify(self, R=-1, literal=False, kinds=15):
         """Post-processing: one Pi_BIVerify for all pending Pi_Inner products (first), then
         in call order the truncation gates in chunks, one Pi_MultVerify per Pi_Mult call,
-        the edaBit inner products in chunks, and one Pi_MultVerify over GF(2^d) per layer
+        (in chunks of triples), the edaBit inner products in chunks, and one Pi_MultVerify over GF(2^d) per layer
         call's Boolean triples; abort unless every Delta is 0.  `kinds` selects which
         pending products are verified now (1 inner, 2 trunc, 4 mult, 8 the non-linear
         layers' edaBit inner products and Boolean triples)."""
@@ -620,13 +623,16 @@ class Ctx(NonlinearMixin):
                 s += 1
             else:
                 _, a, b, c = item
-                log = {"kind": "mult", "s": s}
-                r = self.challenge(op, s, log)
-                x, y, z = self.instance_mult(a, b, c, r)
-                log["z"] = z
-                ok &= self.fold_and_check(x, y, z, op, s, R, log)
-                self.vlog.append(log)
-                s += 1
+                n = a.m.size
+                for lo in range(0, max(n, 1), self.chunk_mult):
+                    hi = min(n, lo + self.chunk_mult)
+                    log = {"kind": "mult", "s": s, "lo": lo, "hi": hi}
+                    r = self.challenge(op, s, log)
+                    x, y, z = self.instance_mult(a, b, c, r, lo, hi)
+                    log["z"] = z
+                    ok &= self.fold_and_check(x, y, z, op, s, R, log)
+                    self.vlog.append(log)
+                    s += 1
         self.pending = rest
         if not ok:
             self.aborted = True

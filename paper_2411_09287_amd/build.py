@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libmpc3.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["engine.cpp", "kernels.hip", "gemm_u64.hip", "gemm_limb.hip"]
+SOURCES = ["engine.cpp", "kernels.hip", "gemm_u64.hip", "gemm_limb.hip", "nonlinear.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

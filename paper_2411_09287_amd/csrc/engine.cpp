@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <tuple>
 #include <new>
@@ -17,6 +18,7 @@
 #include "gemm.h"
 #include "host_util.h"
 #include "kernels.h"
+#include "nonlinear.h"
 
 using namespace mpc3;
 
@@ -98,11 +100,21 @@ struct InjSlot {
     uint64_t e = 0;
 };
 
+// Device memory the context holds for a pending product until it is verified.
+using Hold = std::shared_ptr<void>;
+
+// Pending products of the non-linear layers (kind MPC3_VERIFY_NONLINEAR)
+enum { NL_ROWS = 1, NL_AND = 2 };
+
 struct Pending {
-    int kind;          // MPC3_VERIFY_INNER / TRUNC / MULT
+    int kind;          // MPC3_VERIFY_INNER / TRUNC / MULT / NONLINEAR
+    int sub = 0;       // NONLINEAR: NL_ROWS (edaBit inner products, X/W n x 64, Z the outputs
+                       // as one block of three planes) or NL_AND (Boolean triples: X, W, Z the
+                       // planes of a, b, c, rows = words)
     mpc3_share_t X, W, Z;
     mpc3_trunc_pair_t pair;
     uint32_t op;
+    std::vector<Hold> hold;
 };
 
 constexpr int RMAX = 40;
@@ -124,6 +136,12 @@ struct mpc3_ctx {
     int variant = MPC3_VARIANT_U64;
     int frac = 13;
     int64_t chunk = 1 << 19;
+    int64_t chunk_rows = 1 << 14;      // edaBit inner products per Pi_BIVerify instance
+    int64_t chunk_mult = 1 << 20;      // Pi_Mult triples per Pi_MultVerify instance
+    u64 gf_inv[3] = {};                // GF(2^64): 1/x, 1/(1+x), 1/(x(1+x))
+    // network model for R = MPC3_R_NETWORK (mpc3_set_network)
+    bool net_set = false;
+    double net_rtt = 0, net_bps = 0, net_gpu_round = 0;
     bool keep_msgs = false;
     bool aborted = false;
     uint32_t op = 0;
@@ -330,16 +348,49 @@ int64_t m_bucket(int64_t M) {
     return b;
 }
 
-int auto_rounds(int64_t n0, int R) {
-    int need = 0;
-    while (((int64_t)1 << need) < n0) ++need;
-    if (R < 0) R = std::max(0, need - 3);
-    return std::min(R, need);
+int64_t padded(int64_t n0, int R);
+
+// Modelled seconds of one verification instance of n0 pairs with R reductions on a network
+// of round-trip time rtt and bandwidth bps: the counted messages of the instance in closed
+// form (w bytes per ring element; n_R = padded n0 / 2^R final pairs) -- offline the
+// [Gamma]_2 shares P0 -> P2, w (2R + n_R + 1); online 2R + 4 rounds whose busiest link
+// (P1 <-> P2) carries w (2R + n_R + 1) + 32 (R + 2) -- each phase priced as rounds x rtt
+// plus its busiest link over the bandwidth, plus R rounds of GPU latency.
+double instance_cost(int64_t n0, int R, double wbytes, double rtt, double bps, double gpu_round) {
+    const double nR = (double)(padded(n0, R) >> R);
+    const double off = wbytes * (2.0 * R + nR + 1.0) * 8.0 / bps;
+    const double link = wbytes * (2.0 * R + nR + 1.0) + 32.0 * (R + 2);
+    const double on = (2.0 * R + 4.0) * rtt + link * 8.0 / bps;
+    return off + on + R * gpu_round;
 }
+
+// R of an instance of n0 pairs: the caller's (at most ceil(log2 n0)); R = -1 picks
+// max(0, ceil(log2 n0) - 3); R = MPC3_R_NETWORK the R of least modelled time (ties to the
+// smaller R) on the context's network model.
+int auto_rounds(const mpc3_ctx* c, int64_t n0, int R, double wbytes = 512.0);
 
 int64_t padded(int64_t n0, int R) {
     const int64_t b = (int64_t)1 << R;
     return (n0 + b - 1) / b * b;
+}
+
+int auto_rounds(const mpc3_ctx* c, int64_t n0, int R, double wbytes) {
+    int need = 0;
+    while (((int64_t)1 << need) < n0) ++need;
+    if (R == MPC3_R_NETWORK) {
+        int best = 0;
+        double bt = instance_cost(n0, 0, wbytes, c->net_rtt, c->net_bps, c->net_gpu_round);
+        for (int q = 1; q <= need && q <= RMAX; ++q) {
+            const double t = instance_cost(n0, q, wbytes, c->net_rtt, c->net_bps, c->net_gpu_round);
+            if (t < bt) {
+                bt = t;
+                best = q;
+            }
+        }
+        return best;
+    }
+    if (R < 0) R = std::max(0, need - 3);
+    return std::min(R, need);
 }
 
 struct VerCtx {
@@ -452,10 +503,25 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
         u64* h2 = c->sc->words(3 * 64);
         const Inj i_h0 = take_ver(c, MPC3_SITE_VER_H0_M1, v.inst, k);
         const Inj i_h2 = take_ver(c, MPC3_SITE_VER_H2_GAMMA2, v.inst, k);
-        u64* F2 = c->sc->words(np * half * 64);
-        u64* Dd = c->sc->words(np * half * 64);
-        launch_at_x_diff(XY, np, n, F2, Dd, s);   // D_i = f_i(1) - f_i(0), f_i(x) = f_i(0) + x D_i
-        if (sparse) {
+        if (sparse && c->variant != MPC3_VARIANT_U64) {
+            // both products in one pass over the two planes on the matrix cores: per
+            // workgroup partial 64 x 64 matrices of h(0) and h(x) (P0's sums; P1's and
+            // P2's are 0), summed into H = [C0, 0, 0, C2, 0, 0]
+            u64* H = c->sc->words(6 * 4096);
+            zero(c, H + 4096, 2 * 4096 * 8);
+            zero(c, H + 4 * 4096, 2 * 4096 * 8);
+            const int groups = (int)std::min<int64_t>((half + 31) / 32, 1024);
+            u64* part = c->sc->words((int64_t)groups * 2 * 4096);
+            ck(hpair_sparse(XY, XY + n * 64, half, part, groups, s));
+            const OutView outs[2] = {oview(H, 64, 1), oview(H + 3 * 4096, 64, 1)};
+            ck(split_reduce(part, 64, 64, 2, groups, 1, outs, View{nullptr, 0, 0, 0}, false, s));
+            polyevl_from(c, v, H, P_VER_H0_R, P_VER_H0_GAMMA, sub, i_h0, Inj{-1, 0}, h0, slot(v, MPC3_LOG_H0_M1, k),
+                         slot(v, MPC3_LOG_H0_M2, k), slot(v, MPC3_LOG_H0_G2, k));
+            polyevl_from(c, v, H + 3 * 4096, P_VER_H2_R, P_VER_H2_GAMMA, sub, Inj{-1, 0}, i_h2, h2,
+                         slot(v, MPC3_LOG_H2_M1, k), slot(v, MPC3_LOG_H2_M2, k), slot(v, MPC3_LOG_H2_G2, k));
+        } else if (sparse) {
+            u64* F2 = c->sc->words(np * half * 64);
+            launch_at_x(XY, np, n, F2, s);        // f_i(x) = f_i(0) + x (f_i(1) - f_i(0))
             polyevl_sparse(c, v, half, XY, 128, XY + n * 64, 128, P_VER_H0_R, P_VER_H0_GAMMA, sub, i_h0,
                            Inj{-1, 0}, h0, slot(v, MPC3_LOG_H0_M1, k), slot(v, MPC3_LOG_H0_M2, k),
                            slot(v, MPC3_LOG_H0_G2, k));
@@ -463,6 +529,8 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
                            i_h2, h2, slot(v, MPC3_LOG_H2_M1, k), slot(v, MPC3_LOG_H2_M2, k),
                            slot(v, MPC3_LOG_H2_G2, k));
         } else {
+            u64* F2 = c->sc->words(np * half * 64);
+            launch_at_x(XY, np, n, F2, s);        // f_i(x) = f_i(0) + x (f_i(1) - f_i(0))
             // h(0) and h(x) are independent: h(x) runs on a side stream (its workspace comes
             // from the same bump allocator, so nothing is shared) and joins before round_finish
             int lane_i = 0;
@@ -490,15 +558,16 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
             ck(hipStreamWaitEvent(s, c->ev_join2[0], 0));
         }
         c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
-        // fold: row i <- f_i(0) + zeta (f_i(1) - f_i(0)) on every stored plane
+        // fold: row i <- f_i(0) (1 - zeta) + f_i(1) zeta on every stored plane.  A pair's two
+        // rows are 128 consecutive words, and the planes are stacked, so the np planes run as
+        // one product of np * half rows of 128 words (row c * half + i = rows 2i, 2i + 1 of
+        // plane c, n = 2 half) with [Mat(1 - zeta); Mat(zeta)]
         u64* Wz = c->sc->words(4096);
         round_finish(c, v, sub, k, h0, h2, z, Wz);
+        u64* Wz2 = c->sc->words(2 * 4096);
+        launch_mat_pair(Wz, Wz2, s);
         u64* XYn = c->sc->words(np * half * 64);
-        // the planes are stacked, so the np planes run as one product of np * half rows:
-        // row c * half + i of D and of the output, row 2 (c * half + i) of XY (n = 2 half)
-        GemmArgs g = plain(np * half, 64, 64, view(Dd, 64, 1), view(Wz, 64, 1), oview(XYn, 64, 1), false);
-        g.Dadd = view(XY, 128, 1);
-        run_gemm(c, g);
+        run_gemm(c, plain(np * half, 64, 128, view(XY, 128, 1), view(Wz2, 64, 1), oview(XYn, 64, 1), false));
         XY = XYn;
         n = half;
     }
@@ -592,7 +661,7 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
     launch_gr_mul_rows(lo + (L - 1) * 64, r, 1, 1, rL, s);   // r^L
     u64* hi = c->sc->words(nhi * 64);
     power_table(c, rL, nhi, hi);                    // r^{L q}
-    const int R = auto_rounds(Ksum, Rarg);
+    const int R = auto_rounds(c, Ksum, Rarg);
     const int64_t np = padded(Ksum, R);
     u64* XY = c->sc->words(6 * np * 64);
     zero(c, XY, (size_t)6 * np * 64 * 8);
@@ -666,20 +735,20 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
     fold_and_check(c, v, XY, np, z, R);
 }
 
-void verify_mult(mpc3_ctx* c, const VerCtx& v, const Pending& it, int Rarg) {
+// Pi_MultVerify of the triples [lo, lo + n) of one Pi_Mult call (gate i - lo weighted by r^(i - lo)).
+void verify_mult(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t lo, int64_t n, int Rarg) {
     hipStream_t s = c->cs;
-    const int64_t n = it.X.rows * it.X.cols;
     u64* r = challenge(c, v);
     u64* pw = c->sc->words(n * 64);
     power_table(c, r, n, pw);
-    const int R = auto_rounds(n, Rarg);
+    const int R = auto_rounds(c, n, Rarg);
     const int64_t np = padded(n, R);
     u64* XY = c->sc->words(6 * np * 64);
     zero(c, XY, (size_t)6 * np * 64 * 8);
-    launch_scale_rows(n, it.X.m, it.X.r1, it.X.r2, pw, XY, np * 64, s);      // x'_i = r^i a_i
-    launch_lift_rows(n, it.W.m, it.W.r1, it.W.r2, XY + 3 * np * 64, np * 64, s);
+    launch_scale_rows(n, it.X.m + lo, it.X.r1 + lo, it.X.r2 + lo, pw, XY, np * 64, s);      // x'_i = r^i a_i
+    launch_lift_rows(n, it.W.m + lo, it.W.r1 + lo, it.W.r2 + lo, XY + 3 * np * 64, np * 64, s);
     u64* z = c->sc->words(3 * 64);
-    const u64* Zc[3] = {it.Z.m, it.Z.r1, it.Z.r2};
+    const u64* Zc[3] = {it.Z.m + lo, it.Z.r1 + lo, it.Z.r2 + lo};
     {   // the three planes' claims in one product with the power table as shared operand
         GemmArgs g = plain(1, 64, n, View{}, view(pw, 64, 1), OutView{}, false);
         g.shared = 3;
@@ -705,7 +774,7 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
     u64* pw = c->sc->words(std::max(2 * T, BK) * 64);
     power_table(c, r, std::max(2 * T, BK), pw);   // r^g for the 2T gates of the chunk (and up to BK)
     const int64_t n0 = 128 * T;
-    const int R = auto_rounds(n0, Rarg);
+    const int R = auto_rounds(c, n0, Rarg);
     const int64_t np = padded(n0, R);
     u64* B1 = c->sc->words(T);
     u64* B2 = c->sc->words(T);
@@ -835,6 +904,295 @@ void verify_trunc_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t
     }
     run_gemm(c, plain(nel, 64, L, view(ga, L, 1), view(ML, 64, 1), oview(XY + half * 64, 64, 1), false));
     fold_and_check(c, v, XY, half, z, R, KS, true);
+}
+
+// ---------------------------------------------------------------------------
+// Non-linear layers (Sec. 4.3)
+// ---------------------------------------------------------------------------
+
+Hold dev_hold(mpc3_ctx* c, int64_t words) {
+    void* p = nullptr;
+    if (hipMalloc(&p, (size_t)std::max<int64_t>(words, 1) * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        throw CodeError(MPC3_E_NOMEM);
+    }
+    (void)c;
+    return Hold(p, [](void* q) { (void)hipFree(q); });
+}
+u64* W(const Hold& h, int64_t off = 0) { return (u64*)h.get() + off; }
+P3 planes(const Hold& h, int64_t n) { return P3{{W(h), W(h, n), W(h, 2 * n)}}; }
+C3 cplanes(const P3& p) { return C3{{p.p[0], p.p[1], p.p[2]}}; }
+C3 cplanes(const mpc3_share_t& s) { return C3{{s.m, s.r1, s.r2}}; }
+mpc3_share_t as_share(C3 p, int64_t rows, int64_t cols) {
+    return mpc3_share_t{(uint64_t*)p.p[0], (uint64_t*)p.p[1], (uint64_t*)p.p[2], rows, cols};
+}
+
+// Pi_Mult of n elements whose triple is registered with the buffers it needs held; phase_on
+// is the counter phase of the P1 <-> P2 exchange (offline for preprocessing).
+void mult_internal(mpc3_ctx* c, int64_t n, C3 a, C3 b, P3 out, int phase_on, std::vector<Hold> hold) {
+    const uint32_t op = c->op++;
+    launch_mult(n, c->keys, op, a.p[0], a.p[1], a.p[2], b.p[0], b.p[1], b.p[2], take(c, MPC3_SITE_MULT_GAMMA2, n),
+                out.p[0], out.p[1], out.p[2], nullptr, nullptr, nullptr, c->stream);
+    ck(hipGetLastError());
+    send(c, MPC3_PH_OFFLINE, 0, 2, 8 * n);
+    c->rounds[MPC3_PH_OFFLINE] += 1;
+    send(c, phase_on, 1, 2, 8 * n);
+    send(c, phase_on, 2, 1, 8 * n);
+    c->rounds[phase_on] += 1;
+    Pending p{};
+    p.kind = MPC3_VERIFY_MULT;
+    p.X = as_share(a, n, 1);
+    p.W = as_share(b, n, 1);
+    p.Z = as_share(cplanes(out), n, 1);
+    p.op = op;
+    p.hold = std::move(hold);
+    c->pending.push_back(std::move(p));
+}
+
+// Pi_Rec of n words to every party (nbytes per message), counted.
+void count_open(mpc3_ctx* c, int ph, uint64_t nbytes) {
+    send(c, ph, 0, 2, nbytes);
+    send(c, ph, 0, 1, nbytes);
+    send(c, ph, 1, 0, nbytes);
+    send(c, ph, 1, 2, 32);
+    send(c, ph, 2, 0, 32);
+    send(c, ph, 2, 1, 32);
+    c->rounds[ph] += 1;
+}
+
+// n edaBits (Fig. "The maliciously edaBits generation"): bit words (m from eta_12, [r]_1
+// from eta_01, [r]_2 from eta_02), the products b_1 b_2 of every bit position as one Pi_Mult,
+// r' = b_1 XOR b_2 arithmetically, and r = sum_j 2^j (m_j + r'_j) - Pi_Inner(2^(j+1) m_j, r'_j)
+// with one 64-element inner product per edaBit.
+void edabits_run(mpc3_ctx* c, int64_t n, P3 r, P3 bits) {
+    hipStream_t s = c->stream;
+    const uint32_t op = c->op++;
+    launch_fill(bits.p[0], n, c->keys.k12, make_tag(op, P_EDA_BITS, 0, 0), s);
+    launch_fill(bits.p[1], n, c->keys.k01, make_tag(op, P_EDA_BITS, 1, 0), s);
+    launch_fill(bits.p[2], n, c->keys.k02, make_tag(op, P_EDA_BITS, 2, 0), s);
+    const int64_t e = 64 * n;
+    Hold hz = dev_hold(c, e), hA = dev_hold(c, e), hB = dev_hold(c, e), hC = dev_hold(c, 3 * e),
+         hRP = dev_hold(c, 3 * e), hX = dev_hold(c, e), hW = dev_hold(c, 3 * n);
+    zero(c, W(hz), (size_t)e * 8);
+    launch_lift_bits(e, 64, bits.p[1], 1, W(hA), s);      // <b_1> = (0, -b_1, 0)
+    launch_lift_bits(e, 64, bits.p[2], 1, W(hB), s);      // <b_2> = (0, 0, -b_2)
+    const C3 sb1{{W(hz), W(hA), W(hz)}}, sb2{{W(hz), W(hz), W(hB)}};
+    const P3 prod = planes(hC, e), rp = planes(hRP, e), w = planes(hW, n);
+    mult_internal(c, e, sb1, sb2, prod, MPC3_PH_OFFLINE, {hz, hA, hB, hC});
+    launch_lin3(e, sb1, sb2, cplanes(prod), rp, s);
+    launch_eda_rows(n, c->keys, op, bits.p[0], cplanes(rp), take(c, MPC3_SITE_EDA_W_M1, n), W(hX), w, r, s);
+    ck(hipGetLastError());
+    send(c, MPC3_PH_OFFLINE, 0, 2, 8 * n);
+    send(c, MPC3_PH_OFFLINE, 1, 2, 8 * n);
+    send(c, MPC3_PH_OFFLINE, 2, 1, 8 * n);
+    c->rounds[MPC3_PH_OFFLINE] += 1;
+    Pending p{};
+    p.kind = MPC3_VERIFY_NONLINEAR;
+    p.sub = NL_ROWS;
+    p.X = mpc3_share_t{W(hX), W(hz), W(hz), n, 64};
+    p.W = mpc3_share_t{rp.p[0], rp.p[1], rp.p[2], n, 64};
+    p.Z = mpc3_share_t{w.p[0], w.p[1], w.p[2], n, 1};
+    p.op = op;
+    p.hold = {hz, hX, hRP, hW};
+    c->pending.push_back(std::move(p));
+}
+
+// n daBits: one random bit per word in both sharings, from two Pi_Mult rounds
+// (r' = b_1 XOR b_2, s = m XOR r').
+void dabits_run(mpc3_ctx* c, int64_t n, P3 sa, P3 sb) {
+    hipStream_t s = c->stream;
+    const uint32_t op = c->op++;
+    launch_fill(sb.p[0], n, c->keys.k12, make_tag(op, P_DA_BITS, 0, 0), s);
+    launch_fill(sb.p[1], n, c->keys.k01, make_tag(op, P_DA_BITS, 1, 0), s);
+    launch_fill(sb.p[2], n, c->keys.k02, make_tag(op, P_DA_BITS, 2, 0), s);
+    for (int q = 0; q < 3; ++q) launch_lift_bits(n, 1, sb.p[q], 0, sb.p[q], s);   // keep bit 0
+    Hold hz = dev_hold(c, n), hA = dev_hold(c, n), hB = dev_hold(c, n), hM = dev_hold(c, n),
+         hP1 = dev_hold(c, 3 * n), hRP = dev_hold(c, 3 * n), hP2 = dev_hold(c, 3 * n);
+    zero(c, W(hz), (size_t)n * 8);
+    launch_lift_bits(n, 1, sb.p[1], 1, W(hA), s);
+    launch_lift_bits(n, 1, sb.p[2], 1, W(hB), s);
+    launch_lift_bits(n, 1, sb.p[0], 0, W(hM), s);
+    const C3 sb1{{W(hz), W(hA), W(hz)}}, sb2{{W(hz), W(hz), W(hB)}}, smb{{W(hM), W(hz), W(hz)}};
+    const P3 p1 = planes(hP1, n), rp = planes(hRP, n), p2 = planes(hP2, n);
+    mult_internal(c, n, sb1, sb2, p1, MPC3_PH_OFFLINE, {hz, hA, hB, hP1});
+    launch_lin3(n, sb1, sb2, cplanes(p1), rp, s);
+    mult_internal(c, n, smb, cplanes(rp), p2, MPC3_PH_OFFLINE, {hz, hM, hRP, hP2});
+    launch_lin3(n, smb, cplanes(rp), cplanes(p2), sa, s);
+    ck(hipGetLastError());
+}
+
+// ReLU of n values: out = x * (1 - msb(x)).  The edaBit's Delta = x - r is opened, the carry
+// into bit 63 of Delta + r comes from a Kogge-Stone prefix over the bit words (six Boolean
+// Pi_Mult rounds, their triples one pending record), the complemented top bit is converted
+// with a daBit and multiplied with x.  `keep` holds x and out when the context owns them.
+void relu_run(mpc3_ctx* c, int64_t n, C3 x, P3 out, std::vector<Hold> keep) {
+    hipStream_t s = c->stream;
+    Hold hr = dev_hold(c, 3 * n), hbits = dev_hold(c, 3 * n), hsa = dev_hold(c, 3 * n), hsb = dev_hold(c, 3 * n);
+    const P3 er = planes(hr, n), eb = planes(hbits, n), sa = planes(hsa, n), sb = planes(hsb, n);
+    edabits_run(c, n, er, eb);
+    dabits_run(c, n, sa, sb);
+    // Boolean triples of the six prefix levels: 2n words at k = 1 .. 16, n at k = 32
+    const int64_t wt = 11 * n;
+    Hold habc = dev_hold(c, 9 * wt);
+    auto pl = [&](int which, int64_t off) {
+        return P3{{W(habc, (3 * which + 0) * wt + off), W(habc, (3 * which + 1) * wt + off),
+                   W(habc, (3 * which + 2) * wt + off)}};
+    };
+    {
+        Pending p{};
+        p.kind = MPC3_VERIFY_NONLINEAR;
+        p.sub = NL_AND;
+        const P3 A = pl(0, 0), B = pl(1, 0), C = pl(2, 0);
+        p.X = mpc3_share_t{A.p[0], A.p[1], A.p[2], wt, 1};
+        p.W = mpc3_share_t{B.p[0], B.p[1], B.p[2], wt, 1};
+        p.Z = mpc3_share_t{C.p[0], C.p[1], C.p[2], wt, 1};
+        p.op = c->op;
+        p.hold = {habc};
+        c->pending.push_back(std::move(p));
+    }
+    Hold htmp = dev_hold(c, 13 * n);
+    u64* delta = W(htmp);
+    const P3 P0{{W(htmp, n), W(htmp, 2 * n), W(htmp, 3 * n)}}, G{{W(htmp, 4 * n), W(htmp, 5 * n), W(htmp, 6 * n)}},
+             P{{W(htmp, 7 * n), W(htmp, 8 * n), W(htmp, 9 * n)}}, d{{W(htmp, 10 * n), W(htmp, 11 * n), W(htmp, 12 * n)}};
+    launch_open_diff(n, x, cplanes(er), delta, s);
+    count_open(c, MPC3_PH_ONLINE, 8 * n);
+    launch_a2b_init(n, cplanes(eb), delta, P0, G, P, s);
+    int64_t off = 0;
+    for (int k = 1; k <= 32; k *= 2) {
+        const bool last = k == 32;
+        const int64_t m = last ? n : 2 * n;
+        const P3 A = pl(0, off), B = pl(1, off), C = pl(2, off);
+        launch_ks_prep(n, k, last, cplanes(P), cplanes(G), A, B, s);
+        const uint32_t op = c->op++;
+        launch_and_words(m, c->keys, op, cplanes(A), cplanes(B), take(c, MPC3_SITE_AND_GAMMA2, m), C, s);
+        send(c, MPC3_PH_OFFLINE, 0, 2, 8 * m);
+        c->rounds[MPC3_PH_OFFLINE] += 1;
+        send(c, MPC3_PH_ONLINE, 1, 2, 8 * m);
+        send(c, MPC3_PH_ONLINE, 2, 1, 8 * m);
+        c->rounds[MPC3_PH_ONLINE] += 1;
+        launch_ks_update(n, last, cplanes(C), G, P, s);
+        off += m;
+    }
+    launch_msb_final(n, cplanes(P0), cplanes(G), true, d, s);        // 1 - msb(x)
+    Hold hdl = dev_hold(c, 3 * n);
+    const P3 dl = planes(hdl, n);
+    launch_b2a(n, cplanes(d), cplanes(sb), cplanes(sa), dl, s);
+    count_open(c, MPC3_PH_ONLINE, (uint64_t)((n + 7) / 8));
+    ck(hipGetLastError());
+    // the temporaries stay held with the last product until it is verified, so that no
+    // buffer a queued launch still uses is freed (the stream is not synchronised here)
+    for (const Hold& h : {hdl, htmp, hr, hbits, hsa, hsb}) keep.push_back(h);
+    mult_internal(c, n, x, cplanes(dl), out, MPC3_PH_ONLINE, std::move(keep));
+}
+
+// 2x2 max pooling (stride 2) of an NHWC tensor: max(p, q) = q + ReLU(p - q) over the two row
+// pairs of each window, then over the two results.
+void maxpool_run(mpc3_ctx* c, int B, int H, int Wd, int C, C3 x, P3 out) {
+    hipStream_t s = c->stream;
+    const int64_t N = (int64_t)B * (H / 2) * (Wd / 2) * C;
+    Hold hp = dev_hold(c, 6 * N), hq = dev_hold(c, 6 * N), hd = dev_hold(c, 6 * N), hr = dev_hold(c, 6 * N),
+         hu = dev_hold(c, 6 * N);
+    const P3 p = planes(hp, 2 * N), q = planes(hq, 2 * N), d = planes(hd, 2 * N), r = planes(hr, 2 * N),
+             u = planes(hu, 2 * N);
+    launch_pool_gather(B, H, Wd, C, x, p, q, s);
+    launch_addsub3(2 * N, cplanes(p), cplanes(q), -1, d, s);
+    relu_run(c, 2 * N, cplanes(d), r, {hd, hr, hp, hq});
+    launch_addsub3(2 * N, cplanes(q), cplanes(r), 1, u, s);
+    Hold hd2 = dev_hold(c, 3 * N), hr2 = dev_hold(c, 3 * N);
+    const P3 d2 = planes(hd2, N), r2 = planes(hr2, N);
+    const C3 u1{{u.p[0], u.p[1], u.p[2]}}, u2{{u.p[0] + N, u.p[1] + N, u.p[2] + N}};
+    launch_addsub3(N, u1, u2, -1, d2, s);
+    relu_run(c, N, cplanes(d2), r2, {hd2, hr2, hu});
+    launch_addsub3(N, u2, cplanes(r2), 1, out, s);
+    ck(hipGetLastError());
+}
+
+// Pi_BIVerify of edaBit inner products [lo, lo + T): row p is a 64-element gate, weight
+// r^(p - lo) on its x side.
+void verify_rows_chunk(mpc3_ctx* c, const VerCtx& v, const Pending& it, int64_t lo, int64_t T, int Rarg) {
+    hipStream_t s = c->cs;
+    u64* r = challenge(c, v);
+    u64* pw = c->sc->words(T * 64);
+    power_table(c, r, T, pw);
+    const int64_t n0 = 64 * T;
+    const int R = auto_rounds(c, n0, Rarg);
+    const int64_t np = padded(n0, R);
+    u64* XY = c->sc->words(6 * np * 64);
+    if (np > n0)
+        for (int q = 0; q < 6; ++q) zero(c, XY + (q * np + n0) * 64, (size_t)(np - n0) * 512);
+    const C3 xs{{it.X.m + lo * 64, it.X.r1 + lo * 64, it.X.r2 + lo * 64}};
+    launch_scale_gates(n0, 64, xs, pw, XY, np * 64, s);
+    launch_lift_rows(n0, it.W.m + lo * 64, it.W.r1 + lo * 64, it.W.r2 + lo * 64, XY + 3 * np * 64, np * 64, s);
+    u64* z = c->sc->words(3 * 64);
+    run_gemm(c, plain(3, 64, T, view(it.Z.m + lo, it.Z.rows, 1), view(pw, 64, 1), oview(z, 64, 1), false));
+    ck(hipMemcpyAsync(slot(v, MPC3_LOG_Z), z, 512, hipMemcpyDeviceToDevice, s));
+    c->vinfo.push_back(InstanceInfo{R, np});
+    fold_and_check(c, v, XY, np, z, R);
+}
+
+// Pi_MultVerify over GF(2^64) of one layer call's Boolean triples: gate g = 64 w + b of the
+// concatenated words, weight r^g on the x side.
+void verify_and(mpc3_ctx* c, const VerCtx& v, const Pending& it, int Rarg) {
+    hipStream_t s = c->cs;
+    const int64_t Wn = it.X.rows, G = 64 * Wn;
+    u64* tmp = c->sc->words(8);
+    u64* r = tmp + 3;
+    launch_gf_random(c->keys, v.op, P_VER_R, (uint32_t)v.inst, tmp, r, slot(v, MPC3_LOG_R), s);
+    count_open(c, MPC3_PH_VERIFY_ONLINE, 8);
+    const int R = auto_rounds(c, G, Rarg, 8.0);
+    const int64_t np = padded(G, R);
+    u64* T0 = c->sc->words(64);
+    u64* T1 = c->sc->words(Wn);
+    launch_gf_pow_tables(r, Wn, T0, T1, s);
+    u64* XY = c->sc->words(6 * np);
+    u64* z = c->sc->words(3);
+    launch_gf_tran(Wn, T0, T1, cplanes(it.X), cplanes(it.W), cplanes(it.Z), XY, np, z, scratch_alloc, c->sc, s);
+    ck(hipMemcpyAsync(slot(v, MPC3_LOG_Z), z, 8, hipMemcpyDeviceToDevice, s));
+    c->vinfo.push_back(InstanceInfo{R, np});
+    int64_t n = np;
+    for (int k = 0; k < R; ++k) {
+        const int64_t half = n / 2;
+        u64* XYn = c->sc->words(6 * half);
+        GfRoundArgs a{};
+        a.k = c->keys;
+        a.op = v.op;
+        a.sub = ((uint32_t)v.inst << 8) | (uint32_t)k;
+        for (int q = 0; q < 3; ++q) a.inv[q] = c->gf_inv[q];
+        a.z = z;
+        a.zeta = c->sc->words(1);
+        a.log_zeta = slot(v, MPC3_LOG_ZETA, k);
+        a.log_h0 = slot(v, MPC3_LOG_H0_M1, k);
+        a.log_h2 = slot(v, MPC3_LOG_H2_M1, k);
+        launch_gf_round(half, XY, n, XYn, half, a, scratch_alloc, c->sc, s);
+        for (int h = 0; h < 2; ++h) {
+            send(c, MPC3_PH_VERIFY_OFFLINE, 0, 2, 8);
+            send(c, MPC3_PH_VERIFY_ONLINE, 1, 2, 8);
+            send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8);
+        }
+        c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
+        count_open(c, MPC3_PH_VERIFY_ONLINE, 8);
+        XY = XYn;
+        n = half;
+    }
+    GfDeltaArgs d{};
+    d.k = c->keys;
+    d.op = v.op;
+    d.sub = (uint32_t)v.inst;
+    d.z = z;
+    d.log_delta = slot(v, MPC3_LOG_DELTA);
+    d.log_tr = slot(v, MPC3_LOG_DELTA_M1);
+    d.flag = v.flag;
+    launch_gf_inner_verify(n, XY, n, d, scratch_alloc, c->sc, s);
+    ck(hipGetLastError());
+    send(c, MPC3_PH_VERIFY_OFFLINE, 0, 2, 8 * n);
+    send(c, MPC3_PH_VERIFY_ONLINE, 1, 2, 8 * n);
+    send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8 * n);
+    c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
+    send(c, MPC3_PH_VERIFY_OFFLINE, 0, 2, 8);
+    send(c, MPC3_PH_VERIFY_ONLINE, 1, 2, 8);
+    send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8);
+    c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
+    count_open(c, MPC3_PH_VERIFY_ONLINE, 8);
 }
 
 int guard(mpc3_ctx* c) {
@@ -996,6 +1354,9 @@ int mpc3_ctx_create(const uint8_t master_seed[32], int d, int frac_bits, size_t 
         c->keys.k02 = eta({0, 2});
         c->keys.k12 = eta({1, 2});
         c->keys.kall = eta({0, 1, 2});
+        c->gf_inv[0] = gf_inv_host(2);
+        c->gf_inv[1] = gf_inv_host(3);
+        c->gf_inv[2] = gf_inv_host(gf_mul_host(2, 3));
         // 1/x, 1/(1-x), 1/(x(x-1)): Lagrange denominators over the nodes {0, 1, x}
         host::Elem X(64, 0), one = host::gr_const(1);
         X[1] = 1;
@@ -1139,6 +1500,24 @@ int mpc3_set_chunk(mpc3_ctx* c, int64_t t) {
     return MPC3_OK;
 }
 
+int mpc3_set_verify_chunks(mpc3_ctx* c, int64_t mult_triples, int64_t edabit_rows) {
+    if (!c || mult_triples < 0 || edabit_rows < 0 || mult_triples > ((int64_t)1 << 24) ||
+        edabit_rows > ((int64_t)1 << 18))
+        return MPC3_E_ARG;
+    if (mult_triples) c->chunk_mult = mult_triples;
+    if (edabit_rows) c->chunk_rows = edabit_rows;
+    return MPC3_OK;
+}
+
+int mpc3_set_network(mpc3_ctx* c, double rtt_ms, double mbit_per_s, double gpu_round_ms) {
+    if (!c || !(rtt_ms >= 0) || !(mbit_per_s > 0) || !(gpu_round_ms >= 0)) return MPC3_E_ARG;
+    c->net_rtt = rtt_ms * 1e-3;
+    c->net_bps = mbit_per_s * 1e6;
+    c->net_gpu_round = gpu_round_ms * 1e-3;
+    c->net_set = true;
+    return MPC3_OK;
+}
+
 int mpc3_keep_messages(mpc3_ctx* c, int on) {
     if (!c) return MPC3_E_ARG;
     c->keep_msgs = on != 0;
@@ -1247,23 +1626,29 @@ int mpc3_inner_static(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W,
     });
 }
 
-int mpc3_im2col(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, int KH, int KW, int pad,
-                mpc3_share_t* cols) {
+int mpc3_im2col_strided(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, int KH, int KW, int pad,
+                        int stride, mpc3_share_t* cols) {
     int g = guard(c);
     if (g) return g;
-    if (!valid(x) || !valid(cols) || B < 0 || H <= 0 || W <= 0 || C <= 0 || KH <= 0 || KW <= 0 || pad < 0)
+    if (!valid(x) || !valid(cols) || B < 0 || H <= 0 || W <= 0 || C <= 0 || KH <= 0 || KW <= 0 || pad < 0 ||
+        stride <= 0)
         return MPC3_E_ARG;
-    const int OH = H + 2 * pad - KH + 1, OW = W + 2 * pad - KW + 1;
-    if (OH <= 0 || OW <= 0) return MPC3_E_SHAPE;
+    if (H + 2 * pad < KH || W + 2 * pad < KW) return MPC3_E_SHAPE;
+    const int OH = (H + 2 * pad - KH) / stride + 1, OW = (W + 2 * pad - KW) / stride + 1;
     if (x->rows * x->cols != (int64_t)B * H * W * C) return MPC3_E_SHAPE;
     if (cols->rows != (int64_t)B * OH * OW || cols->cols < (int64_t)KH * KW * C) return MPC3_E_SHAPE;
     return wrap(c, __func__, [&] {
         const u64* const xs[3] = {x->m, x->r1, x->r2};
         u64* const os[3] = {cols->m, cols->r1, cols->r2};
-        launch_im2col3(xs, B, H, W, C, KH, KW, pad, cols->cols, os, c->stream);
+        launch_im2col3(xs, B, H, W, C, KH, KW, pad, cols->cols, os, c->stream, stride);
         ck(hipGetLastError());
         return (int)MPC3_OK;
     });
+}
+
+int mpc3_im2col(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, int KH, int KW, int pad,
+                mpc3_share_t* cols) {
+    return mpc3_im2col_strided(c, x, B, H, W, C, KH, KW, pad, 1, cols);
 }
 
 int mpc3_sumpool2(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, mpc3_share_t* out) {
@@ -1277,6 +1662,52 @@ int mpc3_sumpool2(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C
         launch_sumpool2(x->r1, B, H, W, C, out->r1, c->stream);
         launch_sumpool2(x->r2, B, H, W, C, out->r2, c->stream);
         ck(hipGetLastError());
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_edabits(mpc3_ctx* c, int64_t n, mpc3_share_t* arith, mpc3_share_t* bits) {
+    int g = guard(c);
+    if (g) return g;
+    if (n < 0 || !valid(arith) || !valid(bits)) return MPC3_E_ARG;
+    if (arith->rows * arith->cols != n || bits->rows * bits->cols != n) return MPC3_E_SHAPE;
+    return wrap(c, __func__, [&] {
+        if (n > 0) edabits_run(c, n, P3{{arith->m, arith->r1, arith->r2}}, P3{{bits->m, bits->r1, bits->r2}});
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_dabits(mpc3_ctx* c, int64_t n, mpc3_share_t* arith, mpc3_share_t* bits) {
+    int g = guard(c);
+    if (g) return g;
+    if (n < 0 || !valid(arith) || !valid(bits)) return MPC3_E_ARG;
+    if (arith->rows * arith->cols != n || bits->rows * bits->cols != n) return MPC3_E_SHAPE;
+    return wrap(c, __func__, [&] {
+        if (n > 0) dabits_run(c, n, P3{{arith->m, arith->r1, arith->r2}}, P3{{bits->m, bits->r1, bits->r2}});
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_relu(mpc3_ctx* c, const mpc3_share_t* x, mpc3_share_t* out) {
+    int g = guard(c);
+    if (g) return g;
+    if (!valid(x) || !valid(out)) return MPC3_E_ARG;
+    const int64_t n = x->rows * x->cols;
+    if (out->rows * out->cols != n) return MPC3_E_SHAPE;
+    return wrap(c, __func__, [&] {
+        if (n > 0) relu_run(c, n, cplanes(*x), P3{{out->m, out->r1, out->r2}}, {});
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_maxpool2(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int Wd, int C, mpc3_share_t* out) {
+    int g = guard(c);
+    if (g) return g;
+    if (!valid(x) || !valid(out) || B < 0 || H <= 0 || Wd <= 0 || C <= 0 || (H & 1) || (Wd & 1)) return MPC3_E_ARG;
+    if (x->rows * x->cols != (int64_t)B * H * Wd * C || out->rows * out->cols != (int64_t)B * (H / 2) * (Wd / 2) * C)
+        return MPC3_E_SHAPE;
+    return wrap(c, __func__, [&] {
+        if (B > 0) maxpool_run(c, B, H, Wd, C, cplanes(*x), P3{{out->m, out->r1, out->r2}});
         return (int)MPC3_OK;
     });
 }
@@ -1327,7 +1758,8 @@ int mpc3_trunc(mpc3_ctx* c, const mpc3_trunc_pair_t* p, const mpc3_share_t* Z, m
 int mpc3_verify(mpc3_ctx* c, int R, int kinds, int* ok) {
     int g = guard(c);
     if (g) return g;
-    if (!ok || R > RMAX || kinds <= 0 || kinds > MPC3_VERIFY_ALL) return MPC3_E_ARG;
+    if (!ok || R > RMAX || R < MPC3_R_NETWORK || kinds <= 0 || kinds > MPC3_VERIFY_ALL) return MPC3_E_ARG;
+    if (R == MPC3_R_NETWORK && !c->net_set) return MPC3_E_STATE;
     return wrap(c, __func__, [&] {
         const uint32_t op = c->op++;
         hipStream_t s = c->stream;
@@ -1339,8 +1771,14 @@ int mpc3_verify(mpc3_ctx* c, int R, int kinds, int* ok) {
         for (auto& p : sel)
             if (p.kind == MPC3_VERIFY_INNER) inner.push_back(&p);
         int64_t ninst = inner.empty() ? 0 : 1;
-        for (auto& p : sel)
-            if (p.kind != MPC3_VERIFY_INNER) ninst += p.kind == MPC3_VERIFY_TRUNC ? (p.pair.n + c->chunk - 1) / c->chunk : 1;
+        for (auto& p : sel) {
+            if (p.kind == MPC3_VERIFY_INNER) continue;
+            if (p.kind == MPC3_VERIFY_TRUNC) ninst += (p.pair.n + c->chunk - 1) / c->chunk;
+            else if (p.kind == MPC3_VERIFY_NONLINEAR && p.sub == NL_ROWS) ninst += (p.X.rows + c->chunk_rows - 1) / c->chunk_rows;
+            else if (p.kind == MPC3_VERIFY_MULT)
+                ninst += std::max<int64_t>(1, (p.X.rows * p.X.cols + c->chunk_mult - 1) / c->chunk_mult);
+            else ninst += 1;
+        }
         u64* logd = c->scratch.words(std::max<int64_t>(ninst, 1) * NSLOT * 64);
         int* flags = (int*)c->scratch.alloc(std::max<int64_t>(ninst, 1) * sizeof(int));
         zero(c, logd, (size_t)std::max<int64_t>(ninst, 1) * NSLOT * 64 * 8);
@@ -1391,11 +1829,32 @@ int mpc3_verify(mpc3_ctx* c, int R, int kinds, int* ok) {
                     c->sc->restore(mk);
                     ++inst;
                 }
+            } else if (p.kind == MPC3_VERIFY_NONLINEAR && p.sub == NL_ROWS) {
+                for (int64_t lo = 0; lo < p.X.rows; lo += c->chunk_rows) {
+                    const int64_t T = std::min(c->chunk_rows, p.X.rows - lo);
+                    lane(inst);
+                    Scratch::Mark mk = c->sc->mark();
+                    VerCtx v{op, inst, logd + inst * NSLOT * 64, flags + inst};
+                    verify_rows_chunk(c, v, p, lo, T, R);
+                    c->sc->restore(mk);
+                    ++inst;
+                }
+            } else if (p.kind == MPC3_VERIFY_MULT) {
+                const int64_t n = p.X.rows * p.X.cols;
+                for (int64_t lo = 0; lo < std::max<int64_t>(n, 1); lo += c->chunk_mult) {
+                    const int64_t T = std::min(c->chunk_mult, n - lo);
+                    lane(inst);
+                    Scratch::Mark mk = c->sc->mark();
+                    VerCtx v{op, inst, logd + inst * NSLOT * 64, flags + inst};
+                    verify_mult(c, v, p, lo, T, R);
+                    c->sc->restore(mk);
+                    ++inst;
+                }
             } else {
                 lane(inst);
                 Scratch::Mark mk = c->sc->mark();
                 VerCtx v{op, inst, logd + inst * NSLOT * 64, flags + inst};
-                verify_mult(c, v, p, R);
+                verify_and(c, v, p, R);
                 c->sc->restore(mk);
                 ++inst;
             }
@@ -1462,7 +1921,7 @@ int mpc3_comm_stats(mpc3_ctx* c, mpc3_comm* out) {
 }
 
 int mpc3_inject(mpc3_ctx* c, int site, int64_t index, uint64_t e) {
-    if (!c || site < 1 || site > 9 || index < 0) return MPC3_E_ARG;
+    if (!c || site < 1 || site > 11 || index < 0) return MPC3_E_ARG;
     c->inj[site] = InjSlot{true, index, e};
     return MPC3_OK;
 }

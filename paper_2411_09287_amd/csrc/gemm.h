@@ -61,6 +61,12 @@ hipError_t limb_btiles(const View& B, int64_t K, int64_t N, int8_t* out, hipStre
 // Fills n 32-bit words with 0 (a kernel, so that it can also be captured in a graph).
 hipError_t zero_words32(void* p, int64_t n, hipStream_t stream);
 
+// The h(0) and h(x) products of a Pi_Reduce round over two planes X (x side) and Y (y side)
+// of 2 npairs rows of 64 words: per workgroup g < groups, part[g] = (C0, C2), 2 x 64 x 64
+// words, C0 = sum_i X[2i]^T Y[2i], C2 = sum_i F_X(i)^T F_Y(i), F(i) = f(2i) + x (f(2i+1) -
+// f(2i)) in GR(2^64, 64); the workgroups' partials add up to the products.
+hipError_t hpair_sparse(const u64* X, const u64* Y, int64_t npairs, u64* part, int groups, hipStream_t stream);
+
 // Bytes of partial sums one product may use before the split count is cut back.
 constexpr size_t PART_MAX = (size_t)1 << 30;
 

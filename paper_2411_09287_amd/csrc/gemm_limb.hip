@@ -673,6 +673,110 @@ Opnd combo(const View* v, int64_t b, bool transpose, int64_t rows, int i0, int c
     return o;
 }
 
+
+// ---------------------------------------------------------------------------
+// The two Pi_PolyEvl products of a Pi_Reduce round over the truncation gates' two non-zero
+// planes (the x side's [r]_1 plane X and the y side's [r]_2 plane Y, n rows of 64 words,
+// pairs (2i, 2i+1)), in one pass over the rows:
+//     C0 = sum_i X[2i]^T Y[2i]            (h(0): the 64 x 64 outer products, P0's sum)
+//     C2 = sum_i F_X(i)^T F_Y(i),  F(i) = f(2i) + x (f(2i+1) - f(2i))   (h(x))
+// A workgroup takes blocks of 32 pairs: wave w reads pairs 8w .. 8w+7 (lane = coefficient,
+// 512 coalesced bytes per row), forms f(2i) and F(i) in registers (x (.) by a shift across
+// the lanes), and writes their balanced digits as transposed k-octets (row = coefficient,
+// k = pair) to LDS; then each wave multiplies one 32 x 32 quadrant of C0 and of C2 on the
+// matrix cores (K = 32 pairs per block) and adds the recombined 64-bit values to its
+// running sums.  One 2 x 64 x 64 partial per workgroup (part), summed afterwards.
+// ---------------------------------------------------------------------------
+constexpr int HP_OPS = 4;                       // X f0, X F, Y f0, Y F
+__global__ __launch_bounds__(NT, 2) void k_hpair(const u64* X, const u64* Y, int64_t npairs, int64_t nblocks,
+                                                 u64* part) {
+    __shared__ __attribute__((aligned(16))) int8_t T[HP_OPS][8 * PLANE];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wy = w >> 1, wx = w & 1, r = lane & 31, kh = (lane >> 5) * 16;
+    const int arow = wy * 32 + r, brow = wx * 32 + r;
+    u64 c0[16], c2[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) c0[v] = c2[v] = 0;
+    for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+        // digits of 8 pairs per lane and operand: q[op][d] byte q = pair 8w + q
+        u64 q[HP_OPS][8];
+#pragma unroll
+        for (int o = 0; o < HP_OPS; ++o)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) q[o][d] = 0;
+#pragma unroll
+        for (int pq = 0; pq < 8; ++pq) {
+            const int64_t pr = blk * 32 + w * 8 + pq;
+            const bool in = pr < npairs;
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const u64* P = side ? Y : X;
+                const u64 e = in ? P[(2 * pr) * 64 + lane] : 0;
+                const u64 o = in ? P[(2 * pr + 1) * 64 + lane] : 0;
+                const u64 d = o - e;
+                const u64 top = __shfl(d, 63, 64);
+                u64 xd = __shfl_up(d, 1, 64);
+                if (lane == 0) xd = 0;
+#pragma unroll
+                for (int tq = 0; tq < 4; ++tq)
+                    if (lane == (tq == 0 ? 0 : tq == 1 ? 1 : tq == 2 ? 3 : 4)) xd -= top;
+                const u64 f = e + xd;
+                const u64 be = (e + OFF) ^ OFF, bf = (f + OFF) ^ OFF;
+#pragma unroll
+                for (int dg = 0; dg < 8; ++dg) {
+                    q[2 * side][dg] |= ((be >> (8 * dg)) & 0xFFull) << (8 * pq);
+                    q[2 * side + 1][dg] |= ((bf >> (8 * dg)) & 0xFFull) << (8 * pq);
+                }
+            }
+        }
+        // transposed tile of each operand: plane d, k-octet w, row = coefficient lane
+#pragma unroll
+        for (int o = 0; o < HP_OPS; ++o)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) *(u64*)(T[o] + d * PLANE + w * 512 + lane * 8) = q[o][d];
+        __syncthreads();
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr) {            // pr 0: C0 = Xf0^T Yf0; pr 1: C2 = XF^T YF
+            const int8_t* TA = T[pr];
+            const int8_t* TB = T[2 + pr];
+            v16i acc[8];
+#pragma unroll
+            for (int s2 = 0; s2 < 8; ++s2) acc[s2] = v16i{0};
+            v4i B[8];
+#pragma unroll
+            for (int d = 0; d < 8; ++d) B[d] = frag<false>(TB + d * PLANE, brow, kh);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const v4i A = frag<false>(TA + i * PLANE, arow, kh);
+#pragma unroll
+                for (int s2 = i; s2 < 8; ++s2)
+                    acc[s2] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[s2 - i], acc[s2], 0, 0, 0);
+            }
+            // second half of the 32 pairs: k 16..31 is read by lanes 32..63 (kh) -- the
+            // 32-deep k-block is complete in one pass
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                u64 val = 0;
+#pragma unroll
+                for (int s2 = 0; s2 < 8; ++s2) val += ((u64)(int64_t)acc[s2][v]) << (8 * s2);
+                if (pr == 0) c0[v] += val;
+                else c2[v] += val;
+            }
+        }
+        __syncthreads();
+    }
+    // quadrant (wy, wx): row (coefficient of X) 8 (v >> 2) + 4 (lane >> 5) + (v & 3), column
+    // (coefficient of Y) lane & 31
+    u64* P0 = part + (int64_t)blockIdx.x * 2 * 4096;
+    const int n = wx * 32 + (lane & 31);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int m = wy * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        P0[m * 64 + n] = c0[v];
+        P0[4096 + m * 64 + n] = c2[v];
+    }
+}
+
 }  // namespace
 
 size_t limb_btiles_bytes(int64_t K, int64_t N) {
@@ -687,6 +791,13 @@ hipError_t limb_btiles(const View& B, int64_t K, int64_t N, int8_t* out, hipStre
     job.out[0] = out;
     const int64_t threads = rows_pad * nkb * 4;
     hipLaunchKernelGGL(k_to_tiles, dim3((unsigned)((threads + 255) / 256), 1), dim3(256), 0, st, job, K, nkb, rows_pad);
+    return hipGetLastError();
+}
+
+hipError_t hpair_sparse(const u64* X, const u64* Y, int64_t npairs, u64* part, int groups, hipStream_t st) {
+    const int64_t nblocks = (npairs + 31) / 32;
+    if (groups <= 0 || nblocks <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_hpair, dim3((unsigned)groups), dim3(NT), 0, st, X, Y, npairs, nblocks, part);
     return hipGetLastError();
 }
 

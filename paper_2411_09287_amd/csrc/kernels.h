@@ -34,12 +34,13 @@ void launch_trunc_shift(int64_t n, int t, const u64* zm, const u64* rzm, const u
 void launch_mult(int64_t n, const Keys& k, u32 op, const u64* am, const u64* a1, const u64* a2,
                  const u64* bm, const u64* b1, const u64* b2, Inj g2inj, u64* cm, u64* c1, u64* c2,
                  u64* msg_g2, u64* msg_m1, u64* msg_m2, hipStream_t s);
-// Output rows of ld >= KH KW C words: columns KH KW C .. ld-1 are written as 0.
+// Output rows of ld >= KH KW C words: columns KH KW C .. ld-1 are written as 0.  Output
+// (oh, ow) reads input (stride oh + kh - pad, stride ow + kw - pad).
 void launch_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int pad, int64_t ld, u64* out,
-                   hipStream_t s);
+                   hipStream_t s, int stride = 1);
 // The same for the three share planes in one launch.
 void launch_im2col3(const u64* const x[3], int B, int H, int W, int C, int KH, int KW, int pad, int64_t ld,
-                    u64* const out[3], hipStream_t s);
+                    u64* const out[3], hipStream_t s, int stride = 1);
 void launch_sumpool2(const u64* x, int B, int H, int W, int C, u64* out, hipStream_t s);
 void launch_rec_check(int64_t n, const u64* r1, Inj r1inj, int* flag, hipStream_t s);
 void launch_rec_open(int64_t n, const u64* m, const u64* r1, const u64* r2, const int* flag, u64* out,
@@ -69,6 +70,10 @@ struct PolyEvlArgs {
     int prefolded;         // C holds the three reduced sums (3*64 words) instead of 64x64 products
 };
 void launch_polyevl_finish(const PolyEvlArgs& a, hipStream_t s);
+// For nc planes of n rows (rows 2i, 2i+1 -> row i): F = f0 + x (f1 - f0).
+void launch_at_x(const u64* XY, int nc, int64_t n, u64* F, hipStream_t s);
+// [Mat(1 - z); Mat(z)] (128 x 64 words) from Mat(z) (64 x 64).
+void launch_mat_pair(const u64* Wz, u64* out, hipStream_t s);
 // For nc planes of n rows (rows 2i, 2i+1 -> row i): D = f1 - f0 and F = f0 + x D.
 void launch_at_x_diff(const u64* XY, int nc, int64_t n, u64* F, u64* D, hipStream_t s);
 struct RoundArgs {

@@ -232,8 +232,8 @@ __global__ void k_mult(int64_t n, Keys k, u32 op, const u64* am, const u64* a1, 
 }
 
 // rows (b, oh, ow), columns (kh, kw, c) of a stride-1 convolution with zero padding
-__global__ void k_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int pad, int OH, int OW,
-                         int64_t ld, u64* out) {
+__global__ void k_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int pad, int stride, int OH,
+                         int OW, int64_t ld, u64* out) {
     const int64_t K = (int64_t)KH * KW * C;
     const int64_t total = (int64_t)B * OH * OW * ld;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -250,7 +250,7 @@ __global__ void k_im2col(const u64* x, int B, int H, int W, int C, int KH, int K
     const int ow = (int)(row % OW);
     const int oh = (int)((row / OW) % OH);
     const int b = (int)(row / ((int64_t)OW * OH));
-    const int ih = oh + kh - pad, iw = ow + kw - pad;
+    const int ih = stride * oh + kh - pad, iw = stride * ow + kw - pad;
     u64 v = 0;
     if (ih >= 0 && ih < H && iw >= 0 && iw < W) v = x[(((int64_t)b * H + ih) * W + iw) * C + c];
     out[idx] = v;
@@ -278,7 +278,7 @@ __device__ __forceinline__ u32 fdiv(u32 n, const FastDiv& f) { return (u32)(((u6
 struct Im2colArgs {
     const u64* x[3];
     u64* out[3];
-    int H, W, C, KW, OH, OW, pad;
+    int H, W, C, KW, OH, OW, pad, stride;
     u32 K, ld, total;      // words per output row (KH KW C) and the row stride ld >= K
                            // (columns K .. ld-1 are zero); V-word groups in a plane
     FastDiv fLD, fC, fKW, fOW, fOH;
@@ -303,7 +303,7 @@ __global__ void k_im2col3(Im2colArgs a) {
     const u32 kh = fdiv(seg, a.fKW), kw = seg - kh * a.KW;
     const u32 t = fdiv(row, a.fOW), ow = row - t * a.OW;
     const u32 b = fdiv(t, a.fOH), oh = t - b * a.OH;
-    const int ih = (int)oh + (int)kh - a.pad, iw = (int)ow + (int)kw - a.pad;
+    const int ih = a.stride * (int)oh + (int)kh - a.pad, iw = a.stride * (int)ow + (int)kw - a.pad;
     const bool in = ih >= 0 && ih < a.H && iw >= 0 && iw < a.W;
     const int64_t src = (((int64_t)b * a.H + ih) * a.W + iw) * a.C + c;
     if (V == 2) {
@@ -580,6 +580,35 @@ __global__ void k_at_x_diff(const u64* XY, int64_t n, u64* F, u64* D) {
     const int64_t o = ((int64_t)c * (n / 2) + i) * 64 + k;
     D[o] = d;
     F[o] = a + xmul_coeff(dsh, k);
+}
+
+// The line through (0, f(0)) and (1, f(1)) at the node x for every pair of every plane c:
+// F = f(0) + x (f(1) - f(0)); one wave per (plane, pair), four per block, lanes =
+// coefficients, x (.) as a shift across the lanes with x^64 = -(x^4 + x^3 + x + 1).
+__global__ __launch_bounds__(256) void k_at_x(const u64* XY, int64_t n, int64_t items, u64* F) {
+    const int k = threadIdx.x & 63;
+    const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item >= items) return;
+    const int64_t half = n / 2;
+    const int64_t c = item / half, i = item - c * half;
+    const u64* f0 = XY + (c * n + 2 * i) * 64;
+    const u64 a = f0[k], d = f0[64 + k] - a;
+    const u64 top = __shfl(d, 63, 64);
+    u64 xd = __shfl_up(d, 1, 64);
+    if (k == 0) xd = 0;
+#pragma unroll
+    for (int q = 0; q < NTAPS; ++q)
+        if (k == tap(q)) xd -= top;
+    F[item * 64 + k] = a + xd;
+}
+
+// [Mat(1 - z); Mat(z)] (128 x 64) from Mat(z): the fold f(z) = f(0) (1 - z) + f(1) z of a
+// stored pair (f(0), f(1)) is the pair's 128 words times this matrix.
+__global__ void k_mat_pair(const u64* Wz, u64* out) {
+    const int j = blockIdx.x, k = threadIdx.x;
+    const u64 w = Wz[j * 64 + k];
+    out[j * 64 + k] = (j == k ? 1 : 0) - w;
+    out[(64 + j) * 64 + k] = w;
 }
 
 // Ring product of per-wave operands: wave w multiplies a[w] by b[w] (64 lanes = coefficients).
@@ -1227,24 +1256,24 @@ void launch_mult(int64_t n, const Keys& k, u32 op, const u64* am, const u64* a1,
                        g2inj, cm, c1, c2, msg_g2, msg_m1, msg_m2);
 }
 void launch_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int pad, int64_t ld, u64* out,
-                   hipStream_t s) {
-    const int OH = H + 2 * pad - KH + 1, OW = W + 2 * pad - KW + 1;
+                   hipStream_t s, int stride) {
+    const int OH = (H + 2 * pad - KH) / stride + 1, OW = (W + 2 * pad - KW) / stride + 1;
     const int64_t total = (int64_t)B * OH * OW * ld;
     if (total <= 0) return;
-    hipLaunchKernelGGL(k_im2col, dim3(nblocks(total, TPB)), dim3(TPB), 0, s, x, B, H, W, C, KH, KW, pad, OH, OW,
-                       ld, out);
+    hipLaunchKernelGGL(k_im2col, dim3(nblocks(total, TPB)), dim3(TPB), 0, s, x, B, H, W, C, KH, KW, pad, stride, OH,
+                       OW, ld, out);
 }
 
 void launch_im2col3(const u64* const x[3], int B, int H, int W, int C, int KH, int KW, int pad, int64_t ld,
-                    u64* const out[3], hipStream_t s) {
-    const int OH = H + 2 * pad - KH + 1, OW = W + 2 * pad - KW + 1;
+                    u64* const out[3], hipStream_t s, int stride) {
+    const int OH = (H + 2 * pad - KH) / stride + 1, OW = (W + 2 * pad - KW) / stride + 1;
     const int64_t K = (int64_t)KH * KW * C;
     const int64_t total = (int64_t)B * OH * OW * ld;
     if (total <= 0 || ld < K) return;
     bool aligned = true;
     for (int p = 0; p < 3; ++p) aligned = aligned && (((uintptr_t)x[p] | (uintptr_t)out[p]) & 15) == 0;
     if (total >= ((int64_t)1 << 31)) {       // beyond 32-bit word indices: one word per thread
-        for (int p = 0; p < 3; ++p) launch_im2col(x[p], B, H, W, C, KH, KW, pad, ld, out[p], s);
+        for (int p = 0; p < 3; ++p) launch_im2col(x[p], B, H, W, C, KH, KW, pad, ld, out[p], s, stride);
         return;
     }
     Im2colArgs a{};
@@ -1252,7 +1281,7 @@ void launch_im2col3(const u64* const x[3], int B, int H, int W, int C, int KH, i
         a.x[p] = x[p];
         a.out[p] = out[p];
     }
-    a.H = H; a.W = W; a.C = C; a.KW = KW; a.OH = OH; a.OW = OW; a.pad = pad;
+    a.H = H; a.W = W; a.C = C; a.KW = KW; a.OH = OH; a.OW = OW; a.pad = pad; a.stride = stride;
     a.K = (u32)K;
     a.ld = (u32)ld;
     a.fLD = make_fastdiv((u32)ld); a.fC = make_fastdiv((u32)C); a.fKW = make_fastdiv((u32)KW);
@@ -1300,6 +1329,14 @@ void launch_polyevl_finish(const PolyEvlArgs& a, hipStream_t s) {
 void launch_at_x_diff(const u64* XY, int nc, int64_t n, u64* F, u64* D, hipStream_t s) {
     if (n < 2) return;
     hipLaunchKernelGGL(k_at_x_diff, dim3((unsigned)(n / 2), nc), dim3(64), 0, s, XY, n, F, D);
+}
+void launch_at_x(const u64* XY, int nc, int64_t n, u64* F, hipStream_t s) {
+    if (n < 2) return;
+    const int64_t items = (int64_t)nc * (n / 2);
+    hipLaunchKernelGGL(k_at_x, dim3(nblocks(items, 4)), dim3(256), 0, s, XY, n, items, F);
+}
+void launch_mat_pair(const u64* Wz, u64* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_mat_pair, dim3(64), dim3(64), 0, s, Wz, out);
 }
 void launch_round_finish(const RoundArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_round_finish, dim3(1), dim3(256), 0, s, a);

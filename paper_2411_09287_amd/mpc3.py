@@ -15,10 +15,11 @@ LIB_PATH = os.path.join(_HERE, "libmpc3.so")
 
 OK, E_ARG, E_SHAPE, E_NOMEM, E_ABORTED, E_UNVERIFIED, E_HIP, E_STATE, E_LIMIT = 0, -1, -2, -3, -4, -5, -6, -7, -8
 VARIANT_U64, VARIANT_LIMB_I8, VARIANT_AUTO = 0, 1, 2
+R_NETWORK = -2
 PH_OFFLINE, PH_ONLINE, PH_VERIFY_OFFLINE, PH_VERIFY_ONLINE = 0, 1, 2, 3
-VERIFY_INNER, VERIFY_TRUNC, VERIFY_MULT, VERIFY_ALL = 1, 2, 4, 7
+VERIFY_INNER, VERIFY_TRUNC, VERIFY_MULT, VERIFY_NONLINEAR, VERIFY_ALL = 1, 2, 4, 8, 15
 (SITE_INNER_GAMMA2, SITE_INNER_M1, SITE_TRUNC_GAMMA2, SITE_TRUNC_M1, SITE_MULT_GAMMA2, SITE_VER_H0_M1,
- SITE_VER_H2_GAMMA2, SITE_VER_DELTA_M1, SITE_REC_R1) = range(1, 10)
+ SITE_VER_H2_GAMMA2, SITE_VER_DELTA_M1, SITE_REC_R1, SITE_AND_GAMMA2, SITE_EDA_W_M1) = range(1, 12)
 MSG_GAMMA2, MSG_M1, MSG_M2 = 0, 1, 2
 (LOG_R, LOG_Z, LOG_ZETA, LOG_H0_M1, LOG_H0_M2, LOG_H0_G2, LOG_H2_M1, LOG_H2_M2, LOG_H2_G2, LOG_DELTA,
  LOG_DELTA_M1, LOG_DELTA_M2, LOG_DELTA_G2) = range(13)
@@ -49,6 +50,8 @@ SIGNATURES = {
     "mpc3_set_chunk": (_I, [_P, _I64]),
     "mpc3_autotune": (_I, [_P, _I64, _I64, _I64, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double),
                            ctypes.POINTER(ctypes.c_double)]),
+    "mpc3_set_verify_chunks": (_I, [_P, _I64, _I64]),
+    "mpc3_set_network": (_I, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "mpc3_keep_messages": (_I, [_P, _I]),
     "mpc3_encode": (_I, [_P, _P, _I64, _P]),
     "mpc3_decode": (_I, [_P, _P, _I64, _P]),
@@ -59,8 +62,13 @@ SIGNATURES = {
     "mpc3_inner_static": (_I, [_P, ctypes.POINTER(Share), ctypes.POINTER(Share), ctypes.POINTER(TruncPair),
                                ctypes.POINTER(Share)]),
     "mpc3_im2col": (_I, [_P, ctypes.POINTER(Share), _I, _I, _I, _I, _I, _I, _I, ctypes.POINTER(Share)]),
+    "mpc3_im2col_strided": (_I, [_P, ctypes.POINTER(Share), _I, _I, _I, _I, _I, _I, _I, _I, ctypes.POINTER(Share)]),
     "mpc3_sumpool2": (_I, [_P, ctypes.POINTER(Share), _I, _I, _I, _I, ctypes.POINTER(Share)]),
     "mpc3_mult": (_I, [_P, ctypes.POINTER(Share), ctypes.POINTER(Share), ctypes.POINTER(Share)]),
+    "mpc3_edabits": (_I, [_P, _I64, ctypes.POINTER(Share), ctypes.POINTER(Share)]),
+    "mpc3_dabits": (_I, [_P, _I64, ctypes.POINTER(Share), ctypes.POINTER(Share)]),
+    "mpc3_relu": (_I, [_P, ctypes.POINTER(Share), ctypes.POINTER(Share)]),
+    "mpc3_maxpool2": (_I, [_P, ctypes.POINTER(Share), _I, _I, _I, _I, ctypes.POINTER(Share)]),
     "mpc3_trunc": (_I, [_P, ctypes.POINTER(TruncPair), ctypes.POINTER(Share), ctypes.POINTER(Share)]),
     "mpc3_verify": (_I, [_P, _I, _I, ctypes.POINTER(_I)]),
     "mpc3_reconstruct": (_I, [_P, ctypes.POINTER(Share), _I, _P]),
@@ -181,7 +189,7 @@ class Context:
                                   ctypes.byref(h)), "mpc3_ctx_create")
         self.h = h
         # operands the context still points at, per kind of pending product
-        self._keep = {VERIFY_INNER: [], VERIFY_TRUNC: [], VERIFY_MULT: []}
+        self._keep = {VERIFY_INNER: [], VERIFY_TRUNC: [], VERIFY_MULT: [], VERIFY_NONLINEAR: []}
 
     def close(self):
         if self.h:
@@ -206,6 +214,12 @@ class Context:
 
     def set_chunk(self, t):
         _ck(lib().mpc3_set_chunk(self.h, t), "mpc3_set_chunk", self.h)
+
+    def set_verify_chunks(self, mult_triples=0, edabit_rows=0):
+        _ck(lib().mpc3_set_verify_chunks(self.h, mult_triples, edabit_rows), "mpc3_set_verify_chunks", self.h)
+
+    def set_network(self, rtt_ms, mbit_per_s, gpu_round_ms=0.1):
+        _ck(lib().mpc3_set_network(self.h, rtt_ms, mbit_per_s, gpu_round_ms), "mpc3_set_network", self.h)
 
     def keep_messages(self, on=True):
         _ck(lib().mpc3_keep_messages(self.h, int(on)), "mpc3_keep_messages", self.h)
@@ -256,12 +270,17 @@ class Context:
         self._keep[VERIFY_INNER].append((X, W, Z))
         return Z
 
-    def im2col(self, x, B, H, W, C, KH, KW, pad, ld=None):
+    def im2col(self, x, B, H, W, C, KH, KW, pad, ld=None, stride=1):
         """ld (>= KH KW C): row width of the result, the extra columns zero."""
-        OH, OW = H + 2 * pad - KH + 1, W + 2 * pad - KW + 1
+        OH, OW = (H + 2 * pad - KH) // stride + 1, (W + 2 * pad - KW) // stride + 1
         cols = DShare.empty(B * OH * OW, ld or KH * KW * C, self.device)
         xs, cs = x.c(), cols.c()
-        _ck(lib().mpc3_im2col(self.h, ctypes.byref(xs), B, H, W, C, KH, KW, pad, ctypes.byref(cs)), "mpc3_im2col", self.h)
+        if stride == 1:
+            _ck(lib().mpc3_im2col(self.h, ctypes.byref(xs), B, H, W, C, KH, KW, pad, ctypes.byref(cs)), "mpc3_im2col",
+                self.h)
+        else:
+            _ck(lib().mpc3_im2col_strided(self.h, ctypes.byref(xs), B, H, W, C, KH, KW, pad, stride, ctypes.byref(cs)),
+                "mpc3_im2col_strided", self.h)
         return cols
 
     def sumpool2(self, x, B, H, W, C):
@@ -276,6 +295,33 @@ class Context:
         _ck(lib().mpc3_mult(self.h, ctypes.byref(sa), ctypes.byref(sb), ctypes.byref(sc)), "mpc3_mult", self.h)
         self._keep[VERIFY_MULT].append((a, b, c))
         return c
+
+    def edabits(self, n):
+        """(arith, bits): <r>^l and <r[0..63]>^1 of n random edaBits (n words per plane each)."""
+        a, b = DShare.empty(n, 1, self.device), DShare.empty(n, 1, self.device)
+        sa, sb = a.c(), b.c()
+        _ck(lib().mpc3_edabits(self.h, n, ctypes.byref(sa), ctypes.byref(sb)), "mpc3_edabits", self.h)
+        return a, b
+
+    def dabits(self, n):
+        a, b = DShare.empty(n, 1, self.device), DShare.empty(n, 1, self.device)
+        sa, sb = a.c(), b.c()
+        _ck(lib().mpc3_dabits(self.h, n, ctypes.byref(sa), ctypes.byref(sb)), "mpc3_dabits", self.h)
+        return a, b
+
+    def relu(self, x):
+        out = DShare.empty(x.rows, x.cols, self.device)
+        xs, os_ = x.c(), out.c()
+        _ck(lib().mpc3_relu(self.h, ctypes.byref(xs), ctypes.byref(os_)), "mpc3_relu", self.h)
+        self._keep[VERIFY_MULT].append((x, out))
+        return out
+
+    def maxpool2(self, x, B, H, W, C):
+        out = DShare.empty(B, (H // 2) * (W // 2) * C, self.device)
+        xs, os_ = x.c(), out.c()
+        _ck(lib().mpc3_maxpool2(self.h, ctypes.byref(xs), B, H, W, C, ctypes.byref(os_)), "mpc3_maxpool2", self.h)
+        self._keep[VERIFY_MULT].append((x, out))
+        return out
 
     def trunc(self, pair, Z):
         out = DShare.empty(Z.rows, Z.cols, self.device)

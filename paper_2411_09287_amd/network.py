@@ -1,10 +1,13 @@
-"""Secure evaluation of a chained linear network through the C ABI.
+"""Secure evaluation of a chained network through the C ABI.
 
-The linear layers of the MLP, LeNet-shaped and VGG-shaped networks are chained:
-convolution (im2col) or dense product with Pi_Inner, Pi_Trunc by the fixed-point
-precision, and 2x2 average pooling between stages.  Average pooling is a sum pool of the
-shares (a local linear map) with the factor 1/4 folded into the next layer's plaintext
-weights before encoding.  ReLU / max-pool are non-linear layers outside this path.
+The layers of the MLP, LeNet-shaped and VGG-shaped networks are chained: convolution
+(im2col) or dense product with Pi_Inner, Pi_Trunc by the fixed-point precision, then
+
+  * nonlinear=True: ReLU after every layer but the last and 2x2 max pooling between
+    stages (Sec. 4.3: edaBits, bit extraction, B2A, Pi_Mult);
+  * nonlinear=False (the linear path alone): no activation, and 2x2 average pooling as a
+    sum pool of the shares (a local linear map) with the factor 1/4 folded into the next
+    layer's plaintext weights before encoding.
 
 Weights are encoded and shared once; every call of `forward` shares a new input batch,
 evaluates the layers and leaves the products pending for `verify`.
@@ -23,8 +26,8 @@ def plan(name):
     for i, layer in enumerate(layers):
         d = {"layer": layer, "pool_after": False}
         if layer[0] == "conv":
-            _, kh, kw, cin, cout, pad, (h, w) = layer
-            oh, ow = h + 2 * pad - kh + 1, w + 2 * pad - kw + 1
+            _, kh, kw, cin, cout, pad, (h, w) = layer[:7]
+            oh, ow = workloads.conv_out_hw(layer)
             d["out_hw"] = (oh, ow)
             # contraction width of the product: kh kw cin zero-padded to whole 32-deep
             # k-blocks of the matrix-core kernel (zero columns of the lowered input against
@@ -40,15 +43,15 @@ def plan(name):
     return out
 
 
-def float_weights(name, seed=200):
-    """Plaintext weights (K x N), with 1/4 folded in after every average pool."""
+def float_weights(name, seed=200, nonlinear=False):
+    """Plaintext weights (K x N); on the linear path 1/4 is folded in after every average pool."""
     ws = []
     pooled = False
     for i, d in enumerate(plan(name)):
         layer = d["layer"]
         M, K, N = workloads.layer_gemm_shape(layer, 1)
         w = workloads.layer_weight(layer, seed + i).reshape(K, N)
-        if pooled:
+        if pooled and not nonlinear:
             w = w / 4.0
         ws.append(w)
         pooled = d["pool_after"]
@@ -58,12 +61,13 @@ def float_weights(name, seed=200):
 class Network:
     """Shared weights of one model on one context."""
 
-    def __init__(self, ctx, name, seed=200):
+    def __init__(self, ctx, name, seed=200, nonlinear=False):
         self.ctx = ctx
         self.name = name
+        self.nonlinear = nonlinear
         self.plan = plan(name)
         self.frac = ctx.frac_bits
-        self.w_float = float_weights(name, seed)
+        self.w_float = float_weights(name, seed, nonlinear)
         self.weights = []
         for d, w in zip(self.plan, self.w_float):
             if d.get("kpad", w.shape[0]) > w.shape[0]:
@@ -87,8 +91,8 @@ class Network:
         for i, d in enumerate(self.plan):
             layer = d["layer"]
             if layer[0] == "conv":
-                _, kh, kw, cin, cout, pad, (hh, ww) = layer
-                X = ctx.im2col(h, batch, hh, ww, cin, kh, kw, pad, d["kpad"])
+                _, kh, kw, cin, cout, pad, (hh, ww) = layer[:7]
+                X = ctx.im2col(h, batch, hh, ww, cin, kh, kw, pad, d["kpad"], stride=workloads.conv_stride(layer))
             else:
                 X = h if h.cols == layer[1] else mpc3.DShare(*[t.reshape(batch, -1) for t in (h.m, h.r1, h.r2)])
             M, N = X.rows, self.weights[i].cols
@@ -98,9 +102,11 @@ class Network:
                 Y = ctx.trunc(pair, Z)
             else:
                 Y = ctx.inner(X, self.weights[i])
+            if self.nonlinear and i + 1 < len(self.plan):
+                Y = ctx.relu(Y)
             if d["pool_after"]:
                 oh, ow = d["out_hw"]
-                Y = ctx.sumpool2(mpc3.DShare(*[t.reshape(batch, -1) for t in (Y.m, Y.r1, Y.r2)]),
-                                 batch, oh, ow, layer[4])
+                pool = ctx.maxpool2 if self.nonlinear else ctx.sumpool2
+                Y = pool(mpc3.DShare(*[t.reshape(batch, -1) for t in (Y.m, Y.r1, Y.r2)]), batch, oh, ow, layer[4])
             h = Y if layer[0] == "fc" else mpc3.DShare(*[t.reshape(batch, -1) for t in (Y.m, Y.r1, Y.r2)])
         return h

@@ -39,6 +39,21 @@ MODELS = {
                        ("conv", 3, 3, 64, 128, 1, (16, 16)), ("conv", 3, 3, 128, 128, 1, (16, 16)),
                        ("conv", 3, 3, 128, 256, 1, (8, 8)), ("conv", 3, 3, 256, 256, 1, (8, 8)),
                        ("fc", 4096, 256), ("fc", 256, 10)]},
+    "snn": {"batch": 30, "input": (28, 28, 1),
+            "layers": [("conv", 5, 5, 1, 5, 1, (28, 28), 2), ("fc", 845, 10)]},
+    "lenet5": {"batch": 30, "input": (32, 32, 1),
+               "layers": [("conv", 5, 5, 1, 6, 0, (32, 32)), ("conv", 5, 5, 6, 16, 0, (14, 14)),
+                          ("fc", 400, 120), ("fc", 120, 84), ("fc", 84, 10)]},
+    "vgg16": {"batch": 30, "input": (64, 64, 3),
+              "layers": [("conv", 3, 3, 3, 64, 1, (64, 64)), ("conv", 3, 3, 64, 64, 1, (64, 64)),
+                         ("conv", 3, 3, 64, 128, 1, (32, 32)), ("conv", 3, 3, 128, 128, 1, (32, 32)),
+                         ("conv", 3, 3, 128, 256, 1, (16, 16)), ("conv", 3, 3, 256, 256, 1, (16, 16)),
+                         ("conv", 3, 3, 256, 256, 1, (16, 16)),
+                         ("conv", 3, 3, 256, 512, 1, (8, 8)), ("conv", 3, 3, 512, 512, 1, (8, 8)),
+                         ("conv", 3, 3, 512, 512, 1, (8, 8)),
+                         ("conv", 3, 3, 512, 512, 1, (4, 4)), ("conv", 3, 3, 512, 512, 1, (4, 4)),
+                         ("conv", 3, 3, 512, 512, 1, (4, 4)),
+                         ("fc", 2048, 512), ("fc", 512, 512), ("fc", 512, 200)]},
 }
 
 CONFIG_MODEL = {1: "matmul", 2: "mlp", 3: "lenet", 4: "vgg"}
@@ -48,9 +63,20 @@ def layer_gemm_shape(layer, batch):
     """(M, K, N) of the layer's matrix product (conv via im2col: rows b,oh,ow; cols kh,kw,cin)."""
     if layer[0] == "fc":
         return batch, layer[1], layer[2]
-    _, kh, kw, cin, cout, pad, (h, w) = layer
-    oh, ow = h + 2 * pad - kh + 1, w + 2 * pad - kw + 1
+    oh, ow = conv_out_hw(layer)
+    _, kh, kw, cin, cout = layer[:5]
     return batch * oh * ow, kh * kw * cin, cout
+
+
+def conv_stride(layer):
+    return layer[7] if len(layer) > 7 else 1
+
+
+def conv_out_hw(layer):
+    """Output image size of a convolution layer."""
+    _, kh, kw, cin, cout, pad, (h, w) = layer[:7]
+    s = conv_stride(layer)
+    return (h + 2 * pad - kh) // s + 1, (w + 2 * pad - kw) // s + 1
 
 
 def model_shapes(name, batch=None):

@@ -36,32 +36,42 @@ def test_sumpool_parity(B, H, W, C):
         assert np.array_equal(a.reshape(-1), b.reshape(-1))
 
 
-def fp64_forward(name, x):
-    """FP64 model on the decoded fixed-point input and weights (conv as im2col products)."""
+def fp64_forward(name, x, nonlinear=False):
+    """FP64 model on the decoded fixed-point input and weights (conv as im2col products;
+    with nonlinear, ReLU after every layer but the last and 2x2 max pooling, else 2x2 sum
+    pooling)."""
     from oracle.layers import im2col
     frac = workloads.FRAC_BITS
-    ws = [o_decode(o_encode(w, frac), frac) for w in network.float_weights(name)]
+    ws = [o_decode(o_encode(w, frac), frac) for w in network.float_weights(name, nonlinear=nonlinear)]
     h = o_decode(o_encode(x, frac), frac)
     B = x.shape[0]
-    for d, w in zip(network.plan(name), ws):
+    plan = network.plan(name)
+    for li, (d, w) in enumerate(zip(plan, ws)):
         layer = d["layer"]
+        act = nonlinear and li + 1 < len(plan)
         if layer[0] == "conv":
-            _, kh, kw, cin, cout, pad, (hh, ww) = layer
-            # im2col on float planes through the integer routine's indexing (values as float)
+            _, kh, kw, cin, cout, pad, (hh, ww) = layer[:7]
+            st = workloads.conv_stride(layer)
+            # patches of the padded float input: output (oh, ow) reads (st oh + i - pad, st ow + j - pad)
             xi = h.reshape(B, hh, ww, cin)
             xp = np.zeros((B, hh + 2 * pad, ww + 2 * pad, cin))
             xp[:, pad:pad + hh, pad:pad + ww] = xi
-            oh, ow = hh + 2 * pad - kh + 1, ww + 2 * pad - kw + 1
+            oh, ow = workloads.conv_out_hw(layer)
             cols = np.zeros((B, oh, ow, kh, kw, cin))
             for i in range(kh):
                 for j in range(kw):
-                    cols[:, :, :, i, j] = xp[:, i:i + oh, j:j + ow]
+                    cols[:, :, :, i, j] = xp[:, i:i + st * (oh - 1) + 1:st, j:j + st * (ow - 1) + 1:st]
             y = cols.reshape(B * oh * ow, -1) @ w
+            if act:
+                y = np.maximum(y, 0.0)
             if d["pool_after"]:
-                y = y.reshape(B, oh // 2, 2, ow // 2, 2, cout).sum(axis=(2, 4))
+                y = y.reshape(B, oh // 2, 2, ow // 2, 2, cout)
+                y = y.max(axis=(2, 4)) if nonlinear else y.sum(axis=(2, 4))
             h = y.reshape(B, -1)
         else:
             h = h.reshape(B, -1) @ w
+            if act:
+                h = np.maximum(h, 0.0)
     del im2col
     return h
 
@@ -79,6 +89,81 @@ def test_network_matches_fp64_model(name, batch, variant):
     ref = fp64_forward(name, x)
     err = np.abs(y - ref).max() / np.abs(ref).max()
     assert err <= 2.0 ** -10, err
+
+
+@pytest.mark.parametrize("name,batch,variant", [("mlp", 16, 0), ("mlp", 16, 1), ("lenet", 2, 0), ("lenet", 2, 1),
+                                                ("snn", 4, 1)])
+def test_nonlinear_network_matches_fp64_model(name, batch, variant):
+    """ReLU and max pooling through edaBits (Sec. 4.3): every product verified (linear,
+    truncation gates, Pi_Mult and the Boolean triples), decoded logits within 2^-10
+    (normwise) of the FP64 model with ReLU and max pooling on the decoded inputs."""
+    c = mpc3.Context(workloads.master_seed(2))
+    c.set_variant(variant)
+    net = network.Network(c, name, nonlinear=True)
+    x = workloads.rng(33).random((batch,) + tuple(workloads.MODELS[name]["input"]))
+    out = net.forward(torch.from_numpy(x).cuda())
+    assert c.verify()
+    y = c.decode(c.reconstruct(out)).cpu().numpy().reshape(batch, -1)
+    ref = fp64_forward(name, x, nonlinear=True)
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    assert err <= 2.0 ** -10, err
+
+
+def oracle_forward_nonlinear(o, name, x, batch):
+    """The oracle through network.Network's calls with ReLU and max pooling."""
+    from oracle.layers import im2col_share
+    from oracle.protocol import Share
+
+    frac = workloads.FRAC_BITS
+    plan = network.plan(name)
+    weights = []
+    for d, w in zip(plan, network.float_weights(name, nonlinear=True)):
+        if d.get("kpad", w.shape[0]) > w.shape[0]:
+            w = np.concatenate([w, np.zeros((d["kpad"] - w.shape[0], w.shape[1]))])
+        weights.append(o.share(o_encode(w, frac)))
+    h = o.share(o_encode(x, frac).reshape(batch, -1))
+    for i, (d, W) in enumerate(zip(plan, weights)):
+        layer = d["layer"]
+        if layer[0] == "conv":
+            _, kh, kw, cin, cout, pad, (hh, ww) = layer[:7]
+            X = im2col_share(h.map(lambda a: a.reshape(batch, hh, ww, cin)), kh, kw, pad, workloads.conv_stride(layer))
+            extra = d["kpad"] - X.m.shape[1]
+            if extra:
+                X = X.map(lambda a: np.concatenate([a, np.zeros((a.shape[0], extra), dtype=np.uint64)], axis=1))
+        else:
+            X = h.map(lambda a: a.reshape(batch, -1))
+        pair = o.trunc_pair(X.m.shape[0] * W.m.shape[1], frac)
+        Y = o.trunc(pair, o.inner(X, W, pair))
+        if i + 1 < len(plan):
+            Y = o.relu(Y)
+        if d["pool_after"]:
+            oh, ow = d["out_hw"]
+            Y = o.maxpool2(Y.map(lambda a: a.reshape(batch, -1)), batch, oh, ow, layer[4])
+        h = Share(*[a.reshape(batch, -1) for a in Y.comps()])
+    return h
+
+
+@pytest.mark.parametrize("name,batch", [("mlp", 3), ("snn", 2), ("lenet5", 1)])
+def test_nonlinear_network_chain_matches_oracle(name, batch):
+    """A network with ReLU and max pooling against the oracle running the same calls on the
+    same seeds: the shared logits bit for bit and the counted communication; the GPU then
+    verifies every product and opens the oracle's logits.  (LeNet-5's small logits sit a few
+    units in the last place of f = 13, beyond a 2^-10 comparison with an FP64 model; the
+    bit-exact comparison covers it.)"""
+    seed = workloads.master_seed(8)
+    x = workloads.rng(34).random((batch,) + tuple(workloads.MODELS[name]["input"]))
+    o = Ctx(seed)
+    ho = oracle_forward_nonlinear(o, name, x, batch)
+    c = mpc3.Context(seed)
+    c.set_variant(mpc3.VARIANT_LIMB_I8)
+    net = network.Network(c, name, nonlinear=True)
+    hg = net.forward(torch.from_numpy(x).cuda())
+    for a, b in zip(hg.numpy(), ho.comps()):
+        assert np.array_equal(a.reshape(-1), b.reshape(-1))
+    bg, rg = c.comm_stats()
+    assert np.array_equal(bg, np.array(o.comm, dtype=np.uint64)) and rg == o.rounds
+    assert c.verify()
+    assert np.array_equal(mpc3.from_words(c.reconstruct(hg)).reshape(-1), ho.value().reshape(-1))
 
 
 def test_autotune_records_a_choice_and_auto_matches():
@@ -128,8 +213,8 @@ def oracle_forward(o, name, x, batch):
     for d, W in zip(plan, weights):
         layer = d["layer"]
         if layer[0] == "conv":
-            _, kh, kw, cin, cout, pad, (hh, ww) = layer
-            X = im2col_share(h.map(lambda a: a.reshape(batch, hh, ww, cin)), kh, kw, pad)
+            _, kh, kw, cin, cout, pad, (hh, ww) = layer[:7]
+            X = im2col_share(h.map(lambda a: a.reshape(batch, hh, ww, cin)), kh, kw, pad, workloads.conv_stride(layer))
             extra = d["kpad"] - X.m.shape[1]
             if extra:
                 X = X.map(lambda a: np.concatenate([a, np.zeros((a.shape[0], extra), dtype=np.uint64)], axis=1))
@@ -148,7 +233,7 @@ def oracle_forward(o, name, x, batch):
 _ORACLE_NET = {}
 
 
-@pytest.mark.parametrize("name,batch", [("lenet", 4), ("vgg", 2)])
+@pytest.mark.parametrize("name,batch", [("lenet", 4), ("vgg", 2), ("snn", 3)])
 @pytest.mark.parametrize("variant", [mpc3.VARIANT_U64, mpc3.VARIANT_LIMB_I8])
 def test_network_chain_matches_oracle(name, batch, variant):
     """The chained network against the oracle running the same calls on the same seeds:

@@ -443,3 +443,16 @@ def test_production_truncation_chunk_verifies(variant, inj):
     pg = c.trunc_pair(M * N, 13)
     c.trunc(pg, c.inner(Xg, Wg, pg))
     assert c.verify() == (inj is None)
+
+
+@pytest.mark.parametrize("B,H,W,C,KH,KW,pad,stride", [(2, 28, 28, 1, 5, 5, 1, 2), (1, 9, 7, 3, 3, 3, 1, 2),
+                                                      (2, 10, 11, 2, 3, 2, 0, 3)])
+def test_im2col_strided_parity(B, H, W, C, KH, KW, pad, stride):
+    g = np.random.default_rng(H * W + stride)
+    x0 = u64(g, B, H * W * C)
+    o = Ctx(SEED)
+    c = mpc3.Context(SEED)
+    xo, xg = o.share(x0), c.share(mpc3.to_words(x0))
+    co = im2col_share(xo.map(lambda a: a.reshape(B, H, W, C)), KH, KW, pad, stride)
+    cg = c.im2col(xg, B, H, W, C, KH, KW, pad, stride=stride)
+    assert same_share(cg, co)

@@ -1,5 +1,5 @@
 """Network cost model of the counted communication (host side) and the two sides of the R
-trade-off in the oracle's message counts (the paper's experiments, Sec. 6: more Pi_Reduce
+trade-off in the oracle's message counts (the paper's experiments, Sec. 5: more Pi_Reduce
 repetitions cost rounds and save final-check bytes)."""
 import numpy as np
 import pytest

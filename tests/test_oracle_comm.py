@@ -32,7 +32,7 @@ import numpy as np
 import pytest
 
 from oracle import protocol as P
-from paper_2411_09287_amd import workloads
+from paper_2411_09287_amd import netmodel, workloads
 
 
 def rounds_and_pad(n0, R):
@@ -44,18 +44,14 @@ def rounds_and_pad(n0, R):
 
 def closed_form(d, instances):
     """bytes[phase][src][dst] and rounds[phase] of the verification phases for instances
-    given as (R, n_R)."""
+    given as (R, n_R): the cost model's per-instance message list (netmodel, the formula
+    the library's choice of R prices) summed."""
     b = np.zeros((4, 3, 3), dtype=np.int64)
     rounds = [0, 0, 0, 0]
-    w = 8 * d
     for R, nR in instances:
-        b[P.VER_OFF][0][2] += w * (2 * R + nR + 1)
-        for s, t in ((0, 1), (0, 2), (1, 0)):
-            b[P.VER_ON][s][t] += w * (R + 2)
-        b[P.VER_ON][2][0] += 32 * (R + 2)
-        for s, t in ((1, 2), (2, 1)):
-            b[P.VER_ON][s][t] += w * (2 * R + nR + 1) + 32 * (R + 2)
-        rounds[P.VER_ON] += 2 * R + 4
+        bi, ri = netmodel.instance_messages(8 * d, R, nR)
+        b += np.array(bi, dtype=np.int64)
+        rounds = [x + y for x, y in zip(rounds, ri)]
     return b, rounds
 
 

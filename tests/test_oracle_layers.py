@@ -16,10 +16,10 @@ from oracle.layers import im2col, sumpool2
 MASK = (1 << 64) - 1
 
 
-def direct_conv(x, w, pad):
+def direct_conv(x, w, pad, stride=1):
     B, H, W, C = x.shape
     KH, KW, _, CO = w.shape
-    OH, OW = H + 2 * pad - KH + 1, W + 2 * pad - KW + 1
+    OH, OW = (H + 2 * pad - KH) // stride + 1, (W + 2 * pad - KW) // stride + 1
     out = np.zeros((B, OH, OW, CO), dtype=np.uint64)
     for b in range(B):
         for oh in range(OH):
@@ -28,7 +28,7 @@ def direct_conv(x, w, pad):
                     acc = 0
                     for kh in range(KH):
                         for kw in range(KW):
-                            ih, iw = oh + kh - pad, ow + kw - pad
+                            ih, iw = stride * oh + kh - pad, stride * ow + kw - pad
                             if not (0 <= ih < H and 0 <= iw < W):
                                 continue
                             for c in range(C):
@@ -53,6 +53,22 @@ def test_im2col_product_is_the_direct_convolution(B, H, W, C, KH, KW, CO, pad):
     assert cols.shape == (B * OH * OW, KH * KW * C)
     got = (cols @ w.reshape(KH * KW * C, CO)).reshape(B, OH, OW, CO)
     assert np.array_equal(got, direct_conv(x, w, pad))
+
+
+@pytest.mark.parametrize("B,H,W,C,KH,KW,CO,pad,stride", [
+    (1, 28, 28, 1, 5, 5, 2, 1, 2),     # the S-NN layer's geometry: 13 x 13 outputs
+    (2, 7, 6, 3, 3, 3, 2, 1, 2),
+    (1, 9, 8, 2, 3, 2, 1, 0, 3),
+])
+def test_strided_im2col_product_is_the_direct_convolution(B, H, W, C, KH, KW, CO, pad, stride):
+    g = np.random.default_rng(H * 10 + stride)
+    x = g.integers(0, 1 << 64, size=(B, H, W, C), dtype=np.uint64, endpoint=False)
+    w = g.integers(0, 1 << 64, size=(KH, KW, C, CO), dtype=np.uint64, endpoint=False)
+    cols = im2col(x, KH, KW, pad, stride)
+    OH, OW = (H + 2 * pad - KH) // stride + 1, (W + 2 * pad - KW) // stride + 1
+    assert cols.shape == (B * OH * OW, KH * KW * C)
+    got = (cols @ w.reshape(KH * KW * C, CO)).reshape(B, OH, OW, CO)
+    assert np.array_equal(got, direct_conv(x, w, pad, stride))
 
 
 def test_im2col_entries_by_index():
