@@ -94,8 +94,46 @@ def run_gpu(args):
         log(f"[bench] step {i + 1}/{args.steps} {times[-1] * 1e3:.2f} ms (truncation gates {vt * 1e3:.1f} ms)")
     ktime, launches, macs = ctx.profile_read()
     env = None if args.no_envelope else envelope(ctx)
+    u64_times = []
+    if args.variant == "limb" and not args.no_u64_step:
+        # the same step with every product on the vector ALU (u64 kernels); its truncation
+        # gates are verified afterwards with the matrix-core kernels (bit-identical results)
+        cu = mpc3.Context(workloads.master_seed(4))
+        cu.set_variant(mpc3.VARIANT_U64)
+        netu = network.Network(cu, name)
+        for i in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = netu.forward(x)
+            ok = cu.verify(-1, mpc3.VERIFY_INNER)
+            torch.cuda.synchronize()
+            if i >= args.warmup:
+                u64_times.append(time.perf_counter() - t0)
+            cu.set_variant(mpc3.VARIANT_LIMB_I8)
+            ok = cu.verify(-1, mpc3.VERIFY_TRUNC) and ok
+            cu.set_variant(mpc3.VARIANT_U64)
+            if not ok:
+                raise SystemExit("verification failed in an honest run")
+        log(f"[bench] u64 step {float(np.median(u64_times)) * 1e3:.2f} ms")
     return {"batch": batch, "shapes": shapes, "ops": ops, "ntrunc": ntrunc, "times": times, "vtimes": vtimes,
-            "ktime": ktime, "launches": launches, "macs": macs, "envelope": env}
+            "ktime": ktime, "launches": launches, "macs": macs, "envelope": env, "u64_times": u64_times}
+
+
+# Truncation-gate verification: the HBM bytes the method must move per truncation once its
+# gates are materialised after five symbolic rounds (4 elements per truncation and plane, two
+# planes of 64-word elements): the two planes written once (4096 B), and every later round
+# reading both planes and writing the folded halves, 3 n 512 B for n rows per plane, n =
+# 4, 2, 1, ... per truncation (sum 8): 12288 B.
+V2_BYTES_PER_TRUNCATION = 4096 + 12288
+HBM_PEAK_GBPS = 8000.0
+
+
+def v2_roofline(ntrunc, seconds):
+    achieved = V2_BYTES_PER_TRUNCATION * ntrunc / seconds / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+            "kernel": "truncation-gate verification, whole phase (algorithmic bytes of its materialised rounds: "
+                      f"{V2_BYTES_PER_TRUNCATION} B per truncation)"}
 
 
 def measured_traffic(variant):
@@ -465,6 +503,7 @@ def main():
     ap.add_argument("--nonlinear", action="store_true",
                     help="networks with ReLU and max pooling (edaBits); the step verifies every product")
     ap.add_argument("--no-envelope", action="store_true")
+    ap.add_argument("--no-u64-step", action="store_true", help="skip the u64-kernel run of the step")
     ap.add_argument("--hbm-copy", type=float, default=0.0, help="only time a device copy of this many GiB")
     ap.add_argument("--envelope-only", action="store_true", help="only time the envelope product")
     args = ap.parse_args()
@@ -556,8 +595,13 @@ def main():
                    "images_per_s_incl_truncation_gates": r["batch"] / (t + vt),
                    "envelope_product": r["envelope"]},
         "roofline": roof,
+        "v2_roofline": v2_roofline(r["ntrunc"], vt),
         "cpu_baseline": cpu,
     }
+    if r["u64_times"]:
+        tu = float(np.median(r["u64_times"]))
+        line["config"]["u64_step"] = {"ms_per_step": tu * 1e3, "GOPS": r["ops"] / tu / 1e9,
+                                      "limb_over_u64": tu / t}
     print(json.dumps(line))
 
 

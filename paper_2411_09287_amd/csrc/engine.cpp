@@ -564,10 +564,16 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
         // plane c, n = 2 half) with [Mat(1 - zeta); Mat(zeta)]
         u64* Wz = c->sc->words(4096);
         round_finish(c, v, sub, k, h0, h2, z, Wz);
-        u64* Wz2 = c->sc->words(2 * 4096);
-        launch_mat_pair(Wz, Wz2, s);
         u64* XYn = c->sc->words(np * half * 64);
-        run_gemm(c, plain(np * half, 64, 128, view(XY, 128, 1), view(Wz2, 64, 1), oview(XYn, 64, 1), false));
+        if (c->variant != MPC3_VARIANT_U64) {
+            int8_t* zt = (int8_t*)c->sc->alloc(limb_btiles_bytes(64, 64));
+            ck(limb_btiles(view(Wz, 64, 1), 64, 64, zt, s));
+            ck(fold_rows(XY, np * half, zt, XYn, s));
+        } else {
+            u64* Wz2 = c->sc->words(2 * 4096);
+            launch_mat_pair(Wz, Wz2, s);
+            run_gemm(c, plain(np * half, 64, 128, view(XY, 128, 1), view(Wz2, 64, 1), oview(XYn, 64, 1), false));
+        }
         XY = XYn;
         n = half;
     }

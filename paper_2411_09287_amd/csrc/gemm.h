@@ -67,6 +67,11 @@ hipError_t zero_words32(void* p, int64_t n, hipStream_t stream);
 // f(2i)) in GR(2^64, 64); the workgroups' partials add up to the products.
 hipError_t hpair_sparse(const u64* X, const u64* Y, int64_t npairs, u64* part, int groups, hipStream_t stream);
 
+// The fold of a Pi_Reduce round on the matrix cores: rows of 128 words are pairs (f(0),
+// f(1)) of 64-word GR(2^64, 64) elements; out row i (64 words) = f(0) + (f(1) - f(0)) Z,
+// ztiles the digit tiles (limb_btiles) of the 64 x 64 multiplication matrix Z of the point.
+hipError_t fold_rows(const u64* XY, int64_t rows, const int8_t* ztiles, u64* out, hipStream_t stream);
+
 // Bytes of partial sums one product may use before the split count is cut back.
 constexpr size_t PART_MAX = (size_t)1 << 30;
 

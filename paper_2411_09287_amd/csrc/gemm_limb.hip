@@ -698,12 +698,11 @@ __global__ __launch_bounds__(NT, 2) void k_hpair(const u64* X, const u64* Y, int
 #pragma unroll
     for (int v = 0; v < 16; ++v) c0[v] = c2[v] = 0;
     for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
-        // digits of 8 pairs per lane and operand: q[op][d] byte q = pair 8w + q
-        u64 q[HP_OPS][8];
-#pragma unroll
-        for (int o = 0; o < HP_OPS; ++o)
-#pragma unroll
-            for (int d = 0; d < 8; ++d) q[o][d] = 0;
+        // the 8 pairs of this wave per lane (= coefficient): f(2i) and F(i) of both sides,
+        // then their balanced digits as k-octets (to_digits: q[d] byte i = digit d of word i)
+        u64 wv[HP_OPS][8];
+        // every load of the block first (32 words per lane in flight), then the arithmetic
+        u64 ev[2][8], ov[2][8];
 #pragma unroll
         for (int pq = 0; pq < 8; ++pq) {
             const int64_t pr = blk * 32 + w * 8 + pq;
@@ -711,24 +710,27 @@ __global__ __launch_bounds__(NT, 2) void k_hpair(const u64* X, const u64* Y, int
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
                 const u64* P = side ? Y : X;
-                const u64 e = in ? P[(2 * pr) * 64 + lane] : 0;
-                const u64 o = in ? P[(2 * pr + 1) * 64 + lane] : 0;
-                const u64 d = o - e;
+                ev[side][pq] = in ? P[(2 * pr) * 64 + lane] : 0;
+                ov[side][pq] = in ? P[(2 * pr + 1) * 64 + lane] : 0;
+            }
+        }
+#pragma unroll
+        for (int pq = 0; pq < 8; ++pq) {
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const u64 e = ev[side][pq];
+                const u64 d = ov[side][pq] - e;
                 const u64 top = __shfl(d, 63, 64);
                 u64 xd = __shfl_up(d, 1, 64);
                 if (lane == 0) xd = 0;
-#pragma unroll
-                for (int tq = 0; tq < 4; ++tq)
-                    if (lane == (tq == 0 ? 0 : tq == 1 ? 1 : tq == 2 ? 3 : 4)) xd -= top;
-                const u64 f = e + xd;
-                const u64 be = (e + OFF) ^ OFF, bf = (f + OFF) ^ OFF;
-#pragma unroll
-                for (int dg = 0; dg < 8; ++dg) {
-                    q[2 * side][dg] |= ((be >> (8 * dg)) & 0xFFull) << (8 * pq);
-                    q[2 * side + 1][dg] |= ((bf >> (8 * dg)) & 0xFFull) << (8 * pq);
-                }
+                if (lane == 0 || lane == 1 || lane == 3 || lane == 4) xd -= top;
+                wv[2 * side][pq] = e;
+                wv[2 * side + 1][pq] = e + xd;
             }
         }
+        u64 q[HP_OPS][8];
+#pragma unroll
+        for (int o = 0; o < HP_OPS; ++o) to_digits(wv[o], q[o]);
         // transposed tile of each operand: plane d, k-octet w, row = coefficient lane
 #pragma unroll
         for (int o = 0; o < HP_OPS; ++o)
@@ -777,6 +779,82 @@ __global__ __launch_bounds__(NT, 2) void k_hpair(const u64* X, const u64* Y, int
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// The fold of a Pi_Reduce round: rows of 128 words are pairs (f(0), f(1)) of 64-word
+// elements (the planes stacked), and out = f(0) + (f(1) - f(0)) Z with Z the multiplication
+// matrix of the revealed point: f(0) + zeta (f(1) - f(0)) in GR(2^64, 64).  Z's digit tiles
+// (two 32-deep k-blocks, from limb_btiles) stay in LDS for the workgroup's whole run over
+// 64-row tiles; the A operand f(1) - f(0) is formed while loading and converted to digits,
+// and the epilogue adds f(0) (read again, from cache).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NT, 2) void k_fold(const u64* XY, int64_t rows, const int8_t* zt, u64* out) {
+    __shared__ __attribute__((aligned(16))) int8_t Bs[2 * TILE_BYTES];
+    __shared__ __attribute__((aligned(16))) int8_t As[2][8 * PLANE];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wy = w >> 1, wx = w & 1, r = lane & 31, hf = lane >> 5, kh = hf * 16;
+    const int arow = wy * 32 + r, brow = wx * 32 + r;
+    for (int i = t; i < 2 * TILE_BYTES / 16; i += NT) ((v4i*)Bs)[i] = ((const v4i*)zt)[i];
+    __syncthreads();
+    const int ra = t >> 2, oa = t & 3;            // A loader: row ra, k-octet oa of each k-block
+    const int bread = brow * KB + ((hf ^ swz(brow)) << 4);
+    const int64_t ntiles = (rows + 63) / 64;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * 64;
+        const u64* f = XY + min(r0 + ra, rows - 1) * 128;
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            u64 w8[8], q[8];
+            const int k0 = kb * 32 + oa * 8;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const ulonglong2 a0 = *(const ulonglong2*)(f + k0 + 2 * h);
+                const ulonglong2 a1 = *(const ulonglong2*)(f + 64 + k0 + 2 * h);
+                w8[2 * h] = a1.x - a0.x;
+                w8[2 * h + 1] = a1.y - a0.y;
+            }
+            to_digits(w8, q);
+#pragma unroll
+            for (int d = 0; d < 8; ++d) *(u64*)(As[kb] + d * PLANE + ra * KB + oa * 8) = q[d];
+        }
+        __syncthreads();
+        // f(0) of this lane's outputs, loaded while the matrix cores run
+        const int n = wx * 32 + (lane & 31);
+        u64 f0v[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int64_t m = r0 + wy * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            f0v[v] = XY[min(m, rows - 1) * 128 + n];
+        }
+        v16i acc[8];
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) acc[s2] = v16i{0};
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            v4i B[8];
+#pragma unroll
+            for (int d = 0; d < 8; ++d) B[d] = *(const v4i*)(Bs + kb * TILE_BYTES + d * PLANE + bread);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const v4i A = frag<true>(As[kb] + i * PLANE, arow, kh);
+#pragma unroll
+                for (int s2 = i; s2 < 8; ++s2)
+                    acc[s2] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[s2 - i], acc[s2], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int64_t m = r0 + wy * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            if (m >= rows) continue;
+            u64 val = 0;
+#pragma unroll
+            for (int s2 = 0; s2 < 8; ++s2) val += ((u64)(int64_t)acc[s2][v]) << (8 * s2);
+            out[m * 64 + n] = val + f0v[v];
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 size_t limb_btiles_bytes(int64_t K, int64_t N) {
@@ -798,6 +876,14 @@ hipError_t hpair_sparse(const u64* X, const u64* Y, int64_t npairs, u64* part, i
     const int64_t nblocks = (npairs + 31) / 32;
     if (groups <= 0 || nblocks <= 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_hpair, dim3((unsigned)groups), dim3(NT), 0, st, X, Y, npairs, nblocks, part);
+    return hipGetLastError();
+}
+
+hipError_t fold_rows(const u64* XY, int64_t rows, const int8_t* ztiles, u64* out, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    const int64_t ntiles = (rows + 63) / 64;
+    const int groups = (int)std::min<int64_t>(ntiles, 1024);
+    hipLaunchKernelGGL(k_fold, dim3((unsigned)groups), dim3(NT), 0, st, XY, rows, ztiles, out);
     return hipGetLastError();
 }
 
