@@ -269,6 +269,47 @@ int mpc3_maxpool2(mpc3_ctx* ctx, const mpc3_share_t* x, int B, int H, int W, int
  * No communication (Sec. 4.2). */
 int mpc3_trunc(mpc3_ctx* ctx, const mpc3_trunc_pair_t* p, const mpc3_share_t* Z, mpc3_share_t* out);
 
+/* --- Recorded forward passes (HIP graphs) -------------------------------------------
+ * The online layers of one network at one batch size are the same launches on the same
+ * buffers every time; only the operation ids behind the keystream tags (which make every
+ * mask and every truncation pair fresh) change.  The calls between mpc3_capture_begin and
+ * mpc3_capture_end are recorded into one HIP graph by stream capture on the context's
+ * stream instead of being run.  Only calls that neither allocate nor synchronise may be
+ * recorded: mpc3_encode, mpc3_decode, mpc3_share, mpc3_trunc_pair, mpc3_inner_static,
+ * mpc3_trunc, mpc3_im2col(_strided) and mpc3_sumpool2; every other call on the context
+ * returns MPC3_E_STATE while recording.  Recording leaves the context as it was (no
+ * operation id used, nothing counted, nothing pending); the context keeps the calls'
+ * effects instead: operation ids used, counted bytes and rounds, and products registered
+ * for verification.  The keystream kernels read one device word that is added to every
+ * recorded operation id; mpc3_graph_launch sets it (by a kernel on the stream, before the
+ * graph) to the distance from the recording's first id to the context's next id, so a
+ * replay draws exactly what the same calls made directly at that point would draw, and
+ * then applies the recorded effects under the shifted ids.  The graph holds kernel nodes
+ * only (no memset or copy nodes).  The pair structures the caller passed while recording
+ * keep the ids of the recording. */
+
+/* Start recording on the context's stream (MPC3_E_STATE when the context runs on the
+ * null stream, is recording already, keeps messages or has an injection armed). */
+int mpc3_capture_begin(mpc3_ctx* ctx);
+
+/* Stop recording; *graph_id (> 0) names the instantiated graph.  A call that failed while
+ * recording makes this return that failure's code (or MPC3_E_HIP if the stream capture
+ * was invalidated) with no graph created; the context is as before mpc3_capture_begin. */
+int mpc3_capture_end(mpc3_ctx* ctx, int* graph_id);
+
+/* Replay a graph on the context's stream with fresh operation ids (asynchronous, like the
+ * calls it recorded).  The buffers the recording named must be alive; the caller fills
+ * the recorded input buffers (on the same stream) before.  MPC3_E_STATE while products
+ * of this graph's previous replay are still pending (its buffers would be overwritten
+ * before they are verified) or while recording; MPC3_E_ARG for an unknown id. */
+int mpc3_graph_launch(mpc3_ctx* ctx, int graph_id);
+
+/* Node counts of a graph: kernel nodes and nodes of any other type (memset, copy, ...). */
+int mpc3_graph_nodes(mpc3_ctx* ctx, int graph_id, int64_t* kernel_nodes, int64_t* other_nodes);
+
+/* Free a graph (waits for the context's stream).  Graphs are also freed with the context. */
+int mpc3_graph_destroy(mpc3_ctx* ctx, int graph_id);
+
 /* Post-processing verification (Sec. 3) of the pending products selected by kinds
  * (MPC3_VERIFY_* mask).  The non-linear layers' edaBit inner products run as
  * Pi_BIVerify instances of 64-element gates (16384 per instance), their Boolean

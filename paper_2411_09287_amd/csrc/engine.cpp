@@ -115,6 +115,18 @@ struct Pending {
     mpc3_trunc_pair_t pair;
     uint32_t op;
     std::vector<Hold> hold;
+    int graph = 0;     // the recorded graph whose replay registered it (0: a direct call)
+};
+
+// A recorded sequence of calls: the instantiated graph and the effects its calls had on the
+// context while recording, with operation ids relative to the recording's first id.
+struct GraphRec {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    uint32_t op0 = 0, dop = 0;
+    uint64_t db[4][3][3] = {};
+    uint32_t dr[4] = {};
+    std::vector<Pending> pend;
 };
 
 constexpr int RMAX = 40;
@@ -178,6 +190,17 @@ struct mpc3_ctx {
     std::string err_call;
     // this device's copy of the static workspace (mpc3_inner_static)
     void* static_ws = nullptr;
+    // recording into HIP graphs: the device word added to the op id of every recorded
+    // keystream draw, and the context's state when the recording began
+    u32* op_off_dev = nullptr;
+    bool capturing = false;
+    int cap_err = 0;
+    uint32_t cap_op0 = 0;
+    uint64_t cap_bytes0[4][3][3] = {};
+    uint32_t cap_rounds0[4] = {};
+    size_t cap_pend0 = 0;
+    std::map<int, GraphRec> graphs;
+    int next_graph = 1;
     // launch timing of the Pi_Inner products
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -1201,11 +1224,20 @@ void verify_and(mpc3_ctx* c, const VerCtx& v, const Pending& it, int Rarg) {
     count_open(c, MPC3_PH_VERIFY_ONLINE, 8);
 }
 
-int guard(mpc3_ctx* c) {
+// capture_ok: the entry point may be recorded into a graph (it neither allocates nor
+// synchronises).  Any other call while recording fails, and so does the recording.
+int guard(mpc3_ctx* c, bool capture_ok = false) {
     if (!c) return MPC3_E_ARG;
     if (c->aborted) return MPC3_E_ABORTED;
+    if (c->capturing && !capture_ok) {
+        if (!c->cap_err) c->cap_err = MPC3_E_STATE;
+        return MPC3_E_STATE;
+    }
     return MPC3_OK;
 }
+
+// The op-offset word for the keystream kernels: read only by recorded launches.
+const u32* rec_off(const mpc3_ctx* c) { return c->capturing ? c->op_off_dev : nullptr; }
 
 // Runs an entry point's body; a failure becomes its return code and is recorded in the
 // context (when there is one) for mpc3_last_error.
@@ -1229,6 +1261,7 @@ int wrap(mpc3_ctx* c, const char* fn, F&& f) {
     } catch (const std::bad_alloc&) {
         code = MPC3_E_NOMEM;
     }
+    if (c && c->capturing && code != MPC3_OK && !c->cap_err) c->cap_err = code;
     if (c && code != MPC3_OK && code != MPC3_E_ABORTED) {
         c->err_code = code;
         c->err_hip = hip;
@@ -1280,7 +1313,7 @@ void inner_body(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W, const
     u64* C = (u64*)wsa(wss, (size_t)std::max<int64_t>(3 * n, 1) * 8);
     if (!G1 || !C) throw CodeError(MPC3_E_NOMEM);
     launch_inner_pre(n, c->keys, op, pair ? pair->rx.m : nullptr, pair ? pair->rx.r1 : nullptr,
-                     pair ? pair->rx.r2 : nullptr, Z->r1, Z->r2, G1, s);
+                     pair ? pair->rx.r2 : nullptr, Z->r1, Z->r2, G1, s, rec_off(c));
     GemmArgs ga{};
     ga.M = M; ga.N = N; ga.K = K; ga.batch = 1; ga.party = true; ga.accumulate = false;
     ga.ws_alloc = wsa;
@@ -1373,14 +1406,15 @@ int mpc3_ctx_create(const uint8_t master_seed[32], int d, int frac_bits, size_t 
         }
         host::Elem inv[3] = {host::gr_inv(X), host::gr_inv(omx), host::gr_inv(host::gr_mul(X, xm1))};
         void* p = nullptr;
-        if (hipMalloc(&p, 3 * 512) != hipSuccess) {
+        if (hipMalloc(&p, 3 * 512 + 256) != hipSuccess) {
             delete c;
             return (int)MPC3_E_NOMEM;
         }
         c->inv_dev = (u64*)p;
-        std::vector<uint64_t> hv(3 * 64);
+        c->op_off_dev = (u32*)((char*)p + 3 * 512);
+        std::vector<uint64_t> hv(3 * 64 + 32, 0);
         for (int i = 0; i < 3; ++i) memcpy(hv.data() + 64 * i, inv[i].data(), 512);
-        if (hipMemcpy(c->inv_dev, hv.data(), 3 * 512, hipMemcpyHostToDevice) != hipSuccess) {
+        if (hipMemcpy(c->inv_dev, hv.data(), 3 * 512 + 256, hipMemcpyHostToDevice) != hipSuccess) {
             (void)hipFree(p);
             delete c;
             return (int)MPC3_E_HIP;
@@ -1420,7 +1454,19 @@ int mpc3_ctx_create(const uint8_t master_seed[32], int d, int frac_bits, size_t 
 
 int mpc3_ctx_destroy(mpc3_ctx* c) {
     if (!c) return MPC3_E_ARG;
+    if (c->capturing) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(c->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        c->capturing = false;
+    }
     (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->graphs) {
+        (void)hipGraphExecDestroy(kv.second.ex);
+        (void)hipGraphDestroy(kv.second.g);
+    }
+    c->graphs.clear();
     c->scratch.release();
     for (int i = 0; i < mpc3_ctx::NV; ++i) {
         if (c->vs[i]) {
@@ -1531,7 +1577,7 @@ int mpc3_keep_messages(mpc3_ctx* c, int on) {
 }
 
 int mpc3_encode(mpc3_ctx* c, const double* x, int64_t n, uint64_t* out) {
-    int g = guard(c);
+    int g = guard(c, true);
     if (g) return g;
     if ((!x || !out) && n > 0) return MPC3_E_ARG;
     return wrap(c, __func__, [&] {
@@ -1552,7 +1598,7 @@ int mpc3_decode(mpc3_ctx* c, const uint64_t* v, int64_t n, double* out) {
 }
 
 int mpc3_share(mpc3_ctx* c, int owner, const uint64_t* x, mpc3_share_t* out) {
-    int g = guard(c);
+    int g = guard(c, true);
     if (g) return g;
     if (owner < 0 || owner > 2 || !valid(out) || (!x && out->rows * out->cols > 0)) return MPC3_E_ARG;
     return wrap(c, __func__, [&] {
@@ -1561,7 +1607,7 @@ int mpc3_share(mpc3_ctx* c, int owner, const uint64_t* x, mpc3_share_t* out) {
         const Key k1 = owner == 2 ? c->keys.kall : c->keys.k01;
         const Key k2 = owner == 1 ? c->keys.kall : c->keys.k02;
         launch_share(x, n, k1, make_tag(op, P_SHARE_R, 1, 0), k2, make_tag(op, P_SHARE_R, 2, 0), out->m, out->r1,
-                     out->r2, c->stream);
+                     out->r2, c->stream, rec_off(c));
         ck(hipGetLastError());
         for (int dst = 1; dst <= 2; ++dst)
             if (dst != owner) send(c, MPC3_PH_ONLINE, owner, dst, 8 * n);
@@ -1571,7 +1617,7 @@ int mpc3_share(mpc3_ctx* c, int owner, const uint64_t* x, mpc3_share_t* out) {
 }
 
 int mpc3_trunc_pair(mpc3_ctx* c, int64_t n, int t, mpc3_trunc_pair_t* out) {
-    int g = guard(c);
+    int g = guard(c, true);
     if (g) return g;
     if (!out || n < 0 || t < 1 || t > 62 || !out->rx.m || !out->rx.r1 || !out->rx.r2 || !out->rz.m ||
         !out->rz.r1 || !out->rz.r2)
@@ -1584,7 +1630,8 @@ int mpc3_trunc_pair(mpc3_ctx* c, int64_t n, int t, mpc3_trunc_pair_t* out) {
         out->rx.rows = out->rz.rows = n;
         out->rx.cols = out->rz.cols = 1;
         launch_trunc_pair(n, t, c->keys, op, take(c, MPC3_SITE_TRUNC_GAMMA2, n), take(c, MPC3_SITE_TRUNC_M1, n),
-                          out->rx.m, out->rx.r1, out->rx.r2, out->rz.m, out->rz.r1, out->rz.r2, c->stream);
+                          out->rx.m, out->rx.r1, out->rx.r2, out->rz.m, out->rz.r1, out->rz.r2, c->stream,
+                          rec_off(c));
         ck(hipGetLastError());
         for (int q = 0; q < 2; ++q) {
             send(c, MPC3_PH_OFFLINE, 0, 2, 8 * n);
@@ -1617,7 +1664,7 @@ int mpc3_inner(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W, const 
 
 int mpc3_inner_static(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W, const mpc3_trunc_pair_t* pair,
                       mpc3_share_t* Z) {
-    int g = guard(c);
+    int g = guard(c, true);
     if (g) return g;
     if (!valid(X) || !valid(W) || !valid(Z)) return MPC3_E_ARG;
     if (W->rows != X->cols || Z->rows != X->rows || Z->cols != W->cols) return MPC3_E_SHAPE;
@@ -1634,7 +1681,7 @@ int mpc3_inner_static(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W,
 
 int mpc3_im2col_strided(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, int KH, int KW, int pad,
                         int stride, mpc3_share_t* cols) {
-    int g = guard(c);
+    int g = guard(c, true);
     if (g) return g;
     if (!valid(x) || !valid(cols) || B < 0 || H <= 0 || W <= 0 || C <= 0 || KH <= 0 || KW <= 0 || pad < 0 ||
         stride <= 0)
@@ -1658,7 +1705,7 @@ int mpc3_im2col(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, 
 }
 
 int mpc3_sumpool2(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, mpc3_share_t* out) {
-    int g = guard(c);
+    int g = guard(c, true);
     if (g) return g;
     if (!valid(x) || !valid(out) || B < 0 || H <= 0 || W <= 0 || C <= 0 || (H & 1) || (W & 1)) return MPC3_E_ARG;
     if (x->rows * x->cols != (int64_t)B * H * W * C || out->rows * out->cols != (int64_t)B * (H / 2) * (W / 2) * C)
@@ -1749,7 +1796,7 @@ int mpc3_mult(mpc3_ctx* c, const mpc3_share_t* a, const mpc3_share_t* b, mpc3_sh
 }
 
 int mpc3_trunc(mpc3_ctx* c, const mpc3_trunc_pair_t* p, const mpc3_share_t* Z, mpc3_share_t* out) {
-    int g = guard(c);
+    int g = guard(c, true);
     if (g) return g;
     if (!p || !valid(Z) || !valid(out)) return MPC3_E_ARG;
     const int64_t n = Z->rows * Z->cols;
@@ -1757,6 +1804,135 @@ int mpc3_trunc(mpc3_ctx* c, const mpc3_trunc_pair_t* p, const mpc3_share_t* Z, m
     return wrap(c, __func__, [&] {
         launch_trunc_shift(n, p->t, Z->m, p->rz.m, p->rz.r1, p->rz.r2, out->m, out->r1, out->r2, c->stream);
         ck(hipGetLastError());
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_capture_begin(mpc3_ctx* c) {
+    int g = guard(c);
+    if (g) return g;
+    if (!c->stream || c->keep_msgs) return MPC3_E_STATE;
+    for (const InjSlot& s : c->inj)
+        if (s.active) return MPC3_E_STATE;
+    return wrap(c, __func__, [&] {
+        ck(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        c->capturing = true;
+        c->cap_err = 0;
+        c->cap_op0 = c->op;
+        memcpy(c->cap_bytes0, c->bytes, sizeof c->bytes);
+        memcpy(c->cap_rounds0, c->rounds, sizeof c->rounds);
+        c->cap_pend0 = c->pending.size();
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_capture_end(mpc3_ctx* c, int* graph_id) {
+    if (!c || !graph_id) return MPC3_E_ARG;
+    if (!c->capturing) return MPC3_E_STATE;
+    return wrap(c, __func__, [&] {
+        // take the recorded calls' effects out of the context into the record
+        c->capturing = false;
+        GraphRec r;
+        r.op0 = c->cap_op0;
+        r.dop = c->op - c->cap_op0;
+        for (int ph = 0; ph < 4; ++ph) {
+            r.dr[ph] = c->rounds[ph] - c->cap_rounds0[ph];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) r.db[ph][a][b] = c->bytes[ph][a][b] - c->cap_bytes0[ph][a][b];
+        }
+        for (size_t i = c->cap_pend0; i < c->pending.size(); ++i) {
+            Pending p = c->pending[i];
+            p.op -= r.op0;
+            if (p.kind == MPC3_VERIFY_TRUNC) p.pair.id -= r.op0;
+            r.pend.push_back(p);
+        }
+        c->op = c->cap_op0;
+        memcpy(c->bytes, c->cap_bytes0, sizeof c->bytes);
+        memcpy(c->rounds, c->cap_rounds0, sizeof c->rounds);
+        c->pending.erase(c->pending.begin() + (std::ptrdiff_t)c->cap_pend0, c->pending.end());
+        const int failed = c->cap_err;
+        c->cap_err = 0;
+        hipGraph_t gr = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->stream, &gr);
+        if (e != hipSuccess || failed) {
+            if (gr) (void)hipGraphDestroy(gr);
+            if (failed) throw CodeError(failed);
+            ck(e);
+        }
+        const hipError_t ei = hipGraphInstantiate(&r.ex, gr, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(gr);
+            ck(ei);
+        }
+        r.g = gr;
+        const int id = c->next_graph++;
+        c->graphs[id] = std::move(r);
+        *graph_id = id;
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_graph_launch(mpc3_ctx* c, int graph_id) {
+    int g = guard(c);
+    if (g) return g;
+    auto it = c->graphs.find(graph_id);
+    if (it == c->graphs.end()) return MPC3_E_ARG;
+    for (const Pending& p : c->pending)
+        if (p.graph == graph_id) return MPC3_E_STATE;
+    return wrap(c, __func__, [&] {
+        const GraphRec& r = it->second;
+        const uint32_t base = c->op;
+        launch_set_word(c->op_off_dev, base - r.op0, c->stream);
+        ck(hipGetLastError());
+        ck(hipGraphLaunch(r.ex, c->stream));
+        c->op += r.dop;
+        for (int ph = 0; ph < 4; ++ph) {
+            c->rounds[ph] += r.dr[ph];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) c->bytes[ph][a][b] += r.db[ph][a][b];
+        }
+        for (const Pending& p0 : r.pend) {
+            Pending p = p0;
+            p.op += base;
+            if (p.kind == MPC3_VERIFY_TRUNC) p.pair.id += base;
+            p.graph = graph_id;
+            c->pending.push_back(p);
+        }
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_graph_nodes(mpc3_ctx* c, int graph_id, int64_t* kernel_nodes, int64_t* other_nodes) {
+    if (!c || !kernel_nodes || !other_nodes) return MPC3_E_ARG;
+    auto it = c->graphs.find(graph_id);
+    if (it == c->graphs.end()) return MPC3_E_ARG;
+    return wrap(c, __func__, [&] {
+        size_t n = 0;
+        ck(hipGraphGetNodes(it->second.g, nullptr, &n));
+        std::vector<hipGraphNode_t> nodes(n);
+        if (n) ck(hipGraphGetNodes(it->second.g, nodes.data(), &n));
+        int64_t k = 0, o = 0;
+        for (size_t i = 0; i < n; ++i) {
+            hipGraphNodeType t;
+            ck(hipGraphNodeGetType(nodes[i], &t));
+            (t == hipGraphNodeTypeKernel ? k : o) += 1;
+        }
+        *kernel_nodes = k;
+        *other_nodes = o;
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_graph_destroy(mpc3_ctx* c, int graph_id) {
+    int g = guard(c);
+    if (g && g != MPC3_E_ABORTED) return g;
+    auto it = c->graphs.find(graph_id);
+    if (it == c->graphs.end()) return MPC3_E_ARG;
+    return wrap(c, __func__, [&] {
+        ck(hipStreamSynchronize(c->stream));
+        (void)hipGraphExecDestroy(it->second.ex);
+        (void)hipGraphDestroy(it->second.g);
+        c->graphs.erase(it);
         return (int)MPC3_OK;
     });
 }
@@ -1920,6 +2096,7 @@ int mpc3_reconstruct(mpc3_ctx* c, const mpc3_share_t* X, int to_party, uint64_t*
 
 int mpc3_comm_stats(mpc3_ctx* c, mpc3_comm* out) {
     if (!c || !out) return MPC3_E_ARG;
+    if (c->capturing) return guard(c);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return MPC3_E_HIP;
     memcpy(out->bytes, c->bytes, sizeof c->bytes);
     memcpy(out->rounds, c->rounds, sizeof c->rounds);
@@ -1928,12 +2105,14 @@ int mpc3_comm_stats(mpc3_ctx* c, mpc3_comm* out) {
 
 int mpc3_inject(mpc3_ctx* c, int site, int64_t index, uint64_t e) {
     if (!c || site < 1 || site > 11 || index < 0) return MPC3_E_ARG;
+    if (c->capturing) return guard(c);
     c->inj[site] = InjSlot{true, index, e};
     return MPC3_OK;
 }
 
 int mpc3_message(mpc3_ctx* c, int kind, int which, uint64_t* out, int64_t n) {
     if (!c || kind < 0 || kind > 1 || which < 0 || which > 2 || !out) return MPC3_E_ARG;
+    if (c->capturing) return guard(c);
     if (!c->msg[kind][which] || n > c->msg_n[kind]) return MPC3_E_STATE;
     if (hipMemcpyAsync(out, c->msg[kind][which], (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
         return MPC3_E_HIP;
@@ -1969,6 +2148,7 @@ int mpc3_profile(mpc3_ctx* c, int on) {
 
 int mpc3_profile_read(mpc3_ctx* c, double* total_ms, int64_t* launches, double* ring_macs) {
     if (!c || !total_ms || !launches || !ring_macs) return MPC3_E_ARG;
+    if (c->capturing) return guard(c);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return MPC3_E_HIP;
     double t = 0;
     for (auto& p : c->ev) {

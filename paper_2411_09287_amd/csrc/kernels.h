@@ -20,12 +20,15 @@ void launch_fill(u64* out, int64_t n, Key k, Tag t, hipStream_t s);
 void launch_fill_at(u64* out, int64_t n, int64_t start, Key k, Tag t, hipStream_t s);
 void launch_encode(const double* x, int64_t n, int frac, u64* out, hipStream_t s);
 void launch_decode(const u64* v, int64_t n, int frac, double* out, hipStream_t s);
+// op_off (nullable): a device word added to the operation id of every keystream tag the
+// launch draws (graph replays run under a new id range without re-recording).
 void launch_share(const u64* x, int64_t n, Key k1, Tag t1, Key k2, Tag t2, u64* m, u64* r1, u64* r2,
-                  hipStream_t s);
+                  hipStream_t s, const u32* op_off = nullptr);
 void launch_trunc_pair(int64_t n, int t, const Keys& k, u32 op, Inj g2x, Inj m1z, u64* rxm, u64* rx1,
-                       u64* rx2, u64* rzm, u64* rz1, u64* rz2, hipStream_t s);
+                       u64* rx2, u64* rzm, u64* rz1, u64* rz2, hipStream_t s, const u32* op_off = nullptr);
 void launch_inner_pre(int64_t n, const Keys& k, u32 op, const u64* pm, const u64* p1, const u64* p2,
-                      u64* zr1, u64* zr2, u64* g1, hipStream_t s);
+                      u64* zr1, u64* zr2, u64* g1, hipStream_t s, const u32* op_off = nullptr);
+void launch_set_word(u32* p, u32 v, hipStream_t s);
 void launch_inner_post(int64_t n, const u64* c0, const u64* c1, const u64* c2, const u64* zr1,
                        const u64* zr2, const u64* g1, Inj g2inj, Inj m1inj, u64* zm, u64* msg_g2,
                        u64* msg_m1, u64* msg_m2, hipStream_t s);

@@ -40,10 +40,15 @@ __global__ void k_decode(const u64* v, int64_t n, double scale, double* out) {
     if (i < n) out[i] = (double)(int64_t)v[i] / scale;
 }
 
-__global__ void k_share(const u64* x, int64_t n, Key k1, Tag t1, Key k2, Tag t2, u64* m, u64* r1, u64* r2) {
+__global__ void k_share(const u64* x, int64_t n, Key k1, Tag t1, Key k2, Tag t2, u64* m, u64* r1, u64* r2,
+                        const u32* op_off) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i0 = b * 8;
     if (i0 >= n) return;
+    if (op_off) {
+        t1.n0 += *op_off;
+        t2.n0 += *op_off;
+    }
     u64 w1[8], w2[8];
     prg_block8(k1, t1, (u64)b, w1);
     prg_block8(k2, t2, (u64)b, w2);
@@ -79,7 +84,8 @@ __device__ __forceinline__ void prg_wave512(const Key& k, const Tag& t, u64 blk0
 // A wave covers 512 consecutive elements and its lanes take consecutive ones (the keystream
 // words come through prg_wave512); the eight streams are drawn one after another.
 __global__ void k_trunc_pair(int64_t n, int t, Keys k, u32 op, Inj g2x, Inj m1z, u64* rxm, u64* rx1,
-                             u64* rx2, u64* rzm, u64* rz1, u64* rz2) {
+                             u64* rx2, u64* rzm, u64* rz1, u64* rz2, const u32* op_off) {
+    if (op_off) op += *op_off;
     __shared__ u64 lds[4][64 * 9];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t blk0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;
@@ -139,7 +145,8 @@ __global__ void k_trunc_pair(int64_t n, int t, Keys k, u32 op, Inj g2x, Inj m1z,
 // Pi_Inner preprocessing: output-wire mask [r_Z] (fresh, or the truncation pair's r_x) and
 // [Gamma]_1.  A wave covers 512 consecutive words; its lanes take consecutive words.
 __global__ void k_inner_pre(int64_t n, Keys k, u32 op, const u64* pm, const u64* p1, const u64* p2,
-                            u64* zr1, u64* zr2, u64* g1) {
+                            u64* zr1, u64* zr2, u64* g1, const u32* op_off) {
+    if (op_off) op += *op_off;
     __shared__ u64 lds[4][64 * 9];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t blk0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;   // the wave's first block
@@ -1219,23 +1226,26 @@ void launch_decode(const u64* v, int64_t n, int frac, double* out, hipStream_t s
     hipLaunchKernelGGL(k_decode, dim3(nblocks(n, TPB)), dim3(TPB), 0, s, v, n, (double)((u64)1 << frac), out);
 }
 void launch_share(const u64* x, int64_t n, Key k1, Tag t1, Key k2, Tag t2, u64* m, u64* r1, u64* r2,
-                  hipStream_t s) {
+                  hipStream_t s, const u32* op_off) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_share, dim3(nblocks((n + 7) / 8, TPB)), dim3(TPB), 0, s, x, n, k1, t1, k2, t2, m, r1, r2);
+    hipLaunchKernelGGL(k_share, dim3(nblocks((n + 7) / 8, TPB)), dim3(TPB), 0, s, x, n, k1, t1, k2, t2, m, r1, r2,
+                       op_off);
 }
 void launch_trunc_pair(int64_t n, int t, const Keys& k, u32 op, Inj g2x, Inj m1z, u64* rxm, u64* rx1,
-                       u64* rx2, u64* rzm, u64* rz1, u64* rz2, hipStream_t s) {
+                       u64* rx2, u64* rzm, u64* rz1, u64* rz2, hipStream_t s, const u32* op_off) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_trunc_pair, dim3(nblocks((n + 7) / 8, TPB)), dim3(TPB), 0, s, n, t, k, op, g2x, m1z,
-                       rxm, rx1, rx2, rzm, rz1, rz2);
+                       rxm, rx1, rx2, rzm, rz1, rz2, op_off);
 }
 void launch_inner_pre(int64_t n, const Keys& k, u32 op, const u64* pm, const u64* p1, const u64* p2,
-                      u64* zr1, u64* zr2, u64* g1, hipStream_t s) {
+                      u64* zr1, u64* zr2, u64* g1, hipStream_t s, const u32* op_off) {
     if (n <= 0) return;
     static_assert(TPB == 256, "k_inner_pre holds four waves' exchange buffers");
     hipLaunchKernelGGL(k_inner_pre, dim3(nblocks((n + 7) / 8, TPB)), dim3(TPB), 0, s, n, k, op, pm, p1, p2, zr1,
-                       zr2, g1);
+                       zr2, g1, op_off);
 }
+__global__ void k_set_word(u32* p, u32 v) { *p = v; }
+void launch_set_word(u32* p, u32 v, hipStream_t s) { hipLaunchKernelGGL(k_set_word, dim3(1), dim3(1), 0, s, p, v); }
 void launch_inner_post(int64_t n, const u64* c0, const u64* c1, const u64* c2, const u64* zr1,
                        const u64* zr2, const u64* g1, Inj g2inj, Inj m1inj, u64* zm, u64* msg_g2,
                        u64* msg_m1, u64* msg_m2, hipStream_t s) {

@@ -5,6 +5,7 @@ memory (int64 tensors used as raw 64-bit words) and the stream.  The library mus
 built (``python -m paper_2411_09287_amd.build``); loading fails loudly otherwise.
 """
 import ctypes
+import functools
 import os
 
 import numpy as np
@@ -70,6 +71,11 @@ SIGNATURES = {
     "mpc3_relu": (_I, [_P, ctypes.POINTER(Share), ctypes.POINTER(Share)]),
     "mpc3_maxpool2": (_I, [_P, ctypes.POINTER(Share), _I, _I, _I, _I, ctypes.POINTER(Share)]),
     "mpc3_trunc": (_I, [_P, ctypes.POINTER(TruncPair), ctypes.POINTER(Share), ctypes.POINTER(Share)]),
+    "mpc3_capture_begin": (_I, [_P]),
+    "mpc3_capture_end": (_I, [_P, ctypes.POINTER(_I)]),
+    "mpc3_graph_launch": (_I, [_P, _I]),
+    "mpc3_graph_nodes": (_I, [_P, _I, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "mpc3_graph_destroy": (_I, [_P, _I]),
     "mpc3_verify": (_I, [_P, _I, _I, ctypes.POINTER(_I)]),
     "mpc3_reconstruct": (_I, [_P, ctypes.POINTER(Share), _I, _P]),
     "mpc3_comm_stats": (_I, [_P, ctypes.POINTER(Comm)]),
@@ -175,8 +181,22 @@ class DPair:
         return self.s.t
 
 
+def _on_stream(fn):
+    """Run a Context method with the context's stream current, so that the tensors it
+    allocates belong to the stream its launches are ordered on (torch's caching allocator
+    reuses a freed block on the stream it was allocated on).  Input tensors must be ready
+    on that stream."""
+    @functools.wraps(fn)
+    def run(self, *a, **k):
+        if torch.cuda.current_stream(self.device) == self._stream:
+            return fn(self, *a, **k)
+        with torch.cuda.stream(self._stream):
+            return fn(self, *a, **k)
+    return run
+
+
 class Context:
-    """One three-party context on the current torch stream."""
+    """One three-party context on a torch stream (the current one by default)."""
 
     def __init__(self, master_seed, d=64, frac_bits=13, workspace_bytes=0, device="cuda", stream=None):
         self.device = device
@@ -225,32 +245,44 @@ class Context:
         _ck(lib().mpc3_keep_messages(self.h, int(on)), "mpc3_keep_messages", self.h)
 
     # -- protocol --------------------------------------------------------------
-    def encode(self, x):
+    @property
+    def stream(self):
+        """The torch stream the context's launches are ordered on."""
+        return self._stream
+
+    @_on_stream
+    def encode(self, x, out=None):
         x = x.to(self.device, torch.float64).contiguous()
-        out = torch.empty(x.shape, dtype=torch.int64, device=self.device)
+        if out is None:
+            out = torch.empty(x.shape, dtype=torch.int64, device=self.device)
         _ck(lib().mpc3_encode(self.h, _ptr(x), x.numel(), _ptr(out)), "mpc3_encode", self.h)
         return out
 
+    @_on_stream
     def decode(self, v):
         out = torch.empty(v.shape, dtype=torch.float64, device=self.device)
         _ck(lib().mpc3_decode(self.h, _ptr(v), v.numel(), _ptr(out)), "mpc3_decode", self.h)
         return out
 
-    def share(self, x, owner=0):
+    @_on_stream
+    def share(self, x, owner=0, out=None):
         x = x.contiguous()
         rows = x.shape[0] if x.dim() else 1
         cols = x.numel() // rows if rows else 0
-        out = DShare.empty(rows, cols, self.device)
+        if out is None:
+            out = DShare.empty(rows, cols, self.device)
         s = out.c()
         _ck(lib().mpc3_share(self.h, owner, _ptr(x), ctypes.byref(s)), "mpc3_share", self.h)
         return out
 
-    def trunc_pair(self, n, t):
-        p = DPair(n, self.device)
+    @_on_stream
+    def trunc_pair(self, n, t, out=None):
+        p = out if out is not None else DPair(n, self.device)
         _ck(lib().mpc3_trunc_pair(self.h, n, t, ctypes.byref(p.s)), "mpc3_trunc_pair", self.h)
         self._keep[VERIFY_TRUNC].append(p)
         return p
 
+    @_on_stream
     def inner(self, X, W, pair=None, out=None):
         Z = out if out is not None else DShare.empty(X.rows, W.cols, self.device)
         xs, ws, zs = X.c(), W.c(), Z.c()
@@ -259,6 +291,7 @@ class Context:
         self._keep[VERIFY_INNER].append((X, W, Z))
         return Z
 
+    @_on_stream
     def inner_static(self, X, W, pair=None, out=None):
         """mpc3_inner_static: Pi_Inner with the library's fixed device workspace (no allocation
         inside the call; Z must be given or is allocated here, before the call)."""
@@ -270,10 +303,11 @@ class Context:
         self._keep[VERIFY_INNER].append((X, W, Z))
         return Z
 
-    def im2col(self, x, B, H, W, C, KH, KW, pad, ld=None, stride=1):
+    @_on_stream
+    def im2col(self, x, B, H, W, C, KH, KW, pad, ld=None, stride=1, out=None):
         """ld (>= KH KW C): row width of the result, the extra columns zero."""
         OH, OW = (H + 2 * pad - KH) // stride + 1, (W + 2 * pad - KW) // stride + 1
-        cols = DShare.empty(B * OH * OW, ld or KH * KW * C, self.device)
+        cols = out if out is not None else DShare.empty(B * OH * OW, ld or KH * KW * C, self.device)
         xs, cs = x.c(), cols.c()
         if stride == 1:
             _ck(lib().mpc3_im2col(self.h, ctypes.byref(xs), B, H, W, C, KH, KW, pad, ctypes.byref(cs)), "mpc3_im2col",
@@ -283,12 +317,15 @@ class Context:
                 "mpc3_im2col_strided", self.h)
         return cols
 
-    def sumpool2(self, x, B, H, W, C):
-        out = DShare.empty(B, (H // 2) * (W // 2) * C, self.device)
+    @_on_stream
+    def sumpool2(self, x, B, H, W, C, out=None):
+        if out is None:
+            out = DShare.empty(B, (H // 2) * (W // 2) * C, self.device)
         xs, os_ = x.c(), out.c()
         _ck(lib().mpc3_sumpool2(self.h, ctypes.byref(xs), B, H, W, C, ctypes.byref(os_)), "mpc3_sumpool2", self.h)
         return out
 
+    @_on_stream
     def mult(self, a, b):
         c = DShare.empty(a.rows, a.cols, self.device)
         sa, sb, sc = a.c(), b.c(), c.c()
@@ -296,6 +333,7 @@ class Context:
         self._keep[VERIFY_MULT].append((a, b, c))
         return c
 
+    @_on_stream
     def edabits(self, n):
         """(arith, bits): <r>^l and <r[0..63]>^1 of n random edaBits (n words per plane each)."""
         a, b = DShare.empty(n, 1, self.device), DShare.empty(n, 1, self.device)
@@ -303,12 +341,14 @@ class Context:
         _ck(lib().mpc3_edabits(self.h, n, ctypes.byref(sa), ctypes.byref(sb)), "mpc3_edabits", self.h)
         return a, b
 
+    @_on_stream
     def dabits(self, n):
         a, b = DShare.empty(n, 1, self.device), DShare.empty(n, 1, self.device)
         sa, sb = a.c(), b.c()
         _ck(lib().mpc3_dabits(self.h, n, ctypes.byref(sa), ctypes.byref(sb)), "mpc3_dabits", self.h)
         return a, b
 
+    @_on_stream
     def relu(self, x):
         out = DShare.empty(x.rows, x.cols, self.device)
         xs, os_ = x.c(), out.c()
@@ -316,6 +356,7 @@ class Context:
         self._keep[VERIFY_MULT].append((x, out))
         return out
 
+    @_on_stream
     def maxpool2(self, x, B, H, W, C):
         out = DShare.empty(B, (H // 2) * (W // 2) * C, self.device)
         xs, os_ = x.c(), out.c()
@@ -323,11 +364,33 @@ class Context:
         self._keep[VERIFY_MULT].append((x, out))
         return out
 
-    def trunc(self, pair, Z):
-        out = DShare.empty(Z.rows, Z.cols, self.device)
+    @_on_stream
+    def trunc(self, pair, Z, out=None):
+        if out is None:
+            out = DShare.empty(Z.rows, Z.cols, self.device)
         zs, os_ = Z.c(), out.c()
         _ck(lib().mpc3_trunc(self.h, ctypes.byref(pair.s), ctypes.byref(zs), ctypes.byref(os_)), "mpc3_trunc", self.h)
         return out
+
+    # -- recorded forward passes (HIP graphs) -------------------------------------
+    def capture_begin(self):
+        _ck(lib().mpc3_capture_begin(self.h), "mpc3_capture_begin", self.h)
+
+    def capture_end(self):
+        gid = ctypes.c_int(0)
+        _ck(lib().mpc3_capture_end(self.h, ctypes.byref(gid)), "mpc3_capture_end", self.h)
+        return gid.value
+
+    def graph_launch(self, gid):
+        _ck(lib().mpc3_graph_launch(self.h, gid), "mpc3_graph_launch", self.h)
+
+    def graph_nodes(self, gid):
+        k, o = ctypes.c_int64(0), ctypes.c_int64(0)
+        _ck(lib().mpc3_graph_nodes(self.h, gid, ctypes.byref(k), ctypes.byref(o)), "mpc3_graph_nodes", self.h)
+        return k.value, o.value
+
+    def graph_destroy(self, gid):
+        _ck(lib().mpc3_graph_destroy(self.h, gid), "mpc3_graph_destroy", self.h)
 
     def verify(self, R=-1, kinds=VERIFY_ALL):
         ok = ctypes.c_int(0)
@@ -337,6 +400,7 @@ class Context:
                 self._keep[k] = []
         return bool(ok.value)
 
+    @_on_stream
     def reconstruct(self, X, to_party=-1, out=None):
         if out is None:
             out = torch.empty(X.m.shape, dtype=torch.int64, device=self.device)
@@ -360,6 +424,7 @@ class Context:
     def inject(self, site, index, e):
         _ck(lib().mpc3_inject(self.h, site, index, e & ((1 << 64) - 1)), "mpc3_inject", self.h)
 
+    @_on_stream
     def message(self, kind, which, n):
         out = torch.empty(n, dtype=torch.int64, device=self.device)
         _ck(lib().mpc3_message(self.h, kind, which, _ptr(out), n), "mpc3_message", self.h)

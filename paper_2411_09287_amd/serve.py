@@ -1,15 +1,17 @@
 """Batched serving of mixed secure-inference requests on one GPU.
 
-Requests (model, batch size) arrive together; requests of the same model are packed, in
-arrival order, into row-blocks of at most `cap[model]` images.  A pack runs as one
-secure evaluation: every layer is one Pi_Inner over the packed rows (rows are images x
-output positions, so requests simply stack), one truncation pair, and one verification
-per layer for the whole pack; the opened logits are split back per request.  Packing
-amortises the verification (whose cost does not grow with the number of rows beyond
-the compression products) and the per-launch costs over many requests.
+Requests (model, batch size) are packed per model, in arrival order, into row-blocks of at
+most `cap[model]` images.  A pack runs as one secure evaluation: every layer is one
+Pi_Inner over the packed rows (rows are images x output positions, so requests simply
+stack) with one truncation pair, and one verification covers the whole pack; the opened
+logits are split back per request.  Packing amortises the verification (whose cost does
+not grow with the number of rows beyond the compression products) and the per-launch
+costs over many requests.  With graphs, a pack is padded to its batch bucket (a power of
+two) and its layers replay a HIP graph recorded once per (model, bucket), which removes
+the per-call host work of the linear forward.
 
-The packer also orders packs so that a model's first pack runs as soon as possible
-(first-come order of each pack's first request).
+Requests either all arrive at time 0 (packs in the order of their first request) or
+arrive open-loop at given times (the oldest waiting request's model is served next).
 """
 import time
 
@@ -17,7 +19,7 @@ import numpy as np
 import torch
 
 from . import mpc3, workloads
-from .network import Network
+from .network import Network, RecordedForward
 
 MODEL_NAMES = ("mlp", "lenet", "vgg")
 
@@ -64,11 +66,32 @@ def packs_of(reqs, cap, pack=True):
     return out
 
 
+def bucket_of(b, cap):
+    """The batch bucket of a pack of b images: b rounded up to a power of two, at most cap."""
+    return min(m_bucket(b), max(cap, b))
+
+
+def poisson_arrivals(reqs, rate, seed=7):
+    """Open-loop arrivals: exponential gaps of mean 1/rate seconds, in request order."""
+    g = workloads.rng(seed)
+    t = np.cumsum(g.exponential(1.0 / rate, size=len(reqs)))
+    return {r[0]: float(ti) for r, ti in zip(reqs, t)}
+
+
 class Server:
-    def __init__(self, ctx, models=MODEL_NAMES, cap=None):
+    """graphs=True: every pack runs at its batch bucket (power of two, zero images padding
+    it) from a HIP graph recorded on first use per (model, bucket) (network.RecordedForward;
+    buckets whose layers exceed the library's fixed workspace run by direct calls).
+    buckets=True without graphs pads the same way but makes the calls directly, so both
+    draw the same masks.  The context of a graph server needs a stream of its own."""
+
+    def __init__(self, ctx, models=MODEL_NAMES, cap=None, graphs=False, buckets=None):
         self.ctx = ctx
         self.nets = {m: Network(ctx, m) for m in models}
         self.cap = dict(DEFAULT_CAP if cap is None else cap)
+        self.graphs = graphs
+        self.buckets = graphs if buckets is None else buckets
+        self.recorded = {}
 
     def tune(self, reqs, reps=3, log=None):
         """Autotune the kernel family for every layer shape the packs will produce.  The
@@ -77,6 +100,8 @@ class Server:
         shapes = set()
         for p in packs_of(reqs, self.cap):
             b = sum(r[2] for r in p)
+            if self.buckets:
+                b = bucket_of(b, self.cap[p[0][1]])
             shapes.update((m_bucket(M), K, N) for M, K, N in self.nets[p[0][1]].exec_shapes(b))
         for i, (M, K, N) in enumerate(sorted(shapes)):
             self.ctx.autotune(M, K, N, reps)
@@ -84,37 +109,112 @@ class Server:
                 log(f"tuned {i + 1}/{len(shapes)} shapes")
         return len(shapes)
 
-    def run(self, reqs, pack=True, log=None):
-        """Serve all requests; returns per-request latency (s), makespan (s) and images."""
+    def _graph(self, name, bk):
+        key = (name, bk)
+        if key not in self.recorded:
+            try:
+                self.recorded[key] = RecordedForward(self.nets[name], bk)
+            except mpc3.Mpc3Error as e:
+                if e.code != mpc3.E_LIMIT:
+                    raise
+                self.recorded[key] = None
+        return self.recorded[key]
+
+    def forward(self, name, x):
+        """Shared logits of the images x (rows beyond x.shape[0] belong to padding) and
+        whether a recorded graph produced them."""
+        net = self.nets[name]
+        if not self.buckets:
+            return net.forward(x), False
+        b = x.shape[0]
+        bk = bucket_of(b, self.cap[name])
+        rf = self._graph(name, bk) if self.graphs else None
+        if rf is not None:
+            return rf(x), True
+        if bk > b:
+            x = torch.cat([x, torch.zeros((bk - b,) + tuple(x.shape[1:]), dtype=x.dtype, device=x.device)])
+        return net.forward(x), False
+
+    def _run_pack(self, p, inputs, keep_logits, out):
+        ctx = self.ctx
+        x = torch.cat([inputs[r[0]] for r in p]) if len(p) > 1 else inputs[p[0][0]]
+        h, from_graph = self.forward(p[0][1], x)
+        out["graph_packs"] += int(from_graph)
+        out["ok"] &= ctx.verify()
+        logits = ctx.reconstruct(h)            # synchronises: the pack's results are final
+        if keep_logits:
+            row = 0
+            for r in p:
+                out["logits"][r[0]] = ctx.decode(logits[row:row + r[2]].contiguous())
+                row += r[2]
+
+    def run(self, reqs, pack=True, log=None, arrivals=None, keep_logits=False):
+        """Serve all requests; returns per-request latency (s), makespan (s) and images.
+
+        arrivals=None: every request is there at time 0 and the packs run in the order of
+        their first request (packs_of).  arrivals={request id: seconds}: an open-loop run
+        on a virtual clock advanced by the measured service time of each pack: when the
+        GPU is free, the model of the oldest waiting request is served with its waiting
+        requests of that model (arrival order, at most cap images); latency is completion
+        minus arrival."""
         ctx = self.ctx
         inputs = {r[0]: request_input(r[1], r[2], r[0], ctx.device) for r in reqs}
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        out = {"ok": True, "graph_packs": 0, "logits": {}}
         lat = {}
-        ok_all = True
-        packs = packs_of(reqs, self.cap, pack)
-        for n_done, p in enumerate(packs):
-            if log and n_done % 64 == 0:
-                log(f"pack {n_done}/{len(packs)}")
-            net = self.nets[p[0][1]]
-            x = torch.cat([inputs[r[0]] for r in p]) if len(p) > 1 else inputs[p[0][0]]
-            out = net.forward(x)
-            ok_all &= ctx.verify()
-            logits = ctx.reconstruct(out)          # synchronises: the pack's results are final
-            t = time.perf_counter() - t0
-            row = 0
-            for r in p:
-                lat[r[0]] = t
-                row += r[2]
-            del logits
-        makespan = time.perf_counter() - t0
+        if arrivals is None:
+            t0 = time.perf_counter()
+            packs = packs_of(reqs, self.cap, pack)
+            for n_done, p in enumerate(packs):
+                if log and n_done % 64 == 0:
+                    log(f"pack {n_done}/{len(packs)}")
+                self._run_pack(p, inputs, keep_logits, out)
+                t = time.perf_counter() - t0
+                for r in p:
+                    lat[r[0]] = t
+            makespan = time.perf_counter() - t0
+            npacks = len(packs)
+        else:
+            waiting = sorted(reqs, key=lambda r: (arrivals[r[0]], r[0]))
+            clock, npacks, i = 0.0, 0, 0
+            queue = []
+            while i < len(waiting) or queue:
+                while i < len(waiting) and arrivals[waiting[i][0]] <= clock:
+                    queue.append(waiting[i])
+                    i += 1
+                if not queue:
+                    clock = arrivals[waiting[i][0]]
+                    continue
+                name = queue[0][1]
+                p, n = [], 0
+                for r in queue:
+                    if r[1] != name:
+                        continue
+                    if p and (not pack or n + r[2] > self.cap[name]):
+                        break
+                    p.append(r)
+                    n += r[2]
+                queue = [r for r in queue if r not in p]
+                t0 = time.perf_counter()
+                self._run_pack(p, inputs, keep_logits, out)
+                clock += time.perf_counter() - t0
+                for r in p:
+                    lat[r[0]] = clock - arrivals[r[0]]
+                npacks += 1
+                if log and npacks % 64 == 0:
+                    log(f"pack {npacks}, {i}/{len(waiting)} arrived")
+            makespan = clock - min(arrivals.values())
         images = sum(r[2] for r in reqs)
-        return {"ok": ok_all, "latency": lat, "makespan": makespan, "images": images,
-                "packs": len(packs)}
+        res = {"ok": out["ok"], "latency": lat, "makespan": makespan, "images": images, "packs": npacks,
+               "graph_packs": out["graph_packs"]}
+        if keep_logits:
+            res["logits"] = out["logits"]
+        return res
 
 
 def summary(res):
     lat = np.array(sorted(res["latency"].values()))
     return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "inferences_per_s": res["images"] / res["makespan"], "makespan_s": res["makespan"],
-            "images": res["images"], "packs": res["packs"], "verified": bool(res["ok"])}
+            "images": res["images"], "packs": res["packs"], "graph_packs": res.get("graph_packs", 0),
+            "verified": bool(res["ok"])}
