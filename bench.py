@@ -402,25 +402,78 @@ def run_depth(args):
 
 
 def run_mix(args):
+    """Mixed-request serving: packed with direct calls (every request at time 0), packed
+    from HIP graphs per (model, batch bucket) (every request at time 0, and open-loop
+    Poisson arrivals at 70% of the graph server's measured capacity), and the u64
+    per-request baseline."""
     import torch
     from paper_2411_09287_amd import mpc3, serve
 
     torch.cuda.set_device(0)
     reqs = serve.request_mix(args.requests, seed=5)
     out = {}
-    for label, variant, pack in (("limb_packed", mpc3.VARIANT_AUTO, True), ("u64_per_request", mpc3.VARIANT_U64, False)):
-        if label == "u64_per_request" and args.no_baseline:
-            continue
-        ctx = mpc3.Context(workloads.master_seed(5))
-        ctx.set_variant(variant)
-        srv = serve.Server(ctx)
-        if variant == mpc3.VARIANT_AUTO:
-            n = srv.tune(reqs, log=lambda m: log(f"[mix] {m}"))
-            log(f"[mix] tuned {n} layer shapes")
-        res = srv.run(reqs, pack=pack, log=lambda m: log(f"[mix] {label} {m}"))
-        out[label] = serve.summary(res)
-        log(f"[mix] {label}: {json.dumps(out[label])}")
+    runs = [("limb_packed", mpc3.VARIANT_AUTO, True, False), ("limb_packed_graphs", mpc3.VARIANT_AUTO, True, True)]
+    if not args.no_baseline:
+        runs.append(("u64_per_request", mpc3.VARIANT_U64, False, False))
+    for label, variant, pack, graphs in runs:
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            ctx = mpc3.Context(workloads.master_seed(5))
+            ctx.set_variant(variant)
+            srv = serve.Server(ctx, graphs=graphs)
+            if variant == mpc3.VARIANT_AUTO:
+                n = srv.tune(reqs, log=lambda m: log(f"[mix] {m}"))
+                log(f"[mix] tuned {n} layer shapes")
+            res = srv.run(reqs, pack=pack, log=lambda m: log(f"[mix] {label} {m}"))
+            out[label] = serve.summary(res)
+            log(f"[mix] {label}: {json.dumps(out[label])}")
+            if graphs:
+                # requests per second at 70% of the capacity just measured
+                rate = 0.7 * len(reqs) / res["makespan"]
+                res = srv.run(reqs, pack=pack, arrivals=serve.poisson_arrivals(reqs, rate),
+                              log=lambda m: log(f"[mix] open-loop {m}"))
+                out["limb_graphs_open_loop"] = {**serve.summary(res), "arrival_rate_per_s": rate}
+                log(f"[mix] open loop: {json.dumps(out['limb_graphs_open_loop'])}")
+            ctx.close()
+    out["forward_ms"] = forward_graph_vs_direct()
     return reqs, out
+
+
+def forward_graph_vs_direct(reps=20):
+    """Wall time (host issue + GPU, synchronised) of one linear forward per model and batch
+    bucket: direct calls against the replay of the recorded graph (median of reps; each
+    replay is verified, untimed, before the next)."""
+    import time
+
+    import torch
+    from paper_2411_09287_amd import mpc3, network, serve
+
+    res = {}
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        ctx = mpc3.Context(workloads.master_seed(9))
+        ctx.set_variant(mpc3.VARIANT_LIMB_I8)
+        for name in serve.MODEL_NAMES:
+            net = network.Network(ctx, name)
+            for b in (1, 8, 64):
+                x = serve.request_input(name, b, 0, ctx.device)
+                rf = network.RecordedForward(net, b)
+                tt = {"direct": [], "graph": []}
+                for _ in range(reps):
+                    for kind in ("direct", "graph"):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        h = net.forward(x) if kind == "direct" else rf(x)
+                        torch.cuda.synchronize()
+                        tt[kind].append(time.perf_counter() - t0)
+                        assert ctx.verify()
+                        del h
+                res[f"{name}_b{b}"] = {k: float(np.median(v) * 1e3) for k, v in tt.items()}
+                res[f"{name}_b{b}"]["kernel_nodes"] = rf.nodes()[0]
+                log(f"[mix] forward {name} batch {b}: {json.dumps(res[f'{name}_b{b}'])}")
+                rf.close()
+        ctx.close()
+    return res
 
 
 def run_rtrade(args):
@@ -545,7 +598,7 @@ def main():
 
     if args.workload == "mix":
         reqs, res = run_mix(args)
-        main_res = res["limb_packed"]
+        main_res = res["limb_packed_graphs"]
         line = {"metric": "verified secure inferences/s (linear path)", "value": main_res["inferences_per_s"],
                 "unit": "inferences/s", "n_gpus": 1, "steps": 1, "warmup": 0,
                 "ms_per_step": main_res["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",

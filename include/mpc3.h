@@ -196,13 +196,14 @@ int mpc3_inner(mpc3_ctx* ctx, const mpc3_share_t* X, const mpc3_share_t* W,
  * capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
  * results, registration and counters as mpc3_inner, bit for bit, but the call's
  * device workspace (the three party sums, P0's [Gamma]_1 and the matrix-core digit
- * tiles of W) is one fixed array of 128 MiB per GPU, held from the library's load to
+ * tiles of W) is one fixed array of 256 MiB per GPU, held from the library's load to
  * the end of the process, so the call makes no hipMalloc, hipFree or other device
- * allocation (the host-side list of pending products grows as for mpc3_inner).  The
- * product keeps no split-K partial sums there (K is split only where the 32-bit digit
- * sums require it).  MPC3_E_LIMIT, before any launch, when the operands need more
+ * allocation (the host-side list of pending products grows as for mpc3_inner).  Split-K
+ * partial sums of the product take what the rest of its workspace leaves of the array
+ * (without room, K is split only where the 32-bit digit sums require it, with atomic
+ * adds).  MPC3_E_LIMIT, before any launch, when the operands need more
  * than the array: about 32 bytes per output plus 40 bytes per element of W (VGG-style
- * layers of a batch of 32 fit).  MPC3_E_STATE with mpc3_keep_messages on (message
+ * layers of a batch of 64 fit).  MPC3_E_STATE with mpc3_keep_messages on (message
  * copies would need device memory); profiling (mpc3_profile) does not time it.  Every
  * call on one GPU uses the same array: calls ordered on one stream are safe, calls
  * of different contexts or streams that overlap in time on one GPU race. */

@@ -26,7 +26,7 @@ using namespace mpc3;
 // party sums, P0's [Gamma]_1 and the matrix-core digit tiles of one product.  Each GPU holds
 // its own copy from the library's load to the end of the process.  Host code reaches it only
 // through the address hipGetSymbolAddress returns for the current device (mpc3_ctx_create).
-constexpr size_t STATIC_WS_BYTES = (size_t)128 << 20;
+constexpr size_t STATIC_WS_BYTES = (size_t)256 << 20;
 static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
 
 namespace {
@@ -1236,6 +1236,12 @@ int guard(mpc3_ctx* c, bool capture_ok = false) {
     return MPC3_OK;
 }
 
+// An argument check's failure; while recording, the recording fails with it.
+int fail(mpc3_ctx* c, int code) {
+    if (c->capturing && !c->cap_err) c->cap_err = code;
+    return code;
+}
+
 // The op-offset word for the keystream kernels: read only by recorded launches.
 const u32* rec_off(const mpc3_ctx* c) { return c->capturing ? c->op_off_dev : nullptr; }
 
@@ -1318,7 +1324,12 @@ void inner_body(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W, const
     ga.M = M; ga.N = N; ga.K = K; ga.batch = 1; ga.party = true; ga.accumulate = false;
     ga.ws_alloc = wsa;
     ga.ws_self = wss;
-    ga.no_part = static_ws;
+    if (static_ws) {
+        // split-K partial sums take what the product's other workspace leaves of the array
+        const size_t need = static_ws_need(M, K, N) + 4096;
+        ga.part_max = need < STATIC_WS_BYTES ? STATIC_WS_BYTES - need : 0;
+        ga.no_part = ga.part_max == 0;
+    }
     const u64* Xp[3] = {X->m, X->r1, X->r2};
     const u64* Wp[3] = {W->m, W->r1, W->r2};
     for (int p = 0; p < 3; ++p) {
@@ -1579,7 +1590,7 @@ int mpc3_keep_messages(mpc3_ctx* c, int on) {
 int mpc3_encode(mpc3_ctx* c, const double* x, int64_t n, uint64_t* out) {
     int g = guard(c, true);
     if (g) return g;
-    if ((!x || !out) && n > 0) return MPC3_E_ARG;
+    if ((!x || !out) && n > 0) return fail(c, MPC3_E_ARG);
     return wrap(c, __func__, [&] {
         launch_encode(x, n, c->frac, out, c->stream);
         ck(hipGetLastError());
@@ -1589,7 +1600,7 @@ int mpc3_encode(mpc3_ctx* c, const double* x, int64_t n, uint64_t* out) {
 
 int mpc3_decode(mpc3_ctx* c, const uint64_t* v, int64_t n, double* out) {
     if (!c) return MPC3_E_ARG;
-    if ((!v || !out) && n > 0) return MPC3_E_ARG;
+    if ((!v || !out) && n > 0) return fail(c, MPC3_E_ARG);
     return wrap(c, __func__, [&] {
         launch_decode(v, n, c->frac, out, c->stream);
         ck(hipGetLastError());
@@ -1600,7 +1611,7 @@ int mpc3_decode(mpc3_ctx* c, const uint64_t* v, int64_t n, double* out) {
 int mpc3_share(mpc3_ctx* c, int owner, const uint64_t* x, mpc3_share_t* out) {
     int g = guard(c, true);
     if (g) return g;
-    if (owner < 0 || owner > 2 || !valid(out) || (!x && out->rows * out->cols > 0)) return MPC3_E_ARG;
+    if (owner < 0 || owner > 2 || !valid(out) || (!x && out->rows * out->cols > 0)) return fail(c, MPC3_E_ARG);
     return wrap(c, __func__, [&] {
         const uint32_t op = c->op++;
         const int64_t n = out->rows * out->cols;
@@ -1621,7 +1632,7 @@ int mpc3_trunc_pair(mpc3_ctx* c, int64_t n, int t, mpc3_trunc_pair_t* out) {
     if (g) return g;
     if (!out || n < 0 || t < 1 || t > 62 || !out->rx.m || !out->rx.r1 || !out->rx.r2 || !out->rz.m ||
         !out->rz.r1 || !out->rz.r2)
-        return MPC3_E_ARG;
+        return fail(c, MPC3_E_ARG);
     return wrap(c, __func__, [&] {
         const uint32_t op = c->op++;
         out->t = t;
@@ -1666,11 +1677,11 @@ int mpc3_inner_static(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W,
                       mpc3_share_t* Z) {
     int g = guard(c, true);
     if (g) return g;
-    if (!valid(X) || !valid(W) || !valid(Z)) return MPC3_E_ARG;
-    if (W->rows != X->cols || Z->rows != X->rows || Z->cols != W->cols) return MPC3_E_SHAPE;
-    if (pair && pair->n != X->rows * W->cols) return MPC3_E_SHAPE;
-    if (c->keep_msgs) return MPC3_E_STATE;      // message copies would need device memory
-    if (static_ws_need(X->rows, X->cols, W->cols) > STATIC_WS_BYTES) return MPC3_E_LIMIT;
+    if (!valid(X) || !valid(W) || !valid(Z)) return fail(c, MPC3_E_ARG);
+    if (W->rows != X->cols || Z->rows != X->rows || Z->cols != W->cols) return fail(c, MPC3_E_SHAPE);
+    if (pair && pair->n != X->rows * W->cols) return fail(c, MPC3_E_SHAPE);
+    if (c->keep_msgs) return fail(c, MPC3_E_STATE);      // message copies would need device memory
+    if (static_ws_need(X->rows, X->cols, W->cols) > STATIC_WS_BYTES) return fail(c, MPC3_E_LIMIT);
     return wrap(c, __func__, [&] {
         if (!c->static_ws) throw CodeError(MPC3_E_STATE);
         StaticArena arena{(char*)c->static_ws, STATIC_WS_BYTES, 0};
@@ -1685,11 +1696,11 @@ int mpc3_im2col_strided(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W,
     if (g) return g;
     if (!valid(x) || !valid(cols) || B < 0 || H <= 0 || W <= 0 || C <= 0 || KH <= 0 || KW <= 0 || pad < 0 ||
         stride <= 0)
-        return MPC3_E_ARG;
-    if (H + 2 * pad < KH || W + 2 * pad < KW) return MPC3_E_SHAPE;
+        return fail(c, MPC3_E_ARG);
+    if (H + 2 * pad < KH || W + 2 * pad < KW) return fail(c, MPC3_E_SHAPE);
     const int OH = (H + 2 * pad - KH) / stride + 1, OW = (W + 2 * pad - KW) / stride + 1;
-    if (x->rows * x->cols != (int64_t)B * H * W * C) return MPC3_E_SHAPE;
-    if (cols->rows != (int64_t)B * OH * OW || cols->cols < (int64_t)KH * KW * C) return MPC3_E_SHAPE;
+    if (x->rows * x->cols != (int64_t)B * H * W * C) return fail(c, MPC3_E_SHAPE);
+    if (cols->rows != (int64_t)B * OH * OW || cols->cols < (int64_t)KH * KW * C) return fail(c, MPC3_E_SHAPE);
     return wrap(c, __func__, [&] {
         const u64* const xs[3] = {x->m, x->r1, x->r2};
         u64* const os[3] = {cols->m, cols->r1, cols->r2};
@@ -1707,9 +1718,10 @@ int mpc3_im2col(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, 
 int mpc3_sumpool2(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, mpc3_share_t* out) {
     int g = guard(c, true);
     if (g) return g;
-    if (!valid(x) || !valid(out) || B < 0 || H <= 0 || W <= 0 || C <= 0 || (H & 1) || (W & 1)) return MPC3_E_ARG;
+    if (!valid(x) || !valid(out) || B < 0 || H <= 0 || W <= 0 || C <= 0 || (H & 1) || (W & 1))
+        return fail(c, MPC3_E_ARG);
     if (x->rows * x->cols != (int64_t)B * H * W * C || out->rows * out->cols != (int64_t)B * (H / 2) * (W / 2) * C)
-        return MPC3_E_SHAPE;
+        return fail(c, MPC3_E_SHAPE);
     return wrap(c, __func__, [&] {
         launch_sumpool2(x->m, B, H, W, C, out->m, c->stream);
         launch_sumpool2(x->r1, B, H, W, C, out->r1, c->stream);
@@ -1798,9 +1810,9 @@ int mpc3_mult(mpc3_ctx* c, const mpc3_share_t* a, const mpc3_share_t* b, mpc3_sh
 int mpc3_trunc(mpc3_ctx* c, const mpc3_trunc_pair_t* p, const mpc3_share_t* Z, mpc3_share_t* out) {
     int g = guard(c, true);
     if (g) return g;
-    if (!p || !valid(Z) || !valid(out)) return MPC3_E_ARG;
+    if (!p || !valid(Z) || !valid(out)) return fail(c, MPC3_E_ARG);
     const int64_t n = Z->rows * Z->cols;
-    if (p->n != n || out->rows * out->cols != n) return MPC3_E_SHAPE;
+    if (p->n != n || out->rows * out->cols != n) return fail(c, MPC3_E_SHAPE);
     return wrap(c, __func__, [&] {
         launch_trunc_shift(n, p->t, Z->m, p->rz.m, p->rz.r1, p->rz.r2, out->m, out->r1, out->r2, c->stream);
         ck(hipGetLastError());

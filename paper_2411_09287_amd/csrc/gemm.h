@@ -42,7 +42,12 @@ struct GemmArgs {
     // the workspace takes digit tiles only: K is split only where the 32-bit digit sums
     // require it, with atomic adds into the (zero-filled) output
     bool no_part;
+    // bytes of split-K partial sums the workspace can take (0: PART_MAX)
+    size_t part_max;
 };
+
+// The cap on split-K partial sums of one product.
+inline size_t part_cap(const GemmArgs& g);
 
 // Launch on `stream` with the chosen backend (0 = u64 VALU, 1 = int8 limbs on MFMA).
 hipError_t gemm(const GemmArgs& g, int variant, hipStream_t stream);
@@ -74,5 +79,7 @@ hipError_t fold_rows(const u64* XY, int64_t rows, const int8_t* ztiles, u64* out
 
 // Bytes of partial sums one product may use before the split count is cut back.
 constexpr size_t PART_MAX = (size_t)1 << 30;
+
+inline size_t part_cap(const GemmArgs& g) { return g.part_max && g.part_max < PART_MAX ? g.part_max : PART_MAX; }
 
 }  // namespace mpc3

@@ -984,8 +984,8 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             splits = std::max<int64_t>(splits, std::min<int64_t>(want, maxseg * Kp / 64));
         }
         const size_t plane = (size_t)nprod * g.M * g.N * 8 * nbl;
-        const bool part_ok = g.ws_alloc != nullptr && !g.no_part && plane * need <= PART_MAX;
-        if (part_ok) splits = std::min<int64_t>(splits, std::max<int64_t>(need, (int64_t)(PART_MAX / plane)));
+        const bool part_ok = g.ws_alloc != nullptr && !g.no_part && plane * need <= part_cap(g);
+        if (part_ok) splits = std::min<int64_t>(splits, std::max<int64_t>(need, (int64_t)(part_cap(g) / plane)));
         else splits = need;
         if (splits > 1 && !part_ok) {
             // without room for partials: atomic adds, into a zeroed output when the caller

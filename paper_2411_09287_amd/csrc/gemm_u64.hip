@@ -411,7 +411,7 @@ hipError_t gemm_u64(const GemmArgs& g, hipStream_t stream) {
         const int64_t want = (1024 + tiles - 1) / tiles;          // aim for ~1k workgroups
         const int64_t maxs = (g.K + BK - 1) / BK;                  // at least one K step per split
         int64_t cap = 4096;
-        if (part_ok) cap = std::min<int64_t>(cap, (int64_t)(PART_MAX / ((size_t)nprod * g.M * g.N * 8 * g.batch)));
+        if (part_ok) cap = std::min<int64_t>(cap, (int64_t)(part_cap(g) / ((size_t)nprod * g.M * g.N * 8 * g.batch)));
         ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({want, maxs, cap}));
     }
     int64_t kchunk = (g.K + ksplit - 1) / ksplit;
@@ -485,7 +485,8 @@ static bool rows_fit(const GemmArgs& g) {
         return false;
     for (int p = 1; p < na; ++p)
         if (g.A[p].s1 != g.A[0].s1) return false;
-    return true;
+    const int64_t kc = std::max<int64_t>(256, ((g.K + 1023) / 1024 + 63) / 64 * 64);
+    return (size_t)((g.K + kc - 1) / kc) * (size_t)(g.M * na * g.N) * 8 <= part_cap(g);
 }
 static hipError_t gemm_rows(const GemmArgs& g, hipStream_t stream) {
     const int na = std::max(1, g.shared);

@@ -139,6 +139,25 @@ def test_recording_rejects_calls_that_allocate_or_synchronise():
     cb.close()
 
 
+def test_recording_fails_with_a_recorded_call():
+    """A call refused by its own checks while recording (here the fixed workspace's limit)
+    makes the recording fail with that code; no graph is left behind."""
+    c = mpc3.Context(SEED, stream=torch.cuda.Stream())
+    X, W, Z = mpc3.DShare.empty(1 << 18, 8), mpc3.DShare.empty(8, 64), mpc3.DShare.empty(1 << 18, 64)
+    torch.cuda.synchronize()
+    c.capture_begin()
+    with pytest.raises(mpc3.Mpc3Error) as e:
+        c.inner_static(X, W, out=Z)
+    assert e.value.code == mpc3.E_LIMIT
+    with pytest.raises(mpc3.Mpc3Error) as e:
+        c.capture_end()
+    assert e.value.code == mpc3.E_LIMIT
+    with pytest.raises(mpc3.Mpc3Error) as e:
+        c.graph_launch(1)
+    assert e.value.code == mpc3.E_ARG
+    c.close()
+
+
 def test_recording_needs_a_stream_of_its_own():
     c = mpc3.Context(SEED, stream=torch.cuda.default_stream())
     with pytest.raises(mpc3.Mpc3Error) as e:

@@ -67,10 +67,10 @@ def test_static_matches_allocating_entry_point(variant, shapes):
 
 def test_static_limits_and_state():
     c = mpc3.Context(SEED)
-    # 2^23 outputs need 256 MiB of party sums: refused before any launch
-    X = mpc3.DShare.empty(1 << 17, 8)
+    # 2^24 outputs need 512 MiB of party sums: refused before any launch
+    X = mpc3.DShare.empty(1 << 18, 8)
     W = mpc3.DShare.empty(8, 64)
-    Z = mpc3.DShare.empty(1 << 17, 64)
+    Z = mpc3.DShare.empty(1 << 18, 64)
     with pytest.raises(mpc3.Mpc3Error) as e:
         c.inner_static(X, W, out=Z)
     assert e.value.code == mpc3.E_LIMIT
