@@ -519,86 +519,115 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
                     bool sparse = false) {
     hipStream_t s = c->cs;
     const int np = sparse ? 2 : 6;
-    for (int k = k0; k < R; ++k) {
-        const int64_t half = n / 2;
-        const uint32_t sub = ((uint32_t)v.inst << 8) | (uint32_t)k;
-        u64* h0 = c->sc->words(3 * 64);
-        u64* h2 = c->sc->words(3 * 64);
-        const Inj i_h0 = take_ver(c, MPC3_SITE_VER_H0_M1, v.inst, k);
-        const Inj i_h2 = take_ver(c, MPC3_SITE_VER_H2_GAMMA2, v.inst, k);
-        if (sparse && c->variant != MPC3_VARIANT_U64) {
-            // both products in one pass over the two planes on the matrix cores: per
-            // workgroup partial 64 x 64 matrices of h(0) and h(x) (P0's sums; P1's and
-            // P2's are 0), summed into H = [C0, 0, 0, C2, 0, 0]
-            u64* H = c->sc->words(6 * 4096);
-            zero(c, H + 4096, 2 * 4096 * 8);
-            zero(c, H + 4 * 4096, 2 * 4096 * 8);
-            const int groups = (int)std::min<int64_t>((half + 31) / 32, 1024);
-            u64* part = c->sc->words((int64_t)groups * 2 * 4096);
-            ck(hpair_sparse(XY, XY + n * 64, half, part, groups, s));
-            const OutView outs[2] = {oview(H, 64, 1), oview(H + 3 * 4096, 64, 1)};
-            ck(split_reduce(part, 64, 64, 2, groups, 1, outs, View{nullptr, 0, 0, 0}, false, s));
-            polyevl_from(c, v, H, P_VER_H0_R, P_VER_H0_GAMMA, sub, i_h0, Inj{-1, 0}, h0, slot(v, MPC3_LOG_H0_M1, k),
-                         slot(v, MPC3_LOG_H0_M2, k), slot(v, MPC3_LOG_H0_G2, k));
-            polyevl_from(c, v, H + 3 * 4096, P_VER_H2_R, P_VER_H2_GAMMA, sub, Inj{-1, 0}, i_h2, h2,
-                         slot(v, MPC3_LOG_H2_M1, k), slot(v, MPC3_LOG_H2_M2, k), slot(v, MPC3_LOG_H2_G2, k));
-        } else if (sparse) {
-            u64* F2 = c->sc->words(np * half * 64);
-            launch_at_x(XY, np, n, F2, s);        // f_i(x) = f_i(0) + x (f_i(1) - f_i(0))
-            polyevl_sparse(c, v, half, XY, 128, XY + n * 64, 128, P_VER_H0_R, P_VER_H0_GAMMA, sub, i_h0,
-                           Inj{-1, 0}, h0, slot(v, MPC3_LOG_H0_M1, k), slot(v, MPC3_LOG_H0_M2, k),
-                           slot(v, MPC3_LOG_H0_G2, k));
-            polyevl_sparse(c, v, half, F2, 64, F2 + half * 64, 64, P_VER_H2_R, P_VER_H2_GAMMA, sub, Inj{-1, 0},
-                           i_h2, h2, slot(v, MPC3_LOG_H2_M1, k), slot(v, MPC3_LOG_H2_M2, k),
-                           slot(v, MPC3_LOG_H2_G2, k));
-        } else {
-            u64* F2 = c->sc->words(np * half * 64);
-            launch_at_x(XY, np, n, F2, s);        // f_i(x) = f_i(0) + x (f_i(1) - f_i(0))
-            // h(0) and h(x) are independent: h(x) runs on a side stream (its workspace comes
-            // from the same bump allocator, so nothing is shared) and joins before round_finish
-            int lane_i = 0;
-            while (lane_i < mpc3_ctx::NV && c->vs[lane_i] != s) ++lane_i;
-            hipStream_t side = c->vs[(lane_i + 1) % mpc3_ctx::NV];
-            ck(hipEventRecord(c->ev_fork2, s));
-            ck(hipStreamWaitEvent(side, c->ev_fork2, 0));
-            {   // h(x) = sum f_i(x) g_i(x)
-                c->cs = side;
-                const u64* A[3] = {F2, F2 + half * 64, F2 + 2 * half * 64};
-                const u64* B[3] = {F2 + 3 * half * 64, F2 + 4 * half * 64, F2 + 5 * half * 64};
-                polyevl_run(c, v, half, A, 64, B, 64, P_VER_H2_R, P_VER_H2_GAMMA, sub, Inj{-1, 0}, i_h2, h2,
-                            slot(v, MPC3_LOG_H2_M1, k), slot(v, MPC3_LOG_H2_M2, k), slot(v, MPC3_LOG_H2_G2, k),
-                            nullptr, nullptr);
-                c->cs = s;
+    if (c->variant != MPC3_VARIANT_U64 && k0 < R) {
+        // matrix-core rounds, three launches each: the parties' h(0) and h(x) sums in one
+        // pass over the pairs, everything up to the point's multiplication matrix in one
+        // workgroup, and the fold
+        HPartyArgs ha{};
+        ha.dense = !sparse;
+        const int nparties = sparse ? 1 : 3;
+        ha.part = c->sc->words((int64_t)nparties * hpair_groups(n) * 256);
+        int8_t* zt = (int8_t*)c->sc->alloc(limb_btiles_bytes(64, 64));
+        for (int k = k0; k < R; ++k) {
+            const int64_t half = n / 2;
+            const uint32_t sub = ((uint32_t)v.inst << 8) | (uint32_t)k;
+            const Inj i_h0 = take_ver(c, MPC3_SITE_VER_H0_M1, v.inst, k);
+            const Inj i_h2 = take_ver(c, MPC3_SITE_VER_H2_GAMMA2, v.inst, k);
+            ha.XY = XY;
+            ha.n = n;
+            ck(hpair_party(ha, s));
+            RoundMidArgs m{};
+            m.k = c->keys; m.op = v.op; m.sub = sub;
+            m.part = ha.part; m.nparties = nparties; m.groups = hpair_groups(n);
+            m.inv = c->inv_dev; m.z = z;
+            m.inj_h0_m1 = i_h0.index >= 0 ? (int)i_h0.index : -1; m.e_h0_m1 = i_h0.e;
+            m.inj_h2_g2 = i_h2.index >= 0 ? (int)i_h2.index : -1; m.e_h2_g2 = i_h2.e;
+            m.log_h0[0] = slot(v, MPC3_LOG_H0_M1, k); m.log_h0[1] = slot(v, MPC3_LOG_H0_M2, k);
+            m.log_h0[2] = slot(v, MPC3_LOG_H0_G2, k);
+            m.log_h2[0] = slot(v, MPC3_LOG_H2_M1, k); m.log_h2[1] = slot(v, MPC3_LOG_H2_M2, k);
+            m.log_h2[2] = slot(v, MPC3_LOG_H2_G2, k);
+            m.log_zeta = slot(v, MPC3_LOG_ZETA, k);
+            m.ztiles = zt;
+            launch_round_mid(m, s);
+            ck(hipGetLastError());
+            // two Pi_PolyEvl (P0 -> P2 offline, P1 <-> P2 online), the round, zeta's reveal
+            for (int q = 0; q < 2; ++q) {
+                send(c, MPC3_PH_VERIFY_OFFLINE, 0, 2, 8 * 64);
+                send(c, MPC3_PH_VERIFY_ONLINE, 1, 2, 8 * 64);
+                send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8 * 64);
             }
-            {   // h(0) = sum f_i(0) g_i(0): rows 2i of x and y
-                const u64* A[3] = {XY, XY + n * 64, XY + 2 * n * 64};
-                const u64* B[3] = {XY + 3 * n * 64, XY + 4 * n * 64, XY + 5 * n * 64};
-                polyevl_run(c, v, half, A, 128, B, 128, P_VER_H0_R, P_VER_H0_GAMMA, sub, i_h0, Inj{-1, 0}, h0,
-                            slot(v, MPC3_LOG_H0_M1, k), slot(v, MPC3_LOG_H0_M2, k), slot(v, MPC3_LOG_H0_G2, k),
-                            nullptr, nullptr);
-            }
-            ck(hipEventRecord(c->ev_join2[0], side));
-            ck(hipStreamWaitEvent(s, c->ev_join2[0], 0));
-        }
-        c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
-        // fold: row i <- f_i(0) (1 - zeta) + f_i(1) zeta on every stored plane.  A pair's two
-        // rows are 128 consecutive words, and the planes are stacked, so the np planes run as
-        // one product of np * half rows of 128 words (row c * half + i = rows 2i, 2i + 1 of
-        // plane c, n = 2 half) with [Mat(1 - zeta); Mat(zeta)]
-        u64* Wz = c->sc->words(4096);
-        round_finish(c, v, sub, k, h0, h2, z, Wz);
-        u64* XYn = c->sc->words(np * half * 64);
-        if (c->variant != MPC3_VARIANT_U64) {
-            int8_t* zt = (int8_t*)c->sc->alloc(limb_btiles_bytes(64, 64));
-            ck(limb_btiles(view(Wz, 64, 1), 64, 64, zt, s));
+            c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
+            count_reveal(c, MPC3_PH_VERIFY_ONLINE);
+            u64* XYn = c->sc->words(np * half * 64);
             ck(fold_rows(XY, np * half, zt, XYn, s));
-        } else {
-            u64* Wz2 = c->sc->words(2 * 4096);
-            launch_mat_pair(Wz, Wz2, s);
-            run_gemm(c, plain(np * half, 64, 128, view(XY, 128, 1), view(Wz2, 64, 1), oview(XYn, 64, 1), false));
+            XY = XYn;
+            n = half;
         }
-        XY = XYn;
-        n = half;
+    } else {
+        // the vector-ALU kernel family: the h products as party products and the fold as a
+        // product with [Mat(1 - zeta); Mat(zeta)]
+        for (int k = k0; k < R; ++k) {
+            const int64_t half = n / 2;
+            const uint32_t sub = ((uint32_t)v.inst << 8) | (uint32_t)k;
+            u64* h0 = c->sc->words(3 * 64);
+            u64* h2 = c->sc->words(3 * 64);
+            const Inj i_h0 = take_ver(c, MPC3_SITE_VER_H0_M1, v.inst, k);
+            const Inj i_h2 = take_ver(c, MPC3_SITE_VER_H2_GAMMA2, v.inst, k);
+            if (sparse) {
+                u64* F2 = c->sc->words(np * half * 64);
+                launch_at_x(XY, np, n, F2, s);        // f_i(x) = f_i(0) + x (f_i(1) - f_i(0))
+                polyevl_sparse(c, v, half, XY, 128, XY + n * 64, 128, P_VER_H0_R, P_VER_H0_GAMMA, sub, i_h0,
+                               Inj{-1, 0}, h0, slot(v, MPC3_LOG_H0_M1, k), slot(v, MPC3_LOG_H0_M2, k),
+                               slot(v, MPC3_LOG_H0_G2, k));
+                polyevl_sparse(c, v, half, F2, 64, F2 + half * 64, 64, P_VER_H2_R, P_VER_H2_GAMMA, sub, Inj{-1, 0},
+                               i_h2, h2, slot(v, MPC3_LOG_H2_M1, k), slot(v, MPC3_LOG_H2_M2, k),
+                               slot(v, MPC3_LOG_H2_G2, k));
+            } else {
+                u64* F2 = c->sc->words(np * half * 64);
+                launch_at_x(XY, np, n, F2, s);        // f_i(x) = f_i(0) + x (f_i(1) - f_i(0))
+                // h(0) and h(x) are independent: h(x) runs on a side stream (its workspace comes
+                // from the same bump allocator, so nothing is shared) and joins before round_finish
+                int lane_i = 0;
+                while (lane_i < mpc3_ctx::NV && c->vs[lane_i] != s) ++lane_i;
+                hipStream_t side = c->vs[(lane_i + 1) % mpc3_ctx::NV];
+                ck(hipEventRecord(c->ev_fork2, s));
+                ck(hipStreamWaitEvent(side, c->ev_fork2, 0));
+                {   // h(x) = sum f_i(x) g_i(x)
+                    c->cs = side;
+                    const u64* A[3] = {F2, F2 + half * 64, F2 + 2 * half * 64};
+                    const u64* B[3] = {F2 + 3 * half * 64, F2 + 4 * half * 64, F2 + 5 * half * 64};
+                    polyevl_run(c, v, half, A, 64, B, 64, P_VER_H2_R, P_VER_H2_GAMMA, sub, Inj{-1, 0}, i_h2, h2,
+                                slot(v, MPC3_LOG_H2_M1, k), slot(v, MPC3_LOG_H2_M2, k), slot(v, MPC3_LOG_H2_G2, k),
+                                nullptr, nullptr);
+                    c->cs = s;
+                }
+                {   // h(0) = sum f_i(0) g_i(0): rows 2i of x and y
+                    const u64* A[3] = {XY, XY + n * 64, XY + 2 * n * 64};
+                    const u64* B[3] = {XY + 3 * n * 64, XY + 4 * n * 64, XY + 5 * n * 64};
+                    polyevl_run(c, v, half, A, 128, B, 128, P_VER_H0_R, P_VER_H0_GAMMA, sub, i_h0, Inj{-1, 0}, h0,
+                                slot(v, MPC3_LOG_H0_M1, k), slot(v, MPC3_LOG_H0_M2, k), slot(v, MPC3_LOG_H0_G2, k),
+                                nullptr, nullptr);
+                }
+                ck(hipEventRecord(c->ev_join2[0], side));
+                ck(hipStreamWaitEvent(s, c->ev_join2[0], 0));
+            }
+            c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
+            // fold: row i <- f_i(0) (1 - zeta) + f_i(1) zeta on every stored plane.  A pair's two
+            // rows are 128 consecutive words, and the planes are stacked, so the np planes run as
+            // one product of np * half rows of 128 words (row c * half + i = rows 2i, 2i + 1 of
+            // plane c, n = 2 half) with [Mat(1 - zeta); Mat(zeta)]
+            u64* Wz = c->sc->words(4096);
+            round_finish(c, v, sub, k, h0, h2, z, Wz);
+            u64* XYn = c->sc->words(np * half * 64);
+            {
+                u64* Wz2 = c->sc->words(2 * 4096);
+                launch_mat_pair(Wz, Wz2, s);
+                run_gemm(c, plain(np * half, 64, 128, view(XY, 128, 1), view(Wz2, 64, 1), oview(XYn, 64, 1),
+                                  false));
+            }
+            XY = XYn;
+            n = half;
+        }
     }
     if (sparse) {   // back to six planes for the final check: x = (0, r1, 0), y = (0, 0, r2)
         u64* D6 = c->sc->words(6 * n * 64);

@@ -66,11 +66,23 @@ hipError_t limb_btiles(const View& B, int64_t K, int64_t N, int8_t* out, hipStre
 // Fills n 32-bit words with 0 (a kernel, so that it can also be captured in a graph).
 hipError_t zero_words32(void* p, int64_t n, hipStream_t stream);
 
-// The h(0) and h(x) products of a Pi_Reduce round over two planes X (x side) and Y (y side)
-// of 2 npairs rows of 64 words: per workgroup g < groups, part[g] = (C0, C2), 2 x 64 x 64
-// words, C0 = sum_i X[2i]^T Y[2i], C2 = sum_i F_X(i)^T F_Y(i), F(i) = f(2i) + x (f(2i+1) -
-// f(2i)) in GR(2^64, 64); the workgroups' partials add up to the products.
-hipError_t hpair_sparse(const u64* X, const u64* Y, int64_t npairs, u64* part, int groups, hipStream_t stream);
+// The h(0) and h(x) party sums of a Pi_Reduce round over planes of n rows (pairs (2i, 2i+1))
+// stacked in XY (plane p at XY + p n 64): dense, six planes (x: m, r1, r2; y: m, r1, r2) and
+// the three parties' sums; sparse, two planes (x's [r]_1, y's [r]_2) and P0's sum alone.
+// Each of the G = hpair_groups(n) workgroups per party writes its partial: part[(party G +
+// g) 256 + point 128 + i], point 0 = h(0), 1 = h(x), i < 64 the anti-diagonal sums j + l = i
+// of the party's 64 x 64 outer-product sum, i >= 64 those with j + l = i (= 64 + k);
+// summing the partials and reducing the second half modulo the ring's modulus gives the
+// party's ring element.
+struct HPartyArgs {
+    const u64* XY;
+    int64_t n;
+    int64_t npairs, nblocks;      // set by hpair_party
+    bool dense;
+    u64* part;                    // (3 or 1) x G x 256 words
+};
+int hpair_groups(int64_t n);
+hipError_t hpair_party(const HPartyArgs& a, hipStream_t stream);
 
 // The fold of a Pi_Reduce round on the matrix cores: rows of 128 words are pairs (f(0),
 // f(1)) of 64-word GR(2^64, 64) elements; out row i (64 words) = f(0) + (f(1) - f(0)) Z,

@@ -14,6 +14,7 @@
 #include <type_traits>
 
 #include "gemm.h"
+#include "limb_digits.h"
 
 namespace mpc3 {
 
@@ -24,9 +25,15 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int TM = 64, TN = 64, KB = 32, KSEG = 8192, NT = 256;
-constexpr u64 OFF = 0x8080808080808080ull;
-constexpr int PLANE = 64 * KB;            // bytes of one digit plane of a 64 x 32 tile
+using limb::KB;
+using limb::PLANE;
+using limb::TILE_BYTES;
+using limb::to_digits;
+using limb::swz;
+using limb::toff;
+using limb::OFF;
+using limb::bt4;
+constexpr int TM = 64, TN = 64, KSEG = 8192, NT = 256;
 
 // One operand of a product segment: v(r, k) = sum_i c_i P_i[b + r*s_r + k*s_k].
 struct Opnd {
@@ -93,39 +100,6 @@ __device__ __forceinline__ void load8(const Opnd& o, int64_t row, int64_t k0, in
             }
         }
         w[i] = v;
-    }
-}
-
-// 4x4 byte transpose: out_j byte i = in_i byte j.
-__device__ __forceinline__ void bt4(u32 a, u32 b, u32 c, u32 d, u32& o0, u32& o1, u32& o2, u32& o3) {
-    const u32 ab_lo = (a & 0x00FF00FFu) | ((b & 0x00FF00FFu) << 8);     // a0 b0 a2 b2
-    const u32 ab_hi = ((a >> 8) & 0x00FF00FFu) | (b & 0xFF00FF00u);     // a1 b1 a3 b3
-    const u32 cd_lo = (c & 0x00FF00FFu) | ((d & 0x00FF00FFu) << 8);
-    const u32 cd_hi = ((c >> 8) & 0x00FF00FFu) | (d & 0xFF00FF00u);
-    o0 = (ab_lo & 0xFFFFu) | (cd_lo << 16);
-    o2 = (ab_lo >> 16) | (cd_lo & 0xFFFF0000u);
-    o1 = (ab_hi & 0xFFFFu) | (cd_hi << 16);
-    o3 = (ab_hi >> 16) | (cd_hi & 0xFFFF0000u);
-}
-
-// Balanced digits of 8 words: q[d] byte i = digit d of word i.
-__device__ __forceinline__ void to_digits(const u64 w[8], u64 q[8]) {
-    u32 lo[8], hi[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const u64 v = (w[i] + OFF) ^ OFF;
-        lo[i] = (u32)v;
-        hi[i] = (u32)(v >> 32);
-    }
-    u32 t0[4], t1[4], t2[4], t3[4];
-    bt4(lo[0], lo[1], lo[2], lo[3], t0[0], t0[1], t0[2], t0[3]);   // digits 0..3 of words 0..3
-    bt4(lo[4], lo[5], lo[6], lo[7], t1[0], t1[1], t1[2], t1[3]);   // digits 0..3 of words 4..7
-    bt4(hi[0], hi[1], hi[2], hi[3], t2[0], t2[1], t2[2], t2[3]);   // digits 4..7 of words 0..3
-    bt4(hi[4], hi[5], hi[6], hi[7], t3[0], t3[1], t3[2], t3[3]);   // digits 4..7 of words 4..7
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        q[d] = (u64)t0[d] | ((u64)t1[d] << 32);
-        q[4 + d] = (u64)t2[d] | ((u64)t3[d] << 32);
     }
 }
 
@@ -259,16 +233,7 @@ __global__ __launch_bounds__(NT, 2) void k_lgemm(LArgs a) {
 // balanced digits are written once to a tile buffer and the product kernel copies them to
 // LDS unchanged; only A is converted in the kernel.  A tile is k-block kb (32 deep) of 64
 // consecutive B columns: 8 digit planes x 64 rows x 32 bytes (16 KiB), stored exactly as
-// it sits in LDS.  Within a row the two 16-byte halves are swapped when swz(row) = 1, so
-// the 16-byte fragment reads of 16 consecutive rows fall on distinct banks.
-constexpr int TILE_BYTES = 8 * PLANE;
-
-__device__ __forceinline__ int swz(int row) { return ((row >> 2) ^ (row >> 3)) & 1; }
-
-// byte offset of digit plane d, tile row r, k-octet o (8 bytes) within a tile
-__device__ __forceinline__ int toff(int d, int r, int o) {
-    return d * PLANE + r * KB + (((o >> 1) ^ swz(r)) << 4) + ((o & 1) << 3);
-}
+// it sits in LDS (limb_digits.h).
 
 // Digit tiles of up to five operands (rows x K, any strides, optional two-plane
 // combination), operand blockIdx.y: tile (t, kb) at byte (t * nkb + kb) * TILE_BYTES;
@@ -675,108 +640,172 @@ Opnd combo(const View* v, int64_t b, bool transpose, int64_t rows, int i0, int c
 
 
 // ---------------------------------------------------------------------------
-// The two Pi_PolyEvl products of a Pi_Reduce round over the truncation gates' two non-zero
-// planes (the x side's [r]_1 plane X and the y side's [r]_2 plane Y, n rows of 64 words,
-// pairs (2i, 2i+1)), in one pass over the rows:
-//     C0 = sum_i X[2i]^T Y[2i]            (h(0): the 64 x 64 outer products, P0's sum)
-//     C2 = sum_i F_X(i)^T F_Y(i),  F(i) = f(2i) + x (f(2i+1) - f(2i))   (h(x))
-// A workgroup takes blocks of 32 pairs: wave w reads pairs 8w .. 8w+7 (lane = coefficient,
-// 512 coalesced bytes per row), forms f(2i) and F(i) in registers (x (.) by a shift across
-// the lanes), and writes their balanced digits as transposed k-octets (row = coefficient,
-// k = pair) to LDS; then each wave multiplies one 32 x 32 quadrant of C0 and of C2 on the
-// matrix cores (K = 32 pairs per block) and adds the recombined 64-bit values to its
-// running sums.  One 2 x 64 x 64 partial per workgroup (part), summed afterwards.
+// The two Pi_PolyEvl products of a Pi_Reduce round, h(0) and h(x), as the parties' local
+// sums, in one pass over the stored pairs (f(2i), f(2i+1)) of every plane:
+//     at 0:  sum_i a(f_i(0)) (x) b(g_i(0)),   at x:  sum_i a(F_i) (x) b(G_i),
+//     F_i = f(2i) + x (f(2i+1) - f(2i))
+// where (x) is the 64 x 64 outer product of the coefficient vectors (its anti-diagonal sums,
+// reduced modulo the ring's modulus, are the ring product) and a, b are the combinations of
+// share planes one party multiplies: a workgroup takes one party (blockIdx.y) and adds up
+// its segments (a . b products) over blocks of 32 pairs.  Wave w reads pairs 8w .. 8w+7
+// (lane = coefficient, 512 coalesced bytes per row), forms both points in registers (x (.)
+// is a shift across the lanes), and writes their balanced digits as transposed k-octets
+// (row = coefficient, k = pair) to LDS; each wave then multiplies one 32 x 32 quadrant of
+// both outer products on the matrix cores and adds the recombined 64-bit values to its
+// running sums.  At the end the workgroup folds its two 64 x 64 sums to anti-diagonal sums
+// (lo: j + l = k, hi: j + l = 64 + k) and adds them atomically into acc; the reduction
+// modulo the ring's modulus is linear and is left to the consumer.
 // ---------------------------------------------------------------------------
-constexpr int HP_OPS = 4;                       // X f0, X F, Y f0, Y F
-__global__ __launch_bounds__(NT, 2) void k_hpair(const u64* X, const u64* Y, int64_t npairs, int64_t nblocks,
-                                                 u64* part) {
-    __shared__ __attribute__((aligned(16))) int8_t T[HP_OPS][8 * PLANE];
+constexpr int HP_OPS = 4;                       // a f(0), a F, b f(0), b F
+
+// Segment s of party p's sum, side 0 (a, the x side) or 1 (b, the y side): c0 * plane i0 +
+// c1 * plane i1.  Dense (six planes x: m 0, r1 1, r2 2; y: m 3, r1 4, r2 5), the sums of
+// k_polyevl_finish: P0 (r1 + r2)_x (r1 + r2)_y; P1 m_x r1_y + r1_x m_y; P2 m_x (m_y - r2_y)
+// - r2_x m_y.  Sparse (the truncation gates: x's [r]_1 plane 0, y's [r]_2 plane 1): P0's
+// only product, plane 0 times plane 1.
+struct HSide {
+    int i0, c0, i1, c1;
+};
+__device__ constexpr HSide hseg(bool dense, int party, int s, int side) {
+    return !dense ? (side == 0 ? HSide{0, 1, 0, 0} : HSide{1, 1, 0, 0})
+           : party == 0 ? (side == 0 ? HSide{1, 1, 2, 1} : HSide{4, 1, 5, 1})
+           : party == 1 ? (s == 0 ? (side == 0 ? HSide{0, 1, 0, 0} : HSide{4, 1, 0, 0})
+                                  : (side == 0 ? HSide{1, 1, 0, 0} : HSide{3, 1, 0, 0}))
+                        : (s == 0 ? (side == 0 ? HSide{0, 1, 0, 0} : HSide{3, 1, 5, -1})
+                                  : (side == 0 ? HSide{2, -1, 0, 0} : HSide{3, 1, 0, 0}));
+}
+__device__ constexpr int hnseg(bool dense, int party) { return !dense || party == 0 ? 1 : 2; }
+
+__device__ __forceinline__ u64 hp_load(const u64* XY, int64_t n, const HSide& sd, int64_t row, int lane) {
+    u64 v = XY[(int64_t)sd.i0 * n * 64 + row * 64 + lane];
+    if (sd.c0 < 0) v = 0 - v;
+    if (sd.c1) {
+        const u64 x = XY[(int64_t)sd.i1 * n * 64 + row * 64 + lane];
+        v += sd.c1 > 0 ? x : (0 - x);
+    }
+    return v;
+}
+
+// One side of a segment for the wave's 8 pairs of block blk: f(0) and F = f(0) + x (f(1) -
+// f(0)) of the combination, as balanced-digit k-octets (row = coefficient lane) in tiles
+// T0 (f(0)) and T1 (F).
+__device__ __forceinline__ void hp_side(const HPartyArgs& a, const HSide& sd, int64_t blk, int w, int lane,
+                                        int8_t* T0, int8_t* T1) {
+    u64 ev[8], ov[8];
+#pragma unroll
+    for (int pq = 0; pq < 8; ++pq) {
+        const int64_t pr = blk * 32 + w * 8 + pq;
+        const bool in = pr < a.npairs;
+        ev[pq] = in ? hp_load(a.XY, a.n, sd, 2 * pr, lane) : 0;
+        ov[pq] = in ? hp_load(a.XY, a.n, sd, 2 * pr + 1, lane) : 0;
+    }
+    u64 q[8];
+    to_digits(ev, q);
+#pragma unroll
+    for (int d = 0; d < 8; ++d) *(u64*)(T0 + d * PLANE + w * 512 + lane * 8) = q[d];
+#pragma unroll
+    for (int pq = 0; pq < 8; ++pq) {
+        const u64 e = ev[pq];
+        const u64 dd = ov[pq] - e;
+        const u64 top = __shfl(dd, 63, 64);
+        u64 xd = __shfl_up(dd, 1, 64);
+        if (lane == 0) xd = 0;
+        if (lane == 0 || lane == 1 || lane == 3 || lane == 4) xd -= top;
+        ov[pq] = e + xd;
+    }
+    to_digits(ov, q);
+#pragma unroll
+    for (int d = 0; d < 8; ++d) *(u64*)(T1 + d * PLANE + w * 512 + lane * 8) = q[d];
+}
+
+template <bool DENSE, int PARTY>
+__device__ __forceinline__ void hp_party(const HPartyArgs& a, int8_t (*T)[8 * PLANE], u64 c0[16], u64 c2[16]) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wy = w >> 1, wx = w & 1, r = lane & 31, kh = (lane >> 5) * 16;
     const int arow = wy * 32 + r, brow = wx * 32 + r;
+    for (int64_t blk = blockIdx.x; blk < a.nblocks; blk += gridDim.x) {
+#pragma unroll 1
+        for (int sg = 0; sg < hnseg(DENSE, PARTY); ++sg) {
+            hp_side(a, hseg(DENSE, PARTY, sg, 0), blk, w, lane, T[0], T[1]);
+            hp_side(a, hseg(DENSE, PARTY, sg, 1), blk, w, lane, T[2], T[3]);
+            __syncthreads();
+#pragma unroll
+            for (int pt = 0; pt < 2; ++pt) {            // point 0: f(0) products; point 1: F products
+                const int8_t* TA = T[pt];
+                const int8_t* TB = T[2 + pt];
+                v4i A[8], B[8];
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    A[d] = frag<false>(TA + d * PLANE, arow, kh);
+                    B[d] = frag<false>(TB + d * PLANE, brow, kh);
+                }
+                // digit plane s2 of the product (sum over i + j = s2 of A_i B_j) on one
+                // accumulator at a time, recombined into the 64-bit sums right away
+#pragma unroll
+                for (int s2 = 0; s2 < 8; ++s2) {
+                    v16i acc = v16i{0};
+#pragma unroll
+                    for (int i = 0; i <= s2; ++i)
+                        acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i], B[s2 - i], acc, 0, 0, 0);
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const u64 val = ((u64)(int64_t)acc[v]) << (8 * s2);
+                        if (pt == 0) c0[v] += val;
+                        else c2[v] += val;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <bool DENSE>
+__global__ __launch_bounds__(NT, 2) void k_hpair_party(HPartyArgs a) {
+    __shared__ __attribute__((aligned(16))) int8_t T[HP_OPS][8 * PLANE];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wy = w >> 1, wx = w & 1;
+    const int party = blockIdx.y;
     u64 c0[16], c2[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) c0[v] = c2[v] = 0;
-    for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
-        // the 8 pairs of this wave per lane (= coefficient): f(2i) and F(i) of both sides,
-        // then their balanced digits as k-octets (to_digits: q[d] byte i = digit d of word i)
-        u64 wv[HP_OPS][8];
-        // every load of the block first (32 words per lane in flight), then the arithmetic
-        u64 ev[2][8], ov[2][8];
-#pragma unroll
-        for (int pq = 0; pq < 8; ++pq) {
-            const int64_t pr = blk * 32 + w * 8 + pq;
-            const bool in = pr < npairs;
-#pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                const u64* P = side ? Y : X;
-                ev[side][pq] = in ? P[(2 * pr) * 64 + lane] : 0;
-                ov[side][pq] = in ? P[(2 * pr + 1) * 64 + lane] : 0;
-            }
-        }
-#pragma unroll
-        for (int pq = 0; pq < 8; ++pq) {
-#pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                const u64 e = ev[side][pq];
-                const u64 d = ov[side][pq] - e;
-                const u64 top = __shfl(d, 63, 64);
-                u64 xd = __shfl_up(d, 1, 64);
-                if (lane == 0) xd = 0;
-                if (lane == 0 || lane == 1 || lane == 3 || lane == 4) xd -= top;
-                wv[2 * side][pq] = e;
-                wv[2 * side + 1][pq] = e + xd;
-            }
-        }
-        u64 q[HP_OPS][8];
-#pragma unroll
-        for (int o = 0; o < HP_OPS; ++o) to_digits(wv[o], q[o]);
-        // transposed tile of each operand: plane d, k-octet w, row = coefficient lane
-#pragma unroll
-        for (int o = 0; o < HP_OPS; ++o)
-#pragma unroll
-            for (int d = 0; d < 8; ++d) *(u64*)(T[o] + d * PLANE + w * 512 + lane * 8) = q[o][d];
-        __syncthreads();
-#pragma unroll
-        for (int pr = 0; pr < 2; ++pr) {            // pr 0: C0 = Xf0^T Yf0; pr 1: C2 = XF^T YF
-            const int8_t* TA = T[pr];
-            const int8_t* TB = T[2 + pr];
-            v16i acc[8];
-#pragma unroll
-            for (int s2 = 0; s2 < 8; ++s2) acc[s2] = v16i{0};
-            v4i B[8];
-#pragma unroll
-            for (int d = 0; d < 8; ++d) B[d] = frag<false>(TB + d * PLANE, brow, kh);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const v4i A = frag<false>(TA + i * PLANE, arow, kh);
-#pragma unroll
-                for (int s2 = i; s2 < 8; ++s2)
-                    acc[s2] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[s2 - i], acc[s2], 0, 0, 0);
-            }
-            // second half of the 32 pairs: k 16..31 is read by lanes 32..63 (kh) -- the
-            // 32-deep k-block is complete in one pass
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                u64 val = 0;
-#pragma unroll
-                for (int s2 = 0; s2 < 8; ++s2) val += ((u64)(int64_t)acc[s2][v]) << (8 * s2);
-                if (pr == 0) c0[v] += val;
-                else c2[v] += val;
-            }
-        }
-        __syncthreads();
-    }
-    // quadrant (wy, wx): row (coefficient of X) 8 (v >> 2) + 4 (lane >> 5) + (v & 3), column
-    // (coefficient of Y) lane & 31
-    u64* P0 = part + (int64_t)blockIdx.x * 2 * 4096;
+    if (!DENSE || party == 0) hp_party<DENSE, 0>(a, T, c0, c2);
+    else if (party == 1) hp_party<DENSE, 1>(a, T, c0, c2);
+    else hp_party<DENSE, 2>(a, T, c0, c2);
+    // the two sums as 64 x 64 matrices in LDS (row j = coefficient of a, column l = of b)
+    u64* M0 = (u64*)T[0];
+    u64* M2 = (u64*)T[2];
     const int n = wx * 32 + (lane & 31);
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int m = wy * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        P0[m * 64 + n] = c0[v];
-        P0[4096 + m * 64 + n] = c2[v];
+        M0[m * 64 + n] = c0[v];
+        M2[m * 64 + n] = c2[v];
     }
+    __syncthreads();
+    // thread (q, k): rows 16q .. 16q+15 of anti-diagonals k and 64 + k of both matrices
+    const int k = t & 63, qq = t >> 6;
+    u64 lo0 = 0, hi0 = 0, lo2 = 0, hi2 = 0;
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+        const int j = 16 * qq + jj;
+        const int col = j <= k ? k - j : k + 64 - j;
+        const u64 x0 = M0[j * 64 + col], x2 = M2[j * 64 + col];
+        if (j <= k) { lo0 += x0; lo2 += x2; }
+        else { hi0 += x0; hi2 += x2; }
+    }
+    __syncthreads();
+    u64* red = (u64*)T[1];                         // [q][point][lo 64 | hi 64]
+    red[(qq * 2 + 0) * 128 + k] = lo0;
+    red[(qq * 2 + 0) * 128 + 64 + k] = hi0;
+    red[(qq * 2 + 1) * 128 + k] = lo2;
+    red[(qq * 2 + 1) * 128 + 64 + k] = hi2;
+    __syncthreads();
+    // this workgroup's partial: [point][lo 64 | hi 64], thread t = point (t >> 7), word t & 127
+    u64 sum = 0;
+#pragma unroll
+    for (int q2 = 0; q2 < 4; ++q2) sum += red[(q2 * 2 + (t >> 7)) * 128 + (t & 127)];
+    a.part[((int64_t)party * gridDim.x + blockIdx.x) * 256 + t] = sum;
 }
 
 
@@ -872,10 +901,18 @@ hipError_t limb_btiles(const View& B, int64_t K, int64_t N, int8_t* out, hipStre
     return hipGetLastError();
 }
 
-hipError_t hpair_sparse(const u64* X, const u64* Y, int64_t npairs, u64* part, int groups, hipStream_t st) {
-    const int64_t nblocks = (npairs + 31) / 32;
-    if (groups <= 0 || nblocks <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_hpair, dim3((unsigned)groups), dim3(NT), 0, st, X, Y, npairs, nblocks, part);
+int hpair_groups(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n / 2 + 31) / 32, 512)); }
+
+hipError_t hpair_party(const HPartyArgs& args, hipStream_t st) {
+    HPartyArgs a = args;
+    a.npairs = a.n / 2;
+    a.nblocks = (a.npairs + 31) / 32;
+    const int groups = hpair_groups(a.n);
+    if (a.nblocks <= 0) return hipErrorInvalidValue;
+    if (a.dense)
+        hipLaunchKernelGGL(k_hpair_party<true>, dim3((unsigned)groups, 3), dim3(NT), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_hpair_party<false>, dim3((unsigned)groups, 1), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 

@@ -91,6 +91,25 @@ struct RoundArgs {
     u64* mat_out;          // nullable: multiplication matrix of zeta (64 x 64, row j = zeta x^j)
 };
 void launch_round_finish(const RoundArgs& a, hipStream_t s);
+// Everything of a Pi_Reduce round between the h products and the fold, in one launch: the
+// party sums from the partial anti-diagonal sums of hpair_party, both Pi_PolyEvl exchanges, the
+// revealed point, the Lagrange step of z and the digit tiles of the point's multiplication
+// matrix (the fold's B operand, limb_btiles layout).
+struct RoundMidArgs {
+    Keys k;
+    u32 op, sub;
+    const u64* part;       // hpair_party's partials: nparties x groups x 256 words
+    int nparties, groups;
+    const u64* inv;        // inv_x, inv_1mx, inv_xxm1 (3*64)
+    u64* z;                // share (3*64), updated in place
+    int inj_h0_m1, inj_h2_g2;   // coefficient index or -1
+    u64 e_h0_m1, e_h2_g2;
+    u64* log_h0[3];        // m1, m2, g2 of h(0) (nullable)
+    u64* log_h2[3];        // m1, m2, g2 of h(x) (nullable)
+    u64* log_zeta;         // nullable
+    int8_t* ztiles;        // two 32-deep k-blocks of digit tiles (2 x 16 KiB)
+};
+void launch_round_mid(const RoundMidArgs& a, hipStream_t s);
 // x'_i = Pi_Mult over GR of x_i and alpha from the party products (n x 64 each), with fresh masks.
 void launch_xp_epilogue(int64_t n, const Keys& k, u32 op, u32 sub, const u64* C0, const u64* C1,
                         const u64* C2, u64* XPm, u64* XP1, u64* XP2, hipStream_t s);

@@ -1,5 +1,6 @@
 // Elementwise, PRG and Galois-ring kernels of the protocol (gfx950).
 #include "kernels.h"
+#include "limb_digits.h"
 
 namespace mpc3 {
 
@@ -703,6 +704,191 @@ __global__ void k_round_finish(RoundArgs a) {
     }
 }
 
+// Orders the LDS accesses of one wave around it (a wave's LDS operations complete in order;
+// this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// reduce_lane within one wave (sh: 64 words of LDS of the wave's own)
+__device__ u64 reduce_wave(u64 lo, u64 hi, u64* sh, int k) {
+    sh[k] = hi;
+    wave_sync();
+    u64 v = lo;
+#pragma unroll
+    for (int q = 0; q < NTAPS; ++q) {
+        const int j = k - tap(q);
+        if (j >= 0) v -= sh[j];
+    }
+#pragma unroll
+    for (int q = 0; q < NTAPS; ++q) {
+        const int p = k - tap(q);
+        if (p >= 0 && p <= 2) {
+            u64 ov = 0;
+#pragma unroll
+            for (int r = 0; r < NTAPS; ++r) {
+                const int j = 64 + p - tap(r);
+                if (j >= 0 && j <= 62) ov -= sh[j];
+            }
+            v -= ov;
+        }
+    }
+    wave_sync();
+    return v;
+}
+
+// Coefficient k of a * b in GR(2^64, 64) within one wave (a, b: LDS written by this wave).
+__device__ u64 gr_mul_wave(const u64* a, const u64* b, u64* sh, int k) {
+    wave_sync();
+    u64 lo = 0, hi = 0;
+    for (int i = 0; i < 64; ++i) {
+        const u64 p = a[i] * b[(k - i) & 63];
+        if (i <= k) lo += p; else hi += p;
+    }
+    return reduce_wave(lo, hi, sh, k);
+}
+
+// The middle of a Pi_Reduce round in one workgroup, from the partial anti-diagonal sums of
+// the parties' h(0) and h(x) products (hpair_party): their sum and reduction modulo the
+// ring's modulus, both Pi_PolyEvl exchanges (P0's [Gamma]_2, P1's and P2's m shares, as
+// k_polyevl_finish), the revealed point zeta, the Lagrange step of the claim z (as
+// k_round_finish), and the digit tiles of the multiplication matrix of zeta for the fold
+// on the matrix cores.  Every keystream row the step draws is drawn at once, first; the
+// waves then run their ring products without block-wide barriers: waves 0..2 the Lagrange
+// weights and the three planes of z, wave 3 the point's matrix and its tiles.
+__global__ __launch_bounds__(256) void k_round_mid(RoundMidArgs a) {
+    __shared__ u64 rows[9][64];
+    __shared__ u64 raw[3][256];                       // [party][point][lo 64 | hi 64]
+    __shared__ u64 ssum[6][64];                       // [point * 3 + party]
+    __shared__ u64 sh[4][64];
+    __shared__ u64 opa[4][64], opb[4][64];
+    __shared__ u64 zeta[64], zm1[64], zmx[64], L[3][64], hh[3][3][64];
+    __shared__ u64 mat[64 * 64];
+    const int t = threadIdx.x, w = t >> 6, k = t & 63;
+    if (t < 72) {
+        // rows 0..2: h(0)'s r1, r2 and [Gamma]_1 masks; 3..5: the same for h(x); 6..8: zeta
+        const int row = t >> 3, b = t & 7;
+        const int grp = row / 3, comp = row % 3;
+        Key key;
+        u32 pur;
+        if (grp < 2) {
+            key = comp == 1 ? a.k.k02 : a.k.k01;
+            pur = comp == 2 ? (grp ? P_VER_H2_GAMMA : P_VER_H0_GAMMA) : (grp ? P_VER_H2_R : P_VER_H0_R);
+        } else {
+            key = comp == 0 ? a.k.k12 : comp == 1 ? a.k.k01 : a.k.k02;
+            pur = P_VER_ZETA;
+        }
+        const u32 cc = grp < 2 ? (comp == 2 ? 1u : (u32)comp + 1) : (u32)comp;
+        u64 wv[8];
+        prg_block8(key, make_tag(a.op, pur, cc, a.sub), (u64)b, wv);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) rows[row][8 * b + q] = wv[q];
+    }
+    // the workgroups' partials, summed: thread t = (point t >> 7, word t & 127) of each party
+    for (int p = 0; p < 3; ++p) {
+        u64 s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        if (p < a.nparties) {
+            const u64* src = a.part + (int64_t)p * a.groups * 256 + t;
+            int g = 0;
+            for (; g + 4 <= a.groups; g += 4) {
+                s0 += src[(int64_t)g * 256];
+                s1 += src[(int64_t)(g + 1) * 256];
+                s2 += src[(int64_t)(g + 2) * 256];
+                s3 += src[(int64_t)(g + 3) * 256];
+            }
+            for (; g < a.groups; ++g) s0 += src[(int64_t)g * 256];
+        }
+        raw[p][t] = s0 + s1 + s2 + s3;
+    }
+    __syncthreads();
+    // reduced sums: wave w takes (point, party) w and w + 4
+    for (int pp = w; pp < 6; pp += 4) {
+        const int pt = pp / 3, party = pp % 3;
+        ssum[pp][k] = reduce_wave(raw[party][pt * 128 + k], raw[party][pt * 128 + 64 + k], sh[w], k);
+    }
+    __syncthreads();
+    if (w < 2) {
+        // wave pt: the Pi_PolyEvl exchange of h(0) (pt 0) or h(x) (pt 1); its share (m, r1, r2)
+        // goes to hh[0] (h(0)) or hh[2] (h(x))
+        const int pt = w;
+        const u64 rc1 = rows[3 * pt][k], rc2 = rows[3 * pt + 1][k], g1 = rows[3 * pt + 2][k];
+        u64 g2 = ssum[3 * pt][k] + rc1 + rc2 - g1;            // P0 -> P2
+        if (pt == 1 && k == a.inj_h2_g2) g2 += a.e_h2_g2;
+        u64 m1 = g1 - ssum[3 * pt + 1][k];                     // P1 -> P2
+        if (pt == 0 && k == a.inj_h0_m1) m1 += a.e_h0_m1;
+        const u64 m2 = ssum[3 * pt + 2][k] + g2;               // P2 -> P1
+        const int hi = pt ? 2 : 0;
+        hh[hi][0][k] = m1 + m2;
+        hh[hi][1][k] = rc1;
+        hh[hi][2][k] = rc2;
+        u64* l0 = pt ? a.log_h2[0] : a.log_h0[0];
+        u64* l1 = pt ? a.log_h2[1] : a.log_h0[1];
+        u64* l2 = pt ? a.log_h2[2] : a.log_h0[2];
+        if (l0) {
+            l0[k] = m1;
+            l1[k] = m2;
+            l2[k] = g2;
+        }
+    } else if (w == 2) {
+        const u64 z = rows[6][k] - rows[7][k] - rows[8][k];   // revealed point
+        zeta[k] = z;
+        zm1[k] = z - (k == 0 ? 1 : 0);
+        zmx[k] = z - (k == 1 ? 1 : 0);
+        if (a.log_zeta) a.log_zeta[k] = z;
+    }
+    __syncthreads();
+    if (w < 3) {
+        // h(1) = z - h(0), plane w; Lagrange weight L_w over {0, 1, x}:
+        // L0 = (z-1)(z-x)/x, L1 = z(z-x)/(1-x), L2 = z(z-1)/(x(x-1))
+        hh[1][w][k] = a.z[w * 64 + k] - hh[0][w][k];
+        opa[w][k] = w == 0 ? zm1[k] : zeta[k];
+        opb[w][k] = w == 2 ? zm1[k] : zmx[k];
+        const u64 v = gr_mul_wave(opa[w], opb[w], sh[w], k);
+        opa[w][k] = v;
+        opb[w][k] = a.inv[w * 64 + k];
+        L[w][k] = gr_mul_wave(opa[w], opb[w], sh[w], k);
+    } else {
+        // the multiplication matrix of zeta: row j = zeta x^j (shift up, reduce x^64)
+        u64 cz = zeta[k];
+        for (int j = 0; j < 64; ++j) {
+            mat[j * 64 + k] = cz;
+            const u64 top = __shfl(cz, 63, 64);
+            u64 nc = __shfl_up(cz, 1, 64);
+            if (k == 0) nc = 0;
+#pragma unroll
+            for (int q = 0; q < NTAPS; ++q)
+                if (k == tap(q)) nc -= top;
+            cz = nc;
+        }
+    }
+    __syncthreads();
+    if (w < 3) {
+        // z'_c = sum_i L_i h_i,c for plane c = w
+        const int c = w;
+        u64 zc = 0;
+        for (int i = 0; i < 3; ++i) {
+            opa[w][k] = L[i][k];
+            opb[w][k] = hh[i][c][k];
+            zc += gr_mul_wave(opa[w], opb[w], sh[w], k);
+        }
+        a.z[c * 64 + k] = zc;
+    } else {
+        // the matrix's digit tiles as the fold's B operand: tile row r = column r of the
+        // matrix, k = its row index (k-block kb = rows 32 kb .. 32 kb + 31), k-octet oc
+        for (int item = k; item < 512; item += 64) {
+            const int r = item & 63, oc = (item >> 6) & 3, kb = item >> 8;
+            u64 w8[8], q[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) w8[i] = mat[(32 * kb + 8 * oc + i) * 64 + r];
+            limb::to_digits(w8, q);
+            int8_t* base = a.ztiles + kb * limb::TILE_BYTES;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) *(u64*)(base + limb::toff(d, r, oc)) = q[d];
+        }
+    }
+}
+
 __global__ void k_xp_epilogue(int64_t n, Keys k, u32 op, u32 sub, const u64* C0, const u64* C1,
                               const u64* C2, u64* XPm, u64* XP1, u64* XP2) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1350,6 +1536,9 @@ void launch_mat_pair(const u64* Wz, u64* out, hipStream_t s) {
 }
 void launch_round_finish(const RoundArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_round_finish, dim3(1), dim3(256), 0, s, a);
+}
+void launch_round_mid(const RoundMidArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_round_mid, dim3(1), dim3(256), 0, s, a);
 }
 void launch_xp_epilogue(int64_t n, const Keys& k, u32 op, u32 sub, const u64* C0, const u64* C1,
                         const u64* C2, u64* XPm, u64* XP1, u64* XP2, hipStream_t s) {
