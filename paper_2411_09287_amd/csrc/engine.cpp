@@ -525,9 +525,12 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
         // workgroup, and the fold
         HPartyArgs ha{};
         ha.dense = !sparse;
-        const int nparties = sparse ? 1 : 3;
-        ha.part = c->sc->words((int64_t)nparties * hpair_groups(n) * 256);
+        const int nunits = sparse ? 1 : 5;
+        ha.part = c->sc->words((int64_t)nunits * hpair_groups(n) * 256);
+        u64* pred = c->sc->words((int64_t)nunits * 256);
         int8_t* zt = (int8_t*)c->sc->alloc(limb_btiles_bytes(64, 64));
+        u64* krows = c->sc->words((int64_t)(R - k0) * 9 * 64);
+        launch_round_rows(c->keys, v.op, (uint32_t)v.inst, k0, R - k0, krows, s);
         for (int k = k0; k < R; ++k) {
             const int64_t half = n / 2;
             const uint32_t sub = ((uint32_t)v.inst << 8) | (uint32_t)k;
@@ -538,7 +541,16 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
             ck(hpair_party(ha, s));
             RoundMidArgs m{};
             m.k = c->keys; m.op = v.op; m.sub = sub;
-            m.part = ha.part; m.nparties = nparties; m.groups = hpair_groups(n);
+            m.rows = krows + (int64_t)(k - k0) * 9 * 64;
+            m.part = ha.part; m.nunits = nunits; m.groups = hpair_groups(n);
+            if (m.groups > 16) {
+                // many workgroups' partials: summed by a wide pass first
+                const OutView o[1] = {oview(pred, (int64_t)nunits * 256, 1)};
+                ck(split_reduce(ha.part, 1, (int64_t)nunits * 256, 1, m.groups, 1, o, View{nullptr, 0, 0, 0}, false,
+                                s));
+                m.part = pred;
+                m.groups = 1;
+            }
             m.inv = c->inv_dev; m.z = z;
             m.inj_h0_m1 = i_h0.index >= 0 ? (int)i_h0.index : -1; m.e_h0_m1 = i_h0.e;
             m.inj_h2_g2 = i_h2.index >= 0 ? (int)i_h2.index : -1; m.e_h2_g2 = i_h2.e;

@@ -69,17 +69,18 @@ hipError_t zero_words32(void* p, int64_t n, hipStream_t stream);
 // The h(0) and h(x) party sums of a Pi_Reduce round over planes of n rows (pairs (2i, 2i+1))
 // stacked in XY (plane p at XY + p n 64): dense, six planes (x: m, r1, r2; y: m, r1, r2) and
 // the three parties' sums; sparse, two planes (x's [r]_1, y's [r]_2) and P0's sum alone.
-// Each of the G = hpair_groups(n) workgroups per party writes its partial: part[(party G +
-// g) 256 + point 128 + i], point 0 = h(0), 1 = h(x), i < 64 the anti-diagonal sums j + l = i
-// of the party's 64 x 64 outer-product sum, i >= 64 those with j + l = i (= 64 + k);
-// summing the partials and reducing the second half modulo the ring's modulus gives the
-// party's ring element.
+// The parties' sums are split into units of one product each (dense: P0 unit 0, P1 units 1
+// and 2, P2 units 3 and 4; sparse: P0 unit 0).  Each of the G = hpair_groups(n) workgroups
+// per unit writes its partial: part[(g units + unit) 256 + point 128 + i], point 0 = h(0), 1 =
+// h(x), i < 64 the anti-diagonal sums j + l = i of the unit's 64 x 64 outer-product sum,
+// i >= 64 those with j + l = i (= 64 + k); summing a party's partials and reducing the second
+// half modulo the ring's modulus gives the party's ring element.
 struct HPartyArgs {
     const u64* XY;
     int64_t n;
     int64_t npairs, nblocks;      // set by hpair_party
     bool dense;
-    u64* part;                    // (3 or 1) x G x 256 words
+    u64* part;                    // G x (5 or 1) x 256 words
 };
 int hpair_groups(int64_t n);
 hipError_t hpair_party(const HPartyArgs& a, hipStream_t stream);

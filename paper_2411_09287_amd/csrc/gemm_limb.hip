@@ -658,23 +658,22 @@ Opnd combo(const View* v, int64_t b, bool transpose, int64_t rows, int i0, int c
 // ---------------------------------------------------------------------------
 constexpr int HP_OPS = 4;                       // a f(0), a F, b f(0), b F
 
-// Segment s of party p's sum, side 0 (a, the x side) or 1 (b, the y side): c0 * plane i0 +
-// c1 * plane i1.  Dense (six planes x: m 0, r1 1, r2 2; y: m 3, r1 4, r2 5), the sums of
-// k_polyevl_finish: P0 (r1 + r2)_x (r1 + r2)_y; P1 m_x r1_y + r1_x m_y; P2 m_x (m_y - r2_y)
-// - r2_x m_y.  Sparse (the truncation gates: x's [r]_1 plane 0, y's [r]_2 plane 1): P0's
-// only product, plane 0 times plane 1.
+// Units of work: segment s of party p's sum, side 0 (a, the x side) or 1 (b, the y side):
+// c0 * plane i0 + c1 * plane i1.  Dense (six planes x: m 0, r1 1, r2 2; y: m 3, r1 4, r2 5),
+// the sums of k_polyevl_finish, five units: P0 (r1 + r2)_x (r1 + r2)_y (unit 0); P1 m_x r1_y
+// (1) + r1_x m_y (2); P2 m_x (m_y - r2_y) (3) - r2_x m_y (4).  Sparse (the truncation gates:
+// x's [r]_1 plane 0, y's [r]_2 plane 1): one unit, P0's only product.
 struct HSide {
     int i0, c0, i1, c1;
 };
-__device__ constexpr HSide hseg(bool dense, int party, int s, int side) {
+__device__ constexpr HSide hunit(bool dense, int unit, int side) {
     return !dense ? (side == 0 ? HSide{0, 1, 0, 0} : HSide{1, 1, 0, 0})
-           : party == 0 ? (side == 0 ? HSide{1, 1, 2, 1} : HSide{4, 1, 5, 1})
-           : party == 1 ? (s == 0 ? (side == 0 ? HSide{0, 1, 0, 0} : HSide{4, 1, 0, 0})
-                                  : (side == 0 ? HSide{1, 1, 0, 0} : HSide{3, 1, 0, 0}))
-                        : (s == 0 ? (side == 0 ? HSide{0, 1, 0, 0} : HSide{3, 1, 5, -1})
-                                  : (side == 0 ? HSide{2, -1, 0, 0} : HSide{3, 1, 0, 0}));
+           : unit == 0 ? (side == 0 ? HSide{1, 1, 2, 1} : HSide{4, 1, 5, 1})
+           : unit == 1 ? (side == 0 ? HSide{0, 1, 0, 0} : HSide{4, 1, 0, 0})
+           : unit == 2 ? (side == 0 ? HSide{1, 1, 0, 0} : HSide{3, 1, 0, 0})
+           : unit == 3 ? (side == 0 ? HSide{0, 1, 0, 0} : HSide{3, 1, 5, -1})
+                       : (side == 0 ? HSide{2, -1, 0, 0} : HSide{3, 1, 0, 0});
 }
-__device__ constexpr int hnseg(bool dense, int party) { return !dense || party == 0 ? 1 : 2; }
 
 __device__ __forceinline__ u64 hp_load(const u64* XY, int64_t n, const HSide& sd, int64_t row, int lane) {
     u64 v = XY[(int64_t)sd.i0 * n * 64 + row * 64 + lane];
@@ -686,19 +685,9 @@ __device__ __forceinline__ u64 hp_load(const u64* XY, int64_t n, const HSide& sd
     return v;
 }
 
-// One side of a segment for the wave's 8 pairs of block blk: f(0) and F = f(0) + x (f(1) -
-// f(0)) of the combination, as balanced-digit k-octets (row = coefficient lane) in tiles
-// T0 (f(0)) and T1 (F).
-__device__ __forceinline__ void hp_side(const HPartyArgs& a, const HSide& sd, int64_t blk, int w, int lane,
-                                        int8_t* T0, int8_t* T1) {
-    u64 ev[8], ov[8];
-#pragma unroll
-    for (int pq = 0; pq < 8; ++pq) {
-        const int64_t pr = blk * 32 + w * 8 + pq;
-        const bool in = pr < a.npairs;
-        ev[pq] = in ? hp_load(a.XY, a.n, sd, 2 * pr, lane) : 0;
-        ov[pq] = in ? hp_load(a.XY, a.n, sd, 2 * pr + 1, lane) : 0;
-    }
+// f(0) and F = f(0) + x (f(1) - f(0)) of one side for the wave's 8 pairs, as balanced-digit
+// k-octets (row = coefficient lane) in tiles T0 (f(0)) and T1 (F); ev, ov: f(0), f(1).
+__device__ __forceinline__ void hp_stash(u64 ev[8], u64 ov[8], int w, int lane, int8_t* T0, int8_t* T1) {
     u64 q[8];
     to_digits(ev, q);
 #pragma unroll
@@ -718,60 +707,72 @@ __device__ __forceinline__ void hp_side(const HPartyArgs& a, const HSide& sd, in
     for (int d = 0; d < 8; ++d) *(u64*)(T1 + d * PLANE + w * 512 + lane * 8) = q[d];
 }
 
-template <bool DENSE, int PARTY>
-__device__ __forceinline__ void hp_party(const HPartyArgs& a, int8_t (*T)[8 * PLANE], u64 c0[16], u64 c2[16]) {
+template <bool DENSE, int UNIT>
+__device__ __forceinline__ void hp_unit(const HPartyArgs& a, int8_t (*T)[8 * PLANE], u64 c0[16], u64 c2[16]) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wy = w >> 1, wx = w & 1, r = lane & 31, kh = (lane >> 5) * 16;
     const int arow = wy * 32 + r, brow = wx * 32 + r;
+    constexpr HSide sa = hunit(DENSE, UNIT, 0), sb = hunit(DENSE, UNIT, 1);
     for (int64_t blk = blockIdx.x; blk < a.nblocks; blk += gridDim.x) {
-#pragma unroll 1
-        for (int sg = 0; sg < hnseg(DENSE, PARTY); ++sg) {
-            hp_side(a, hseg(DENSE, PARTY, sg, 0), blk, w, lane, T[0], T[1]);
-            hp_side(a, hseg(DENSE, PARTY, sg, 1), blk, w, lane, T[2], T[3]);
-            __syncthreads();
+        // both sides' loads first (the block's 8 pairs per wave), then the conversions
+        u64 ea[8], oa[8], eb[8], ob[8];
 #pragma unroll
-            for (int pt = 0; pt < 2; ++pt) {            // point 0: f(0) products; point 1: F products
-                const int8_t* TA = T[pt];
-                const int8_t* TB = T[2 + pt];
-                v4i A[8], B[8];
+        for (int pq = 0; pq < 8; ++pq) {
+            const int64_t pr = blk * 32 + w * 8 + pq;
+            const bool in = pr < a.npairs;
+            ea[pq] = in ? hp_load(a.XY, a.n, sa, 2 * pr, lane) : 0;
+            oa[pq] = in ? hp_load(a.XY, a.n, sa, 2 * pr + 1, lane) : 0;
+            eb[pq] = in ? hp_load(a.XY, a.n, sb, 2 * pr, lane) : 0;
+            ob[pq] = in ? hp_load(a.XY, a.n, sb, 2 * pr + 1, lane) : 0;
+        }
+        hp_stash(ea, oa, w, lane, T[0], T[1]);
+        hp_stash(eb, ob, w, lane, T[2], T[3]);
+        __syncthreads();
 #pragma unroll
-                for (int d = 0; d < 8; ++d) {
-                    A[d] = frag<false>(TA + d * PLANE, arow, kh);
-                    B[d] = frag<false>(TB + d * PLANE, brow, kh);
-                }
-                // digit plane s2 of the product (sum over i + j = s2 of A_i B_j) on one
-                // accumulator at a time, recombined into the 64-bit sums right away
+        for (int pt = 0; pt < 2; ++pt) {            // point 0: f(0) products; point 1: F products
+            const int8_t* TA = T[pt];
+            const int8_t* TB = T[2 + pt];
+            v4i A[8], B[8];
 #pragma unroll
-                for (int s2 = 0; s2 < 8; ++s2) {
-                    v16i acc = v16i{0};
+            for (int d = 0; d < 8; ++d) {
+                A[d] = frag<false>(TA + d * PLANE, arow, kh);
+                B[d] = frag<false>(TB + d * PLANE, brow, kh);
+            }
+            // digit plane s2 of the product (sum over i + j = s2 of A_i B_j) on one
+            // accumulator at a time, recombined into the 64-bit sums right away
 #pragma unroll
-                    for (int i = 0; i <= s2; ++i)
-                        acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i], B[s2 - i], acc, 0, 0, 0);
+            for (int s2 = 0; s2 < 8; ++s2) {
+                v16i acc = v16i{0};
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) {
-                        const u64 val = ((u64)(int64_t)acc[v]) << (8 * s2);
-                        if (pt == 0) c0[v] += val;
-                        else c2[v] += val;
-                    }
+                for (int i = 0; i <= s2; ++i)
+                    acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i], B[s2 - i], acc, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const u64 val = ((u64)(int64_t)acc[v]) << (8 * s2);
+                    if (pt == 0) c0[v] += val;
+                    else c2[v] += val;
                 }
             }
-            __syncthreads();
         }
+        __syncthreads();
     }
 }
 
+// grid: (G, units): units 5 (dense) or 1 (sparse); each workgroup writes one partial
 template <bool DENSE>
 __global__ __launch_bounds__(NT, 2) void k_hpair_party(HPartyArgs a) {
     __shared__ __attribute__((aligned(16))) int8_t T[HP_OPS][8 * PLANE];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wy = w >> 1, wx = w & 1;
-    const int party = blockIdx.y;
+    const int unit = blockIdx.y;
     u64 c0[16], c2[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) c0[v] = c2[v] = 0;
-    if (!DENSE || party == 0) hp_party<DENSE, 0>(a, T, c0, c2);
-    else if (party == 1) hp_party<DENSE, 1>(a, T, c0, c2);
-    else hp_party<DENSE, 2>(a, T, c0, c2);
+    if (!DENSE || unit == 0) hp_unit<DENSE, 0>(a, T, c0, c2);
+    else if (unit == 1) hp_unit<DENSE, 1>(a, T, c0, c2);
+    else if (unit == 2) hp_unit<DENSE, 2>(a, T, c0, c2);
+    else if (unit == 3) hp_unit<DENSE, 3>(a, T, c0, c2);
+    else hp_unit<DENSE, 4>(a, T, c0, c2);
     // the two sums as 64 x 64 matrices in LDS (row j = coefficient of a, column l = of b)
     u64* M0 = (u64*)T[0];
     u64* M2 = (u64*)T[2];
@@ -805,7 +806,7 @@ __global__ __launch_bounds__(NT, 2) void k_hpair_party(HPartyArgs a) {
     u64 sum = 0;
 #pragma unroll
     for (int q2 = 0; q2 < 4; ++q2) sum += red[(q2 * 2 + (t >> 7)) * 128 + (t & 127)];
-    a.part[((int64_t)party * gridDim.x + blockIdx.x) * 256 + t] = sum;
+    a.part[((int64_t)blockIdx.x * gridDim.y + unit) * 256 + t] = sum;
 }
 
 
@@ -901,7 +902,7 @@ hipError_t limb_btiles(const View& B, int64_t K, int64_t N, int8_t* out, hipStre
     return hipGetLastError();
 }
 
-int hpair_groups(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n / 2 + 31) / 32, 512)); }
+int hpair_groups(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n / 2 + 31) / 32, 1024)); }
 
 hipError_t hpair_party(const HPartyArgs& args, hipStream_t st) {
     HPartyArgs a = args;
@@ -910,7 +911,7 @@ hipError_t hpair_party(const HPartyArgs& args, hipStream_t st) {
     const int groups = hpair_groups(a.n);
     if (a.nblocks <= 0) return hipErrorInvalidValue;
     if (a.dense)
-        hipLaunchKernelGGL(k_hpair_party<true>, dim3((unsigned)groups, 3), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL(k_hpair_party<true>, dim3((unsigned)groups, 5), dim3(NT), 0, st, a);
     else
         hipLaunchKernelGGL(k_hpair_party<false>, dim3((unsigned)groups, 1), dim3(NT), 0, st, a);
     return hipGetLastError();

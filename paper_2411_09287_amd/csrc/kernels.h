@@ -98,8 +98,9 @@ void launch_round_finish(const RoundArgs& a, hipStream_t s);
 struct RoundMidArgs {
     Keys k;
     u32 op, sub;
-    const u64* part;       // hpair_party's partials: nparties x groups x 256 words
-    int nparties, groups;
+    const u64* rows;       // the round's nine keystream rows (launch_round_rows)
+    const u64* part;       // hpair_party's partials: groups x nunits x 256 words
+    int nunits, groups;
     const u64* inv;        // inv_x, inv_1mx, inv_xxm1 (3*64)
     u64* z;                // share (3*64), updated in place
     int inj_h0_m1, inj_h2_g2;   // coefficient index or -1
@@ -110,6 +111,9 @@ struct RoundMidArgs {
     int8_t* ztiles;        // two 32-deep k-blocks of digit tiles (2 x 16 KiB)
 };
 void launch_round_mid(const RoundMidArgs& a, hipStream_t s);
+// The keystream rows of rounds k0 .. k0 + rounds - 1 of verification instance inst (9 x 64
+// words per round: both Pi_PolyEvl exchanges' masks and the point's three shares).
+void launch_round_rows(const Keys& k, u32 op, u32 inst, int k0, int rounds, u64* out, hipStream_t s);
 // x'_i = Pi_Mult over GR of x_i and alpha from the party products (n x 64 each), with fresh masks.
 void launch_xp_epilogue(int64_t n, const Keys& k, u32 op, u32 sub, const u64* C0, const u64* C1,
                         const u64* C2, u64* XPm, u64* XP1, u64* XP2, hipStream_t s);

@@ -738,15 +738,62 @@ __device__ u64 reduce_wave(u64 lo, u64 hi, u64* sh, int k) {
     return v;
 }
 
-// Coefficient k of a * b in GR(2^64, 64) within one wave (a, b: LDS written by this wave).
-__device__ u64 gr_mul_wave(const u64* a, const u64* b, u64* sh, int k) {
+__device__ __forceinline__ u64 readlane64(u64 v, int i) {
+    const u32 lo = __builtin_amdgcn_readlane((int)(u32)v, i), hi = __builtin_amdgcn_readlane((int)(u32)(v >> 32), i);
+    return (u64)lo | ((u64)hi << 32);
+}
+
+// Coefficient k of a * b in GR(2^64, 64) within one wave: av is lane k's coefficient of a,
+// b is in LDS written by this wave.  a_i is read across the lanes (uniform), b_(k-i) from LDS.
+__device__ u64 gr_mul_wave(u64 av, const u64* b, u64* sh, int k) {
     wave_sync();
     u64 lo = 0, hi = 0;
+#pragma unroll
     for (int i = 0; i < 64; ++i) {
-        const u64 p = a[i] * b[(k - i) & 63];
+        const u64 p = readlane64(av, i) * b[(k - i) & 63];
         if (i <= k) lo += p; else hi += p;
     }
     return reduce_wave(lo, hi, sh, k);
+}
+
+// Coefficient k of a0 b0 + a1 b1 + a2 b2 within one wave (as gr_mul_wave, one reduction).
+__device__ u64 gr_mul3_wave(u64 a0, const u64* b0, u64 a1, const u64* b1, u64 a2, const u64* b2, u64* sh, int k) {
+    wave_sync();
+    u64 lo = 0, hi = 0;
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+        const int j = (k - i) & 63;
+        const u64 p = readlane64(a0, i) * b0[j] + readlane64(a1, i) * b1[j] + readlane64(a2, i) * b2[j];
+        if (i <= k) lo += p; else hi += p;
+    }
+    return reduce_wave(lo, hi, sh, k);
+}
+
+// The keystream rows of rounds k0 .. k0 + gridDim.x - 1 of a verification instance (block b =
+// round k0 + b; nine rows of 64 words each): 0..2 h(0)'s [r]_1, [r]_2 and [Gamma]_1 masks of
+// Pi_PolyEvl, 3..5 the same for h(x), 6..8 the three shares of the revealed point.  Each row
+// is one party's local keystream, drawn ahead of the round.
+__global__ void k_round_rows(Keys kk, u32 op, u32 inst, int k0, u64* out) {
+    const int t = threadIdx.x;
+    if (t >= 72) return;
+    const u32 sub = (inst << 8) | (u32)(k0 + blockIdx.x);
+    const int row = t >> 3, b = t & 7;
+    const int grp = row / 3, comp = row % 3;
+    Key key;
+    u32 pur;
+    if (grp < 2) {
+        key = comp == 1 ? kk.k02 : kk.k01;
+        pur = comp == 2 ? (grp ? P_VER_H2_GAMMA : P_VER_H0_GAMMA) : (grp ? P_VER_H2_R : P_VER_H0_R);
+    } else {
+        key = comp == 0 ? kk.k12 : comp == 1 ? kk.k01 : kk.k02;
+        pur = P_VER_ZETA;
+    }
+    const u32 cc = grp < 2 ? (comp == 2 ? 1u : (u32)comp + 1) : (u32)comp;
+    u64 wv[8];
+    prg_block8(key, make_tag(op, pur, cc, sub), (u64)b, wv);
+    u64* o = out + (int64_t)blockIdx.x * 9 * 64 + row * 64 + 8 * b;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) o[q] = wv[q];
 }
 
 // The middle of a Pi_Reduce round in one workgroup, from the partial anti-diagonal sums of
@@ -754,50 +801,35 @@ __device__ u64 gr_mul_wave(const u64* a, const u64* b, u64* sh, int k) {
 // ring's modulus, both Pi_PolyEvl exchanges (P0's [Gamma]_2, P1's and P2's m shares, as
 // k_polyevl_finish), the revealed point zeta, the Lagrange step of the claim z (as
 // k_round_finish), and the digit tiles of the multiplication matrix of zeta for the fold
-// on the matrix cores.  Every keystream row the step draws is drawn at once, first; the
-// waves then run their ring products without block-wide barriers: waves 0..2 the Lagrange
-// weights and the three planes of z, wave 3 the point's matrix and its tiles.
+// on the matrix cores.  The keystream rows come drawn ahead (k_round_rows); the waves run
+// their ring products without block-wide barriers: waves 0..2 the Lagrange weights and the
+// three planes of z, wave 3 the point's matrix and its tiles.
 __global__ __launch_bounds__(256) void k_round_mid(RoundMidArgs a) {
     __shared__ u64 rows[9][64];
     __shared__ u64 raw[3][256];                       // [party][point][lo 64 | hi 64]
     __shared__ u64 ssum[6][64];                       // [point * 3 + party]
     __shared__ u64 sh[4][64];
-    __shared__ u64 opa[4][64], opb[4][64];
+    __shared__ u64 opb[4][64];
     __shared__ u64 zeta[64], zm1[64], zmx[64], L[3][64], hh[3][3][64];
     __shared__ u64 mat[64 * 64];
     const int t = threadIdx.x, w = t >> 6, k = t & 63;
-    if (t < 72) {
-        // rows 0..2: h(0)'s r1, r2 and [Gamma]_1 masks; 3..5: the same for h(x); 6..8: zeta
-        const int row = t >> 3, b = t & 7;
-        const int grp = row / 3, comp = row % 3;
-        Key key;
-        u32 pur;
-        if (grp < 2) {
-            key = comp == 1 ? a.k.k02 : a.k.k01;
-            pur = comp == 2 ? (grp ? P_VER_H2_GAMMA : P_VER_H0_GAMMA) : (grp ? P_VER_H2_R : P_VER_H0_R);
-        } else {
-            key = comp == 0 ? a.k.k12 : comp == 1 ? a.k.k01 : a.k.k02;
-            pur = P_VER_ZETA;
-        }
-        const u32 cc = grp < 2 ? (comp == 2 ? 1u : (u32)comp + 1) : (u32)comp;
-        u64 wv[8];
-        prg_block8(key, make_tag(a.op, pur, cc, a.sub), (u64)b, wv);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) rows[row][8 * b + q] = wv[q];
-    }
-    // the workgroups' partials, summed: thread t = (point t >> 7, word t & 127) of each party
+    for (int i = t; i < 9 * 64; i += 256) rows[i >> 6][i & 63] = a.rows[i];
+    // the workgroups' partials, summed per party (units: P0 0; P1 1, 2; P2 3, 4): thread t =
+    // (point t >> 7, word t & 127)
     for (int p = 0; p < 3; ++p) {
         u64 s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        if (p < a.nparties) {
-            const u64* src = a.part + (int64_t)p * a.groups * 256 + t;
+        const int u0 = p == 0 ? 0 : 2 * p - 1, u1 = p == 0 ? 1 : 2 * p + 1;
+        for (int u = u0; u < u1 && u < a.nunits; ++u) {
+            const u64* src = a.part + (int64_t)u * 256 + t;
+            const int64_t st = (int64_t)a.nunits * 256;
             int g = 0;
             for (; g + 4 <= a.groups; g += 4) {
-                s0 += src[(int64_t)g * 256];
-                s1 += src[(int64_t)(g + 1) * 256];
-                s2 += src[(int64_t)(g + 2) * 256];
-                s3 += src[(int64_t)(g + 3) * 256];
+                s0 += src[g * st];
+                s1 += src[(g + 1) * st];
+                s2 += src[(g + 2) * st];
+                s3 += src[(g + 3) * st];
             }
-            for (; g < a.groups; ++g) s0 += src[(int64_t)g * 256];
+            for (; g < a.groups; ++g) s0 += src[g * st];
         }
         raw[p][t] = s0 + s1 + s2 + s3;
     }
@@ -842,12 +874,11 @@ __global__ __launch_bounds__(256) void k_round_mid(RoundMidArgs a) {
         // h(1) = z - h(0), plane w; Lagrange weight L_w over {0, 1, x}:
         // L0 = (z-1)(z-x)/x, L1 = z(z-x)/(1-x), L2 = z(z-1)/(x(x-1))
         hh[1][w][k] = a.z[w * 64 + k] - hh[0][w][k];
-        opa[w][k] = w == 0 ? zm1[k] : zeta[k];
+        const u64 iv = a.inv[w * 64 + k];
         opb[w][k] = w == 2 ? zm1[k] : zmx[k];
-        const u64 v = gr_mul_wave(opa[w], opb[w], sh[w], k);
-        opa[w][k] = v;
-        opb[w][k] = a.inv[w * 64 + k];
-        L[w][k] = gr_mul_wave(opa[w], opb[w], sh[w], k);
+        const u64 v = gr_mul_wave(w == 0 ? zm1[k] : zeta[k], opb[w], sh[w], k);
+        opb[w][k] = iv;
+        L[w][k] = gr_mul_wave(v, opb[w], sh[w], k);
     } else {
         // the multiplication matrix of zeta: row j = zeta x^j (shift up, reduce x^64)
         u64 cz = zeta[k];
@@ -866,13 +897,7 @@ __global__ __launch_bounds__(256) void k_round_mid(RoundMidArgs a) {
     if (w < 3) {
         // z'_c = sum_i L_i h_i,c for plane c = w
         const int c = w;
-        u64 zc = 0;
-        for (int i = 0; i < 3; ++i) {
-            opa[w][k] = L[i][k];
-            opb[w][k] = hh[i][c][k];
-            zc += gr_mul_wave(opa[w], opb[w], sh[w], k);
-        }
-        a.z[c * 64 + k] = zc;
+        a.z[c * 64 + k] = gr_mul3_wave(L[0][k], hh[0][c], L[1][k], hh[1][c], L[2][k], hh[2][c], sh[w], k);
     } else {
         // the matrix's digit tiles as the fold's B operand: tile row r = column r of the
         // matrix, k = its row index (k-block kb = rows 32 kb .. 32 kb + 31), k-octet oc
@@ -1539,6 +1564,10 @@ void launch_round_finish(const RoundArgs& a, hipStream_t s) {
 }
 void launch_round_mid(const RoundMidArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_round_mid, dim3(1), dim3(256), 0, s, a);
+}
+void launch_round_rows(const Keys& k, u32 op, u32 inst, int k0, int rounds, u64* out, hipStream_t s) {
+    if (rounds <= 0) return;
+    hipLaunchKernelGGL(k_round_rows, dim3((unsigned)rounds), dim3(128), 0, s, k, op, inst, k0, out);
 }
 void launch_xp_epilogue(int64_t n, const Keys& k, u32 op, u32 sub, const u64* C0, const u64* C1,
                         const u64* C2, u64* XPm, u64* XP1, u64* XP2, hipStream_t s) {
