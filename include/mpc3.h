@@ -210,6 +210,20 @@ int mpc3_inner(mpc3_ctx* ctx, const mpc3_share_t* X, const mpc3_share_t* W,
 int mpc3_inner_static(mpc3_ctx* ctx, const mpc3_share_t* X, const mpc3_share_t* W,
                       const mpc3_trunc_pair_t* out_mask, mpc3_share_t* Z);
 
+/* A convolution layer's Pi_Inner: the lowering of mpc3_im2col_strided into cols, then
+ * mpc3_inner(cols, W) with the same arguments, results and counters, bit for bit.  The
+ * product is registered with its input x as well: for a same-padded stride-1 convolution
+ * (KH = KW = 2 pad + 1) the verification forms each compressed x-side element
+ * sum_m r^(o+m) cols[m, k] from x directly -- column k = (kh, kw, c) is channel c shifted by
+ * delta = (kh - pad) W + (kw - pad) positions, so the sum is r^(o - delta) times the
+ * power-weighted sum of channel c over the whole input minus the same sum over the border
+ * rows and columns that shift leaves out -- reading x (KH KW times smaller than cols)
+ * instead of cols; the values are identical.  x, cols, W and Z must stay alive and
+ * unmodified until verified. */
+int mpc3_inner_conv(mpc3_ctx* ctx, const mpc3_share_t* x, int B, int H, int W, int C, int KH, int KW,
+                    int pad, int stride, mpc3_share_t* cols, const mpc3_share_t* Wt,
+                    const mpc3_trunc_pair_t* out_mask, mpc3_share_t* Z);
+
 /* Convolution lowering: cols (B*OH*OW rows, KH*KW*C cols) from an NHWC shared
  * tensor x (B*H*W*C words per plane), zero padding pad, stride 1.  Each plane
  * is rearranged alone (a local linear map); Sec. 4.1 evaluates a convolution

@@ -116,6 +116,10 @@ struct Pending {
     uint32_t op;
     std::vector<Hold> hold;
     int graph = 0;     // the recorded graph whose replay registered it (0: a direct call)
+    // INNER products of mpc3_inner_conv: X is the lowering of the NHWC input cx
+    bool conv = false;
+    mpc3_share_t cx{};
+    int cB = 0, cH = 0, cW = 0, cC = 0, cKH = 0, cKW = 0, cpad = 0, cstride = 0;
 };
 
 // A recorded sequence of calls: the instantiated graph and the effects its calls had on the
@@ -775,9 +779,47 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
             g.btiles_nkb = L / 32;
             return g;
         };
-        three(lo_b(plain(K, 64, M, View{}, view(lo, 64, 1), OutView{}, false)), Xc, 1, K,
-              [&](int p) { return oview(U + p * np * 64, 64, 1); });
-        launch_gr_mul_rows(sigo, U, K, K, U, s, 3, np * 64);
+        // a same-padded stride-1 convolution from its input: S_c = sum_n r^n h[n, c] over the
+        // B H W positions, the band sums of the positions each shift leaves out, and
+        // x_(kh,kw,c) = r^(o_l - delta) (S_c - E); every power is non-negative once o_l is at
+        // least the largest forward shift pad W + pad (so not for the first product)
+        const Pending& P = *it;
+        const bool conv_fast = P.conv && P.cstride == 1 && P.cKH == P.cKW && P.cKH == 2 * P.cpad + 1 &&
+                               (int64_t)P.cB * P.cH * P.cW == M && K >= (int64_t)P.cKH * P.cKW * P.cC &&
+                               off >= (int64_t)P.cpad * P.cW + P.cpad && P.cpad >= 1;
+        if (conv_fast) {
+            const int64_t C = P.cC;
+            u64* S = c->sc->words(3 * C * 64);
+            const u64* Hc[3] = {P.cx.m, P.cx.r1, P.cx.r2};
+            three(lo_b(plain(C, 64, M, View{}, view(lo, 64, 1), OutView{}, false)), Hc, 1, C,
+                  [&](int p) { return oview(S + p * C * 64, 64, 1); });
+            ConvBandArgs ba{};
+            for (int p = 0; p < 3; ++p) ba.h[p] = Hc[p];
+            ba.lo = lo;
+            ba.B = P.cB; ba.H = P.cH; ba.W = P.cW; ba.C = P.cC; ba.pad = P.cpad;
+            ba.nsets = 4 * P.cpad + 4 * P.cpad * P.cpad;
+            // chunks of at most 32 positions (k_conv_bands stages one chunk in LDS)
+            const int64_t band = (int64_t)P.cB * std::max(P.cH, P.cW);
+            const int chunks = (int)std::max<int64_t>(1, (band + 31) / 32);
+            const int64_t esz = 3 * (int64_t)ba.nsets * C * 64;
+            ba.part = c->sc->words(chunks * esz);
+            launch_conv_bands(ba, chunks, s);
+            u64* E = c->sc->words(esz);
+            const OutView eo[1] = {oview(E, esz, 1)};
+            ck(split_reduce(ba.part, 1, esz, 1, chunks, 1, eo, View{nullptr, 0, 0, 0}, false, s));
+            u64* F = c->sc->words((int64_t)P.cKH * P.cKW * 64);
+            launch_pow_shifts(lo, hi, L, off + (int64_t)P.cpad * P.cW + P.cpad, P.cKH, P.cKW, P.cW, F, s);
+            ConvXArgs xa{};
+            xa.S = S; xa.E = E; xa.F = F;
+            xa.KH = P.cKH; xa.KW = P.cKW; xa.C = P.cC; xa.pad = P.cpad; xa.nsets = ba.nsets;
+            xa.K = K; xa.U = U; xa.ustride = np * 64;
+            launch_conv_x(xa, s);
+            ck(hipGetLastError());
+        } else {
+            three(lo_b(plain(K, 64, M, View{}, view(lo, 64, 1), OutView{}, false)), Xc, 1, K,
+                  [&](int p) { return oview(U + p * np * 64, 64, 1); });
+            launch_gr_mul_rows(sigo, U, K, K, U, s, 3, np * 64);
+        }
         // y_k = sum_n r^{M n} W[k, n]
         three(plain(K, 64, N, View{}, view(sig, 64, 1), OutView{}, false), Wc, N, 1,
               [&](int p) { return oview(XY + (3 + p) * np * 64 + row * 64, 64, 1); });
@@ -1727,6 +1769,35 @@ int mpc3_inner_static(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W,
         if (!c->static_ws) throw CodeError(MPC3_E_STATE);
         StaticArena arena{(char*)c->static_ws, STATIC_WS_BYTES, 0};
         inner_body(c, X, W, pair, Z, static_alloc, &arena, true);
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_inner_conv(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int C, int KH, int KW, int pad,
+                    int stride, mpc3_share_t* cols, const mpc3_share_t* Wt, const mpc3_trunc_pair_t* pair,
+                    mpc3_share_t* Z) {
+    int g = guard(c);
+    if (g) return g;
+    if (!valid(x) || !valid(cols) || !valid(Wt) || !valid(Z) || B < 0 || H <= 0 || W <= 0 || C <= 0 || KH <= 0 ||
+        KW <= 0 || pad < 0 || stride <= 0)
+        return MPC3_E_ARG;
+    if (H + 2 * pad < KH || W + 2 * pad < KW) return MPC3_E_SHAPE;
+    const int OH = (H + 2 * pad - KH) / stride + 1, OW = (W + 2 * pad - KW) / stride + 1;
+    if (x->rows * x->cols != (int64_t)B * H * W * C) return MPC3_E_SHAPE;
+    if (cols->rows != (int64_t)B * OH * OW || cols->cols < (int64_t)KH * KW * C) return MPC3_E_SHAPE;
+    if (Wt->rows != cols->cols || Z->rows != cols->rows || Z->cols != Wt->cols) return MPC3_E_SHAPE;
+    if (pair && pair->n != cols->rows * Wt->cols) return MPC3_E_SHAPE;
+    return wrap(c, __func__, [&] {
+        const u64* const xs[3] = {x->m, x->r1, x->r2};
+        u64* const os[3] = {cols->m, cols->r1, cols->r2};
+        launch_im2col3(xs, B, H, W, C, KH, KW, pad, cols->cols, os, c->stream, stride);
+        ck(hipGetLastError());
+        c->scratch.reset();
+        inner_body(c, cols, Wt, pair, Z, scratch_alloc, &c->scratch, false);
+        Pending& p = c->pending.back();
+        p.conv = true;
+        p.cx = *x;
+        p.cB = B; p.cH = H; p.cW = W; p.cC = C; p.cKH = KH; p.cKW = KW; p.cpad = pad; p.cstride = stride;
         return (int)MPC3_OK;
     });
 }

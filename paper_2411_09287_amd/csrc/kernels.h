@@ -45,6 +45,30 @@ void launch_im2col(const u64* x, int B, int H, int W, int C, int KH, int KW, int
 void launch_im2col3(const u64* const x[3], int B, int H, int W, int C, int KH, int KW, int pad, int64_t ld,
                     u64* const out[3], hipStream_t s, int stride = 1);
 void launch_sumpool2(const u64* x, int B, int H, int W, int C, u64* out, hipStream_t s);
+
+// The x side of a same-padded stride-1 convolution's compressed pairs from its input h
+// (B x H x W x C per plane, NHWC): band sums of the positions a shift leaves out, the powers
+// r^(o - delta) of the KH KW shifts, and U[k] = (S_c - E) r^(o - delta) (kernels.hip).
+struct ConvBandArgs {
+    const u64* h[3];       // input planes
+    const u64* lo;         // r^n, n < B H W (64 words each)
+    int B, H, W, C, pad;
+    int nsets;             // 4 pad + 4 pad^2: rows, columns, corner cells
+    u64* part;             // chunks x 3 x nsets x C x 64
+};
+void launch_conv_bands(const ConvBandArgs& a, int chunks, hipStream_t s);
+void launch_pow_shifts(const u64* lo, const u64* hi, int64_t L, int64_t e0, int KH, int KW, int W, u64* out,
+                       hipStream_t s);
+struct ConvXArgs {
+    const u64* S;          // 3 x C x 64: sum_n r^n h[n, c]
+    const u64* E;          // 3 x nsets x C x 64: the band sums
+    const u64* F;          // KH KW x 64: r^(o - delta) per shift
+    int KH, KW, C, pad, nsets;
+    int64_t K;             // columns of the lowered input (>= KH KW C; the rest are zero)
+    u64* U;                // plane p at U + p ustride: K x 64
+    int64_t ustride;
+};
+void launch_conv_x(const ConvXArgs& a, hipStream_t s);
 void launch_rec_check(int64_t n, const u64* r1, Inj r1inj, int* flag, hipStream_t s);
 void launch_rec_open(int64_t n, const u64* m, const u64* r1, const u64* r2, const int* flag, u64* out,
                      hipStream_t s);

@@ -1414,6 +1414,139 @@ __global__ void k_pow_ap(const u64* lo, const u64* hi, int64_t L, int64_t e0, in
     out[(int64_t)blockIdx.x * 64 + k] = gr_mul_lane(a, b, sh, k);
 }
 
+// ---------------------------------------------------------------------------
+// The x side of a same-padded, stride-1 convolution's compressed pairs from its input
+// ---------------------------------------------------------------------------
+// With output row m = b H W + oh W + ow and input position n = b H W + y W + x (OH = H,
+// OW = W), column k = (kh, kw, c) of the lowered input holds h[n, c] at m = n - delta,
+// delta = (kh - pad) W + (kw - pad), for the positions n whose output lies inside the image.
+// So sum_m r^(o + m) X[m, k] = r^(o - delta) (S_c - E_(kh,kw),c) with S_c = sum_n r^n h[n, c]
+// over every position and E the same sum over the positions left out: the top (kh - pad) or
+// bottom (pad - kh) rows and the left or right columns (their union; the corner cells are in
+// both bands once too many).  The band sums are over "sets": rows y < pad and y >= H - pad,
+// columns x < pad and x >= W - pad, and the 4 pad^2 corner cells.
+
+// Set s of the band sums: the number of positions and position j's (b, y, x).
+__device__ __forceinline__ int64_t band_size(const ConvBandArgs& a, int s) {
+    const int p2 = 2 * a.pad;
+    return s < p2 ? (int64_t)a.B * a.W : s < 2 * p2 ? (int64_t)a.B * a.H : (int64_t)a.B;
+}
+__device__ __forceinline__ int64_t band_pos(const ConvBandArgs& a, int s, int64_t j) {
+    const int p = a.pad, p2 = 2 * p;
+    int64_t b, y, x;
+    if (s < p2) {                                   // row band: y fixed
+        y = s < p ? s : a.H - p2 + s;
+        b = j / a.W;
+        x = j - b * a.W;
+    } else if (s < 2 * p2) {                        // column band: x fixed
+        const int q = s - p2;
+        x = q < p ? q : a.W - p2 + q;
+        b = j / a.H;
+        y = j - b * a.H;
+    } else {                                        // corner cell (y index, x index)
+        const int q = s - 2 * p2, qy = q / p2, qx = q % p2;
+        y = qy < p ? qy : a.H - p2 + qy;
+        x = qx < p ? qx : a.W - p2 + qx;
+        b = j;
+    }
+    return (b * a.H + y) * a.W + x;
+}
+
+// Block (set s, plane, chunk and group of 64 channels): for its positions n (at most 64),
+// sum_n h[n, c] r^n over the 64 coefficients for each channel c of the group ->
+// part[chunk][plane][s][c][64].  The positions' power rows and channel values are staged in
+// LDS first (all loads in flight at once), then thread (k = lane, wave w) sums channels w,
+// w + 4, ... of the group.
+__global__ __launch_bounds__(256) void k_conv_bands(ConvBandArgs a) {
+    __shared__ u64 Lt[64][64];                   // [position][coefficient]
+    __shared__ u64 Ht[64][65];                   // [position][channel] (padded row)
+    // blockIdx.z = chunk * cgroups + channel group (64 channels each)
+    const int cgroups = (a.C + 63) / 64;
+    const int s = blockIdx.x, plane = blockIdx.y, chunk = blockIdx.z / cgroups, cg = blockIdx.z % cgroups;
+    const int nchunks = gridDim.z / cgroups;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t size = band_size(a, s);
+    const int64_t per = (size + nchunks - 1) / nchunks;
+    const int64_t j0 = (int64_t)chunk * per;
+    const int np = (int)max<int64_t>(0, min<int64_t>(per, size - j0));   // per <= 64 (host)
+    const u64* h = a.h[plane];
+    u64* out = a.part + (((int64_t)chunk * 3 + plane) * a.nsets + s) * (int64_t)a.C * 64;
+    __shared__ int64_t pos[64];
+    if (t < 64) pos[t] = t < np ? band_pos(a, s, j0 + t) : 0;
+    __syncthreads();
+    for (int i = t; i < 64 * 64; i += 256) {
+        const int jj = i >> 6, k = i & 63;
+        Lt[jj][k] = jj < np ? a.lo[pos[jj] * 64 + k] : 0;
+    }
+    {
+        const int c0 = cg * 64, cw = min(64, a.C - c0);
+        __syncthreads();
+        for (int i = t; i < 64 * 64; i += 256) {
+            const int jj = i >> 6, cc = i & 63;
+            Ht[jj][cc] = jj < np && cc < cw ? h[pos[jj] * a.C + c0 + cc] : 0;
+        }
+        __syncthreads();
+        u64 acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = 0;
+        for (int jj = 0; jj < np; ++jj) {
+            const u64 rv = Lt[jj][lane];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] += Ht[jj][4 * q + w] * rv;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int c = 4 * q + w;
+            if (c < cw) out[(int64_t)(c0 + c) * 64 + lane] = acc[q];
+        }
+    }
+}
+
+// Block b = kh KW + kw: r^(e0 - kh W - kw) from the two power tables (e0 = o + pad W + pad).
+__global__ void k_pow_shifts(const u64* lo, const u64* hi, int64_t L, int64_t e0, int KW, int W, u64* out) {
+    __shared__ u64 pa[64], pb[64], sh[64];
+    const int k = threadIdx.x, b = blockIdx.x;
+    const int64_t e = e0 - (int64_t)(b / KW) * W - (b % KW);
+    pa[k] = hi[(e / L) * 64 + k];
+    pb[k] = lo[(e % L) * 64 + k];
+    __syncthreads();
+    out[(int64_t)b * 64 + k] = gr_mul_lane(pa, pb, sh, k);
+}
+
+// Wave (k, plane): U[plane][k] = (S_c - E_(kh,kw),c) r^(o - delta), 0 for the zero columns
+// k >= KH KW C.  Four waves per block.
+__global__ __launch_bounds__(256) void k_conv_x(ConvXArgs a) {
+    __shared__ u64 vb[4][64], sh[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t kk = (int64_t)blockIdx.x * 4 + w;
+    const int plane = blockIdx.y;
+    if (kk >= a.K) return;                          // whole waves: no block barrier below
+    u64* out = a.U + plane * a.ustride + kk * 64;
+    if (kk >= (int64_t)a.KH * a.KW * a.C) {
+        out[lane] = 0;
+        return;
+    }
+    const int c = (int)(kk % a.C), kw = (int)((kk / a.C) % a.KW), kh = (int)(kk / ((int64_t)a.C * a.KW));
+    const int p = a.pad, p2 = 2 * p, dy = kh - p, dx = kw - p;
+    const int64_t cs = (int64_t)a.C * 64;
+    const u64* E = a.E + (int64_t)plane * a.nsets * cs + (int64_t)c * 64 + lane;
+    u64 v = a.S[(int64_t)plane * cs + (int64_t)c * 64 + lane];
+    // row band: dy > 0 leaves out rows 0 .. dy-1 (sets 0 .. dy-1); dy < 0 rows H+dy .. H-1
+    // (sets p2 + dy .. p2 - 1); likewise the columns (sets p2 + ...) and their corner cells
+    const int r0 = dy > 0 ? 0 : p2 + dy, r1 = dy > 0 ? dy : p2;
+    const int q0 = dx > 0 ? 0 : p2 + dx, q1 = dx > 0 ? dx : p2;
+    if (dy)
+        for (int r = r0; r < r1; ++r) v -= E[(int64_t)r * cs];
+    if (dx)
+        for (int q = q0; q < q1; ++q) v -= E[(int64_t)(p2 + q) * cs];
+    if (dy && dx)
+        for (int r = r0; r < r1; ++r)
+            for (int q = q0; q < q1; ++q) v += E[(int64_t)(2 * p2 + r * p2 + q) * cs];
+    vb[w][lane] = v;
+    const u64 f = a.F[(int64_t)(kh * a.KW + kw) * 64 + lane];
+    out[lane] = gr_mul_wave(f, vb[w], sh[w], lane);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1648,6 +1781,19 @@ void launch_pow_ap(const u64* lo, const u64* hi, int64_t L, int64_t e0, int64_t 
                    hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_pow_ap, dim3((unsigned)n), dim3(64), 0, s, lo, hi, L, e0, step, out);
+}
+void launch_conv_bands(const ConvBandArgs& a, int chunks, hipStream_t s) {
+    if (a.nsets <= 0 || chunks <= 0) return;
+    hipLaunchKernelGGL(k_conv_bands, dim3((unsigned)a.nsets, 3, (unsigned)(chunks * ((a.C + 63) / 64))), dim3(256), 0,
+                       s, a);
+}
+void launch_pow_shifts(const u64* lo, const u64* hi, int64_t L, int64_t e0, int KH, int KW, int W, u64* out,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_pow_shifts, dim3((unsigned)(KH * KW)), dim3(64), 0, s, lo, hi, L, e0, KW, W, out);
+}
+void launch_conv_x(const ConvXArgs& a, hipStream_t s) {
+    if (a.K <= 0) return;
+    hipLaunchKernelGGL(k_conv_x, dim3((unsigned)((a.K + 3) / 4), 3), dim3(256), 0, s, a);
 }
 void launch_gr_mul_rows(const u64* P, const u64* Q, int64_t n, int64_t per, u64* out, hipStream_t s, int planes,
                         int64_t pstride) {

@@ -63,6 +63,8 @@ SIGNATURES = {
     "mpc3_inner_static": (_I, [_P, ctypes.POINTER(Share), ctypes.POINTER(Share), ctypes.POINTER(TruncPair),
                                ctypes.POINTER(Share)]),
     "mpc3_im2col": (_I, [_P, ctypes.POINTER(Share), _I, _I, _I, _I, _I, _I, _I, ctypes.POINTER(Share)]),
+    "mpc3_inner_conv": (_I, [_P, ctypes.POINTER(Share), _I, _I, _I, _I, _I, _I, _I, _I, ctypes.POINTER(Share),
+                             ctypes.POINTER(Share), ctypes.POINTER(TruncPair), ctypes.POINTER(Share)]),
     "mpc3_im2col_strided": (_I, [_P, ctypes.POINTER(Share), _I, _I, _I, _I, _I, _I, _I, _I, ctypes.POINTER(Share)]),
     "mpc3_sumpool2": (_I, [_P, ctypes.POINTER(Share), _I, _I, _I, _I, ctypes.POINTER(Share)]),
     "mpc3_mult": (_I, [_P, ctypes.POINTER(Share), ctypes.POINTER(Share), ctypes.POINTER(Share)]),
@@ -301,6 +303,21 @@ class Context:
                                     ctypes.byref(pair.s) if pair is not None else None, ctypes.byref(zs)),
             "mpc3_inner_static", self.h)
         self._keep[VERIFY_INNER].append((X, W, Z))
+        return Z
+
+    @_on_stream
+    def inner_conv(self, x, B, H, W, C, KH, KW, pad, Wt, pair=None, ld=None, stride=1, cols=None, out=None):
+        """mpc3_inner_conv: im2col of x into cols (ld >= KH KW C columns) and Pi_Inner with Wt,
+        the product verified from x.  Returns Z."""
+        OH, OW = (H + 2 * pad - KH) // stride + 1, (W + 2 * pad - KW) // stride + 1
+        if cols is None:
+            cols = DShare.empty(B * OH * OW, ld or KH * KW * C, self.device)
+        Z = out if out is not None else DShare.empty(cols.rows, Wt.cols, self.device)
+        xs, cs, ws, zs = x.c(), cols.c(), Wt.c(), Z.c()
+        _ck(lib().mpc3_inner_conv(self.h, ctypes.byref(xs), B, H, W, C, KH, KW, pad, stride, ctypes.byref(cs),
+                                  ctypes.byref(ws), ctypes.byref(pair.s) if pair is not None else None,
+                                  ctypes.byref(zs)), "mpc3_inner_conv", self.h)
+        self._keep[VERIFY_INNER].append((x, cols, Wt, Z))
         return Z
 
     @_on_stream

@@ -102,18 +102,27 @@ class Network:
         h = ctx.share(ctx.encode(x).reshape(batch, -1))
         for i, d in enumerate(self.plan):
             layer = d["layer"]
+            Wt = self.weights[i]
             if layer[0] == "conv":
+                # the lowering and the product in one call, verified from the layer's input
                 _, kh, kw, cin, cout, pad, (hh, ww) = layer[:7]
-                X = ctx.im2col(h, batch, hh, ww, cin, kh, kw, pad, d["kpad"], stride=workloads.conv_stride(layer))
+                oh, ow = workloads.conv_out_hw(layer)
+                M = batch * oh * ow
+
+                def product(pair, layer=layer, kh=kh, kw=kw, cin=cin, pad=pad, hh=hh, ww=ww, h=h, d=d, Wt=Wt):
+                    return ctx.inner_conv(h, batch, hh, ww, cin, kh, kw, pad, Wt, pair, ld=d["kpad"],
+                                          stride=workloads.conv_stride(layer))
             else:
                 X = h if h.cols == layer[1] else mpc3.DShare(*[t.reshape(batch, -1) for t in (h.m, h.r1, h.r2)])
-            M, N = X.rows, self.weights[i].cols
+                M = X.rows
+
+                def product(pair, X=X, Wt=Wt):
+                    return ctx.inner(X, Wt, pair)
             if trunc:
-                pair = ctx.trunc_pair(M * N, self.frac)
-                Z = ctx.inner(X, self.weights[i], pair)
-                Y = ctx.trunc(pair, Z)
+                pair = ctx.trunc_pair(M * Wt.cols, self.frac)
+                Y = ctx.trunc(pair, product(pair))
             else:
-                Y = ctx.inner(X, self.weights[i])
+                Y = product(None)
             if self.nonlinear and i + 1 < len(self.plan):
                 Y = ctx.relu(Y)
             if d["pool_after"]:

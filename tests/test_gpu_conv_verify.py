@@ -1,0 +1,94 @@
+"""mpc3_inner_conv (lowering + Pi_Inner, the product verified from the layer's input) against
+mpc3_im2col + mpc3_inner on the same seeds and call sequence: every share plane, the counted
+messages and the batched Pi_BIVerify transcript (claim, every round's messages and points,
+the final Delta) bit for bit.  The cases cover same-padded convolutions that take the
+input-side compression (3x3 and 5x5, channel counts below and above 64, a zero-padded
+contraction width, batch > 1, H != W), the cases that keep the lowered form (stride 2, no
+padding, a convolution as the first product), and an injected error in a convolution's
+output share."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2411_09287_amd import mpc3  # noqa: E402
+
+SEED = bytes(range(21, 53))
+
+
+def u64(g, *shape):
+    return g.integers(0, 1 << 64, size=shape, dtype=np.uint64, endpoint=False)
+
+
+# (B, H, W, C, K, pad, stride, N, ld)
+CASES = [
+    [(2, 8, 8, 3, 3, 1, 1, 16, 32), (1, 6, 10, 70, 3, 1, 1, 9, None), (2, 7, 7, 5, 5, 2, 1, 4, None)],
+    [(1, 8, 8, 4, 3, 1, 2, 6, None), (2, 6, 6, 3, 3, 0, 1, 5, None), (3, 5, 9, 64, 3, 1, 1, 8, None)],
+]
+
+
+def run(use_conv, convs, seed, first_dense=True, variant=1, inject=None):
+    g = np.random.default_rng(seed)
+    c = mpc3.Context(SEED)
+    c.set_variant(variant)
+    if first_dense:
+        c.inner(c.share(mpc3.to_words(u64(g, 40, 24))), c.share(mpc3.to_words(u64(g, 24, 7))))
+    zs = []
+    for B, H, W, C, K, pad, stride, N, ld in convs:
+        kk = ld or K * K * C
+        x = c.share(mpc3.to_words(u64(g, B, H * W * C)))
+        w = u64(g, kk, N)
+        w[K * K * C:] = 0
+        Wt = c.share(mpc3.to_words(w))
+        if use_conv:
+            Z = c.inner_conv(x, B, H, W, C, K, K, pad, Wt, ld=ld, stride=stride)
+        else:
+            cols = c.im2col(x, B, H, W, C, K, K, pad, ld, stride=stride)
+            Z = c.inner(cols, Wt)
+        zs.append(Z)
+    if inject is not None:
+        li, row, col = inject
+        zs[li].m[row, col] += 1
+    ok = c.verify()
+    _, R, _ = c.verify_log(0, mpc3.LOG_R)
+    log = [c.verify_log(0, sl)[0] for sl in (mpc3.LOG_R, mpc3.LOG_Z, mpc3.LOG_DELTA, mpc3.LOG_DELTA_M1)]
+    for k in range(R):
+        log += [c.verify_log(0, sl, k)[0] for sl in (mpc3.LOG_ZETA, mpc3.LOG_H0_M1, mpc3.LOG_H2_G2)]
+    planes = [z.numpy() for z in zs]
+    comm = c.comm_stats()
+    c.close()
+    return ok, planes, log, comm
+
+
+@pytest.mark.parametrize("variant", [1, 0])
+@pytest.mark.parametrize("case", [0, 1])
+def test_inner_conv_matches_lowered_product(case, variant):
+    a = run(True, CASES[case], seed=100 + case, variant=variant)
+    b = run(False, CASES[case], seed=100 + case, variant=variant)
+    assert a[0] and b[0], "honest verification failed"
+    for za, zb in zip(a[1], b[1]):
+        for pa, pb in zip(za, zb):
+            assert np.array_equal(pa, pb)
+    assert len(a[2]) == len(b[2])
+    for la, lb in zip(a[2], b[2]):
+        assert np.array_equal(la, lb)
+    assert np.array_equal(a[3][0], b[3][0]) and a[3][1] == b[3][1]
+
+
+def test_inner_conv_first_product_keeps_lowered_form():
+    convs = [(2, 6, 6, 3, 3, 1, 1, 5, None), (1, 6, 6, 8, 3, 1, 1, 4, None)]
+    a = run(True, convs, seed=7, first_dense=False)
+    b = run(False, convs, seed=7, first_dense=False)
+    assert a[0] and b[0]
+    for la, lb in zip(a[2], b[2]):
+        assert np.array_equal(la, lb)
+
+
+@pytest.mark.parametrize("inject", [(0, 5, 3), (2, 0, 1)])
+def test_inner_conv_error_detected(inject):
+    ok, _, _, _ = run(True, CASES[0], seed=300, inject=inject)
+    assert not ok
