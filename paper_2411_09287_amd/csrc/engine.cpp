@@ -645,6 +645,37 @@ void fold_and_check(mpc3_ctx* c, const VerCtx& v, u64* XY, int64_t n, u64* z, in
             n = half;
         }
     }
+    {
+        // a few final pairs: Pi_InnerVerify in one workgroup
+        InnerVerifyArgs ia{};
+        ia.k = c->keys; ia.op = v.op; ia.inst = (uint32_t)v.inst; ia.n = (int)n;
+        for (int p = 0; p < 6; ++p) ia.p[p] = sparse ? nullptr : XY + (int64_t)p * n * 64;
+        if (sparse) {
+            ia.p[1] = XY;                      // x = (0, r1, 0), y = (0, 0, r2)
+            ia.p[5] = XY + n * 64;
+        }
+        ia.z = z;
+        ia.log_m1 = slot(v, MPC3_LOG_DELTA_M1); ia.log_m2 = slot(v, MPC3_LOG_DELTA_M2);
+        ia.log_g2 = slot(v, MPC3_LOG_DELTA_G2); ia.reveal = slot(v, MPC3_LOG_DELTA); ia.flag = v.flag;
+        if (n >= 1 && n <= 8) {
+            const Inj id = take_ver(c, MPC3_SITE_VER_DELTA_M1, v.inst, -1);
+            ia.inj_m1 = id.index >= 0 ? (int)id.index : -1;
+            ia.e_m1 = id.e;
+            if (!launch_inner_verify_small(ia, s)) throw CodeError(MPC3_E_STATE);
+            ck(hipGetLastError());
+            // x'_i: P0 -> P2 offline, P1 <-> P2 online; Pi_PolyEvl of Delta; Delta's reveal
+            send(c, MPC3_PH_VERIFY_OFFLINE, 0, 2, 8 * 64 * n);
+            send(c, MPC3_PH_VERIFY_ONLINE, 1, 2, 8 * 64 * n);
+            send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8 * 64 * n);
+            c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
+            send(c, MPC3_PH_VERIFY_OFFLINE, 0, 2, 8 * 64);
+            send(c, MPC3_PH_VERIFY_ONLINE, 1, 2, 8 * 64);
+            send(c, MPC3_PH_VERIFY_ONLINE, 2, 1, 8 * 64);
+            c->rounds[MPC3_PH_VERIFY_ONLINE] += 1;
+            count_reveal(c, MPC3_PH_VERIFY_ONLINE);
+            return;
+        }
+    }
     if (sparse) {   // back to six planes for the final check: x = (0, r1, 0), y = (0, 0, r2)
         u64* D6 = c->sc->words(6 * n * 64);
         zero(c, D6, (size_t)6 * n * 64 * 8);
@@ -747,10 +778,30 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
     Scratch* home_sc = c->sc;
     ck(hipEventRecord(c->ev_fork2, home));
     for (int i = 0; i < mpc3_ctx::NV; ++i) ck(hipStreamWaitEvent(c->vs[i], c->ev_fork2, 0));
-    int64_t row = 0, off = 0, li = 0;
-    for (const Pending* it : items) {
+    // rows in XY and gate offsets follow the call order; the compressions are issued smallest
+    // first, round-robin over the worker streams, so that the short, latency-bound chains of
+    // the small products run while the large ones fill the GPU
+    const size_t ni = items.size();
+    std::vector<int64_t> rows_at(ni), offs(ni), cost(ni);
+    std::vector<size_t> order(ni);
+    {
+        int64_t r0 = 0, o0 = 0;
+        for (size_t i = 0; i < ni; ++i) {
+            const int64_t M = items[i]->X.rows, K = items[i]->X.cols, N = items[i]->W.cols;
+            rows_at[i] = r0;
+            offs[i] = o0;
+            cost[i] = M * K + M * N + K * N;
+            r0 += K;
+            o0 += M * N;
+            order[i] = i;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] < cost[b]; });
+    }
+    for (size_t q = 0; q < ni; ++q) {
+        const Pending* it = items[order[q]];
+        const int64_t row = rows_at[order[q]], off = offs[order[q]];
         const int64_t M = it->X.rows, K = it->X.cols, N = it->W.cols;
-        const int w = (int)(li++ % mpc3_ctx::NV);
+        const int w = (int)(q % mpc3_ctx::NV);
         c->cs = c->vs[w];
         c->sc = &c->vsc2[w];
         s = c->cs;
@@ -831,8 +882,6 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
         three(plain(64, 64, N, View{}, view(sigo, 64, 1), OutView{}, true), Tp, 1, 64,
               [&](int p) { return oview(Cz + p * 4096, 1, 64); });
         c->sc->restore(mk);
-        row += K;
-        off += M * N;
     }
     c->cs = s = home;
     c->sc = home_sc;

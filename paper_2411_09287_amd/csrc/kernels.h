@@ -46,6 +46,23 @@ void launch_im2col3(const u64* const x[3], int B, int H, int W, int C, int KH, i
                     u64* const out[3], hipStream_t s, int stride = 1);
 void launch_sumpool2(const u64* x, int B, int H, int W, int C, u64* out, hipStream_t s);
 
+// Pi_InnerVerify of n <= 8 final pairs in one launch (kernels.hip): p[0..2] the x planes,
+// p[3..5] the y planes (n x 64 each; a null plane is 0), z the claim share (3 x 64).  Returns
+// false (nothing launched) for larger n.
+struct InnerVerifyArgs {
+    Keys k;
+    u32 op, inst;
+    int n;
+    const u64* p[6];
+    const u64* z;
+    int inj_m1;            // Delta's P1 -> P2 message: coefficient index or -1
+    u64 e_m1;
+    u64* log_m1; u64* log_m2; u64* log_g2;
+    u64* reveal;           // Delta (64 words)
+    int* flag;             // set when Delta is not 0
+};
+bool launch_inner_verify_small(const InnerVerifyArgs& a, hipStream_t s);
+
 // The x side of a same-padded stride-1 convolution's compressed pairs from its input h
 // (B x H x W x C per plane, NHWC): band sums of the positions a shift leaves out, the powers
 // r^(o - delta) of the KH KW shifts, and U[k] = (S_c - E) r^(o - delta) (kernels.hip).

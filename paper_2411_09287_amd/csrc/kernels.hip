@@ -1415,6 +1415,176 @@ __global__ void k_pow_ap(const u64* lo, const u64* hi, int64_t L, int64_t e0, in
 }
 
 // ---------------------------------------------------------------------------
+// Pi_InnerVerify of a few final pairs in one workgroup
+// ---------------------------------------------------------------------------
+// For n <= IV_MAX pairs (the default choice of R leaves at most 8) (x_i, y_i) (share planes; a null plane is 0) and the claim z: the
+// random alpha, x'_i = Pi_Mult(x_i, alpha) (P0's [Gamma]_2, P1's and P2's m shares, as
+// k_xp_epilogue), then Pi_PolyEvl of the n + 1 pairs (x'_i, y_i) and (-alpha, z) with the
+// reveal of Delta (as k_polyevl_finish).  Every keystream row is drawn first; the ring
+// products are spread over the four waves, each summing its share of a party's terms.
+constexpr int IV_MAX = 8;
+
+// lo/hi of sum over a list of ring products a_t b_t for lane k (a, b: 64-word vectors in LDS)
+__device__ __forceinline__ void gr_acc(const u64* a, const u64* b, int k, u64& lo, u64& hi) {
+#pragma unroll 8
+    for (int i = 0; i < 64; ++i) {
+        const u64 p = a[i] * b[(k - i) & 63];
+        if (i <= k) lo += p; else hi += p;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_inner_verify_small(InnerVerifyArgs a) {
+    const int n = a.n, n1 = n + 1;
+    __shared__ u64 xa[IV_MAX + 1][5][64];    // x'_i (m, r1, r2, r1 + r2) and x_i first; row n: -alpha
+    __shared__ u64 yb[IV_MAX + 1][5][64];    // y_i (m, r1, r2, r1 + r2, m - r2); row n: z
+    __shared__ u64 al[5][64];                // alpha: m, r1, r2, r1 + r2, m - r2
+    __shared__ u64 red[4][3][128];
+    __shared__ u64 dr[3][64];                // Delta's masks: r1, r2, [Gamma]_1
+    __shared__ u64 sh[4][64];
+    __shared__ int nz;
+    const int t = threadIdx.x, w = t >> 6, k = t & 63;
+    if (t == 0) nz = 0;
+    // keystream: alpha (3 rows), Delta's masks (3 rows), and x'_i's masks (3 n rows), one
+    // block of 8 words per thread
+    for (int blk = t; blk < 8 * (6 + 3 * n); blk += 256) {
+        const int row = blk >> 3, b = blk & 7;
+        u64 wv[8];
+        if (row < 3) {
+            const Key& key = row == 0 ? a.k.k12 : row == 1 ? a.k.k01 : a.k.k02;
+            prg_block8(key, make_tag(a.op, P_VER_ALPHA, (u32)row, a.inst), (u64)b, wv);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) al[row][8 * b + q] = wv[q];
+        } else if (row < 6) {
+            const int c = row - 3;      // r1 (k01, comp 1), r2 (k02, comp 2), [Gamma]_1 (k01, comp 1)
+            const Key& key = c == 1 ? a.k.k02 : a.k.k01;
+            prg_block8(key, make_tag(a.op, c == 2 ? P_VER_DELTA_GAMMA : P_VER_DELTA_R, c == 1 ? 2u : 1u, a.inst),
+                       (u64)b, wv);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) dr[c][8 * b + q] = wv[q];
+        } else {
+            // x'_i masks at words 64 i .. 64 i + 63: blocks 8 i .. 8 i + 7 of each stream
+            const int r = row - 6, i = r / 3, c = r % 3;
+            const Key& key = c == 1 ? a.k.k02 : a.k.k01;
+            prg_block8(key, make_tag(a.op, c == 2 ? P_VER_XP_GAMMA : P_VER_XP_R, c == 1 ? 2u : 1u, a.inst),
+                       (u64)(8 * i + b), wv);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (c == 0) xa[i][1][8 * b + q] = wv[q];       // r1 of x'_i
+                else if (c == 1) xa[i][2][8 * b + q] = wv[q];  // r2 of x'_i
+                else xa[i][4][8 * b + q] = wv[q];              // [Gamma]_1 of x'_i
+            }
+        }
+    }
+    // the pairs' y sides and the claim
+    for (int idx = t; idx < n1 * 64; idx += 256) {
+        const int i = idx >> 6, kk = idx & 63;
+        u64 m, r1, r2;
+        if (i < n) {
+            m = a.p[3] ? a.p[3][(int64_t)i * 64 + kk] : 0;
+            r1 = a.p[4] ? a.p[4][(int64_t)i * 64 + kk] : 0;
+            r2 = a.p[5] ? a.p[5][(int64_t)i * 64 + kk] : 0;
+        } else {
+            m = a.z[kk];
+            r1 = a.z[64 + kk];
+            r2 = a.z[128 + kk];
+        }
+        yb[i][0][kk] = m;
+        yb[i][1][kk] = r1;
+        yb[i][2][kk] = r2;
+        yb[i][3][kk] = r1 + r2;
+        yb[i][4][kk] = m - r2;
+    }
+    __syncthreads();
+    if (t < 64) {
+        al[3][k] = al[1][k] + al[2][k];
+        al[4][k] = al[0][k] - al[2][k];
+        // alpha's revealed value is m - r1 - r2; its shares stay (m, r1, r2)
+    }
+    __syncthreads();
+    // x'_i = Pi_Mult(x_i, alpha): wave w takes the elements i = w, w + 4, ...
+    for (int i = w; i < n; i += 4) {
+        // x_i's planes (read into the wave's own LDS slices: xs = x_i m, r1, r2, r1 + r2)
+        u64 xm = a.p[0] ? a.p[0][(int64_t)i * 64 + k] : 0;
+        u64 x1 = a.p[1] ? a.p[1][(int64_t)i * 64 + k] : 0;
+        u64 x2 = a.p[2] ? a.p[2][(int64_t)i * 64 + k] : 0;
+        xa[i][0][k] = xm;
+        xa[i][3][k] = x1 + x2;
+        // (r1, r2 rows of xa[i] hold x'_i's masks: x_i's r1 and r2 go through registers)
+        wave_sync();
+        u64 lo = 0, hi = 0;
+        gr_acc(xa[i][3], al[3], k, lo, hi);                    // P0: R_x R_alpha
+        const u64 c0 = reduce_wave(lo, hi, sh[w], k);
+        lo = hi = 0;
+        gr_acc(xa[i][0], al[1], k, lo, hi);                    // P1: m_x r1_alpha + r1_x m_alpha
+        xa[i][3][k] = x1;
+        wave_sync();
+        gr_acc(xa[i][3], al[0], k, lo, hi);
+        const u64 c1 = reduce_wave(lo, hi, sh[w], k);
+        lo = hi = 0;
+        gr_acc(xa[i][0], al[4], k, lo, hi);                    // P2: m_x (m_alpha - r2_alpha) - r2_x m_alpha
+        xa[i][3][k] = 0 - x2;
+        wave_sync();
+        gr_acc(xa[i][3], al[0], k, lo, hi);
+        const u64 c2 = reduce_wave(lo, hi, sh[w], k);
+        const u64 r1 = xa[i][1][k], r2 = xa[i][2][k], g1 = xa[i][4][k];
+        const u64 g2 = c0 + r1 + r2 - g1;                      // P0 -> P2
+        const u64 m1 = g1 - c1;                                // P1
+        const u64 m2 = c2 + g2;                                // P2
+        xa[i][0][k] = m1 + m2;
+        xa[i][3][k] = r1 + r2;
+    }
+    if (w == 0) {
+        // row n: -alpha
+        xa[n][0][k] = 0 - al[0][k];
+        xa[n][1][k] = 0 - al[1][k];
+        xa[n][2][k] = 0 - al[2][k];
+        xa[n][3][k] = 0 - al[3][k];
+    }
+    __syncthreads();
+    // Pi_PolyEvl sums over the n + 1 pairs: terms (party 0: R R), (party 1: m r1, r1 m),
+    // (party 2: m (m - r2), -r2 m); wave w takes the pairs i = w, w + 4, ...
+    u64 plo[3] = {0, 0, 0}, phi[3] = {0, 0, 0};
+    for (int i = w; i < n1; i += 4) {
+        gr_acc(xa[i][3], yb[i][3], k, plo[0], phi[0]);
+        gr_acc(xa[i][0], yb[i][1], k, plo[1], phi[1]);
+        gr_acc(xa[i][1], yb[i][0], k, plo[1], phi[1]);
+        gr_acc(xa[i][0], yb[i][4], k, plo[2], phi[2]);
+        u64 l2 = 0, h2 = 0;
+        gr_acc(xa[i][2], yb[i][0], k, l2, h2);
+        plo[2] -= l2;
+        phi[2] -= h2;
+    }
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        red[w][p][k] = plo[p];
+        red[w][p][64 + k] = phi[p];
+    }
+    __syncthreads();
+    if (w < 3) {
+        const int p = w;
+        const u64 lo = red[0][p][k] + red[1][p][k] + red[2][p][k] + red[3][p][k];
+        const u64 hi = red[0][p][64 + k] + red[1][p][64 + k] + red[2][p][64 + k] + red[3][p][64 + k];
+        al[p][k] = reduce_wave(lo, hi, sh[w], k);              // the party sums s0, s1, s2
+    }
+    __syncthreads();
+    if (w == 0) {
+        const u64 rc1 = dr[0][k], rc2 = dr[1][k], g1 = dr[2][k];
+        u64 g2 = al[0][k] + rc1 + rc2 - g1;                    // P0 -> P2
+        u64 m1 = g1 - al[1][k];                                // P1 -> P2
+        if (k == a.inj_m1) m1 += a.e_m1;
+        const u64 m2 = al[2][k] + g2;                          // P2 -> P1
+        const u64 v = m1 + m2 - rc1 - rc2;                     // Delta
+        a.log_m1[k] = m1;
+        a.log_m2[k] = m2;
+        a.log_g2[k] = g2;
+        a.reveal[k] = v;
+        if (v) atomicOr(&nz, 1);
+    }
+    __syncthreads();
+    if (t == 0 && nz) atomicOr(a.flag, 1);
+}
+
+// ---------------------------------------------------------------------------
 // The x side of a same-padded, stride-1 convolution's compressed pairs from its input
 // ---------------------------------------------------------------------------
 // With output row m = b H W + oh W + ow and input position n = b H W + y W + x (OH = H,
@@ -1781,6 +1951,11 @@ void launch_pow_ap(const u64* lo, const u64* hi, int64_t L, int64_t e0, int64_t 
                    hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_pow_ap, dim3((unsigned)n), dim3(64), 0, s, lo, hi, L, e0, step, out);
+}
+bool launch_inner_verify_small(const InnerVerifyArgs& a, hipStream_t s) {
+    if (a.n < 1 || a.n > IV_MAX) return false;
+    hipLaunchKernelGGL(k_inner_verify_small, dim3(1), dim3(256), 0, s, a);
+    return true;
 }
 void launch_conv_bands(const ConvBandArgs& a, int chunks, hipStream_t s) {
     if (a.nsets <= 0 || chunks <= 0) return;
