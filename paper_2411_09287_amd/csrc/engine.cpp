@@ -770,10 +770,20 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
     const int64_t np = padded(Ksum, R);
     u64* XY = c->sc->words(6 * np * 64);
     zero(c, XY, (size_t)6 * np * 64 * 8);
+    // the claim z = sum_l sum_n r^{o_l + M_l n} T_{l,n}: every product's T rows and powers are
+    // stacked (rows j_l .. j_l + N_l - 1), and one product after the join forms the 64 x 64
+    // matrices sum_j T_j (x) r^(.)_j, folded into z
+    int64_t J = 0;
+    std::vector<int64_t> jrow(items.size());
+    for (size_t i = 0; i < items.size(); ++i) {
+        jrow[i] = J;
+        J += items[i]->W.cols;
+    }
+    u64* Tall = c->sc->words(3 * J * 64);
+    u64* Sall = c->sc->words(J * 64);
     u64* Cz = c->sc->words(3 * 4096);
-    zero(c, Cz, 3 * 4096 * 8);
     // the products' compressions are independent: they run on the worker streams (each with
-    // its own workspace) and add their claims into Cz atomically, then join this stream
+    // its own workspace) and write their claim matrices, then join this stream
     hipStream_t home = c->cs;
     Scratch* home_sc = c->sc;
     ck(hipEventRecord(c->ev_fork2, home));
@@ -807,13 +817,12 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
         s = c->cs;
         Scratch::Mark mk = c->sc->mark();
         u64* sig = c->sc->words(N * 64);             // r^{M n}
-        u64* sigo = c->sc->words(N * 64);            // r^{o_l + M n} (row 0: r^{o_l})
-        launch_pow_ap(lo, hi, L, 0, M, N, sig, s);
-        launch_pow_ap(lo, hi, L, off, M, N, sigo, s);
+        u64* sigo = Sall + jrow[order[q]] * 64;      // r^{o_l + M n} (row 0: r^{o_l})
+        launch_pow_ap2(lo, hi, L, 0, off, M, N, sig, sigo, s);
         const u64* Xc[3] = {it->X.m, it->X.r1, it->X.r2};
         const u64* Wc[3] = {it->W.m, it->W.r1, it->W.r2};
         const u64* Zc[3] = {it->Z.m, it->Z.r1, it->Z.r2};
-        u64* T = c->sc->words(3 * N * 64);
+        u64* T = Tall + jrow[order[q]] * 64;         // plane p at T + p J 64
         // one product per step for the three share planes (shared right operand)
         auto three = [&](GemmArgs g, const u64* const* Ap, int64_t as0, int64_t as1, auto out) {
             g.shared = 3;
@@ -874,13 +883,10 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
         // y_k = sum_n r^{M n} W[k, n]
         three(plain(K, 64, N, View{}, view(sig, 64, 1), OutView{}, false), Wc, N, 1,
               [&](int p) { return oview(XY + (3 + p) * np * 64 + row * 64, 64, 1); });
-        // T_n = sum_m r^m Z[m, n]; z += sum_n r^{o_l + M n} T_n (ring products, folded below;
-        // as the transposed product T^T r^{o_l + M n} into a transposed view of Cz)
+        // T_n = sum_m r^m Z[m, n] into the stacked rows; z += sum_n r^{o_l + M n} T_n is one
+        // product over all stacked rows after the join
         three(lo_b(plain(N, 64, M, View{}, view(lo, 64, 1), OutView{}, false)), Zc, 1, N,
-              [&](int p) { return oview(T + p * N * 64, 64, 1); });
-        const u64* Tp[3] = {T, T + N * 64, T + 2 * N * 64};
-        three(plain(64, 64, N, View{}, view(sigo, 64, 1), OutView{}, true), Tp, 1, 64,
-              [&](int p) { return oview(Cz + p * 4096, 1, 64); });
+              [&](int p) { return oview(T + p * J * 64, 64, 1); });
         c->sc->restore(mk);
     }
     c->cs = s = home;
@@ -890,6 +896,19 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
         ck(hipStreamWaitEvent(home, c->ev_join2[i], 0));
     }
     u64* z = c->sc->words(3 * 64);
+    {
+        const u64* Tp[3] = {Tall, Tall + J * 64, Tall + 2 * J * 64};
+        GemmArgs g = plain(64, 64, J, View{}, view(Sall, 64, 1), OutView{}, false);
+        g.shared = 3;
+        for (int p = 0; p < 3; ++p) {
+            g.A[p] = view(Tp[p], 1, 64);
+            g.C[p] = oview(Cz + p * 4096, 1, 64);
+        }
+        // one 64 x 64 tile against a long K: the vector-ALU kernel splits K over the CUs
+        g.ws_alloc = scratch_alloc;
+        g.ws_self = c->sc;
+        ck(gemm(g, MPC3_VARIANT_U64, c->cs));
+    }
     launch_fold_plain(Cz, 3, z, s);
     ck(hipMemcpyAsync(slot(v, MPC3_LOG_Z), z, 512, hipMemcpyDeviceToDevice, s));
     c->vinfo.push_back(InstanceInfo{R, np});

@@ -100,6 +100,11 @@ void launch_mulmat(const u64* src, int64_t stride, int nb, u64* W, hipStream_t s
 void launch_gr_outer(const u64* P, int64_t np, const u64* Q, int64_t nq, u64* out, hipStream_t s);
 // Anti-diagonal fold of 64x64 products and reduction modulo f, nb matrices (stride 4096).
 void launch_fold_plain(const u64* C, int nb, u64* out, hipStream_t s);
+// out[i] = sum over l < nsum of C[l words + i], i < words.
+void launch_sum_blocks(const u64* C, int nsum, int64_t words, u64* out, hipStream_t s);
+// r^(e0a + step j) and r^(e0b + step j), j < n, into outa and outb (as launch_pow_ap).
+void launch_pow_ap2(const u64* lo, const u64* hi, int64_t L, int64_t e0a, int64_t e0b, int64_t step, int64_t n,
+                    u64* outa, u64* outb, hipStream_t s);
 // Pi_PolyEvl outputs from the three party products C0, C1, C2 (each 64x64).
 struct PolyEvlArgs {
     const u64* C;          // 3 consecutive 64x64 matrices

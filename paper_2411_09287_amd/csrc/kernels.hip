@@ -506,6 +506,22 @@ __device__ u64 fold_lane(const u64* C, u64* sh, int k) {
     return reduce_lane(lo, hi, sh, k);
 }
 
+// out[i] = sum over l < nsum of C[l words + i], i < words (one word per thread)
+__global__ void k_sum_blocks(const u64* C, int nsum, int64_t words, u64* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= words) return;
+    u64 v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+    int l = 0;
+    for (; l + 4 <= nsum; l += 4) {
+        v0 += C[(int64_t)l * words + i];
+        v1 += C[(int64_t)(l + 1) * words + i];
+        v2 += C[(int64_t)(l + 2) * words + i];
+        v3 += C[(int64_t)(l + 3) * words + i];
+    }
+    for (; l < nsum; ++l) v0 += C[(int64_t)l * words + i];
+    out[i] = v0 + v1 + v2 + v3;
+}
+
 __global__ void k_fold_plain(const u64* C, u64* out) {
     __shared__ u64 tile[4096];
     __shared__ u64 part[512];
@@ -1404,6 +1420,21 @@ __global__ void k_pow_level(u64* out, int64_t len, int64_t cnt, const u64* P, u6
 }
 
 // out[j] = r^{e0 + j step} from two power tables: lo[i] = r^i (i < L), hi[q] = r^{L q}.
+// Two progressions in one launch: blocks < n give r^(e0a + step j) into outa, the rest
+// r^(e0b + step j) into outb.
+__global__ void k_pow_ap2(const u64* lo, const u64* hi, int64_t L, int64_t e0a, int64_t e0b, int64_t step,
+                          int64_t n, u64* outa, u64* outb) {
+    __shared__ u64 a[64], b[64], sh[64];
+    const int k = threadIdx.x;
+    const bool second = blockIdx.x >= n;
+    const int64_t j = second ? blockIdx.x - n : blockIdx.x;
+    const int64_t e = (second ? e0b : e0a) + j * step;
+    a[k] = hi[(e / L) * 64 + k];
+    b[k] = lo[(e % L) * 64 + k];
+    __syncthreads();
+    (second ? outb : outa)[j * 64 + k] = gr_mul_lane(a, b, sh, k);
+}
+
 __global__ void k_pow_ap(const u64* lo, const u64* hi, int64_t L, int64_t e0, int64_t step, u64* out) {
     __shared__ u64 a[64], b[64], sh[64];
     const int k = threadIdx.x;
@@ -1843,6 +1874,15 @@ void launch_gr_outer(const u64* P, int64_t np, const u64* Q, int64_t nq, u64* ou
 void launch_mulmat(const u64* src, int64_t stride, int nb, u64* W, hipStream_t s) {
     if (nb <= 0) return;
     hipLaunchKernelGGL(k_mulmat, dim3(nb), dim3(64), 0, s, src, stride, W);
+}
+void launch_sum_blocks(const u64* C, int nsum, int64_t words, u64* out, hipStream_t s) {
+    if (words <= 0) return;
+    hipLaunchKernelGGL(k_sum_blocks, dim3(nblocks(words, TPB)), dim3(TPB), 0, s, C, nsum, words, out);
+}
+void launch_pow_ap2(const u64* lo, const u64* hi, int64_t L, int64_t e0a, int64_t e0b, int64_t step, int64_t n,
+                    u64* outa, u64* outb, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_pow_ap2, dim3((unsigned)(2 * n)), dim3(64), 0, s, lo, hi, L, e0a, e0b, step, n, outa, outb);
 }
 void launch_fold_plain(const u64* C, int nb, u64* out, hipStream_t s) {
     hipLaunchKernelGGL(k_fold_plain, dim3(nb), dim3(256), 0, s, C, out);
