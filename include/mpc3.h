@@ -340,6 +340,19 @@ int mpc3_graph_destroy(mpc3_ctx* ctx, int graph_id);
  * context is aborted.  Synchronises. */
 int mpc3_verify(mpc3_ctx* ctx, int R, int kinds, int* ok);
 
+/* mpc3_verify in two halves, for pipelining: mpc3_verify_begin takes the selected pending
+ * products off the pending list (with the same operation ids, draws and transcript as
+ * mpc3_verify at that point) and enqueues their verification on the context's worker
+ * streams after everything enqueued on its stream so far; it returns without waiting.  Later
+ * calls on the context's stream (for example the next batch's layers) run alongside.
+ * mpc3_verify_end waits for it and reports as mpc3_verify (*ok, abort, transcript).  One
+ * verification may be in flight: mpc3_verify_begin and mpc3_verify return MPC3_E_STATE
+ * while one is; mpc3_reconstruct returns MPC3_E_UNVERIFIED and mpc3_verify_log
+ * MPC3_E_STATE until it has ended.  The operands of the products in flight must stay alive
+ * and unmodified until mpc3_verify_end. */
+int mpc3_verify_begin(mpc3_ctx* ctx, int R, int kinds);
+int mpc3_verify_end(mpc3_ctx* ctx, int* ok);
+
 /* Pi_Rec (Preliminaries, "Verifiability of share reconstruction"): open X into
  * out_dev (rows*cols words) after cross-checking the copies the receivers got.
  * to_party < 0 opens to all three parties (Pi_Rec^l); to_party = k opens to P_k

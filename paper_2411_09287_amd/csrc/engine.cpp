@@ -194,6 +194,16 @@ struct mpc3_ctx {
     std::string err_call;
     // this device's copy of the static workspace (mpc3_inner_static)
     void* static_ws = nullptr;
+    // a verification in flight (mpc3_verify_begin .. mpc3_verify_end): its products, its
+    // device results (in vres, apart from the scratch the protocol calls use) and the pinned
+    // host buffers they are copied into
+    bool verifying = false;
+    std::vector<Pending> inflight;
+    Scratch vres;
+    int64_t vninst = 0;
+    int* hflags = nullptr;
+    u64* hlog = nullptr;
+    size_t hcap = 0;          // instances the pinned buffers hold
     // recording into HIP graphs: the device word added to the op id of every recorded
     // keystream draw, and the context's state when the recording began
     u32* op_off_dev = nullptr;
@@ -1624,6 +1634,11 @@ int mpc3_ctx_destroy(mpc3_ctx* c) {
         c->capturing = false;
     }
     (void)hipStreamSynchronize(c->stream);
+    for (int i = 0; i < mpc3_ctx::NV; ++i)
+        if (c->vs[i]) (void)hipStreamSynchronize(c->vs[i]);
+    if (c->hflags) (void)hipHostFree(c->hflags);
+    if (c->hlog) (void)hipHostFree(c->hlog);
+    c->vres.release();
     for (auto& kv : c->graphs) {
         (void)hipGraphExecDestroy(kv.second.ex);
         (void)hipGraphDestroy(kv.second.g);
@@ -2071,6 +2086,8 @@ int mpc3_graph_launch(mpc3_ctx* c, int graph_id) {
     if (it == c->graphs.end()) return MPC3_E_ARG;
     for (const Pending& p : c->pending)
         if (p.graph == graph_id) return MPC3_E_STATE;
+    for (const Pending& p : c->inflight)
+        if (p.graph == graph_id) return MPC3_E_STATE;
     return wrap(c, __func__, [&] {
         const GraphRec& r = it->second;
         const uint32_t base = c->op;
@@ -2129,15 +2146,16 @@ int mpc3_graph_destroy(mpc3_ctx* c, int graph_id) {
     });
 }
 
-int mpc3_verify(mpc3_ctx* c, int R, int kinds, int* ok) {
+int mpc3_verify_begin(mpc3_ctx* c, int R, int kinds) {
     int g = guard(c);
     if (g) return g;
-    if (!ok || R > RMAX || R < MPC3_R_NETWORK || kinds <= 0 || kinds > MPC3_VERIFY_ALL) return MPC3_E_ARG;
+    if (R > RMAX || R < MPC3_R_NETWORK || kinds <= 0 || kinds > MPC3_VERIFY_ALL) return MPC3_E_ARG;
     if (R == MPC3_R_NETWORK && !c->net_set) return MPC3_E_STATE;
+    if (c->verifying) return MPC3_E_STATE;
     return wrap(c, __func__, [&] {
         const uint32_t op = c->op++;
         hipStream_t s = c->stream;
-        c->scratch.reset();
+        c->vres.reset();
         std::vector<Pending> sel, rest;
         for (auto& p : c->pending) (p.kind & kinds ? sel : rest).push_back(p);
         // all Pi_Inner products form instance 0; then the truncation chunks and each Pi_Mult
@@ -2153,8 +2171,8 @@ int mpc3_verify(mpc3_ctx* c, int R, int kinds, int* ok) {
                 ninst += std::max<int64_t>(1, (p.X.rows * p.X.cols + c->chunk_mult - 1) / c->chunk_mult);
             else ninst += 1;
         }
-        u64* logd = c->scratch.words(std::max<int64_t>(ninst, 1) * NSLOT * 64);
-        int* flags = (int*)c->scratch.alloc(std::max<int64_t>(ninst, 1) * sizeof(int));
+        u64* logd = c->vres.words(std::max<int64_t>(ninst, 1) * NSLOT * 64);
+        int* flags = (int*)c->vres.alloc(std::max<int64_t>(ninst, 1) * sizeof(int));
         zero(c, logd, (size_t)std::max<int64_t>(ninst, 1) * NSLOT * 64 * 8);
         zero(c, flags, std::max<int64_t>(ninst, 1) * sizeof(int));
         c->vinfo.clear();
@@ -2233,29 +2251,63 @@ int mpc3_verify(mpc3_ctx* c, int R, int kinds, int* ok) {
                 ++inst;
             }
         }
-        for (int i = 0; i < mpc3_ctx::NV; ++i) {
+        // the worker streams join on stream 0, which copies the results into pinned host
+        // memory; the context's own stream goes on with later calls meanwhile
+        for (int i = 1; i < mpc3_ctx::NV; ++i) {
             ck(hipEventRecord(c->ev_join[i], c->vs[i]));
-            ck(hipStreamWaitEvent(s, c->ev_join[i], 0));
+            ck(hipStreamWaitEvent(c->vs[0], c->ev_join[i], 0));
         }
-        std::vector<int> hflags(std::max<int64_t>(ninst, 1), 0);
-        c->vlog.assign((size_t)std::max<int64_t>(ninst, 1) * NSLOT * 64, 0);
-        ck(hipMemcpyAsync(hflags.data(), flags, hflags.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-        ck(hipMemcpyAsync(c->vlog.data(), logd, c->vlog.size() * 8, hipMemcpyDeviceToHost, s));
-        ck(hipStreamSynchronize(s));
+        const int64_t nres = std::max<int64_t>(ninst, 1);
+        if ((size_t)nres > c->hcap) {
+            if (c->hflags) (void)hipHostFree(c->hflags);
+            if (c->hlog) (void)hipHostFree(c->hlog);
+            c->hflags = nullptr;
+            c->hlog = nullptr;
+            c->hcap = 0;
+            ck(hipHostMalloc((void**)&c->hflags, (size_t)nres * sizeof(int), hipHostMallocDefault));
+            ck(hipHostMalloc((void**)&c->hlog, (size_t)nres * NSLOT * 64 * 8, hipHostMallocDefault));
+            c->hcap = (size_t)nres;
+        }
+        ck(hipMemcpyAsync(c->hflags, flags, (size_t)nres * sizeof(int), hipMemcpyDeviceToHost, c->vs[0]));
+        ck(hipMemcpyAsync(c->hlog, logd, (size_t)nres * NSLOT * 64 * 8, hipMemcpyDeviceToHost, c->vs[0]));
         c->pending = rest;
+        c->inflight = std::move(sel);
+        c->vninst = ninst;
+        c->verifying = true;
+        return (int)MPC3_OK;
+    });
+}
+
+int mpc3_verify_end(mpc3_ctx* c, int* ok) {
+    if (!c || !ok) return MPC3_E_ARG;
+    if (c->capturing) return guard(c);
+    if (!c->verifying) return MPC3_E_STATE;
+    return wrap(c, __func__, [&] {
+        c->verifying = false;
+        ck(hipStreamSynchronize(c->vs[0]));
+        const int64_t nres = std::max<int64_t>(c->vninst, 1);
+        c->vlog.assign(c->hlog, c->hlog + nres * NSLOT * 64);
         bool pass = true;
-        for (int64_t i = 0; i < ninst; ++i) pass = pass && hflags[i] == 0;
+        for (int64_t i = 0; i < c->vninst; ++i) pass = pass && c->hflags[i] == 0;
+        c->inflight.clear();
         *ok = pass ? 1 : 0;
         if (!pass) c->aborted = true;
         return (int)MPC3_OK;
     });
 }
 
+int mpc3_verify(mpc3_ctx* c, int R, int kinds, int* ok) {
+    if (!ok) return MPC3_E_ARG;
+    const int b = mpc3_verify_begin(c, R, kinds);
+    if (b != MPC3_OK) return b;
+    return mpc3_verify_end(c, ok);
+}
+
 int mpc3_reconstruct(mpc3_ctx* c, const mpc3_share_t* X, int to_party, uint64_t* out) {
     int g = guard(c);
     if (g) return g;
     if (!valid(X) || !out || to_party > 2) return MPC3_E_ARG;
-    if (!c->pending.empty()) return MPC3_E_UNVERIFIED;
+    if (!c->pending.empty() || c->verifying) return MPC3_E_UNVERIFIED;
     return wrap(c, __func__, [&] {
         const int64_t n = X->rows * X->cols;
         const bool all = to_party < 0;
@@ -2312,7 +2364,9 @@ int mpc3_message(mpc3_ctx* c, int kind, int which, uint64_t* out, int64_t n) {
 }
 
 int mpc3_verify_log(mpc3_ctx* c, int64_t instance, int sl, int round, uint64_t* out, int* R_out, int64_t* dim_out) {
-    if (!c || instance < 0 || instance >= (int64_t)c->vinfo.size() || round < 0 || round >= RMAX) return MPC3_E_ARG;
+    if (!c) return MPC3_E_ARG;
+    if (c->verifying) return MPC3_E_STATE;
+    if (instance < 0 || instance >= (int64_t)c->vinfo.size() || round < 0 || round >= RMAX) return MPC3_E_ARG;
     if (R_out) *R_out = c->vinfo[instance].R;
     if (dim_out) *dim_out = c->vinfo[instance].npad;
     if (!out) return MPC3_OK;

@@ -79,6 +79,8 @@ SIGNATURES = {
     "mpc3_graph_nodes": (_I, [_P, _I, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "mpc3_graph_destroy": (_I, [_P, _I]),
     "mpc3_verify": (_I, [_P, _I, _I, ctypes.POINTER(_I)]),
+    "mpc3_verify_begin": (_I, [_P, _I, _I]),
+    "mpc3_verify_end": (_I, [_P, ctypes.POINTER(_I)]),
     "mpc3_reconstruct": (_I, [_P, ctypes.POINTER(Share), _I, _P]),
     "mpc3_comm_stats": (_I, [_P, ctypes.POINTER(Comm)]),
     "mpc3_inject": (_I, [_P, _I, _I64, _U64]),
@@ -415,6 +417,20 @@ class Context:
         for k in self._keep:
             if kinds & k:
                 self._keep[k] = []
+        return bool(ok.value)
+
+    def verify_begin(self, R=-1, kinds=VERIFY_ALL):
+        """mpc3_verify_begin: enqueue the verification and return; verify_end() gives ok."""
+        _ck(lib().mpc3_verify_begin(self.h, R, kinds), "mpc3_verify_begin", self.h)
+        self._inflight = [self._keep[k] for k in self._keep if kinds & k]
+        for k in self._keep:
+            if kinds & k:
+                self._keep[k] = []
+
+    def verify_end(self):
+        ok = ctypes.c_int(0)
+        _ck(lib().mpc3_verify_end(self.h, ctypes.byref(ok)), "mpc3_verify_end", self.h)
+        self._inflight = []
         return bool(ok.value)
 
     @_on_stream
