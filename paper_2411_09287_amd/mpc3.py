@@ -143,6 +143,15 @@ def from_words(t):
     return t.detach().cpu().numpy().view(np.uint64)
 
 
+def _planes(k, rows, cols, device):
+    """k planes of rows x cols int64 words carved from one allocation, each starting on a
+    256-byte boundary."""
+    n = rows * cols
+    stride = -(-n // 32) * 32
+    base = torch.empty(max(k * stride, 1), dtype=torch.int64, device=device)
+    return [base[p * stride:p * stride + n].view(rows, cols) for p in range(k)]
+
+
 class DShare:
     """<v> on the device: three int64 tensors of one shape (m, [r]_1, [r]_2)."""
 
@@ -151,7 +160,7 @@ class DShare:
 
     @classmethod
     def empty(cls, rows, cols, device="cuda"):
-        return cls(*[torch.empty((rows, cols), dtype=torch.int64, device=device) for _ in range(3)])
+        return cls(*_planes(3, rows, cols, device))
 
     @property
     def rows(self):
@@ -172,8 +181,9 @@ class DPair:
     """Truncation pair: planes of <r_x> and <r_z> (n words each) plus the C struct."""
 
     def __init__(self, n, device="cuda"):
-        self.rx = DShare.empty(n, 1, device)
-        self.rz = DShare.empty(n, 1, device)
+        pl = _planes(6, n, 1, device)
+        self.rx = DShare(*pl[:3])
+        self.rz = DShare(*pl[3:])
         self.s = TruncPair(self.rx.c(), self.rz.c(), 0, n, 0)
 
     @property
