@@ -57,6 +57,13 @@ def run_gpu(args):
     if args.variant == "auto":
         for M, K, N in net.exec_shapes(batch):
             ctx.autotune(M, K, N, 3)
+    # the limb kernel's launch shape per layer, tuned once before any timed step
+    tuning = []
+    if args.variant != "u64" and not args.no_tune:
+        for M, K, N in net.exec_shapes(batch):
+            sh, md, mb = ctx.autotune_launch(M, K, N, 5)
+            tuning.append({"shape": [M, K, N], "launch": list(sh), "ms_builtin": round(md, 4), "ms_tuned": round(mb, 4)})
+        log(f"[bench] launch tuning: {json.dumps(tuning)}")
     x = torch.from_numpy(workloads.rng(4).random((batch,) + tuple(workloads.MODELS[name]["input"]))).cuda()
     ops = sum(2.0 * M * K * N for M, K, N in shapes)
     ntrunc = sum(M * N for M, K, N in shapes)
@@ -127,6 +134,23 @@ def run_gpu(args):
         if not (ok and ok2):
             raise SystemExit("verification failed in an honest run")
         log(f"[bench] pipelined {args.steps} steps: {piped * 1e3:.2f} ms per step")
+    # the serial step's two halves on their own: the forward (issue and GPU, synchronised),
+    # then the batched Pi_BIVerify of its products (synchronous)
+    fw_times, v1_times = [], []
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = net.forward(x)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ok = ctx.verify(-1, mpc3.VERIFY_INNER)
+        t2 = time.perf_counter()
+        fw_times.append(t1 - t0)
+        v1_times.append(t2 - t1)
+        ok2, _, _ = finish(out)
+        if not (ok and ok2):
+            raise SystemExit("verification failed in an honest run")
+    log(f"[bench] forward {float(np.median(fw_times)) * 1e3:.2f} ms, Pi_BIVerify {float(np.median(v1_times)) * 1e3:.2f} ms")
     env = None if args.no_envelope else envelope(ctx)
     u64_times = []
     if args.variant == "limb" and not args.no_u64_step:
@@ -152,7 +176,7 @@ def run_gpu(args):
     gc.enable()
     return {"batch": batch, "shapes": shapes, "ops": ops, "ntrunc": ntrunc, "times": times, "vtimes": vtimes,
             "ktime": ktime, "launches": launches, "macs": macs, "envelope": env, "u64_times": u64_times,
-            "piped": piped}
+            "piped": piped, "fw_times": fw_times, "v1_times": v1_times, "tuning": tuning}
 
 
 # Truncation-gate verification: the HBM bytes the method must move per truncation once its
@@ -593,6 +617,7 @@ def main():
                     help="networks with ReLU and max pooling (edaBits); the step verifies every product")
     ap.add_argument("--no-envelope", action="store_true")
     ap.add_argument("--no-u64-step", action="store_true", help="skip the u64-kernel run of the step")
+    ap.add_argument("--no-tune", action="store_true", help="built-in launch shapes (no launch-shape autotuning)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="report the synchronised one-step-at-a-time time only")
     ap.add_argument("--hbm-copy", type=float, default=0.0, help="only time a device copy of this many GiB")
@@ -684,11 +709,14 @@ def main():
                              + ("; steps pipelined (a batch's Pi_BIVerify overlaps the next batch's layers)"
                                 if r["piped"] is not None else ""),
                    "serial_ms_per_step": ts * 1e3,
+                   "forward_ms": float(np.median(r["fw_times"])) * 1e3,
+                   "pi_biverify_ms": float(np.median(r["v1_times"])) * 1e3,
                    "linear_images_per_s": r["batch"] / t,
                    "truncation_gate_verify_ms": vt * 1e3,
                    "truncations_per_s": r["ntrunc"] / vt,
                    "images_per_s_incl_truncation_gates": r["batch"] / (t + vt),
-                   "envelope_product": r["envelope"]},
+                   "envelope_product": r["envelope"],
+                   "launch_tuning": r["tuning"]},
         "roofline": roof,
         "v2_roofline": v2_roofline(r["ntrunc"], vt),
         "cpu_baseline": cpu,

@@ -136,6 +136,26 @@ int mpc3_set_variant(mpc3_ctx* ctx, int variant);
 int mpc3_autotune(mpc3_ctx* ctx, int64_t M, int64_t K, int64_t N, int reps, int* choice, double* ms_u64,
                   double* ms_limb);
 
+/* Launch-shape autotuner of the limb kernel (MPC3_VARIANT_LIMB_I8) for the three-party
+ * product of an M x K by K x N layer: times (random operands in the context's workspace,
+ * `reps` timed runs each after one warm-up) the built-in launch and the candidates -- one
+ * or two 64-column tiles per workgroup, the built-in launch order or 1, 2, 4, ..., 64 row
+ * tiles per group of the order in which workgroups reach the XCDs, K splits as built in or
+ * doubled -- and remembers the fastest for (M rounded up to a power of two, K, N) if it
+ * beats the built-in launch by 2% both in the sweep and when the two are timed again,
+ * else forgets any earlier choice for that shape.  shape[3] receives (ns, rb, split), all
+ * 0 for the built-in launch; ms_default / ms_best (nullable) the median times (of the
+ * second timing when a shape is kept).  Every Pi_Inner of that shape on the limb kernel then uses
+ * the remembered launch.  Synchronises.  Results are bit-identical for every launch shape. */
+int mpc3_autotune_launch(mpc3_ctx* ctx, int64_t M, int64_t K, int64_t N, int reps, int* shape,
+                         double* ms_default, double* ms_best);
+
+/* Remember a launch shape for the limb kernel's three-party products of shape (M, K, N)
+ * without timing (a tuning result kept from an earlier process): ns 0 or 1 (1 keeps one
+ * column tile per workgroup), rb 0..65535 (0 = built-in launch order), split 0..16 (0 or 1
+ * = built-in K splits); all zero forgets the shape's entry.  MPC3_E_ARG otherwise. */
+int mpc3_set_launch(mpc3_ctx* ctx, int64_t M, int64_t K, int64_t N, int ns, int rb, int split);
+
 /* Truncations per Pi_BIVerify instance of the truncation gates (default and maximum
  * 524288 = 2^19; a chunk of T truncations holds about 20 KiB x T of workspace while
  * verified).  MPC3_E_ARG outside 1 .. 2^19. */
@@ -210,16 +230,21 @@ int mpc3_inner(mpc3_ctx* ctx, const mpc3_share_t* X, const mpc3_share_t* W,
 int mpc3_inner_static(mpc3_ctx* ctx, const mpc3_share_t* X, const mpc3_share_t* W,
                       const mpc3_trunc_pair_t* out_mask, mpc3_share_t* Z);
 
-/* A convolution layer's Pi_Inner: the lowering of mpc3_im2col_strided into cols, then
- * mpc3_inner(cols, W) with the same arguments, results and counters, bit for bit.  The
- * product is registered with its input x as well: for a same-padded stride-1 convolution
- * (KH = KW = 2 pad + 1) the verification forms each compressed x-side element
- * sum_m r^(o+m) cols[m, k] from x directly -- column k = (kh, kw, c) is channel c shifted by
- * delta = (kh - pad) W + (kw - pad) positions, so the sum is r^(o - delta) times the
- * power-weighted sum of channel c over the whole input minus the same sum over the border
- * rows and columns that shift leaves out -- reading x (KH KW times smaller than cols)
- * instead of cols; the values are identical.  x, cols, W and Z must stay alive and
- * unmodified until verified. */
+/* A convolution layer's Pi_Inner: the lowering of mpc3_im2col_strided of x (W->rows =
+ * ld >= KH KW C columns, the extra ones 0), then mpc3_inner(lowering, W) with the same
+ * arguments, results and counters, bit for bit.  The product is registered with its input
+ * x as well: for a same-padded stride-1 convolution (KH = KW = 2 pad + 1) the verification
+ * forms each compressed x-side element sum_m r^(o+m) cols[m, k] from x directly -- column
+ * k = (kh, kw, c) is channel c shifted by delta = (kh - pad) W + (kw - pad) positions, so
+ * the sum is r^(o - delta) times the power-weighted sum of channel c over the whole input
+ * minus the same sum over the border rows and columns that shift leaves out -- reading x
+ * (KH KW times smaller than cols) instead of cols; the values are identical (this needs
+ * o >= pad W + pad, o the gates of the products registered before it in its batch).
+ * cols receives the lowering; cols = NULL lets the library choose: when that condition
+ * holds, C is a multiple of 32, ld = KH KW C and the product runs on the limb kernel, the
+ * kernel reads the lowered rows straight from x (no lowering is written); otherwise the
+ * lowering goes to device memory of the library's, held until the product is verified.
+ * x, cols (if given), W and Z must stay alive and unmodified until verified. */
 int mpc3_inner_conv(mpc3_ctx* ctx, const mpc3_share_t* x, int B, int H, int W, int C, int KH, int KW,
                     int pad, int stride, mpc3_share_t* cols, const mpc3_share_t* Wt,
                     const mpc3_trunc_pair_t* out_mask, mpc3_share_t* Z);

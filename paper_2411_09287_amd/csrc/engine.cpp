@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -187,6 +188,8 @@ struct mpc3_ctx {
     Scratch* sc = nullptr;
     // autotuned kernel family per (M, K, N) of a three-party product
     std::map<std::tuple<int64_t, int64_t, int64_t>, int> tuned;
+    // launch shape of the limb kernel per (M, K, N) of a three-party product: ns, rb, split
+    std::map<std::tuple<int64_t, int64_t, int64_t>, std::array<int, 3>> tuned_launch;
     // the last failure of an entry point: its return code, the entry point, and for a
     // failed HIP call the hipError_t and the call at the failing site
     int err_code = 0, err_hip = 0, err_line = 0;
@@ -292,6 +295,13 @@ void run_gemm(mpc3_ctx* c, const GemmArgs& g) {
     a.ws_alloc = scratch_alloc;
     a.ws_self = c->sc;
     ck(gemm(a, c->variant, c->cs));
+}
+
+void run_gemm_as(mpc3_ctx* c, const GemmArgs& g, int variant) {
+    GemmArgs a = g;
+    a.ws_alloc = scratch_alloc;
+    a.ws_self = c->sc;
+    ck(gemm(a, variant, c->cs));
 }
 
 // Few rows and columns against a long K: the 64-bit kernel (it splits K over workgroups,
@@ -1470,8 +1480,18 @@ Key key_of(const uint8_t d[32]) {
 // Product Protocol").  The workspace (the party sums, [Gamma]_1 and the product's own) comes
 // from `wsa`; with static_ws it is the fixed device array, no message copies are kept, no
 // launch is timed and the product keeps no split-K partial sums.
+// The kernel family a three-party product of shape (M, K, N) runs on.
+int resolve_variant(const mpc3_ctx* c, int64_t M, int64_t K, int64_t N) {
+    if (c->variant != MPC3_VARIANT_AUTO) return c->variant;
+    auto it = c->tuned.find(std::make_tuple(m_bucket(M), K, N));
+    return it == c->tuned.end() ? MPC3_VARIANT_LIMB_I8 : it->second;
+}
+
+// conv: X's planes are a convolution's input, lowered implicitly by the limb kernel with
+// conv's geometry (X->rows, X->cols are the product's M and K)
 void inner_body(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W, const mpc3_trunc_pair_t* pair,
-                mpc3_share_t* Z, void* (*wsa)(void*, size_t), void* wss, bool static_ws) {
+                mpc3_share_t* Z, void* (*wsa)(void*, size_t), void* wss, bool static_ws,
+                const GemmArgs* conv = nullptr) {
     const int64_t M = X->rows, K = X->cols, N = W->cols;
     const uint32_t op = c->op++;
     const int64_t n = M * N;
@@ -1498,10 +1518,19 @@ void inner_body(mpc3_ctx* c, const mpc3_share_t* X, const mpc3_share_t* W, const
         ga.B[p] = view(Wp[p], N, 1);
         ga.C[p] = oview(C + p * n, N, 1);
     }
-    int variant = c->variant;
-    if (variant == MPC3_VARIANT_AUTO) {
-        auto it = c->tuned.find(std::make_tuple(m_bucket(M), K, N));
-        variant = it == c->tuned.end() ? MPC3_VARIANT_LIMB_I8 : it->second;
+    const int variant = resolve_variant(c, M, K, N);
+    if (conv) {
+        ga.conv = 1;
+        ga.cH = conv->cH; ga.cW = conv->cW; ga.cC = conv->cC; ga.cKH = conv->cKH; ga.cKW = conv->cKW;
+        ga.cpad = conv->cpad; ga.cOH = conv->cOH; ga.cOW = conv->cOW;
+    }
+    if (variant != MPC3_VARIANT_U64) {
+        auto it = c->tuned_launch.find(std::make_tuple(m_bucket(M), K, N));
+        if (it != c->tuned_launch.end()) {
+            ga.lt_ns = it->second[0];
+            ga.lt_rb = it->second[1];
+            ga.lt_split = it->second[2];
+        }
     }
     if (K == 0) {
         zero(c, C, (size_t)3 * n * 8);
@@ -1723,6 +1752,105 @@ int mpc3_autotune(mpc3_ctx* c, int64_t M, int64_t K, int64_t N, int reps, int* c
     });
 }
 
+int mpc3_set_launch(mpc3_ctx* c, int64_t M, int64_t K, int64_t N, int ns, int rb, int split) {
+    int g = guard(c);
+    if (g) return g;
+    if (M <= 0 || K <= 0 || N <= 0 || ns < 0 || ns > 1 || rb < 0 || rb > 65535 || split < 0 || split > 16)
+        return fail(c, MPC3_E_ARG);
+    const auto key = std::make_tuple(m_bucket(M), K, N);
+    if (ns == 0 && rb == 0 && split <= 1) c->tuned_launch.erase(key);
+    else c->tuned_launch[key] = {ns, rb, split};
+    return MPC3_OK;
+}
+
+int mpc3_autotune_launch(mpc3_ctx* c, int64_t M, int64_t K, int64_t N, int reps, int* shape, double* ms_default,
+                         double* ms_best) {
+    int g = guard(c);
+    if (g) return g;
+    if (M <= 0 || K <= 0 || N <= 0 || reps <= 0 || !shape) return MPC3_E_ARG;
+    return wrap(c, __func__, [&] {
+        hipStream_t s = c->stream;
+        c->scratch.reset();
+        u64* X = c->scratch.words(3 * M * K);
+        u64* W = c->scratch.words(3 * K * N);
+        u64* C = c->scratch.words(3 * M * N);
+        launch_fill(X, 3 * M * K, c->keys.kall, make_tag(0xFFFFFFFFu, 0xFFFF, 1, 0), s);
+        launch_fill(W, 3 * K * N, c->keys.kall, make_tag(0xFFFFFFFFu, 0xFFFF, 2, 0), s);
+        GemmArgs ga{};
+        ga.M = M; ga.N = N; ga.K = K; ga.batch = 1; ga.party = true; ga.accumulate = false;
+        for (int p = 0; p < 3; ++p) {
+            ga.A[p] = view(X + p * M * K, K, 1);
+            ga.B[p] = view(W + p * K * N, N, 1);
+            ga.C[p] = oview(C + p * M * N, N, 1);
+        }
+        // the timing events live until the function returns (also when a call throws)
+        struct Events {
+            hipEvent_t a = nullptr, b = nullptr;
+            ~Events() {
+                if (a) (void)hipEventDestroy(a);
+                if (b) (void)hipEventDestroy(b);
+            }
+        } ev;
+        ck(hipEventCreate(&ev.a));
+        ck(hipEventCreate(&ev.b));
+        hipEvent_t e0 = ev.a, e1 = ev.b;
+        auto timed = [&](int ns, int rb, int split) {
+            GemmArgs a = ga;
+            a.lt_ns = ns; a.lt_rb = rb; a.lt_split = split;
+            std::vector<float> t(reps);
+            run_gemm_as(c, a, MPC3_VARIANT_LIMB_I8);
+            for (int i = 0; i < reps; ++i) {
+                ck(hipEventRecord(e0, s));
+                run_gemm_as(c, a, MPC3_VARIANT_LIMB_I8);
+                ck(hipEventRecord(e1, s));
+                ck(hipEventSynchronize(e1));
+                ck(hipEventElapsedTime(&t[i], e0, e1));
+            }
+            std::sort(t.begin(), t.end());
+            return (double)t[reps / 2];
+        };
+        // candidates: one or two column tiles per workgroup, the built-in launch order or
+        // 1 ... 64 row tiles per group, K splits as built in or doubled
+        double base = timed(0, 0, 0);
+        double best = base;
+        std::array<int, 3> pick{0, 0, 0};
+        for (int ns : {0, 1})
+            for (int rb : {0, 1, 2, 4, 8, 16, 32, 64})
+                for (int split : {0, 2}) {
+                    if (ns == 0 && rb == 0 && split == 0) continue;
+                    const double t = timed(ns, rb, split);
+                    if (t < best) {
+                        best = t;
+                        pick = {ns, rb, split};
+                    }
+                }
+        // a shape is kept only when it beats the built-in launch by 2% twice: in the sweep
+        // and when both are timed again (two launches can be the same one: the sweep's
+        // winner may only be timing noise)
+        if (best < 0.98 * base) {
+            const double base2 = timed(0, 0, 0), best2 = timed(pick[0], pick[1], pick[2]);
+            if (best2 < 0.98 * base2) {
+                base = base2;
+                best = best2;
+            } else {
+                best = base;
+            }
+        }
+        const auto key = std::make_tuple(m_bucket(M), K, N);
+        if (best < 0.98 * base) {
+            c->tuned_launch[key] = pick;
+        } else {
+            c->tuned_launch.erase(key);
+            pick = {0, 0, 0};
+            best = base;
+        }
+        for (int i = 0; i < 3; ++i) shape[i] = pick[i];
+        if (ms_default) *ms_default = base;
+        if (ms_best) *ms_best = best;
+        return (int)MPC3_OK;
+    });
+}
+
 int mpc3_set_chunk(mpc3_ctx* c, int64_t t) {
     if (!c || t <= 0 || t > MAX_CHUNK) return MPC3_E_ARG;
     c->chunk = t;
@@ -1861,26 +1989,58 @@ int mpc3_inner_conv(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int
                     mpc3_share_t* Z) {
     int g = guard(c);
     if (g) return g;
-    if (!valid(x) || !valid(cols) || !valid(Wt) || !valid(Z) || B < 0 || H <= 0 || W <= 0 || C <= 0 || KH <= 0 ||
-        KW <= 0 || pad < 0 || stride <= 0)
+    if (!valid(x) || (cols && !valid(cols)) || !valid(Wt) || !valid(Z) || B < 0 || H <= 0 || W <= 0 || C <= 0 ||
+        KH <= 0 || KW <= 0 || pad < 0 || stride <= 0)
         return MPC3_E_ARG;
     if (H + 2 * pad < KH || W + 2 * pad < KW) return MPC3_E_SHAPE;
     const int OH = (H + 2 * pad - KH) / stride + 1, OW = (W + 2 * pad - KW) / stride + 1;
+    const int64_t M = (int64_t)B * OH * OW, K = Wt->rows;
     if (x->rows * x->cols != (int64_t)B * H * W * C) return MPC3_E_SHAPE;
-    if (cols->rows != (int64_t)B * OH * OW || cols->cols < (int64_t)KH * KW * C) return MPC3_E_SHAPE;
-    if (Wt->rows != cols->cols || Z->rows != cols->rows || Z->cols != Wt->cols) return MPC3_E_SHAPE;
-    if (pair && pair->n != cols->rows * Wt->cols) return MPC3_E_SHAPE;
+    if (K < (int64_t)KH * KW * C || (cols && (cols->rows != M || cols->cols != K))) return MPC3_E_SHAPE;
+    if (Z->rows != M || Z->cols != Wt->cols) return MPC3_E_SHAPE;
+    if (pair && pair->n != M * Wt->cols) return MPC3_E_SHAPE;
     return wrap(c, __func__, [&] {
         const u64* const xs[3] = {x->m, x->r1, x->r2};
-        u64* const os[3] = {cols->m, cols->r1, cols->r2};
-        launch_im2col3(xs, B, H, W, C, KH, KW, pad, cols->cols, os, c->stream, stride);
-        ck(hipGetLastError());
+        // gates of the pending products this one follows in its verification batch
+        int64_t o = 0;
+        for (const Pending& q : c->pending)
+            if (q.kind == MPC3_VERIFY_INNER) o += q.Z.rows * q.Z.cols;
+        // without cols, a same-padded stride-1 convolution that will be verified from its
+        // input (not a batch's first product) runs on the limb kernel's implicit lowering
+        GemmArgs geo{};
+        geo.M = M; geo.N = Wt->cols; geo.K = K; geo.batch = 1; geo.party = true;
+        geo.ws_alloc = scratch_alloc;
+        for (int p = 0; p < 3; ++p) geo.A[p] = view(xs[p], C, 1);
+        geo.conv = 1;
+        geo.cH = H; geo.cW = W; geo.cC = C; geo.cKH = KH; geo.cKW = KW; geo.cpad = pad; geo.cOH = OH; geo.cOW = OW;
+        const bool implicit = !cols && stride == 1 && KH == KW && KH == 2 * pad + 1 && pad >= 1 &&
+                              o >= (int64_t)pad * W + pad &&
+                              resolve_variant(c, M, K, Wt->cols) != MPC3_VARIANT_U64 && limb_conv_ok(geo);
+        mpc3_share_t low{};
+        Hold hold;
+        if (implicit) {
+            low = mpc3_share_t{x->m, x->r1, x->r2, M, K};
+        } else {
+            if (cols) {
+                low = *cols;
+            } else {
+                // the lowering in device memory held until the product is verified
+                hold = dev_hold(c, 3 * M * K);
+                u64* b = (u64*)hold.get();
+                low = mpc3_share_t{b, b + M * K, b + 2 * M * K, M, K};
+            }
+            u64* const os[3] = {low.m, low.r1, low.r2};
+            launch_im2col3(xs, B, H, W, C, KH, KW, pad, K, os, c->stream, stride);
+            ck(hipGetLastError());
+        }
         c->scratch.reset();
-        inner_body(c, cols, Wt, pair, Z, scratch_alloc, &c->scratch, false);
+        inner_body(c, &low, Wt, pair, Z, scratch_alloc, &c->scratch, false, implicit ? &geo : nullptr);
         Pending& p = c->pending.back();
         p.conv = true;
         p.cx = *x;
         p.cB = B; p.cH = H; p.cW = W; p.cC = C; p.cKH = KH; p.cKW = KW; p.cpad = pad; p.cstride = stride;
+        if (implicit) p.X.m = p.X.r1 = p.X.r2 = nullptr;    // no lowered matrix: verified from x
+        if (hold) p.hold.push_back(std::move(hold));
         return (int)MPC3_OK;
     });
 }

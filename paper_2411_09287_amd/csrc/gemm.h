@@ -44,7 +44,22 @@ struct GemmArgs {
     bool no_part;
     // bytes of split-K partial sums the workspace can take (0: PART_MAX)
     size_t part_max;
+    // launch shape of the limb kernel, 0 = the built-in choice: lt_ns = 1 keeps one 64-column
+    // tile per workgroup where two would be taken; lt_rb row tiles per launch-order group;
+    // lt_split multiplies the number of K splits (where the workspace takes the partials).
+    // Results do not depend on them.
+    int lt_ns, lt_rb, lt_split;
+    // implicit lowering of a stride-1 convolution (limb kernel, where limb_conv_ok): A[p]
+    // are the planes of the NHWC input (images of cH x cW x cC words); row m of the product
+    // is output position (b, oh, ow) of cOH x cOW per image, column k = (kh, kw, c) of
+    // K = cKH cKW cC; input positions outside the image (padding cpad) read as 0
+    int conv;
+    int cH, cW, cC, cKH, cKW, cpad, cOH, cOW;
 };
+
+// Whether the limb kernel takes g's implicit lowering (C a multiple of 32, K = KH KW C,
+// stride 1, 16-byte aligned planes, one batch, a workspace for the B tiles).
+bool limb_conv_ok(const GemmArgs& g);
 
 // The cap on split-K partial sums of one product.
 inline size_t part_cap(const GemmArgs& g);

@@ -287,6 +287,10 @@ struct L2Args {
     int tn64;                    // 64-column tiles of B
     int tm;                      // 64-row tiles
     int rb;                      // row tiles per group of the launch order
+    // implicit lowering (CONV kernels): A is the NHWC input of a stride-1 convolution, row m
+    // = output position (b, oh, ow) of cOH x cOW per image, column k = (kh, kw, c) with
+    // C = 32 ccb channels; positions outside the input read as 0
+    int cH, cW, cC, cKW, cpad, cOH, cOW, ccb;
     int atomic;
     View D;
     u64* part;                   // split-K partial sums: plane (batch, split, product) of M x N
@@ -338,8 +342,9 @@ __device__ __forceinline__ void wait_vm() {
 //     flight, so every wait the compiler places is exact.
 // Otherwise (NS = 1): B tiles are copied straight into LDS (global_load_lds) and A words are
 // converted after the MFMAs.
-template <bool FAST, int NS, bool TA = false>
+template <bool FAST, int NS, bool TA = false, bool CONV = false>
 __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
+    static_assert(!CONV || (FAST && !TA), "the implicit lowering loads 16-byte pieces of k-contiguous rows");
     constexpr int WPT = 8 / NS;                  // A words converted per thread and k-block
     __shared__ __attribute__((aligned(16))) int8_t As[2][TILE_BYTES];
     __shared__ __attribute__((aligned(16))) int8_t Bs[2][NS * TILE_BYTES];
@@ -376,8 +381,20 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
     // consecutive threads take 64 consecutive rows, so each of their loads is coalesced.
     const int ra = TA ? t & 63 : (NS == 1 ? t >> 2 : t >> 3);
     const int part = TA ? t >> 6 : (NS == 1 ? t & 3 : t & 7);
-    // rows past M load row M-1: they only feed accumulator rows that are never stored
-    const int64_t aoff = min(r0a + ra, a.M - 1) * a.lda + part * WPT * a.ldk;
+    // rows past M load row M-1: they only feed accumulator rows that are never stored.  With
+    // the implicit lowering the row's offset is that of input position (oh - pad, ow - pad)
+    // of its image (possibly outside the input; only valid positions are dereferenced).
+    int64_t aoff;
+    int ohw = 0;                                 // CONV: oh << 16 | ow
+    if constexpr (CONV) {
+        const int64_t m = min(r0a + ra, a.M - 1), per_img = (int64_t)a.cOH * a.cOW;
+        const int64_t b = m / per_img;
+        const int rem = (int)(m - b * per_img), oh = rem / a.cOW, ow = rem - oh * a.cOW;
+        ohw = (oh << 16) | ow;
+        aoff = ((b * a.cH + oh - a.cpad) * a.cW + (ow - a.cpad)) * a.cC + part * WPT;
+    } else {
+        aoff = min(r0a + ra, a.M - 1) * a.lda + part * WPT * a.ldk;
+    }
     const int tt = t & (NT - 1);
     // column tiles past the last one read the last one: their outputs are never stored
     const int64_t boff = (int64_t)min(tcol, a.tn64 - 1) * a.bnkb * TILE_BYTES + tt * 16;
@@ -411,15 +428,30 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
         kb = P.nseg == 2 ? g >> 1 : g;
         return s;
     };
-    // the WPT words of block g at x[0, WPT); with SUM the second plane's at x[WPT, 2 WPT)
-    auto loadA = [&](int g, u64* x, auto sum_c) {
+    // the WPT words of block g at x[0, WPT); with SUM the second plane's at x[WPT, 2 WPT).
+    // Returns the mask the conversion applies to them: all ones, or 0 for a position of the
+    // implicit lowering outside the input (then the loads read the row's own first words;
+    // masking at conversion keeps the loads in flight until then).
+    auto loadA = [&](int g, u64* x, auto sum_c) -> u64 {
         constexpr bool SUM = decltype(sum_c)::value;
         int kb;
         const int s = seg_of(g, kb);
         const int64_t k0 = (int64_t)kb * KB;
+        u64 zm = ~0ull;
+        int64_t d = k0 * a.ldk;
+        if constexpr (CONV) {
+            const int khkw = kb / a.ccb, c0 = (kb - khkw * a.ccb) * KB;
+            const int kh = khkw / a.cKW, kw = khkw - kh * a.cKW;
+            const int ih = (ohw >> 16) + kh - a.cpad, iw = (ohw & 0xFFFF) + kw - a.cpad;
+            const bool ok = (unsigned)ih < (unsigned)a.cH && (unsigned)iw < (unsigned)a.cW;
+            // invalid: the words at the image's first position (always inside the plane)
+            const int64_t b0 = -((int64_t)((ohw >> 16) - a.cpad) * a.cW + ((ohw & 0xFFFF) - a.cpad)) * a.cC;
+            d = ok ? ((int64_t)kh * a.cW + kw) * a.cC + c0 : b0;
+            zm = ok ? ~0ull : 0ull;
+        }
 #pragma unroll
         for (int h = 0; h < (SUM ? 2 : 1); ++h) {
-            const u64* rp = (h ? pa2 : s ? pa[1] : pa[0]) + k0 * a.ldk;
+            const u64* rp = (h ? pa2 : s ? pa[1] : pa[0]) + d;
             u64* xh = x + h * WPT;
             if (TA) {
 #pragma unroll
@@ -435,6 +467,7 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
                 raw8<false>(rp, k0 + part * WPT, a.K, xh);
             }
         }
+        return zm;
     };
     auto dmaB = [&](int g, int buf) {
         int kb;
@@ -475,12 +508,12 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
         }
     };
     // conversion piece c of WPT words (c = 0: balanced bytes; c >= 1: one 4x4 transpose)
-    auto piece = [&](int c, const u64* xc, u32 lo[WPT], u32 hi[WPT], u32 tq[4][4], auto sum_c) {
+    auto piece = [&](int c, const u64* xc, u64 zm, u32 lo[WPT], u32 hi[WPT], u32 tq[4][4], auto sum_c) {
         constexpr bool SUM = decltype(sum_c)::value;
         if (c == 0) {
 #pragma unroll
             for (int j = 0; j < WPT; ++j) {
-                const u64 v = ((SUM ? xc[j] + xc[WPT + j] : xc[j]) + OFF) ^ OFF;
+                const u64 v = (((SUM ? xc[j] + xc[WPT + j] : xc[j]) & zm) + OFF) ^ OFF;
                 lo[j] = (u32)v;
                 hi[j] = (u32)(v >> 32);
                 asm volatile("" : "+v"(lo[j]), "+v"(hi[j]));
@@ -537,21 +570,22 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
                 buf ^= 1;
             }
         } else {
+            u64 ma = ~0ull, mb = ~0ull;          // the conversion masks of xa, xb
             if (gbeg < gend) {
                 loadB(gbeg);
-                loadA(gbeg, xb, sum_c);
+                const u64 m0 = loadA(gbeg, xb, sum_c);
                 u32 lo[WPT], hi[WPT], tq[4][4];
 #pragma unroll
-                for (int c = 0; c <= WPT / 2; ++c) piece(c, xb, lo, hi, tq, sum_c);
+                for (int c = 0; c <= WPT / 2; ++c) piece(c, xb, m0, lo, hi, tq, sum_c);
                 store_digits(tq, 0);
                 storeB(0);
-                loadA(min(gbeg + 1, gend - 1), xa, sum_c);
+                ma = loadA(min(gbeg + 1, gend - 1), xa, sum_c);
             }
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
-            auto body = [&](int g, const u64* xc, u64* xn) {
+            auto body = [&](int g, const u64* xc, u64 mc, u64* xn, u64& mn) {
                 loadB(min(g + 1, gend - 1));              // past the end: re-reads valid blocks
-                loadA(min(g + 2, gend - 1), xn, sum_c);
+                mn = loadA(min(g + 2, gend - 1), xn, sum_c);
                 __builtin_amdgcn_sched_barrier(0);
                 v4i B[8];
 #pragma unroll
@@ -568,7 +602,7 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
                     A = An;
                     // (the empty asm in piece() pins each part here: without it the compiler
                     // sinks the arithmetic to its use after the last MFMA)
-                    piece(i, xc, lo, hi, tq, sum_c);
+                    piece(i, xc, mc, lo, hi, tq, sum_c);
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 store_digits(tq, buf ^ 1);
@@ -580,10 +614,10 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
             };
             int g = gbeg;
             for (; g + 1 < gend; g += 2) {
-                body(g, xa, xb);
-                body(g + 1, xb, xa);
+                body(g, xa, ma, xb, mb);
+                body(g + 1, xb, mb, xa, ma);
             }
-            if (g < gend) body(g, xa, xb);
+            if (g < gend) body(g, xa, ma, xb, mb);
         }
     };
     // (one-tile FAST kernels convert 8 words per thread: a second plane would spill)
@@ -928,8 +962,20 @@ hipError_t fold_rows(const u64* XY, int64_t rows, const int8_t* ztiles, u64* out
     return hipGetLastError();
 }
 
+bool limb_conv_ok(const GemmArgs& g) {
+    if (!g.conv) return false;
+    const int np = g.party ? 3 : 1;
+    bool ok = g.batch == 1 && g.ws_alloc && g.cC > 0 && g.cC % KB == 0 && g.K == (int64_t)g.cKH * g.cKW * g.cC &&
+              g.cOH == g.cH + 2 * g.cpad - g.cKH + 1 && g.cOW == g.cW + 2 * g.cpad - g.cKW + 1 && g.cOH > 0 &&
+              g.cOW > 0 && g.cOH < 32768 && g.cOW < 65536 && g.M % ((int64_t)g.cOH * g.cOW) == 0 && g.shared <= 1;
+    for (int p = 0; p < np && ok; ++p) ok = ((uintptr_t)g.A[p].p & 15) == 0;
+    return ok;
+}
+
 hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    if (g.conv && !limb_conv_ok(g)) return hipErrorInvalidValue;
+    const bool conv = g.conv != 0;
     const int64_t tm = rup(g.M, TM) / TM, tn = rup(g.N, TN) / TN;
     const int64_t Kp = rup(g.K, KB);
     // B pre-converted to digit tiles when every A plane is k-contiguous with one row
@@ -947,6 +993,10 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         kc = kc && g.A[p].s1 == 1 && g.A[p].s0 == g.A[0].s0;
         ta = ta && g.A[p].s0 == 1 && g.A[p].s1 == g.A[0].s1;   // transposed view, rows contiguous
     }
+    if (conv) {
+        kc = true;
+        ta = false;
+    }
     const bool two = kc || ta;
     // Batches with uniform strides (every A plane, every B plane and every output) run in
     // one launch of the converted-B kernel
@@ -957,7 +1007,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
     // Small products stay on the vector ALU, where the launch is cheaper (a uniform batch
     // counts as one launch).
     const double work = (double)g.M * (double)g.N * (double)g.K * (uni ? (double)g.batch : 1.0);
-    if (work < (double)(1 << 22) || g.K == 0) return gemm(g, 0, st);
+    if ((work < (double)(1 << 22) && !conv) || g.K == 0) return gemm(g, 0, st);
     for (int b = 0; b < g.batch; ++b) {
         LArgs a{};
         a.M = g.M; a.N = g.N; a.K = g.K; a.Kp = Kp;
@@ -1007,7 +1057,8 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
         }
         bool fast = ta || (kc && g.K % KB == 0 && g.A[0].s0 % 2 == 0);
         for (int p = 0; p < na && fast && !ta; ++p) fast = ((uintptr_t)(g.A[p].p + b * g.A[p].sb) & 15) == 0;
-        const int ns = fast && tn >= 2 ? 2 : 1;
+        if (conv) fast = true;                   // limb_conv_ok: aligned planes, K in whole k-blocks
+        const int ns = fast && tn >= 2 && g.lt_ns != 1 ? 2 : 1;
         // K is split when the 64 x 64 tiles number fewer than the CUs (measured: a split costs
         // more than a half-filled second wave) and when it exceeds what the 32-bit digit sums
         // hold.  The splits write partial sums to the workspace and one pass adds them up
@@ -1024,6 +1075,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             const int64_t want = (4 * fill + groups - 1) / groups;
             splits = std::max<int64_t>(splits, std::min<int64_t>(want, maxseg * Kp / 64));
         }
+        if (g.lt_split > 1) splits = std::max<int64_t>(splits, std::min<int64_t>(splits * g.lt_split, maxseg * Kp / 64));
         const size_t plane = (size_t)nprod * g.M * g.N * 8 * nbl;
         const bool part_ok = g.ws_alloc != nullptr && !g.no_part && plane * need <= part_cap(g);
         if (part_ok) splits = std::min<int64_t>(splits, std::max<int64_t>(need, (int64_t)(part_cap(g) / plane)));
@@ -1086,6 +1138,11 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             l.M = g.M; l.N = g.N; l.K = g.K;
             l.lda = ta ? 1 : g.A[0].s0;
             l.ldk = ta ? g.A[0].s1 : 1;
+            if (conv) {
+                l.lda = 0;
+                l.cH = g.cH; l.cW = g.cW; l.cC = g.cC; l.cKW = g.cKW; l.cpad = g.cpad;
+                l.cOH = g.cOH; l.cOW = g.cOW; l.ccb = g.cC / KB;
+            }
             l.nkb = (int)nkb; l.bnkb = (int)nkb; l.kcb = (int)(kchunk / KB); l.nprod = nprod; l.splits = (int)splits;
             l.atomic = a.atomic; l.D = a.D; l.part = a.part;
             l.sbA = g.A[0].sb; l.sbC = g.C[0].sb; l.sbT = (int64_t)tbytes;
@@ -1143,8 +1200,11 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             l.rb = bbytes <= ((size_t)2 << 20) || nwg <= (ns == 2 ? 256 : 512)
                        ? 1
                        : (int)std::max<int64_t>(1, std::min<int64_t>(tm, (ns == 2 ? 32 : 64) / l.tn));
+            if (g.lt_rb > 0) l.rb = (int)std::min<int64_t>(g.lt_rb, tm);
             const dim3 gr((unsigned)(l.tn * tm * nprod * splits * nbl));
-            if (ta && ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2, true>), gr, dim3(2 * NT), 0, st, l);
+            if (conv && ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2, false, true>), gr, dim3(2 * NT), 0, st, l);
+            else if (conv) hipLaunchKernelGGL((k_lgemm2<true, 1, false, true>), gr, dim3(NT), 0, st, l);
+            else if (ta && ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2, true>), gr, dim3(2 * NT), 0, st, l);
             else if (ta) hipLaunchKernelGGL((k_lgemm2<true, 1, true>), gr, dim3(NT), 0, st, l);
             else if (ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2>), gr, dim3(2 * NT), 0, st, l);
             else if (fast) hipLaunchKernelGGL((k_lgemm2<true, 1>), gr, dim3(NT), 0, st, l);

@@ -523,6 +523,8 @@ static hipError_t gemm_rows(const GemmArgs& g, hipStream_t stream) {
 
 hipError_t gemm(const GemmArgs& g, int variant, hipStream_t stream) {
     if (g.shared > 1 && (g.party || g.shared > 3 || g.Dadd.p)) return hipErrorInvalidValue;
+    // the implicit lowering of a convolution exists in the limb kernel only
+    if (g.conv) return variant == 1 ? gemm_limb(g, stream) : hipErrorInvalidValue;
     // a few rows against a long K: one pass over B at full bandwidth, whichever backend
     if (rows_fit(g)) return gemm_rows(g, stream);
     // one small output tile: the K-parallel kernel, whichever backend was asked for (both

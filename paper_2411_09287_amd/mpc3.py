@@ -51,6 +51,9 @@ SIGNATURES = {
     "mpc3_set_chunk": (_I, [_P, _I64]),
     "mpc3_autotune": (_I, [_P, _I64, _I64, _I64, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double),
                            ctypes.POINTER(ctypes.c_double)]),
+    "mpc3_autotune_launch": (_I, [_P, _I64, _I64, _I64, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]),
+    "mpc3_set_launch": (_I, [_P, _I64, _I64, _I64, _I, _I, _I]),
     "mpc3_set_verify_chunks": (_I, [_P, _I64, _I64]),
     "mpc3_set_network": (_I, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "mpc3_keep_messages": (_I, [_P, _I]),
@@ -246,6 +249,17 @@ class Context:
             "mpc3_autotune", self.h)
         return ch.value, a.value, b.value
 
+    def autotune_launch(self, M, K, N, reps=5):
+        """Launch-shape autotuner of the limb kernel: ((ns, rb, split), ms_default, ms_best)."""
+        sh = (ctypes.c_int * 3)()
+        a, b = ctypes.c_double(0), ctypes.c_double(0)
+        _ck(lib().mpc3_autotune_launch(self.h, M, K, N, reps, sh, ctypes.byref(a), ctypes.byref(b)),
+            "mpc3_autotune_launch", self.h)
+        return (sh[0], sh[1], sh[2]), a.value, b.value
+
+    def set_launch(self, M, K, N, ns=0, rb=0, split=0):
+        _ck(lib().mpc3_set_launch(self.h, M, K, N, ns, rb, split), "mpc3_set_launch", self.h)
+
     def set_chunk(self, t):
         _ck(lib().mpc3_set_chunk(self.h, t), "mpc3_set_chunk", self.h)
 
@@ -319,14 +333,18 @@ class Context:
 
     @_on_stream
     def inner_conv(self, x, B, H, W, C, KH, KW, pad, Wt, pair=None, ld=None, stride=1, cols=None, out=None):
-        """mpc3_inner_conv: im2col of x into cols (ld >= KH KW C columns) and Pi_Inner with Wt,
-        the product verified from x.  Returns Z."""
+        """mpc3_inner_conv: Pi_Inner of the lowering of x (Wt.rows = ld >= KH KW C columns) with
+        Wt, the product verified from x.  cols=None lets the library lower implicitly in the
+        product kernel or into memory of its own; a DShare cols receives the lowering.
+        Returns Z."""
         OH, OW = (H + 2 * pad - KH) // stride + 1, (W + 2 * pad - KW) // stride + 1
-        if cols is None:
-            cols = DShare.empty(B * OH * OW, ld or KH * KW * C, self.device)
-        Z = out if out is not None else DShare.empty(cols.rows, Wt.cols, self.device)
-        xs, cs, ws, zs = x.c(), cols.c(), Wt.c(), Z.c()
-        _ck(lib().mpc3_inner_conv(self.h, ctypes.byref(xs), B, H, W, C, KH, KW, pad, stride, ctypes.byref(cs),
+        if ld is not None and ld != Wt.rows:
+            raise ValueError("ld must equal Wt.rows")
+        Z = out if out is not None else DShare.empty(B * OH * OW, Wt.cols, self.device)
+        xs, ws, zs = x.c(), Wt.c(), Z.c()
+        cs = cols.c() if cols is not None else None
+        _ck(lib().mpc3_inner_conv(self.h, ctypes.byref(xs), B, H, W, C, KH, KW, pad, stride,
+                                  ctypes.byref(cs) if cs is not None else None,
                                   ctypes.byref(ws), ctypes.byref(pair.s) if pair is not None else None,
                                   ctypes.byref(zs)), "mpc3_inner_conv", self.h)
         self._keep[VERIFY_INNER].append((x, cols, Wt, Z))

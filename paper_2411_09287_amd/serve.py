@@ -94,8 +94,9 @@ class Server:
         self.recorded = {}
 
     def tune(self, reqs, reps=3, log=None):
-        """Autotune the kernel family for every layer shape the packs will produce.  The
-        library keeps one choice per (M rounded up to a power of two, K, N), so each such
+        """Autotune the kernel family for every layer shape the packs will produce, and the
+        limb kernel's launch shape where that family wins on a product large enough for it.
+        The library keeps one choice per (M rounded up to a power of two, K, N), so each such
         bucket is timed once, at its largest M."""
         shapes = set()
         for p in packs_of(reqs, self.cap):
@@ -104,7 +105,9 @@ class Server:
                 b = bucket_of(b, self.cap[p[0][1]])
             shapes.update((m_bucket(M), K, N) for M, K, N in self.nets[p[0][1]].exec_shapes(b))
         for i, (M, K, N) in enumerate(sorted(shapes)):
-            self.ctx.autotune(M, K, N, reps)
+            choice, _, _ = self.ctx.autotune(M, K, N, reps)
+            if choice == mpc3.VARIANT_LIMB_I8 and M * K * N >= (1 << 22):
+                self.ctx.autotune_launch(M, K, N, reps)
             if log and (i + 1) % 16 == 0:
                 log(f"tuned {i + 1}/{len(shapes)} shapes")
         return len(shapes)

@@ -31,7 +31,14 @@ CASES = [
 ]
 
 
-def run(use_conv, convs, seed, first_dense=True, variant=1, inject=None):
+# same-padded convolutions whose channel counts are multiples of 32: with no cols buffer the
+# limb kernel lowers them implicitly (one and two 64-column tiles per workgroup, 3x3 and 5x5,
+# ragged row counts); the u64 kernel family lowers into the library's own memory
+CASES_IMPLICIT = [(2, 8, 8, 32, 3, 1, 1, 64, None), (1, 6, 10, 64, 3, 1, 1, 130, None),
+                  (2, 7, 5, 32, 5, 2, 1, 9, None), (3, 9, 7, 96, 3, 1, 1, 200, None)]
+
+
+def run(use_conv, convs, seed, first_dense=True, variant=1, inject=None, own_cols=False):
     g = np.random.default_rng(seed)
     c = mpc3.Context(SEED)
     c.set_variant(variant)
@@ -45,7 +52,11 @@ def run(use_conv, convs, seed, first_dense=True, variant=1, inject=None):
         w[K * K * C:] = 0
         Wt = c.share(mpc3.to_words(w))
         if use_conv:
-            Z = c.inner_conv(x, B, H, W, C, K, K, pad, Wt, ld=ld, stride=stride)
+            cols = None
+            if own_cols:
+                OH, OW = (H + 2 * pad - K) // stride + 1, (W + 2 * pad - K) // stride + 1
+                cols = mpc3.DShare.empty(B * OH * OW, kk, "cuda")
+            Z = c.inner_conv(x, B, H, W, C, K, K, pad, Wt, ld=ld, stride=stride, cols=cols)
         else:
             cols = c.im2col(x, B, H, W, C, K, K, pad, ld, stride=stride)
             Z = c.inner(cols, Wt)
@@ -91,4 +102,38 @@ def test_inner_conv_first_product_keeps_lowered_form():
 @pytest.mark.parametrize("inject", [(0, 5, 3), (2, 0, 1)])
 def test_inner_conv_error_detected(inject):
     ok, _, _, _ = run(True, CASES[0], seed=300, inject=inject)
+    assert not ok
+
+
+@pytest.mark.parametrize("variant", [1, 0])
+@pytest.mark.parametrize("own_cols", [False, True])
+def test_inner_conv_implicit_lowering_matches_lowered_product(variant, own_cols):
+    a = run(True, CASES_IMPLICIT, seed=500, variant=variant, own_cols=own_cols)
+    b = run(False, CASES_IMPLICIT, seed=500, variant=variant)
+    assert a[0] and b[0], "honest verification failed"
+    for za, zb in zip(a[1], b[1]):
+        for pa, pb in zip(za, zb):
+            assert np.array_equal(pa, pb)
+    assert len(a[2]) == len(b[2])
+    for la, lb in zip(a[2], b[2]):
+        assert np.array_equal(la, lb)
+    assert np.array_equal(a[3][0], b[3][0]) and a[3][1] == b[3][1]
+
+
+def test_inner_conv_first_product_with_32_channels_is_lowered():
+    # the batch's first product (o = 0) cannot be verified from its input: the library
+    # lowers it into its own memory and verifies the lowered form
+    convs = [(2, 6, 6, 32, 3, 1, 1, 64, None), (1, 6, 6, 64, 3, 1, 1, 70, None)]
+    a = run(True, convs, seed=9, first_dense=False)
+    b = run(False, convs, seed=9, first_dense=False)
+    assert a[0] and b[0]
+    for za, zb in zip(a[1], b[1]):
+        for pa, pb in zip(za, zb):
+            assert np.array_equal(pa, pb)
+    for la, lb in zip(a[2], b[2]):
+        assert np.array_equal(la, lb)
+
+
+def test_inner_conv_implicit_error_detected():
+    ok, _, _, _ = run(True, CASES_IMPLICIT, seed=501, inject=(1, 3, 77))
     assert not ok
