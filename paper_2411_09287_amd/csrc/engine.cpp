@@ -186,6 +186,8 @@ struct mpc3_ctx {
     hipEvent_t ev_fork2 = nullptr, ev_join2[NV] = {};
     hipStream_t cs = nullptr;
     Scratch* sc = nullptr;
+    // the verification's grouped products (host tables kept until the next group run)
+    GemmGroup* grp = nullptr;
     // autotuned kernel family per (M, K, N) of a three-party product
     std::map<std::tuple<int64_t, int64_t, int64_t>, int> tuned;
     // launch shape of the limb kernel per (M, K, N) of a three-party product: ns, rb, split
@@ -802,15 +804,9 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
     u64* Tall = c->sc->words(3 * J * 64);
     u64* Sall = c->sc->words(J * 64);
     u64* Cz = c->sc->words(3 * 4096);
-    // the products' compressions are independent: they run on the worker streams (each with
-    // its own workspace) and write their claim matrices, then join this stream
     hipStream_t home = c->cs;
     Scratch* home_sc = c->sc;
-    ck(hipEventRecord(c->ev_fork2, home));
-    for (int i = 0; i < mpc3_ctx::NV; ++i) ck(hipStreamWaitEvent(c->vs[i], c->ev_fork2, 0));
-    // rows in XY and gate offsets follow the call order; the compressions are issued smallest
-    // first, round-robin over the worker streams, so that the short, latency-bound chains of
-    // the small products run while the large ones fill the GPU
+    // rows in XY and gate offsets follow the call order
     const size_t ni = items.size();
     std::vector<int64_t> rows_at(ni), offs(ni), cost(ni);
     std::vector<size_t> order(ni);
@@ -827,52 +823,88 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
         }
         std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] < cost[b]; });
     }
+    // one product per step for the three share planes (shared right operand)
+    auto three = [&](GemmArgs g, const u64* const* Ap, int64_t as0, int64_t as1, auto out) {
+        g.shared = 3;
+        for (int p = 0; p < 3; ++p) {
+            g.A[p] = view(Ap[p], as0, as1);
+            g.C[p] = out(p);
+        }
+        run_gemm(c, g);
+    };
+    // products with leading rows of lo: the limb kernels take its digit tiles
+    auto lo_b = [&](GemmArgs g) {
+        g.btiles = lo_tiles;
+        g.btiles_nkb = L / 32;
+        return g;
+    };
+    // a same-padded stride-1 convolution from its input: S_c = sum_n r^n h[n, c] over the
+    // B H W positions, the band sums of the positions each shift leaves out, and
+    // x_(kh,kw,c) = r^(o_l - delta) (S_c - E); every power is non-negative once o_l is at
+    // least the largest forward shift pad W + pad (so not for the first product)
+    std::vector<char> conv_fast(ni, 0);
+    for (size_t i = 0; i < ni; ++i) {
+        const Pending& P = *items[i];
+        conv_fast[i] = P.conv && P.cstride == 1 && P.cKH == P.cKW && P.cKH == 2 * P.cpad + 1 &&
+                       (int64_t)P.cB * P.cH * P.cW == P.X.rows && P.X.cols >= (int64_t)P.cKH * P.cKW * P.cC &&
+                       offs[i] >= (int64_t)P.cpad * P.cW + P.cpad && P.cpad >= 1;
+        // a product registered without its lowered matrix is verified from its input
+        if (!conv_fast[i] && !P.X.m) throw CodeError(MPC3_E_STATE);
+    }
+    // Every product's sums against leading rows of lo -- x_k = sum_m r^m X[m, k] (or a
+    // convolution's channel sums S), T_n = sum_m r^m Z[m, n] -- in one grouped launch on this
+    // stream (the limb kernel: one grid over all of them, one grouped reduction of their
+    // split-K partial sums)
+    if (!c->grp) c->grp = gemm_group_new();
+    auto grouped = [&](GemmArgs g) {
+        g.group = c->grp;
+        return g;
+    };
+    std::vector<u64*> Sbuf(ni, nullptr);
+    for (size_t i = 0; i < ni; ++i) {
+        const Pending& P = *items[i];
+        const int64_t M = P.X.rows, K = P.X.cols, N = P.W.cols;
+        if (conv_fast[i]) {
+            const int64_t C = P.cC;
+            Sbuf[i] = c->sc->words(3 * C * 64);
+            const u64* Hc[3] = {P.cx.m, P.cx.r1, P.cx.r2};
+            three(grouped(lo_b(plain(C, 64, M, View{}, view(lo, 64, 1), OutView{}, false))), Hc, 1, C,
+                  [&](int p) { return oview(Sbuf[i] + p * C * 64, 64, 1); });
+        } else {
+            const u64* Xc[3] = {P.X.m, P.X.r1, P.X.r2};
+            u64* U = XY + rows_at[i] * 64;
+            three(grouped(lo_b(plain(K, 64, M, View{}, view(lo, 64, 1), OutView{}, false))), Xc, 1, K,
+                  [&](int p) { return oview(U + p * np * 64, 64, 1); });
+        }
+        const u64* Zc[3] = {P.Z.m, P.Z.r1, P.Z.r2};
+        u64* T = Tall + jrow[i] * 64;                // plane p at T + p J 64
+        three(grouped(lo_b(plain(N, 64, M, View{}, view(lo, 64, 1), OutView{}, false))), Zc, 1, N,
+              [&](int p) { return oview(T + p * J * 64, 64, 1); });
+    }
+    ck(gemm_group_run(c->grp, scratch_alloc, c->sc, home));
+    // the rest of each product's compression is independent of the others: on the worker
+    // streams (each with its own workspace), issued smallest first, round-robin, so that the
+    // short chains of the small products run beside the large ones; then they join this stream
+    ck(hipEventRecord(c->ev_fork2, home));
+    for (int i = 0; i < mpc3_ctx::NV; ++i) ck(hipStreamWaitEvent(c->vs[i], c->ev_fork2, 0));
     for (size_t q = 0; q < ni; ++q) {
-        const Pending* it = items[order[q]];
-        const int64_t row = rows_at[order[q]], off = offs[order[q]];
-        const int64_t M = it->X.rows, K = it->X.cols, N = it->W.cols;
+        const size_t i = order[q];
+        const Pending& P = *items[i];
+        const int64_t row = rows_at[i], off = offs[i];
+        const int64_t M = P.X.rows, K = P.X.cols, N = P.W.cols;
         const int w = (int)(q % mpc3_ctx::NV);
         c->cs = c->vs[w];
         c->sc = &c->vsc2[w];
         s = c->cs;
         Scratch::Mark mk = c->sc->mark();
         u64* sig = c->sc->words(N * 64);             // r^{M n}
-        u64* sigo = Sall + jrow[order[q]] * 64;      // r^{o_l + M n} (row 0: r^{o_l})
+        u64* sigo = Sall + jrow[i] * 64;             // r^{o_l + M n} (row 0: r^{o_l})
         launch_pow_ap2(lo, hi, L, 0, off, M, N, sig, sigo, s);
-        const u64* Xc[3] = {it->X.m, it->X.r1, it->X.r2};
-        const u64* Wc[3] = {it->W.m, it->W.r1, it->W.r2};
-        const u64* Zc[3] = {it->Z.m, it->Z.r1, it->Z.r2};
-        u64* T = Tall + jrow[order[q]] * 64;         // plane p at T + p J 64
-        // one product per step for the three share planes (shared right operand)
-        auto three = [&](GemmArgs g, const u64* const* Ap, int64_t as0, int64_t as1, auto out) {
-            g.shared = 3;
-            for (int p = 0; p < 3; ++p) {
-                g.A[p] = view(Ap[p], as0, as1);
-                g.C[p] = out(p);
-            }
-            run_gemm(c, g);
-        };
+        const u64* Wc[3] = {P.W.m, P.W.r1, P.W.r2};
         u64* U = XY + row * 64;
-        // x_k = r^{o_l} sum_m r^m X[m, k]
-        auto lo_b = [&](GemmArgs g) {
-            g.btiles = lo_tiles;
-            g.btiles_nkb = L / 32;
-            return g;
-        };
-        // a same-padded stride-1 convolution from its input: S_c = sum_n r^n h[n, c] over the
-        // B H W positions, the band sums of the positions each shift leaves out, and
-        // x_(kh,kw,c) = r^(o_l - delta) (S_c - E); every power is non-negative once o_l is at
-        // least the largest forward shift pad W + pad (so not for the first product)
-        const Pending& P = *it;
-        const bool conv_fast = P.conv && P.cstride == 1 && P.cKH == P.cKW && P.cKH == 2 * P.cpad + 1 &&
-                               (int64_t)P.cB * P.cH * P.cW == M && K >= (int64_t)P.cKH * P.cKW * P.cC &&
-                               off >= (int64_t)P.cpad * P.cW + P.cpad && P.cpad >= 1;
-        if (conv_fast) {
+        if (conv_fast[i]) {
             const int64_t C = P.cC;
-            u64* S = c->sc->words(3 * C * 64);
             const u64* Hc[3] = {P.cx.m, P.cx.r1, P.cx.r2};
-            three(lo_b(plain(C, 64, M, View{}, view(lo, 64, 1), OutView{}, false)), Hc, 1, C,
-                  [&](int p) { return oview(S + p * C * 64, 64, 1); });
             ConvBandArgs ba{};
             for (int p = 0; p < 3; ++p) ba.h[p] = Hc[p];
             ba.lo = lo;
@@ -890,23 +922,18 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
             u64* F = c->sc->words((int64_t)P.cKH * P.cKW * 64);
             launch_pow_shifts(lo, hi, L, off + (int64_t)P.cpad * P.cW + P.cpad, P.cKH, P.cKW, P.cW, F, s);
             ConvXArgs xa{};
-            xa.S = S; xa.E = E; xa.F = F;
+            xa.S = Sbuf[i]; xa.E = E; xa.F = F;
             xa.KH = P.cKH; xa.KW = P.cKW; xa.C = P.cC; xa.pad = P.cpad; xa.nsets = ba.nsets;
             xa.K = K; xa.U = U; xa.ustride = np * 64;
             launch_conv_x(xa, s);
             ck(hipGetLastError());
         } else {
-            three(lo_b(plain(K, 64, M, View{}, view(lo, 64, 1), OutView{}, false)), Xc, 1, K,
-                  [&](int p) { return oview(U + p * np * 64, 64, 1); });
+            // x_k = r^{o_l} sum_m r^m X[m, k]
             launch_gr_mul_rows(sigo, U, K, K, U, s, 3, np * 64);
         }
         // y_k = sum_n r^{M n} W[k, n]
         three(plain(K, 64, N, View{}, view(sig, 64, 1), OutView{}, false), Wc, N, 1,
               [&](int p) { return oview(XY + (3 + p) * np * 64 + row * 64, 64, 1); });
-        // T_n = sum_m r^m Z[m, n] into the stacked rows; z += sum_n r^{o_l + M n} T_n is one
-        // product over all stacked rows after the join
-        three(lo_b(plain(N, 64, M, View{}, view(lo, 64, 1), OutView{}, false)), Zc, 1, N,
-              [&](int p) { return oview(T + p * J * 64, 64, 1); });
         c->sc->restore(mk);
     }
     c->cs = s = home;
@@ -1690,6 +1717,7 @@ int mpc3_ctx_destroy(mpc3_ctx* c) {
         for (int i = 0; i < 3; ++i)
             if (c->msg[k][i]) (void)hipFree(c->msg[k][i]);
     if (c->inv_dev) (void)hipFree(c->inv_dev);
+    if (c->grp) gemm_group_free(c->grp);
     delete c;
     return MPC3_OK;
 }

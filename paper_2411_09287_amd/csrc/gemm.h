@@ -5,6 +5,8 @@
 namespace mpc3 {
 
 // A strided view: element (i, j) of batch b is p[b*sb + i*s0 + j*s1].
+struct GemmGroup;
+
 struct View {
     const u64* p;
     int64_t s0, s1, sb;
@@ -55,7 +57,19 @@ struct GemmArgs {
     // K = cKH cKW cC; input positions outside the image (padding cpad) read as 0
     int conv;
     int cH, cW, cC, cKH, cKW, cpad, cOH, cOW;
+    // record instead of launch (gemm_group_run)
+    GemmGroup* group;
 };
+
+// Products launched together: with GemmArgs::group set, a product that runs on the limb
+// kernel's converted-B path is recorded instead of launched (any B conversion it needs is
+// still launched at once), and gemm_group_run launches every recorded product of one kernel
+// variant as one grid over a device table of the products (each workgroup finds its product
+// and tile there), then all their split-K reductions as one more grid.  Other products
+// launch at once.  The group keeps the host copies of its tables until its next run.
+GemmGroup* gemm_group_new();
+void gemm_group_free(GemmGroup* g);
+hipError_t gemm_group_run(GemmGroup* g, void* (*ws_alloc)(void*, size_t), void* ws_self, hipStream_t stream);
 
 // Whether the limb kernel takes g's implicit lowering (C a multiple of 32, K = KH KW C,
 // stride 1, 16-byte aligned planes, one batch, a workspace for the B tiles).
@@ -66,6 +80,20 @@ inline size_t part_cap(const GemmArgs& g);
 
 // Launch on `stream` with the chosen backend (0 = u64 VALU, 1 = int8 limbs on MFMA).
 hipError_t gemm(const GemmArgs& g, int variant, hipStream_t stream);
+
+// One split-K reduction: part holds batch x splits x nprod planes of M x N words (n
+// fastest); C[p] = their sum (+ D for nprod 1), or C[p] += sum with atomics.
+struct RedArgs {
+    const u64* part;
+    int64_t M, N;
+    int nprod, splits, batch, atomic;
+    OutView C[3];
+    View D;
+};
+// Many reductions in one grid: tab (device) holds n jobs, start (device) n + 1 prefix counts
+// of 64-output blocks; W waves per block (at most 16) share each block's splits.
+hipError_t split_reduce_group(const RedArgs* tab, const int64_t* start, int n, int64_t nblk, int W,
+                              hipStream_t stream);
 
 // Split-K partial sums: part holds batch x splits x nprod planes of M x N words (n fastest).
 // C[p] = sum over splits (+ D when D.p is set, nprod == 1), or C[p] += sum (64-bit atomic

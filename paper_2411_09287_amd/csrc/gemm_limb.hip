@@ -11,7 +11,9 @@
 // int8: the byte carries of that addition are exactly the carries of the balanced
 // representation.  Tiles are read as 64-bit words, converted in registers, transposed
 // to digit planes in LDS and fed to v_mfma_i32_32x32x32_i8; no digit planes touch HBM.
+#include <cstring>
 #include <type_traits>
+#include <vector>
 
 #include "gemm.h"
 #include "limb_digits.h"
@@ -342,8 +344,9 @@ __device__ __forceinline__ void wait_vm() {
 //     flight, so every wait the compiler places is exact.
 // Otherwise (NS = 1): B tiles are copied straight into LDS (global_load_lds) and A words are
 // converted after the MFMAs.
-template <bool FAST, int NS, bool TA = false, bool CONV = false>
-__global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
+// One workgroup's tile: workgroup L of the nwg of product a.
+template <bool FAST, int NS, bool TA, bool CONV>
+__device__ __forceinline__ void lgemm2_tile(const L2Args& a, const int L, const int nwg) {
     static_assert(!CONV || (FAST && !TA), "the implicit lowering loads 16-byte pieces of k-contiguous rows");
     constexpr int WPT = 8 / NS;                  // A words converted per thread and k-block
     __shared__ __attribute__((aligned(16))) int8_t As[2][TILE_BYTES];
@@ -355,7 +358,8 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
     // group of one (product, split) before the next: the workgroups an XCD runs at once
     // walk K together over the same B tiles, and the column groups of a row tile share
     // its A rows, in that XCD's L2.
-    const int nwg = gridDim.x, L = blockIdx.x, q8 = nwg / 8;
+    if (L >= nwg) return;                        // a group's padding workgroup
+    const int q8 = nwg / 8;
     const int T0 = L < 8 * q8 ? (L % 8) * q8 + L / 8 : L;
     const int per = a.tn * a.nprod * a.splits;   // workgroups per row tile
     const int bI = T0 / (per * a.tm);            // batch (consecutive runs of T)
@@ -649,6 +653,25 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
             *p = val;
         }
     }
+}
+
+template <bool FAST, int NS, bool TA = false, bool CONV = false>
+__global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2(L2Args a) {
+    lgemm2_tile<FAST, NS, TA, CONV>(a, blockIdx.x, gridDim.x);
+}
+
+// The products of a group in one grid: product j takes workgroups start[j] ..
+// start[j] + count[j] - 1; start[j] is a multiple of 8, so each product's workgroups reach
+// the XCDs in the order its tile numbering assumes.  The block index decides the product
+// for the whole workgroup, so its fields are read as scalars.
+template <bool FAST, int NS, bool TA = false, bool CONV = false>
+__global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2_group(const L2Args* tab, const int* start,
+                                                                   const int* count, int n) {
+    const int blk = blockIdx.x;
+    int j = 0;
+    for (int i = 1; i < n; ++i)
+        if (start[i] <= blk) j = i;
+    lgemm2_tile<FAST, NS, TA, CONV>(tab[j], blk - start[j], count[j]);
 }
 
 inline int64_t rup(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
@@ -972,6 +995,90 @@ bool limb_conv_ok(const GemmArgs& g) {
     return ok;
 }
 
+// Recorded products per kernel variant (0: <false, 1>, 1: <true, 1>, 2: <true, 2>, 3 and 4:
+// the transposed-view kernels with 1 and 2 column tiles, 5 and 6: the implicit lowering),
+// their reductions, and the host staging of the device tables.
+struct GemmGroup {
+    static constexpr int NVAR = 7;
+    std::vector<L2Args> args[NVAR];
+    std::vector<int> count[NVAR];
+    std::vector<RedArgs> red;
+    std::vector<char> stage[NVAR + 1];
+};
+
+GemmGroup* gemm_group_new() { return new GemmGroup(); }
+void gemm_group_free(GemmGroup* g) { delete g; }
+
+hipError_t gemm_group_run(GemmGroup* g, void* (*ws_alloc)(void*, size_t), void* ws_self, hipStream_t st) {
+    // a table of n entries of type T, then the n + 1 prefix starts (workgroups rounded up to
+    // a multiple of 8, or blocks) and the n counts, copied to the workspace in one transfer
+    auto upload = [&](std::vector<char>& h, const void* tab, size_t tbytes, const std::vector<int64_t>& start,
+                      const std::vector<int>& cnt, bool wide, char** dev) -> hipError_t {
+        const size_t sbytes = start.size() * (wide ? 8 : 4), cbytes = cnt.size() * 4;
+        const size_t o1 = (tbytes + 255) & ~(size_t)255, o2 = (o1 + sbytes + 255) & ~(size_t)255;
+        h.assign(o2 + cbytes, 0);
+        std::memcpy(h.data(), tab, tbytes);
+        for (size_t i = 0; i < start.size(); ++i) {
+            if (wide) ((int64_t*)(h.data() + o1))[i] = start[i];
+            else ((int*)(h.data() + o1))[i] = (int)start[i];
+        }
+        if (cbytes) std::memcpy(h.data() + o2, cnt.data(), cbytes);
+        *dev = (char*)ws_alloc(ws_self, h.size());
+        if (!*dev) return hipErrorOutOfMemory;
+        return hipMemcpyAsync(*dev, h.data(), h.size(), hipMemcpyHostToDevice, st);
+    };
+    for (int v = 0; v < GemmGroup::NVAR; ++v) {
+        const int n = (int)g->args[v].size();
+        if (n == 0) continue;
+        std::vector<int64_t> start(n + 1, 0);
+        for (int i = 0; i < n; ++i) start[i + 1] = start[i] + (g->count[v][i] + 7) / 8 * 8;
+        if (start[n] > 0x7FFFFFFF) return hipErrorInvalidValue;
+        char* dev = nullptr;
+        hipError_t e = upload(g->stage[v], g->args[v].data(), n * sizeof(L2Args), start, g->count[v], false, &dev);
+        if (e != hipSuccess) return e;
+        const size_t o1 = (n * sizeof(L2Args) + 255) & ~(size_t)255;
+        const size_t o2 = (o1 + (n + 1) * 4 + 255) & ~(size_t)255;
+        const L2Args* tab = (const L2Args*)dev;
+        const int* sp = (const int*)(dev + o1);
+        const int* cp = (const int*)(dev + o2);
+        const dim3 gr((unsigned)start[n]);
+        switch (v) {
+            case 0: hipLaunchKernelGGL((k_lgemm2_group<false, 1>), gr, dim3(NT), 0, st, tab, sp, cp, n); break;
+            case 1: hipLaunchKernelGGL((k_lgemm2_group<true, 1>), gr, dim3(NT), 0, st, tab, sp, cp, n); break;
+            case 2: hipLaunchKernelGGL((k_lgemm2_group<true, 2>), gr, dim3(2 * NT), 0, st, tab, sp, cp, n); break;
+            case 3: hipLaunchKernelGGL((k_lgemm2_group<true, 1, true>), gr, dim3(NT), 0, st, tab, sp, cp, n); break;
+            case 4: hipLaunchKernelGGL((k_lgemm2_group<true, 2, true>), gr, dim3(2 * NT), 0, st, tab, sp, cp, n); break;
+            case 5:
+                hipLaunchKernelGGL((k_lgemm2_group<true, 1, false, true>), gr, dim3(NT), 0, st, tab, sp, cp, n);
+                break;
+            default:
+                hipLaunchKernelGGL((k_lgemm2_group<true, 2, false, true>), gr, dim3(2 * NT), 0, st, tab, sp, cp, n);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        g->args[v].clear();
+        g->count[v].clear();
+    }
+    const int nr = (int)g->red.size();
+    if (nr > 0) {
+        std::vector<int64_t> start(nr + 1, 0);
+        int W = 1;
+        for (int i = 0; i < nr; ++i) {
+            const RedArgs& r = g->red[i];
+            start[i + 1] = start[i] + ((int64_t)r.batch * r.nprod * r.M * r.N + 63) / 64;
+            W = std::max(W, std::min(r.splits, 16));
+        }
+        char* dev = nullptr;
+        hipError_t e = upload(g->stage[GemmGroup::NVAR], g->red.data(), nr * sizeof(RedArgs), start, {}, true, &dev);
+        if (e != hipSuccess) return e;
+        const size_t o1 = (nr * sizeof(RedArgs) + 255) & ~(size_t)255;
+        e = split_reduce_group((const RedArgs*)dev, (const int64_t*)(dev + o1), nr, start[nr], W, st);
+        if (e != hipSuccess) return e;
+        g->red.clear();
+    }
+    return hipSuccess;
+}
+
 hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     if (g.conv && !limb_conv_ok(g)) return hipErrorInvalidValue;
@@ -1076,6 +1183,9 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
             splits = std::max<int64_t>(splits, std::min<int64_t>(want, maxseg * Kp / 64));
         }
         if (g.lt_split > 1) splits = std::max<int64_t>(splits, std::min<int64_t>(splits * g.lt_split, maxseg * Kp / 64));
+        // a grouped product need not fill the GPU alone: at least 1024 of K per split, so
+        // that a workgroup's k-loop outweighs its partial-sum tile
+        if (g.group) splits = std::max<int64_t>(need, std::min<int64_t>(splits, maxseg * Kp / 1024));
         const size_t plane = (size_t)nprod * g.M * g.N * 8 * nbl;
         const bool part_ok = g.ws_alloc != nullptr && !g.no_part && plane * need <= part_cap(g);
         if (part_ok) splits = std::min<int64_t>(splits, std::max<int64_t>(need, (int64_t)(part_cap(g) / plane)));
@@ -1202,6 +1312,23 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
                        : (int)std::max<int64_t>(1, std::min<int64_t>(tm, (ns == 2 ? 32 : 64) / l.tn));
             if (g.lt_rb > 0) l.rb = (int)std::min<int64_t>(g.lt_rb, tm);
             const dim3 gr((unsigned)(l.tn * tm * nprod * splits * nbl));
+            if (g.group) {
+                // recorded for gemm_group_run (kernel variant, arguments, workgroups, reduction)
+                const int vid = conv ? (ns == 2 ? 6 : 5) : ta ? (ns == 2 ? 4 : 3) : ns == 2 ? 2 : fast ? 1 : 0;
+                g.group->args[vid].push_back(l);
+                g.group->count[vid].push_back((int)gr.x);
+                if (a.part) {
+                    RedArgs r{};
+                    r.part = a.part;
+                    r.M = g.M; r.N = g.N; r.nprod = nprod; r.splits = (int)splits; r.batch = (int)nbl;
+                    r.atomic = g.accumulate ? 1 : 0;
+                    for (int p = 0; p < nprod; ++p) r.C[p] = outs[p];
+                    r.D = nprod == 1 ? a.D : View{nullptr, 0, 0, 0};
+                    g.group->red.push_back(r);
+                }
+                if (nbl > 1) return hipSuccess;
+                continue;
+            }
             if (conv && ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2, false, true>), gr, dim3(2 * NT), 0, st, l);
             else if (conv) hipLaunchKernelGGL((k_lgemm2<true, 1, false, true>), gr, dim3(NT), 0, st, l);
             else if (ta && ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2, true>), gr, dim3(2 * NT), 0, st, l);

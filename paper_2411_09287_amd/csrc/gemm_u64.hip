@@ -277,21 +277,13 @@ __global__ __launch_bounds__(256) void k_gemm_kpar(GemmArgs g) {
     store(g.C[p], b, m, n, v, g.accumulate);
 }
 
-struct RedArgs {
-    const u64* part;
-    int64_t M, N;
-    int nprod, splits, batch, atomic;
-    OutView C[3];
-    View D;
-};
-
 // Block = 64 consecutive output words x W waves: wave w adds the partials of splits w,
 // w + W, ... for its 64 words (coalesced 512-byte reads), then the W sums are added in LDS.
-__global__ __launch_bounds__(1024) void k_split_reduce(RedArgs r) {
+__device__ __forceinline__ void split_reduce_block(const RedArgs& r, int64_t blk) {
     __shared__ u64 acc[16][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, W = blockDim.x >> 6;
     const int64_t mn = r.M * r.N;
-    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t idx = blk * 64 + lane;
     const bool live = idx < (int64_t)r.batch * r.nprod * mn;
     const int64_t e = idx % mn, bp = idx / mn;
     const int p = (int)(bp % r.nprod);
@@ -318,6 +310,18 @@ __global__ __launch_bounds__(1024) void k_split_reduce(RedArgs r) {
         if (r.D.p) v += r.D.p[b * r.D.sb + m * r.D.s0 + n * r.D.s1];
         *dst = v;
     }
+}
+
+__global__ __launch_bounds__(1024) void k_split_reduce(RedArgs r) { split_reduce_block(r, blockIdx.x); }
+
+// Job j takes blocks start[j] .. start[j + 1] - 1 (the block index decides the job for the
+// whole workgroup, so the job's fields are read as scalars).
+__global__ __launch_bounds__(1024) void k_split_reduce_group(const RedArgs* tab, const int64_t* start, int n) {
+    const int64_t blk = blockIdx.x;
+    int j = 0;
+    for (int i = 1; i < n; ++i)
+        if (start[i] <= blk) j = i;
+    split_reduce_block(tab[j], blk - start[j]);
 }
 
 // A few rows against a tall operand (up to RD_M rows of A, N <= 64, long K): a workgroup
@@ -475,6 +479,15 @@ hipError_t split_reduce(const u64* part, int64_t M, int64_t N, int nprod, int sp
     hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((n + 63) / 64)), dim3(64 * W), 0, stream, r);
     return hipGetLastError();
 }
+
+hipError_t split_reduce_group(const RedArgs* tab, const int64_t* start, int n, int64_t nblk, int W,
+                              hipStream_t stream) {
+    if (n <= 0 || nblk <= 0) return hipSuccess;
+    if (nblk > 0x7FFFFFFF || W < 1 || W > 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_split_reduce_group, dim3((unsigned)nblk), dim3(64 * W), 0, stream, tab, start, n);
+    return hipGetLastError();
+}
+
 
 // Plain or shared products with at most RD_M rows of A in all, N <= 64 and a long K
 // (A planes with one k stride): k_rows_dot over about 1024 ranges of K, then the split
