@@ -463,16 +463,16 @@ def run_depth(args):
 
 def run_mix(args):
     """Mixed-request serving: packed with direct calls (every request at time 0), packed
-    from HIP graphs per (model, batch bucket) (every request at time 0, and open-loop
-    Poisson arrivals at 70% of the graph server's measured capacity), and the u64
-    per-request baseline."""
+    per (model, batch bucket) from HIP graphs where the replay was measured faster than
+    direct calls (every request at time 0, and open-loop Poisson arrivals at 70% of that
+    server's measured capacity), and the u64 per-request baseline."""
     import torch
     from paper_2411_09287_amd import mpc3, serve
 
     torch.cuda.set_device(0)
     reqs = serve.request_mix(args.requests, seed=5)
     out = {}
-    runs = [("limb_packed", mpc3.VARIANT_AUTO, True, False), ("limb_packed_graphs", mpc3.VARIANT_AUTO, True, True)]
+    runs = [("limb_packed", mpc3.VARIANT_AUTO, True, False), ("limb_packed_graphs", mpc3.VARIANT_AUTO, True, "auto")]
     if not args.no_baseline:
         runs.append(("u64_per_request", mpc3.VARIANT_U64, False, False))
     for label, variant, pack, graphs in runs:
@@ -484,6 +484,10 @@ def run_mix(args):
             if variant == mpc3.VARIANT_AUTO:
                 n = srv.tune(reqs, log=lambda m: log(f"[mix] {m}"))
                 log(f"[mix] tuned {n} layer shapes")
+            if graphs == "auto":
+                picks = srv.tune_graphs()
+                out["graph_buckets"] = sorted(f"{m}_b{b}" for (m, b), v in picks.items() if v)
+                log(f"[mix] graphs chosen for {out['graph_buckets']}")
             res = srv.run(reqs, pack=pack, log=lambda m: log(f"[mix] {label} {m}"))
             out[label] = serve.summary(res)
             log(f"[mix] {label}: {json.dumps(out[label])}")

@@ -82,16 +82,23 @@ class Server:
     """graphs=True: every pack runs at its batch bucket (power of two, zero images padding
     it) from a HIP graph recorded on first use per (model, bucket) (network.RecordedForward;
     buckets whose layers exceed the library's fixed workspace run by direct calls).
-    buckets=True without graphs pads the same way but makes the calls directly, so both
-    draw the same masks.  The context of a graph server needs a stream of its own."""
+    graphs="auto": the same for the (model, bucket) pairs where tune_graphs measured the
+    replay faster than direct calls (the direct calls can use kernels a recording cannot,
+    such as the implicit lowering of convolutions); the other packs run unpadded by direct
+    calls.  buckets=True without graphs pads every pack the same way but makes the calls
+    directly, buckets="picked" pads only the packs whose bucket has a graph picked: both draw
+    the masks of the graph servers.  The context of a graph server needs a stream of its own."""
 
     def __init__(self, ctx, models=MODEL_NAMES, cap=None, graphs=False, buckets=None):
         self.ctx = ctx
         self.nets = {m: Network(ctx, m) for m in models}
         self.cap = dict(DEFAULT_CAP if cap is None else cap)
         self.graphs = graphs
-        self.buckets = graphs if buckets is None else buckets
+        if buckets is None:
+            buckets = "picked" if graphs == "auto" else bool(graphs)
+        self.buckets = buckets
         self.recorded = {}
+        self.graph_pick = {}
 
     def tune(self, reqs, reps=3, log=None):
         """Autotune the kernel family for every layer shape the packs will produce, and the
@@ -101,9 +108,9 @@ class Server:
         shapes = set()
         for p in packs_of(reqs, self.cap):
             b = sum(r[2] for r in p)
-            if self.buckets:
-                b = bucket_of(b, self.cap[p[0][1]])
-            shapes.update((m_bucket(M), K, N) for M, K, N in self.nets[p[0][1]].exec_shapes(b))
+            # the pack's own size, and its bucket where packs may be padded
+            for bb in {b, bucket_of(b, self.cap[p[0][1]]) if self.buckets else b}:
+                shapes.update((m_bucket(M), K, N) for M, K, N in self.nets[p[0][1]].exec_shapes(bb))
         for i, (M, K, N) in enumerate(sorted(shapes)):
             choice, _, _ = self.ctx.autotune(M, K, N, reps)
             if choice == mpc3.VARIANT_LIMB_I8 and M * K * N >= (1 << 22):
@@ -111,6 +118,36 @@ class Server:
             if log and (i + 1) % 16 == 0:
                 log(f"tuned {i + 1}/{len(shapes)} shapes")
         return len(shapes)
+
+    def tune_graphs(self, reps=3, log=None):
+        """graphs="auto": for every model and batch bucket up to its cap, time a direct
+        forward against the replay of the recorded graph (median of reps, each verified
+        before the next, synchronised wall time) and keep the faster.  Returns the picks."""
+        ctx = self.ctx
+        for name, net in self.nets.items():
+            bk = 1
+            while bk <= self.cap[name]:
+                rf = self._graph(name, bk)
+                if rf is None:
+                    self.graph_pick[(name, bk)] = False
+                else:
+                    x = request_input(name, bk, 0, ctx.device)
+                    tt = {"direct": [], "graph": []}
+                    for _ in range(reps):
+                        for kind in tt:
+                            torch.cuda.synchronize()
+                            t0 = time.perf_counter()
+                            h = net.forward(x) if kind == "direct" else rf(x)
+                            torch.cuda.synchronize()
+                            tt[kind].append(time.perf_counter() - t0)
+                            if not ctx.verify():
+                                raise RuntimeError("verification failed in an honest run")
+                            del h
+                    self.graph_pick[(name, bk)] = float(np.median(tt["graph"])) < float(np.median(tt["direct"]))
+                if log:
+                    log(f"graph pick {name} bucket {bk}: {self.graph_pick[(name, bk)]}")
+                bk *= 2
+        return dict(self.graph_pick)
 
     def _graph(self, name, bk):
         key = (name, bk)
@@ -127,11 +164,13 @@ class Server:
         """Shared logits of the images x (rows beyond x.shape[0] belong to padding) and
         whether a recorded graph produced them."""
         net = self.nets[name]
-        if not self.buckets:
-            return net.forward(x), False
         b = x.shape[0]
         bk = bucket_of(b, self.cap[name])
-        rf = self._graph(name, bk) if self.graphs else None
+        pick = self.graph_pick.get((name, bk), False)
+        if not (self.buckets is True or (self.buckets == "picked" and pick)):
+            return net.forward(x), False
+        use = self.graphs is True or (self.graphs == "auto" and pick)
+        rf = self._graph(name, bk) if use else None
         if rf is not None:
             return rf(x), True
         if bk > b:

@@ -190,3 +190,30 @@ def test_server_with_graphs_matches_direct_packs():
             assert la.shape == (r[2], 10) and torch.equal(la, lb)
     ca.close()
     cb.close()
+
+
+def test_server_auto_graphs_matches_direct_packs():
+    """graphs="auto": every (model, bucket) up to the cap gets a measured pick, and packs
+    served with the picked graphs (the others unpadded, by direct calls) open to the same
+    logits as a twin server that makes the same calls directly (its tuning makes the same
+    forwards and it pads the same packs, so both draw the same masks)."""
+    reqs = [(0, "mlp", 3), (1, "lenet", 2), (2, "mlp", 5), (3, "lenet", 1), (4, "mlp", 2)]
+    cap = {"mlp": 8, "lenet": 4, "vgg": 2}
+    ca = mpc3.Context(SEED, stream=torch.cuda.Stream())
+    cb = mpc3.Context(SEED, stream=torch.cuda.Stream())
+    sa = serve.Server(ca, models=("mlp", "lenet"), cap=cap, graphs="auto")
+    sb = serve.Server(cb, models=("mlp", "lenet"), cap=cap, graphs=False, buckets="picked")
+    pa = sa.tune_graphs(reps=1)
+    sb.tune_graphs(reps=1)
+    sb.graph_pick = dict(pa)
+    assert set(pa) == {("mlp", b) for b in (1, 2, 4, 8)} | {("lenet", b) for b in (1, 2, 4)}
+    ra = sa.run(reqs, keep_logits=True)
+    rb = sb.run(reqs, keep_logits=True)
+    assert ra["ok"] and rb["ok"] and rb["graph_packs"] == 0
+    picked = sum(int(pa[(p[0][1], serve.bucket_of(sum(r[2] for r in p), cap[p[0][1]]))])
+                 for p in serve.packs_of(reqs, cap))
+    assert ra["graph_packs"] == picked
+    for r in reqs:
+        assert torch.equal(ra["logits"][r[0]], rb["logits"][r[0]])
+    ca.close()
+    cb.close()
