@@ -812,49 +812,68 @@ __global__ void k_round_rows(Keys kk, u32 op, u32 inst, int k0, u64* out) {
     for (int q = 0; q < 8; ++q) o[q] = wv[q];
 }
 
+// Quarter q (coefficients i of a in [16 q, 16 q + 16)) of the anti-diagonal sums of
+// a (x) b at lane k: lo takes the terms with i <= k (coefficient k), hi the others
+// (coefficient 64 + k, for reduce_wave); a and b in LDS, a read as a broadcast.
+__device__ __forceinline__ void gr_acc_quarter(const u64* a, const u64* b, int k, int q, u64& lo, u64& hi) {
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) {
+        const int i = 16 * q + ii;
+        const u64 p = a[i] * b[(k - i) & 63];
+        if (i <= k) lo += p;
+        else hi += p;
+    }
+}
+
 // The middle of a Pi_Reduce round in one workgroup, from the partial anti-diagonal sums of
 // the parties' h(0) and h(x) products (hpair_party): their sum and reduction modulo the
-// ring's modulus, both Pi_PolyEvl exchanges (P0's [Gamma]_2, P1's and P2's m shares, as
-// k_polyevl_finish), the revealed point zeta, the Lagrange step of the claim z (as
-// k_round_finish), and the digit tiles of the multiplication matrix of zeta for the fold
-// on the matrix cores.  The keystream rows come drawn ahead (k_round_rows); the waves run
-// their ring products without block-wide barriers: waves 0..2 the Lagrange weights and the
-// three planes of z, wave 3 the point's matrix and its tiles.
-__global__ __launch_bounds__(256) void k_round_mid(RoundMidArgs a) {
+// ring's modulus, both Pi_PolyEvl exchanges (P0's [Gamma]_2, P1's and P2's m shares), the
+// revealed point zeta, the Lagrange step of the claim z, and the digit tiles of the
+// multiplication matrix of zeta for the fold on the matrix cores.  The keystream rows come
+// drawn ahead (k_round_rows).  Each of the ring products (the three Lagrange weights in
+// two products each, then the three planes of the new claim) is split over four waves by
+// quarters of its first factor's coefficients, twelve waves at a time, and summed and
+// reduced by one wave; a thirteenth wave builds the point's matrix and its tiles meanwhile.
+constexpr int RM_THREADS = 13 * 64;
+__global__ __launch_bounds__(RM_THREADS) void k_round_mid(RoundMidArgs a) {
     __shared__ u64 rows[9][64];
     __shared__ u64 raw[3][256];                       // [party][point][lo 64 | hi 64]
     __shared__ u64 ssum[6][64];                       // [point * 3 + party]
     __shared__ u64 sh[4][64];
-    __shared__ u64 opb[4][64];
-    __shared__ u64 zeta[64], zm1[64], zmx[64], L[3][64], hh[3][3][64];
+    __shared__ u64 zeta[64], zm1[64], zmx[64], inv[3][64], V[3][64], L[3][64], hh[3][3][64];
+    __shared__ u64 qpart[3][4][128];                  // [product][quarter][lo 64 | hi 64]
     __shared__ u64 mat[64 * 64];
     const int t = threadIdx.x, w = t >> 6, k = t & 63;
-    for (int i = t; i < 9 * 64; i += 256) rows[i >> 6][i & 63] = a.rows[i];
+    for (int i = t; i < 9 * 64; i += RM_THREADS) rows[i >> 6][i & 63] = a.rows[i];
+    if (t < 192) inv[t >> 6][k] = a.inv[t];
     // the workgroups' partials, summed per party (units: P0 0; P1 1, 2; P2 3, 4): thread t =
     // (point t >> 7, word t & 127)
-    for (int p = 0; p < 3; ++p) {
-        u64 s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        const int u0 = p == 0 ? 0 : 2 * p - 1, u1 = p == 0 ? 1 : 2 * p + 1;
-        for (int u = u0; u < u1 && u < a.nunits; ++u) {
-            const u64* src = a.part + (int64_t)u * 256 + t;
-            const int64_t st = (int64_t)a.nunits * 256;
-            int g = 0;
-            for (; g + 4 <= a.groups; g += 4) {
-                s0 += src[g * st];
-                s1 += src[(g + 1) * st];
-                s2 += src[(g + 2) * st];
-                s3 += src[(g + 3) * st];
+    if (t < 256) {
+        for (int p = 0; p < 3; ++p) {
+            u64 s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+            const int u0 = p == 0 ? 0 : 2 * p - 1, u1 = p == 0 ? 1 : 2 * p + 1;
+            for (int u = u0; u < u1 && u < a.nunits; ++u) {
+                const u64* src = a.part + (int64_t)u * 256 + t;
+                const int64_t st = (int64_t)a.nunits * 256;
+                int g = 0;
+                for (; g + 4 <= a.groups; g += 4) {
+                    s0 += src[g * st];
+                    s1 += src[(g + 1) * st];
+                    s2 += src[(g + 2) * st];
+                    s3 += src[(g + 3) * st];
+                }
+                for (; g < a.groups; ++g) s0 += src[g * st];
             }
-            for (; g < a.groups; ++g) s0 += src[g * st];
+            raw[p][t] = s0 + s1 + s2 + s3;
         }
-        raw[p][t] = s0 + s1 + s2 + s3;
     }
     __syncthreads();
     // reduced sums: wave w takes (point, party) w and w + 4
-    for (int pp = w; pp < 6; pp += 4) {
-        const int pt = pp / 3, party = pp % 3;
-        ssum[pp][k] = reduce_wave(raw[party][pt * 128 + k], raw[party][pt * 128 + 64 + k], sh[w], k);
-    }
+    if (w < 4)
+        for (int pp = w; pp < 6; pp += 4) {
+            const int pt = pp / 3, party = pp % 3;
+            ssum[pp][k] = reduce_wave(raw[party][pt * 128 + k], raw[party][pt * 128 + 64 + k], sh[w], k);
+        }
     __syncthreads();
     if (w < 2) {
         // wave pt: the Pi_PolyEvl exchange of h(0) (pt 0) or h(x) (pt 1); its share (m, r1, r2)
@@ -886,15 +905,14 @@ __global__ __launch_bounds__(256) void k_round_mid(RoundMidArgs a) {
         if (a.log_zeta) a.log_zeta[k] = z;
     }
     __syncthreads();
-    if (w < 3) {
-        // h(1) = z - h(0), plane w; Lagrange weight L_w over {0, 1, x}:
-        // L0 = (z-1)(z-x)/x, L1 = z(z-x)/(1-x), L2 = z(z-1)/(x(x-1))
-        hh[1][w][k] = a.z[w * 64 + k] - hh[0][w][k];
-        const u64 iv = a.inv[w * 64 + k];
-        opb[w][k] = w == 2 ? zm1[k] : zmx[k];
-        const u64 v = gr_mul_wave(w == 0 ? zm1[k] : zeta[k], opb[w], sh[w], k);
-        opb[w][k] = iv;
-        L[w][k] = gr_mul_wave(v, opb[w], sh[w], k);
+    // Lagrange weights over {0, 1, x}: L0 = (z-1)(z-x)/x, L1 = z(z-x)/(1-x),
+    // L2 = z(z-1)/(x(x-1)); first v_p = (z-1)(z-x), z(z-x), z(z-1) on waves 4p .. 4p + 3
+    if (w < 12) {
+        const int p = w >> 2, q = w & 3;
+        u64 lo = 0, hi = 0;
+        gr_acc_quarter(p == 0 ? zm1 : zeta, p == 2 ? zm1 : zmx, k, q, lo, hi);
+        qpart[p][q][k] = lo;
+        qpart[p][q][64 + k] = hi;
     } else {
         // the multiplication matrix of zeta: row j = zeta x^j (shift up, reduce x^64)
         u64 cz = zeta[k];
@@ -911,22 +929,54 @@ __global__ __launch_bounds__(256) void k_round_mid(RoundMidArgs a) {
     }
     __syncthreads();
     if (w < 3) {
-        // z'_c = sum_i L_i h_i,c for plane c = w
-        const int c = w;
-        a.z[c * 64 + k] = gr_mul3_wave(L[0][k], hh[0][c], L[1][k], hh[1][c], L[2][k], hh[2][c], sh[w], k);
+        hh[1][w][k] = a.z[w * 64 + k] - hh[0][w][k];          // h(1) = z - h(0), plane w
+        const u64 lo = qpart[w][0][k] + qpart[w][1][k] + qpart[w][2][k] + qpart[w][3][k];
+        const u64 hi = qpart[w][0][64 + k] + qpart[w][1][64 + k] + qpart[w][2][64 + k] + qpart[w][3][64 + k];
+        V[w][k] = reduce_wave(lo, hi, sh[w], k);
+    }
+    __syncthreads();
+    // L_p = v_p times the public inverse
+    if (w < 12) {
+        const int p = w >> 2, q = w & 3;
+        u64 lo = 0, hi = 0;
+        gr_acc_quarter(V[p], inv[p], k, q, lo, hi);
+        qpart[p][q][k] = lo;
+        qpart[p][q][64 + k] = hi;
     } else {
         // the matrix's digit tiles as the fold's B operand: tile row r = column r of the
         // matrix, k = its row index (k-block kb = rows 32 kb .. 32 kb + 31), k-octet oc
         for (int item = k; item < 512; item += 64) {
             const int r = item & 63, oc = (item >> 6) & 3, kb = item >> 8;
-            u64 w8[8], q[8];
+            u64 w8[8], q8[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) w8[i] = mat[(32 * kb + 8 * oc + i) * 64 + r];
-            limb::to_digits(w8, q);
+            limb::to_digits(w8, q8);
             int8_t* base = a.ztiles + kb * limb::TILE_BYTES;
 #pragma unroll
-            for (int d = 0; d < 8; ++d) *(u64*)(base + limb::toff(d, r, oc)) = q[d];
+            for (int d = 0; d < 8; ++d) *(u64*)(base + limb::toff(d, r, oc)) = q8[d];
         }
+    }
+    __syncthreads();
+    if (w < 3) {
+        const u64 lo = qpart[w][0][k] + qpart[w][1][k] + qpart[w][2][k] + qpart[w][3][k];
+        const u64 hi = qpart[w][0][64 + k] + qpart[w][1][64 + k] + qpart[w][2][64 + k] + qpart[w][3][64 + k];
+        L[w][k] = reduce_wave(lo, hi, sh[w], k);
+    }
+    __syncthreads();
+    // z'_c = sum_i L_i h_i,c: plane c on waves 4c .. 4c + 3
+    if (w < 12) {
+        const int c = w >> 2, q = w & 3;
+        u64 lo = 0, hi = 0;
+#pragma unroll
+        for (int i3 = 0; i3 < 3; ++i3) gr_acc_quarter(L[i3], hh[i3][c], k, q, lo, hi);
+        qpart[c][q][k] = lo;
+        qpart[c][q][64 + k] = hi;
+    }
+    __syncthreads();
+    if (w < 3) {
+        const u64 lo = qpart[w][0][k] + qpart[w][1][k] + qpart[w][2][k] + qpart[w][3][k];
+        const u64 hi = qpart[w][0][64 + k] + qpart[w][1][64 + k] + qpart[w][2][64 + k] + qpart[w][3][64 + k];
+        a.z[w * 64 + k] = reduce_wave(lo, hi, sh[w], k);
     }
 }
 
@@ -1906,7 +1956,7 @@ void launch_round_finish(const RoundArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_round_finish, dim3(1), dim3(256), 0, s, a);
 }
 void launch_round_mid(const RoundMidArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_round_mid, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_round_mid, dim3(1), dim3(RM_THREADS), 0, s, a);
 }
 void launch_round_rows(const Keys& k, u32 op, u32 inst, int k0, int rounds, u64* out, hipStream_t s) {
     if (rounds <= 0) return;
