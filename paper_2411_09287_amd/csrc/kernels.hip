@@ -1514,20 +1514,24 @@ __device__ __forceinline__ void gr_acc(const u64* a, const u64* b, int k, u64& l
     }
 }
 
-__global__ __launch_bounds__(256) void k_inner_verify_small(InnerVerifyArgs a) {
+constexpr int IV_WAVES = 16;
+__global__ __launch_bounds__(IV_WAVES * 64) void k_inner_verify_small(InnerVerifyArgs a) {
     const int n = a.n, n1 = n + 1;
-    __shared__ u64 xa[IV_MAX + 1][5][64];    // x'_i (m, r1, r2, r1 + r2) and x_i first; row n: -alpha
+    __shared__ u64 xa[IV_MAX + 1][5][64];    // x'_i (m, r1, r2, r1 + r2) and its [Gamma]_1; row n: -alpha
     __shared__ u64 yb[IV_MAX + 1][5][64];    // y_i (m, r1, r2, r1 + r2, m - r2); row n: z
+    __shared__ u64 xs[IV_MAX][4][64];        // x_i: m, r1, r1 + r2, -r2
+    __shared__ u64 cp[IV_MAX][3][64];        // the parties' sums of x_i alpha
     __shared__ u64 al[5][64];                // alpha: m, r1, r2, r1 + r2, m - r2
-    __shared__ u64 red[4][3][128];
+    __shared__ u64 red[IV_WAVES][3][128];
     __shared__ u64 dr[3][64];                // Delta's masks: r1, r2, [Gamma]_1
-    __shared__ u64 sh[4][64];
+    __shared__ u64 sh[IV_WAVES][64];
     __shared__ int nz;
     const int t = threadIdx.x, w = t >> 6, k = t & 63;
+    constexpr int NTH = IV_WAVES * 64;
     if (t == 0) nz = 0;
     // keystream: alpha (3 rows), Delta's masks (3 rows), and x'_i's masks (3 n rows), one
     // block of 8 words per thread
-    for (int blk = t; blk < 8 * (6 + 3 * n); blk += 256) {
+    for (int blk = t; blk < 8 * (6 + 3 * n); blk += NTH) {
         const int row = blk >> 3, b = blk & 7;
         u64 wv[8];
         if (row < 3) {
@@ -1556,14 +1560,21 @@ __global__ __launch_bounds__(256) void k_inner_verify_small(InnerVerifyArgs a) {
             }
         }
     }
-    // the pairs' y sides and the claim
-    for (int idx = t; idx < n1 * 64; idx += 256) {
+    // the pairs' y sides and the claim; the x_i
+    for (int idx = t; idx < n1 * 64; idx += NTH) {
         const int i = idx >> 6, kk = idx & 63;
         u64 m, r1, r2;
         if (i < n) {
             m = a.p[3] ? a.p[3][(int64_t)i * 64 + kk] : 0;
             r1 = a.p[4] ? a.p[4][(int64_t)i * 64 + kk] : 0;
             r2 = a.p[5] ? a.p[5][(int64_t)i * 64 + kk] : 0;
+            const u64 xm = a.p[0] ? a.p[0][(int64_t)i * 64 + kk] : 0;
+            const u64 x1 = a.p[1] ? a.p[1][(int64_t)i * 64 + kk] : 0;
+            const u64 x2 = a.p[2] ? a.p[2][(int64_t)i * 64 + kk] : 0;
+            xs[i][0][kk] = xm;
+            xs[i][1][kk] = x1;
+            xs[i][2][kk] = x1 + x2;
+            xs[i][3][kk] = 0 - x2;
         } else {
             m = a.z[kk];
             r1 = a.z[64 + kk];
@@ -1582,39 +1593,32 @@ __global__ __launch_bounds__(256) void k_inner_verify_small(InnerVerifyArgs a) {
         // alpha's revealed value is m - r1 - r2; its shares stay (m, r1, r2)
     }
     __syncthreads();
-    // x'_i = Pi_Mult(x_i, alpha): wave w takes the elements i = w, w + 4, ...
-    for (int i = w; i < n; i += 4) {
-        // x_i's planes (read into the wave's own LDS slices: xs = x_i m, r1, r2, r1 + r2)
-        u64 xm = a.p[0] ? a.p[0][(int64_t)i * 64 + k] : 0;
-        u64 x1 = a.p[1] ? a.p[1][(int64_t)i * 64 + k] : 0;
-        u64 x2 = a.p[2] ? a.p[2][(int64_t)i * 64 + k] : 0;
-        xa[i][0][k] = xm;
-        xa[i][3][k] = x1 + x2;
-        // (r1, r2 rows of xa[i] hold x'_i's masks: x_i's r1 and r2 go through registers)
-        wave_sync();
+    // x'_i = Pi_Mult(x_i, alpha): one wave per (element i, party): P0 R_x R_alpha; P1
+    // m_x r1_alpha + r1_x m_alpha; P2 m_x (m_alpha - r2_alpha) - r2_x m_alpha
+    for (int u = w; u < 3 * n; u += IV_WAVES) {
+        const int i = u / 3, p = u - 3 * i;
         u64 lo = 0, hi = 0;
-        gr_acc(xa[i][3], al[3], k, lo, hi);                    // P0: R_x R_alpha
-        const u64 c0 = reduce_wave(lo, hi, sh[w], k);
-        lo = hi = 0;
-        gr_acc(xa[i][0], al[1], k, lo, hi);                    // P1: m_x r1_alpha + r1_x m_alpha
-        xa[i][3][k] = x1;
-        wave_sync();
-        gr_acc(xa[i][3], al[0], k, lo, hi);
-        const u64 c1 = reduce_wave(lo, hi, sh[w], k);
-        lo = hi = 0;
-        gr_acc(xa[i][0], al[4], k, lo, hi);                    // P2: m_x (m_alpha - r2_alpha) - r2_x m_alpha
-        xa[i][3][k] = 0 - x2;
-        wave_sync();
-        gr_acc(xa[i][3], al[0], k, lo, hi);
-        const u64 c2 = reduce_wave(lo, hi, sh[w], k);
+        if (p == 0) {
+            gr_acc(xs[i][2], al[3], k, lo, hi);
+        } else if (p == 1) {
+            gr_acc(xs[i][0], al[1], k, lo, hi);
+            gr_acc(xs[i][1], al[0], k, lo, hi);
+        } else {
+            gr_acc(xs[i][0], al[4], k, lo, hi);
+            gr_acc(xs[i][3], al[0], k, lo, hi);
+        }
+        cp[i][p][k] = reduce_wave(lo, hi, sh[w], k);
+    }
+    __syncthreads();
+    if (w < n) {
+        const int i = w;
         const u64 r1 = xa[i][1][k], r2 = xa[i][2][k], g1 = xa[i][4][k];
-        const u64 g2 = c0 + r1 + r2 - g1;                      // P0 -> P2
-        const u64 m1 = g1 - c1;                                // P1
-        const u64 m2 = c2 + g2;                                // P2
+        const u64 g2 = cp[i][0][k] + r1 + r2 - g1;             // P0 -> P2
+        const u64 m1 = g1 - cp[i][1][k];                       // P1
+        const u64 m2 = cp[i][2][k] + g2;                       // P2
         xa[i][0][k] = m1 + m2;
         xa[i][3][k] = r1 + r2;
-    }
-    if (w == 0) {
+    } else if (w == IV_WAVES - 1) {
         // row n: -alpha
         xa[n][0][k] = 0 - al[0][k];
         xa[n][1][k] = 0 - al[1][k];
@@ -1623,17 +1627,22 @@ __global__ __launch_bounds__(256) void k_inner_verify_small(InnerVerifyArgs a) {
     }
     __syncthreads();
     // Pi_PolyEvl sums over the n + 1 pairs: terms (party 0: R R), (party 1: m r1, r1 m),
-    // (party 2: m (m - r2), -r2 m); wave w takes the pairs i = w, w + 4, ...
+    // (party 2: m (m - r2), -r2 m); one wave per (pair, party), partial sums per wave
     u64 plo[3] = {0, 0, 0}, phi[3] = {0, 0, 0};
-    for (int i = w; i < n1; i += 4) {
-        gr_acc(xa[i][3], yb[i][3], k, plo[0], phi[0]);
-        gr_acc(xa[i][0], yb[i][1], k, plo[1], phi[1]);
-        gr_acc(xa[i][1], yb[i][0], k, plo[1], phi[1]);
-        gr_acc(xa[i][0], yb[i][4], k, plo[2], phi[2]);
-        u64 l2 = 0, h2 = 0;
-        gr_acc(xa[i][2], yb[i][0], k, l2, h2);
-        plo[2] -= l2;
-        phi[2] -= h2;
+    for (int u = w; u < 3 * n1; u += IV_WAVES) {
+        const int i = u / 3, p = u - 3 * i;
+        if (p == 0) {
+            gr_acc(xa[i][3], yb[i][3], k, plo[0], phi[0]);
+        } else if (p == 1) {
+            gr_acc(xa[i][0], yb[i][1], k, plo[1], phi[1]);
+            gr_acc(xa[i][1], yb[i][0], k, plo[1], phi[1]);
+        } else {
+            gr_acc(xa[i][0], yb[i][4], k, plo[2], phi[2]);
+            u64 l2 = 0, h2 = 0;
+            gr_acc(xa[i][2], yb[i][0], k, l2, h2);
+            plo[2] -= l2;
+            phi[2] -= h2;
+        }
     }
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
@@ -1643,8 +1652,12 @@ __global__ __launch_bounds__(256) void k_inner_verify_small(InnerVerifyArgs a) {
     __syncthreads();
     if (w < 3) {
         const int p = w;
-        const u64 lo = red[0][p][k] + red[1][p][k] + red[2][p][k] + red[3][p][k];
-        const u64 hi = red[0][p][64 + k] + red[1][p][64 + k] + red[2][p][64 + k] + red[3][p][64 + k];
+        u64 lo = 0, hi = 0;
+#pragma unroll
+        for (int q = 0; q < IV_WAVES; ++q) {
+            lo += red[q][p][k];
+            hi += red[q][p][64 + k];
+        }
         al[p][k] = reduce_wave(lo, hi, sh[w], k);              // the party sums s0, s1, s2
     }
     __syncthreads();
@@ -2044,7 +2057,7 @@ void launch_pow_ap(const u64* lo, const u64* hi, int64_t L, int64_t e0, int64_t 
 }
 bool launch_inner_verify_small(const InnerVerifyArgs& a, hipStream_t s) {
     if (a.n < 1 || a.n > IV_MAX) return false;
-    hipLaunchKernelGGL(k_inner_verify_small, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_inner_verify_small, dim3(1), dim3(IV_WAVES * 64), 0, s, a);
     return true;
 }
 void launch_conv_bands(const ConvBandArgs& a, int chunks, hipStream_t s) {
