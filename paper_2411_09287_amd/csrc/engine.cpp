@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
+#include <cstring>
 
 #include <algorithm>
 #include <array>
@@ -186,8 +187,10 @@ struct mpc3_ctx {
     hipEvent_t ev_fork2 = nullptr, ev_join2[NV] = {};
     hipStream_t cs = nullptr;
     Scratch* sc = nullptr;
-    // the verification's grouped products (host tables kept until the next group run)
+    // the verification's grouped products (host tables kept until the next group run) and
+    // its other job tables' host copy
     GemmGroup* grp = nullptr;
+    std::vector<char> jobs_host;
     // autotuned kernel family per (M, K, N) of a three-party product
     std::map<std::tuple<int64_t, int64_t, int64_t>, int> tuned;
     // launch shape of the limb kernel per (M, K, N) of a three-party product: ns, rb, split
@@ -808,20 +811,15 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
     Scratch* home_sc = c->sc;
     // rows in XY and gate offsets follow the call order
     const size_t ni = items.size();
-    std::vector<int64_t> rows_at(ni), offs(ni), cost(ni);
-    std::vector<size_t> order(ni);
+    std::vector<int64_t> rows_at(ni), offs(ni);
     {
         int64_t r0 = 0, o0 = 0;
         for (size_t i = 0; i < ni; ++i) {
-            const int64_t M = items[i]->X.rows, K = items[i]->X.cols, N = items[i]->W.cols;
             rows_at[i] = r0;
             offs[i] = o0;
-            cost[i] = M * K + M * N + K * N;
-            r0 += K;
-            o0 += M * N;
-            order[i] = i;
+            r0 += items[i]->X.cols;
+            o0 += items[i]->X.rows * items[i]->W.cols;
         }
-        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] < cost[b]; });
     }
     // one product per step for the three share planes (shared right operand)
     auto three = [&](GemmArgs g, const u64* const* Ap, int64_t as0, int64_t as1, auto out) {
@@ -882,66 +880,106 @@ void verify_inner_batch(mpc3_ctx* c, const VerCtx& v, const std::vector<const Pe
               [&](int p) { return oview(T + p * J * 64, 64, 1); });
     }
     ck(gemm_group_run(c->grp, scratch_alloc, c->sc, home));
-    // the rest of each product's compression is independent of the others: on the worker
-    // streams (each with its own workspace), issued smallest first, round-robin, so that the
-    // short chains of the small products run beside the large ones; then they join this stream
-    ck(hipEventRecord(c->ev_fork2, home));
-    for (int i = 0; i < mpc3_ctx::NV; ++i) ck(hipStreamWaitEvent(c->vs[i], c->ev_fork2, 0));
-    for (size_t q = 0; q < ni; ++q) {
-        const size_t i = order[q];
+    // The rest of every product's compression, each step of all products in one launch from
+    // job tables (uploaded in one copy): the powers r^{M_l n}, r^{o_l + M_l n} and the
+    // convolutions' shift factors; the scaling of U by r^{o_l}; the convolutions' band sums,
+    // their reduction and the x sides; the y sides V as one more group of products.
+    std::vector<PowJob> pj;
+    std::vector<RowsJob> rj;
+    std::vector<BandJob> bj;
+    std::vector<RedArgs> red;
+    std::vector<ConvXArgs> xj;
+    std::vector<u64*> sig(ni);
+    int64_t max_rows = 0, max_k = 0;
+    int max_sets = 0, max_z = 0;
+    for (size_t i = 0; i < ni; ++i) {
         const Pending& P = *items[i];
-        const int64_t row = rows_at[i], off = offs[i];
-        const int64_t M = P.X.rows, K = P.X.cols, N = P.W.cols;
-        const int w = (int)(q % mpc3_ctx::NV);
-        c->cs = c->vs[w];
-        c->sc = &c->vsc2[w];
-        s = c->cs;
-        Scratch::Mark mk = c->sc->mark();
-        u64* sig = c->sc->words(N * 64);             // r^{M n}
+        const int64_t M = P.X.rows, K = P.X.cols, N = P.W.cols, off = offs[i];
+        sig[i] = c->sc->words(N * 64);               // r^{M n}
         u64* sigo = Sall + jrow[i] * 64;             // r^{o_l + M n} (row 0: r^{o_l})
-        launch_pow_ap2(lo, hi, L, 0, off, M, N, sig, sigo, s);
-        const u64* Wc[3] = {P.W.m, P.W.r1, P.W.r2};
-        u64* U = XY + row * 64;
+        for (int64_t nn = 0; nn < N; ++nn) {
+            pj.push_back(PowJob{nn * M, sig[i] + nn * 64});
+            pj.push_back(PowJob{off + nn * M, sigo + nn * 64});
+        }
+        u64* U = XY + rows_at[i] * 64;
         if (conv_fast[i]) {
             const int64_t C = P.cC;
-            const u64* Hc[3] = {P.cx.m, P.cx.r1, P.cx.r2};
-            ConvBandArgs ba{};
-            for (int p = 0; p < 3; ++p) ba.h[p] = Hc[p];
-            ba.lo = lo;
-            ba.B = P.cB; ba.H = P.cH; ba.W = P.cW; ba.C = P.cC; ba.pad = P.cpad;
-            ba.nsets = 4 * P.cpad + 4 * P.cpad * P.cpad;
+            BandJob b{};
+            for (int p = 0; p < 3; ++p) b.a.h[p] = (&P.cx.m)[p];
+            b.a.lo = lo;
+            b.a.B = P.cB; b.a.H = P.cH; b.a.W = P.cW; b.a.C = P.cC; b.a.pad = P.cpad;
+            b.a.nsets = 4 * P.cpad + 4 * P.cpad * P.cpad;
             // chunks of at most 32 positions (k_conv_bands stages one chunk in LDS)
             const int64_t band = (int64_t)P.cB * std::max(P.cH, P.cW);
-            const int chunks = (int)std::max<int64_t>(1, (band + 31) / 32);
-            const int64_t esz = 3 * (int64_t)ba.nsets * C * 64;
-            ba.part = c->sc->words(chunks * esz);
-            launch_conv_bands(ba, chunks, s);
+            b.chunks = (int)std::max<int64_t>(1, (band + 31) / 32);
+            const int64_t esz = 3 * (int64_t)b.a.nsets * C * 64;
+            b.a.part = c->sc->words(b.chunks * esz);
             u64* E = c->sc->words(esz);
-            const OutView eo[1] = {oview(E, esz, 1)};
-            ck(split_reduce(ba.part, 1, esz, 1, chunks, 1, eo, View{nullptr, 0, 0, 0}, false, s));
+            RedArgs r{};
+            r.part = b.a.part;
+            r.M = 1; r.N = esz; r.nprod = 1; r.splits = b.chunks; r.batch = 1; r.atomic = 0;
+            r.C[0] = oview(E, esz, 1);
+            red.push_back(r);
+            max_sets = std::max(max_sets, b.a.nsets);
+            max_z = std::max(max_z, b.chunks * (int)((C + 63) / 64));
+            bj.push_back(b);
             u64* F = c->sc->words((int64_t)P.cKH * P.cKW * 64);
-            launch_pow_shifts(lo, hi, L, off + (int64_t)P.cpad * P.cW + P.cpad, P.cKH, P.cKW, P.cW, F, s);
+            const int64_t e0 = off + (int64_t)P.cpad * P.cW + P.cpad;
+            for (int kh = 0; kh < P.cKH; ++kh)
+                for (int kw = 0; kw < P.cKW; ++kw)
+                    pj.push_back(PowJob{e0 - (int64_t)kh * P.cW - kw, F + (int64_t)(kh * P.cKW + kw) * 64});
             ConvXArgs xa{};
             xa.S = Sbuf[i]; xa.E = E; xa.F = F;
-            xa.KH = P.cKH; xa.KW = P.cKW; xa.C = P.cC; xa.pad = P.cpad; xa.nsets = ba.nsets;
+            xa.KH = P.cKH; xa.KW = P.cKW; xa.C = P.cC; xa.pad = P.cpad; xa.nsets = b.a.nsets;
             xa.K = K; xa.U = U; xa.ustride = np * 64;
-            launch_conv_x(xa, s);
-            ck(hipGetLastError());
+            xj.push_back(xa);
+            max_k = std::max(max_k, K);
         } else {
             // x_k = r^{o_l} sum_m r^m X[m, k]
-            launch_gr_mul_rows(sigo, U, K, K, U, s, 3, np * 64);
+            rj.push_back(RowsJob{sigo, U, K});
+            max_rows = std::max(max_rows, K);
         }
-        // y_k = sum_n r^{M n} W[k, n]
-        three(plain(K, 64, N, View{}, view(sig, 64, 1), OutView{}, false), Wc, N, 1,
-              [&](int p) { return oview(XY + (3 + p) * np * 64 + row * 64, 64, 1); });
-        c->sc->restore(mk);
     }
+    // the job tables in one upload (host copies kept in the context until its next verification)
+    std::vector<char>& hb = c->jobs_host;
+    hb.clear();
+    auto put = [&](const void* p, size_t n) {
+        const size_t o = (hb.size() + 255) & ~(size_t)255;
+        hb.resize(o + n);
+        if (n) std::memcpy(hb.data() + o, p, n);
+        return o;
+    };
+    std::vector<int64_t> rstart(red.size() + 1, 0);
+    for (size_t q = 0; q < red.size(); ++q)
+        rstart[q + 1] = rstart[q] + (red[q].M * red[q].N + 63) / 64;
+    const size_t o_pj = put(pj.data(), pj.size() * sizeof(PowJob)), o_rj = put(rj.data(), rj.size() * sizeof(RowsJob)),
+                 o_bj = put(bj.data(), bj.size() * sizeof(BandJob)), o_red = put(red.data(), red.size() * sizeof(RedArgs)),
+                 o_rs = put(rstart.data(), rstart.size() * sizeof(int64_t)),
+                 o_xj = put(xj.data(), xj.size() * sizeof(ConvXArgs));
+    char* dj = (char*)c->sc->alloc(hb.size());
+    ck(hipMemcpyAsync(dj, hb.data(), hb.size(), hipMemcpyHostToDevice, home));
+    launch_pow_list(lo, hi, L, (const PowJob*)(dj + o_pj), (int64_t)pj.size(), home);
+    launch_gr_scale_rows((const RowsJob*)(dj + o_rj), (int)rj.size(), max_rows, np * 64, home);
+    launch_conv_bands_jobs((const BandJob*)(dj + o_bj), (int)bj.size(), max_sets, max_z, home);
+    if (!red.empty()) {
+        int W = 1;
+        for (const RedArgs& r : red) W = std::max(W, std::min(r.splits, 16));
+        ck(split_reduce_group((const RedArgs*)(dj + o_red), (const int64_t*)(dj + o_rs), (int)red.size(),
+                              rstart.back(), W, home));
+    }
+    launch_conv_x_jobs((const ConvXArgs*)(dj + o_xj), (int)xj.size(), max_k, home);
+    ck(hipGetLastError());
+    // y_k = sum_n r^{M n} W[k, n]
+    for (size_t i = 0; i < ni; ++i) {
+        const Pending& P = *items[i];
+        const int64_t K = P.X.cols, N = P.W.cols;
+        const u64* Wc[3] = {P.W.m, P.W.r1, P.W.r2};
+        three(grouped(plain(K, 64, N, View{}, view(sig[i], 64, 1), OutView{}, false)), Wc, N, 1,
+              [&](int p) { return oview(XY + (3 + p) * np * 64 + rows_at[i] * 64, 64, 1); });
+    }
+    ck(gemm_group_run(c->grp, scratch_alloc, c->sc, home));
     c->cs = s = home;
     c->sc = home_sc;
-    for (int i = 0; i < mpc3_ctx::NV; ++i) {
-        ck(hipEventRecord(c->ev_join2[i], c->vs[i]));
-        ck(hipStreamWaitEvent(home, c->ev_join2[i], 0));
-    }
     u64* z = c->sc->words(3 * 64);
     {
         const u64* Tp[3] = {Tall, Tall + J * 64, Tall + 2 * J * 64};

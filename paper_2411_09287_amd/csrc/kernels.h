@@ -86,6 +86,30 @@ struct ConvXArgs {
     int64_t ustride;
 };
 void launch_conv_x(const ConvXArgs& a, hipStream_t s);
+
+// Many products' steps in one launch each, from tables in device memory (the tables' host
+// copies built by the caller; every job independent of the others):
+//   r^e for a list of exponents (r^e = r^(L (e / L)) r^(e mod L) from the two power tables)
+struct PowJob {
+    int64_t e;
+    u64* out;              // 64 words
+};
+void launch_pow_list(const u64* lo, const u64* hi, int64_t L, const PowJob* jobs, int64_t n, hipStream_t s);
+//   rows [0, n) of three planes (plane stride pstride) of Q times the element P, in place
+struct RowsJob {
+    const u64* P;
+    u64* Q;
+    int64_t n;
+};
+void launch_gr_scale_rows(const RowsJob* jobs, int njobs, int64_t max_n, int64_t pstride, hipStream_t s);
+//   convolutions' band sums (launch_conv_bands per job, chunks per job)
+struct BandJob {
+    ConvBandArgs a;
+    int chunks;
+};
+void launch_conv_bands_jobs(const BandJob* jobs, int njobs, int max_sets, int max_z, hipStream_t s);
+//   convolutions' x sides (launch_conv_x per job)
+void launch_conv_x_jobs(const ConvXArgs* jobs, int njobs, int64_t max_k, hipStream_t s);
 void launch_rec_check(int64_t n, const u64* r1, Inj r1inj, int* flag, hipStream_t s);
 void launch_rec_open(int64_t n, const u64* m, const u64* r1, const u64* r2, const int* flag, u64* out,
                      hipStream_t s);

@@ -1400,6 +1400,33 @@ __global__ void k_xshift_rows(const u64* in, int64_t n, int e, u64* out) {
     out[i * 64 + k] = a;
 }
 
+// Job blockIdx.z: rows 2 blockIdx.x and 2 blockIdx.x + 1 of plane blockIdx.y of its Q times
+// its element P, in place (one pass over the coefficients for both rows).
+__global__ void k_gr_scale_rows(const RowsJob* jobs, int64_t pstride) {
+    __shared__ u64 a[64], b0[64], b1[64], sh[64];
+    const RowsJob& j = jobs[blockIdx.z];
+    const int k = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 2;
+    if (i >= j.n) return;
+    u64* q = j.Q + (int64_t)blockIdx.y * pstride;
+    const bool two = i + 1 < j.n;
+    a[k] = j.P[k];
+    b0[k] = q[i * 64 + k];
+    b1[k] = two ? q[(i + 1) * 64 + k] : 0;
+    __syncthreads();
+    u64 lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
+    for (int m = 0; m < 64; ++m) {
+        const u64 x = a[m];
+        const int c = (k - m) & 63;
+        const u64 p0 = x * b0[c], p1 = x * b1[c];
+        if (m <= k) { lo0 += p0; lo1 += p1; } else { hi0 += p0; hi1 += p1; }
+    }
+    const u64 v0 = reduce_lane(lo0, hi0, sh, k);
+    const u64 v1 = reduce_lane(lo1, hi1, sh, k);
+    q[i * 64 + k] = v0;
+    if (two) q[(i + 1) * 64 + k] = v1;
+}
+
 // One workgroup (one wave) per rpb consecutive rows (even), taken two at a time: rows 2j and
 // 2j + 1 with the same multiplier share its loads in one pass over the coefficients.
 __global__ void k_gr_mul_rows(const u64* P, const u64* Q, int64_t n, int64_t per, u64* out, int64_t pstride,
@@ -1721,13 +1748,12 @@ __device__ __forceinline__ int64_t band_pos(const ConvBandArgs& a, int s, int64_
 // part[chunk][plane][s][c][64].  The positions' power rows and channel values are staged in
 // LDS first (all loads in flight at once), then thread (k = lane, wave w) sums channels w,
 // w + 4, ... of the group.
-__global__ __launch_bounds__(256) void k_conv_bands(ConvBandArgs a) {
+// Block (set s, plane, z = chunk * cgroups + channel group of 64 channels) of nchunks chunks.
+__device__ __forceinline__ void conv_bands_block(const ConvBandArgs& a, int s, int plane, int z, int nchunks) {
     __shared__ u64 Lt[64][64];                   // [position][coefficient]
     __shared__ u64 Ht[64][65];                   // [position][channel] (padded row)
-    // blockIdx.z = chunk * cgroups + channel group (64 channels each)
     const int cgroups = (a.C + 63) / 64;
-    const int s = blockIdx.x, plane = blockIdx.y, chunk = blockIdx.z / cgroups, cg = blockIdx.z % cgroups;
-    const int nchunks = gridDim.z / cgroups;
+    const int chunk = z / cgroups, cg = z % cgroups;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t size = band_size(a, s);
     const int64_t per = (size + nchunks - 1) / nchunks;
@@ -1766,6 +1792,18 @@ __global__ __launch_bounds__(256) void k_conv_bands(ConvBandArgs a) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_conv_bands(ConvBandArgs a) {
+    conv_bands_block(a, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.z / ((a.C + 63) / 64));
+}
+
+// Job blockIdx.y / 3, plane blockIdx.y % 3; blocks past a job's sets or chunks return.
+__global__ __launch_bounds__(256) void k_conv_bands_jobs(const BandJob* jobs) {
+    const BandJob& j = jobs[blockIdx.y / 3];
+    const int cgroups = (j.a.C + 63) / 64;
+    if ((int)blockIdx.x >= j.a.nsets || (int)blockIdx.z >= j.chunks * cgroups) return;
+    conv_bands_block(j.a, blockIdx.x, blockIdx.y % 3, blockIdx.z, j.chunks);
+}
+
 // Block b = kh KW + kw: r^(e0 - kh W - kw) from the two power tables (e0 = o + pad W + pad).
 __global__ void k_pow_shifts(const u64* lo, const u64* hi, int64_t L, int64_t e0, int KW, int W, u64* out) {
     __shared__ u64 pa[64], pb[64], sh[64];
@@ -1779,11 +1817,10 @@ __global__ void k_pow_shifts(const u64* lo, const u64* hi, int64_t L, int64_t e0
 
 // Wave (k, plane): U[plane][k] = (S_c - E_(kh,kw),c) r^(o - delta), 0 for the zero columns
 // k >= KH KW C.  Four waves per block.
-__global__ __launch_bounds__(256) void k_conv_x(ConvXArgs a) {
+__device__ __forceinline__ void conv_x_block(const ConvXArgs& a, int64_t bx, int plane) {
     __shared__ u64 vb[4][64], sh[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t kk = (int64_t)blockIdx.x * 4 + w;
-    const int plane = blockIdx.y;
+    const int64_t kk = bx * 4 + w;
     if (kk >= a.K) return;                          // whole waves: no block barrier below
     u64* out = a.U + plane * a.ustride + kk * 64;
     if (kk >= (int64_t)a.KH * a.KW * a.C) {
@@ -1809,6 +1846,24 @@ __global__ __launch_bounds__(256) void k_conv_x(ConvXArgs a) {
     vb[w][lane] = v;
     const u64 f = a.F[(int64_t)(kh * a.KW + kw) * 64 + lane];
     out[lane] = gr_mul_wave(f, vb[w], sh[w], lane);
+}
+
+__global__ __launch_bounds__(256) void k_conv_x(ConvXArgs a) { conv_x_block(a, blockIdx.x, blockIdx.y); }
+
+// Job blockIdx.y / 3, plane blockIdx.y % 3 (conv_x_block returns per wave past the job's K).
+__global__ __launch_bounds__(256) void k_conv_x_jobs(const ConvXArgs* jobs) {
+    conv_x_block(jobs[blockIdx.y / 3], blockIdx.x, blockIdx.y % 3);
+}
+
+// One exponent per block: r^e = hi[e / L] lo[e mod L].
+__global__ void k_pow_list(const u64* lo, const u64* hi, int64_t L, const PowJob* jobs) {
+    __shared__ u64 pa[64], pb[64], sh[64];
+    const int k = threadIdx.x;
+    const PowJob j = jobs[blockIdx.x];
+    pa[k] = hi[(j.e / L) * 64 + k];
+    pb[k] = lo[(j.e % L) * 64 + k];
+    __syncthreads();
+    j.out[k] = gr_mul_lane(pa, pb, sh, k);
 }
 
 }  // namespace
@@ -2072,6 +2127,24 @@ void launch_pow_shifts(const u64* lo, const u64* hi, int64_t L, int64_t e0, int 
 void launch_conv_x(const ConvXArgs& a, hipStream_t s) {
     if (a.K <= 0) return;
     hipLaunchKernelGGL(k_conv_x, dim3((unsigned)((a.K + 3) / 4), 3), dim3(256), 0, s, a);
+}
+void launch_pow_list(const u64* lo, const u64* hi, int64_t L, const PowJob* jobs, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_pow_list, dim3((unsigned)n), dim3(64), 0, s, lo, hi, L, jobs);
+}
+void launch_gr_scale_rows(const RowsJob* jobs, int njobs, int64_t max_n, int64_t pstride, hipStream_t s) {
+    if (njobs <= 0 || max_n <= 0) return;
+    hipLaunchKernelGGL(k_gr_scale_rows, dim3((unsigned)((max_n + 1) / 2), 3, (unsigned)njobs), dim3(64), 0, s, jobs,
+                       pstride);
+}
+void launch_conv_bands_jobs(const BandJob* jobs, int njobs, int max_sets, int max_z, hipStream_t s) {
+    if (njobs <= 0 || max_sets <= 0 || max_z <= 0) return;
+    hipLaunchKernelGGL(k_conv_bands_jobs, dim3((unsigned)max_sets, (unsigned)(3 * njobs), (unsigned)max_z), dim3(256),
+                       0, s, jobs);
+}
+void launch_conv_x_jobs(const ConvXArgs* jobs, int njobs, int64_t max_k, hipStream_t s) {
+    if (njobs <= 0 || max_k <= 0) return;
+    hipLaunchKernelGGL(k_conv_x_jobs, dim3((unsigned)((max_k + 3) / 4), (unsigned)(3 * njobs)), dim3(256), 0, s, jobs);
 }
 void launch_gr_mul_rows(const u64* P, const u64* Q, int64_t n, int64_t per, u64* out, hipStream_t s, int planes,
                         int64_t pstride) {
