@@ -252,17 +252,44 @@ __global__ void k_to_tiles(TileJob job, int64_t K, int64_t nkb, int64_t rows_pad
     if (o.p[1]) o.p[1] += blockIdx.z * job.ob;
     int8_t* out = job.out[blockIdx.y] + blockIdx.z * job.tb;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= rows_pad * nkb * 4) return;
-    int64_t r, o8;
-    if (o.s_k == 1) { o8 = idx % (nkb * 4); r = idx / (nkb * 4); }
-    else { r = idx % rows_pad; o8 = idx / rows_pad; }
     u64 w[8], q[8];
-    load8(o, r, o8 * 8, K, w);
-    to_digits(w, q);
-    int8_t* base = out + ((r >> 6) * nkb + (o8 >> 2)) * TILE_BYTES;
-    const int rr = (int)(r & 63), oc = (int)(o8 & 3);
+    if (o.s_k == 1) {
+        // k contiguous: consecutive threads take consecutive octets of a row (the four of a
+        // k-block together write its 32-byte row segment of each plane)
+        if (idx >= rows_pad * nkb * 4) return;
+        const int64_t o8 = idx % (nkb * 4), r = idx / (nkb * 4);
+        load8(o, r, o8 * 8, K, w);
+        to_digits(w, q);
+        int8_t* base = out + ((r >> 6) * nkb + (o8 >> 2)) * TILE_BYTES;
+        const int rr = (int)(r & 63), oc = (int)(o8 & 3);
 #pragma unroll
-    for (int d = 0; d < 8; ++d) *(u64*)(base + toff(d, rr, oc)) = q[d];
+        for (int d = 0; d < 8; ++d) *(u64*)(base + toff(d, rr, oc)) = q[d];
+        return;
+    }
+    // rows contiguous: consecutive threads take consecutive rows (coalesced loads), each all
+    // four octets of one k-block, so that every 32-byte row segment of a plane is written
+    // whole by one thread (8-byte pieces from different waves made partial-sector writes:
+    // four times the bytes at the memory)
+    if (idx >= rows_pad * nkb) return;
+    const int64_t r = idx % rows_pad, kb = idx / rows_pad;
+    int8_t* base = out + ((r >> 6) * nkb + kb) * TILE_BYTES;
+    const int rr = (int)(r & 63);
+    u64 qq[4][8];
+#pragma unroll
+    for (int oc = 0; oc < 4; ++oc) {
+        load8(o, r, (kb * 4 + oc) * 8, K, w);
+        to_digits(w, qq[oc]);
+    }
+    // each 16-byte half of the row segment (octets 2h, 2h + 1) in one store
+#pragma unroll
+    for (int d = 0; d < 8; ++d)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            ulonglong2 v;
+            v.x = qq[2 * h][d];
+            v.y = qq[2 * h + 1][d];
+            *(ulonglong2*)(base + toff(d, rr, 2 * h)) = v;
+        }
 }
 
 // A segment of a product: one A plane (k contiguous, row stride lda), or the sum of two
@@ -427,9 +454,16 @@ __device__ __forceinline__ void lgemm2_tile(const L2Args& a, const int L, const 
     // two segments alternate block by block, so that the three products of a row tile,
     // which share its A planes two by two, read each k-block of a plane at about the same
     // time and the second read hits L2 (measured on 32768 x 576 x 64: 689 -> 533 MB fetched)
+    // With the implicit lowering the blocks are visited channel block by channel block, the
+    // KH KW kernel offsets of one innermost: consecutive blocks then read the same channels
+    // at nearby shifts of the input, which stay in cache (the sum is the same in any order).
     auto seg_of = [&](int g, int& kb) {
         const int s = P.nseg == 2 ? g & 1 : 0;
         kb = P.nseg == 2 ? g >> 1 : g;
+        if constexpr (CONV) {
+            const int khkw = a.nkb / a.ccb, cb = kb / khkw;
+            kb = (kb - cb * khkw) * a.ccb + cb;
+        }
         return s;
     };
     // the WPT words of block g at x[0, WPT); with SUM the second plane's at x[WPT, 2 WPT).
@@ -957,7 +991,7 @@ hipError_t limb_btiles(const View& B, int64_t K, int64_t N, int8_t* out, hipStre
     TileJob job{};
     job.o[0] = opnd(B, 0, true, N);
     job.out[0] = out;
-    const int64_t threads = rows_pad * nkb * 4;
+    const int64_t threads = rows_pad * nkb * (job.o[0].s_k == 1 ? 4 : 1);
     hipLaunchKernelGGL(k_to_tiles, dim3((unsigned)((threads + 255) / 256), 1), dim3(256), 0, st, job, K, nkb, rows_pad);
     return hipGetLastError();
 }
@@ -1239,7 +1273,9 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
                     if (!job.out[i]) return false;
                     tb[i] = job.out[i];
                 }
-                const int64_t threads = rows_pad * nkb * 4;
+                bool kc = false;                       // a k-contiguous operand: a thread per octet
+                for (int i = 0; i < n; ++i) kc = kc || bo[i].s_k == 1;
+                const int64_t threads = rows_pad * nkb * (kc ? 4 : 1);
                 hipLaunchKernelGGL(k_to_tiles, dim3((unsigned)((threads + 255) / 256), (unsigned)n, (unsigned)nbl),
                                    dim3(256), 0, st, job, g.K, nkb, rows_pad);
                 return true;
