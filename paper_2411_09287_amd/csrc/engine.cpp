@@ -146,6 +146,18 @@ struct InstanceInfo {
     int64_t npad;
 };
 
+// Device buffers a context keeps for the lowerings it makes itself (mpc3_inner_conv without
+// cols): a buffer goes back to the pool when its product has been verified (the verification
+// has synchronised by then) and serves the next request of the same size, so a network's
+// steps allocate only in the first.  Later users run on the context's stream, after the
+// verification that released it.
+struct DevPool {
+    std::mutex mu;
+    std::multimap<size_t, void*> free;
+    ~DevPool() {
+        for (auto& kv : free) (void)hipFree(kv.second);
+    }
+};
 }  // namespace
 
 struct mpc3_ctx {
@@ -191,6 +203,8 @@ struct mpc3_ctx {
     // its other job tables' host copy
     GemmGroup* grp = nullptr;
     std::vector<char> jobs_host;
+    // buffers of the lowerings the context makes itself (pooled_hold)
+    std::shared_ptr<DevPool> pool = std::make_shared<DevPool>();
     // autotuned kernel family per (M, K, N) of a three-party product
     std::map<std::tuple<int64_t, int64_t, int64_t>, int> tuned;
     // launch shape of the limb kernel per (M, K, N) of a three-party product: ns, rb, split
@@ -1185,6 +1199,28 @@ Hold dev_hold(mpc3_ctx* c, int64_t words) {
     return Hold(p, [](void* q) { (void)hipFree(q); });
 }
 u64* W(const Hold& h, int64_t off = 0) { return (u64*)h.get() + off; }
+
+Hold pooled_hold(mpc3_ctx* c, int64_t words) {
+    const size_t bytes = (size_t)std::max<int64_t>(words, 1) * 8;
+    std::shared_ptr<DevPool> pool = c->pool;
+    void* p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(pool->mu);
+        auto it = pool->free.find(bytes);
+        if (it != pool->free.end()) {
+            p = it->second;
+            pool->free.erase(it);
+        }
+    }
+    if (!p && hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        throw CodeError(MPC3_E_NOMEM);
+    }
+    return Hold(p, [pool, bytes](void* q) {
+        std::lock_guard<std::mutex> lk(pool->mu);
+        pool->free.emplace(bytes, q);
+    });
+}
 P3 planes(const Hold& h, int64_t n) { return P3{{W(h), W(h, n), W(h, 2 * n)}}; }
 C3 cplanes(const P3& p) { return C3{{p.p[0], p.p[1], p.p[2]}}; }
 C3 cplanes(const mpc3_share_t& s) { return C3{{s.m, s.r1, s.r2}}; }
@@ -2091,7 +2127,7 @@ int mpc3_inner_conv(mpc3_ctx* c, const mpc3_share_t* x, int B, int H, int W, int
                 low = *cols;
             } else {
                 // the lowering in device memory held until the product is verified
-                hold = dev_hold(c, 3 * M * K);
+                hold = pooled_hold(c, 3 * M * K);
                 u64* b = (u64*)hold.get();
                 low = mpc3_share_t{b, b + M * K, b + 2 * M * K, M, K};
             }
