@@ -916,12 +916,13 @@ __global__ __launch_bounds__(NT, 2) void k_fold(const u64* XY, int64_t rows, con
     __shared__ __attribute__((aligned(16))) int8_t Bs[2 * TILE_BYTES];
     __shared__ __attribute__((aligned(16))) int8_t As[2][8 * PLANE];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wy = w >> 1, wx = w & 1, r = lane & 31, hf = lane >> 5, kh = hf * 16;
+    const int wy = w >> 1, wx = w & 1, r = lane & 31, hf = lane >> 5;
     const int arow = wy * 32 + r, brow = wx * 32 + r;
     for (int i = t; i < 2 * TILE_BYTES / 16; i += NT) ((v4i*)Bs)[i] = ((const v4i*)zt)[i];
     __syncthreads();
     const int ra = t >> 2, oa = t & 3;            // A loader: row ra, k-octet oa of each k-block
     const int bread = brow * KB + ((hf ^ swz(brow)) << 4);
+    const int aread = arow * KB + ((hf ^ swz(arow)) << 4);
     const int64_t ntiles = (rows + 63) / 64;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t r0 = tile * 64;
@@ -938,8 +939,10 @@ __global__ __launch_bounds__(NT, 2) void k_fold(const u64* XY, int64_t rows, con
                 w8[2 * h + 1] = a1.y - a0.y;
             }
             to_digits(w8, q);
+            // the row's two 16-byte halves swapped as in the digit tiles (swz), so that the
+            // fragment reads of consecutive rows fall on distinct banks
 #pragma unroll
-            for (int d = 0; d < 8; ++d) *(u64*)(As[kb] + d * PLANE + ra * KB + oa * 8) = q[d];
+            for (int d = 0; d < 8; ++d) *(u64*)(As[kb] + toff(d, ra, oa)) = q[d];
         }
         __syncthreads();
         // f(0) of this lane's outputs, loaded while the matrix cores run
@@ -960,7 +963,7 @@ __global__ __launch_bounds__(NT, 2) void k_fold(const u64* XY, int64_t rows, con
             for (int d = 0; d < 8; ++d) B[d] = *(const v4i*)(Bs + kb * TILE_BYTES + d * PLANE + bread);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const v4i A = frag<true>(As[kb] + i * PLANE, arow, kh);
+                const v4i A = *(const v4i*)(As[kb] + i * PLANE + aread);
 #pragma unroll
                 for (int s2 = i; s2 < 8; ++s2)
                     acc[s2] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[s2 - i], acc[s2], 0, 0, 0);
