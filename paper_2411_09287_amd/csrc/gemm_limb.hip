@@ -266,30 +266,19 @@ __global__ void k_to_tiles(TileJob job, int64_t K, int64_t nkb, int64_t rows_pad
         for (int d = 0; d < 8; ++d) *(u64*)(base + toff(d, rr, oc)) = q[d];
         return;
     }
-    // rows contiguous: consecutive threads take consecutive rows (coalesced loads), each all
-    // four octets of one k-block, so that every 32-byte row segment of a plane is written
-    // whole by one thread (8-byte pieces from different waves made partial-sector writes:
-    // four times the bytes at the memory)
-    if (idx >= rows_pad * nkb) return;
-    const int64_t r = idx % rows_pad, kb = idx / rows_pad;
+    // rows contiguous: quads of threads take consecutive rows (coalesced loads of 16 rows per
+    // octet), the four threads of a quad the four octets of one k-block's row segment, so that
+    // each store of a wave writes whole 32-byte segments (8-byte pieces of one octet from
+    // every row made partial-sector writes: four times the bytes at the memory)
+    if (idx >= rows_pad * nkb * 4) return;
+    const int oc = (int)(idx & 3);
+    const int64_t r = (idx >> 2) % rows_pad, kb = (idx >> 2) / rows_pad;
+    load8(o, r, (kb * 4 + oc) * 8, K, w);
+    to_digits(w, q);
     int8_t* base = out + ((r >> 6) * nkb + kb) * TILE_BYTES;
     const int rr = (int)(r & 63);
-    u64 qq[4][8];
 #pragma unroll
-    for (int oc = 0; oc < 4; ++oc) {
-        load8(o, r, (kb * 4 + oc) * 8, K, w);
-        to_digits(w, qq[oc]);
-    }
-    // each 16-byte half of the row segment (octets 2h, 2h + 1) in one store
-#pragma unroll
-    for (int d = 0; d < 8; ++d)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            ulonglong2 v;
-            v.x = qq[2 * h][d];
-            v.y = qq[2 * h + 1][d];
-            *(ulonglong2*)(base + toff(d, rr, 2 * h)) = v;
-        }
+    for (int d = 0; d < 8; ++d) *(u64*)(base + toff(d, rr, oc)) = q[d];
 }
 
 // A segment of a product: one A plane (k contiguous, row stride lda), or the sum of two
@@ -994,7 +983,7 @@ hipError_t limb_btiles(const View& B, int64_t K, int64_t N, int8_t* out, hipStre
     TileJob job{};
     job.o[0] = opnd(B, 0, true, N);
     job.out[0] = out;
-    const int64_t threads = rows_pad * nkb * (job.o[0].s_k == 1 ? 4 : 1);
+    const int64_t threads = rows_pad * nkb * 4;
     hipLaunchKernelGGL(k_to_tiles, dim3((unsigned)((threads + 255) / 256), 1), dim3(256), 0, st, job, K, nkb, rows_pad);
     return hipGetLastError();
 }
@@ -1276,9 +1265,7 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
                     if (!job.out[i]) return false;
                     tb[i] = job.out[i];
                 }
-                bool kc = false;                       // a k-contiguous operand: a thread per octet
-                for (int i = 0; i < n; ++i) kc = kc || bo[i].s_k == 1;
-                const int64_t threads = rows_pad * nkb * (kc ? 4 : 1);
+                const int64_t threads = rows_pad * nkb * 4;           // a thread per octet
                 hipLaunchKernelGGL(k_to_tiles, dim3((unsigned)((threads + 255) / 256), (unsigned)n, (unsigned)nbl),
                                    dim3(256), 0, st, job, g.K, nkb, rows_pad);
                 return true;
