@@ -121,6 +121,15 @@ int mpc3_ctx_create(const uint8_t master_seed[32], int d, int frac_bits, size_t 
                     void* hip_stream, mpc3_ctx** out);
 int mpc3_ctx_destroy(mpc3_ctx* ctx);
 
+/* Return the device memory the context caches between calls: the call workspaces (they
+ * grow to the largest call made and are otherwise kept), the verification workspaces and
+ * results, and the free buffers of its own lowerings (mpc3_inner_conv without cols).
+ * Memory of products not yet verified, message copies and recorded graphs stay.  The
+ * next call that needs a workspace allocates it again.  Synchronises the context's
+ * streams.  *freed_bytes (may be NULL) is the amount returned.  MPC3_E_STATE while a
+ * verification is in flight or while recording. */
+int mpc3_trim(mpc3_ctx* ctx, int64_t* freed_bytes);
+
 /* Kernel family for every matrix product: MPC3_VARIANT_U64 (64-bit integer
  * VALU) or MPC3_VARIANT_LIMB_I8 (8-bit limbs on int8 MFMA, recombined modulo
  * 2^64).  Both give bit-identical results. */

@@ -1796,6 +1796,38 @@ int mpc3_ctx_destroy(mpc3_ctx* c) {
     return MPC3_OK;
 }
 
+int mpc3_trim(mpc3_ctx* c, int64_t* freed_bytes) {
+    int g = guard(c);
+    if (g) return g;
+    if (c->verifying) return MPC3_E_STATE;
+    return wrap(c, __func__, [&] {
+        ck(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < mpc3_ctx::NV; ++i)
+            if (c->vs[i]) ck(hipStreamSynchronize(c->vs[i]));
+        int64_t n = 0;
+        auto drop = [&](Scratch& s) {
+            for (auto& b : s.blks) n += (int64_t)b.cap;
+            s.release();
+        };
+        drop(c->scratch);
+        drop(c->vres);
+        for (int i = 0; i < mpc3_ctx::NV; ++i) {
+            drop(c->vsc[i]);
+            drop(c->vsc2[i]);
+        }
+        {
+            std::lock_guard<std::mutex> lk(c->pool->mu);
+            for (auto& kv : c->pool->free) {
+                n += (int64_t)kv.first;
+                (void)hipFree(kv.second);
+            }
+            c->pool->free.clear();
+        }
+        if (freed_bytes) *freed_bytes = n;
+        return (int)MPC3_OK;
+    });
+}
+
 int mpc3_set_variant(mpc3_ctx* c, int variant) {
     if (!c || variant < MPC3_VARIANT_U64 || variant > MPC3_VARIANT_AUTO) return MPC3_E_ARG;
     c->variant = variant;

@@ -47,6 +47,7 @@ _U64 = ctypes.c_uint64
 SIGNATURES = {
     "mpc3_ctx_create": (_I, [_P, _I, _I, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
     "mpc3_ctx_destroy": (_I, [_P]),
+    "mpc3_trim": (_I, [_P, ctypes.POINTER(_I64)]),
     "mpc3_set_variant": (_I, [_P, _I]),
     "mpc3_set_chunk": (_I, [_P, _I64]),
     "mpc3_autotune": (_I, [_P, _I64, _I64, _I64, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double),
@@ -490,6 +491,13 @@ class Context:
         out = torch.empty(n, dtype=torch.int64, device=self.device)
         _ck(lib().mpc3_message(self.h, kind, which, _ptr(out), n), "mpc3_message", self.h)
         return out
+
+    def trim(self):
+        """Return the device memory the context caches between calls (workspaces, pooled
+        lowering buffers); the bytes returned."""
+        n = ctypes.c_int64(0)
+        _ck(lib().mpc3_trim(self.h, ctypes.byref(n)), "mpc3_trim", self.h)
+        return n.value
 
     def profile(self, on=True):
         _ck(lib().mpc3_profile(self.h, int(on)), "mpc3_profile", self.h)

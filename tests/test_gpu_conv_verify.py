@@ -137,3 +137,58 @@ def test_inner_conv_first_product_with_32_channels_is_lowered():
 def test_inner_conv_implicit_error_detected():
     ok, _, _, _ = run(True, CASES_IMPLICIT, seed=501, inject=(1, 3, 77))
     assert not ok
+
+
+def batches(trim, seed):
+    """Two batches (a dense product, then lowered convolutions that use the library's pooled
+    buffers and the implicit path), each verified; with trim, mpc3_trim between them."""
+    g = np.random.default_rng(seed)
+    c = mpc3.Context(SEED)
+    c.set_variant(1)
+    res, freed = [], None
+    for rep in range(2):
+        c.inner(c.share(mpc3.to_words(u64(g, 40, 24))), c.share(mpc3.to_words(u64(g, 24, 7))))
+        zs = []
+        for B, H, W, C, K, pad, stride, N, _ in (CASES[0][1], CASES_IMPLICIT[1]):
+            x = c.share(mpc3.to_words(u64(g, B, H * W * C)))
+            Wt = c.share(mpc3.to_words(u64(g, K * K * C, N)))
+            zs.append(c.inner_conv(x, B, H, W, C, K, K, pad, Wt, stride=stride))
+        ok = c.verify()
+        log = [c.verify_log(0, sl)[0] for sl in (mpc3.LOG_R, mpc3.LOG_Z, mpc3.LOG_DELTA)]
+        res.append((ok, [z.numpy() for z in zs], log))
+        if trim and rep == 0:
+            freed = c.trim()
+    c.close()
+    return res, freed
+
+
+def test_trim_keeps_results_and_releases_memory():
+    a, freed = batches(True, 900)
+    b, _ = batches(False, 900)
+    assert freed > 0
+    for (oka, za, la), (okb, zb, lb) in zip(a, b):
+        assert oka and okb, "honest verification failed"
+        for pa, pb in zip(za, zb):
+            for qa, qb in zip(pa, pb):
+                assert np.array_equal(qa, qb)
+        for x, y in zip(la, lb):
+            assert np.array_equal(x, y)
+
+
+def test_trim_refused_while_verifying_or_recording():
+    g = np.random.default_rng(901)
+    c = mpc3.Context(SEED, stream=torch.cuda.Stream())
+    c.inner(c.share(mpc3.to_words(u64(g, 16, 8))), c.share(mpc3.to_words(u64(g, 8, 4))))
+    c.verify_begin()
+    with pytest.raises(mpc3.Mpc3Error) as e:
+        c.trim()
+    assert e.value.code == mpc3.E_STATE
+    assert c.verify_end()
+    c.capture_begin()
+    with pytest.raises(mpc3.Mpc3Error) as e:
+        c.trim()
+    assert e.value.code == mpc3.E_STATE
+    with pytest.raises(mpc3.Mpc3Error):
+        c.capture_end()
+    assert c.trim() >= 0
+    c.close()
