@@ -699,6 +699,146 @@ __global__ __launch_bounds__(NT * NS, 2 / NS) void k_lgemm2_group(const L2Args* 
 
 inline int64_t rup(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// Plain products of one or two k-blocks (K <= 64, one split), whose workgroups k_lgemm2
+// would run as a short chain of dependent steps (load, convert, multiply, store) with little
+// to overlap: a fixed grid walks the 64 x 64 output tiles instead, and each workgroup loads
+// the next step's A words and B tiles while the matrix cores and the stores of the current
+// one run (a step is one k-block of one tile; one LDS buffer per operand).  The stores are
+// buffer stores whose offset is moved out of the buffer's range for outputs past M or N, so
+// that every step issues the same count and the wait for the next step's loads does not wait
+// for them.  Workgroups are dealt to the 8 XCDs round-robin: each XCD takes a contiguous
+// range of tiles, so the tiles one XCD runs at once share their B tiles in its L2.  Tile
+// order: column tile fastest, then product, row tile, batch.  gridDim.x is a multiple of 8;
+// C plain (no D, no atomics), strides >= 0, a tile's outputs within 2^31 bytes of its first.
+typedef u32 v2u __attribute__((ext_vector_type(2)));
+
+template <int NKB>
+__global__ __launch_bounds__(NT, 2) void k_lgemm_stream(L2Args a, int ntiles) {
+    __shared__ __attribute__((aligned(16))) int8_t As[TILE_BYTES];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[TILE_BYTES];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wy = w >> 1, wx = w & 1, r = lane & 31, hf = lane >> 5;
+    const int arow = wy * 32 + r, brow = wx * 32 + r;
+    const int aread = arow * KB + ((hf ^ swz(arow)) << 4);
+    const int bread = brow * KB + ((hf ^ swz(brow)) << 4);
+    // A loader: row ra of the tile, the 8 words of octet part of the k-block
+    const int ra = t >> 2, part = t & 3;
+    const int astore = ra * KB + (((part >> 1) ^ swz(ra)) << 4) + ((part & 1) << 3);
+    const int per_x = (ntiles + 7) >> 3, nx = (int)(gridDim.x >> 3);
+    const int lo = (int)(blockIdx.x & 7) * per_x, hi = min(ntiles, lo + per_x);
+    int T = lo + (int)(blockIdx.x >> 3);
+    if (T >= hi) return;                         // the whole workgroup
+    struct Tile {
+        int bI, tmi, prod, tni;
+    };
+    auto decode = [&](int v) {
+        const unsigned u = (unsigned)v, q1 = u / (unsigned)a.tn, q2 = q1 / (unsigned)a.nprod,
+                       q3 = q2 / (unsigned)a.tm;
+        Tile d;
+        d.tni = __builtin_amdgcn_readfirstlane((int)(u - q1 * (unsigned)a.tn));
+        d.prod = __builtin_amdgcn_readfirstlane((int)(q1 - q2 * (unsigned)a.nprod));
+        d.tmi = __builtin_amdgcn_readfirstlane((int)(q2 - q3 * (unsigned)a.tm));
+        d.bI = __builtin_amdgcn_readfirstlane((int)q3);
+        return d;
+    };
+    u64 x[8];
+    v4i bx[4];
+    // rows past M load row M-1 (their accumulator rows are never stored)
+    auto load = [&](const Tile& d, int kb) {
+        const Seg2& S = a.prod[d.prod].seg[0];
+        const u64* rp = S.p + d.bI * a.sbA + min((int64_t)d.tmi * TM + ra, a.M - 1) * a.lda + part * 8 + kb * KB;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const ulonglong2 u = *(const ulonglong2*)(rp + 2 * h);
+            x[2 * h] = u.x;
+            x[2 * h + 1] = u.y;
+        }
+        const int8_t* bp = S.bt + d.bI * a.sbT + ((int64_t)d.tni * a.bnkb + kb) * TILE_BYTES + t * 16;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) bx[h] = *(const v4i*)(bp + h * 4096);
+    };
+    v16i acc[8];
+    // one tile: its k-blocks, then its stores; the loads of the next step are issued before
+    // the MFMAs of each step (past the range they re-read the current tile: always issued)
+    auto tile = [&](const Tile& cur, const Tile& nxt) {
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) {
+            u64 q[8];
+            to_digits(x, q);
+            __syncthreads();                     // the previous step's fragment reads are done
+            storeA8(As, astore, q);
+#pragma unroll
+            for (int h = 0; h < 4; ++h) *(v4i*)(Bs + t * 16 + h * 4096) = bx[h];
+            __syncthreads();
+            if (kb + 1 < NKB) load(cur, kb + 1);
+            else load(nxt, 0);
+            if (kb == 0) {
+#pragma unroll
+                for (int s = 0; s < 8; ++s) acc[s] = v16i{0};
+            }
+            v4i B[8];
+#pragma unroll
+            for (int d = 0; d < 8; ++d) B[d] = *(const v4i*)(Bs + d * PLANE + bread);
+            v4i A = *(const v4i*)(As + aread);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const v4i An = i < 7 ? *(const v4i*)(As + (i + 1) * PLANE + aread) : A;
+#pragma unroll
+                for (int s = i; s < 8; ++s)
+                    acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[s - i], acc[s], 0, 0, 0);
+                A = An;
+            }
+        }
+        const OutView& C = a.prod[cur.prod].C;
+        u64* base = C.p + (int64_t)cur.bI * a.sbC + (int64_t)cur.tmi * TM * C.s0;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, 0, 0x7FFFFFFF, 0x00020000);
+        const int n = cur.tni * TN + wx * 32 + r;
+        const bool nok = n < a.N;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int mloc = wy * 32 + 8 * (v >> 2) + 4 * hf + (v & 3);
+            const bool ok = nok && cur.tmi * TM + mloc < a.M;
+            const int off = ok ? (int)((mloc * C.s0 + n * C.s1) * 8) : (int)0x80000000;
+            u64 val = 0;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) val += ((u64)(int64_t)acc[s][v]) << (8 * s);
+            const v2u u = {(u32)val, (u32)(val >> 32)};
+            __builtin_amdgcn_raw_buffer_store_b64(u, rs, off, 0, 0);
+        }
+    };
+    // the first tile outside the loop, so that every path into the loop has issued the same
+    // loads and stores and the wait for the loads is exact
+    Tile cur = decode(T);
+    load(cur, 0);
+    int Tn = T + nx;
+    Tile nxt = Tn < hi ? decode(Tn) : cur;
+    tile(cur, nxt);
+    while (Tn < hi) {
+        cur = nxt;
+        Tn += nx;
+        nxt = Tn < hi ? decode(Tn) : cur;
+        tile(cur, nxt);
+    }
+}
+
+// Workgroups of k_lgemm_stream for ntiles tiles: per XCD at most as many as its CUs hold at
+// once (the device's own figures, per device).
+int stream_grid(int64_t ntiles) {
+    static int per_xcd[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (!per_xcd[dev]) {
+        int cus = 0, occ = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_lgemm_stream<1>, NT, 0) != hipSuccess)
+            return 0;
+        per_xcd[dev] = std::max(1, cus / 8) * std::max(1, occ);
+    }
+    const int64_t per_x = (ntiles + 7) / 8;
+    return 8 * (int)std::min<int64_t>(per_x, per_xcd[dev]);
+}
+
+
 Opnd opnd(const View& v, int64_t b, bool transpose, int64_t rows, int c0 = 1) {
     Opnd o{};
     o.p[0] = v.p + b * v.sb;
@@ -1355,7 +1495,18 @@ hipError_t gemm_limb(const GemmArgs& g, hipStream_t st) {
                 if (nbl > 1) return hipSuccess;
                 continue;
             }
-            if (conv && ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2, false, true>), gr, dim3(2 * NT), 0, st, l);
+            const int64_t ntiles = (int64_t)gr.x;
+            bool stream = fast && !ta && !conv && ns == 1 && !g.party && nkb <= 2 && splits == 1 && !a.part &&
+                          !a.atomic && !a.D.p && ntiles < ((int64_t)1 << 31) && g.M < ((int64_t)1 << 31) &&
+                          g.N < ((int64_t)1 << 31);
+            for (int p = 0; p < nprod && stream; ++p) {
+                const OutView& C = l.prod[p].C;
+                stream = C.s0 >= 0 && C.s1 >= 0 && ((TM - 1) * C.s0 + (g.N - 1) * C.s1) * 8 + 8 <= 0x7FFFFFFF;
+            }
+            const int sg = stream ? stream_grid(ntiles) : 0;
+            if (sg > 0 && nkb == 1) hipLaunchKernelGGL(k_lgemm_stream<1>, dim3((unsigned)sg), dim3(NT), 0, st, l, (int)ntiles);
+            else if (sg > 0) hipLaunchKernelGGL(k_lgemm_stream<2>, dim3((unsigned)sg), dim3(NT), 0, st, l, (int)ntiles);
+            else if (conv && ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2, false, true>), gr, dim3(2 * NT), 0, st, l);
             else if (conv) hipLaunchKernelGGL((k_lgemm2<true, 1, false, true>), gr, dim3(NT), 0, st, l);
             else if (ta && ns == 2) hipLaunchKernelGGL((k_lgemm2<true, 2, true>), gr, dim3(2 * NT), 0, st, l);
             else if (ta) hipLaunchKernelGGL((k_lgemm2<true, 1, true>), gr, dim3(NT), 0, st, l);
