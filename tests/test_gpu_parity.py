@@ -209,10 +209,11 @@ def test_mult_claims_long_parity(variant):
 
 @pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("inj", [None, (mpc3.SITE_TRUNC_M1, 700, 1 << 40)])
-@pytest.mark.parametrize("M,N", [(32, 32), (64, 128)])
+@pytest.mark.parametrize("M,N", [(32, 32), (64, 128), (40, 25)])
 def test_long_truncation_chunk_verifies(variant, inj, M, N):
     """One chunk of M N truncations: 1024 (2048 gates: claims over 2048 powers, 32 blocks of
-    64 gates in the materialisation) and 8192 (16384 gates: blocks of 128 gates).  The
+    64 gates in the materialisation), 8192 (16384 gates: blocks of 128 gates) and 1000 (2000
+    gates, not a multiple of 64: the materialisation products have a ragged last row tile).  The
     oracle's verification at these sizes is too slow for a test, so the forward values are
     compared with the oracle and the verification is checked by its outcome: it passes on
     honest messages and fails on one added error."""
