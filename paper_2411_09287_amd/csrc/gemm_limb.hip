@@ -961,17 +961,22 @@ __device__ __forceinline__ void hp_unit(const HPartyArgs& a, int8_t (*T)[8 * PLA
                 A[d] = frag<false>(TA + d * PLANE, arow, kh);
                 B[d] = frag<false>(TB + d * PLANE, brow, kh);
             }
-            // digit plane s2 of the product (sum over i + j = s2 of A_i B_j) on one
-            // accumulator at a time, recombined into the 64-bit sums right away
+            // digit planes 2u and 2u + 1 of the product (sums over i + j = s2 of A_i B_j)
+            // on two accumulators at a time (two independent MFMA chains), joined in 32 bits
+            // and added into the 64-bit sums: a plane sums at most 8 x 32 products of digits
+            // in [-128, 127], |acc| <= 2^22, so acc_2u + 2^8 acc_2u+1 < 2^31 in magnitude
 #pragma unroll
-            for (int s2 = 0; s2 < 8; ++s2) {
-                v16i acc = v16i{0};
+            for (int u = 0; u < 4; ++u) {
+                v16i a0 = v16i{0}, a1 = v16i{0};
 #pragma unroll
-                for (int i = 0; i <= s2; ++i)
-                    acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i], B[s2 - i], acc, 0, 0, 0);
+                for (int i = 0; i <= 2 * u + 1; ++i) {
+                    if (i <= 2 * u) a0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i], B[2 * u - i], a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i], B[2 * u + 1 - i], a1, 0, 0, 0);
+                }
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
-                    const u64 val = ((u64)(int64_t)acc[v]) << (8 * s2);
+                    const int32_t j = (int32_t)((u32)a0[v] + ((u32)a1[v] << 8));
+                    const u64 val = ((u64)(int64_t)j) << (16 * u);
                     if (pt == 0) c0[v] += val;
                     else c2[v] += val;
                 }
