@@ -31,6 +31,8 @@ from paper_2411_09287_amd import workloads  # noqa: E402
 INT8_PEAK_TOPS = 5000.0       # MI355X dense int8 MFMA
 ENVELOPE = (32768, 2304, 256)  # largest VGG-style conv product (batch 32, 3x3x256 -> 256)
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "pi_inner_vgg_hbm_traffic.txt")
+V2_TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "truncation_gates_vgg_hbm_traffic.txt")
 # 64-bit integer multiply-accumulate on the vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # of single-issue vector instructions (39.3 T lane-instructions/s), four per u64 MAC in the
 # product kernel (one 32x32->64 multiply-add, two 32-bit low multiplies, one three-way add),
@@ -188,10 +190,29 @@ V2_BYTES_PER_TRUNCATION = 4096 + 12288
 HBM_PEAK_GBPS = 8000.0
 
 
-def v2_roofline(ntrunc, seconds):
+def v2_measured_bytes_per_truncation():
+    """HBM bytes per truncation of the truncation-gate phase measured with rocprofv3 counters
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), valid only while the sources of its
+    kernels and host steps are the ones they were taken on; None otherwise."""
+    import hashlib
+    try:
+        lines = open(V2_TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    kv = dict(ln.split(":", 1) for ln in lines if ln.startswith(("source_sha256:", "bytes_per_truncation:")))
+    h = hashlib.sha256()
+    for name in ("gemm_limb.hip", "kernels.hip", "engine.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_2411_09287_amd", "csrc", name), "rb").read())
+    if kv.get("source_sha256", "").strip() != h.hexdigest() or "bytes_per_truncation" not in kv:
+        return None
+    return float(kv["bytes_per_truncation"])
+
+
+def v2_roofline(ntrunc, seconds, variant="limb"):
     achieved = V2_BYTES_PER_TRUNCATION * ntrunc / seconds / 1e9
+    per = v2_measured_bytes_per_truncation() if variant == "limb" else None
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBPS, "traffic": per * ntrunc if per else None,
             "kernel": "truncation-gate verification, whole phase (algorithmic bytes of its materialised rounds: "
                       f"{V2_BYTES_PER_TRUNCATION} B per truncation)"}
 
@@ -722,7 +743,7 @@ def main():
                    "envelope_product": r["envelope"],
                    "launch_tuning": r["tuning"]},
         "roofline": roof,
-        "v2_roofline": v2_roofline(r["ntrunc"], vt),
+        "v2_roofline": v2_roofline(r["ntrunc"], vt, args.variant),
         "cpu_baseline": cpu,
     }
     if r["u64_times"]:
