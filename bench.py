@@ -727,7 +727,8 @@ def main():
         "value": r["ops"] / t / 1e9, "unit": "GOPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"u64": "u64", "limb": "int8-limb", "auto": "autotuned"}[args.variant], "data": "synthetic",
-        "config": {"workload": f"{args.workload} linear network, batch {r['batch']}", "variant": args.variant,
+        "config": {"workload": f"{args.workload} linear network (no activations; 2x2 sum pooling, its 1/4 folded into "
+                               f"the next weights, in place of max pooling), batch {r['batch']}", "variant": args.variant,
                    "layers": [list(s) for s in r["shapes"]],
                    "window": "encode+share, im2col, truncation pairs, Pi_Inner, truncation, pooling, "
                              "one batched Pi_BIVerify of every layer product"
