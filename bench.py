@@ -68,6 +68,9 @@ def run_gpu(args):
         log(f"[bench] launch tuning: {json.dumps(tuning)}")
     x = torch.from_numpy(workloads.rng(4).random((batch,) + tuple(workloads.MODELS[name]["input"]))).cuda()
     ops = sum(2.0 * M * K * N for M, K, N in shapes)
+    # the products run at the contraction width padded to whole k-blocks; work is counted at
+    # the model's own (the library's counter takes the executed width)
+    work_scale = sum(M * K * N for M, K, N in shapes) / sum(M * K * N for M, K, N in net.exec_shapes(batch))
     ntrunc = sum(M * N for M, K, N in shapes)
     log(f"[bench] workload={name} variant={args.variant} layers={len(shapes)} ring GOP per step={ops / 1e9:.3f}")
 
@@ -177,7 +180,7 @@ def run_gpu(args):
         log(f"[bench] u64 step {float(np.median(u64_times)) * 1e3:.2f} ms")
     gc.enable()
     return {"batch": batch, "shapes": shapes, "ops": ops, "ntrunc": ntrunc, "times": times, "vtimes": vtimes,
-            "ktime": ktime, "launches": launches, "macs": macs, "envelope": env, "u64_times": u64_times,
+            "ktime": ktime, "launches": launches, "macs": macs * work_scale, "envelope": env, "u64_times": u64_times,
             "piped": piped, "fw_times": fw_times, "v1_times": v1_times, "tuning": tuning}
 
 
